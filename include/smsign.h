@@ -1,0 +1,237 @@
+/*
+ * smsign.h -- C ABI of the MI355X submatrix-method density-matrix library.
+ *
+ * The library computes the density matrix of a sparse, atom-block-structured,
+ * symmetric Kohn-Sham matrix H with an orthogonal basis,
+ *
+ *     P = 1/2 (I - sign(H - mu I))            (Eq. 14 of the paper with S = I)
+ *
+ * by the submatrix method (Fig. 2 of the paper): for every atom block i it
+ * gathers the dense principal submatrix T_i of all orbitals coupled to block i
+ * (build_submatrices), evaluates sign(T_i) (Eq. 13) by Newton-Schulz iteration
+ * on the GPU (submatrix_sign), and writes block i's columns of the result into
+ * the sparse P (assemble_P).  energy_trace reduces tr(PH) and tr P in float64.
+ *
+ * Conventions
+ *   - Every function returns an int status: SM_OK (0) or a negative SM_ERR_*.
+ *     The message of the last error of the calling thread is sm_last_error().
+ *   - "host" pointers are CPU memory owned by the caller; the library copies
+ *     what it keeps.  "device" pointers are GPU memory (hipMalloc'd or a torch
+ *     tensor's data_ptr) owned by the caller, on the device that is current
+ *     when the plan is first used.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream unless stated otherwise.
+ *   - Matrices are symmetric with the full block pattern stored, in the
+ *     block-column panel layout:
+ *       col_ptr[c]..col_ptr[c+1]-1 index the stored blocks of block column c,
+ *       row_idx[k] is the block row (atom) of stored block k, strictly
+ *       ascending inside a column, and the diagonal block is present;
+ *       the blocks of column c are stacked, in ascending row order, into one
+ *       dense column-major panel of height h_c = sum block_size[row] and
+ *       width block_size[c], starting at panel_off[c] (in elements).
+ *     P is returned in the same layout and pattern as H.  The structural
+ *     pattern (explicit zero blocks included) defines the index sets, so a
+ *     wider pattern gives larger, more accurate submatrices.
+ */
+#ifndef SMSIGN_H
+#define SMSIGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define SM_OK             0
+#define SM_ERR_ARG       -1   /* invalid argument (null pointer, bad pattern, bad option) */
+#define SM_ERR_HIP       -2   /* a HIP runtime call failed; message names it */
+#define SM_ERR_NONFINITE -3   /* NaN/Inf found in the input; message names the submatrix */
+#define SM_ERR_OOM       -4   /* allocation of a library-owned table failed */
+#define SM_ERR_STATE     -5   /* call out of order (e.g. sign before build) */
+
+/* ---- precisions ----
+ * Arithmetic of one Newton-Schulz phase.  SM_F64 / SM_F32 use the float64 /
+ * float32 MFMA instructions.  SM_BF16 and SM_F16 round both GEMM operands to
+ * bfloat16 / float16 and accumulate in float32.  SM_BF16X3 splits each float32
+ * operand x = hi + lo into two bfloat16 values and forms
+ * A.B ~ Ahi.Bhi + Ahi.Blo + Alo.Bhi with float32 accumulation (Henry, Tang and
+ * Heinecke, ARITH 2019).  All phases except SM_F64 keep the iterate in float32. */
+typedef enum { SM_F64 = 0, SM_F32 = 1, SM_BF16 = 2, SM_F16 = 3, SM_BF16X3 = 4 } sm_prec;
+
+/* ---- scaling of X_0 = T / c ---- */
+typedef enum {
+  SM_SCALE_GERSHGORIN = 0, /* c = max_p sum_q |T_pq|  (an upper bound on rho(T)) */
+  SM_SCALE_POWER      = 1, /* c = (1 + margin) * power-iteration estimate of rho(T) */
+  SM_SCALE_LEARNED    = 2  /* c from the scaling network, accepted only if the
+                              power-iteration guard confirms it, else Gershgorin */
+} sm_scaling;
+
+typedef struct {
+  int32_t n_atoms;            /* number of atom blocks */
+  const int32_t* block_size;  /* host [n_atoms]: orbitals per atom, >= 1 */
+  const int64_t* col_ptr;     /* host [n_atoms+1] */
+  const int32_t* row_idx;     /* host [col_ptr[n_atoms]] */
+  const int64_t* panel_off;   /* host [n_atoms+1]: panel start of every block column */
+} sm_bsr_pattern;
+
+typedef struct {
+  int32_t phase1;        /* sm_prec of the main Newton-Schulz phase */
+  int32_t refine;        /* sm_prec of the refinement steps (SM_F32 or SM_F64) */
+  int32_t refine_steps;  /* updates in `refine` after the switch; 0 = no refinement:
+                            phase 1 then runs until ||X^2 - I||_F < tol */
+  int32_t max_iter;      /* cap on the total number of updates per submatrix */
+  double tol;            /* convergence threshold on ||X^2 - I||_F (no refinement) */
+  double switch_tol;     /* switch to refinement once ||X^2 - I||_F < switch_tol */
+  double stall_below;    /* stagnation test, only while ||X^2 - I||_F < stall_below: */
+  double stall_ratio;    /*   res_k > stall_ratio * res_{k-1} ends the phase */
+  int32_t scaling;       /* sm_scaling */
+  int32_t power_steps;   /* power-iteration steps (SM_SCALE_POWER / the guard) */
+  double scale_margin;   /* c = (1 + margin) * estimate for the power / learned scale */
+  int32_t probes;        /* float64 probe vectors for the final residual check (0..8) */
+  int32_t reserved;
+} sm_sign_opts;
+
+/* Per-submatrix result record, written on the device by submatrix_sign. */
+typedef struct {
+  int32_t iters;       /* Newton-Schulz updates applied in total */
+  int32_t iters_low;   /* ... of which in the phase-1 precision */
+  int32_t status;      /* 1 converged, 0 hit max_iter, 2 refinement done */
+  int32_t scale_src;   /* 0 Gershgorin, 1 power, 2 learned accepted, 3 learned rejected */
+  double scale;        /* c used for X_0 = T / c */
+  double res;          /* last ||X^2 - I||_F from the GEMM epilogue (float64 sum) */
+  double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v||, -1 if off */
+} sm_sub_stats;
+
+typedef struct sm_plan sm_plan;
+typedef struct sm_mlp sm_mlp;
+
+/* Fills `o` with the defaults for a precision schedule: phase1 = prec; for
+ * SM_F64 tol 1e-10 and no refinement; for SM_F32 no refinement with a
+ * stagnation stop; for SM_BF16 / SM_F16 / SM_BF16X3 switch at 0.1 (or on
+ * stagnation) and 2 (3 for SM_BF16) SM_F32 refinement steps. */
+int sm_default_opts(int32_t prec, sm_sign_opts* o);
+
+/* Symbolic plan (host only; no device work until the first device call).
+ *   pattern         block pattern of H (copied).  Errors: SM_ERR_ARG if rows are
+ *                   unsorted, the diagonal block is missing, panel_off does not
+ *                   match the block sizes, or a block size is < 1.
+ *   pad_to          every submatrix is stored padded to a multiple of this
+ *                   (64 or 128); the pad is the identity, a fixed point of the
+ *                   iteration.
+ *   max_chunk_elems workspace budget in matrix elements per chunk: submatrices
+ *                   are processed in chunks whose three n_pad^2 buffers fit
+ *                   (a single larger submatrix forms its own chunk); <= 0 means
+ *                   one chunk.
+ * Index set of atom i: the atoms of block column i's stored pattern (ascending);
+ * n_i = panel height h_i; loc_i = offset of atom i's own rows in its panel. */
+int sm_plan_create(const sm_bsr_pattern* pattern, int32_t pad_to,
+                   int64_t max_chunk_elems, sm_plan** out);
+void sm_plan_destroy(sm_plan* plan);
+
+/* Sizes for caller-owned buffers.
+ *   storage_prec SM_F64 or SM_F32 (the iterate's storage type).
+ *   n_sub       number of submatrices (= n_atoms), n_chunks number of chunks,
+ *   ws_bytes    device workspace bytes needed by build/sign/assemble,
+ *   p_nnz_vals  length of P's (and H's) value array.  Any pointer may be NULL. */
+int sm_plan_sizes(const sm_plan* plan, int32_t storage_prec, int64_t* n_sub,
+                  int64_t* n_chunks, int64_t* ws_bytes, int64_t* p_nnz_vals);
+
+/* Host copies of the plan for inspection (each pointer may be NULL):
+ *   n_out[n_atoms], npad_out[n_atoms], loc_out[n_atoms], chunk_out[n_atoms],
+ *   order_out[n_atoms] (processing order: submatrix ids chunk by chunk). */
+int sm_plan_info(const sm_plan* plan, int32_t* n_out, int32_t* npad_out, int32_t* loc_out,
+                 int32_t* chunk_out, int32_t* order_out);
+
+/* Step 1 of Fig. 2 for every submatrix of `chunk`: T_i = H[idx_i, idx_i] - mu I,
+ * zero where H stores no block, identity-padded, then scaled to X_0 = T_i / c_i
+ * with c_i from opts->scaling; also computes the 16 per-submatrix features.
+ *   H_vals  device float64 [p_nnz_vals], panel layout.
+ *   ws      device workspace of ws_bytes (caller-owned, reused across chunks).
+ *   stats   device sm_sub_stats[n_atoms] indexed by submatrix id.
+ * SM_ERR_NONFINITE (synchronous check of a device flag) if T_i holds NaN/Inf. */
+int build_submatrices(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
+                      const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, void* stream);
+
+/* Step 2 of Fig. 2: sign(T_i) (Eq. 13) of every submatrix of `chunk` by the
+ * Newton-Schulz iteration X <- 1/2 X (3I - X^2) under the precision schedule of
+ * opts, all submatrices batched into the same launches; a device scheduler
+ * retires converged submatrices.  Writes the per-submatrix records in `stats`.
+ * Non-convergence is reported in stats[i].status, not as an error.  Blocks the
+ * host only to poll the number of active submatrices. */
+int submatrix_sign(sm_plan* plan, int32_t chunk, void* ws, const sm_sign_opts* opts,
+                   sm_sub_stats* stats, void* stream);
+
+/* Step 3 of Fig. 2: for every submatrix i of `chunk`, block column i of P is
+ * 1/2 (E - sign(T_i)[:, loc_i : loc_i + b_i]) over the rows idx_i (no
+ * symmetrisation; each block column has exactly one writer).
+ *   P_vals device float64 [p_nnz_vals], same layout as H. */
+int assemble_P(const sm_plan* plan, int32_t chunk, const void* ws, double* P_vals,
+               void* stream);
+
+/* E = tr(P H) = sum over stored entries of P .* H (H symmetric) and
+ * Ne = tr P, reduced in float64 in a fixed order (bitwise reproducible).
+ * Synchronises `stream`; E_host / Ne_host may be NULL. */
+int energy_trace(const sm_plan* plan, const double* H_vals, const double* P_vals,
+                 double* E_host, double* Ne_host, void* stream);
+
+/* Whole evaluation at fixed mu: for every chunk build, sign, assemble; then
+ * energy_trace.  Synchronises `stream`. */
+int sm_density_matrix(sm_plan* plan, const double* H_vals, double mu,
+                      const sm_sign_opts* opts, void* ws, double* P_vals,
+                      sm_sub_stats* stats, double* E_host, double* Ne_host, void* stream);
+
+/* Chemical potential by bisection on the electron count (the paper leaves the
+ * rule open): start from the global Gershgorin bracket of H, evaluate
+ * Ne(mid) = tr P with the full method at each midpoint, stop at the first
+ * midpoint with |Ne - n_target| < accept, else after max_steps midpoints.
+ * On return P_vals (if not NULL) holds P at the returned mu.
+ *   mu_hist / ne_hist  host arrays of max_steps entries (may be NULL).
+ * Synchronises `stream`. */
+int sm_find_mu(sm_plan* plan, const double* H_vals, double n_target, double accept,
+               int32_t max_steps, const sm_sign_opts* opts, void* ws, double* P_vals,
+               sm_sub_stats* stats, double* mu_out, int32_t* steps_out,
+               double* mu_hist, double* ne_hist, void* stream);
+
+/* Global Gershgorin bracket [lo, hi] of H (synchronous). */
+int sm_gershgorin_bracket(sm_plan* plan, const double* H_vals, double* lo, double* hi,
+                          void* stream);
+
+/* Workspace layout, for inspection by tests: region offsets in bytes
+ *   regions9 = [matrices, state, partials, lists, features, scratch, vecs, flag, total]
+ * and, per processing index g, the element offset of submatrix order[g]'s three
+ * n_pad x n_pad column-major buffers (X_even, X_odd, Y) inside the matrix region
+ * of its chunk.  After build_submatrices X_even holds X_0 = T_i / c_i; after
+ * submatrix_sign the converged X is the buffer of parity stats[i].iters.
+ * Either output may be NULL. */
+int sm_plan_ws_layout(const sm_plan* plan, int32_t storage_prec, int64_t* regions9,
+                      int64_t* mat_off_g);
+
+/* Diagnostic: one matrix-core instruction of precision `prec` on a single
+ * wavefront with the operand lane layout the kernels assume; out_host receives
+ * 256 doubles, out[lane*4 + v] = the result element held by `lane` in register
+ * v, to be compared with D[4*(lane/16)+v][lane%16] of the exact product.
+ * Synchronous; allocates and frees a 2 KiB device buffer. */
+int sm_selftest_mfma(int32_t prec, double* out_host);
+
+/* Kernel timing for measurement.  While enabled, every Newton-Schulz GEMM
+ * launch made by submatrix_sign is bracketed by a pair of HIP events recorded
+ * on the caller's stream.  sm_profile_read synchronises on the recorded
+ * events, adds up their elapsed times per kernel class, and clears them:
+ * class = 2 * precision + kind (precision = sm_prec, kind 0 = square
+ * A = X^2 / Y = 3I - A, kind 1 = update X' = 1/2 X Y), 10 classes.
+ *   launches[10], ms[10]   host outputs (either may be NULL). */
+int sm_profile_enable(sm_plan* plan, int32_t on);
+int sm_profile_read(sm_plan* plan, int64_t* launches, double* ms);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* sm_last_error(void);
+
+/* Library version string. */
+const char* sm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMSIGN_H */

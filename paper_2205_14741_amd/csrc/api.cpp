@@ -1,0 +1,330 @@
+// C-ABI entry points: argument checks, chunk loop, the host side of the
+// Newton-Schulz driver, chemical-potential bisection.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "plan.h"
+
+using namespace sm;
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_opts(const sm_sign_opts* o) {
+  if (!o) return set_error(SM_ERR_ARG, "null sm_sign_opts");
+  if (o->phase1 < SM_F64 || o->phase1 > SM_BF16X3) return set_error(SM_ERR_ARG, "opts.phase1 = %d is not an sm_prec", o->phase1);
+  if (o->refine_steps < 0 || o->refine_steps > 16) return set_error(SM_ERR_ARG, "opts.refine_steps = %d out of [0, 16]", o->refine_steps);
+  if (o->refine_steps > 0 && o->refine != SM_F32 && o->refine != SM_F64)
+    return set_error(SM_ERR_ARG, "opts.refine must be SM_F32 or SM_F64");
+  if (o->refine_steps > 0 && (o->refine == SM_F64) != (o->phase1 == SM_F64))
+    return set_error(SM_ERR_ARG, "refinement and main phase must both be float64 or both use float32 storage");
+  if (o->max_iter < 0 || o->max_iter > 1000) return set_error(SM_ERR_ARG, "opts.max_iter = %d out of [0, 1000]", o->max_iter);
+  if (o->scaling < SM_SCALE_GERSHGORIN || o->scaling > SM_SCALE_LEARNED) return set_error(SM_ERR_ARG, "opts.scaling = %d invalid", o->scaling);
+  if (o->probes < 0 || o->probes > kMaxProbes) return set_error(SM_ERR_ARG, "opts.probes = %d out of [0, %d]", o->probes, kMaxProbes);
+  if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
+  if (!(o->tol >= 0) || !(o->switch_tol >= 0) || !(o->stall_ratio >= 0) || !(o->stall_below >= 0) ||
+      !(o->scale_margin >= 0))
+    return set_error(SM_ERR_ARG, "negative or NaN tolerance in opts");
+  return SM_OK;
+}
+
+int chunk_range(const sm_plan* p, int32_t chunk, int& g0, int& nsub) {
+  const int nch = (int)p->chunk_ptr.size() - 1;
+  if (chunk < 0 || chunk >= nch) return set_error(SM_ERR_ARG, "chunk %d out of [0, %d)", chunk, nch);
+  g0 = (int)p->chunk_ptr[chunk];
+  nsub = (int)(p->chunk_ptr[chunk + 1] - p->chunk_ptr[chunk]);
+  return SM_OK;
+}
+
+struct WsPtrs {
+  void* mats;
+  SubState* st;
+  double* partials;
+  int32_t* lists;
+  float* features;
+  double* scratch;
+  double* vecs;
+  int32_t* flag;
+};
+
+WsPtrs ws_ptrs(const sm_plan* p, void* ws, int f64) {
+  const WsLayout L = p->layout(f64);
+  char* w = static_cast<char*>(ws);
+  return WsPtrs{w + L.mats, (SubState*)(w + L.state), (double*)(w + L.partials), (int32_t*)(w + L.lists),
+                (float*)(w + L.features), (double*)(w + L.scratch), (double*)(w + L.vecs),
+                (int32_t*)(w + L.flag)};
+}
+
+int64_t list_stride(const sm_plan* p) { return 2 + 2 * p->max_subs + 1; }
+
+int chunk_tiles(const sm_plan* p, int g0, int nsub) {
+  int64_t t = 0;
+  for (int g = g0; g < g0 + nsub; ++g) {
+    const int64_t T = p->npad_g[g] / kTile;
+    t += T * (T + 1) / 2;
+  }
+  return (int)std::min<int64_t>(t, 1 << 30);
+}
+
+// Launch one Newton-Schulz GEMM, bracketed by timing events when profiling.
+int gemm_launch(sm_plan* p, int mode, int which, int g0, void* mats, SubState* st, const int32_t* cnt,
+                const int32_t* ids, const int32_t* pre, double* partials, int grid, hipStream_t s) {
+  size_t k = 0;
+  if (p->profiling) {
+    k = p->prof_cls.size();
+    while (p->prof_ev.size() < 2 * (k + 1)) {
+      hipEvent_t e;
+      SM_HIP(hipEventCreate(&e));
+      p->prof_ev.push_back(e);
+    }
+    SM_HIP(hipEventRecord(p->prof_ev[2 * k], s));
+  }
+  SM_HIP(launch_ns_gemm(mode, which, p->dev, g0, mats, st, cnt, ids, pre, partials, grid, s));
+  if (p->profiling) {
+    SM_HIP(hipEventRecord(p->prof_ev[2 * k + 1], s));
+    p->prof_cls.push_back(2 * mode + which);
+  }
+  return SM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sm_profile_enable(sm_plan* p, int32_t on) {
+  if (!p) return set_error(SM_ERR_ARG, "sm_profile_enable: null plan");
+  p->profiling = on != 0;
+  return SM_OK;
+}
+
+int sm_profile_read(sm_plan* p, int64_t* launches, double* ms) {
+  if (!p) return set_error(SM_ERR_ARG, "sm_profile_read: null plan");
+  int64_t n[10] = {0};
+  double t[10] = {0};
+  for (size_t k = 0; k < p->prof_cls.size(); ++k) {
+    SM_HIP(hipEventSynchronize(p->prof_ev[2 * k + 1]));
+    float e = 0.f;
+    SM_HIP(hipEventElapsedTime(&e, p->prof_ev[2 * k], p->prof_ev[2 * k + 1]));
+    n[p->prof_cls[k]] += 1;
+    t[p->prof_cls[k]] += e;
+  }
+  p->prof_cls.clear();
+  if (launches) std::memcpy(launches, n, sizeof(n));
+  if (ms) std::memcpy(ms, t, sizeof(t));
+  return SM_OK;
+}
+
+
+int sm_plan_ws_layout(const sm_plan* p, int32_t storage_prec, int64_t* regions9, int64_t* mat_off_g) {
+  if (!p) return set_error(SM_ERR_ARG, "sm_plan_ws_layout: null plan");
+  if (storage_prec != SM_F64 && storage_prec != SM_F32)
+    return set_error(SM_ERR_ARG, "sm_plan_ws_layout: storage must be SM_F64 or SM_F32");
+  const WsLayout L = p->layout(storage_prec == SM_F64);
+  if (regions9) {
+    const int64_t r[9] = {L.mats, L.state, L.partials, L.lists, L.features, L.scratch, L.vecs, L.flag, L.total};
+    std::memcpy(regions9, r, sizeof(r));
+  }
+  if (mat_off_g) std::memcpy(mat_off_g, p->mat_off_g.data(), p->mat_off_g.size() * 8);
+  return SM_OK;
+}
+
+int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_sign_opts* o,
+                      void* ws, sm_sub_stats* stats, void* stream) {
+  if (!p || !H || !ws || !stats) return set_error(SM_ERR_ARG, "build_submatrices: null argument");
+  if (!std::isfinite(mu)) return set_error(SM_ERR_ARG, "build_submatrices: mu is not finite");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  int g0, nsub;
+  if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
+  if ((rc = ensure_device(p))) return rc;
+  const size_t lds = (size_t)(2 * p->max_m + p->max_npad) * sizeof(int);
+  if (lds > 64 * 1024)
+    return set_error(SM_ERR_ARG, "build_submatrices: index set too large for the gather (needs %zu B of LDS)", lds);
+  const int f64 = storage_is_f64(o);
+  WsPtrs w = ws_ptrs(p, ws, f64);
+  hipStream_t s = as_stream(stream);
+  SM_HIP(launch_fill_i32(w.flag, 0, 1, s));
+  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, w.flag, s));
+  SM_HIP(launch_analyze(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin,
+                        w.vecs, nullptr, w.features, w.st, stats, s));
+  SM_HIP(hipMemcpyAsync(&p->h_pinned[8], w.flag, 4, hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  p->last_f64 = f64;
+  if (p->h_pinned[8] != 0)
+    return set_error(SM_ERR_NONFINITE, "build_submatrices: NaN/Inf in submatrix of atom %d", p->h_pinned[8] - 1);
+  return SM_OK;
+}
+
+int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, sm_sub_stats* stats,
+                   void* stream) {
+  if (!p || !ws || !stats) return set_error(SM_ERR_ARG, "submatrix_sign: null argument");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  int g0, nsub;
+  if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
+  if ((rc = ensure_device(p))) return rc;
+  const int f64 = storage_is_f64(o);
+  if (p->last_f64 != f64)
+    return set_error(SM_ERR_STATE, "submatrix_sign: the workspace was not built for this precision schedule");
+  WsPtrs w = ws_ptrs(p, ws, f64);
+  hipStream_t s = as_stream(stream);
+  const int64_t stride = list_stride(p);
+  int32_t* L0 = w.lists;
+  auto list_count = [&](int L) { return L0 + L * stride; };
+  auto list_ids = [&](int L) { return L0 + L * stride + 2; };
+  auto list_pre = [&](int L) { return L0 + L * stride + 2 + p->max_subs; };
+  const int grid = std::max(1, std::min(chunk_tiles(p, g0, nsub), 2048));
+  const int mode_main = o->phase1;
+  const int mode_ref = o->refine;
+  const bool has_ref = o->refine_steps > 0;
+
+  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, (int)p->max_subs, *o, 1, stats, s));
+  const int lim = o->max_iter + o->refine_steps + 2;
+  for (int it = 0; it <= lim; ++it) {
+    if ((rc = gemm_launch(p, mode_main, 0, g0, w.mats, w.st, list_count(2), list_ids(2), list_pre(2),
+                          w.partials, grid, s)))
+      return rc;
+    if (has_ref && (rc = gemm_launch(p, mode_ref, 0, g0, w.mats, w.st, list_count(3), list_ids(3),
+                                     list_pre(3), w.partials, grid, s)))
+      return rc;
+    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, (int)p->max_subs, *o, 0, stats, s));
+    SM_HIP(hipMemcpyAsync(&p->h_pinned[it & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
+    SM_HIP(hipEventRecord(p->ev[it & 1], s));
+    if ((rc = gemm_launch(p, mode_main, 1, g0, w.mats, w.st, list_count(0), list_ids(0), list_pre(0),
+                          w.partials, grid, s)))
+      return rc;
+    if (has_ref && (rc = gemm_launch(p, mode_ref, 1, g0, w.mats, w.st, list_count(1), list_ids(1),
+                                     list_pre(1), w.partials, grid, s)))
+      return rc;
+    if (it >= 1) {
+      SM_HIP(hipEventSynchronize(p->ev[(it - 1) & 1]));
+      if (p->h_pinned[(it - 1) & 1] == 0) break;
+    }
+  }
+  SM_HIP(launch_finish(p->dev, g0, nsub, w.mats, f64, w.st, o->probes, w.vecs, stats, s));
+  return SM_OK;
+}
+
+int assemble_P(const sm_plan* p, int32_t chunk, const void* ws, double* P, void* stream) {
+  if (!p || !ws || !P) return set_error(SM_ERR_ARG, "assemble_P: null argument");
+  int g0, nsub, rc;
+  if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
+  if (p->device < 0) return set_error(SM_ERR_STATE, "assemble_P: plan has not been used on a device yet");
+  const int f64 = p->last_f64;
+  if (f64 < 0) return set_error(SM_ERR_STATE, "assemble_P: no submatrices built");
+  WsPtrs w = ws_ptrs(p, const_cast<void*>(ws), f64);
+  SM_HIP(launch_scatter(p->dev, g0, nsub, w.mats, f64, w.st, P, as_stream(stream)));
+  return SM_OK;
+}
+
+int energy_trace(const sm_plan* pc, const double* H, const double* P, double* E, double* Ne, void* stream) {
+  if (!pc || !H || !P) return set_error(SM_ERR_ARG, "energy_trace: null argument");
+  sm_plan* p = const_cast<sm_plan*>(pc);
+  int rc;
+  if ((rc = ensure_device(p))) return rc;
+  hipStream_t s = as_stream(stream);
+  double* out = p->d_trace_parts + 2 * kTraceBlocks;
+  SM_HIP(launch_trace(H, P, p->nvals, p->d_diag_idx, (int64_t)p->diag_idx.size(), p->d_trace_parts,
+                      kTraceBlocks, out, s));
+  double* h = reinterpret_cast<double*>(&p->h_pinned[10]);
+  SM_HIP(hipMemcpyAsync(h, out, 16, hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  if (E) *E = h[0];
+  if (Ne) *Ne = h[1];
+  return SM_OK;
+}
+
+int sm_density_matrix(sm_plan* p, const double* H, double mu, const sm_sign_opts* o, void* ws,
+                      double* P, sm_sub_stats* stats, double* E, double* Ne, void* stream) {
+  if (!p) return set_error(SM_ERR_ARG, "sm_density_matrix: null plan");
+  const int nch = (int)p->chunk_ptr.size() - 1;
+  int rc;
+  for (int c = 0; c < nch; ++c) {
+    if ((rc = build_submatrices(p, c, H, mu, o, ws, stats, stream))) return rc;
+    if ((rc = submatrix_sign(p, c, ws, o, stats, stream))) return rc;
+    if ((rc = assemble_P(p, c, ws, P, stream))) return rc;
+  }
+  return energy_trace(p, H, P, E, Ne, stream);
+}
+
+int sm_gershgorin_bracket(sm_plan* p, const double* H, double* lo, double* hi, void* stream) {
+  if (!p || !H || !lo || !hi) return set_error(SM_ERR_ARG, "sm_gershgorin_bracket: null argument");
+  int rc;
+  if ((rc = ensure_device(p))) return rc;
+  hipStream_t s = as_stream(stream);
+  SM_HIP(launch_gersh_rows(p->dev, p->n_atoms, H, p->d_gersh, s));
+  std::vector<double> h(2 * (size_t)p->n_atoms);
+  SM_HIP(hipMemcpyAsync(h.data(), p->d_gersh, h.size() * 8, hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  double a = h[0], b = h[1];
+  for (int c = 1; c < p->n_atoms; ++c) {
+    a = std::min(a, h[2 * c]);
+    b = std::max(b, h[2 * c + 1]);
+  }
+  *lo = a;
+  *hi = b;
+  return SM_OK;
+}
+
+int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int32_t max_steps,
+               const sm_sign_opts* o, void* ws, double* P, sm_sub_stats* stats, double* mu_out,
+               int32_t* steps_out, double* mu_hist, double* ne_hist, void* stream) {
+  if (!p || !H || !ws || !stats || !mu_out) return set_error(SM_ERR_ARG, "sm_find_mu: null argument");
+  if (max_steps < 1 || max_steps > 200) return set_error(SM_ERR_ARG, "sm_find_mu: max_steps out of [1, 200]");
+  if (!(accept > 0)) return set_error(SM_ERR_ARG, "sm_find_mu: accept must be > 0");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  double lo, hi;
+  if ((rc = sm_gershgorin_bracket(p, H, &lo, &hi, stream))) return rc;
+  hipStream_t s = as_stream(stream);
+  const int nch = (int)p->chunk_ptr.size() - 1;
+  std::vector<double> ne_sub((size_t)p->n_atoms);
+  double mid = 0.5 * (lo + hi);
+  int step = 1;
+  for (; step <= max_steps; ++step) {
+    mid = 0.5 * (lo + hi);
+    for (int c = 0; c < nch; ++c) {
+      if ((rc = build_submatrices(p, c, H, mid, o, ws, stats, stream))) return rc;
+      if ((rc = submatrix_sign(p, c, ws, o, stats, stream))) return rc;
+      int g0, nsub;
+      chunk_range(p, c, g0, nsub);
+      WsPtrs w = ws_ptrs(p, ws, storage_is_f64(o));
+      SM_HIP(launch_ne_from_x(p->dev, g0, nsub, w.mats, storage_is_f64(o), w.st, p->d_ne_sub, s));
+      if (P && (rc = assemble_P(p, c, ws, P, stream))) return rc;
+    }
+    SM_HIP(hipMemcpyAsync(ne_sub.data(), p->d_ne_sub, ne_sub.size() * 8, hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    // compensated sum in atom order
+    double sum = 0.0, comp = 0.0;
+    for (double x : ne_sub) {
+      const double t = sum + x;
+      comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
+      sum = t;
+    }
+    const double ne = sum + comp;
+    if (mu_hist) mu_hist[step - 1] = mid;
+    if (ne_hist) ne_hist[step - 1] = ne;
+    if (std::fabs(ne - n_target) < accept) break;
+    if (ne < n_target) lo = mid; else hi = mid;
+  }
+  *mu_out = mid;
+  if (steps_out) *steps_out = std::min(step, (int)max_steps);
+  return SM_OK;
+}
+
+int sm_selftest_mfma(int32_t prec, double* out_host) {
+  if (!out_host) return set_error(SM_ERR_ARG, "sm_selftest_mfma: null output");
+  if (prec < SM_F64 || prec > SM_BF16X3) return set_error(SM_ERR_ARG, "sm_selftest_mfma: bad precision");
+  double* d = nullptr;
+  SM_HIP(hipMalloc(&d, 256 * sizeof(double)));
+  hipError_t e = launch_selftest_mfma(prec, d, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out_host, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_error(e, "sm_selftest_mfma");
+  return SM_OK;
+}
+
+}  // extern "C"

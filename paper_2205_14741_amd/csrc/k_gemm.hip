@@ -1,0 +1,529 @@
+// Step 2 of the submatrix method (Fig. 2 of the paper) on the matrix cores:
+// sign(T_i) (Eq. 13) of every submatrix by the Newton-Schulz iteration
+//     A = X^2,  Y = 3I - A,  X' = 1/2 X Y,
+// all submatrices of a chunk in the same launches.  X, A, Y and X' are
+// polynomials in the symmetric T_i, so they are symmetric: only tiles on or
+// below the diagonal are computed and each is stored twice (as itself and as
+// its transpose), which halves the MFMA work and keeps every iterate exactly
+// symmetric.  A device scheduler (one workgroup) retires converged
+// submatrices and builds the tile lists of the next launches.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "smsign_internal.h"
+
+namespace sm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// per-precision traits
+//   S    storage type of the iterate in the workspace
+//   L    LDS element type
+//   K    k-depth of one LDS stage
+//   KP   LDS row padding (elements) against bank conflicts
+// ---------------------------------------------------------------------------
+template <int MODE> struct Traits;
+template <> struct Traits<SM_F64> { using S = double; using L = double; static constexpr int K = 16, KP = 2; using Acc = d4; };
+template <> struct Traits<SM_F32> { using S = float; using L = float; static constexpr int K = 32, KP = 4; using Acc = f4; };
+template <> struct Traits<SM_BF16> { using S = float; using L = uint16_t; static constexpr int K = 64, KP = 8; using Acc = f4; };
+template <> struct Traits<SM_F16> { using S = float; using L = _Float16; static constexpr int K = 64, KP = 8; using Acc = f4; };
+template <> struct Traits<SM_BF16X3> { using S = float; using L = uint16_t; static constexpr int K = 64, KP = 8; using Acc = f4; };
+
+constexpr int kBlock = 256;   // 4 waves in a 2 x 2 arrangement, 32 x 32 outputs each
+
+struct ListView {
+  const int32_t* count;   // [0] tiles, [1] submatrices
+  const int32_t* list;    // local submatrix ids
+  const int32_t* prefix;  // tile prefix, [n+1]
+};
+
+__device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
+  int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
+  while (r * (r + 1) / 2 > lt) --r;
+  while ((r + 1) * (r + 2) / 2 <= lt) ++r;
+  bi = r;
+  bj = lt - r * (r + 1) / 2;
+}
+
+// WHICH = 0: A = X^2 -> Y = 3I - A, residual partial sum (A - I)^2 per tile.
+// WHICH = 1: X' = 1/2 X Y.
+// C[r][c] = sum_k L[k][r] R[k][c] with L = X and R = X or Y stored column-major;
+// by symmetry L[k][r] = X[r][k], so C = X R.  Both operand panels are read as
+// columns (contiguous k), i.e. LDS rows hold one output row's k-slab.
+template <int MODE, int WHICH>
+__global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
+                                                         typename Traits<MODE>::S* __restrict__ mats,
+                                                         const SubState* __restrict__ st, ListView lv,
+                                                         double* __restrict__ partials) {
+  using Tr = Traits<MODE>;
+  using S = typename Tr::S;
+  using LT = typename Tr::L;
+  constexpr int K = Tr::K;
+  constexpr int LD = K + Tr::KP;
+  constexpr int NL = K / 4;              // elements per thread per operand per stage
+  constexpr bool SPLIT = (MODE == SM_BF16X3);
+  constexpr int NOP = SPLIT ? 4 : 2;     // A, B (+ A_lo, B_lo)
+  __shared__ __attribute__((aligned(16))) LT lds[2][NOP][64 * LD];
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lrow = tid >> 2;             // 0..63: row of the operand panel this thread loads
+  const int lpart = (tid & 3) * NL;      // k offset inside the stage
+  const int total = lv.count[0];
+  const int nlist = lv.count[1];
+
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = nlist - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (lv.prefix[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const int l = lv.list[lo];
+    const int lt = t - lv.prefix[lo];
+    const int g = g0 + l;
+    const int npad = p.npad_g[g];
+    const int64_t nn = (int64_t)npad * npad;
+    S* base = mats + p.mat_off_g[g];
+    const int it = st[l].iters;
+    const S* Xp;
+    const S* Rp;
+    S* Out;
+    if (WHICH == 0) {
+      Xp = base + (int64_t)(it & 1) * nn;
+      Rp = Xp;
+      Out = base + 2 * nn;
+    } else {
+      Xp = base + (int64_t)((it + 1) & 1) * nn;
+      Rp = base + 2 * nn;
+      Out = base + (int64_t)(it & 1) * nn;
+    }
+    int bi, bj;
+    tile_coords(lt, bi, bj);
+    const int r0 = bi * 64, c0 = bj * 64;
+    const S* ga = Xp + (int64_t)(r0 + lrow) * npad + lpart;
+    const S* gb = Rp + (int64_t)(c0 + lrow) * npad + lpart;
+
+    typename Tr::Acc acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = typename Tr::Acc{0, 0, 0, 0};
+
+    S ra[NL], rb[NL];
+#pragma unroll
+    for (int e = 0; e < NL; ++e) { ra[e] = ga[e]; rb[e] = gb[e]; }
+
+    const int nst = npad / K;
+    for (int s = 0; s < nst; ++s) {
+      const int buf = s & 1;
+      // ---- registers -> LDS (with the precision conversion) ----
+      LT* sa = &lds[buf][0][lrow * LD + lpart];
+      LT* sb = &lds[buf][1][lrow * LD + lpart];
+      if constexpr (MODE == SM_F64 || MODE == SM_F32) {
+#pragma unroll
+        for (int e = 0; e < NL; ++e) { sa[e] = ra[e]; sb[e] = rb[e]; }
+      } else if constexpr (MODE == SM_F16) {
+#pragma unroll
+        for (int e = 0; e < NL; ++e) { sa[e] = (_Float16)ra[e]; sb[e] = (_Float16)rb[e]; }
+      } else if constexpr (MODE == SM_BF16) {
+#pragma unroll
+        for (int e = 0; e < NL; ++e) { sa[e] = f32_to_bf16_bits(ra[e]); sb[e] = f32_to_bf16_bits(rb[e]); }
+      } else {  // split: x = hi + lo
+        LT* sal = &lds[buf][2][lrow * LD + lpart];
+        LT* sbl = &lds[buf][3][lrow * LD + lpart];
+#pragma unroll
+        for (int e = 0; e < NL; ++e) {
+          const uint16_t ha = f32_to_bf16_bits(ra[e]);
+          const uint16_t hb = f32_to_bf16_bits(rb[e]);
+          sa[e] = ha;
+          sb[e] = hb;
+          sal[e] = f32_to_bf16_bits(ra[e] - bf16_bits_to_f32(ha));
+          sbl[e] = f32_to_bf16_bits(rb[e] - bf16_bits_to_f32(hb));
+        }
+      }
+      __syncthreads();
+      // ---- prefetch the next stage into registers ----
+      if (s + 1 < nst) {
+        const S* na = ga + (int64_t)(s + 1) * K;
+        const S* nb = gb + (int64_t)(s + 1) * K;
+#pragma unroll
+        for (int e = 0; e < NL; ++e) { ra[e] = na[e]; rb[e] = nb[e]; }
+      }
+      // ---- MFMA on the LDS stage ----
+      const int kq = lane >> 4;    // k group of this lane
+      const int rl = lane & 15;    // row / column inside a 16 x 16 block
+      if constexpr (MODE == SM_F64) {
+        // 16x16x4: lane supplies A[rl][kq], B[kq][rl]; the k index inside the
+        // stage is permuted to 4 kq + kk so each lane reads 4 contiguous values.
+        double a[2][4], b[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            a[x][kk] = lds[buf][0][(wm * 32 + x * 16 + rl) * LD + 4 * kq + kk];
+            b[x][kk] = lds[buf][1][(wn * 32 + x * 16 + rl) * LD + 4 * kq + kk];
+          }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][kk], b[y][kk], acc[x][y], 0, 0, 0);
+      } else if constexpr (MODE == SM_F32) {
+        float a[2][8], b[2][8];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
+            a[x][kk] = lds[buf][0][(wm * 32 + x * 16 + rl) * LD + 8 * kq + kk];
+            b[x][kk] = lds[buf][1][(wn * 32 + x * 16 + rl) * LD + 8 * kq + kk];
+          }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][kk], b[y][kk], acc[x][y], 0, 0, 0);
+      } else {
+        // 16x16x32: lane supplies A[rl][8 kq .. 8 kq + 7], B[8 kq .. 8 kq + 7][rl]
+#pragma unroll
+        for (int kh = 0; kh < K / 32; ++kh) {
+          const int ko = kh * 32 + 8 * kq;
+          if constexpr (MODE == SM_F16) {
+            f16x8 a[2], b[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              a[x] = *reinterpret_cast<const f16x8*>(&lds[buf][0][(wm * 32 + x * 16 + rl) * LD + ko]);
+              b[x] = *reinterpret_cast<const f16x8*>(&lds[buf][1][(wn * 32 + x * 16 + rl) * LD + ko]);
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int y = 0; y < 2; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x], b[y], acc[x][y], 0, 0, 0);
+          } else {
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              a[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][0][(wm * 32 + x * 16 + rl) * LD + ko]));
+              b[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][1][(wn * 32 + x * 16 + rl) * LD + ko]));
+            }
+            if constexpr (SPLIT) {
+              bf16x8 al[2], bl[2];
+#pragma unroll
+              for (int x = 0; x < 2; ++x) {
+                al[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][2][(wm * 32 + x * 16 + rl) * LD + ko]));
+                bl[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][3][(wn * 32 + x * 16 + rl) * LD + ko]));
+              }
+#pragma unroll
+              for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                  acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], b[y], acc[x][y], 0, 0, 0);
+                  acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bl[y], acc[x][y], 0, 0, 0);
+                  acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+              for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                  acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+
+    // ---- epilogue: 16 x 16 result block.  Register v of lane l holds column
+    // l % 16 and row 4 (l / 16) + v for the float32-accumulating instructions,
+    // row l / 16 + 4 v for the float64 one (checked by sm_selftest_mfma). ----
+    double part = 0.0;
+    const bool mirror = (bi != bj);
+    const int kq = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int rb = r0 + wm * 32 + x * 16;
+        const int cc = c0 + wn * 32 + y * 16 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = rb + (MODE == SM_F64 ? kq + 4 * v : 4 * kq + v);
+          const double a = (double)acc[x][y][v];
+          S outv;
+          if (WHICH == 0) {
+            const double dg = (rr == cc) ? 1.0 : 0.0;
+            const double e = a - dg;
+            part += e * e;
+            outv = (S)(3.0 * dg - a);
+          } else {
+            outv = (S)(0.5 * a);
+          }
+          Out[(int64_t)cc * npad + rr] = outv;
+          if (mirror) Out[(int64_t)rr * npad + cc] = outv;
+        }
+      }
+    if (WHICH == 0) {
+      part = wave_sum(part);
+      if (lane == 0) red[wid] = part;
+      __syncthreads();
+      if (tid == 0) {
+        const double sum = ((red[0] + red[1]) + red[2]) + red[3];
+        partials[p.tile_off_g[g] + lt] = mirror ? 2.0 * sum : sum;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int MODE>
+static hipError_t launch_mode(int which, const DevPlan& p, int g0, void* mats, const SubState* st,
+                              ListView lv, double* partials, int grid, hipStream_t s) {
+  using S = typename Traits<MODE>::S;
+  if (which == 0)
+    hipLaunchKernelGGL((ns_gemm_kernel<MODE, 0>), dim3(grid), dim3(kBlock), 0, s, p, g0, (S*)mats,
+                       st, lv, partials);
+  else
+    hipLaunchKernelGGL((ns_gemm_kernel<MODE, 1>), dim3(grid), dim3(kBlock), 0, s, p, g0, (S*)mats,
+                       st, lv, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_gemm(int mode, int which, const DevPlan& p, int g0, void* mats,
+                          const SubState* st, const int32_t* count, const int32_t* list,
+                          const int32_t* prefix, double* partials, int grid, hipStream_t s) {
+  ListView lv{count, list, prefix};
+  switch (mode) {
+    case SM_F64: return launch_mode<SM_F64>(which, p, g0, mats, st, lv, partials, grid, s);
+    case SM_F32: return launch_mode<SM_F32>(which, p, g0, mats, st, lv, partials, grid, s);
+    case SM_BF16: return launch_mode<SM_BF16>(which, p, g0, mats, st, lv, partials, grid, s);
+    case SM_F16: return launch_mode<SM_F16>(which, p, g0, mats, st, lv, partials, grid, s);
+    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, p, g0, mats, st, lv, partials, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// device scheduler
+// ---------------------------------------------------------------------------
+struct SchedOpts {
+  int refine_steps, max_iter;
+  double tol, switch_tol, stall_below, stall_ratio;
+};
+
+enum { DEC_UPD = 1, DEC_SQ = 2, DEC_REF = 4 };
+
+// exclusive scan over the block; returns the block total in `total`
+__device__ int block_excl_scan(int v, int* sh, int& total) {
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  int off = 0;
+  total = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (w < wid) off += sh[w];
+    total += sh[w];
+  }
+  __syncthreads();
+  return off + x - v;
+}
+
+// One workgroup.  Phase A (a wavefront per submatrix): reduce the residual
+// partials of the square just computed in a fixed order, apply the stopping /
+// phase-switch rules, advance the iteration counters.  Phase B: ordered
+// compaction into four tile lists: update in the main / refinement precision,
+// square (next iteration) in the main / refinement precision.
+__global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int nsub, SubState* st,
+                                                        const double* __restrict__ partials,
+                                                        int32_t* lists, int max_subs, SchedOpts o,
+                                                        int first) {
+  extern __shared__ unsigned char dec_s[];
+  __shared__ int sh[16];
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int l = wid; l < nsub; l += nw) {
+    SubState s = st[l];
+    int dec = 0;
+    if (first) {
+      s.active = 1;
+      s.phase = 0;
+      s.iters = 0;
+      s.iters_low = 0;
+      s.refine_left = 0;
+      s.status = 0;
+      s.res = 1e300;
+      s.res_prev = 1e300;
+      dec = DEC_SQ;
+    } else if (s.active) {
+      const int g = g0 + l;
+      const int T = p.npad_g[g] / kTile;
+      const int nt = T * (T + 1) / 2;
+      const double* pp = partials + p.tile_off_g[g];
+      double r = 0.0;
+      for (int k = lane; k < nt; k += 64) r += pp[k];
+      r = sqrt(fmax(wave_sum(r), 0.0));
+      s.res_prev = s.res;
+      s.res = r;
+      const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
+      if (!(r < 1e300)) {
+        s.status = -1;
+        s.active = 0;
+      } else if (s.phase == 0) {
+        if (o.refine_steps == 0) {
+          if (r < o.tol || stalled) {
+            s.status = 1;
+            s.active = 0;
+          } else if (s.iters >= o.max_iter) {
+            s.status = 0;
+            s.active = 0;
+          } else {
+            dec = DEC_UPD | DEC_SQ;
+            s.iters++;
+            s.iters_low++;
+          }
+        } else if (r < o.switch_tol || stalled || s.iters >= o.max_iter) {
+          s.phase = 1;
+          s.refine_left = o.refine_steps;
+        } else {
+          dec = DEC_UPD | DEC_SQ;
+          s.iters++;
+          s.iters_low++;
+        }
+      }
+      if (s.active && s.phase == 1 && dec == 0) {
+        dec = DEC_UPD | DEC_REF;
+        s.iters++;
+        s.refine_left--;
+        if (s.refine_left > 0) {
+          dec |= DEC_SQ;
+        } else {
+          s.status = 2;
+          s.active = 0;
+        }
+      }
+    }
+    if (lane == 0) {
+      st[l] = s;
+      dec_s[l] = (unsigned char)dec;
+    }
+  }
+  __syncthreads();
+  const int stride = 2 + 2 * max_subs + 1;
+  int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
+  for (int base = 0; base < nsub; base += blockDim.x) {
+    const int l = base + threadIdx.x;
+    int dec = 0, nt = 0;
+    if (l < nsub) {
+      dec = dec_s[l];
+      const int T = p.npad_g[g0 + l] / kTile;
+      nt = T * (T + 1) / 2;
+    }
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+      const bool in = (L == 0) ? ((dec & DEC_UPD) && !(dec & DEC_REF))
+                    : (L == 1) ? ((dec & DEC_UPD) && (dec & DEC_REF))
+                    : (L == 2) ? ((dec & DEC_SQ) && !(dec & DEC_REF))
+                               : ((dec & DEC_SQ) && (dec & DEC_REF));
+      int tot_s, tot_t;
+      const int ps = block_excl_scan(in ? 1 : 0, sh, tot_s);
+      const int pt = block_excl_scan(in ? nt : 0, sh, tot_t);
+      int32_t* Lb = lists + L * stride;
+      if (in) {
+        Lb[2 + run_subs[L] + ps] = l;
+        Lb[2 + max_subs + run_subs[L] + ps] = run_tiles[L] + pt;
+      }
+      run_subs[L] += tot_s;
+      run_tiles[L] += tot_t;
+    }
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+      int32_t* Lb = lists + L * stride;
+      Lb[0] = run_tiles[L];
+      Lb[1] = run_subs[L];
+      Lb[2 + max_subs + run_subs[L]] = run_tiles[L];
+    }
+    // number of submatrices still in flight, for the host's stopping poll
+    lists[4 * stride] = run_subs[0] + run_subs[1] + run_subs[2] + run_subs[3];
+  }
+}
+
+hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
+                           const double* partials, int32_t* lists, int max_subs,
+                           const sm_sign_opts& so, int first, sm_sub_stats* /*stats*/,
+                           hipStream_t s) {
+  SchedOpts o{so.refine_steps, so.max_iter, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
+  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), (size_t)(nsub > 0 ? nsub : 1), s, p, g0,
+                     nsub, st, partials, lists, max_subs, o, first);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// self-test of the MFMA lane layout assumed above (one wavefront):
+// A[r][k] = ((r + 3 k) mod 11) - 5, B[k][c] = ((2 k + 5 c) mod 13) - 6, exact in
+// every precision; out[lane * 4 + v] = D element the lane holds in register v.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float st_a(int r, int k) { return (float)(((r + 3 * k) % 11) - 5); }
+__device__ __forceinline__ float st_b(int k, int c) { return (float)(((2 * k + 5 * c) % 13) - 6); }
+
+__global__ void selftest_kernel(int prec, double* out) {
+  const int l = threadIdx.x;
+  const int rl = l & 15, kq = l >> 4;
+  if (prec == SM_F64) {
+    d4 acc{0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)st_a(rl, kq), (double)st_b(kq, rl), acc, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+  } else if (prec == SM_F32) {
+    f4 acc{0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(st_a(rl, kq), st_b(kq, rl), acc, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+  } else if (prec == SM_F16) {
+    f16x8 a, b;
+    for (int e = 0; e < 8; ++e) {
+      a[e] = (_Float16)st_a(rl, 8 * kq + e);
+      b[e] = (_Float16)st_b(8 * kq + e, rl);
+    }
+    f4 acc{0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+  } else {
+    u16x8 a, b;
+    for (int e = 0; e < 8; ++e) {
+      a[e] = f32_to_bf16_bits(st_a(rl, 8 * kq + e));
+      b[e] = f32_to_bf16_bits(st_b(8 * kq + e, rl));
+    }
+    f4 acc{0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+  }
+}
+
+hipError_t launch_selftest_mfma(int prec, double* out_dev, hipStream_t s) {
+  hipLaunchKernelGGL(selftest_kernel, dim3(1), dim3(64), 0, s, prec, out_dev);
+  return hipGetLastError();
+}
+
+}  // namespace sm

@@ -1,0 +1,244 @@
+// After the sign iteration: float64 probe check of sign(T)^2 = I, step 3 of
+// the submatrix method (Fig. 2 of the paper: insert block i's columns into P),
+// and the float64 reductions tr(PH), tr P of Eq. 14's density matrix.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "smsign_internal.h"
+
+namespace sm {
+
+template <typename T>
+__device__ __forceinline__ const T* final_x(const DevPlan& p, int g, const T* mats, const SubState* st,
+                                             int l) {
+  const int64_t np = p.npad_g[g];
+  return mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * np * np;
+}
+
+// One workgroup per submatrix: copy the per-submatrix iteration record into
+// `stats` and, with probes > 0, estimate max_v ||X (X v) - v|| / ||v|| in float64
+// for fixed +-1 vectors v (a residual of sign(T)^2 = I, Eq. 13).
+template <typename T>
+__global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T* __restrict__ mats,
+                                                     const SubState* __restrict__ st, int probes,
+                                                     double* __restrict__ vecs,
+                                                     sm_sub_stats* __restrict__ stats) {
+  __shared__ double red[16];
+  const int l = blockIdx.x;
+  const int g = g0 + l;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int n = p.height[i];
+  const T* X = final_x(p, g, mats, st, l);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  double worst = -1.0;
+  if (probes > 0) {
+    double* v = vecs + p.vec_off_g[g];
+    double* w = v + npad;
+    double* z = w + npad;
+    worst = 0.0;
+    for (int pr = 0; pr < probes; ++pr) {
+      for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] = probe_entry(pr, d);
+      __syncthreads();
+      for (int c = wid; c < n; c += nw) {
+        const T* col = X + (int64_t)c * npad;
+        double s = 0.0;
+        for (int d = lane; d < n; d += kWave) s += (double)col[d] * v[d];
+        s = wave_sum(s);
+        if (lane == 0) w[c] = s;
+      }
+      __syncthreads();
+      for (int c = wid; c < n; c += nw) {
+        const T* col = X + (int64_t)c * npad;
+        double s = 0.0;
+        for (int d = lane; d < n; d += kWave) s += (double)col[d] * w[d];
+        s = wave_sum(s);
+        if (lane == 0) z[c] = s;
+      }
+      __syncthreads();
+      double e = 0.0;
+      for (int d = threadIdx.x; d < n; d += blockDim.x) {
+        const double t = z[d] - v[d];
+        e += t * t;
+      }
+      e = block_reduce<0>(e, red);
+      worst = fmax(worst, sqrt(e / (double)n));
+    }
+  }
+  if (threadIdx.x == 0) {
+    const SubState s = st[l];
+    sm_sub_stats& r = stats[i];
+    r.iters = s.iters;
+    r.iters_low = s.iters_low;
+    r.status = s.status;
+    r.res = s.res;
+    if (probes > 0) r.res_probe = worst;
+  }
+}
+
+hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                         const SubState* st, int probes, double* vecs, sm_sub_stats* stats,
+                         hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  if (storage_f64)
+    hipLaunchKernelGGL(finish_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0,
+                       (const double*)mats, st, probes, vecs, stats);
+  else
+    hipLaunchKernelGGL(finish_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0,
+                       (const float*)mats, st, probes, vecs, stats);
+  return hipGetLastError();
+}
+
+// Block column i of P = 1/2 (E - X[:, loc_i : loc_i + b_i]) over the n_i rows of
+// submatrix i; P's panel of column i has exactly those rows in that order, so
+// this is a contiguous, coalesced copy with one writer per block column.
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_kernel(DevPlan p, int g0, const T* __restrict__ mats,
+                                                      const SubState* __restrict__ st,
+                                                      double* __restrict__ P) {
+  const int l = blockIdx.x;
+  const int g = g0 + l;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int n = p.height[i];
+  const int loc = p.loc[i];
+  const int b = p.bs[i];
+  const T* X = final_x(p, g, mats, st, l);
+  double* out = P + p.panel_off[i];
+  const int total = n * b;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int q = e / n;
+    const int r = e - q * n;
+    const double x = (double)X[(int64_t)(loc + q) * npad + r];
+    out[e] = 0.5 * ((r == loc + q ? 1.0 : 0.0) - x);
+  }
+}
+
+hipError_t launch_scatter(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                          const SubState* st, double* P, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  if (storage_f64)
+    hipLaunchKernelGGL(scatter_kernel<double>, dim3(nsub), dim3(256), 0, s, p, g0,
+                       (const double*)mats, st, P);
+  else
+    hipLaunchKernelGGL(scatter_kernel<float>, dim3(nsub), dim3(256), 0, s, p, g0,
+                       (const float*)mats, st, P);
+  return hipGetLastError();
+}
+
+// tr(PH) = sum of P .* H over the common stored pattern (H symmetric) and
+// tr P = sum of P's diagonal; block b reduces a fixed contiguous range, the
+// final kernel adds the block partials in block order: bitwise reproducible.
+__global__ __launch_bounds__(256) void trace_partial_kernel(const double* __restrict__ H,
+                                                            const double* __restrict__ P, int64_t nvals,
+                                                            const int64_t* __restrict__ diag,
+                                                            int64_t ndiag, double* __restrict__ parts) {
+  __shared__ double red[8];
+  const int64_t per = (nvals + gridDim.x - 1) / gridDim.x;
+  const int64_t a = blockIdx.x * per;
+  const int64_t e = a + per < nvals ? a + per : nvals;
+  double s = 0.0;
+  for (int64_t k = a + threadIdx.x; k < e; k += blockDim.x) s += P[k] * H[k];
+  s = block_reduce<0>(s, red);
+  const int64_t perd = (ndiag + gridDim.x - 1) / gridDim.x;
+  const int64_t ad = blockIdx.x * perd;
+  const int64_t ed = ad + perd < ndiag ? ad + perd : ndiag;
+  double t = 0.0;
+  for (int64_t k = ad + threadIdx.x; k < ed; k += blockDim.x) t += P[diag[k]];
+  t = block_reduce<0>(t, red);
+  if (threadIdx.x == 0) {
+    parts[blockIdx.x] = s;
+    parts[gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void trace_final_kernel(const double* __restrict__ parts, int nb,
+                                                          double* __restrict__ out) {
+  __shared__ double red[8];
+  double s = 0.0, t = 0.0;
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    s += parts[k];
+    t += parts[nb + k];
+  }
+  s = block_reduce<0>(s, red);
+  t = block_reduce<0>(t, red);
+  if (threadIdx.x == 0) {
+    out[0] = s;
+    out[1] = t;
+  }
+}
+
+hipError_t launch_trace(const double* H, const double* P, int64_t nvals, const int64_t* diag_idx,
+                        int64_t ndiag, double* partials, int nblocks, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(trace_partial_kernel, dim3(nblocks), dim3(256), 0, s, H, P, nvals, diag_idx,
+                     ndiag, partials);
+  hipLaunchKernelGGL(trace_final_kernel, dim3(1), dim3(256), 0, s, partials, nblocks, out2);
+  return hipGetLastError();
+}
+
+// Electron count of submatrix i: trace of P_ii = 1/2 (I - X_ii) read from X.
+template <typename T>
+__global__ void ne_kernel(DevPlan p, int g0, int nsub, const T* __restrict__ mats,
+                          const SubState* __restrict__ st, double* __restrict__ ne) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nsub) return;
+  const int g = g0 + l;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int loc = p.loc[i];
+  const int b = p.bs[i];
+  const T* X = final_x(p, g, mats, st, l);
+  double s = 0.0;
+  for (int q = 0; q < b; ++q) s += 0.5 * (1.0 - (double)X[(int64_t)(loc + q) * npad + loc + q]);
+  ne[i] = s;
+}
+
+hipError_t launch_ne_from_x(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                            const SubState* st, double* ne_parts, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  const int grid = (nsub + 255) / 256;
+  if (storage_f64)
+    hipLaunchKernelGGL(ne_kernel<double>, dim3(grid), dim3(256), 0, s, p, g0, nsub,
+                       (const double*)mats, st, ne_parts);
+  else
+    hipLaunchKernelGGL(ne_kernel<float>, dim3(grid), dim3(256), 0, s, p, g0, nsub,
+                       (const float*)mats, st, ne_parts);
+  return hipGetLastError();
+}
+
+// Global Gershgorin discs of H, one workgroup per block column c: for every
+// orbital column q, [h_qq - R_q, h_qq + R_q] with R_q the off-diagonal abs sum
+// (column sums equal row sums since H is symmetric).  Writes min / max per c.
+__global__ __launch_bounds__(256) void gersh_kernel(DevPlan p, const double* __restrict__ H,
+                                                    double* __restrict__ out) {
+  __shared__ double red[8];
+  const int c = blockIdx.x;
+  const int h = p.height[c];
+  const int b = p.bs[c];
+  const int loc = p.loc[c];
+  const double* panel = H + p.panel_off[c];
+  double lo = 1e300, hi = -1e300;
+  for (int q = 0; q < b; ++q) {
+    double s = 0.0;
+    for (int d = threadIdx.x; d < h; d += blockDim.x) s += fabs(panel[(int64_t)q * h + d]);
+    s = block_reduce<0>(s, red);
+    const double dg = panel[(int64_t)q * h + loc + q];
+    const double R = s - fabs(dg);
+    lo = fmin(lo, dg - R);
+    hi = fmax(hi, dg + R);
+  }
+  if (threadIdx.x == 0) {
+    out[2 * c] = lo;
+    out[2 * c + 1] = hi;
+  }
+}
+
+hipError_t launch_gersh_rows(const DevPlan& p, int n_atoms, const double* H, double* lohi_parts,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(gersh_kernel, dim3(n_atoms), dim3(256), 0, s, p, H, lohi_parts);
+  return hipGetLastError();
+}
+
+}  // namespace sm

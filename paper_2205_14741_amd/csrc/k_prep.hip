@@ -1,0 +1,287 @@
+// Step 1 of the submatrix method (Fig. 2 of the paper): build every dense
+// principal submatrix T_i = H[idx_i, idx_i] - mu I (Eq. 14 with S = I) straight
+// from the block-column panels of H, then pick the spectral scale c_i and form
+// X_0 = T_i / c_i, the starting point of the sign iteration.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "smsign_internal.h"
+
+namespace sm {
+
+// One workgroup per submatrix.  For every atom j of the index set I_i (one block
+// column of T_i at a time) the workgroup
+//   (a) intersects the stored pattern of H's block column j with I_i by binary
+//       search in LDS and records, for every destination row of T_i, which
+//       panel row of column j supplies it (-1: block not stored -> zero);
+//   (b) writes the b_j columns of T_i top to bottom (coalesced stores; reads
+//       are runs of one contiguous panel column), subtracting mu on the
+//       diagonal, and zero / identity in the padding.
+// LDS: atoms of I_i, their row offsets, and the row map (2 m + n_pad ints).
+template <typename T>
+__global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
+                                                     double mu, T* __restrict__ mats, int* nonfinite) {
+  extern __shared__ int smem[];
+  const int g = g0 + blockIdx.x;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int n = p.height[i];
+  const int64_t k0 = p.col_ptr[i];
+  const int m = (int)(p.col_ptr[i + 1] - k0);
+  int* s_atom = smem;
+  int* s_off = smem + m;
+  int* s_src = smem + 2 * m;
+  T* X = mats + p.mat_off_g[g];
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    s_atom[t] = p.row_idx[k0 + t];
+    s_off[t] = p.blk_rowoff[k0 + t];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int jj = 0; jj < m; ++jj) {
+    const int j = s_atom[jj];
+    const int locj = s_off[jj];
+    const int bj = p.bs[j];
+    const int hj = p.height[j];
+    const int64_t kj0 = p.col_ptr[j];
+    const int mj = (int)(p.col_ptr[j + 1] - kj0);
+    for (int d = threadIdx.x; d < n; d += blockDim.x) s_src[d] = -1;
+    __syncthreads();
+    for (int t = threadIdx.x; t < mj; t += blockDim.x) {
+      const int k = p.row_idx[kj0 + t];
+      int lo = 0, hi = m;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_atom[mid] < k) lo = mid + 1; else hi = mid;
+      }
+      if (lo < m && s_atom[lo] == k) {
+        const int dst = s_off[lo];
+        const int src = p.blk_rowoff[kj0 + t];
+        const int bk = p.bs[k];
+        for (int q = 0; q < bk; ++q) s_src[dst + q] = src + q;
+      }
+    }
+    __syncthreads();
+    const double* panel = H + p.panel_off[j];
+    const int total = bj * npad;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int q = e / npad;
+      const int d = e - q * npad;
+      double v = 0.0;
+      if (d < n) {
+        const int s = s_src[d];
+        if (s >= 0) v = panel[(int64_t)q * hj + s];
+        if (d == locj + q) v -= mu;
+      }
+      bad |= !isfinite(v);
+      X[(int64_t)(locj + q) * npad + d] = (T)v;
+    }
+    __syncthreads();
+  }
+  // identity padding: X stays exactly I on the pad under the iteration
+  const int64_t padcols = (int64_t)(npad - n) * npad;
+  for (int64_t e = threadIdx.x; e < padcols; e += blockDim.x) {
+    const int c = n + (int)(e / npad);
+    const int d = (int)(e - (int64_t)(c - n) * npad);
+    X[(int64_t)c * npad + d] = (T)(d == c ? 1.0 : 0.0);
+  }
+  if (bad) *nonfinite = 1 + i;
+}
+
+hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
+                         const double* H, double mu, void* mats, int storage_f64,
+                         int* nonfinite, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  const size_t lds = (size_t)(2 * max_m + max_npad) * sizeof(int);
+  if (storage_f64)
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
+                       (double*)mats, nonfinite);
+  else
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
+                       (float*)mats, nonfinite);
+  return hipGetLastError();
+}
+
+// One workgroup (8 waves) per submatrix, after the gather:
+//   * column abs sums (= row sums, T symmetric) -> Gershgorin bound c_G and the
+//     16 features of the scaling network;
+//   * optional power iteration (column dots with a vector kept in the
+//     workspace) -> est <= rho(T);
+//   * c_i by the requested rule; X_0 = T_i / c_i on the n x n block (the
+//     identity pad is left as is).
+template <typename T>
+__global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __restrict__ mats,
+                                                      int scaling, int power_steps, double margin,
+                                                      double* __restrict__ vecs,
+                                                      const float* __restrict__ learned_scale,
+                                                      float* __restrict__ features,
+                                                      sm_sub_stats* __restrict__ stats) {
+  __shared__ double red[16];
+  const int l = blockIdx.x;
+  const int g = g0 + l;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int n = p.height[i];
+  const int loc = p.loc[i];
+  const int b = p.bs[i];
+  T* X = mats + p.mat_off_g[g];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+
+  double cmax = 0.0, sdiag = 0.0, sdiag2 = 0.0, mind = 1e300, maxd = -1e300, sR = 0.0, maxR = 0.0;
+  double minabs = 1e300, mingap = 1e300, nneg = 0.0, ssq = 0.0, sown = 0.0, minown = 1e300, sabs = 0.0;
+  for (int c = wid; c < n; c += nw) {
+    const T* col = X + (int64_t)c * npad;
+    double s = 0.0, q = 0.0;
+    for (int d = lane; d < n; d += kWave) {
+      const double v = (double)col[d];
+      s += fabs(v);
+      q += v * v;
+    }
+    s = wave_sum(s);
+    q = wave_sum(q);
+    const double dg = (double)col[c];
+    const double R = s - fabs(dg);
+    cmax = fmax(cmax, s);
+    sdiag += dg;
+    sdiag2 += dg * dg;
+    mind = fmin(mind, dg);
+    maxd = fmax(maxd, dg);
+    sR += R;
+    maxR = fmax(maxR, R);
+    minabs = fmin(minabs, fabs(dg));
+    mingap = fmin(mingap, fabs(dg) - R);
+    nneg += dg < 0.0 ? 1.0 : 0.0;
+    ssq += q;
+    sabs += fabs(dg);
+    if (c >= loc && c < loc + b) {
+      sown += dg;
+      minown = fmin(minown, fabs(dg));
+    }
+  }
+  // every lane of a wave holds identical values; reduce across waves
+  cmax = block_reduce<1>(lane == 0 ? cmax : 0.0, red);
+  sdiag = block_reduce<0>(lane == 0 ? sdiag : 0.0, red);
+  sdiag2 = block_reduce<0>(lane == 0 ? sdiag2 : 0.0, red);
+  mind = block_reduce<2>(lane == 0 ? mind : 1e300, red);
+  maxd = block_reduce<1>(lane == 0 ? maxd : -1e300, red);
+  sR = block_reduce<0>(lane == 0 ? sR : 0.0, red);
+  maxR = block_reduce<1>(lane == 0 ? maxR : 0.0, red);
+  minabs = block_reduce<2>(lane == 0 ? minabs : 1e300, red);
+  mingap = block_reduce<2>(lane == 0 ? mingap : 1e300, red);
+  nneg = block_reduce<0>(lane == 0 ? nneg : 0.0, red);
+  ssq = block_reduce<0>(lane == 0 ? ssq : 0.0, red);
+  sown = block_reduce<0>(lane == 0 ? sown : 0.0, red);
+  minown = block_reduce<2>(lane == 0 ? minown : 1e300, red);
+  sabs = block_reduce<0>(lane == 0 ? sabs : 0.0, red);
+  const double cG = cmax > 0.0 ? cmax : 1.0;
+
+  // power iteration on T: v_{k+1} = T v_k / ||T v_k||, est = ||T v_k|| (<= rho)
+  double est = 0.0;
+  if (scaling != SM_SCALE_GERSHGORIN && power_steps > 0) {
+    double* v = vecs + p.vec_off_g[g];
+    double* w = v + npad;
+    double nv = 0.0;
+    for (int d = threadIdx.x; d < n; d += blockDim.x) {
+      const double x = probe_entry(11, d);
+      v[d] = x;
+      nv += x * x;
+    }
+    nv = block_reduce<0>(nv, red);
+    double inv = 1.0 / sqrt(nv);
+    for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] *= inv;
+    __syncthreads();
+    for (int it = 0; it < power_steps; ++it) {
+      for (int c = wid; c < n; c += nw) {
+        const T* col = X + (int64_t)c * npad;
+        double s = 0.0;
+        for (int d = lane; d < n; d += kWave) s += (double)col[d] * v[d];
+        s = wave_sum(s);
+        if (lane == 0) w[c] = s;
+      }
+      __syncthreads();
+      double nw2 = 0.0;
+      for (int d = threadIdx.x; d < n; d += blockDim.x) nw2 += w[d] * w[d];
+      nw2 = block_reduce<0>(nw2, red);
+      est = sqrt(nw2);
+      inv = est > 0.0 ? 1.0 / est : 0.0;
+      for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] = w[d] * inv;
+      __syncthreads();
+    }
+  }
+
+  double c = cG;
+  int src = 0;
+  if (scaling == SM_SCALE_POWER && est > 0.0) {
+    c = fmin(cG, (1.0 + margin) * est);
+    src = 1;
+  } else if (scaling == SM_SCALE_LEARNED) {
+    const double cp = learned_scale ? (double)learned_scale[l] : 0.0;
+    if (cp > 0.0 && isfinite(cp) && cp >= (1.0 + margin) * est && cp <= cG) {
+      c = cp;
+      src = 2;
+    } else {
+      src = 3;
+    }
+  }
+  const double sc = 1.0 / c;
+  for (int cc = wid; cc < n; cc += nw) {
+    T* col = X + (int64_t)cc * npad;
+    for (int d = lane; d < n; d += kWave) col[d] = (T)((double)col[d] * sc);
+  }
+  if (threadIdx.x == 0) {
+    const double nn = (double)n;
+    float* f = features + (int64_t)l * kNumFeatures;
+    const double mean = sdiag / nn;
+    f[0] = (float)log(nn);
+    f[1] = (float)log(cG);
+    f[2] = (float)(mean / cG);
+    f[3] = (float)(sqrt(fmax(sdiag2 / nn - mean * mean, 0.0)) / cG);
+    f[4] = (float)(mind / cG);
+    f[5] = (float)(maxd / cG);
+    f[6] = (float)(sR / nn / cG);
+    f[7] = (float)(maxR / cG);
+    f[8] = (float)(minabs / cG);
+    f[9] = (float)(mingap / cG);
+    f[10] = (float)(nneg / nn);
+    f[11] = (float)(sqrt(ssq) / (cG * sqrt(nn)));
+    f[12] = (float)(b / nn);
+    f[13] = (float)(sown / b / cG);
+    f[14] = (float)(minown / cG);
+    f[15] = (float)(sabs / nn / cG);
+    sm_sub_stats& r = stats[i];
+    r.scale = c;
+    r.scale_src = src;
+    r.res_probe = est;   // overwritten by the final probe; keeps the estimate if probes are off
+  }
+}
+
+hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64,
+                          int scaling, int power_steps, double margin, double* vecs,
+                          const float* learned_scale, float* features, SubState* /*st*/,
+                          sm_sub_stats* stats, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  if (storage_f64)
+    hipLaunchKernelGGL(analyze_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats,
+                       scaling, power_steps, margin, vecs, learned_scale, features, stats);
+  else
+    hipLaunchKernelGGL(analyze_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats,
+                       scaling, power_steps, margin, vecs, learned_scale, features, stats);
+  return hipGetLastError();
+}
+
+__global__ void fill_i32_kernel(int32_t* dst, int32_t value, int64_t count) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < count;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = value;
+}
+
+hipError_t launch_fill_i32(int32_t* dst, int32_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int grid = (int)((count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid), dim3(256), 0, s, dst, value, count);
+  return hipGetLastError();
+}
+
+}  // namespace sm

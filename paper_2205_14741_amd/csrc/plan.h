@@ -1,0 +1,72 @@
+// Host-side plan object and error helpers (internal).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "smsign_internal.h"
+
+struct sm_plan {
+  // pattern (copied from the caller)
+  int32_t n_atoms = 0;
+  int64_t nnzb = 0;
+  int64_t nvals = 0;
+  std::vector<int32_t> bs;
+  std::vector<int64_t> col_ptr;
+  std::vector<int32_t> row_idx;
+  std::vector<int64_t> panel_off;
+  // derived, per atom
+  std::vector<int32_t> blk_rowoff;  // [nnzb]
+  std::vector<int32_t> height;      // panel height = submatrix size n_i
+  std::vector<int32_t> loc;         // offset of the atom's own rows in its panel
+  std::vector<int32_t> npad;
+  std::vector<int64_t> diag_idx;    // [N] position of every diagonal entry in vals
+  // processing order and chunks
+  int32_t pad_to = sm::kTile;
+  std::vector<int32_t> order_g;     // submatrix id at processing index g
+  std::vector<int32_t> npad_g;
+  std::vector<int64_t> mat_off_g;   // element offset inside the chunk
+  std::vector<int32_t> tile_off_g;  // residual-partial offset inside the chunk
+  std::vector<int64_t> vec_off_g;   // probe / power vector offset inside the chunk
+  std::vector<int32_t> chunk_of;    // [n_atoms] chunk of every submatrix
+  std::vector<int64_t> chunk_ptr;   // [n_chunks+1] ranges of g
+  int64_t max_mats = 0;             // max over chunks of sum 3 npad^2
+  int64_t max_subs = 0;
+  int64_t max_tiles = 0;
+  int64_t max_vecs = 0;             // max over chunks of sum npad * 2 * kMaxProbes
+  int32_t max_m = 0;                // largest index-set size (atoms)
+  int32_t max_npad = 0;
+
+  // device copies (allocated on first device use)
+  int device = -1;
+  sm::DevPlan dev{};
+  std::vector<void*> dev_allocs;
+  int64_t* d_diag_idx = nullptr;
+  double* d_trace_parts = nullptr;  // [2 * kTraceBlocks + 2]
+  double* d_ne_sub = nullptr;       // [n_atoms]
+  double* d_gersh = nullptr;        // [2 * n_atoms]
+  int32_t* h_pinned = nullptr;      // pinned host counters [8]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int last_f64 = -1;                // storage precision of the last build (-1: none)
+  // kernel timing (sm_profile_enable)
+  bool profiling = false;
+  std::vector<hipEvent_t> prof_ev;  // pool, pairs (start, stop)
+  std::vector<int> prof_cls;        // class of every recorded pair
+
+  sm::WsLayout layout(int storage_f64) const;
+};
+
+namespace sm {
+constexpr int kTraceBlocks = 512;
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+int ensure_device(sm_plan* p);
+int storage_is_f64(const sm_sign_opts* o);
+}  // namespace sm
+
+#define SM_HIP(expr)                                         \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return sm::hip_error(_e, #expr);   \
+  } while (0)

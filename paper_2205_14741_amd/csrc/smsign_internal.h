@@ -1,0 +1,89 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/smsign.h"
+
+namespace sm {
+
+constexpr int kTile = 64;          // output tile edge of the Newton-Schulz GEMMs
+constexpr int kNumFeatures = 16;   // per-submatrix features for the scaling network
+constexpr int kMaxProbes = 8;
+
+// Device view of the plan.  Arrays named *_g are indexed by the processing
+// index g (submatrices in chunk order); the rest by atom id.
+struct DevPlan {
+  const int32_t* bs;         // [n_atoms] block sizes
+  const int64_t* col_ptr;    // [n_atoms+1]
+  const int32_t* row_idx;    // [nnzb]
+  const int64_t* panel_off;  // [n_atoms+1]
+  const int32_t* blk_rowoff; // [nnzb] row offset of stored block k inside its panel
+  const int32_t* height;     // [n_atoms] panel height h_c (= n of submatrix c)
+  const int32_t* loc;        // [n_atoms] row offset of the diagonal block in panel c
+  const int32_t* order_g;    // [n_atoms] submatrix (atom) id at processing index g
+  const int32_t* npad_g;     // [n_atoms] padded size
+  const int64_t* mat_off_g;  // [n_atoms] element offset of the submatrix's 3 buffers in its chunk
+  const int32_t* tile_off_g; // [n_atoms] offset of its residual partials in its chunk
+  const int64_t* vec_off_g;  // [n_atoms] offset of its probe / power vectors in its chunk
+};
+
+// Per-submatrix iteration state (indexed by local index inside the chunk).
+struct SubState {
+  int32_t active;      // 1 while the submatrix still iterates
+  int32_t phase;       // 0 main phase, 1 refinement
+  int32_t iters;       // updates applied (parity selects the buffer holding X)
+  int32_t iters_low;   // updates in the main phase
+  int32_t refine_left; // refinement updates still to apply
+  int32_t status;
+  double res;          // last residual
+  double res_prev;     // residual before that
+};
+
+// Workspace layout (bytes) for one chunk, given the storage element size.
+struct WsLayout {
+  int64_t mats;        // 3 * sum npad^2 elements
+  int64_t state;       // SubState[max_subs]
+  int64_t partials;    // double[max_tiles]
+  int64_t lists;       // int32: counts[4], list[2][max_subs], prefix[2][max_subs+1]
+  int64_t features;    // float[max_subs * kNumFeatures]
+  int64_t scratch;     // double[max_subs * 4] (power iteration, probes)
+  int64_t vecs;        // double[sum over chunk of npad * kMaxProbes*2] probe / power vectors
+  int64_t flag;        // int32 nonfinite flag + padding
+  int64_t total;
+};
+
+// Launchers (k_*.hip).  All return hipError_t from hipGetLastError.
+hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
+                         const double* H, double mu, void* mats, int storage_f64,
+                         int* nonfinite, hipStream_t s);
+hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64,
+                          int scaling, int power_steps, double margin, double* vecs,
+                          const float* learned_scale, float* features, SubState* st,
+                          sm_sub_stats* stats, hipStream_t s);
+hipError_t launch_ns_init(int nsub, SubState* st, hipStream_t s);
+hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
+                           const double* partials, int32_t* lists, int max_subs,
+                           const sm_sign_opts& o, int first, sm_sub_stats* stats,
+                           hipStream_t s);
+hipError_t launch_ns_gemm(int mode, int which, const DevPlan& p, int g0, void* mats,
+                          const SubState* st, const int32_t* count, const int32_t* list,
+                          const int32_t* prefix, double* partials, int grid, hipStream_t s);
+hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                         const SubState* st, int probes, double* vecs, sm_sub_stats* stats,
+                         hipStream_t s);
+hipError_t launch_scatter(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                          const SubState* st, double* P, hipStream_t s);
+hipError_t launch_trace(const double* H, const double* P, int64_t nvals, const int64_t* diag_idx,
+                        int64_t ndiag, double* partials, int nblocks, double* out2,
+                        hipStream_t s);
+hipError_t launch_ne_from_x(const DevPlan& p, int g0, int nsub, const void* mats,
+                            int storage_f64, const SubState* st, double* ne_parts,
+                            hipStream_t s);
+hipError_t launch_gersh_rows(const DevPlan& p, int n_atoms, const double* H, double* lohi_parts,
+                             hipStream_t s);
+hipError_t launch_fill_i32(int32_t* dst, int32_t value, int64_t count, hipStream_t s);
+hipError_t launch_selftest_mfma(int prec, double* out_dev, hipStream_t s);
+
+}  // namespace sm

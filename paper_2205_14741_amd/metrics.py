@@ -1,0 +1,57 @@
+"""Flop accounting of the Newton-Schulz passes from the per-submatrix records.
+
+A pass over submatrix i of size n (padded to np) runs, per precision phase,
+some squares (A = X^2, Y = 3I - A) and updates (X' = 1/2 X Y).  Every product
+is symmetric, so the kernels compute the tiles on and below the diagonal only:
+
+    useful flops of one product  = n^2 (n + 1)       (n(n+1)/2 entries x 2n)
+    issued MFMA flops            = T(T+1)/2 * 2 * 64 * 64 * np,  T = np / 64
+
+With a refinement phase of r steps (status 2) the counts are
+    main precision:   squares = iters_low + 1, updates = iters_low
+    refinement:       squares = r - 1,         updates = r
+and without one (status 0 / 1): squares = iters + 1, updates = iters.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PEAK_TFLOPS = {0: 78.6, 1: 157.3, 2: 2500.0, 3: 2500.0, 4: 2500.0}   # MI355X dense matrix peaks
+
+
+def product_counts(stats: np.ndarray, opts) -> dict:
+    """{(precision, kind): per-submatrix product counts}; kind 0 square, 1 update."""
+    iters = stats["iters"].astype(np.int64)
+    low = stats["iters_low"].astype(np.int64)
+    r = int(opts.refine_steps)
+    refined = (stats["status"] == 2)
+    out = {}
+    main_sq = np.where(refined, low + 1, iters + 1)
+    main_up = np.where(refined, low, iters)
+    out[(int(opts.phase1), 0)] = main_sq
+    out[(int(opts.phase1), 1)] = main_up
+    if r > 0:
+        ref_up = np.where(refined, iters - low, 0)
+        ref_sq = np.where(refined, np.maximum(ref_up - 1, 0), 0)
+        key_sq = (int(opts.refine), 0)
+        key_up = (int(opts.refine), 1)
+        out[key_sq] = out.get(key_sq, 0) + ref_sq
+        out[key_up] = out.get(key_up, 0) + ref_up
+    return out
+
+
+def flops_by_class(stats: np.ndarray, n: np.ndarray, npad: np.ndarray, opts):
+    """{(precision, kind): (useful flops, issued MFMA flops)} of one pass."""
+    n = n.astype(np.float64)
+    T = (npad // 64).astype(np.float64)
+    useful_one = n * n * (n + 1.0)
+    issued_one = T * (T + 1) / 2 * 2 * 64 * 64 * npad.astype(np.float64)
+    res = {}
+    for key, cnt in product_counts(stats, opts).items():
+        cnt = np.asarray(cnt, dtype=np.float64)
+        res[key] = (float((cnt * useful_one).sum()), float((cnt * issued_one).sum()))
+    return res
+
+
+def useful_flops(stats, n, npad, opts) -> float:
+    return sum(v[0] for v in flops_by_class(stats, n, npad, opts).values())

@@ -1,0 +1,287 @@
+"""Thin ctypes binding of libsmsign.so (the C ABI declared in include/smsign.h).
+
+Only argument marshalling lives here: every step of the method runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory and the stream.
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmsign.so")
+
+SM_OK, SM_ERR_ARG, SM_ERR_HIP, SM_ERR_NONFINITE, SM_ERR_OOM, SM_ERR_STATE = 0, -1, -2, -3, -4, -5
+SM_F64, SM_F32, SM_BF16, SM_F16, SM_BF16X3 = 0, 1, 2, 3, 4
+PREC = {"f64": SM_F64, "f32": SM_F32, "bf16": SM_BF16, "f16": SM_F16, "bf16x3": SM_BF16X3}
+SM_SCALE_GERSHGORIN, SM_SCALE_POWER, SM_SCALE_LEARNED = 0, 1, 2
+
+EXPORTED = (
+    "sm_default_opts", "sm_plan_create", "sm_plan_destroy", "sm_plan_sizes", "sm_plan_info",
+    "sm_plan_ws_layout", "build_submatrices", "submatrix_sign", "assemble_P", "energy_trace",
+    "sm_density_matrix", "sm_find_mu", "sm_gershgorin_bracket", "sm_selftest_mfma",
+    "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
+)
+
+
+class SmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"smsign error {code}: {msg}")
+        self.code = code
+
+
+class BsrPattern(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("block_size", C.c_void_p), ("col_ptr", C.c_void_p),
+                ("row_idx", C.c_void_p), ("panel_off", C.c_void_p)]
+
+
+class SignOpts(C.Structure):
+    _fields_ = [("phase1", C.c_int32), ("refine", C.c_int32), ("refine_steps", C.c_int32),
+                ("max_iter", C.c_int32), ("tol", C.c_double), ("switch_tol", C.c_double),
+                ("stall_below", C.c_double), ("stall_ratio", C.c_double), ("scaling", C.c_int32),
+                ("power_steps", C.c_int32), ("scale_margin", C.c_double), ("probes", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def copy(self) -> "SignOpts":
+        o = SignOpts()
+        C.pointer(o)[0] = self
+        return o
+
+
+class SubStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("iters_low", C.c_int32), ("status", C.c_int32),
+                ("scale_src", C.c_int32), ("scale", C.c_double), ("res", C.c_double),
+                ("res_probe", C.c_double)]
+
+
+STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"),
+                        ("scale_src", "<i4"), ("scale", "<f8"), ("res", "<f8"),
+                        ("res_probe", "<f8")])
+assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 40
+assert C.sizeof(SignOpts) == 72
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libsmsign.so once; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2205_14741_amd.build` "
+                          "(hipcc, gfx950); there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "sm_default_opts": (i32, [i32, C.POINTER(SignOpts)]),
+        "sm_plan_create": (i32, [C.POINTER(BsrPattern), i32, i64, C.POINTER(vp)]),
+        "sm_plan_destroy": (None, [vp]),
+        "sm_plan_sizes": (i32, [vp, i32, vp, vp, vp, vp]),
+        "sm_plan_info": (i32, [vp, vp, vp, vp, vp, vp]),
+        "sm_plan_ws_layout": (i32, [vp, i32, vp, vp]),
+        "build_submatrices": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, vp]),
+        "submatrix_sign": (i32, [vp, i32, vp, C.POINTER(SignOpts), vp, vp]),
+        "assemble_P": (i32, [vp, i32, vp, vp, vp]),
+        "energy_trace": (i32, [vp, vp, vp, vp, vp, vp]),
+        "sm_density_matrix": (i32, [vp, vp, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp]),
+        "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "sm_gershgorin_bracket": (i32, [vp, vp, vp, vp, vp]),
+        "sm_selftest_mfma": (i32, [i32, vp]),
+        "sm_profile_enable": (i32, [vp, i32]),
+        "sm_profile_read": (i32, [vp, vp, vp]),
+        "sm_last_error": (C.c_char_p, []),
+        "sm_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SM_OK:
+        raise SmError(rc, lib().sm_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def default_opts(prec="f64", **kw) -> SignOpts:
+    o = SignOpts()
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(lib().sm_default_opts(p, C.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def storage_prec(opts: SignOpts) -> int:
+    if opts.phase1 == SM_F64 or (opts.refine_steps > 0 and opts.refine == SM_F64):
+        return SM_F64
+    return SM_F32
+
+
+class Plan:
+    """Symbolic plan over a block pattern (host arrays are copied by the library)."""
+
+    def __init__(self, m, pad_to: int = 64, max_chunk_elems: int = 0):
+        self.n_atoms = int(m.block_size.shape[0])
+        self._bs = np.ascontiguousarray(m.block_size, dtype=np.int32)
+        self._cp = np.ascontiguousarray(m.col_ptr, dtype=np.int64)
+        self._ri = np.ascontiguousarray(m.row_idx, dtype=np.int32)
+        self._po = np.ascontiguousarray(m.panel_off, dtype=np.int64)
+        pat = BsrPattern(self.n_atoms, self._bs.ctypes.data, self._cp.ctypes.data,
+                         self._ri.ctypes.data, self._po.ctypes.data)
+        h = C.c_void_p()
+        _check(lib().sm_plan_create(C.byref(pat), int(pad_to), int(max_chunk_elems), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().sm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sizes(self, storage: int):
+        v = [C.c_int64() for _ in range(4)]
+        _check(lib().sm_plan_sizes(self.handle, int(storage), *[C.byref(x) for x in v]))
+        return tuple(int(x.value) for x in v)  # n_sub, n_chunks, ws_bytes, nvals
+
+    def info(self) -> dict:
+        n = self.n_atoms
+        out = {k: np.zeros(n, np.int32) for k in ("n", "npad", "loc", "chunk", "order")}
+        _check(lib().sm_plan_info(self.handle, *[out[k].ctypes.data for k in
+                                                 ("n", "npad", "loc", "chunk", "order")]))
+        return out
+
+    def ws_layout(self, storage: int):
+        reg = np.zeros(9, np.int64)
+        off = np.zeros(self.n_atoms, np.int64)
+        _check(lib().sm_plan_ws_layout(self.handle, int(storage), reg.ctypes.data, off.ctypes.data))
+        return reg, off
+
+    @property
+    def n_chunks(self) -> int:
+        return self.sizes(SM_F64)[1]
+
+
+# ---- the C entry points, same names ----
+
+def build_submatrices(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, stream=None):
+    _check(lib().build_submatrices(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts),
+                                   _ptr(ws), _ptr(stats), _stream(stream)))
+
+
+def submatrix_sign(plan: Plan, chunk: int, ws, opts: SignOpts, stats, stream=None):
+    _check(lib().submatrix_sign(plan.handle, int(chunk), _ptr(ws), C.byref(opts), _ptr(stats),
+                                _stream(stream)))
+
+
+def assemble_P(plan: Plan, chunk: int, ws, P, stream=None):
+    _check(lib().assemble_P(plan.handle, int(chunk), _ptr(ws), _ptr(P), _stream(stream)))
+
+
+def energy_trace(plan: Plan, H, P, stream=None):
+    E, Ne = C.c_double(), C.c_double()
+    _check(lib().energy_trace(plan.handle, _ptr(H), _ptr(P), C.byref(E), C.byref(Ne), _stream(stream)))
+    return E.value, Ne.value
+
+
+def sm_density_matrix(plan: Plan, H, mu: float, opts: SignOpts, ws, P, stats, stream=None):
+    E, Ne = C.c_double(), C.c_double()
+    _check(lib().sm_density_matrix(plan.handle, _ptr(H), float(mu), C.byref(opts), _ptr(ws), _ptr(P),
+                                   _ptr(stats), C.byref(E), C.byref(Ne), _stream(stream)))
+    return E.value, Ne.value
+
+
+def sm_find_mu(plan: Plan, H, n_target: float, opts: SignOpts, ws, stats, P=None, accept=0.5,
+               max_steps=60, stream=None):
+    mu = C.c_double()
+    steps = C.c_int32()
+    mh = np.zeros(max_steps)
+    nh = np.zeros(max_steps)
+    _check(lib().sm_find_mu(plan.handle, _ptr(H), float(n_target), float(accept), int(max_steps),
+                            C.byref(opts), _ptr(ws), _ptr(P), _ptr(stats), C.byref(mu),
+                            C.byref(steps), mh.ctypes.data, nh.ctypes.data, _stream(stream)))
+    k = steps.value
+    return mu.value, k, list(zip(mh[:k].tolist(), nh[:k].tolist()))
+
+
+def sm_gershgorin_bracket(plan: Plan, H, stream=None):
+    lo, hi = C.c_double(), C.c_double()
+    _check(lib().sm_gershgorin_bracket(plan.handle, _ptr(H), C.byref(lo), C.byref(hi), _stream(stream)))
+    return lo.value, hi.value
+
+
+def sm_selftest_mfma(prec) -> np.ndarray:
+    out = np.zeros(256)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(lib().sm_selftest_mfma(p, out.ctypes.data))
+    return out
+
+
+def sm_profile_enable(plan: Plan, on: bool = True):
+    _check(lib().sm_profile_enable(plan.handle, 1 if on else 0))
+
+
+def sm_profile_read(plan: Plan):
+    """(launches[10], ms[10]) per class 2 * precision + kind."""
+    n = np.zeros(10, np.int64)
+    t = np.zeros(10)
+    _check(lib().sm_profile_read(plan.handle, n.ctypes.data, t.ctypes.data))
+    return n, t
+
+
+def version() -> str:
+    return lib().sm_version().decode()
+
+
+# ---- convenience: buffers owned by torch ----
+
+class Workspace:
+    """Device buffers for one plan and one storage precision (torch-owned)."""
+
+    def __init__(self, plan: Plan, storage: int, device="cuda"):
+        import torch
+        n_sub, n_chunks, ws_bytes, nvals = plan.sizes(storage)
+        self.plan = plan
+        self.storage = storage
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=device)
+        self.stats = torch.zeros(n_sub * STATS_DTYPE.itemsize, dtype=torch.uint8, device=device)
+        self.P = torch.zeros(nvals, dtype=torch.float64, device=device)
+
+    def stats_host(self) -> np.ndarray:
+        return self.stats.cpu().numpy().view(STATS_DTYPE)
+
+
+def density_matrix(plan: Plan, H, mu: float, opts: SignOpts, work: Workspace | None = None,
+                   stream=None):
+    """P, E = tr(PH), Ne = tr P and the per-submatrix records at fixed mu."""
+    work = work or Workspace(plan, storage_prec(opts), H.device)
+    E, Ne = sm_density_matrix(plan, H, mu, opts, work.ws, work.P, work.stats, stream)
+    return work.P, E, Ne, work.stats_host()

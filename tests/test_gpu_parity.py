@@ -1,0 +1,219 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Float64 path: every stored entry of P within 1e-9 of the oracle (Newton-Schulz
+stops at ||X^2 - I||_F < 1e-10, so ||X - sign|| ~ 5e-11), energies within
+1e-11 relative.  Float32 and the low-precision schedules: the bar of the
+workload, relative energy error <= 1e-5 and max |dP| <= 1e-4, is asserted for
+the schedules expected to meet it (float32, split-bf16 + float32 refinement);
+plain bf16 and fp16 are measured and bounded loosely (their error floors are
+reported, not hidden).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import submatrix as om
+from oracle import newton_schulz as ons
+from paper_2205_14741_amd import smsign as sm
+from gpu_helpers import run_fixed_mu, gap_mu, rel, h_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16", "bf16"])
+def test_mfma_lane_layout(prec, dev):
+    out = sm.sm_selftest_mfma(prec)
+    K = 4 if prec in ("f64", "f32") else 32
+    A = np.array([[((r + 3 * k) % 11) - 5 for k in range(K)] for r in range(16)], float)
+    B = np.array([[((2 * k + 5 * c) % 13) - 6 for c in range(16)] for k in range(K)], float)
+    D = A @ B
+    assert len(np.unique(D)) > 40
+    # float64: register v of lane l holds row l/16 + 4v; float32 accumulators: 4 (l/16) + v
+    row = (lambda l, v: l // 16 + 4 * v) if prec == "f64" else (lambda l, v: 4 * (l // 16) + v)
+    expect = np.array([D[row(l, v), l % 16] for l in range(64) for v in range(4)])
+    np.testing.assert_array_equal(out, expect)
+
+
+def _oracle_T_scaled(view, i, mu, c):
+    return om.submatrix(view, i, mu) * (1.0 / c)
+
+
+@pytest.mark.parametrize("make", [synth.config1, lambda: synth.water_system(16, 1.5, 3)])
+def test_gather_and_gershgorin(make, dev):
+    """X_0 = (H[idx, idx] - mu I) / c is bit-exact in float64; the identity
+    pad is exact; c is the Gershgorin bound of T."""
+    import torch
+    m = make()
+    mu = 0.137
+    plan = sm.Plan(m, 64)
+    o = sm.default_opts("f64")
+    H = h_dev(m)
+    work = sm.Workspace(plan, sm.SM_F64, H.device)
+    sm.build_submatrices(plan, 0, H, mu, o, work.ws, work.stats)
+    torch.cuda.synchronize()
+    reg, off = plan.ws_layout(sm.SM_F64)
+    ws = work.ws.cpu().numpy()
+    mats = ws[reg[0]:reg[1]].view(np.float64)
+    st = work.stats_host()
+    info = plan.info()
+    view = om.BlockView(m)
+    for g in range(m.n_atoms):
+        i = info["order"][g]
+        n, npad = info["n"][i], info["npad"][i]
+        X = mats[off[g]:off[g] + npad * npad].reshape(npad, npad).T   # column-major
+        T = om.submatrix(view, i, mu)
+        c = st["scale"][i]
+        assert rel(c, om.gershgorin_bound(T)) < 1e-14
+        np.testing.assert_array_equal(X[:n, :n], T * (1.0 / c))
+        np.testing.assert_array_equal(X[n:, n:], np.eye(npad - n))
+        assert not X[:n, n:].any() and not X[n:, :n].any()
+
+
+def _compare(m, P, E, Ne, mu, atoms=None):
+    Po = om.density_matrix(m, mu, atoms=atoms)
+    mask = ~np.isnan(Po)
+    dP = np.max(np.abs(P[mask] - Po[mask]))
+    if atoms is None:
+        Eo, Neo = om.energy_trace(m, Po)
+        return dP, rel(E, Eo), abs(Ne - Neo)
+    return dP, None, None
+
+
+def test_config1_f64(dev):
+    m = synth.config1()
+    mu = gap_mu(m)
+    P, E, Ne, st, _ = run_fixed_mu(m, mu, "f64")
+    dP, dE, dNe = _compare(m, P, E, Ne, mu)
+    assert dP < 1e-9 and dE < 1e-11 and dNe < 1e-9, (dP, dE, dNe)
+    assert np.all(st["status"] == 1) and np.all(st["res"] < 1e-10)
+    assert np.all(st["res_probe"] < 1e-9)
+    # iteration counts of the plain float64 iteration from the same X_0
+    view = om.BlockView(m)
+    for i in (0, 17, 63):
+        T = om.submatrix(view, i, mu)
+        _, k, _ = ons.ns_sign(T, st["scale"][i], tol=1e-10)
+        assert abs(int(st["iters"][i]) - k) <= 1
+
+
+def test_water_multi_tile_f64(dev):
+    """Uneven blocks (13/5 orbitals), several 64-tiles per submatrix, ragged n."""
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, "f64")
+    info = plan.info()
+    assert info["npad"].max() >= 192 and len(set(info["n"] % 64)) > 3
+    dP, dE, dNe = _compare(m, P, E, Ne, mu)
+    assert dP < 1e-9 and dE < 1e-11 and dNe < 1e-9, (dP, dE, dNe)
+
+
+def test_chunked_equals_single_chunk(dev):
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    P1, E1, N1, _, _ = run_fixed_mu(m, mu, "f64")
+    P2, E2, N2, _, plan = run_fixed_mu(m, mu, "f64", max_chunk_elems=3 * 256 * 256 * 5)
+    assert plan.n_chunks > 3
+    np.testing.assert_array_equal(P1, P2)
+    assert E1 == E2 and N1 == N2
+
+
+def test_deterministic(dev):
+    m = synth.water_system(16, 1.5, 3)
+    mu = gap_mu(m)
+    runs = [run_fixed_mu(m, mu, "bf16x3") for _ in range(3)]
+    for P, E, Ne, _, _ in runs[1:]:
+        np.testing.assert_array_equal(P, runs[0][0])
+        assert E == runs[0][1] and Ne == runs[0][2]
+
+
+@pytest.mark.parametrize("prec,dp_max,de_max", [
+    ("f32", 1e-4, 1e-5),
+    ("bf16x3", 1e-4, 1e-5),
+    ("f16", 5e-3, 1e-3),
+    ("bf16", 5e-2, 1e-2),
+])
+def test_precision_schedules_water(prec, dp_max, de_max, dev):
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    P, E, Ne, st, _ = run_fixed_mu(m, mu, prec)
+    dP, dE, dNe = _compare(m, P, E, Ne, mu)
+    print(f"{prec}: max|dP| {dP:.3e} rel dE {dE:.3e} dNe {dNe:.3e} iters "
+          f"{st['iters'].min()}-{st['iters'].max()} low {st['iters_low'].min()}-{st['iters_low'].max()} "
+          f"probe {st['res_probe'].max():.2e}")
+    assert dP < dp_max and dE < de_max, (dP, dE)
+
+
+def test_find_mu_config1(dev):
+    import torch
+    m = synth.config1()
+    mu_o, steps_o, hist_o = om.find_mu(m, m.n_occ)
+    plan = sm.Plan(m, 64)
+    o = sm.default_opts("f64", max_iter=60)
+    H = h_dev(m)
+    work = sm.Workspace(plan, sm.SM_F64, H.device)
+    lo, hi = sm.sm_gershgorin_bracket(plan, H)
+    lo_o, hi_o = om.global_gershgorin_bracket(m)
+    assert rel(lo, lo_o) < 1e-14 and rel(hi, hi_o) < 1e-14
+    mu, steps, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P)
+    assert steps == steps_o
+    for (a, na), (b, nb) in zip(hist, hist_o):
+        assert abs(a - b) < 1e-12 and abs(na - nb) < 1e-8
+    E, Ne = sm.energy_trace(plan, H, work.P)
+    Po = om.density_matrix(m, mu)
+    Eo, Neo = om.energy_trace(m, Po)
+    assert rel(E, Eo) < 1e-11
+
+
+def _read_bufs(plan, work, storage, g):
+    reg, off = plan.ws_layout(storage)
+    dt = np.float64 if storage == sm.SM_F64 else np.float32
+    mats = work.ws.cpu().numpy()[reg[0]:reg[1]].view(dt)
+    npad = plan.info()["npad"][plan.info()["order"][g]]
+    nn = npad * npad
+    return [mats[off[g] + b * nn: off[g] + (b + 1) * nn].reshape(npad, npad).T.astype(np.float64)
+            for b in range(3)]
+
+
+# unit roundoff of one product in each schedule (operand rounding; accumulation
+# is float32 except for f64)
+_U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16x3": 2.0 ** -17, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "f16", "bf16"])
+def test_single_iteration_accuracy(prec, dev):
+    """One Newton-Schulz step on the GPU against float64 products of the
+    GPU's own X_0: Y_0 = 3I - X_0^2 (square kernel) and X_1 = 1/2 X_0 Y_0
+    (update kernel), within the deterministic bound 2 (k u + u_acc k) |A||B|."""
+    import torch
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    plan = sm.Plan(m, 64)
+    H = h_dev(m)
+    o = sm.default_opts(prec, refine_steps=0, max_iter=1, tol=0.0, stall_below=0.0, probes=0)
+    storage = sm.storage_prec(o)
+    work = sm.Workspace(plan, storage, H.device)
+    sm.build_submatrices(plan, 0, H, mu, o, work.ws, work.stats)
+    sm.submatrix_sign(plan, 0, work.ws, o, work.stats)
+    torch.cuda.synchronize()
+    st = work.stats_host()
+    assert np.all(st["iters"] == 1)
+    u_acc = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
+    worst = []
+    for g in (0, 7, 33):
+        X0, X1, Y1 = _read_bufs(plan, work, storage, g)
+        k = X0.shape[0]
+        I = np.eye(k)
+        Y0 = 3 * I - X0 @ X0
+        X1_ref = 0.5 * X0 @ Y0
+        bound = (k * _U[prec] * 2 + k * u_acc) * (0.5 * np.abs(X0) @ np.abs(Y0)) + 1e-30
+        err = np.abs(X1 - X1_ref)
+        Y1_ref = 3 * I - X1 @ X1
+        bY = (k * _U[prec] * 2 + k * u_acc) * (np.abs(X1) @ np.abs(X1)) + 1e-30
+        errY = np.abs(Y1 - Y1_ref)
+        rel_rms = np.sqrt(np.mean(err ** 2)) / np.sqrt(np.mean(X1_ref ** 2))
+        bias = np.mean(X1 - X1_ref) / np.sqrt(np.mean(err ** 2) + 1e-300)
+        worst.append((float((err / bound).max()), float((errY / bY).max()), rel_rms, bias))
+        print(f"{prec} g={g}: err/bound X1 {worst[-1][0]:.3e} Y1 {worst[-1][1]:.3e} "
+              f"rel rms {rel_rms:.3e} bias/rms {bias:+.3f} max|err| {err.max():.3e}")
+        assert np.all(err <= bound) and np.all(errY <= bY)
