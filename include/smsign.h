@@ -92,15 +92,20 @@ typedef struct {
   int32_t reserved;
 } sm_sign_opts;
 
-/* Per-submatrix result record, written on the device by submatrix_sign. */
+/* Per-submatrix result record, written on the device by build_submatrices
+ * (scale, scale_src, gersh, rho_est, feat) and submatrix_sign (the rest).
+ * 120 bytes, indexed by submatrix (atom) id. */
 typedef struct {
   int32_t iters;       /* Newton-Schulz updates applied in total */
   int32_t iters_low;   /* ... of which in the phase-1 precision */
-  int32_t status;      /* 1 converged, 0 hit max_iter, 2 refinement done */
+  int32_t status;      /* 1 converged, 0 hit max_iter, 2 refinement done, -1 diverged */
   int32_t scale_src;   /* 0 Gershgorin, 1 power, 2 learned accepted, 3 learned rejected */
   double scale;        /* c used for X_0 = T / c */
   double res;          /* last ||X^2 - I||_F from the GEMM epilogue (float64 sum) */
-  double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v||, -1 if off */
+  double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v|| (-1 if off) */
+  double gersh;        /* Gershgorin bound c_G = max_p sum_q |T_pq| */
+  double rho_est;      /* power-iteration estimate of rho(T) (<= rho), -1 if not run */
+  float feat[16];      /* features of the scaling network (see sm_mlp_create) */
 } sm_sub_stats;
 
 typedef struct sm_plan sm_plan;
@@ -213,6 +218,45 @@ int sm_plan_ws_layout(const sm_plan* plan, int32_t storage_prec, int64_t* region
  * v, to be compared with D[4*(lane/16)+v][lane%16] of the exact product.
  * Synchronous; allocates and frees a 2 KiB device buffer. */
 int sm_selftest_mfma(int32_t prec, double* out_host);
+
+/* ---- the spectral-scaling network (learned scaling, SM_SCALE_LEARNED) ----
+ * The paper proposes no network; its closing remarks suggest models that are
+ * trusted only where they are accurate and retrained on explicitly computed
+ * cases.  Here a float32 multilayer perceptron 16 -> 64 -> 64 -> 2 with tanh
+ * hidden layers maps the 16 features of a submatrix (sm_sub_stats.feat:
+ * log n, log c_G, diagonal and Gershgorin-radius statistics relative to c_G)
+ * to y0 ~ log(rho(T)/c_G) and y1 (a second spectral target of the caller's
+ * choice).  Inputs are normalised by a stored mean / std (32 floats).
+ * Parameters are packed as W1 (64x16 row-major), b1, W2 (64x64), b2, W3 (2x64),
+ * b3: 5378 floats.  Loss = mean over samples of sum over outputs of
+ * (y - t)^2; Adam with beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected.
+ * The network owns its device buffers (current device at creation). */
+
+/* Weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a SplitMix64 stream of
+ * `seed`; normalisation mean 0, std 1. */
+int sm_mlp_create(uint64_t seed, sm_mlp** out);
+void sm_mlp_destroy(sm_mlp* mlp);
+/* Host float[5378] parameters and float[32] (mean[16], std[16]); either may be
+ * NULL.  Setting parameters resets the Adam state. */
+int sm_mlp_set_weights(sm_mlp* mlp, const float* params, const float* norm);
+int sm_mlp_get_weights(const sm_mlp* mlp, float* params, float* norm);
+/* Y[n][2] (device) = network(X) for device X with row stride ldx >= 16 floats. */
+int sm_mlp_infer(sm_mlp* mlp, const float* X, int64_t ldx, int64_t n, float* Y, void* stream);
+/* Full-batch loss (host double) and gradient (host float[5378], may be NULL)
+ * for device inputs X (stride ldx) and targets T[n][2].  Synchronous. */
+int sm_mlp_loss_grad(sm_mlp* mlp, const float* X, int64_t ldx, const float* T, int64_t n,
+                     double* loss, float* grad, void* stream);
+/* Mini-batch Adam: `epochs` passes over the n samples in batches of `batch`
+ * (order shuffled per epoch from shuffle_seed, or kept if 0), learning rate
+ * lr; with fit_norm the normalisation is first set to the samples' mean/std.
+ * loss_hist (host, `epochs` doubles, may be NULL) receives the mean loss of
+ * every epoch.  Synchronous (one host sync per epoch). */
+int sm_mlp_train(sm_mlp* mlp, const float* X, int64_t ldx, const float* T, int64_t n, int32_t epochs,
+                 int32_t batch, float lr, int32_t fit_norm, uint64_t shuffle_seed, double* loss_hist,
+                 void* stream);
+/* Attach the network used by build_submatrices when opts->scaling is
+ * SM_SCALE_LEARNED (not owned by the plan; NULL detaches). */
+int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
 
 /* Kernel timing for measurement.  While enabled, every Newton-Schulz GEMM
  * launch made by submatrix_sign is bracketed by a pair of HIP events recorded

@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsmsign.so")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "api.cpp", "k_prep.hip", "k_gemm.hip", "k_post.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "mlp.cpp", "k_prep.hip", "k_gemm.hip", "k_post.hip", "k_mlp.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -148,8 +148,18 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   hipStream_t s = as_stream(stream);
   SM_HIP(launch_fill_i32(w.flag, 0, 1, s));
   SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, w.flag, s));
-  SM_HIP(launch_analyze(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin,
-                        w.vecs, nullptr, w.features, w.st, stats, s));
+  double* cg = w.scratch;                                 // [max_subs]
+  float* pred = reinterpret_cast<float*>(w.scratch + p->max_subs);  // [2 max_subs]
+  SM_HIP(launch_analyze(p->dev, g0, nsub, w.mats, f64, w.features, cg, stats, s));
+  const float* predp = nullptr;
+  if (o->scaling == SM_SCALE_LEARNED) {
+    if (!p->mlp) return set_error(SM_ERR_STATE, "build_submatrices: learned scaling needs a network (sm_plan_set_mlp)");
+    if (p->mlp->device != p->device) return set_error(SM_ERR_STATE, "build_submatrices: network lives on another device");
+    SM_HIP(launch_mlp_infer(p->mlp->theta, p->mlp->norm, w.features, kNumFeatures, nsub, pred, s));
+    predp = pred;
+  }
+  SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
+                      cg, predp, stats, s));
   SM_HIP(hipMemcpyAsync(&p->h_pinned[8], w.flag, 4, hipMemcpyDeviceToHost, s));
   SM_HIP(hipStreamSynchronize(s));
   p->last_f64 = f64;

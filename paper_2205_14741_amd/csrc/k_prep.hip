@@ -102,19 +102,13 @@ hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_
   return hipGetLastError();
 }
 
-// One workgroup (8 waves) per submatrix, after the gather:
-//   * column abs sums (= row sums, T symmetric) -> Gershgorin bound c_G and the
-//     16 features of the scaling network;
-//   * optional power iteration (column dots with a vector kept in the
-//     workspace) -> est <= rho(T);
-//   * c_i by the requested rule; X_0 = T_i / c_i on the n x n block (the
-//     identity pad is left as is).
+// One workgroup (8 waves) per submatrix, after the gather: column abs sums
+// (= row sums, T is symmetric) give the Gershgorin bound c_G >= rho(T) and,
+// with the diagonal, the 16 features of the scaling network.
 template <typename T>
-__global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __restrict__ mats,
-                                                      int scaling, int power_steps, double margin,
-                                                      double* __restrict__ vecs,
-                                                      const float* __restrict__ learned_scale,
+__global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, const T* __restrict__ mats,
                                                       float* __restrict__ features,
+                                                      double* __restrict__ cg_out,
                                                       sm_sub_stats* __restrict__ stats) {
   __shared__ double red[16];
   const int l = blockIdx.x;
@@ -124,7 +118,7 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __re
   const int n = p.height[i];
   const int loc = p.loc[i];
   const int b = p.bs[i];
-  T* X = mats + p.mat_off_g[g];
+  const T* X = mats + p.mat_off_g[g];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
@@ -160,7 +154,7 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __re
       minown = fmin(minown, fabs(dg));
     }
   }
-  // every lane of a wave holds identical values; reduce across waves
+  // every lane of a wave holds the same values; reduce across waves
   cmax = block_reduce<1>(lane == 0 ? cmax : 0.0, red);
   sdiag = block_reduce<0>(lane == 0 ? sdiag : 0.0, red);
   sdiag2 = block_reduce<0>(lane == 0 ? sdiag2 : 0.0, red);
@@ -175,10 +169,63 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __re
   sown = block_reduce<0>(lane == 0 ? sown : 0.0, red);
   minown = block_reduce<2>(lane == 0 ? minown : 1e300, red);
   sabs = block_reduce<0>(lane == 0 ? sabs : 0.0, red);
-  const double cG = cmax > 0.0 ? cmax : 1.0;
+  if (threadIdx.x == 0) {
+    const double cG = cmax > 0.0 ? cmax : 1.0;
+    const double nn = (double)n;
+    const double mean = sdiag / nn;
+    float f[kNumFeatures];
+    f[0] = (float)log(nn);
+    f[1] = (float)log(cG);
+    f[2] = (float)(mean / cG);
+    f[3] = (float)(sqrt(fmax(sdiag2 / nn - mean * mean, 0.0)) / cG);
+    f[4] = (float)(mind / cG);
+    f[5] = (float)(maxd / cG);
+    f[6] = (float)(sR / nn / cG);
+    f[7] = (float)(maxR / cG);
+    f[8] = (float)(minabs / cG);
+    f[9] = (float)(mingap / cG);
+    f[10] = (float)(nneg / nn);
+    f[11] = (float)(sqrt(ssq) / (cG * sqrt(nn)));
+    f[12] = (float)(b / nn);
+    f[13] = (float)(sown / b / cG);
+    f[14] = (float)(minown / cG);
+    f[15] = (float)(sabs / nn / cG);
+    sm_sub_stats& r = stats[i];
+    for (int k = 0; k < kNumFeatures; ++k) {
+      features[(int64_t)l * kNumFeatures + k] = f[k];
+      r.feat[k] = f[k];
+    }
+    r.gersh = cG;
+    cg_out[l] = cG;
+  }
+}
 
-  // power iteration on T: v_{k+1} = T v_k / ||T v_k||, est = ||T v_k|| (<= rho)
-  double est = 0.0;
+// One workgroup per submatrix: optional power iteration on T (column dots with
+// a vector kept in the workspace; est = ||T v_k|| <= rho(T)), the choice of c,
+// and X_0 = T / c on the n x n block (the identity pad is left as is).
+//   Gershgorin: c = c_G.   Power: c = min(c_G, (1 + margin) est).
+//   Learned: c_hat = c_G exp(y0) (1 + margin) from the network, accepted only if
+//   est <= c_hat <= c_G (the guard), else c = c_G.
+template <typename T>
+__global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __restrict__ mats, int scaling,
+                                                    int power_steps, double margin,
+                                                    double* __restrict__ vecs,
+                                                    const double* __restrict__ cg_in,
+                                                    const float* __restrict__ pred,
+                                                    sm_sub_stats* __restrict__ stats) {
+  __shared__ double red[16];
+  const int l = blockIdx.x;
+  const int g = g0 + l;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int n = p.height[i];
+  T* X = mats + p.mat_off_g[g];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const double cG = cg_in[l];
+
+  double est = -1.0;
   if (scaling != SM_SCALE_GERSHGORIN && power_steps > 0) {
     double* v = vecs + p.vec_off_g[g];
     double* w = v + npad;
@@ -210,16 +257,16 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __re
       __syncthreads();
     }
   }
-
   double c = cG;
   int src = 0;
   if (scaling == SM_SCALE_POWER && est > 0.0) {
     c = fmin(cG, (1.0 + margin) * est);
     src = 1;
   } else if (scaling == SM_SCALE_LEARNED) {
-    const double cp = learned_scale ? (double)learned_scale[l] : 0.0;
-    if (cp > 0.0 && isfinite(cp) && cp >= (1.0 + margin) * est && cp <= cG) {
-      c = cp;
+    const double y0 = pred ? (double)pred[2 * l] : 0.0;
+    const double ch = cG * exp(fmin(y0, 0.0)) * (1.0 + margin);
+    if (pred && isfinite(y0) && ch >= est && ch <= cG) {
+      c = ch;
       src = 2;
     } else {
       src = 3;
@@ -231,43 +278,35 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, T* __re
     for (int d = lane; d < n; d += kWave) col[d] = (T)((double)col[d] * sc);
   }
   if (threadIdx.x == 0) {
-    const double nn = (double)n;
-    float* f = features + (int64_t)l * kNumFeatures;
-    const double mean = sdiag / nn;
-    f[0] = (float)log(nn);
-    f[1] = (float)log(cG);
-    f[2] = (float)(mean / cG);
-    f[3] = (float)(sqrt(fmax(sdiag2 / nn - mean * mean, 0.0)) / cG);
-    f[4] = (float)(mind / cG);
-    f[5] = (float)(maxd / cG);
-    f[6] = (float)(sR / nn / cG);
-    f[7] = (float)(maxR / cG);
-    f[8] = (float)(minabs / cG);
-    f[9] = (float)(mingap / cG);
-    f[10] = (float)(nneg / nn);
-    f[11] = (float)(sqrt(ssq) / (cG * sqrt(nn)));
-    f[12] = (float)(b / nn);
-    f[13] = (float)(sown / b / cG);
-    f[14] = (float)(minown / cG);
-    f[15] = (float)(sabs / nn / cG);
     sm_sub_stats& r = stats[i];
     r.scale = c;
     r.scale_src = src;
-    r.res_probe = est;   // overwritten by the final probe; keeps the estimate if probes are off
+    r.rho_est = est;
   }
 }
 
-hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64,
-                          int scaling, int power_steps, double margin, double* vecs,
-                          const float* learned_scale, float* features, SubState* /*st*/,
-                          sm_sub_stats* stats, hipStream_t s) {
+hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                          float* features, double* cg_out, sm_sub_stats* stats, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   if (storage_f64)
-    hipLaunchKernelGGL(analyze_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats,
-                       scaling, power_steps, margin, vecs, learned_scale, features, stats);
+    hipLaunchKernelGGL(analyze_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (const double*)mats,
+                       features, cg_out, stats);
   else
-    hipLaunchKernelGGL(analyze_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats,
-                       scaling, power_steps, margin, vecs, learned_scale, features, stats);
+    hipLaunchKernelGGL(analyze_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (const float*)mats,
+                       features, cg_out, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
+                        int power_steps, double margin, double* vecs, const double* cg_in,
+                        const float* pred, sm_sub_stats* stats, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  if (storage_f64)
+    hipLaunchKernelGGL(scale_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats, scaling,
+                       power_steps, margin, vecs, cg_in, pred, stats);
+  else
+    hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
+                       power_steps, margin, vecs, cg_in, pred, stats);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <string>
 #include <vector>
 
+#include "mlp.h"
 #include "smsign_internal.h"
 
 struct sm_plan {
@@ -48,6 +49,7 @@ struct sm_plan {
   int32_t* h_pinned = nullptr;      // pinned host counters [8]
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_f64 = -1;                // storage precision of the last build (-1: none)
+  sm_mlp* mlp = nullptr;            // scaling network for SM_SCALE_LEARNED (not owned)
   // kernel timing (sm_profile_enable)
   bool profiling = false;
   std::vector<hipEvent_t> prof_ev;  // pool, pairs (start, stop)

@@ -58,11 +58,11 @@ struct WsLayout {
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
                          const double* H, double mu, void* mats, int storage_f64,
                          int* nonfinite, hipStream_t s);
-hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64,
-                          int scaling, int power_steps, double margin, double* vecs,
-                          const float* learned_scale, float* features, SubState* st,
-                          sm_sub_stats* stats, hipStream_t s);
-hipError_t launch_ns_init(int nsub, SubState* st, hipStream_t s);
+hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
+                          float* features, double* cg_out, sm_sub_stats* stats, hipStream_t s);
+hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
+                        int power_steps, double margin, double* vecs, const double* cg_in,
+                        const float* pred, sm_sub_stats* stats, hipStream_t s);
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, sm_sub_stats* stats,

@@ -25,6 +25,8 @@ EXPORTED = (
     "sm_plan_ws_layout", "build_submatrices", "submatrix_sign", "assemble_P", "energy_trace",
     "sm_density_matrix", "sm_find_mu", "sm_gershgorin_bracket", "sm_selftest_mfma",
     "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
+    "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
+    "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp",
 )
 
 
@@ -55,13 +57,17 @@ class SignOpts(C.Structure):
 class SubStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("iters_low", C.c_int32), ("status", C.c_int32),
                 ("scale_src", C.c_int32), ("scale", C.c_double), ("res", C.c_double),
-                ("res_probe", C.c_double)]
+                ("res_probe", C.c_double), ("gersh", C.c_double), ("rho_est", C.c_double),
+                ("feat", C.c_float * 16)]
 
 
 STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"),
                         ("scale_src", "<i4"), ("scale", "<f8"), ("res", "<f8"),
-                        ("res_probe", "<f8")])
-assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 40
+                        ("res_probe", "<f8"), ("gersh", "<f8"), ("rho_est", "<f8"),
+                        ("feat", "<f4", (16,))])
+STATS_FEAT_OFFSET = 56   # bytes from the start of a record to feat[0]
+assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 120
+assert STATS_DTYPE.fields["feat"][1] == STATS_FEAT_OFFSET
 assert C.sizeof(SignOpts) == 72
 
 _lib = None
@@ -94,6 +100,14 @@ def lib() -> C.CDLL:
         "sm_selftest_mfma": (i32, [i32, vp]),
         "sm_profile_enable": (i32, [vp, i32]),
         "sm_profile_read": (i32, [vp, vp, vp]),
+        "sm_mlp_create": (i32, [C.c_uint64, C.POINTER(vp)]),
+        "sm_mlp_destroy": (None, [vp]),
+        "sm_mlp_set_weights": (i32, [vp, vp, vp]),
+        "sm_mlp_get_weights": (i32, [vp, vp, vp]),
+        "sm_mlp_infer": (i32, [vp, vp, i64, i64, vp, vp]),
+        "sm_mlp_loss_grad": (i32, [vp, vp, i64, vp, i64, vp, vp, vp]),
+        "sm_mlp_train": (i32, [vp, vp, i64, vp, i64, i32, i32, C.c_float, i32, C.c_uint64, vp, vp]),
+        "sm_plan_set_mlp": (i32, [vp, vp]),
         "sm_last_error": (C.c_char_p, []),
         "sm_version": (C.c_char_p, []),
     }
@@ -255,6 +269,69 @@ def sm_profile_read(plan: Plan):
     t = np.zeros(10)
     _check(lib().sm_profile_read(plan.handle, n.ctypes.data, t.ctypes.data))
     return n, t
+
+
+N_MLP_PARAMS = 5378
+
+
+class Mlp:
+    """The spectral-scaling network (device buffers owned by the library)."""
+
+    def __init__(self, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().sm_mlp_create(int(seed), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().sm_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, params=None, norm=None):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        q = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        _check(lib().sm_mlp_set_weights(self.handle, None if p is None else p.ctypes.data,
+                                        None if q is None else q.ctypes.data))
+
+    def get_weights(self):
+        p = np.zeros(N_MLP_PARAMS, np.float32)
+        q = np.zeros(32, np.float32)
+        _check(lib().sm_mlp_get_weights(self.handle, p.ctypes.data, q.ctypes.data))
+        return p, q
+
+
+def sm_mlp_infer(mlp: Mlp, X, n: int, ldx: int = 16, Y=None, stream=None):
+    import torch
+    Y = Y if Y is not None else torch.empty((n, 2), dtype=torch.float32, device=X.device)
+    _check(lib().sm_mlp_infer(mlp.handle, _ptr(X), int(ldx), int(n), _ptr(Y), _stream(stream)))
+    return Y
+
+
+def sm_mlp_loss_grad(mlp: Mlp, X, T, n: int, ldx: int = 16, stream=None):
+    loss = C.c_double()
+    g = np.zeros(N_MLP_PARAMS, np.float32)
+    _check(lib().sm_mlp_loss_grad(mlp.handle, _ptr(X), int(ldx), _ptr(T), int(n), C.byref(loss),
+                                  g.ctypes.data, _stream(stream)))
+    return loss.value, g
+
+
+def sm_mlp_train(mlp: Mlp, X, T, n: int, epochs: int, batch: int, lr: float, ldx: int = 16,
+                 fit_norm: bool = True, shuffle_seed: int = 1, stream=None):
+    hist = np.zeros(max(epochs, 1))
+    _check(lib().sm_mlp_train(mlp.handle, _ptr(X), int(ldx), _ptr(T), int(n), int(epochs), int(batch),
+                              float(lr), 1 if fit_norm else 0, int(shuffle_seed), hist.ctypes.data,
+                              _stream(stream)))
+    return hist[:epochs]
+
+
+def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):
+    _check(lib().sm_plan_set_mlp(plan.handle, None if mlp is None else mlp.handle))
 
 
 def version() -> str:
