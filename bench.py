@@ -79,9 +79,8 @@ def main():
 
     dev = torch.device("cuda:0")
     m = synth.config2(a.seed)
-    plan = sm.Plan(m, 64)
-    info = plan.info()
-    n, npad = info["n"], info["npad"]
+    # float64 / float32 schedules pad submatrices to 32, the bf16-family ones to 64
+    plans = {32: sm.Plan(m, 32), 64: sm.Plan(m, 64)}
     H = torch.from_numpy(m.vals).to(dev)
     torch.cuda.synchronize()
 
@@ -92,6 +91,9 @@ def main():
     ref_P = ref_E = None
     for mode in modes:
         o = sm.default_opts(MODES[mode])
+        plan = plans[32 if mode in ("f64", "f32") else 64]
+        info = plan.info()
+        n, npad = info["n"], info["npad"]
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
 
         def step():
@@ -118,7 +120,7 @@ def main():
         fl = metrics.flops_by_class(st, n, npad, o)
         useful = sum(v[0] for v in fl.values())
         P = work.P.cpu().numpy()
-        r = {"ms_per_step": dt / a.steps * 1e3, "mu": mu, "bisection_passes": k, "E": E, "Ne": Ne,
+        r = {"ms_per_step": dt / a.steps * 1e3, "pad_to": 32 if mode in ("f64", "f32") else 64, "mu": mu, "bisection_passes": k, "E": E, "Ne": Ne,
              "iters": [int(st["iters"].min()), int(st["iters"].max())],
              "iters_mean": float(st["iters"].mean()),
              "submatrices_per_s": m.n_atoms * a.steps / dt,

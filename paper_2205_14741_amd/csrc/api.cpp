@@ -63,7 +63,7 @@ int64_t list_stride(const sm_plan* p) { return 2 + 2 * p->max_subs + 1; }
 int chunk_tiles(const sm_plan* p, int g0, int nsub) {
   int64_t t = 0;
   for (int g = g0; g < g0 + nsub; ++g) {
-    const int64_t T = p->npad_g[g] / kTile;
+    const int64_t T = tiles_of(p->npad_g[g]);
     t += T * (T + 1) / 2;
   }
   return (int)std::min<int64_t>(t, 1 << 30);
@@ -177,6 +177,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
   if ((rc = ensure_device(p))) return rc;
   const int f64 = storage_is_f64(o);
+  if (o->phase1 >= SM_BF16 && p->pad_to < 64)
+    return set_error(SM_ERR_ARG, "submatrix_sign: bf16 / f16 / split-bf16 phases need a plan padded to 64 or 128");
   if (p->last_f64 != f64)
     return set_error(SM_ERR_STATE, "submatrix_sign: the workspace was not built for this precision schedule");
   WsPtrs w = ws_ptrs(p, ws, f64);

@@ -42,6 +42,26 @@ struct ListView {
   const int32_t* prefix;  // tile prefix, [n+1]
 };
 
+// NL consecutive elements of one operand column as 16-byte vector loads
+// (zeros for a row past n_pad).  The address is 16-byte aligned: n_pad and
+// the per-thread k offset are multiples of 4 doubles / 8 floats.
+template <typename S, int NL>
+__device__ __forceinline__ void load_col(S (&r)[NL], const S* __restrict__ p, bool ok) {
+  constexpr int V = 16 / (int)sizeof(S);
+  static_assert(NL % V == 0, "vector width");
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < NL / V; ++q) {
+      const u4 t = *reinterpret_cast<const u4*>(p + q * V);
+      __builtin_memcpy(&r[q * V], &t, 16);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < NL; ++e) r[e] = S(0);
+  }
+}
+
 __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
   int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
   while (r * (r + 1) / 2 > lt) --r;
@@ -108,8 +128,15 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
     int bi, bj;
     tile_coords(lt, bi, bj);
     const int r0 = bi * 64, c0 = bj * 64;
-    const S* ga = Xp + (int64_t)(r0 + lrow) * npad + lpart;
-    const S* gb = Rp + (int64_t)(c0 + lrow) * npad + lpart;
+    // the last tile row / column may reach past n_pad (a multiple of 32): its
+    // operand rows load as zeros and the wave blocks there are skipped
+    const bool va = (r0 + lrow) < npad;
+    const bool vb = (c0 + lrow) < npad;
+    // wave blocks past n_pad, and the block of a diagonal tile that lies
+    // wholly above the diagonal, compute nothing
+    const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && !(bi == bj && wm < wn);
+    const S* ga = Xp + (int64_t)(va ? r0 + lrow : 0) * npad + lpart;
+    const S* gb = Rp + (int64_t)(vb ? c0 + lrow : 0) * npad + lpart;
 
     typename Tr::Acc acc[2][2];
 #pragma unroll
@@ -118,8 +145,8 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
       for (int b = 0; b < 2; ++b) acc[a][b] = typename Tr::Acc{0, 0, 0, 0};
 
     S ra[NL], rb[NL];
-#pragma unroll
-    for (int e = 0; e < NL; ++e) { ra[e] = ga[e]; rb[e] = gb[e]; }
+    load_col<S, NL>(ra, ga, va);
+    load_col<S, NL>(rb, gb, vb);
 
     const int nst = npad / K;
     for (int s = 0; s < nst; ++s) {
@@ -154,13 +181,15 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
       if (s + 1 < nst) {
         const S* na = ga + (int64_t)(s + 1) * K;
         const S* nb = gb + (int64_t)(s + 1) * K;
-#pragma unroll
-        for (int e = 0; e < NL; ++e) { ra[e] = na[e]; rb[e] = nb[e]; }
+        load_col<S, NL>(ra, na, va);
+        load_col<S, NL>(rb, nb, vb);
       }
       // ---- MFMA on the LDS stage ----
       const int kq = lane >> 4;    // k group of this lane
       const int rl = lane & 15;    // row / column inside a 16 x 16 block
-      if constexpr (MODE == SM_F64) {
+      if (!wvalid) {
+        // wave block past n_pad: nothing to accumulate
+      } else if constexpr (MODE == SM_F64) {
         // 16x16x4: lane supplies A[rl][kq], B[kq][rl]; the k index inside the
         // stage is permuted to 4 kq + kk so each lane reads 4 contiguous values.
         double a[2][4], b[2][4];
@@ -247,12 +276,15 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
 
     // ---- epilogue: 16 x 16 result block.  Register v of lane l holds column
     // l % 16 and row 4 (l / 16) + v for the float32-accumulating instructions,
-    // row l / 16 + 4 v for the float64 one (checked by sm_selftest_mfma). ----
+    // row l / 16 + 4 v for the float64 one (checked by sm_selftest_mfma).
+    // Only entries on or below the diagonal are kept and each is written to
+    // both (r, c) and (c, r): the stored result is exactly symmetric.  This
+    // matters because the kernels read X as X^T: a skew-symmetric part would
+    // be multiplied by -2 in every iteration instead of being left alone. ----
     double part = 0.0;
-    const bool mirror = (bi != bj);
     const int kq = lane >> 4;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < (wvalid ? 2 : 0); ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const int rb = r0 + wm * 32 + x * 16;
@@ -260,18 +292,19 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = rb + (MODE == SM_F64 ? kq + 4 * v : 4 * kq + v);
+          if (rr < cc) continue;   // upper triangle: written by the mirror of (cc, rr)
           const double a = (double)acc[x][y][v];
           S outv;
           if (WHICH == 0) {
             const double dg = (rr == cc) ? 1.0 : 0.0;
             const double e = a - dg;
-            part += e * e;
+            part += (rr == cc) ? e * e : 2.0 * e * e;
             outv = (S)(3.0 * dg - a);
           } else {
             outv = (S)(0.5 * a);
           }
           Out[(int64_t)cc * npad + rr] = outv;
-          if (mirror) Out[(int64_t)rr * npad + cc] = outv;
+          if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
         }
       }
     if (WHICH == 0) {
@@ -280,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
       __syncthreads();
       if (tid == 0) {
         const double sum = ((red[0] + red[1]) + red[2]) + red[3];
-        partials[p.tile_off_g[g] + lt] = mirror ? 2.0 * sum : sum;
+        partials[p.tile_off_g[g] + lt] = sum;
       }
     }
     __syncthreads();
@@ -348,96 +381,94 @@ __device__ int block_excl_scan(int v, int* sh, int& total) {
   return off + x - v;
 }
 
-// One workgroup.  Phase A (a wavefront per submatrix): reduce the residual
-// partials of the square just computed in a fixed order, apply the stopping /
-// phase-switch rules, advance the iteration counters.  Phase B: ordered
-// compaction into four tile lists: update in the main / refinement precision,
-// square (next iteration) in the main / refinement precision.
+// A wavefront per submatrix: the residual ||X^2 - I||_F of the square just
+// computed, from its per-tile partial sums added in tile order.
+__global__ __launch_bounds__(256) void residual_kernel(DevPlan p, int g0, int nsub, SubState* st,
+                                                       const double* __restrict__ partials) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= nsub || !st[l].active) return;
+  const int g = g0 + l;
+  const int T = tiles_of(p.npad_g[g]);
+  const int nt = T * (T + 1) / 2;
+  const double* pp = partials + p.tile_off_g[g];
+  double r = 0.0;
+  for (int k = lane; k < nt; k += 64) r += pp[k];
+  r = wave_sum(r);
+  if (lane == 0) st[l].res_new = sqrt(fmax(r, 0.0));
+}
+
+// One workgroup, a thread per submatrix: apply the stopping / phase-switch
+// rules to the new residual, advance the counters, and compact the
+// submatrices into four tile lists by ordered block scans: update in the
+// main / refinement precision, square (next iteration) in the main /
+// refinement precision.
 __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int nsub, SubState* st,
-                                                        const double* __restrict__ partials,
                                                         int32_t* lists, int max_subs, SchedOpts o,
                                                         int first) {
-  extern __shared__ unsigned char dec_s[];
   __shared__ int sh[16];
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  for (int l = wid; l < nsub; l += nw) {
-    SubState s = st[l];
-    int dec = 0;
-    if (first) {
-      s.active = 1;
-      s.phase = 0;
-      s.iters = 0;
-      s.iters_low = 0;
-      s.refine_left = 0;
-      s.status = 0;
-      s.res = 1e300;
-      s.res_prev = 1e300;
-      dec = DEC_SQ;
-    } else if (s.active) {
-      const int g = g0 + l;
-      const int T = p.npad_g[g] / kTile;
-      const int nt = T * (T + 1) / 2;
-      const double* pp = partials + p.tile_off_g[g];
-      double r = 0.0;
-      for (int k = lane; k < nt; k += 64) r += pp[k];
-      r = sqrt(fmax(wave_sum(r), 0.0));
-      s.res_prev = s.res;
-      s.res = r;
-      const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
-      if (!(r < 1e300)) {
-        s.status = -1;
-        s.active = 0;
-      } else if (s.phase == 0) {
-        if (o.refine_steps == 0) {
-          if (r < o.tol || stalled) {
-            s.status = 1;
-            s.active = 0;
-          } else if (s.iters >= o.max_iter) {
-            s.status = 0;
-            s.active = 0;
-          } else {
-            dec = DEC_UPD | DEC_SQ;
-            s.iters++;
-            s.iters_low++;
-          }
-        } else if (r < o.switch_tol || stalled || s.iters >= o.max_iter) {
-          s.phase = 1;
-          s.refine_left = o.refine_steps;
-        } else {
-          dec = DEC_UPD | DEC_SQ;
-          s.iters++;
-          s.iters_low++;
-        }
-      }
-      if (s.active && s.phase == 1 && dec == 0) {
-        dec = DEC_UPD | DEC_REF;
-        s.iters++;
-        s.refine_left--;
-        if (s.refine_left > 0) {
-          dec |= DEC_SQ;
-        } else {
-          s.status = 2;
-          s.active = 0;
-        }
-      }
-    }
-    if (lane == 0) {
-      st[l] = s;
-      dec_s[l] = (unsigned char)dec;
-    }
-  }
-  __syncthreads();
   const int stride = 2 + 2 * max_subs + 1;
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
   for (int base = 0; base < nsub; base += blockDim.x) {
     const int l = base + threadIdx.x;
     int dec = 0, nt = 0;
     if (l < nsub) {
-      dec = dec_s[l];
-      const int T = p.npad_g[g0 + l] / kTile;
+      SubState s = st[l];
+      const int T = tiles_of(p.npad_g[g0 + l]);
       nt = T * (T + 1) / 2;
+      if (first) {
+        s.active = 1;
+        s.phase = 0;
+        s.iters = 0;
+        s.iters_low = 0;
+        s.refine_left = 0;
+        s.status = 0;
+        s.res = 1e300;
+        s.res_prev = 1e300;
+        dec = DEC_SQ;
+      } else if (s.active) {
+        const double r = s.res_new;
+        s.res_prev = s.res;
+        s.res = r;
+        const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
+        if (!(r < 1e300)) {
+          s.status = -1;
+          s.active = 0;
+        } else if (s.phase == 0) {
+          if (o.refine_steps == 0) {
+            if (r < o.tol || stalled) {
+              s.status = 1;
+              s.active = 0;
+            } else if (s.iters >= o.max_iter) {
+              s.status = 0;
+              s.active = 0;
+            } else {
+              dec = DEC_UPD | DEC_SQ;
+              s.iters++;
+              s.iters_low++;
+            }
+          } else if (r < o.switch_tol || stalled || s.iters >= o.max_iter) {
+            s.phase = 1;
+            s.refine_left = o.refine_steps;
+          } else {
+            dec = DEC_UPD | DEC_SQ;
+            s.iters++;
+            s.iters_low++;
+          }
+        }
+        if (s.active && s.phase == 1 && dec == 0) {
+          dec = DEC_UPD | DEC_REF;
+          s.iters++;
+          s.refine_left--;
+          if (s.refine_left > 0) {
+            dec |= DEC_SQ;
+          } else {
+            s.status = 2;
+            s.active = 0;
+          }
+        }
+      }
+      st[l] = s;
     }
 #pragma unroll
     for (int L = 0; L < 4; ++L) {
@@ -475,8 +506,9 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const sm_sign_opts& so, int first, sm_sub_stats* /*stats*/,
                            hipStream_t s) {
   SchedOpts o{so.refine_steps, so.max_iter, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
-  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), (size_t)(nsub > 0 ? nsub : 1), s, p, g0,
-                     nsub, st, partials, lists, max_subs, o, first);
+  if (!first && nsub > 0)
+    hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
+  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, lists, max_subs, o, first);
   return hipGetLastError();
 }
 

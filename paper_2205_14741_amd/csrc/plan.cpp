@@ -106,8 +106,8 @@ int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_
   if (pat->n_atoms <= 0) return set_error(SM_ERR_ARG, "sm_plan_create: n_atoms must be > 0");
   if (!pat->block_size || !pat->col_ptr || !pat->row_idx || !pat->panel_off)
     return set_error(SM_ERR_ARG, "sm_plan_create: null pattern array");
-  if (pad_to != 64 && pad_to != 128)
-    return set_error(SM_ERR_ARG, "sm_plan_create: pad_to must be 64 or 128 (got %d)", pad_to);
+  if (pad_to != 32 && pad_to != 64 && pad_to != 128)
+    return set_error(SM_ERR_ARG, "sm_plan_create: pad_to must be 32, 64 or 128 (got %d)", pad_to);
   const int32_t n = pat->n_atoms;
   if (pat->col_ptr[0] != 0) return set_error(SM_ERR_ARG, "sm_plan_create: col_ptr[0] != 0");
   for (int32_t c = 0; c < n; ++c) {
@@ -189,7 +189,7 @@ int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_
     int32_t i = g;
     int64_t np = p->npad[i];
     int64_t need = 3 * np * np;
-    int64_t T = np / kTile;
+    int64_t T = tiles_of((int)np);
     int64_t nt = T * (T + 1) / 2;
     if (subs > 0 && max_chunk_elems > 0 && mats + need > max_chunk_elems) {
       p->chunk_ptr.push_back(g);

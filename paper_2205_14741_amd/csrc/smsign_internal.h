@@ -9,6 +9,8 @@
 namespace sm {
 
 constexpr int kTile = 64;          // output tile edge of the Newton-Schulz GEMMs
+// tiles per dimension of an n_pad x n_pad submatrix (the last one may be half full)
+__host__ __device__ inline int tiles_of(int npad) { return (npad + kTile - 1) / kTile; }
 constexpr int kNumFeatures = 16;   // per-submatrix features for the scaling network
 constexpr int kMaxProbes = 8;
 
@@ -39,6 +41,8 @@ struct SubState {
   int32_t status;
   double res;          // last residual
   double res_prev;     // residual before that
+  double res_new;      // residual of the square just computed (residual_kernel)
+  double pad_;
 };
 
 // Workspace layout (bytes) for one chunk, given the storage element size.

@@ -5,7 +5,9 @@ some squares (A = X^2, Y = 3I - A) and updates (X' = 1/2 X Y).  Every product
 is symmetric, so the kernels compute the tiles on and below the diagonal only:
 
     useful flops of one product  = n^2 (n + 1)       (n(n+1)/2 entries x 2n)
-    issued MFMA flops            = T(T+1)/2 * 2 * 64 * 64 * np,  T = np / 64
+    issued MFMA flops            = (32 x 32 wave blocks computed) * 2 * 32 * 32 * np
+                                   (64 x 64 tiles on / below the diagonal; a wave block
+                                   that lies past n_pad, a multiple of 32, is skipped)
 
 With a refinement phase of r steps (status 2) the counts are
     main precision:   squares = iters_low + 1, updates = iters_low
@@ -43,14 +45,27 @@ def product_counts(stats: np.ndarray, opts) -> dict:
 def flops_by_class(stats: np.ndarray, n: np.ndarray, npad: np.ndarray, opts):
     """{(precision, kind): (useful flops, issued MFMA flops)} of one pass."""
     n = n.astype(np.float64)
-    T = (npad // 64).astype(np.float64)
     useful_one = n * n * (n + 1.0)
-    issued_one = T * (T + 1) / 2 * 2 * 64 * 64 * npad.astype(np.float64)
+    issued_one = wave_blocks(npad) * 2.0 * 32 * 32 * npad.astype(np.float64)
     res = {}
     for key, cnt in product_counts(stats, opts).items():
         cnt = np.asarray(cnt, dtype=np.float64)
         res[key] = (float((cnt * useful_one).sum()), float((cnt * issued_one).sum()))
     return res
+
+
+def wave_blocks(npad: np.ndarray) -> np.ndarray:
+    """32 x 32 wave blocks computed per product: all blocks of the 64 x 64
+    tiles with bi >= bj, minus those past n_pad."""
+    npad = np.asarray(npad, dtype=np.int64)
+    nb = npad // 32                                  # valid 32-blocks per dimension
+    T = (npad + 63) // 64
+    full = T * (T + 1) // 2 * 4                      # every tile, 4 wave blocks
+    # blocks past n_pad appear only when nb is odd (last tile half full)
+    odd = (nb % 2 == 1)
+    # last tile row (bi = T-1) and column (bj = T-1) lose their outer half
+    lost = np.where(odd, 2 * (T - 1) + 3, 0)         # T-1 off-diagonal tiles x 2 blocks + 3 in the corner tile
+    return (full - lost).astype(np.float64)
 
 
 def useful_flops(stats, n, npad, opts) -> float:

@@ -81,10 +81,11 @@ def _compare(m, P, E, Ne, mu, atoms=None):
     return dP, None, None
 
 
-def test_config1_f64(dev):
+@pytest.mark.parametrize("pad_to", [32, 64])
+def test_config1_f64(pad_to, dev):
     m = synth.config1()
     mu = gap_mu(m)
-    P, E, Ne, st, _ = run_fixed_mu(m, mu, "f64")
+    P, E, Ne, st, _ = run_fixed_mu(m, mu, "f64", pad_to=pad_to)
     dP, dE, dNe = _compare(m, P, E, Ne, mu)
     assert dP < 1e-9 and dE < 1e-11 and dNe < 1e-9, (dP, dE, dNe)
     assert np.all(st["status"] == 1) and np.all(st["res"] < 1e-10)
@@ -97,15 +98,25 @@ def test_config1_f64(dev):
         assert abs(int(st["iters"][i]) - k) <= 1
 
 
-def test_water_multi_tile_f64(dev):
-    """Uneven blocks (13/5 orbitals), several 64-tiles per submatrix, ragged n."""
+@pytest.mark.parametrize("pad_to", [32, 64, 128])
+def test_water_multi_tile_f64(pad_to, dev):
+    """Uneven blocks (13/5 orbitals), several 64-tiles per submatrix, ragged n;
+    with pad 32 half of the last tile row / column lies past n_pad."""
     m = synth.water_system(24, 1.4, 5)
     mu = gap_mu(m)
-    P, E, Ne, st, plan = run_fixed_mu(m, mu, "f64")
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, "f64", pad_to=pad_to)
     info = plan.info()
     assert info["npad"].max() >= 192 and len(set(info["n"] % 64)) > 3
+    if pad_to == 32:
+        assert np.any(info["npad"] % 64 == 32)
     dP, dE, dNe = _compare(m, P, E, Ne, mu)
     assert dP < 1e-9 and dE < 1e-11 and dNe < 1e-9, (dP, dE, dNe)
+
+
+def test_low_precision_needs_pad_64(dev):
+    m = synth.config1()
+    with pytest.raises(sm.SmError, match="padded to 64"):
+        run_fixed_mu(m, 0.0, "bf16x3", pad_to=32)
 
 
 def test_chunked_equals_single_chunk(dev):
@@ -217,3 +228,54 @@ def test_single_iteration_accuracy(prec, dev):
         print(f"{prec} g={g}: err/bound X1 {worst[-1][0]:.3e} Y1 {worst[-1][1]:.3e} "
               f"rel rms {rel_rms:.3e} bias/rms {bias:+.3f} max|err| {err.max():.3e}")
         assert np.all(err <= bound) and np.all(errY <= bY)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_trajectory_against_float64(prec, dev):
+    """X_N after N Newton-Schulz steps on the GPU against the float64 iteration
+    from the GPU's own X_0, for every N up to convergence; also the GPU's
+    float64 residual against ||X_N^2 - I||_F recomputed from X_N."""
+    import torch
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    plan = sm.Plan(m, 64)
+    H = h_dev(m)
+    info = plan.info()
+    rows = []
+    for N in range(1, 15):
+        o = sm.default_opts(prec, refine_steps=0, max_iter=N, tol=0.0, stall_below=0.0, probes=0)
+        storage = sm.storage_prec(o)
+        work = sm.Workspace(plan, storage, H.device)
+        sm.build_submatrices(plan, 0, H, mu, o, work.ws, work.stats)
+        sm.submatrix_sign(plan, 0, work.ws, o, work.stats)
+        torch.cuda.synchronize()
+        st = work.stats_host()
+        dev_max, res_gap = 0.0, 0.0
+        for g in (0, 33):
+            bufs = _read_bufs(plan, work, storage, g)
+            X0 = bufs[0] if N > 0 else None
+            if N == 1:
+                pass
+            XN = bufs[N & 1]
+            # float64 reference from the GPU X_0 (buffer 0 holds X_0 only while N < 2)
+            if g not in _X0_CACHE.setdefault(prec, {}):
+                o1 = sm.default_opts(prec, refine_steps=0, max_iter=0, tol=0.0, stall_below=0.0, probes=0)
+                w1 = sm.Workspace(plan, storage, H.device)
+                sm.build_submatrices(plan, 0, H, mu, o1, w1.ws, w1.stats)
+                torch.cuda.synchronize()
+                _X0_CACHE[prec][g] = _read_bufs(plan, w1, storage, g)[0]
+            X = _X0_CACHE[prec][g]
+            k = X.shape[0]
+            I = np.eye(k)
+            for _ in range(N):
+                X = 0.5 * X @ (3 * I - X @ X)
+            dev_max = max(dev_max, float(np.abs(XN - X).max()))
+            i = info["order"][g]
+            res_np = float(np.linalg.norm(XN @ XN - I))
+            res_gap = max(res_gap, abs(st["res"][i] - res_np) / max(res_np, 1e-30))
+        rows.append((N, dev_max, res_gap, float(np.median(st["res"]))))
+        print(f"{prec} N={N}: max|X_N - X_N(f64)| {dev_max:.3e}  res rel gap {res_gap:.2e}  median res {rows[-1][3]:.3e}")
+    assert rows[-1][1] < 1e-4
+
+
+_X0_CACHE = {}
