@@ -95,6 +95,9 @@ def main():
         info = plan.info()
         n, npad = info["n"], info["npad"]
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
+        # the autotuner picks the GEMM kernel variant for this schedule (untimed)
+        lo, hi = sm.sm_gershgorin_bracket(plan, H)
+        best, tune_ms = sm.sm_autotune(plan, 0, H, 0.5 * (lo + hi), o, work.ws, work.stats, repeats=2)
 
         def step():
             mu, k, _ = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P)
@@ -126,7 +129,8 @@ def main():
              "submatrices_per_s": m.n_atoms * a.steps / dt,
              "useful_tflops": useful * k * a.steps / dt / 1e12,
              "status_ok": bool(np.all(st["status"] >= 1)),
-             "probe_max": float(st["res_probe"].max())}
+             "probe_max": float(st["res_probe"].max()),
+             "gemm_variant": int(best), "autotune_sign_ms": [float(x) for x in tune_ms]}
         if prof:
             # dominant GEMM class of this schedule: most kernel time
             cls = int(np.argmax(ms))
@@ -153,7 +157,8 @@ def main():
         res[mode] = r
         print(f"# {mode}: {r['ms_per_step']:.2f} ms/step, {r['submatrices_per_s']:.0f} subm/s, "
               f"{r['useful_tflops']:.2f} TF/s useful, iters {r['iters']}, dE {r['rel_dE_vs_f64']:.2e}, "
-              f"dP {r['max_dP_vs_f64']:.2e}" + (f", {r['kernel']['name']} {r['kernel']['achieved_tflops']:.2f} TF/s" if prof else ""),
+              f"dP {r['max_dP_vs_f64']:.2e}, variant {best} (tune ms {' / '.join(f'{x:.2f}' for x in tune_ms)})"
+              + (f", {r['kernel']['name']} {r['kernel']['achieved_tflops']:.2f} TF/s" if prof else ""),
               file=sys.stderr, flush=True)
         del work
 

@@ -89,7 +89,11 @@ typedef struct {
   int32_t power_steps;   /* power-iteration steps (SM_SCALE_POWER / the guard) */
   double scale_margin;   /* c = (1 + margin) * estimate for the power / learned scale */
   int32_t probes;        /* float64 probe vectors for the final residual check (0..8) */
-  int32_t reserved;
+  int32_t variant;       /* Newton-Schulz GEMM kernel variant: -1 = the plan's tuned choice
+                            (see sm_autotune; 0 before tuning); 0 = tiles dealt to workgroups
+                            in list order, 1 = each XCD walks a contiguous range of the tile
+                            list (a submatrix stays in one L2), 2 = as 1 with operands
+                            prefetched two stages ahead */
 } sm_sign_opts;
 
 /* Per-submatrix result record, written on the device by build_submatrices
@@ -257,6 +261,21 @@ int sm_mlp_train(sm_mlp* mlp, const float* X, int64_t ldx, const float* T, int64
 /* Attach the network used by build_submatrices when opts->scaling is
  * SM_SCALE_LEARNED (not owned by the plan; NULL detaches). */
 int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
+
+/* Autotuner: for every GEMM kernel variant, one build + submatrix_sign pass
+ * over `chunk` at fixed mu (the sign phase timed with HIP events, best of
+ * `repeats`), then records the fastest variant as the plan's choice for the
+ * precisions of `opts` (used when opts->variant == -1).
+ *   best_out   host int32 (may be NULL): the chosen variant
+ *   times_ms   host double[3] (may be NULL): sign time of each variant
+ * Synchronous.  Leaves the workspace holding the last variant's result. */
+int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
+                const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, int32_t repeats,
+                int32_t* best_out, double* times_ms, void* stream);
+/* Tuned variant per precision (int32[5], indexed by sm_prec): `get` receives
+ * the table, `set` (if not NULL) replaces it -- to persist the autotuner's
+ * choices across processes.  Either pointer may be NULL. */
+int sm_plan_tuning(sm_plan* plan, int32_t* get, const int32_t* set);
 
 /* Kernel timing for measurement.  While enabled, every Newton-Schulz GEMM
  * launch made by submatrix_sign is bracketed by a pair of HIP events recorded

@@ -24,6 +24,9 @@ SOURCES = ["plan.cpp", "api.cpp", "mlp.cpp", "k_prep.hip", "k_gemm.hip", "k_post
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # matrix-core accumulators in VGPRs: keeps the loop-carried accumulators
+          # from being copied to AGPRs and back around every MFMA stage
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
           "-I", os.path.join(HERE, "..", "include")]
 

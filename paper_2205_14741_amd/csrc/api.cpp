@@ -24,6 +24,7 @@ int check_opts(const sm_sign_opts* o) {
   if (o->max_iter < 0 || o->max_iter > 1000) return set_error(SM_ERR_ARG, "opts.max_iter = %d out of [0, 1000]", o->max_iter);
   if (o->scaling < SM_SCALE_GERSHGORIN || o->scaling > SM_SCALE_LEARNED) return set_error(SM_ERR_ARG, "opts.scaling = %d invalid", o->scaling);
   if (o->probes < 0 || o->probes > kMaxProbes) return set_error(SM_ERR_ARG, "opts.probes = %d out of [0, %d]", o->probes, kMaxProbes);
+  if (o->variant < -1 || o->variant >= kGemmVariants) return set_error(SM_ERR_ARG, "opts.variant = %d out of [-1, %d)", o->variant, kGemmVariants);
   if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
   if (!(o->tol >= 0) || !(o->switch_tol >= 0) || !(o->stall_ratio >= 0) || !(o->stall_below >= 0) ||
       !(o->scale_margin >= 0))
@@ -41,6 +42,7 @@ int chunk_range(const sm_plan* p, int32_t chunk, int& g0, int& nsub) {
 
 struct WsPtrs {
   void* mats;
+  TileRec* tiles;
   SubState* st;
   double* partials;
   int32_t* lists;
@@ -53,7 +55,7 @@ struct WsPtrs {
 WsPtrs ws_ptrs(const sm_plan* p, void* ws, int f64) {
   const WsLayout L = p->layout(f64);
   char* w = static_cast<char*>(ws);
-  return WsPtrs{w + L.mats, (SubState*)(w + L.state), (double*)(w + L.partials), (int32_t*)(w + L.lists),
+  return WsPtrs{w + L.mats, (TileRec*)(w + L.tiles), (SubState*)(w + L.state), (double*)(w + L.partials), (int32_t*)(w + L.lists),
                 (float*)(w + L.features), (double*)(w + L.scratch), (double*)(w + L.vecs),
                 (int32_t*)(w + L.flag)};
 }
@@ -70,8 +72,12 @@ int chunk_tiles(const sm_plan* p, int g0, int nsub) {
 }
 
 // Launch one Newton-Schulz GEMM, bracketed by timing events when profiling.
-int gemm_launch(sm_plan* p, int mode, int which, int g0, void* mats, SubState* st, const int32_t* cnt,
-                const int32_t* ids, const int32_t* pre, double* partials, int grid, hipStream_t s) {
+int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, const int32_t* cnt,
+                const TileRec* recs, double* partials, int max_tiles, hipStream_t s) {
+  const int v = variant >= 0 ? variant : p->tuned[mode];
+  // persistent grid: all resident workgroups, a multiple of the 8 XCDs
+  int grid = std::min(max_tiles, p->num_cu * ns_gemm_blocks_per_cu(mode, which, v));
+  grid = std::max(8, grid / 8 * 8);
   size_t k = 0;
   if (p->profiling) {
     k = p->prof_cls.size();
@@ -82,7 +88,7 @@ int gemm_launch(sm_plan* p, int mode, int which, int g0, void* mats, SubState* s
     }
     SM_HIP(hipEventRecord(p->prof_ev[2 * k], s));
   }
-  SM_HIP(launch_ns_gemm(mode, which, p->dev, g0, mats, st, cnt, ids, pre, partials, grid, s));
+  SM_HIP(launch_ns_gemm(mode, which, v, mats, cnt, recs, partials, grid, s));
   if (p->profiling) {
     SM_HIP(hipEventRecord(p->prof_ev[2 * k + 1], s));
     p->prof_cls.push_back(2 * mode + which);
@@ -186,31 +192,34 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   const int64_t stride = list_stride(p);
   int32_t* L0 = w.lists;
   auto list_count = [&](int L) { return L0 + L * stride; };
-  auto list_ids = [&](int L) { return L0 + L * stride + 2; };
-  auto list_pre = [&](int L) { return L0 + L * stride + 2 + p->max_subs; };
-  const int grid = std::max(1, std::min(chunk_tiles(p, g0, nsub), 2048));
+  const int max_tiles = chunk_tiles(p, g0, nsub);
   const int mode_main = o->phase1;
   const int mode_ref = o->refine;
   const bool has_ref = o->refine_steps > 0;
+  TileRec* rec_main = w.tiles;
+  TileRec* rec_ref = w.tiles + p->max_tiles;
+  const int ms = (int)p->max_subs;
+  // expand lists (Lm, Lr) into tile records, then run the GEMMs of kind `which`
+  auto phase = [&](int Lm, int Lr, int which) -> int {
+    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, Lm, Lr, rec_main, has_ref ? rec_ref : nullptr, nsub, s));
+    int r;
+    if ((r = gemm_launch(p, mode_main, which, o->variant, w.mats, list_count(Lm), rec_main, w.partials,
+                         max_tiles, s)))
+      return r;
+    if (has_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, list_count(Lr), rec_ref,
+                                    w.partials, max_tiles, s)))
+      return r;
+    return SM_OK;
+  };
 
-  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, (int)p->max_subs, *o, 1, stats, s));
+  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, stats, s));
   const int lim = o->max_iter + o->refine_steps + 2;
   for (int it = 0; it <= lim; ++it) {
-    if ((rc = gemm_launch(p, mode_main, 0, g0, w.mats, w.st, list_count(2), list_ids(2), list_pre(2),
-                          w.partials, grid, s)))
-      return rc;
-    if (has_ref && (rc = gemm_launch(p, mode_ref, 0, g0, w.mats, w.st, list_count(3), list_ids(3),
-                                     list_pre(3), w.partials, grid, s)))
-      return rc;
-    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, (int)p->max_subs, *o, 0, stats, s));
+    if ((rc = phase(2, 3, 0))) return rc;          // squares: A = X^2, Y = 3I - A
+    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, stats, s));
     SM_HIP(hipMemcpyAsync(&p->h_pinned[it & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
     SM_HIP(hipEventRecord(p->ev[it & 1], s));
-    if ((rc = gemm_launch(p, mode_main, 1, g0, w.mats, w.st, list_count(0), list_ids(0), list_pre(0),
-                          w.partials, grid, s)))
-      return rc;
-    if (has_ref && (rc = gemm_launch(p, mode_ref, 1, g0, w.mats, w.st, list_count(1), list_ids(1),
-                                     list_pre(1), w.partials, grid, s)))
-      return rc;
+    if ((rc = phase(0, 1, 1))) return rc;          // updates: X' = 1/2 X Y
     if (it >= 1) {
       SM_HIP(hipEventSynchronize(p->ev[(it - 1) & 1]));
       if (p->h_pinned[(it - 1) & 1] == 0) break;
@@ -324,6 +333,60 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
   }
   *mu_out = mid;
   if (steps_out) *steps_out = std::min(step, (int)max_steps);
+  return SM_OK;
+}
+
+int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_sign_opts* o, void* ws,
+                sm_sub_stats* stats, int32_t repeats, int32_t* best_out, double* times_ms, void* stream) {
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (!p || !H || !ws || !stats) return set_error(SM_ERR_ARG, "sm_autotune: null argument");
+  if (repeats < 1 || repeats > 20) return set_error(SM_ERR_ARG, "sm_autotune: repeats out of [1, 20]");
+  if ((rc = ensure_device(p))) return rc;
+  hipStream_t s = as_stream(stream);
+  hipEvent_t e0, e1;
+  SM_HIP(hipEventCreate(&e0));
+  SM_HIP(hipEventCreate(&e1));
+  double best_t = 1e300;
+  int best = 0;
+  for (int v = 0; v < kGemmVariants; ++v) {
+    sm_sign_opts ov = *o;
+    ov.variant = v;
+    double tv = 1e300;
+    for (int r = 0; r < repeats; ++r) {
+      if ((rc = build_submatrices(p, chunk, H, mu, &ov, ws, stats, stream))) break;
+      SM_HIP(hipEventRecord(e0, s));
+      if ((rc = submatrix_sign(p, chunk, ws, &ov, stats, stream))) break;
+      SM_HIP(hipEventRecord(e1, s));
+      SM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      SM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      tv = std::min(tv, (double)ms);
+    }
+    if (rc) break;
+    if (times_ms) times_ms[v] = tv;
+    if (tv < best_t) {
+      best_t = tv;
+      best = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  p->tuned[o->phase1] = best;
+  if (o->refine_steps > 0) p->tuned[o->refine] = best;
+  if (best_out) *best_out = best;
+  return SM_OK;
+}
+
+int sm_plan_tuning(sm_plan* p, int32_t* get, const int32_t* set) {
+  if (!p) return set_error(SM_ERR_ARG, "sm_plan_tuning: null plan");
+  if (get) std::memcpy(get, p->tuned, sizeof(p->tuned));
+  if (set) {
+    for (int k = 0; k < 5; ++k)
+      if (set[k] < 0 || set[k] >= kGemmVariants) return set_error(SM_ERR_ARG, "sm_plan_tuning: variant out of range");
+    std::memcpy(p->tuned, set, sizeof(p->tuned));
+  }
   return SM_OK;
 }
 

@@ -9,6 +9,8 @@
 // submatrices and builds the tile lists of the next launches.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "smsign_internal.h"
 
@@ -35,12 +37,6 @@ template <> struct Traits<SM_F16> { using S = float; using L = _Float16; static 
 template <> struct Traits<SM_BF16X3> { using S = float; using L = uint16_t; static constexpr int K = 64, KP = 8; using Acc = f4; };
 
 constexpr int kBlock = 256;   // 4 waves in a 2 x 2 arrangement, 32 x 32 outputs each
-
-struct ListView {
-  const int32_t* count;   // [0] tiles, [1] submatrices
-  const int32_t* list;    // local submatrix ids
-  const int32_t* prefix;  // tile prefix, [n+1]
-};
 
 // NL consecutive elements of one operand column as 16-byte vector loads
 // (zeros for a row past n_pad).  The address is 16-byte aligned: n_pad and
@@ -75,10 +71,19 @@ __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
 // C[r][c] = sum_k L[k][r] R[k][c] with L = X and R = X or Y stored column-major;
 // by symmetry L[k][r] = X[r][k], so C = X R.  Both operand panels are read as
 // columns (contiguous k), i.e. LDS rows hold one output row's k-slab.
-template <int MODE, int WHICH>
-__global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
-                                                         typename Traits<MODE>::S* __restrict__ mats,
-                                                         const SubState* __restrict__ st, ListView lv,
+// DEPTH: how many stages ahead the operand panels are loaded into registers
+// (1: the next stage, 2: the one after; more latency cover, more registers).
+// XCD: workgroups are dealt to the 8 XCDs round-robin (workgroup b on XCD
+// b % 8), each with its own L2.  With XCD set, the workgroups of XCD x walk
+// the x-th contiguous eighth of the tile list, so all tiles of a submatrix
+// (adjacent in the list) share one L2 instead of pulling its operands into
+// all eight.
+constexpr int kXcds = 8;
+
+template <int MODE, int WHICH, int DEPTH, bool XCD>
+__global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::S* __restrict__ mats,
+                                                         const int32_t* __restrict__ count,
+                                                         const TileRec* __restrict__ recs,
                                                          double* __restrict__ partials) {
   using Tr = Traits<MODE>;
   using S = typename Tr::S;
@@ -97,22 +102,24 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
   const int wm = wid >> 1, wn = wid & 1;
   const int lrow = tid >> 2;             // 0..63: row of the operand panel this thread loads
   const int lpart = (tid & 3) * NL;      // k offset inside the stage
-  const int total = lv.count[0];
-  const int nlist = lv.count[1];
+  const int total = count[0];
 
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    int lo = 0, hi = nlist - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (lv.prefix[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    const int l = lv.list[lo];
-    const int lt = t - lv.prefix[lo];
-    const int g = g0 + l;
-    const int npad = p.npad_g[g];
+  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x;
+  if (XCD) {
+    const int x = blockIdx.x % kXcds;
+    t_step = ((int)gridDim.x - x + kXcds - 1) / kXcds;   // workgroups on XCD x
+    t_begin = (int)((int64_t)total * x / kXcds) + (int)blockIdx.x / kXcds;
+    t_end = (int)((int64_t)total * (x + 1) / kXcds);
+  }
+  TileRec nxt;
+  if (t_begin < t_end) nxt = recs[t_begin];
+  for (int t = t_begin; t < t_end; t += t_step) {
+    const TileRec rec = nxt;
+    if (t + t_step < t_end) nxt = recs[t + t_step];   // prefetch the next tile's record
+    const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
-    S* base = mats + p.mat_off_g[g];
-    const int it = st[l].iters;
+    S* base = mats + rec.mat_off;
+    const int it = rec.it;
     const S* Xp;
     const S* Rp;
     S* Out;
@@ -125,8 +132,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
       Rp = base + 2 * nn;
       Out = base + (int64_t)(it & 1) * nn;
     }
-    int bi, bj;
-    tile_coords(lt, bi, bj);
+    const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
     const int r0 = bi * 64, c0 = bj * 64;
     // the last tile row / column may reach past n_pad (a multiple of 32): its
     // operand rows load as zeros and the wave blocks there are skipped
@@ -144,13 +150,23 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = typename Tr::Acc{0, 0, 0, 0};
 
-    S ra[NL], rb[NL];
-    load_col<S, NL>(ra, ga, va);
-    load_col<S, NL>(rb, gb, vb);
-
+    // operand stages are loaded DEPTH stages ahead of their use (register sets
+    // s % DEPTH), so a global load has DEPTH stages of MFMA work to arrive
     const int nst = npad / K;
+    auto k_loop = [&](auto compute_tag) {
+    constexpr bool COMPUTE = decltype(compute_tag)::value;
+    S rga[DEPTH][NL], rgb[DEPTH][NL];
+#pragma unroll
+    for (int q = 0; q < DEPTH; ++q)
+      if (q < nst) {
+        load_col<S, NL>(rga[q], ga + q * K, va);
+        load_col<S, NL>(rgb[q], gb + q * K, vb);
+      }
     for (int s = 0; s < nst; ++s) {
       const int buf = s & 1;
+      const int rs = DEPTH == 1 ? 0 : (s % DEPTH);
+      S (&ra)[NL] = rga[rs];
+      S (&rb)[NL] = rgb[rs];
       // ---- registers -> LDS (with the precision conversion) ----
       LT* sa = &lds[buf][0][lrow * LD + lpart];
       LT* sb = &lds[buf][1][lrow * LD + lpart];
@@ -177,18 +193,16 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
         }
       }
       __syncthreads();
-      // ---- prefetch the next stage into registers ----
-      if (s + 1 < nst) {
-        const S* na = ga + (int64_t)(s + 1) * K;
-        const S* nb = gb + (int64_t)(s + 1) * K;
-        load_col<S, NL>(ra, na, va);
-        load_col<S, NL>(rb, nb, vb);
+      // ---- prefetch stage s + DEPTH into the register set just emptied ----
+      if (s + DEPTH < nst) {
+        load_col<S, NL>(ra, ga + (int64_t)(s + DEPTH) * K, va);
+        load_col<S, NL>(rb, gb + (int64_t)(s + DEPTH) * K, vb);
       }
       // ---- MFMA on the LDS stage ----
       const int kq = lane >> 4;    // k group of this lane
       const int rl = lane & 15;    // row / column inside a 16 x 16 block
-      if (!wvalid) {
-        // wave block past n_pad: nothing to accumulate
+      if constexpr (!COMPUTE) {
+        // wave block past n_pad (or above the diagonal): nothing to accumulate
       } else if constexpr (MODE == SM_F64) {
         // 16x16x4: lane supplies A[rl][kq], B[kq][rl]; the k index inside the
         // stage is permuted to 4 kq + kk so each lane reads 4 contiguous values.
@@ -273,6 +287,8 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
         }
       }
     }
+    };
+    if (wvalid) k_loop(std::true_type{}); else k_loop(std::false_type{});
 
     // ---- epilogue: 16 x 16 result block.  Register v of lane l holds column
     // l % 16 and row 4 (l / 16) + v for the float32-accumulating instructions,
@@ -313,38 +329,140 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(DevPlan p, int g0,
       __syncthreads();
       if (tid == 0) {
         const double sum = ((red[0] + red[1]) + red[2]) + red[3];
-        partials[p.tile_off_g[g] + lt] = sum;
+        partials[rec.part_idx] = sum;
       }
     }
     __syncthreads();
   }
 }
 
-template <int MODE>
-static hipError_t launch_mode(int which, const DevPlan& p, int g0, void* mats, const SubState* st,
-                              ListView lv, double* partials, int grid, hipStream_t s) {
-  using S = typename Traits<MODE>::S;
-  if (which == 0)
-    hipLaunchKernelGGL((ns_gemm_kernel<MODE, 0>), dim3(grid), dim3(kBlock), 0, s, p, g0, (S*)mats,
-                       st, lv, partials);
-  else
-    hipLaunchKernelGGL((ns_gemm_kernel<MODE, 1>), dim3(grid), dim3(kBlock), 0, s, p, g0, (S*)mats,
-                       st, lv, partials);
+// Tile records of the submatrices in lists `list_main` / `list_ref`: one
+// workgroup per (listed submatrix, list).
+__global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const SubState* __restrict__ st,
+                                                     const int32_t* __restrict__ lists, int max_subs,
+                                                     int list_main, int list_ref,
+                                                     TileRec* __restrict__ recs_main,
+                                                     TileRec* __restrict__ recs_ref) {
+  const int stride = 2 + 2 * max_subs + 1;
+  const int32_t* Lb = lists + (blockIdx.y == 0 ? list_main : list_ref) * stride;
+  TileRec* out = blockIdx.y == 0 ? recs_main : recs_ref;
+  const int a = blockIdx.x;
+  if (a >= Lb[1]) return;
+  const int l = Lb[2 + a];
+  const int first = Lb[2 + max_subs + a];
+  const int g = g0 + l;
+  const int npad = p.npad_g[g];
+  const int T = tiles_of(npad);
+  const int nt = T * (T + 1) / 2;
+  const int64_t mo = p.mat_off_g[g];
+  const int it = st[l].iters;
+  const int po = p.tile_off_g[g];
+  for (int lt = threadIdx.x; lt < nt; lt += blockDim.x) {
+    int bi, bj;
+    tile_coords(lt, bi, bj);
+    TileRec r;
+    r.mat_off = mo;
+    r.l = l;
+    r.bibj = (bi << 16) | bj;
+    r.npad = npad;
+    r.it = it;
+    r.part_idx = po + lt;
+    r.pad_ = 0;
+    out[first + lt] = r;
+  }
+}
+
+hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
+                         int max_subs, int list_main, int list_ref, TileRec* recs_main,
+                         TileRec* recs_ref, int grid_subs, hipStream_t s) {
+  if (grid_subs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, recs_ref ? 2 : 1), dim3(256), 0, s, p, g0, st, lists,
+                     max_subs, list_main, list_ref, recs_main, recs_ref);
   return hipGetLastError();
 }
 
-hipError_t launch_ns_gemm(int mode, int which, const DevPlan& p, int g0, void* mats,
-                          const SubState* st, const int32_t* count, const int32_t* list,
-                          const int32_t* prefix, double* partials, int grid, hipStream_t s) {
-  ListView lv{count, list, prefix};
+// kernel variants: 0 = {depth 1, linear}, 1 = {depth 1, XCD-aware}, 2 = {depth 2, XCD-aware}
+template <int MODE, int WHICH, int V>
+struct Var {
+  static constexpr int DEPTH = V == 2 ? 2 : 1;
+  static constexpr bool XCD = V >= 1;
+};
+
+template <int MODE, int WHICH, int V>
+static void* kernel_ptr() {
+  return reinterpret_cast<void*>(&ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::DEPTH, Var<MODE, WHICH, V>::XCD>);
+}
+
+template <int MODE, int WHICH, int V>
+static hipError_t launch_one(void* mats, const int32_t* count, const TileRec* recs, double* partials,
+                             int grid, hipStream_t s) {
+  using S = typename Traits<MODE>::S;
+  hipLaunchKernelGGL((ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::DEPTH, Var<MODE, WHICH, V>::XCD>),
+                     dim3(grid), dim3(kBlock), 0, s, (S*)mats, count, recs, partials);
+  return hipGetLastError();
+}
+
+template <int MODE, int WHICH>
+static hipError_t launch_which(int variant, void* mats, const int32_t* count, const TileRec* recs,
+                               double* partials, int grid, hipStream_t s) {
+  switch (variant) {
+    case 1: return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
+    case 2: return launch_one<MODE, WHICH, 2>(mats, count, recs, partials, grid, s);
+    default: return launch_one<MODE, WHICH, 0>(mats, count, recs, partials, grid, s);
+  }
+}
+
+template <int MODE>
+static hipError_t launch_mode(int which, int variant, void* mats, const int32_t* count, const TileRec* recs,
+                              double* partials, int grid, hipStream_t s) {
+  return which == 0 ? launch_which<MODE, 0>(variant, mats, count, recs, partials, grid, s)
+                    : launch_which<MODE, 1>(variant, mats, count, recs, partials, grid, s);
+}
+
+hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, const int32_t* count,
+                          const TileRec* recs, double* partials, int grid, hipStream_t s) {
   switch (mode) {
-    case SM_F64: return launch_mode<SM_F64>(which, p, g0, mats, st, lv, partials, grid, s);
-    case SM_F32: return launch_mode<SM_F32>(which, p, g0, mats, st, lv, partials, grid, s);
-    case SM_BF16: return launch_mode<SM_BF16>(which, p, g0, mats, st, lv, partials, grid, s);
-    case SM_F16: return launch_mode<SM_F16>(which, p, g0, mats, st, lv, partials, grid, s);
-    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, p, g0, mats, st, lv, partials, grid, s);
+    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, count, recs, partials, grid, s);
+    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, count, recs, partials, grid, s);
+    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, count, recs, partials, grid, s);
+    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, count, recs, partials, grid, s);
+    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, count, recs, partials, grid, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <int MODE, int WHICH>
+static void* ptr_which(int variant) {
+  switch (variant) {
+    case 1: return kernel_ptr<MODE, WHICH, 1>();
+    case 2: return kernel_ptr<MODE, WHICH, 2>();
+    default: return kernel_ptr<MODE, WHICH, 0>();
+  }
+}
+
+template <int MODE>
+static void* ptr_mode(int which, int variant) {
+  return which == 0 ? ptr_which<MODE, 0>(variant) : ptr_which<MODE, 1>(variant);
+}
+
+// Resident workgroups per compute unit of a GEMM kernel (persistent grid size).
+int ns_gemm_blocks_per_cu(int mode, int which, int variant) {
+  static int cache[5][2][kGemmVariants] = {};
+  if (mode < 0 || mode > 4 || which < 0 || which > 1 || variant < 0 || variant >= kGemmVariants) return 1;
+  int& c = cache[mode][which][variant];
+  if (c) return c;
+  void* f = nullptr;
+  switch (mode) {
+    case SM_F64: f = ptr_mode<SM_F64>(which, variant); break;
+    case SM_F32: f = ptr_mode<SM_F32>(which, variant); break;
+    case SM_BF16: f = ptr_mode<SM_BF16>(which, variant); break;
+    case SM_F16: f = ptr_mode<SM_F16>(which, variant); break;
+    default: f = ptr_mode<SM_BF16X3>(which, variant); break;
+  }
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  c = nb;
+  return nb;
 }
 
 // ---------------------------------------------------------------------------

@@ -52,6 +52,8 @@ sm::WsLayout sm_plan::layout(int storage_f64) const {
   L.lists = off;
   // 4 lists: count_tiles, count_subs, list[max_subs], prefix[max_subs+1]
   off = align256(off + 4 * (2 + max_subs + max_subs + 1) * 4 + 64);
+  L.tiles = off;
+  off = align256(off + 2 * max_tiles * (int64_t)sizeof(TileRec));
   L.features = off;
   off = align256(off + max_subs * kNumFeatures * 4);
   L.scratch = off;
@@ -85,6 +87,7 @@ int sm_default_opts(int32_t prec, sm_sign_opts* o) {
   o->power_steps = 8;
   o->scale_margin = 0.05;
   o->probes = 2;
+  o->variant = -1;
   if (prec == SM_F64) {
     o->refine_steps = 0;
     o->refine = SM_F64;
@@ -314,6 +317,9 @@ int ensure_device(sm_plan* p) {
   if ((rc = dev_alloc(p, (size_t)2 * p->n_atoms, &p->d_gersh)) != SM_OK) return rc;
   SM_HIP(hipHostMalloc((void**)&p->h_pinned, 64, hipHostMallocDefault));
   std::memset(p->h_pinned, 0, 64);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    p->num_cu = ncu;
   SM_HIP(hipEventCreateWithFlags(&p->ev[0], hipEventDisableTiming));
   SM_HIP(hipEventCreateWithFlags(&p->ev[1], hipEventDisableTiming));
   p->device = dev;

@@ -40,6 +40,7 @@ struct sm_plan {
 
   // device copies (allocated on first device use)
   int device = -1;
+  int num_cu = 256;
   sm::DevPlan dev{};
   std::vector<void*> dev_allocs;
   int64_t* d_diag_idx = nullptr;
@@ -49,6 +50,7 @@ struct sm_plan {
   int32_t* h_pinned = nullptr;      // pinned host counters [8]
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_f64 = -1;                // storage precision of the last build (-1: none)
+  int32_t tuned[5] = {0, 0, 0, 0, 0};  // GEMM variant per precision (sm_autotune)
   sm_mlp* mlp = nullptr;            // scaling network for SM_SCALE_LEARNED (not owned)
   // kernel timing (sm_profile_enable)
   bool profiling = false;

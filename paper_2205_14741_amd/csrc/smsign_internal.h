@@ -45,12 +45,25 @@ struct SubState {
   double pad_;
 };
 
+// One output tile of a Newton-Schulz GEMM launch, written by expand_kernel so
+// that a GEMM workgroup finds everything about its tile in one 32-byte load.
+struct TileRec {
+  int64_t mat_off;   // element offset of the submatrix's buffers in the chunk
+  int32_t l;         // local submatrix index
+  int32_t bibj;      // tile row << 16 | tile column (row >= column)
+  int32_t npad;
+  int32_t it;        // iteration counter (parity selects the X buffer)
+  int32_t part_idx;  // index of this tile's residual partial
+  int32_t pad_;
+};
+
 // Workspace layout (bytes) for one chunk, given the storage element size.
 struct WsLayout {
   int64_t mats;        // 3 * sum npad^2 elements
   int64_t state;       // SubState[max_subs]
   int64_t partials;    // double[max_tiles]
   int64_t lists;       // int32: counts[4], list[2][max_subs], prefix[2][max_subs+1]
+  int64_t tiles;       // TileRec[2][max_tiles]: tile records of the main / refinement GEMMs
   int64_t features;    // float[max_subs * kNumFeatures]
   int64_t scratch;     // double[max_subs * 4] (power iteration, probes)
   int64_t vecs;        // double[sum over chunk of npad * kMaxProbes*2] probe / power vectors
@@ -71,9 +84,13 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, sm_sub_stats* stats,
                            hipStream_t s);
-hipError_t launch_ns_gemm(int mode, int which, const DevPlan& p, int g0, void* mats,
-                          const SubState* st, const int32_t* count, const int32_t* list,
-                          const int32_t* prefix, double* partials, int grid, hipStream_t s);
+hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
+                         int max_subs, int list_main, int list_ref, TileRec* recs_main,
+                         TileRec* recs_ref, int grid_subs, hipStream_t s);
+constexpr int kGemmVariants = 3;   // 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2
+hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, const int32_t* count,
+                          const TileRec* recs, double* partials, int grid, hipStream_t s);
+int ns_gemm_blocks_per_cu(int mode, int which, int variant);
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                          const SubState* st, int probes, double* vecs, sm_sub_stats* stats,
                          hipStream_t s);

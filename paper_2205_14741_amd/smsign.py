@@ -26,7 +26,7 @@ EXPORTED = (
     "sm_density_matrix", "sm_find_mu", "sm_gershgorin_bracket", "sm_selftest_mfma",
     "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
-    "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp",
+    "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning",
 )
 
 
@@ -46,7 +46,7 @@ class SignOpts(C.Structure):
                 ("max_iter", C.c_int32), ("tol", C.c_double), ("switch_tol", C.c_double),
                 ("stall_below", C.c_double), ("stall_ratio", C.c_double), ("scaling", C.c_int32),
                 ("power_steps", C.c_int32), ("scale_margin", C.c_double), ("probes", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("variant", C.c_int32)]
 
     def copy(self) -> "SignOpts":
         o = SignOpts()
@@ -108,6 +108,8 @@ def lib() -> C.CDLL:
         "sm_mlp_loss_grad": (i32, [vp, vp, i64, vp, i64, vp, vp, vp]),
         "sm_mlp_train": (i32, [vp, vp, i64, vp, i64, i32, i32, C.c_float, i32, C.c_uint64, vp, vp]),
         "sm_plan_set_mlp": (i32, [vp, vp]),
+        "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, vp, vp, vp]),
+        "sm_plan_tuning": (i32, [vp, vp, vp]),
         "sm_last_error": (C.c_char_p, []),
         "sm_version": (C.c_char_p, []),
     }
@@ -332,6 +334,27 @@ def sm_mlp_train(mlp: Mlp, X, T, n: int, epochs: int, batch: int, lr: float, ldx
 
 def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):
     _check(lib().sm_plan_set_mlp(plan.handle, None if mlp is None else mlp.handle))
+
+
+N_VARIANTS = 3
+
+
+def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, repeats: int = 2,
+                stream=None):
+    """(best variant, sign-phase ms per variant) -- the plan keeps the choice."""
+    best = C.c_int32()
+    t = np.zeros(N_VARIANTS)
+    _check(lib().sm_autotune(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts), _ptr(ws),
+                             _ptr(stats), int(repeats), C.byref(best), t.ctypes.data, _stream(stream)))
+    return best.value, t
+
+
+def sm_plan_tuning(plan: Plan, table=None):
+    """Current tuned variant per precision; replace it with `table` if given."""
+    get = np.zeros(5, np.int32)
+    st = None if table is None else np.ascontiguousarray(table, dtype=np.int32)
+    _check(lib().sm_plan_tuning(plan.handle, get.ctypes.data, None if st is None else st.ctypes.data))
+    return get
 
 
 def version() -> str:
