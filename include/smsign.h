@@ -93,7 +93,15 @@ typedef struct {
                             (see sm_autotune; 0 before tuning); 0 = tiles dealt to workgroups
                             in list order, 1 = each XCD walks a contiguous range of the tile
                             list (a submatrix stays in one L2), 2 = as 1 with operands
-                            prefetched two stages ahead */
+                            prefetched two stages ahead, 3 = as 1 with 128 x 128 output
+                            tiles (float32-accumulating precisions, plans padded to 64 or
+                            128; otherwise runs as 1) */
+  int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
+                            G > 0: capture G iterations (tile expansion, squares, residuals,
+                            scheduler, updates) into one HIP graph, cached per plan / chunk /
+                            workspace, and replay it until no submatrix is left (the host
+                            polls once per replay).  Ignored while kernel timing is on. */
+  int32_t reserved;
 } sm_sign_opts;
 
 /* Per-submatrix result record, written on the device by build_submatrices
@@ -267,7 +275,8 @@ int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
  * `repeats`), then records the fastest variant as the plan's choice for the
  * precisions of `opts` (used when opts->variant == -1).
  *   best_out   host int32 (may be NULL): the chosen variant
- *   times_ms   host double[3] (may be NULL): sign time of each variant
+ *   times_ms   host double[4] (may be NULL): sign time of each variant (-1: not
+ *              applicable to this plan / precision)
  * Synchronous.  Leaves the workspace holding the last variant's result. */
 int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
                 const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, int32_t repeats,

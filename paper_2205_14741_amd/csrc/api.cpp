@@ -25,6 +25,7 @@ int check_opts(const sm_sign_opts* o) {
   if (o->scaling < SM_SCALE_GERSHGORIN || o->scaling > SM_SCALE_LEARNED) return set_error(SM_ERR_ARG, "opts.scaling = %d invalid", o->scaling);
   if (o->probes < 0 || o->probes > kMaxProbes) return set_error(SM_ERR_ARG, "opts.probes = %d out of [0, %d]", o->probes, kMaxProbes);
   if (o->variant < -1 || o->variant >= kGemmVariants) return set_error(SM_ERR_ARG, "opts.variant = %d out of [-1, %d)", o->variant, kGemmVariants);
+  if (o->graph_iters < 0 || o->graph_iters > 64) return set_error(SM_ERR_ARG, "opts.graph_iters = %d out of [0, 64]", o->graph_iters);
   if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
   if (!(o->tol >= 0) || !(o->switch_tol >= 0) || !(o->stall_ratio >= 0) || !(o->stall_below >= 0) ||
       !(o->scale_margin >= 0))
@@ -72,9 +73,17 @@ int chunk_tiles(const sm_plan* p, int g0, int nsub) {
 }
 
 // Launch one Newton-Schulz GEMM, bracketed by timing events when profiling.
+// Variant that actually runs: the 128-wide tiles need n_pad % 64 == 0 and a
+// float32-accumulating precision, otherwise the XCD-aware 64-wide kernel.
+int effective_variant(const sm_plan* p, int mode, int variant) {
+  int v = variant >= 0 ? variant : p->tuned[mode];
+  if (v == 3 && (mode == SM_F64 || p->pad_to < 64)) v = 1;
+  return v;
+}
+
 int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, const int32_t* cnt,
                 const TileRec* recs, double* partials, int max_tiles, hipStream_t s) {
-  const int v = variant >= 0 ? variant : p->tuned[mode];
+  const int v = effective_variant(p, mode, variant);
   // persistent grid: all resident workgroups, a multiple of the 8 XCDs
   int grid = std::min(max_tiles, p->num_cu * ns_gemm_blocks_per_cu(mode, which, v));
   grid = std::max(8, grid / 8 * 8);
@@ -188,7 +197,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   if (p->last_f64 != f64)
     return set_error(SM_ERR_STATE, "submatrix_sign: the workspace was not built for this precision schedule");
   WsPtrs w = ws_ptrs(p, ws, f64);
-  hipStream_t s = as_stream(stream);
+  hipStream_t s = as_stream(stream);   // the lambdas below launch on `s`
   const int64_t stride = list_stride(p);
   int32_t* L0 = w.lists;
   auto list_count = [&](int L) { return L0 + L * stride; };
@@ -199,9 +208,12 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   TileRec* rec_main = w.tiles;
   TileRec* rec_ref = w.tiles + p->max_tiles;
   const int ms = (int)p->max_subs;
+  const int tsh_main = tile_shift(effective_variant(p, mode_main, o->variant), mode_main);
+  const int tsh_ref = tile_shift(effective_variant(p, mode_ref, o->variant), mode_ref);
   // expand lists (Lm, Lr) into tile records, then run the GEMMs of kind `which`
   auto phase = [&](int Lm, int Lr, int which) -> int {
-    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, Lm, Lr, rec_main, has_ref ? rec_ref : nullptr, nsub, s));
+    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, Lm, Lr, rec_main, has_ref ? rec_ref : nullptr,
+                         tsh_main, tsh_ref, nsub, s));
     int r;
     if ((r = gemm_launch(p, mode_main, which, o->variant, w.mats, list_count(Lm), rec_main, w.partials,
                          max_tiles, s)))
@@ -212,17 +224,73 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     return SM_OK;
   };
 
-  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, stats, s));
+  // one iteration of the loop: squares, residuals + scheduler, updates
+  auto iteration = [&](hipStream_t st) -> int {
+    int r;
+    hipStream_t keep = s;
+    s = st;
+    r = phase(2, 3, 0);                                                   // A = X^2, Y = 3I - A
+    if (!r) {
+      hipError_t e = launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref, st);
+      if (e != hipSuccess) r = hip_error(e, "launch_schedule");
+    }
+    if (!r) r = phase(0, 1, 1);                                           // X' = 1/2 X Y
+    s = keep;
+    return r;
+  };
+
+  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, tsh_main, tsh_ref, s));
   const int lim = o->max_iter + o->refine_steps + 2;
-  for (int it = 0; it <= lim; ++it) {
-    if ((rc = phase(2, 3, 0))) return rc;          // squares: A = X^2, Y = 3I - A
-    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, stats, s));
-    SM_HIP(hipMemcpyAsync(&p->h_pinned[it & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
-    SM_HIP(hipEventRecord(p->ev[it & 1], s));
-    if ((rc = phase(0, 1, 1))) return rc;          // updates: X' = 1/2 X Y
-    if (it >= 1) {
-      SM_HIP(hipEventSynchronize(p->ev[(it - 1) & 1]));
-      if (p->h_pinned[(it - 1) & 1] == 0) break;
+  const int G = p->profiling ? 0 : o->graph_iters;
+  if (G == 0) {
+    for (int it = 0; it <= lim; ++it) {
+      if ((rc = phase(2, 3, 0))) return rc;          // squares: A = X^2, Y = 3I - A
+      SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref, s));
+      SM_HIP(hipMemcpyAsync(&p->h_pinned[it & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
+      SM_HIP(hipEventRecord(p->ev[it & 1], s));
+      if ((rc = phase(0, 1, 1))) return rc;          // updates: X' = 1/2 X Y
+      if (it >= 1) {
+        SM_HIP(hipEventSynchronize(p->ev[(it - 1) & 1]));
+        if (p->h_pinned[(it - 1) & 1] == 0) break;
+      }
+    }
+  } else {
+    // find or capture the graph of G iterations for this chunk / workspace / schedule
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : p->graphs)
+      if (e.chunk == chunk && e.ws == ws && std::memcmp(&e.opts, o, sizeof(*o)) == 0 &&
+          std::memcmp(e.tuned, p->tuned, sizeof(p->tuned)) == 0)
+        exec = e.exec;
+    if (!exec) {
+      if (!p->capture_stream) SM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+      for (int m = 0; m < 5; ++m)                    // occupancy queries outside the capture
+        for (int wh = 0; wh < 2; ++wh) (void)ns_gemm_blocks_per_cu(m, wh, effective_variant(p, m, o->variant));
+      SM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+      int r = SM_OK;
+      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
+      if (r) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+      }
+      if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
+      sm_plan::GraphEntry ge{chunk, ws, *o, {0}, exec};
+      std::memcpy(ge.tuned, p->tuned, sizeof(p->tuned));
+      p->graphs.push_back(ge);
+    }
+    const int replays = (lim + G) / G;
+    for (int r = 0; r < replays; ++r) {
+      SM_HIP(hipGraphLaunch(exec, s));
+      SM_HIP(hipMemcpyAsync(&p->h_pinned[r & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
+      SM_HIP(hipEventRecord(p->ev[r & 1], s));
+      if (r >= 1) {
+        SM_HIP(hipEventSynchronize(p->ev[(r - 1) & 1]));
+        if (p->h_pinned[(r - 1) & 1] == 0) break;
+      }
     }
   }
   SM_HIP(launch_finish(p->dev, g0, nsub, w.mats, f64, w.st, o->probes, w.vecs, stats, s));
@@ -353,6 +421,10 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
     sm_sign_opts ov = *o;
     ov.variant = v;
     double tv = 1e300;
+    if (v == 3 && effective_variant(p, o->phase1, 3) != 3) {   // no 128-wide kernel here
+      if (times_ms) times_ms[v] = -1.0;
+      continue;
+    }
     for (int r = 0; r < repeats; ++r) {
       if ((rc = build_submatrices(p, chunk, H, mu, &ov, ws, stats, stream))) break;
       SM_HIP(hipEventRecord(e0, s));

@@ -337,48 +337,281 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
 }
 
 // Tile records of the submatrices in lists `list_main` / `list_ref`: one
-// workgroup per (listed submatrix, list).
+// workgroup per (listed submatrix, list).  Tiles have edge 1 << tshift (64 or
+// 128); residual partial slots are always those of the 64-tiles.
 __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const SubState* __restrict__ st,
                                                      const int32_t* __restrict__ lists, int max_subs,
                                                      int list_main, int list_ref,
                                                      TileRec* __restrict__ recs_main,
-                                                     TileRec* __restrict__ recs_ref) {
+                                                     TileRec* __restrict__ recs_ref, int tshift_main,
+                                                     int tshift_ref) {
   const int stride = 2 + 2 * max_subs + 1;
   const int32_t* Lb = lists + (blockIdx.y == 0 ? list_main : list_ref) * stride;
   TileRec* out = blockIdx.y == 0 ? recs_main : recs_ref;
+  const int tshift = blockIdx.y == 0 ? tshift_main : tshift_ref;
   const int a = blockIdx.x;
   if (a >= Lb[1]) return;
   const int l = Lb[2 + a];
   const int first = Lb[2 + max_subs + a];
   const int g = g0 + l;
   const int npad = p.npad_g[g];
-  const int T = tiles_of(npad);
+  const int T = (npad + (1 << tshift) - 1) >> tshift;
+  const int f = 1 << (tshift - 6);
   const int nt = T * (T + 1) / 2;
   const int64_t mo = p.mat_off_g[g];
   const int it = st[l].iters;
   const int po = p.tile_off_g[g];
+  const int t64 = tiles_of(npad);
   for (int lt = threadIdx.x; lt < nt; lt += blockDim.x) {
     int bi, bj;
     tile_coords(lt, bi, bj);
+    const int b64i = bi * f, b64j = bj * f;
     TileRec r;
     r.mat_off = mo;
     r.l = l;
     r.bibj = (bi << 16) | bj;
     r.npad = npad;
     r.it = it;
-    r.part_idx = po + lt;
-    r.pad_ = 0;
+    r.part_idx = po + b64i * (b64i + 1) / 2 + b64j;
+    r.tiles64 = t64;
     out[first + lt] = r;
   }
 }
 
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int grid_subs, hipStream_t s) {
+                         TileRec* recs_ref, int tshift_main, int tshift_ref, int grid_subs,
+                         hipStream_t s) {
   if (grid_subs <= 0) return hipSuccess;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, recs_ref ? 2 : 1), dim3(256), 0, s, p, g0, st, lists,
-                     max_subs, list_main, list_ref, recs_main, recs_ref);
+                     max_subs, list_main, list_ref, recs_main, recs_ref, tshift_main, tshift_ref);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 128 x 128 output tiles for large submatrices (float32 accumulation only):
+// 4 waves in 2 x 2, 64 x 64 outputs each (4 x 4 MFMA blocks of 16 x 16), half
+// the operand traffic per flop of the 64 x 64 tiles.  n_pad must be a multiple
+// of 64; a 64-wide wave block past n_pad is skipped.  The tile's residual sum
+// goes to the partial slot of its top-left 64-tile, zeros to the other 64-tile
+// slots it covers, so the residual reduction is the same for both tile sizes.
+// ---------------------------------------------------------------------------
+template <int MODE> struct Traits128;
+template <> struct Traits128<SM_F32> { using S = float; using L = float; static constexpr int K = 16, KP = 4; };
+template <> struct Traits128<SM_BF16> { using S = float; using L = uint16_t; static constexpr int K = 32, KP = 8; };
+template <> struct Traits128<SM_F16> { using S = float; using L = _Float16; static constexpr int K = 32, KP = 8; };
+template <> struct Traits128<SM_BF16X3> { using S = float; using L = uint16_t; static constexpr int K = 32, KP = 8; };
+
+template <int MODE, int WHICH>
+__global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ mats,
+                                                            const int32_t* __restrict__ count,
+                                                            const TileRec* __restrict__ recs,
+                                                            double* __restrict__ partials) {
+  using Tr = Traits128<MODE>;
+  using S = typename Tr::S;
+  using LT = typename Tr::L;
+  constexpr int K = Tr::K;
+  constexpr int LD = K + Tr::KP;
+  constexpr int NL = K / 2;              // 128 rows x K per operand over 256 threads
+  constexpr bool SPLIT = (MODE == SM_BF16X3);
+  constexpr int NOP = SPLIT ? 4 : 2;
+  __shared__ __attribute__((aligned(16))) LT lds[2][NOP][128 * LD];
+  __shared__ double red[4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int lrow = tid >> 1;             // 0..127
+  const int lpart = (tid & 1) * NL;
+  const int total = count[0];
+  const int x8 = blockIdx.x % kXcds;
+  const int t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
+  const int t_begin = (int)((int64_t)total * x8 / kXcds) + (int)blockIdx.x / kXcds;
+  const int t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
+  TileRec nxt;
+  if (t_begin < t_end) nxt = recs[t_begin];
+  for (int t = t_begin; t < t_end; t += t_step) {
+    const TileRec rec = nxt;
+    if (t + t_step < t_end) nxt = recs[t + t_step];
+    const int npad = rec.npad;
+    const int64_t nn = (int64_t)npad * npad;
+    S* base = mats + rec.mat_off;
+    const int it = rec.it;
+    const S* Xp;
+    const S* Rp;
+    S* Out;
+    if (WHICH == 0) {
+      Xp = base + (int64_t)(it & 1) * nn;
+      Rp = Xp;
+      Out = base + 2 * nn;
+    } else {
+      Xp = base + (int64_t)((it + 1) & 1) * nn;
+      Rp = base + 2 * nn;
+      Out = base + (int64_t)(it & 1) * nn;
+    }
+    const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
+    const int r0 = bi * 128, c0 = bj * 128;
+    const bool va = (r0 + lrow) < npad;
+    const bool vb = (c0 + lrow) < npad;
+    const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && !(bi == bj && wm < wn);
+    const S* ga = Xp + (int64_t)(va ? r0 + lrow : 0) * npad + lpart;
+    const S* gb = Rp + (int64_t)(vb ? c0 + lrow : 0) * npad + lpart;
+    const int nst = npad / K;
+    const int kq = lane >> 4;
+    const int rl = lane & 15;
+
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+    auto k_loop = [&](auto compute_tag) {
+      constexpr bool COMPUTE = decltype(compute_tag)::value;
+      S ra[NL], rb[NL];
+      load_col<S, NL>(ra, ga, va);
+      load_col<S, NL>(rb, gb, vb);
+      for (int s = 0; s < nst; ++s) {
+        const int buf = s & 1;
+        LT* sa = &lds[buf][0][lrow * LD + lpart];
+        LT* sb = &lds[buf][1][lrow * LD + lpart];
+        if constexpr (MODE == SM_F32) {
+#pragma unroll
+          for (int e = 0; e < NL; ++e) { sa[e] = ra[e]; sb[e] = rb[e]; }
+        } else if constexpr (MODE == SM_F16) {
+#pragma unroll
+          for (int e = 0; e < NL; ++e) { sa[e] = (_Float16)ra[e]; sb[e] = (_Float16)rb[e]; }
+        } else if constexpr (MODE == SM_BF16) {
+#pragma unroll
+          for (int e = 0; e < NL; ++e) { sa[e] = f32_to_bf16_bits(ra[e]); sb[e] = f32_to_bf16_bits(rb[e]); }
+        } else {
+          LT* sal = &lds[buf][2][lrow * LD + lpart];
+          LT* sbl = &lds[buf][3][lrow * LD + lpart];
+#pragma unroll
+          for (int e = 0; e < NL; ++e) {
+            const uint16_t ha = f32_to_bf16_bits(ra[e]);
+            const uint16_t hb = f32_to_bf16_bits(rb[e]);
+            sa[e] = ha;
+            sb[e] = hb;
+            sal[e] = f32_to_bf16_bits(ra[e] - bf16_bits_to_f32(ha));
+            sbl[e] = f32_to_bf16_bits(rb[e] - bf16_bits_to_f32(hb));
+          }
+        }
+        __syncthreads();
+        if (s + 1 < nst) {
+          load_col<S, NL>(ra, ga + (int64_t)(s + 1) * K, va);
+          load_col<S, NL>(rb, gb + (int64_t)(s + 1) * K, vb);
+        }
+        if constexpr (!COMPUTE) {
+        } else if constexpr (MODE == SM_F32) {
+          // 16x16x4 with the stage's k permuted to 4 kq + kk (one 16-byte read per fragment)
+          float a[4][4], b[4][4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+              a[x][kk] = lds[buf][0][(wm * 64 + x * 16 + rl) * LD + 4 * kq + kk];
+              b[x][kk] = lds[buf][1][(wn * 64 + x * 16 + rl) * LD + 4 * kq + kk];
+            }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][kk], b[y][kk], acc[x][y], 0, 0, 0);
+        } else if constexpr (MODE == SM_F16) {
+          f16x8 a[4], b[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            a[x] = *reinterpret_cast<const f16x8*>(&lds[buf][0][(wm * 64 + x * 16 + rl) * LD + 8 * kq]);
+            b[x] = *reinterpret_cast<const f16x8*>(&lds[buf][1][(wn * 64 + x * 16 + rl) * LD + 8 * kq]);
+          }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[x], b[y], acc[x][y], 0, 0, 0);
+        } else {
+          bf16x8 a[4], b[4];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            a[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][0][(wm * 64 + x * 16 + rl) * LD + 8 * kq]));
+            b[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][1][(wn * 64 + x * 16 + rl) * LD + 8 * kq]));
+          }
+          if constexpr (SPLIT) {
+            bf16x8 al[4], bl[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+              al[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][2][(wm * 64 + x * 16 + rl) * LD + 8 * kq]));
+              bl[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][3][(wn * 64 + x * 16 + rl) * LD + 8 * kq]));
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y) {
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[x], b[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], bl[y], acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+              }
+          } else {
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+          }
+        }
+      }
+    };
+    if (wvalid) k_loop(std::true_type{}); else k_loop(std::false_type{});
+
+    // epilogue: lower triangle mirrored (exactly symmetric result)
+    double part = 0.0;
+#pragma unroll
+    for (int x = 0; x < (wvalid ? 4 : 0); ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int rb = r0 + wm * 64 + x * 16 + 4 * kq;
+        const int cc = c0 + wn * 64 + y * 16 + rl;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = rb + v;
+          if (rr < cc) continue;
+          const double a = (double)acc[x][y][v];
+          S outv;
+          if (WHICH == 0) {
+            const double dg = (rr == cc) ? 1.0 : 0.0;
+            const double e = a - dg;
+            part += (rr == cc) ? e * e : 2.0 * e * e;
+            outv = (S)(3.0 * dg - a);
+          } else {
+            outv = (S)(0.5 * a);
+          }
+          Out[(int64_t)cc * npad + rr] = outv;
+          if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
+        }
+      }
+    if (WHICH == 0) {
+      part = wave_sum(part);
+      if (lane == 0) red[wid] = part;
+      __syncthreads();
+      if (tid == 0) {
+        partials[rec.part_idx] = ((red[0] + red[1]) + red[2]) + red[3];
+        // other 64-tile slots covered by this tile (lower triangle, inside n_pad)
+        const int b0i = 2 * bi, b0j = 2 * bj;
+        const int s0 = b0i * (b0i + 1) / 2 + b0j;
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          const int ti = b0i + (q >> 1), tj = b0j + (q & 1);
+          if (ti < rec.tiles64 && tj < rec.tiles64 && ti >= tj)
+            partials[rec.part_idx + (ti * (ti + 1) / 2 + tj - s0)] = 0.0;
+        }
+      }
+    }
+    __syncthreads();
+  }
 }
 
 // kernel variants: 0 = {depth 1, linear}, 1 = {depth 1, XCD-aware}, 2 = {depth 2, XCD-aware}
@@ -408,6 +641,14 @@ static hipError_t launch_which(int variant, void* mats, const int32_t* count, co
   switch (variant) {
     case 1: return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
     case 2: return launch_one<MODE, WHICH, 2>(mats, count, recs, partials, grid, s);
+    case 3:
+      if constexpr (MODE != SM_F64) {
+        hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH>), dim3(grid), dim3(kBlock), 0, s, (float*)mats,
+                           count, recs, partials);
+        return hipGetLastError();
+      } else {
+        return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
+      }
     default: return launch_one<MODE, WHICH, 0>(mats, count, recs, partials, grid, s);
   }
 }
@@ -436,6 +677,9 @@ static void* ptr_which(int variant) {
   switch (variant) {
     case 1: return kernel_ptr<MODE, WHICH, 1>();
     case 2: return kernel_ptr<MODE, WHICH, 2>();
+    case 3:
+      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH>);
+      else return kernel_ptr<MODE, WHICH, 1>();
     default: return kernel_ptr<MODE, WHICH, 0>();
   }
 }
@@ -523,17 +767,20 @@ __global__ __launch_bounds__(256) void residual_kernel(DevPlan p, int g0, int ns
 // refinement precision.
 __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int nsub, SubState* st,
                                                         int32_t* lists, int max_subs, SchedOpts o,
-                                                        int first) {
+                                                        int first, int tshift_main, int tshift_ref) {
   __shared__ int sh[16];
   const int stride = 2 + 2 * max_subs + 1;
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
   for (int base = 0; base < nsub; base += blockDim.x) {
     const int l = base + threadIdx.x;
-    int dec = 0, nt = 0;
+    int dec = 0, ntm = 0, ntr = 0;
     if (l < nsub) {
       SubState s = st[l];
-      const int T = tiles_of(p.npad_g[g0 + l]);
-      nt = T * (T + 1) / 2;
+      const int np = p.npad_g[g0 + l];
+      const int Tm = (np + (1 << tshift_main) - 1) >> tshift_main;
+      const int Tr = (np + (1 << tshift_ref) - 1) >> tshift_ref;
+      ntm = Tm * (Tm + 1) / 2;
+      ntr = Tr * (Tr + 1) / 2;
       if (first) {
         s.active = 1;
         s.phase = 0;
@@ -594,6 +841,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
                     : (L == 1) ? ((dec & DEC_UPD) && (dec & DEC_REF))
                     : (L == 2) ? ((dec & DEC_SQ) && !(dec & DEC_REF))
                                : ((dec & DEC_SQ) && (dec & DEC_REF));
+      const int nt = (L & 1) ? ntr : ntm;
       int tot_s, tot_t;
       const int ps = block_excl_scan(in ? 1 : 0, sh, tot_s);
       const int pt = block_excl_scan(in ? nt : 0, sh, tot_t);
@@ -621,12 +869,13 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
 
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
-                           const sm_sign_opts& so, int first, sm_sub_stats* /*stats*/,
+                           const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
                            hipStream_t s) {
   SchedOpts o{so.refine_steps, so.max_iter, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
   if (!first && nsub > 0)
     hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
-  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, lists, max_subs, o, first);
+  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, lists, max_subs, o, first,
+                     tshift_main, tshift_ref);
   return hipGetLastError();
 }
 

@@ -88,6 +88,7 @@ int sm_default_opts(int32_t prec, sm_sign_opts* o) {
   o->scale_margin = 0.05;
   o->probes = 2;
   o->variant = -1;
+  o->graph_iters = 0;
   if (prec == SM_F64) {
     o->refine_steps = 0;
     o->refine = SM_F64;
@@ -229,6 +230,8 @@ void sm_plan_destroy(sm_plan* p) {
     for (auto& e : p->ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : p->prof_ev) (void)hipEventDestroy(e);
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     if (cur >= 0) (void)hipSetDevice(cur);
   }
   delete p;

@@ -51,6 +51,16 @@ struct sm_plan {
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_f64 = -1;                // storage precision of the last build (-1: none)
   int32_t tuned[5] = {0, 0, 0, 0, 0};  // GEMM variant per precision (sm_autotune)
+  // captured iteration graphs (sm_sign_opts.graph_iters)
+  struct GraphEntry {
+    int chunk;
+    void* ws;
+    sm_sign_opts opts;
+    int32_t tuned[5];
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t capture_stream = nullptr;
   sm_mlp* mlp = nullptr;            // scaling network for SM_SCALE_LEARNED (not owned)
   // kernel timing (sm_profile_enable)
   bool profiling = false;

@@ -53,8 +53,8 @@ struct TileRec {
   int32_t bibj;      // tile row << 16 | tile column (row >= column)
   int32_t npad;
   int32_t it;        // iteration counter (parity selects the X buffer)
-  int32_t part_idx;  // index of this tile's residual partial
-  int32_t pad_;
+  int32_t part_idx;  // residual-partial slot of the 64-tile at the tile's top-left corner
+  int32_t tiles64;   // 64-tiles per dimension of the submatrix (partial slots: lower triangle)
 };
 
 // Workspace layout (bytes) for one chunk, given the storage element size.
@@ -82,12 +82,17 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
                         const float* pred, sm_sub_stats* stats, hipStream_t s);
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
-                           const sm_sign_opts& o, int first, sm_sub_stats* stats,
+                           const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
                            hipStream_t s);
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int grid_subs, hipStream_t s);
-constexpr int kGemmVariants = 3;   // 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2
+                         TileRec* recs_ref, int tshift_main, int tshift_ref, int grid_subs,
+                         hipStream_t s);
+// 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2, 3: XCD-aware 128 x 128 tiles
+constexpr int kGemmVariants = 4;
+// output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
+// exist for the float32-accumulating precisions and need n_pad % 64 == 0
+__host__ __device__ inline int tile_shift(int variant, int mode) { return (variant == 3 && mode != SM_F64) ? 7 : 6; }
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, const int32_t* count,
                           const TileRec* recs, double* partials, int grid, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);

@@ -46,7 +46,7 @@ class SignOpts(C.Structure):
                 ("max_iter", C.c_int32), ("tol", C.c_double), ("switch_tol", C.c_double),
                 ("stall_below", C.c_double), ("stall_ratio", C.c_double), ("scaling", C.c_int32),
                 ("power_steps", C.c_int32), ("scale_margin", C.c_double), ("probes", C.c_int32),
-                ("variant", C.c_int32)]
+                ("variant", C.c_int32), ("graph_iters", C.c_int32), ("reserved", C.c_int32)]
 
     def copy(self) -> "SignOpts":
         o = SignOpts()
@@ -68,7 +68,7 @@ STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"
 STATS_FEAT_OFFSET = 56   # bytes from the start of a record to feat[0]
 assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 120
 assert STATS_DTYPE.fields["feat"][1] == STATS_FEAT_OFFSET
-assert C.sizeof(SignOpts) == 72
+assert C.sizeof(SignOpts) == 80
 
 _lib = None
 
@@ -336,7 +336,7 @@ def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):
     _check(lib().sm_plan_set_mlp(plan.handle, None if mlp is None else mlp.handle))
 
 
-N_VARIANTS = 3
+N_VARIANTS = 4
 
 
 def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, repeats: int = 2,
