@@ -43,6 +43,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3"],
+                    help="cfg2: the metric's workload (default); cfg3: the precision form, 1000 "
+                         "water-like molecules, errors against the oracle on sampled submatrices")
+    ap.add_argument("--graph", type=int, default=0, help="iterations per captured HIP graph (0: eager)")
+    ap.add_argument("--scaling", default="gershgorin", choices=["gershgorin", "power"])
+    ap.add_argument("--chunk-gb", type=float, default=48.0, help="workspace matrix budget per chunk (cfg3)")
+    ap.add_argument("--samples", type=int, default=6, help="oracle-checked submatrices (cfg3)")
     return ap.parse_args()
 
 
@@ -65,6 +72,100 @@ def cpu_baseline(m, mu, target_s):
                       f"{m.n_atoms} submatrices at the benchmark's mu ({dt:.1f} s)"}
 
 
+def precision_form(a):
+    """1000 water-like molecules (N = 23000, 3000 submatrices of n ~ 2300-2900),
+    chunked workspace; each schedule timed for one full evaluation at fixed mu,
+    its error measured against the float64 oracle on sampled submatrices (their
+    P columns and their share of tr(PH))."""
+    import torch
+    import synth
+    from oracle import submatrix as om
+    from paper_2205_14741_amd import smsign as sm
+    from paper_2205_14741_amd import metrics
+    dev = torch.device("cuda:0")
+    m = synth.config3(a.seed)
+    H = torch.from_numpy(m.vals).to(dev)
+    budget = int(a.chunk_gb * 2 ** 30 / 4)
+    plan = sm.Plan(m, 64, budget)
+    info = plan.info()
+    n, npad = info["n"], info["npad"]
+    rng = np.random.default_rng(a.seed)
+    atoms = sorted(rng.choice(m.n_atoms, size=a.samples, replace=False).tolist())
+    # mu inside the gap of this generator's water systems (occupied states end
+    # near -4.2, empty ones start near -1.7); checked on the sampled spectra
+    mu = -2.95
+    print(f"# cfg3: N {m.n_orb}, {m.n_atoms} submatrices n {n.min()}-{n.max()}, {plan.n_chunks} chunks; "
+          f"oracle on {len(atoms)} sampled submatrices ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    cache = om.SpectralCache(m, atoms=atoms)
+    gap_lo = float(cache.lam[cache.lam < mu].max())
+    gap_hi = float(cache.lam[cache.lam > mu].min())
+    Po = om.density_matrix(m, mu, atoms=atoms)
+    t_or = time.perf_counter() - t0
+    print(f"# oracle done in {t_or:.1f} s; sampled spectra leave ({gap_lo:.3f}, {gap_hi:.3f}) around mu",
+          file=sys.stderr, flush=True)
+    mask = ~np.isnan(Po)
+    sel = np.zeros_like(mask)
+    for i in atoms:
+        sel[m.panel_off[i]:m.panel_off[i + 1]] = True
+    E_or = float(np.sum(Po[sel] * m.vals[sel]))
+    res = {}
+    for mode in [x for x in a.modes.split(",") if x and x != "f64"]:
+        o = sm.default_opts(MODES[mode], graph_iters=a.graph)
+        if a.scaling == "power":
+            o.scaling, o.power_steps = sm.SM_SCALE_POWER, 8
+        work = sm.Workspace(plan, sm.storage_prec(o), dev)
+        print(f"# {mode}: autotuning on chunk 0 ...", file=sys.stderr, flush=True)
+        best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4))
+        print(f"# {mode}: variant {best}; timing one evaluation ...", file=sys.stderr, flush=True)
+        sm.sm_profile_read(plan)
+        sm.sm_profile_enable(plan, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E, Ne = sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sm.sm_profile_enable(plan, False)
+        launches, ms = sm.sm_profile_read(plan)
+        st = work.stats_host()
+        fl = metrics.flops_by_class(st, n, npad, o)
+        useful = sum(v[0] for v in fl.values())
+        P = work.P.cpu().numpy()
+        dP = float(np.max(np.abs(P[mask] - Po[mask])))
+        dEs = abs(float(np.sum(P[sel] * m.vals[sel])) - E_or) / abs(E_or)
+        cls = int(np.argmax(ms))
+        key = (cls // 2, cls % 2)
+        r = {"s_per_eval": dt, "submatrices_per_s": m.n_atoms / dt, "useful_tflops": useful / dt / 1e12,
+             "gemm_variant": int(best), "autotune_sign_ms": [float(x) for x in tune_ms],
+             "iters": [int(st["iters"].min()), int(st["iters"].max())], "iters_mean": float(st["iters"].mean()),
+             "max_dP_sampled": dP, "rel_dE_sampled": dEs, "E": E, "Ne": Ne,
+             "status_ok": bool(np.all(st["status"] >= 1)),
+             "kernel": {"name": f"ns_gemm<{DT_NAME[key[0]]},{'square' if key[1] == 0 else 'update'}>",
+                        "launches": int(launches[cls]), "avg_ms": float(ms[cls] / max(launches[cls], 1)),
+                        "achieved_tflops": fl.get(key, (0.0, 0.0))[0] / max(ms[cls] * 1e-3, 1e-12) / 1e12,
+                        "gemm_ms_total": float(ms.sum()), "peak_tflops": metrics.PEAK_TFLOPS[key[0]]}}
+        res[mode] = r
+        print(f"# {mode}: {dt:.2f} s/eval, {r['submatrices_per_s']:.0f} subm/s, {r['useful_tflops']:.1f} TF/s useful, "
+              f"iters {r['iters']}, max|dP| (sampled) {dP:.2e}, rel dE (sampled) {dEs:.2e}, variant {best} "
+              f"(tune ms {' / '.join(f'{x:.0f}' for x in tune_ms)}), {r['kernel']['name']} "
+              f"{r['kernel']['achieved_tflops']:.1f} TF/s", file=sys.stderr, flush=True)
+        del work
+    ok = [k for k in res if res[k]["max_dP_sampled"] <= 1e-4 and res[k]["rel_dE_sampled"] <= 1e-5
+          and res[k]["status_ok"]]
+    head = max(ok, key=lambda k: res[k]["submatrices_per_s"]) if ok else next(iter(res))
+    out = {"metric": "submatrix-sign TFLOP/s & submatrices/s vs FP64 plain at 1e-5 rel energy",
+           "value": res[head]["submatrices_per_s"], "unit": "submatrices/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": res[head]["s_per_eval"] * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if head != "f32" else ""),
+           "config": {"workload": "water1000: 1000 water-like molecules (O 13, H 5 orbitals, N=23000), "
+                                  "cutoff 3.0, 3000 submatrices n=%d..%d, fixed mu" % (n.min(), n.max()),
+                      "mode": head, "seed": a.seed, "chunks": plan.n_chunks},
+           "useful_tflops": res[head]["useful_tflops"], "modes": res,
+           "oracle_sample": {"atoms": atoms, "seconds": t_or, "gap_around_mu": [gap_lo, gap_hi], "mu": mu}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -72,6 +173,8 @@ def main():
         print("bench.py: this build runs on one GPU only (the submatrix path shards by atom "
               "domains; the multi-GPU exchange is not built). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if a.config == "cfg3":
+        return precision_form(a)
     import torch
     import synth
     from paper_2205_14741_amd import smsign as sm
@@ -90,7 +193,9 @@ def main():
     res = {}
     ref_P = ref_E = None
     for mode in modes:
-        o = sm.default_opts(MODES[mode])
+        o = sm.default_opts(MODES[mode], graph_iters=a.graph)
+        if a.scaling == "power":
+            o.scaling, o.power_steps = sm.SM_SCALE_POWER, 8
         plan = plans[32 if mode in ("f64", "f32") else 64]
         info = plan.info()
         n, npad = info["n"], info["npad"]

@@ -95,7 +95,9 @@ typedef struct {
                             list (a submatrix stays in one L2), 2 = as 1 with operands
                             prefetched two stages ahead, 3 = as 1 with 128 x 128 output
                             tiles (float32-accumulating precisions, plans padded to 64 or
-                            128; otherwise runs as 1) */
+                            128; otherwise runs as 1), 4 = 128 x 128 tiles walked in list
+                            order (all XCDs on the same submatrices: their operands stay in
+                            the shared last-level cache) */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,
                             scheduler, updates) into one HIP graph, cached per plan / chunk /
@@ -273,14 +275,15 @@ int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
 /* Autotuner: for every GEMM kernel variant, one build + submatrix_sign pass
  * over `chunk` at fixed mu (the sign phase timed with HIP events, best of
  * `repeats`), then records the fastest variant as the plan's choice for the
- * precisions of `opts` (used when opts->variant == -1).
+ * precisions of `opts` (used when opts->variant == -1).  variant_mask: bit v
+ * set = try variant v (0 = all).
  *   best_out   host int32 (may be NULL): the chosen variant
- *   times_ms   host double[4] (may be NULL): sign time of each variant (-1: not
+ *   times_ms   host double[5] (may be NULL): sign time of each variant (-1: not
  *              applicable to this plan / precision)
  * Synchronous.  Leaves the workspace holding the last variant's result. */
 int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
                 const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, int32_t repeats,
-                int32_t* best_out, double* times_ms, void* stream);
+                int32_t variant_mask, int32_t* best_out, double* times_ms, void* stream);
 /* Tuned variant per precision (int32[5], indexed by sm_prec): `get` receives
  * the table, `set` (if not NULL) replaces it -- to persist the autotuner's
  * choices across processes.  Either pointer may be NULL. */

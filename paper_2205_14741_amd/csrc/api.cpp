@@ -77,7 +77,7 @@ int chunk_tiles(const sm_plan* p, int g0, int nsub) {
 // float32-accumulating precision, otherwise the XCD-aware 64-wide kernel.
 int effective_variant(const sm_plan* p, int mode, int variant) {
   int v = variant >= 0 ? variant : p->tuned[mode];
-  if (v == 3 && (mode == SM_F64 || p->pad_to < 64)) v = 1;
+  if (v >= 3 && (mode == SM_F64 || p->pad_to < 64)) v = 1;
   return v;
 }
 
@@ -405,7 +405,8 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
 }
 
 int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_sign_opts* o, void* ws,
-                sm_sub_stats* stats, int32_t repeats, int32_t* best_out, double* times_ms, void* stream) {
+                sm_sub_stats* stats, int32_t repeats, int32_t variant_mask, int32_t* best_out,
+                double* times_ms, void* stream) {
   int rc = check_opts(o);
   if (rc) return rc;
   if (!p || !H || !ws || !stats) return set_error(SM_ERR_ARG, "sm_autotune: null argument");
@@ -416,12 +417,13 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
   SM_HIP(hipEventCreate(&e0));
   SM_HIP(hipEventCreate(&e1));
   double best_t = 1e300;
-  int best = 0;
+  int best = -1;
   for (int v = 0; v < kGemmVariants; ++v) {
     sm_sign_opts ov = *o;
     ov.variant = v;
     double tv = 1e300;
-    if (v == 3 && effective_variant(p, o->phase1, 3) != 3) {   // no 128-wide kernel here
+    if ((variant_mask && !(variant_mask & (1 << v))) ||
+        (v >= 3 && effective_variant(p, o->phase1, v) != v)) {   // not requested / no 128-wide kernel
       if (times_ms) times_ms[v] = -1.0;
       continue;
     }
@@ -445,6 +447,7 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
+  if (best < 0) return set_error(SM_ERR_ARG, "sm_autotune: no variant selected by the mask");
   p->tuned[o->phase1] = best;
   if (o->refine_steps > 0) p->tuned[o->refine] = best;
   if (best_out) *best_out = best;

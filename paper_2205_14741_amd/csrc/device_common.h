@@ -48,11 +48,10 @@ __device__ __forceinline__ double block_reduce(double v, double* red) {
   return r;
 }
 
-// float -> bfloat16 bits, round to nearest even (finite inputs).
+// float -> bfloat16 bits, round to nearest even: a plain conversion, which
+// gfx950 executes as v_cvt_pk_bf16_f32.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
-  uint32_t u = __builtin_bit_cast(uint32_t, x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __builtin_bit_cast(float, (uint32_t)b << 16);

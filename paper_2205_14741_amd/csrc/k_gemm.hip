@@ -402,7 +402,7 @@ template <> struct Traits128<SM_BF16> { using S = float; using L = uint16_t; sta
 template <> struct Traits128<SM_F16> { using S = float; using L = _Float16; static constexpr int K = 32, KP = 8; };
 template <> struct Traits128<SM_BF16X3> { using S = float; using L = uint16_t; static constexpr int K = 32, KP = 8; };
 
-template <int MODE, int WHICH>
+template <int MODE, int WHICH, bool XCD>
 __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ mats,
                                                             const int32_t* __restrict__ count,
                                                             const TileRec* __restrict__ recs,
@@ -425,10 +425,13 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
   const int lrow = tid >> 1;             // 0..127
   const int lpart = (tid & 1) * NL;
   const int total = count[0];
-  const int x8 = blockIdx.x % kXcds;
-  const int t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
-  const int t_begin = (int)((int64_t)total * x8 / kXcds) + (int)blockIdx.x / kXcds;
-  const int t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
+  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x;
+  if (XCD) {
+    const int x8 = blockIdx.x % kXcds;
+    t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
+    t_begin = (int)((int64_t)total * x8 / kXcds) + (int)blockIdx.x / kXcds;
+    t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
+  }
   TileRec nxt;
   if (t_begin < t_end) nxt = recs[t_begin];
   for (int t = t_begin; t < t_end; t += t_step) {
@@ -642,9 +645,14 @@ static hipError_t launch_which(int variant, void* mats, const int32_t* count, co
     case 1: return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
     case 2: return launch_one<MODE, WHICH, 2>(mats, count, recs, partials, grid, s);
     case 3:
+    case 4:
       if constexpr (MODE != SM_F64) {
-        hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH>), dim3(grid), dim3(kBlock), 0, s, (float*)mats,
-                           count, recs, partials);
+        if (variant == 3)
+          hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH, true>), dim3(grid), dim3(kBlock), 0, s,
+                             (float*)mats, count, recs, partials);
+        else
+          hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH, false>), dim3(grid), dim3(kBlock), 0, s,
+                             (float*)mats, count, recs, partials);
         return hipGetLastError();
       } else {
         return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
@@ -678,7 +686,10 @@ static void* ptr_which(int variant) {
     case 1: return kernel_ptr<MODE, WHICH, 1>();
     case 2: return kernel_ptr<MODE, WHICH, 2>();
     case 3:
-      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH>);
+      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true>);
+      else return kernel_ptr<MODE, WHICH, 1>();
+    case 4:
+      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, false>);
       else return kernel_ptr<MODE, WHICH, 1>();
     default: return kernel_ptr<MODE, WHICH, 0>();
   }

@@ -88,11 +88,12 @@ hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
                          TileRec* recs_ref, int tshift_main, int tshift_ref, int grid_subs,
                          hipStream_t s);
-// 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2, 3: XCD-aware 128 x 128 tiles
-constexpr int kGemmVariants = 4;
+// 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2, 3: XCD-aware 128 x 128 tiles,
+// 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices)
+constexpr int kGemmVariants = 5;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
 // exist for the float32-accumulating precisions and need n_pad % 64 == 0
-__host__ __device__ inline int tile_shift(int variant, int mode) { return (variant == 3 && mode != SM_F64) ? 7 : 6; }
+__host__ __device__ inline int tile_shift(int variant, int mode) { return (variant >= 3 && mode != SM_F64) ? 7 : 6; }
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, const int32_t* count,
                           const TileRec* recs, double* partials, int grid, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);

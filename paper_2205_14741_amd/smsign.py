@@ -108,7 +108,7 @@ def lib() -> C.CDLL:
         "sm_mlp_loss_grad": (i32, [vp, vp, i64, vp, i64, vp, vp, vp]),
         "sm_mlp_train": (i32, [vp, vp, i64, vp, i64, i32, i32, C.c_float, i32, C.c_uint64, vp, vp]),
         "sm_plan_set_mlp": (i32, [vp, vp]),
-        "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, vp, vp, vp]),
+        "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, i32, vp, vp, vp]),
         "sm_plan_tuning": (i32, [vp, vp, vp]),
         "sm_last_error": (C.c_char_p, []),
         "sm_version": (C.c_char_p, []),
@@ -336,16 +336,18 @@ def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):
     _check(lib().sm_plan_set_mlp(plan.handle, None if mlp is None else mlp.handle))
 
 
-N_VARIANTS = 4
+N_VARIANTS = 5
 
 
 def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, repeats: int = 2,
-                stream=None):
+                variants=None, stream=None):
     """(best variant, sign-phase ms per variant) -- the plan keeps the choice."""
     best = C.c_int32()
     t = np.zeros(N_VARIANTS)
+    mask = 0 if variants is None else sum(1 << v for v in variants)
     _check(lib().sm_autotune(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts), _ptr(ws),
-                             _ptr(stats), int(repeats), C.byref(best), t.ctypes.data, _stream(stream)))
+                             _ptr(stats), int(repeats), int(mask), C.byref(best), t.ctypes.data,
+                             _stream(stream)))
     return best.value, t
 
 
