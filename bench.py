@@ -49,7 +49,12 @@ def parse():
     ap.add_argument("--graph", type=int, default=0, help="iterations per captured HIP graph (0: eager)")
     ap.add_argument("--scaling", default="gershgorin", choices=["gershgorin", "power"])
     ap.add_argument("--chunk-gb", type=float, default=48.0, help="workspace matrix budget per chunk (cfg3)")
+    ap.add_argument("--chunk-mb", type=float, default=0.0,
+                    help="float32 matrix budget per chunk in MiB (cfg2; 0: one chunk)")
     ap.add_argument("--samples", type=int, default=6, help="oracle-checked submatrices (cfg3)")
+    ap.add_argument("--copy-calibrate", type=float, default=0.0, metavar="MIB",
+                    help="first run a plain copy kernel (negation of a float32 buffer of MIB MiB), "
+                         "the reference for scaling memory-traffic counters")
     return ap.parse_args()
 
 
@@ -140,9 +145,10 @@ def precision_form(a):
              "iters": [int(st["iters"].min()), int(st["iters"].max())], "iters_mean": float(st["iters"].mean()),
              "max_dP_sampled": dP, "rel_dE_sampled": dEs, "E": E, "Ne": Ne,
              "status_ok": bool(np.all(st["status"] >= 1)),
-             "kernel": {"name": f"ns_gemm<{DT_NAME[key[0]]},{'square' if key[1] == 0 else 'update'}>",
+             "kernel": {"name": metrics.gemm_kernel_symbol(key[0], key[1], int(sm.sm_plan_tuning(plan)[key[0]]), 64),
                         "launches": int(launches[cls]), "avg_ms": float(ms[cls] / max(launches[cls], 1)),
-                        "achieved_tflops": fl.get(key, (0.0, 0.0))[0] / max(ms[cls] * 1e-3, 1e-12) / 1e12,
+                        "achieved_tflops": fl.get(key, (0.0, 0.0))[0] * metrics.MFMA_PRODUCTS[key[0]]
+                        / max(ms[cls] * 1e-3, 1e-12) / 1e12,
                         "gemm_ms_total": float(ms.sum()), "peak_tflops": metrics.PEAK_TFLOPS[key[0]]}}
         res[mode] = r
         print(f"# {mode}: {dt:.2f} s/eval, {r['submatrices_per_s']:.0f} subm/s, {r['useful_tflops']:.1f} TF/s useful, "
@@ -181,9 +187,18 @@ def main():
     from paper_2205_14741_amd import metrics
 
     dev = torch.device("cuda:0")
+    if a.copy_calibrate > 0:
+        src = torch.ones(int(a.copy_calibrate * 2 ** 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(f"# copy kernel: {src.numel() * 4} bytes", file=sys.stderr, flush=True)
+        del src, dst
     m = synth.config2(a.seed)
     # float64 / float32 schedules pad submatrices to 32, the bf16-family ones to 64
-    plans = {32: sm.Plan(m, 32), 64: sm.Plan(m, 64)}
+    budget = int(a.chunk_mb * 2 ** 20 / 4)
+    plans = {32: sm.Plan(m, 32, budget), 64: sm.Plan(m, 64, budget)}
     H = torch.from_numpy(m.vals).to(dev)
     torch.cuda.synchronize()
 
@@ -242,12 +257,19 @@ def main():
             key = (cls // 2, cls % 2)
             fu, fi = fl.get(key, (0.0, 0.0))
             passes = k * a.steps
-            avg_ms = ms[cls] / max(launches[cls], 1)
-            per_launch = fu * passes / max(launches[cls], 1)
-            r["kernel"] = {"name": f"ns_gemm_kernel<{DT_NAME[key[0]]},{'square' if key[1] == 0 else 'update'}>",
+            nl = max(int(launches[cls]), 1)
+            avg_ms = ms[cls] / nl
+            # algorithmic matrix-core flops: useful product flops times the
+            # products the precision's form needs (3 for split bfloat16)
+            per_launch = fu * metrics.MFMA_PRODUCTS[key[0]] * passes / nl
+            variant = int(sm.sm_plan_tuning(plan)[key[0]])
+            sym = metrics.gemm_kernel_symbol(key[0], key[1], variant, r["pad_to"])
+            r["kernel"] = {"name": sym, "precision": DT_NAME[key[0]],
+                           "product": "square" if key[1] == 0 else "update",
                            "launches": int(launches[cls]), "avg_ms": avg_ms,
-                           "useful_flops_per_launch": per_launch,
-                           "issued_flops_per_launch": fi * passes / max(launches[cls], 1),
+                           "algorithmic_flops_per_launch": per_launch,
+                           "useful_flops_per_launch": fu * passes / nl,
+                           "issued_flops_per_launch": fi * metrics.MFMA_PRODUCTS[key[0]] * passes / nl,
                            "achieved_tflops": per_launch / (avg_ms * 1e-3) / 1e12,
                            "gemm_ms_total_per_step": float(ms.sum()) / a.steps,
                            "peak_tflops": metrics.PEAK_TFLOPS[key[0]]}
@@ -290,9 +312,13 @@ def main():
     }
     if "kernel" in h:
         kk = h["kernel"]
+        from paper_2205_14741_amd import profsum
+        traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", "ns_gemm_traffic_lattice1000.txt"),
+                                       kk["name"])
         out["roofline"] = {"bound": "mfma", "achieved": kk["achieved_tflops"], "peak": kk["peak_tflops"],
                            "unit": "TFLOP/s", "frac": kk["achieved_tflops"] / kk["peak_tflops"],
-                           "traffic": None, "kernel": kk["name"]}
+                           "traffic": traffic, "kernel": kk["name"], "avg_launch_ms": kk["avg_ms"],
+                           "flops_per_launch": kk["algorithmic_flops_per_launch"]}
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(m, res["f64"]["mu"], a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -53,8 +53,8 @@ struct WsPtrs {
   int32_t* flag;
 };
 
-WsPtrs ws_ptrs(const sm_plan* p, void* ws, int f64) {
-  const WsLayout L = p->layout(f64);
+WsPtrs ws_ptrs(const sm_plan* p, void* ws, int storage) {
+  const WsLayout L = p->layout(storage);
   char* w = static_cast<char*>(ws);
   return WsPtrs{w + L.mats, (TileRec*)(w + L.tiles), (SubState*)(w + L.state), (double*)(w + L.partials), (int32_t*)(w + L.lists),
                 (float*)(w + L.features), (double*)(w + L.scratch), (double*)(w + L.vecs),
@@ -81,7 +81,8 @@ int effective_variant(const sm_plan* p, int mode, int variant) {
   return v;
 }
 
-int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, const int32_t* cnt,
+int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_t shadow, int shadow_kind,
+                const int32_t* cnt,
                 const TileRec* recs, double* partials, int max_tiles, hipStream_t s) {
   const int v = effective_variant(p, mode, variant);
   // persistent grid: all resident workgroups, a multiple of the 8 XCDs
@@ -97,7 +98,7 @@ int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, const 
     }
     SM_HIP(hipEventRecord(p->prof_ev[2 * k], s));
   }
-  SM_HIP(launch_ns_gemm(mode, which, v, mats, cnt, recs, partials, grid, s));
+  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, shadow_kind, cnt, recs, partials, grid, s));
   if (p->profiling) {
     SM_HIP(hipEventRecord(p->prof_ev[2 * k + 1], s));
     p->prof_cls.push_back(2 * mode + which);
@@ -135,9 +136,8 @@ int sm_profile_read(sm_plan* p, int64_t* launches, double* ms) {
 
 int sm_plan_ws_layout(const sm_plan* p, int32_t storage_prec, int64_t* regions9, int64_t* mat_off_g) {
   if (!p) return set_error(SM_ERR_ARG, "sm_plan_ws_layout: null plan");
-  if (storage_prec != SM_F64 && storage_prec != SM_F32)
-    return set_error(SM_ERR_ARG, "sm_plan_ws_layout: storage must be SM_F64 or SM_F32");
-  const WsLayout L = p->layout(storage_prec == SM_F64);
+  if (!valid_storage(storage_prec)) return set_error(SM_ERR_ARG, "sm_plan_ws_layout: bad storage code %d", storage_prec);
+  const WsLayout L = p->layout(storage_prec);
   if (regions9) {
     const int64_t r[9] = {L.mats, L.state, L.partials, L.lists, L.features, L.scratch, L.vecs, L.flag, L.total};
     std::memcpy(regions9, r, sizeof(r));
@@ -158,8 +158,10 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   const size_t lds = (size_t)(2 * p->max_m + p->max_npad) * sizeof(int);
   if (lds > 64 * 1024)
     return set_error(SM_ERR_ARG, "build_submatrices: index set too large for the gather (needs %zu B of LDS)", lds);
-  const int f64 = storage_is_f64(o);
-  WsPtrs w = ws_ptrs(p, ws, f64);
+  const int storage = ws_storage(o);
+  const int f64 = storage == SM_F64;
+  const int64_t shadow = storage >= SM_BF16 ? p->shadow_off() : 0;
+  WsPtrs w = ws_ptrs(p, ws, storage);
   hipStream_t s = as_stream(stream);
   SM_HIP(launch_fill_i32(w.flag, 0, 1, s));
   SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, w.flag, s));
@@ -174,10 +176,10 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
     predp = pred;
   }
   SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
-                      cg, predp, stats, s));
+                      cg, predp, stats, storage >= SM_BF16 ? storage : 0, shadow, s));
   SM_HIP(hipMemcpyAsync(&p->h_pinned[8], w.flag, 4, hipMemcpyDeviceToHost, s));
   SM_HIP(hipStreamSynchronize(s));
-  p->last_f64 = f64;
+  p->last_storage = storage;
   if (p->h_pinned[8] != 0)
     return set_error(SM_ERR_NONFINITE, "build_submatrices: NaN/Inf in submatrix of atom %d", p->h_pinned[8] - 1);
   return SM_OK;
@@ -191,12 +193,14 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   int g0, nsub;
   if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
   if ((rc = ensure_device(p))) return rc;
-  const int f64 = storage_is_f64(o);
+  const int storage = ws_storage(o);
+  const int f64 = storage == SM_F64;
+  const int64_t shadow = storage >= SM_BF16 ? p->shadow_off() : 0;
   if (o->phase1 >= SM_BF16 && p->pad_to < 64)
     return set_error(SM_ERR_ARG, "submatrix_sign: bf16 / f16 / split-bf16 phases need a plan padded to 64 or 128");
-  if (p->last_f64 != f64)
+  if (p->last_storage != storage)
     return set_error(SM_ERR_STATE, "submatrix_sign: the workspace was not built for this precision schedule");
-  WsPtrs w = ws_ptrs(p, ws, f64);
+  WsPtrs w = ws_ptrs(p, ws, storage);
   hipStream_t s = as_stream(stream);   // the lambdas below launch on `s`
   const int64_t stride = list_stride(p);
   int32_t* L0 = w.lists;
@@ -211,15 +215,19 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   const int tsh_main = tile_shift(effective_variant(p, mode_main, o->variant), mode_main);
   const int tsh_ref = tile_shift(effective_variant(p, mode_ref, o->variant), mode_ref);
   // expand lists (Lm, Lr) into tile records, then run the GEMMs of kind `which`
+  // the main phase's products keep only 16-bit copies of their results, so
+  // a submatrix's first refinement update reads those (tile flag)
+  const int shadow_kind = storage >= SM_BF16 ? storage : 0;
   auto phase = [&](int Lm, int Lr, int which) -> int {
+    const int first_ref = (which == 1 && shadow_kind) ? o->refine_steps - 1 : -1;
     SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, Lm, Lr, rec_main, has_ref ? rec_ref : nullptr,
-                         tsh_main, tsh_ref, nsub, s));
+                         tsh_main, tsh_ref, first_ref, nsub, s));
     int r;
-    if ((r = gemm_launch(p, mode_main, which, o->variant, w.mats, list_count(Lm), rec_main, w.partials,
-                         max_tiles, s)))
+    if ((r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, 0, list_count(Lm), rec_main,
+                         w.partials, max_tiles, s)))
       return r;
-    if (has_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, list_count(Lr), rec_ref,
-                                    w.partials, max_tiles, s)))
+    if (has_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, shadow_kind,
+                                    list_count(Lr), rec_ref, w.partials, max_tiles, s)))
       return r;
     return SM_OK;
   };
@@ -293,6 +301,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       }
     }
   }
+  if (shadow_kind)   // final X of submatrices that ended in the main phase
+    SM_HIP(launch_materialize(p->dev, g0, nsub, (float*)w.mats, w.st, shadow_kind, shadow, s));
   SM_HIP(launch_finish(p->dev, g0, nsub, w.mats, f64, w.st, o->probes, w.vecs, stats, s));
   return SM_OK;
 }
@@ -302,9 +312,10 @@ int assemble_P(const sm_plan* p, int32_t chunk, const void* ws, double* P, void*
   int g0, nsub, rc;
   if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
   if (p->device < 0) return set_error(SM_ERR_STATE, "assemble_P: plan has not been used on a device yet");
-  const int f64 = p->last_f64;
-  if (f64 < 0) return set_error(SM_ERR_STATE, "assemble_P: no submatrices built");
-  WsPtrs w = ws_ptrs(p, const_cast<void*>(ws), f64);
+  const int storage = p->last_storage;
+  if (storage < 0) return set_error(SM_ERR_STATE, "assemble_P: no submatrices built");
+  const int f64 = storage == SM_F64;
+  WsPtrs w = ws_ptrs(p, const_cast<void*>(ws), storage);
   SM_HIP(launch_scatter(p->dev, g0, nsub, w.mats, f64, w.st, P, as_stream(stream)));
   return SM_OK;
 }
@@ -380,7 +391,7 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
       if ((rc = submatrix_sign(p, c, ws, o, stats, stream))) return rc;
       int g0, nsub;
       chunk_range(p, c, g0, nsub);
-      WsPtrs w = ws_ptrs(p, ws, storage_is_f64(o));
+      WsPtrs w = ws_ptrs(p, ws, ws_storage(o));
       SM_HIP(launch_ne_from_x(p->dev, g0, nsub, w.mats, storage_is_f64(o), w.st, p->d_ne_sub, s));
       if (P && (rc = assemble_P(p, c, ws, P, stream))) return rc;
     }

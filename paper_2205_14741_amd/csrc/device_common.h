@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/smsign.h"
+
 namespace sm {
 
 constexpr int kWave = 64;
@@ -55,6 +57,21 @@ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
+  return __builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
+// Operand copies of a float32 value for the matrix-core products (written by
+// the producer of a buffer so the products read them without converting):
+// SM_BF16 / SM_F16 keep one plane (the rounded value), SM_BF16X3 two planes,
+// hi = bf16(x) and lo = bf16(x - hi), with x - hi exact in float32.
+__device__ __forceinline__ uint16_t shadow_hi(float x, int kind) {
+  return kind == SM_F16 ? f32_to_f16_bits(x) : f32_to_bf16_bits(x);
+}
+__device__ __forceinline__ uint16_t shadow_lo(float x, uint16_t hi) {
+  return f32_to_bf16_bits(x - bf16_bits_to_f32(hi));
 }
 
 // Deterministic probe-vector entry in {-1, +1} for (probe, row).

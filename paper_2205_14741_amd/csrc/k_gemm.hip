@@ -58,6 +58,178 @@ __device__ __forceinline__ void load_col(S (&r)[NL], const S* __restrict__ p, bo
   }
 }
 
+// ---------------------------------------------------------------------------
+// Operand sources.  float64 / float32 products read the iterate's own buffer.
+// The bf16 / f16 / split-bf16 products read the 16-bit copies that the
+// producer of the buffer wrote next to it (at float offset shadow_off): one
+// plane of n_pad^2 values, or for split bf16 the hi plane followed by the lo
+// plane.  Staging them is then a plain copy into LDS, with half the bytes of
+// the float32 buffer for bf16 / f16, and no per-tile conversion work.
+// ---------------------------------------------------------------------------
+template <int MODE> struct Pre {
+  static constexpr bool value = MODE == SM_BF16 || MODE == SM_F16 || MODE == SM_BF16X3;
+};
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int MODE, bool PRE = Pre<MODE>::value> struct Operand;
+
+// NL float32 values of an operand row rebuilt from 16-bit copies of the
+// precision `kind`: the bf16 / f16 value, or hi + lo for split bf16.
+template <int NL>
+__device__ __forceinline__ void load_col_shadow(float (&r)[NL], const uint16_t* p, int64_t nn, int kind,
+                                                bool ok) {
+  static_assert(NL % 8 == 0, "vector width");
+#pragma unroll
+  for (int v = 0; v < NL / 8; ++v) {
+    u32x4 h = u32x4{0, 0, 0, 0}, l = u32x4{0, 0, 0, 0};
+    if (ok) {
+      h = *reinterpret_cast<const u32x4*>(p + 8 * v);
+      if (kind == SM_BF16X3) l = *reinterpret_cast<const u32x4*>(p + nn + 8 * v);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint16_t hb = (uint16_t)(h[e >> 1] >> (16 * (e & 1)));
+      const uint16_t lb = (uint16_t)(l[e >> 1] >> (16 * (e & 1)));
+      float x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, hb) : bf16_bits_to_f32(hb);
+      if (kind == SM_BF16X3) x += bf16_bits_to_f32(lb);
+      r[8 * v + e] = x;
+    }
+  }
+}
+
+template <int MODE> struct Operand<MODE, false> {
+  using S = typename Traits<MODE>::S;
+  const S* p;
+  const uint16_t* q;   // 16-bit copies (float32 products of a first refinement update)
+  int64_t nn;
+  int kind;            // main precision of the copies; 0: read the buffer itself
+  __device__ Operand(const S* buf, int64_t shadow_off, int64_t off, int64_t nn_, int kind_)
+      : p(buf + off),
+        q(kind_ ? reinterpret_cast<const uint16_t*>(reinterpret_cast<const float*>(buf) + shadow_off) + off
+                : nullptr),
+        nn(nn_),
+        kind(kind_) {}
+  template <int K, int NL>
+  __device__ __forceinline__ void load(S (&r)[NL], int stage, bool ok) const {
+    if constexpr (MODE == SM_F32) {
+      if (kind) {
+        load_col_shadow<NL>(r, q + (int64_t)stage * K, nn, kind, ok);
+        return;
+      }
+    }
+    load_col<S, NL>(r, p + (int64_t)stage * K, ok);
+  }
+};
+
+template <int MODE> struct Operand<MODE, true> {
+  const uint16_t* p;
+  int64_t nn;
+  __device__ Operand(const float* buf, int64_t shadow_off, int64_t off, int64_t nn_, int)
+      : p(reinterpret_cast<const uint16_t*>(buf + shadow_off) + off), nn(nn_) {}
+  // NL 16-bit values per plane (NL / 2 words), planes one after the other in r
+  template <int K, int NL, int RN>
+  __device__ __forceinline__ void load(uint32_t (&r)[RN], int stage, bool ok) const {
+    constexpr int NW = NL / 2;
+    static_assert(RN % NW == 0 && NW % 4 == 0, "operand register layout");
+#pragma unroll
+    for (int q = 0; q < RN / NW; ++q) {
+      const uint16_t* src = p + q * nn + (int64_t)stage * K;
+#pragma unroll
+      for (int v = 0; v < NW / 4; ++v) {
+        u32x4 t = u32x4{0, 0, 0, 0};
+        if (ok) t = *reinterpret_cast<const u32x4*>(src + 8 * v);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[q * NW + 4 * v + e] = t[e];
+      }
+    }
+  }
+};
+
+// registers -> LDS rows of one stage (hi / only plane to `dst`, lo to `dst_lo`)
+template <int MODE, int NL, typename RT, int RN, typename LT>
+__device__ __forceinline__ void stage_store(const RT (&r)[RN], LT* dst, LT* dst_lo) {
+  if constexpr (!Pre<MODE>::value) {
+#pragma unroll
+    for (int e = 0; e < NL; ++e) dst[e] = r[e];
+  } else {
+    constexpr int NW = NL / 2;
+#pragma unroll
+    for (int q = 0; q < RN / NW; ++q) {
+      u32x4* d = reinterpret_cast<u32x4*>(q == 0 ? dst : dst_lo);
+#pragma unroll
+      for (int v = 0; v < NW / 4; ++v)
+        d[v] = u32x4{r[q * NW + 4 * v], r[q * NW + 4 * v + 1], r[q * NW + 4 * v + 2], r[q * NW + 4 * v + 3]};
+    }
+  }
+}
+
+// Epilogue of a float32-accumulating product for one lane's four results
+// (rows rb .. rb + 3 of column cc): entries on or below the diagonal are
+// written to (r, c) and mirrored to (c, r); for the square, Y = 3I - A is
+// stored and (A - I)^2 is added to the residual partial sum.  Products of the
+// low-precision main phases store only the 16-bit copies their consumers read
+// (the float32 value is rebuilt where a refinement step or the final
+// read-out needs it); float32 products store float32.
+template <int MODE, int WHICH>
+__device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t shadow_off, int64_t nn,
+                                           int npad, int rb, int cc, double& part) {
+  constexpr bool PRE = Pre<MODE>::value;
+  float o[4];
+  uint16_t h[4], l[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int rr = rb + v;
+    const double a = (double)a4[v];
+    if (WHICH == 0) {
+      const double dg = (rr == cc) ? 1.0 : 0.0;
+      const double e = a - dg;
+      if (rr >= cc) part += (rr == cc) ? e * e : 2.0 * e * e;
+      o[v] = (float)(3.0 * dg - a);
+    } else {
+      o[v] = (float)(0.5 * a);
+    }
+    if constexpr (PRE) {
+      h[v] = shadow_hi(o[v], MODE);
+      l[v] = MODE == SM_BF16X3 ? shadow_lo(o[v], h[v]) : 0;
+    }
+  }
+  uint16_t* sh = PRE ? reinterpret_cast<uint16_t*>(Out + shadow_off) : nullptr;
+  const int64_t dcol = (int64_t)cc * npad + rb;     // (rb .. rb + 3, cc): contiguous
+  if (rb >= cc) {
+    if constexpr (PRE) {
+      typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+      *reinterpret_cast<u2*>(sh + dcol) = u2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+      if (MODE == SM_BF16X3)
+        *reinterpret_cast<u2*>(sh + nn + dcol) = u2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
+    } else {
+      *reinterpret_cast<f4*>(Out + dcol) = f4{o[0], o[1], o[2], o[3]};
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (rb + v >= cc) {
+        if constexpr (PRE) {
+          sh[dcol + v] = h[v];
+          if (MODE == SM_BF16X3) sh[nn + dcol + v] = l[v];
+        } else {
+          Out[dcol + v] = o[v];
+        }
+      }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (rb + v > cc) {
+      const int64_t m = (int64_t)(rb + v) * npad + cc;
+      if constexpr (PRE) {
+        sh[m] = h[v];
+        if (MODE == SM_BF16X3) sh[nn + m] = l[v];
+      } else {
+        Out[m] = o[v];
+      }
+    }
+}
+
 __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
   int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
   while (r * (r + 1) / 2 > lt) --r;
@@ -82,6 +254,7 @@ constexpr int kXcds = 8;
 
 template <int MODE, int WHICH, int DEPTH, bool XCD>
 __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::S* __restrict__ mats,
+                                                         int64_t shadow_off, int shadow_kind,
                                                          const int32_t* __restrict__ count,
                                                          const TileRec* __restrict__ recs,
                                                          double* __restrict__ partials) {
@@ -92,7 +265,11 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
   constexpr int LD = K + Tr::KP;
   constexpr int NL = K / 4;              // elements per thread per operand per stage
   constexpr bool SPLIT = (MODE == SM_BF16X3);
-  constexpr int NOP = SPLIT ? 4 : 2;     // A, B (+ A_lo, B_lo)
+  constexpr bool PRE = Pre<MODE>::value;
+  constexpr int NPL = SPLIT ? 2 : 1;     // operand planes (hi, lo)
+  constexpr int NOP = 2 * NPL;           // A, B (+ A_lo, B_lo)
+  using RT = typename std::conditional<PRE, uint32_t, S>::type;
+  constexpr int RN = PRE ? NPL * NL / 2 : NL;   // registers per operand per stage
   __shared__ __attribute__((aligned(16))) LT lds[2][NOP][64 * LD];
   __shared__ double red[4];
 
@@ -141,8 +318,11 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     // wave blocks past n_pad, and the block of a diagonal tile that lies
     // wholly above the diagonal, compute nothing
     const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && !(bi == bj && wm < wn);
-    const S* ga = Xp + (int64_t)(va ? r0 + lrow : 0) * npad + lpart;
-    const S* gb = Rp + (int64_t)(vb ? c0 + lrow : 0) * npad + lpart;
+    const int64_t oa = (int64_t)(va ? r0 + lrow : 0) * npad + lpart;
+    const int64_t ob = (int64_t)(vb ? c0 + lrow : 0) * npad + lpart;
+    const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
+    const Operand<MODE> opa(Xp, shadow_off, oa, nn, fk);
+    const Operand<MODE> opb(Rp, shadow_off, ob, nn, fk);
 
     typename Tr::Acc acc[2][2];
 #pragma unroll
@@ -155,48 +335,26 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     const int nst = npad / K;
     auto k_loop = [&](auto compute_tag) {
     constexpr bool COMPUTE = decltype(compute_tag)::value;
-    S rga[DEPTH][NL], rgb[DEPTH][NL];
+    RT rga[DEPTH][RN], rgb[DEPTH][RN];
 #pragma unroll
     for (int q = 0; q < DEPTH; ++q)
       if (q < nst) {
-        load_col<S, NL>(rga[q], ga + q * K, va);
-        load_col<S, NL>(rgb[q], gb + q * K, vb);
+        opa.template load<K, NL>(rga[q], q, va);
+        opb.template load<K, NL>(rgb[q], q, vb);
       }
     for (int s = 0; s < nst; ++s) {
       const int buf = s & 1;
       const int rs = DEPTH == 1 ? 0 : (s % DEPTH);
-      S (&ra)[NL] = rga[rs];
-      S (&rb)[NL] = rgb[rs];
-      // ---- registers -> LDS (with the precision conversion) ----
-      LT* sa = &lds[buf][0][lrow * LD + lpart];
-      LT* sb = &lds[buf][1][lrow * LD + lpart];
-      if constexpr (MODE == SM_F64 || MODE == SM_F32) {
-#pragma unroll
-        for (int e = 0; e < NL; ++e) { sa[e] = ra[e]; sb[e] = rb[e]; }
-      } else if constexpr (MODE == SM_F16) {
-#pragma unroll
-        for (int e = 0; e < NL; ++e) { sa[e] = (_Float16)ra[e]; sb[e] = (_Float16)rb[e]; }
-      } else if constexpr (MODE == SM_BF16) {
-#pragma unroll
-        for (int e = 0; e < NL; ++e) { sa[e] = f32_to_bf16_bits(ra[e]); sb[e] = f32_to_bf16_bits(rb[e]); }
-      } else {  // split: x = hi + lo
-        LT* sal = &lds[buf][2][lrow * LD + lpart];
-        LT* sbl = &lds[buf][3][lrow * LD + lpart];
-#pragma unroll
-        for (int e = 0; e < NL; ++e) {
-          const uint16_t ha = f32_to_bf16_bits(ra[e]);
-          const uint16_t hb = f32_to_bf16_bits(rb[e]);
-          sa[e] = ha;
-          sb[e] = hb;
-          sal[e] = f32_to_bf16_bits(ra[e] - bf16_bits_to_f32(ha));
-          sbl[e] = f32_to_bf16_bits(rb[e] - bf16_bits_to_f32(hb));
-        }
-      }
+      RT (&ra)[RN] = rga[rs];
+      RT (&rb)[RN] = rgb[rs];
+      // ---- registers -> LDS ----
+      stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
+      stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
       __syncthreads();
       // ---- prefetch stage s + DEPTH into the register set just emptied ----
       if (s + DEPTH < nst) {
-        load_col<S, NL>(ra, ga + (int64_t)(s + DEPTH) * K, va);
-        load_col<S, NL>(rb, gb + (int64_t)(s + DEPTH) * K, vb);
+        opa.template load<K, NL>(ra, s + DEPTH, va);
+        opb.template load<K, NL>(rb, s + DEPTH, vb);
       }
       // ---- MFMA on the LDS stage ----
       const int kq = lane >> 4;    // k group of this lane
@@ -305,22 +463,26 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
       for (int y = 0; y < 2; ++y) {
         const int rb = r0 + wm * 32 + x * 16;
         const int cc = c0 + wn * 32 + y * 16 + (lane & 15);
+        if constexpr (MODE == SM_F64) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = rb + (MODE == SM_F64 ? kq + 4 * v : 4 * kq + v);
-          if (rr < cc) continue;   // upper triangle: written by the mirror of (cc, rr)
-          const double a = (double)acc[x][y][v];
-          S outv;
-          if (WHICH == 0) {
-            const double dg = (rr == cc) ? 1.0 : 0.0;
-            const double e = a - dg;
-            part += (rr == cc) ? e * e : 2.0 * e * e;
-            outv = (S)(3.0 * dg - a);
-          } else {
-            outv = (S)(0.5 * a);
+          for (int v = 0; v < 4; ++v) {
+            const int rr = rb + kq + 4 * v;
+            if (rr < cc) continue;   // upper triangle: written by the mirror of (cc, rr)
+            const double a = acc[x][y][v];
+            double outv;
+            if (WHICH == 0) {
+              const double dg = (rr == cc) ? 1.0 : 0.0;
+              const double e = a - dg;
+              part += (rr == cc) ? e * e : 2.0 * e * e;
+              outv = 3.0 * dg - a;
+            } else {
+              outv = 0.5 * a;
+            }
+            Out[(int64_t)cc * npad + rr] = outv;
+            if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
           }
-          Out[(int64_t)cc * npad + rr] = outv;
-          if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
+        } else {
+          store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb + 4 * kq, cc, part);
         }
       }
     if (WHICH == 0) {
@@ -344,7 +506,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
                                                      int list_main, int list_ref,
                                                      TileRec* __restrict__ recs_main,
                                                      TileRec* __restrict__ recs_ref, int tshift_main,
-                                                     int tshift_ref) {
+                                                     int tshift_ref, int first_ref) {
   const int stride = 2 + 2 * max_subs + 1;
   const int32_t* Lb = lists + (blockIdx.y == 0 ? list_main : list_ref) * stride;
   TileRec* out = blockIdx.y == 0 ? recs_main : recs_ref;
@@ -360,6 +522,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int nt = T * (T + 1) / 2;
   const int64_t mo = p.mat_off_g[g];
   const int it = st[l].iters;
+  const int16_t flags = (blockIdx.y == 1 && first_ref >= 0 && st[l].refine_left == first_ref) ? kTileFromShadow : 0;
   const int po = p.tile_off_g[g];
   const int t64 = tiles_of(npad);
   for (int lt = threadIdx.x; lt < nt; lt += blockDim.x) {
@@ -373,18 +536,19 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
     r.npad = npad;
     r.it = it;
     r.part_idx = po + b64i * (b64i + 1) / 2 + b64j;
-    r.tiles64 = t64;
+    r.tiles64 = (int16_t)t64;
+    r.flags = flags;
     out[first + lt] = r;
   }
 }
 
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int tshift_main, int tshift_ref, int grid_subs,
+                         TileRec* recs_ref, int tshift_main, int tshift_ref, int first_ref, int grid_subs,
                          hipStream_t s) {
   if (grid_subs <= 0) return hipSuccess;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, recs_ref ? 2 : 1), dim3(256), 0, s, p, g0, st, lists,
-                     max_subs, list_main, list_ref, recs_main, recs_ref, tshift_main, tshift_ref);
+                     max_subs, list_main, list_ref, recs_main, recs_ref, tshift_main, tshift_ref, first_ref);
   return hipGetLastError();
 }
 
@@ -403,7 +567,8 @@ template <> struct Traits128<SM_F16> { using S = float; using L = _Float16; stat
 template <> struct Traits128<SM_BF16X3> { using S = float; using L = uint16_t; static constexpr int K = 32, KP = 8; };
 
 template <int MODE, int WHICH, bool XCD>
-__global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ mats,
+__global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ mats, int64_t shadow_off,
+                                                            int shadow_kind,
                                                             const int32_t* __restrict__ count,
                                                             const TileRec* __restrict__ recs,
                                                             double* __restrict__ partials) {
@@ -414,7 +579,11 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
   constexpr int LD = K + Tr::KP;
   constexpr int NL = K / 2;              // 128 rows x K per operand over 256 threads
   constexpr bool SPLIT = (MODE == SM_BF16X3);
-  constexpr int NOP = SPLIT ? 4 : 2;
+  constexpr bool PRE = Pre<MODE>::value;
+  constexpr int NPL = SPLIT ? 2 : 1;
+  constexpr int NOP = 2 * NPL;
+  using RT = typename std::conditional<PRE, uint32_t, S>::type;
+  constexpr int RN = PRE ? NPL * NL / 2 : NL;
   __shared__ __attribute__((aligned(16))) LT lds[2][NOP][128 * LD];
   __shared__ double red[4];
 
@@ -458,8 +627,9 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
     const bool va = (r0 + lrow) < npad;
     const bool vb = (c0 + lrow) < npad;
     const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && !(bi == bj && wm < wn);
-    const S* ga = Xp + (int64_t)(va ? r0 + lrow : 0) * npad + lpart;
-    const S* gb = Rp + (int64_t)(vb ? c0 + lrow : 0) * npad + lpart;
+    const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
+    const Operand<MODE> opa(Xp, shadow_off, (int64_t)(va ? r0 + lrow : 0) * npad + lpart, nn, fk);
+    const Operand<MODE> opb(Rp, shadow_off, (int64_t)(vb ? c0 + lrow : 0) * npad + lpart, nn, fk);
     const int nst = npad / K;
     const int kq = lane >> 4;
     const int rl = lane & 15;
@@ -472,39 +642,17 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
 
     auto k_loop = [&](auto compute_tag) {
       constexpr bool COMPUTE = decltype(compute_tag)::value;
-      S ra[NL], rb[NL];
-      load_col<S, NL>(ra, ga, va);
-      load_col<S, NL>(rb, gb, vb);
+      RT ra[RN], rb[RN];
+      opa.template load<K, NL>(ra, 0, va);
+      opb.template load<K, NL>(rb, 0, vb);
       for (int s = 0; s < nst; ++s) {
         const int buf = s & 1;
-        LT* sa = &lds[buf][0][lrow * LD + lpart];
-        LT* sb = &lds[buf][1][lrow * LD + lpart];
-        if constexpr (MODE == SM_F32) {
-#pragma unroll
-          for (int e = 0; e < NL; ++e) { sa[e] = ra[e]; sb[e] = rb[e]; }
-        } else if constexpr (MODE == SM_F16) {
-#pragma unroll
-          for (int e = 0; e < NL; ++e) { sa[e] = (_Float16)ra[e]; sb[e] = (_Float16)rb[e]; }
-        } else if constexpr (MODE == SM_BF16) {
-#pragma unroll
-          for (int e = 0; e < NL; ++e) { sa[e] = f32_to_bf16_bits(ra[e]); sb[e] = f32_to_bf16_bits(rb[e]); }
-        } else {
-          LT* sal = &lds[buf][2][lrow * LD + lpart];
-          LT* sbl = &lds[buf][3][lrow * LD + lpart];
-#pragma unroll
-          for (int e = 0; e < NL; ++e) {
-            const uint16_t ha = f32_to_bf16_bits(ra[e]);
-            const uint16_t hb = f32_to_bf16_bits(rb[e]);
-            sa[e] = ha;
-            sb[e] = hb;
-            sal[e] = f32_to_bf16_bits(ra[e] - bf16_bits_to_f32(ha));
-            sbl[e] = f32_to_bf16_bits(rb[e] - bf16_bits_to_f32(hb));
-          }
-        }
+        stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
+        stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
         __syncthreads();
         if (s + 1 < nst) {
-          load_col<S, NL>(ra, ga + (int64_t)(s + 1) * K, va);
-          load_col<S, NL>(rb, gb + (int64_t)(s + 1) * K, vb);
+          opa.template load<K, NL>(ra, s + 1, va);
+          opb.template load<K, NL>(rb, s + 1, vb);
         }
         if constexpr (!COMPUTE) {
         } else if constexpr (MODE == SM_F32) {
@@ -575,27 +723,9 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
 #pragma unroll
     for (int x = 0; x < (wvalid ? 4 : 0); ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int rb = r0 + wm * 64 + x * 16 + 4 * kq;
-        const int cc = c0 + wn * 64 + y * 16 + rl;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = rb + v;
-          if (rr < cc) continue;
-          const double a = (double)acc[x][y][v];
-          S outv;
-          if (WHICH == 0) {
-            const double dg = (rr == cc) ? 1.0 : 0.0;
-            const double e = a - dg;
-            part += (rr == cc) ? e * e : 2.0 * e * e;
-            outv = (S)(3.0 * dg - a);
-          } else {
-            outv = (S)(0.5 * a);
-          }
-          Out[(int64_t)cc * npad + rr] = outv;
-          if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
-        }
-      }
+      for (int y = 0; y < 4; ++y)
+        store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 64 + x * 16 + 4 * kq,
+                                c0 + wn * 64 + y * 16 + rl, part);
     if (WHICH == 0) {
       part = wave_sum(part);
       if (lane == 0) red[wid] = part;
@@ -630,52 +760,56 @@ static void* kernel_ptr() {
 }
 
 template <int MODE, int WHICH, int V>
-static hipError_t launch_one(void* mats, const int32_t* count, const TileRec* recs, double* partials,
-                             int grid, hipStream_t s) {
+static hipError_t launch_one(void* mats, int64_t so, int sk, const int32_t* count, const TileRec* recs,
+                             double* partials, int grid, hipStream_t s) {
   using S = typename Traits<MODE>::S;
   hipLaunchKernelGGL((ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::DEPTH, Var<MODE, WHICH, V>::XCD>),
-                     dim3(grid), dim3(kBlock), 0, s, (S*)mats, count, recs, partials);
+                     dim3(grid), dim3(kBlock), 0, s, (S*)mats, so, sk, count, recs, partials);
   return hipGetLastError();
 }
 
 template <int MODE, int WHICH>
-static hipError_t launch_which(int variant, void* mats, const int32_t* count, const TileRec* recs,
-                               double* partials, int grid, hipStream_t s) {
+static hipError_t launch_which(int variant, void* mats, int64_t so, int sk, const int32_t* count,
+                               const TileRec* recs, double* partials, int grid, hipStream_t s) {
   switch (variant) {
-    case 1: return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
-    case 2: return launch_one<MODE, WHICH, 2>(mats, count, recs, partials, grid, s);
+    case 1: return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, grid, s);
+    case 2: return launch_one<MODE, WHICH, 2>(mats, so, sk, count, recs, partials, grid, s);
     case 3:
     case 4:
       if constexpr (MODE != SM_F64) {
         if (variant == 3)
           hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH, true>), dim3(grid), dim3(kBlock), 0, s,
-                             (float*)mats, count, recs, partials);
+                             (float*)mats, so, sk, count, recs, partials);
         else
           hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH, false>), dim3(grid), dim3(kBlock), 0, s,
-                             (float*)mats, count, recs, partials);
+                             (float*)mats, so, sk, count, recs, partials);
         return hipGetLastError();
       } else {
-        return launch_one<MODE, WHICH, 1>(mats, count, recs, partials, grid, s);
+        return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, grid, s);
       }
-    default: return launch_one<MODE, WHICH, 0>(mats, count, recs, partials, grid, s);
+    default: return launch_one<MODE, WHICH, 0>(mats, so, sk, count, recs, partials, grid, s);
   }
 }
 
 template <int MODE>
-static hipError_t launch_mode(int which, int variant, void* mats, const int32_t* count, const TileRec* recs,
-                              double* partials, int grid, hipStream_t s) {
-  return which == 0 ? launch_which<MODE, 0>(variant, mats, count, recs, partials, grid, s)
-                    : launch_which<MODE, 1>(variant, mats, count, recs, partials, grid, s);
+static hipError_t launch_mode(int which, int variant, void* mats, int64_t so, int sk, const int32_t* count,
+                              const TileRec* recs, double* partials, int grid, hipStream_t s) {
+  return which == 0 ? launch_which<MODE, 0>(variant, mats, so, sk, count, recs, partials, grid, s)
+                    : launch_which<MODE, 1>(variant, mats, so, sk, count, recs, partials, grid, s);
 }
 
-hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, const int32_t* count,
-                          const TileRec* recs, double* partials, int grid, hipStream_t s) {
+hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t so, int sk,
+                          const int32_t* count, const TileRec* recs, double* partials, int grid,
+                          hipStream_t s) {
+  // the bf16 / f16 / split-bf16 products, and float32 ones that may read
+  // copies, need the copy region
+  if ((mode >= SM_BF16 || sk != 0) && so <= 0) return hipErrorInvalidValue;
   switch (mode) {
-    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, count, recs, partials, grid, s);
-    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, count, recs, partials, grid, s);
-    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, count, recs, partials, grid, s);
-    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, count, recs, partials, grid, s);
-    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, count, recs, partials, grid, s);
+    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, 0, 0, count, recs, partials, grid, s);
+    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, so, sk, count, recs, partials, grid, s);
+    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, so, 0, count, recs, partials, grid, s);
+    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, so, 0, count, recs, partials, grid, s);
+    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, so, 0, count, recs, partials, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -15,6 +15,33 @@ __device__ __forceinline__ const T* final_x(const DevPlan& p, int g, const T* ma
   return mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * np * np;
 }
 
+// One workgroup per submatrix whose iteration ended in a low-precision main
+// phase (no refinement step ran, status != 2): its final X exists only as the
+// 16-bit operand copies; write the float32 values that the read-out kernels
+// below use (hi + lo for split bf16).
+__global__ __launch_bounds__(256) void materialize_kernel(DevPlan p, int g0, float* __restrict__ mats,
+                                                          const SubState* __restrict__ st, int kind,
+                                                          int64_t shadow_off) {
+  const int l = blockIdx.x;
+  if (st[l].status == 2) return;
+  const int g = g0 + l;
+  const int64_t nn = (int64_t)p.npad_g[g] * p.npad_g[g];
+  float* X = mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * nn;
+  const uint16_t* h = reinterpret_cast<const uint16_t*>(X + shadow_off);
+  for (int64_t k = threadIdx.x; k < nn; k += blockDim.x) {
+    float x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, h[k]) : bf16_bits_to_f32(h[k]);
+    if (kind == SM_BF16X3) x += bf16_bits_to_f32(h[nn + k]);
+    X[k] = x;
+  }
+}
+
+hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,
+                              int shadow_kind, int64_t shadow_off, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  hipLaunchKernelGGL(materialize_kernel, dim3(nsub), dim3(256), 0, s, p, g0, mats, st, shadow_kind, shadow_off);
+  return hipGetLastError();
+}
+
 // One workgroup per submatrix: copy the per-submatrix iteration record into
 // `stats` and, with probes > 0, estimate max_v ||X (X v) - v|| / ||v|| in float64
 // for fixed +-1 vectors v (a residual of sign(T)^2 = I, Eq. 13).

@@ -4,6 +4,8 @@
 // X_0 = T_i / c_i, the starting point of the sign iteration.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_common.h"
 #include "smsign_internal.h"
 
@@ -212,7 +214,8 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     double* __restrict__ vecs,
                                                     const double* __restrict__ cg_in,
                                                     const float* __restrict__ pred,
-                                                    sm_sub_stats* __restrict__ stats) {
+                                                    sm_sub_stats* __restrict__ stats, int shadow_kind,
+                                                    int64_t shadow_off) {
   __shared__ double red[16];
   const int l = blockIdx.x;
   const int g = g0 + l;
@@ -277,6 +280,20 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     T* col = X + (int64_t)cc * npad;
     for (int d = lane; d < n; d += kWave) col[d] = (T)((double)col[d] * sc);
   }
+  if constexpr (std::is_same<T, float>::value) {
+    // operand copy of the whole padded X_0 for the low-precision products
+    if (shadow_kind) {
+      __syncthreads();
+      const int64_t nn = (int64_t)npad * npad;
+      uint16_t* hi = reinterpret_cast<uint16_t*>(X + shadow_off);
+      for (int64_t k = threadIdx.x; k < nn; k += blockDim.x) {
+        const float x = X[k];
+        const uint16_t h = shadow_hi(x, shadow_kind);
+        hi[k] = h;
+        if (shadow_kind == SM_BF16X3) hi[nn + k] = shadow_lo(x, h);
+      }
+    }
+  }
   if (threadIdx.x == 0) {
     sm_sub_stats& r = stats[i];
     r.scale = c;
@@ -299,14 +316,15 @@ hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, 
 
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
-                        const float* pred, sm_sub_stats* stats, hipStream_t s) {
+                        const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
+                        hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   if (storage_f64)
     hipLaunchKernelGGL(scale_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats, scaling,
-                       power_steps, margin, vecs, cg_in, pred, stats);
+                       power_steps, margin, vecs, cg_in, pred, stats, 0, (int64_t)0);
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
-                       power_steps, margin, vecs, cg_in, pred, stats);
+                       power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off);
   return hipGetLastError();
 }
 

@@ -33,15 +33,28 @@ int storage_is_f64(const sm_sign_opts* o) {
   return 0;
 }
 
+// Workspace storage of a schedule: SM_F64 or SM_F32 for the iterate's type,
+// or the main precision (SM_BF16 / SM_F16 / SM_BF16X3) for float32 buffers
+// each paired with the operand copy its matrix-core products read.
+int ws_storage(const sm_sign_opts* o) {
+  if (storage_is_f64(o)) return SM_F64;
+  if (o->phase1 == SM_BF16 || o->phase1 == SM_F16 || o->phase1 == SM_BF16X3) return o->phase1;
+  return SM_F32;
+}
+
+bool valid_storage(int storage) { return storage >= SM_F64 && storage <= SM_BF16X3; }
+
 static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 }  // namespace sm
 
 using namespace sm;
 
-sm::WsLayout sm_plan::layout(int storage_f64) const {
+sm::WsLayout sm_plan::layout(int storage) const {
   WsLayout L{};
-  const int64_t es = storage_f64 ? 8 : 4;
+  // float64 iterates, or float32 ones followed by a region of operand copies
+  // of the same size (2 bf16 / f16 planes or one, in a float32 slot each)
+  const int64_t es = storage == SM_F32 ? 4 : 8;
   int64_t off = 0;
   L.mats = off;
   off = align256(off + max_mats * es);
@@ -240,11 +253,11 @@ void sm_plan_destroy(sm_plan* p) {
 int sm_plan_sizes(const sm_plan* p, int32_t storage_prec, int64_t* n_sub, int64_t* n_chunks,
                   int64_t* ws_bytes, int64_t* p_nnz_vals) {
   if (!p) return set_error(SM_ERR_ARG, "sm_plan_sizes: null plan");
-  if (storage_prec != SM_F64 && storage_prec != SM_F32)
-    return set_error(SM_ERR_ARG, "sm_plan_sizes: storage precision must be SM_F64 or SM_F32");
+  if (!valid_storage(storage_prec))
+    return set_error(SM_ERR_ARG, "sm_plan_sizes: bad storage code %d", storage_prec);
   if (n_sub) *n_sub = p->n_atoms;
   if (n_chunks) *n_chunks = (int64_t)p->chunk_ptr.size() - 1;
-  if (ws_bytes) *ws_bytes = p->layout(storage_prec == SM_F64).total;
+  if (ws_bytes) *ws_bytes = p->layout(storage_prec).total;
   if (p_nnz_vals) *p_nnz_vals = p->nvals;
   return SM_OK;
 }

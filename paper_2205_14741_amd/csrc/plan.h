@@ -49,7 +49,7 @@ struct sm_plan {
   double* d_gersh = nullptr;        // [2 * n_atoms]
   int32_t* h_pinned = nullptr;      // pinned host counters [8]
   hipEvent_t ev[2] = {nullptr, nullptr};
-  int last_f64 = -1;                // storage precision of the last build (-1: none)
+  int last_storage = -1;            // workspace storage of the last build (ws_storage; -1: none)
   int32_t tuned[5] = {0, 0, 0, 0, 0};  // GEMM variant per precision (sm_autotune)
   // captured iteration graphs (sm_sign_opts.graph_iters)
   struct GraphEntry {
@@ -67,7 +67,9 @@ struct sm_plan {
   std::vector<hipEvent_t> prof_ev;  // pool, pairs (start, stop)
   std::vector<int> prof_cls;        // class of every recorded pair
 
-  sm::WsLayout layout(int storage_f64) const;
+  sm::WsLayout layout(int storage) const;
+  // float offset of a float32 buffer's pre-converted operand copy
+  int64_t shadow_off() const { return max_mats; }
 };
 
 namespace sm {
@@ -77,6 +79,8 @@ int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 int ensure_device(sm_plan* p);
 int storage_is_f64(const sm_sign_opts* o);
+int ws_storage(const sm_sign_opts* o);
+bool valid_storage(int storage);
 }  // namespace sm
 
 #define SM_HIP(expr)                                         \

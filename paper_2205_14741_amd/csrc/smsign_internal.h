@@ -54,8 +54,13 @@ struct TileRec {
   int32_t npad;
   int32_t it;        // iteration counter (parity selects the X buffer)
   int32_t part_idx;  // residual-partial slot of the 64-tile at the tile's top-left corner
-  int32_t tiles64;   // 64-tiles per dimension of the submatrix (partial slots: lower triangle)
+  int16_t tiles64;   // 64-tiles per dimension of the submatrix (partial slots: lower triangle)
+  int16_t flags;     // kTileFromShadow: operands are the 16-bit copies of the main phase
 };
+
+// First refinement update of a submatrix: its X and Y were produced by the
+// low-precision main phase, which stores only their 16-bit operand copies.
+constexpr int16_t kTileFromShadow = 1;
 
 // Workspace layout (bytes) for one chunk, given the storage element size.
 struct WsLayout {
@@ -77,25 +82,39 @@ hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_
                          int* nonfinite, hipStream_t s);
 hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                           float* features, double* cg_out, sm_sub_stats* stats, hipStream_t s);
+// shadow_kind: 0, or SM_BF16 / SM_F16 / SM_BF16X3 to also write X_0's operand
+// copy at float offset shadow_off from its float32 buffer
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
-                        const float* pred, sm_sub_stats* stats, hipStream_t s);
+                        const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
+                        hipStream_t s);
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
                            hipStream_t s);
+// first_ref >= 0: refinement-list tiles of submatrices with refine_left ==
+// first_ref (their first refinement update) get kTileFromShadow.
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int tshift_main, int tshift_ref, int grid_subs,
-                         hipStream_t s);
+                         TileRec* recs_ref, int tshift_main, int tshift_ref, int first_ref,
+                         int grid_subs, hipStream_t s);
 // 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2, 3: XCD-aware 128 x 128 tiles,
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices)
 constexpr int kGemmVariants = 5;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
 // exist for the float32-accumulating precisions and need n_pad % 64 == 0
 __host__ __device__ inline int tile_shift(int variant, int mode) { return (variant >= 3 && mode != SM_F64) ? 7 : 6; }
-hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, const int32_t* count,
-                          const TileRec* recs, double* partials, int grid, hipStream_t s);
+// shadow_off: float offset of the operand copies (bf16 / f16 / split-bf16
+// products read them and also write them for their outputs); 0 otherwise
+// shadow_kind: the main precision whose copies a float32 refinement product
+// reads for kTileFromShadow tiles (0: none)
+hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t shadow_off,
+                          int shadow_kind, const int32_t* count, const TileRec* recs,
+                          double* partials, int grid, hipStream_t s);
+// Float32 values of the final X from its 16-bit copies, for submatrices whose
+// iteration ended in a low-precision main phase (status != 2).
+hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,
+                              int shadow_kind, int64_t shadow_off, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                          const SubState* st, int probes, double* vecs, sm_sub_stats* stats,

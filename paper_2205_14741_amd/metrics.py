@@ -70,3 +70,21 @@ def wave_blocks(npad: np.ndarray) -> np.ndarray:
 
 def useful_flops(stats, n, npad, opts) -> float:
     return sum(v[0] for v in flops_by_class(stats, n, npad, opts).values())
+
+
+# Matrix-core products one product of the schedule costs: the split-bfloat16
+# form computes hi*hi + hi*lo + lo*hi, three bfloat16 products per product.
+MFMA_PRODUCTS = {0: 1, 1: 1, 2: 1, 3: 1, 4: 3}
+
+
+def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
+    """Demangled name prefix (as profilers print it) of the GEMM kernel that
+    runs for (precision, square/update, kernel variant) on a plan with the
+    given padding; mirrors the variant fallback of the launcher."""
+    v = variant
+    if v >= 3 and (mode == 0 or pad_to < 64):
+        v = 1
+    if v >= 3:
+        return f"sm::ns_gemm128_kernel<{mode}, {which}, {'true' if v == 3 else 'false'}>"
+    depth = 2 if v == 2 else 1
+    return f"sm::ns_gemm_kernel<{mode}, {which}, {depth}, {'true' if v >= 1 else 'false'}>"

@@ -1,0 +1,133 @@
+"""Short text summaries of rocprofv3 output, for keeping next to the results.
+
+    python -m paper_2205_14741_amd.profsum stats --csv RUN_kernel_stats.csv \
+        --cmd "<the profiled command>" --out SUMMARY.txt
+    python -m paper_2205_14741_amd.profsum traffic --fetch FETCH_counter_collection.csv \
+        --write WRITE_counter_collection.csv --copy-bytes B --cmd-fetch "..." \
+        --cmd-write "..." --out SUMMARY.txt
+
+`stats` lists the kernels of a kernel-trace run by total time (calls, average,
+total, share).  `traffic` averages the FETCH_SIZE and WRITE_SIZE counters (KiB
+per dispatch) of every GEMM kernel over two counter runs, and scales each by
+what the same counter reads for a plain copy kernel of known size (the
+elementwise negation of a float32 buffer of B bytes, run by the profiled
+command first): factor = B / counter bytes.  The traffic lines carry a hash
+of the GEMM sources, so a reader can tell whether the kernel has changed since.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GEMM_SOURCES = ("csrc/k_gemm.hip", "csrc/device_common.h", "csrc/smsign_internal.h")
+
+
+def gemm_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """Kernel name without its argument list: 'sm::ns_gemm_kernel<4, 0, 1, true>'."""
+    m = re.match(r"\s*(?:void\s+)?([^(]*)", name)
+    return (m.group(1) if m else name).strip()
+
+
+def stats_summary(path: str, cmd: str, top: int = 25) -> str:
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["# rocprofv3 --kernel-trace --stats", f"# command: {cmd}",
+           f"# {'kernel':64s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in rows[:top]:
+        out.append(f"  {short_name(r['Name'])[:64]:64s} {int(r['Calls']):7d} "
+                   f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                   f"{float(r['Percentage']):6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def counter_means(path: str, counter: str) -> dict:
+    """{kernel short name: (dispatches, mean counter value per dispatch)}."""
+    acc = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, cmd_f: str, cmd_w: str) -> str:
+    fe = counter_means(fetch_csv, "FETCH_SIZE")
+    wr = counter_means(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, v in fe.items() if "neg" in k]
+    copy_w = [v for k, v in wr.items() if "neg" in k]
+    if not copy_f or not copy_w:
+        raise SystemExit("no copy-kernel dispatches found in the counter runs")
+    ff = copy_bytes / (copy_f[0][1] * 1024.0)
+    fw = copy_bytes / (copy_w[0][1] * 1024.0)
+    out = ["# rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch)",
+           f"# command (FETCH_SIZE): {cmd_f}", f"# command (WRITE_SIZE): {cmd_w}",
+           f"# copy kernel: {copy_bytes:.0f} bytes read and written; it reads FETCH {copy_f[0][1]:.1f} KiB, "
+           f"WRITE {copy_w[0][1]:.1f} KiB per dispatch",
+           f"copy_fetch_factor {ff:.4f}", f"copy_write_factor {fw:.4f}",
+           f"gemm_source_sha {gemm_source_hash()}",
+           "# traffic <kernel> | dispatches | fetch_kib | write_kib | scaled_bytes_per_dispatch"]
+    for k in sorted(fe):
+        if "gemm" not in k or k not in wr:
+            continue
+        n, f = fe[k]
+        _, w = wr[k]
+        out.append(f"traffic {k} | {n} | {f:.1f} | {w:.1f} | {f * 1024 * ff + w * 1024 * fw:.0f}")
+    return "\n".join(out) + "\n"
+
+
+def read_traffic(path: str, symbol: str):
+    """Scaled HBM bytes per dispatch of `symbol` from a traffic summary, or
+    None when the summary is missing, lacks the kernel, or was taken on GEMM
+    sources other than the current ones."""
+    if not os.path.exists(path):
+        return None
+    sha, val = None, None
+    for line in open(path):
+        if line.startswith("gemm_source_sha "):
+            sha = line.split()[1]
+        elif line.startswith("traffic ") and line[8:].split(" | ")[0].strip() == symbol:
+            val = float(line.rsplit("|", 1)[1])
+    if sha != gemm_source_hash():
+        return None
+    return val
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--csv", required=True)
+    s.add_argument("--cmd", dest="command", required=True)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--cmd-fetch", required=True)
+    t.add_argument("--cmd-write", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        text = stats_summary(a.csv, a.command)
+    else:
+        text = traffic_summary(a.fetch, a.write, a.copy_bytes, a.cmd_fetch, a.cmd_write)
+    with open(a.out, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()

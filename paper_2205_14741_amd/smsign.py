@@ -152,9 +152,24 @@ def default_opts(prec="f64", **kw) -> SignOpts:
 
 
 def storage_prec(opts: SignOpts) -> int:
+    """Workspace storage code of a schedule: SM_F64 / SM_F32 for the iterate's
+    type, or the main precision (SM_BF16 / SM_F16 / SM_BF16X3) for float32
+    iterates plus the 16-bit operand copies their products read."""
     if opts.phase1 == SM_F64 or (opts.refine_steps > 0 and opts.refine == SM_F64):
         return SM_F64
+    if opts.phase1 in (SM_BF16, SM_F16, SM_BF16X3):
+        return int(opts.phase1)
     return SM_F32
+
+
+def _check_ws(plan, ws, opts: SignOpts):
+    """A workspace tensor must hold the bytes the schedule's storage needs."""
+    if hasattr(ws, "element_size"):
+        need = plan.sizes(storage_prec(opts))[2]
+        have = ws.numel() * ws.element_size()
+        if have < need:
+            raise SmError(1, f"workspace of {have} bytes, the schedule needs {need} "
+                             f"(storage code {storage_prec(opts)})")
 
 
 class Plan:
@@ -209,11 +224,13 @@ class Plan:
 # ---- the C entry points, same names ----
 
 def build_submatrices(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, stream=None):
+    _check_ws(plan, ws, opts)
     _check(lib().build_submatrices(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts),
                                    _ptr(ws), _ptr(stats), _stream(stream)))
 
 
 def submatrix_sign(plan: Plan, chunk: int, ws, opts: SignOpts, stats, stream=None):
+    _check_ws(plan, ws, opts)
     _check(lib().submatrix_sign(plan.handle, int(chunk), _ptr(ws), C.byref(opts), _ptr(stats),
                                 _stream(stream)))
 
@@ -229,6 +246,7 @@ def energy_trace(plan: Plan, H, P, stream=None):
 
 
 def sm_density_matrix(plan: Plan, H, mu: float, opts: SignOpts, ws, P, stats, stream=None):
+    _check_ws(plan, ws, opts)
     E, Ne = C.c_double(), C.c_double()
     _check(lib().sm_density_matrix(plan.handle, _ptr(H), float(mu), C.byref(opts), _ptr(ws), _ptr(P),
                                    _ptr(stats), C.byref(E), C.byref(Ne), _stream(stream)))
@@ -237,6 +255,7 @@ def sm_density_matrix(plan: Plan, H, mu: float, opts: SignOpts, ws, P, stats, st
 
 def sm_find_mu(plan: Plan, H, n_target: float, opts: SignOpts, ws, stats, P=None, accept=0.5,
                max_steps=60, stream=None):
+    _check_ws(plan, ws, opts)
     mu = C.c_double()
     steps = C.c_int32()
     mh = np.zeros(max_steps)
@@ -342,6 +361,7 @@ N_VARIANTS = 5
 def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, repeats: int = 2,
                 variants=None, stream=None):
     """(best variant, sign-phase ms per variant) -- the plan keeps the choice."""
+    _check_ws(plan, ws, opts)
     best = C.c_int32()
     t = np.zeros(N_VARIANTS)
     mask = 0 if variants is None else sum(1 << v for v in variants)

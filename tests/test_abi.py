@@ -54,6 +54,25 @@ def test_plan_matches_oracle_index_sets(make):
     reg, off = p.ws_layout(sm.SM_F64)
     assert np.all(np.diff(reg) >= 0) and reg[-1] == ws_bytes
     assert off[0] == 0 and np.all(np.diff(off) == 3 * info["npad"][:-1].astype(np.int64) ** 2)
+    # float32 iterates plus their 16-bit operand copies take 8 bytes per element slot
+    for code in (sm.SM_BF16, sm.SM_F16, sm.SM_BF16X3):
+        assert p.sizes(code)[2] == ws_bytes
+    assert p.sizes(sm.SM_F32)[2] < ws_bytes
+    with pytest.raises(sm.SmError, match="storage"):
+        p.sizes(7)
+
+
+def test_workspace_too_small_for_schedule():
+    """A float32-storage workspace is refused (before any launch) for a
+    schedule whose products read operand copies."""
+    import torch
+    m = synth.config1()
+    p = sm.Plan(m, 64)
+    ws = torch.empty(p.sizes(sm.SM_F32)[2], dtype=torch.uint8)
+    stats = torch.empty(1, dtype=torch.uint8)
+    H = torch.zeros(m.vals.shape[0], dtype=torch.float64)
+    with pytest.raises(sm.SmError, match="workspace"):
+        sm.build_submatrices(p, 0, H, 0.0, sm.default_opts("bf16x3"), ws, stats)
 
 
 def test_chunking_respects_budget():
@@ -118,6 +137,7 @@ def test_default_opts():
     assert o.phase1 == sm.SM_F64 and o.refine_steps == 0 and o.tol == 1e-10
     o = sm.default_opts("bf16x3")
     assert o.phase1 == sm.SM_BF16X3 and o.refine == sm.SM_F32 and o.refine_steps == 2
-    assert sm.storage_prec(o) == sm.SM_F32
+    assert sm.storage_prec(o) == sm.SM_BF16X3
+    assert sm.storage_prec(sm.default_opts("f32")) == sm.SM_F32
     with pytest.raises(sm.SmError):
         sm.default_opts(9)

@@ -177,13 +177,34 @@ def test_find_mu_config1(dev):
 
 
 def _read_bufs(plan, work, storage, g):
+    """X_even, X_odd, Y of processing index g as float64 (column-major, shown
+    transposed).  Low-precision main phases keep only the 16-bit copies their
+    products read (hi + lo for split bf16), in a region after the float32
+    buffers; those are decoded here."""
     reg, off = plan.ws_layout(storage)
-    dt = np.float64 if storage == sm.SM_F64 else np.float32
-    mats = work.ws.cpu().numpy()[reg[0]:reg[1]].view(dt)
-    npad = plan.info()["npad"][plan.info()["order"][g]]
+    info = plan.info()
+    npad = info["npad"][info["order"][g]]
     nn = npad * npad
-    return [mats[off[g] + b * nn: off[g] + (b + 1) * nn].reshape(npad, npad).T.astype(np.float64)
-            for b in range(3)]
+    raw = work.ws.cpu().numpy()[reg[0]:reg[1]]
+    if storage in (sm.SM_F64, sm.SM_F32):
+        mats = raw.view(np.float64 if storage == sm.SM_F64 else np.float32)
+        bufs = [mats[off[g] + b * nn: off[g] + (b + 1) * nn] for b in range(3)]
+    else:
+        np_all = info["npad"].astype(np.int64)
+        max_mats = max(int(3 * (np_all[info["chunk"] == c] ** 2).sum()) for c in range(plan.n_chunks))
+        u16 = raw[4 * max_mats:].view(np.uint16)
+        bf = lambda b: (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        bufs = []
+        for b in range(3):
+            o = 2 * (off[g] + b * nn)
+            hi = u16[o: o + nn]
+            if storage == sm.SM_F16:
+                bufs.append(hi.view(np.float16).astype(np.float64))
+            elif storage == sm.SM_BF16:
+                bufs.append(bf(hi))
+            else:
+                bufs.append(bf(hi) + bf(u16[o + nn: o + 2 * nn]))
+    return [x.reshape(npad, npad).T.astype(np.float64) for x in bufs]
 
 
 # unit roundoff of one product in each schedule (operand rounding; accumulation
@@ -228,6 +249,24 @@ def test_single_iteration_accuracy(prec, dev):
         print(f"{prec} g={g}: err/bound X1 {worst[-1][0]:.3e} Y1 {worst[-1][1]:.3e} "
               f"rel rms {rel_rms:.3e} bias/rms {bias:+.3f} max|err| {err.max():.3e}")
         assert np.all(err <= bound) and np.all(errY <= bY)
+
+
+@pytest.mark.parametrize("prec,dp_max", [("bf16x3", 1e-3), ("f16", 3e-2), ("bf16", 2e-1)])
+def test_low_precision_without_refinement(prec, dp_max, dev):
+    """With no refinement step the iteration ends in the low-precision phase
+    (stopped by the stagnation rule), whose products keep only 16-bit copies
+    of X; P is read out of the float32 values rebuilt from them."""
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=64, refine_steps=0)
+    dP, dE, dNe = _compare(m, P, E, Ne, mu)
+    print(f"{prec} without refinement: max|dP| {dP:.2e}, rel dE {dE:.2e}, iters {st['iters'].min()}-{st['iters'].max()}")
+    assert dP < dp_max
+    assert np.all(st["status"] == 1) and np.all(st["iters_low"] == st["iters"])
+    # the refinement steps restore X^2 = I but cannot undo the subspace
+    # rotation of the main phase: both schedules sit at the same error level
+    P2, E2, Ne2, st2, _ = run_fixed_mu(m, mu, prec, plan=plan)
+    assert np.max(np.abs(P2 - P)) < dp_max
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
