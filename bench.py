@@ -30,6 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MODES = {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3", "f16": "f16", "bf16": "bf16"}
+# "<mode>+L": the learned form -- scale and the lower spectral bound l_0 from
+# the scaling network (guarded), scaled Newton-Schulz in the main phase
+for _k in list(MODES):
+    MODES[_k + "+L"] = _k
 DT_NAME = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "bf16x3"}
 
 
@@ -38,7 +42,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--modes", default="f64,f32,bf16x3")
+    ap.add_argument("--modes", default="f64,f32,bf16x3,f32+L,bf16x3+L")
+    ap.add_argument("--guard-steps", type=int, default=4,
+                    help="power-iteration steps of the learned-scale guard (+L modes)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
@@ -56,6 +62,42 @@ def parse():
                     help="first run a plain copy kernel (negation of a float32 buffer of MIB MiB), "
                          "the reference for scaling memory-traffic counters")
     return ap.parse_args()
+
+
+def mode_opts(sm, mode, a):
+    """Schedule of a benchmark mode."""
+    o = sm.default_opts(MODES[mode], graph_iters=a.graph)
+    if mode.endswith("+L"):
+        o.scaling, o.power_steps, o.scale_margin, o.accel = sm.SM_SCALE_LEARNED, a.guard_steps, 0.05, 1
+    elif a.scaling == "power":
+        o.scaling, o.power_steps = sm.SM_SCALE_POWER, 8
+    return o
+
+
+def train_scaling_net(sm, synth, dev, seed):
+    """The scaling network trained on bounds the method produces for another
+    system of the same family (a different seed: other vacancies and jitter):
+    a plain float64 run with power-iteration scaling at that system's own mu
+    gives, per submatrix, rho_est (-> log rho / c_G) and lb_est (-> log l / c_G)."""
+    import torch
+    m = synth.config2(seed)
+    plan = sm.Plan(m, 32)
+    H = torch.from_numpy(m.vals).to(dev)
+    o = sm.default_opts("f64", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
+    work = sm.Workspace(plan, sm.storage_prec(o), dev)
+    sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats)
+    st = work.stats_host()
+    ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
+    X = torch.from_numpy(np.ascontiguousarray(st["feat"][ok]).astype(np.float32)).to(dev)
+    Y = torch.from_numpy(np.stack([np.log(st["rho_est"] / st["gersh"]),
+                                   np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok]
+                         .astype(np.float32)).to(dev)
+    net = sm.Mlp(seed=seed)
+    hist = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
+    print(f"# scaling network: {int(ok.sum())} samples from seed {seed}, loss {hist[0]:.3g} -> {hist[-1]:.3g}",
+          file=sys.stderr, flush=True)
+    return net, {"train_seed": seed, "samples": int(ok.sum()), "loss_first": float(hist[0]),
+                 "loss_last": float(hist[-1])}
 
 
 def cpu_baseline(m, mu, target_s):
@@ -203,15 +245,19 @@ def main():
     torch.cuda.synchronize()
 
     modes = [x for x in a.modes.split(",") if x]
-    if "f64" not in modes:
-        modes = ["f64"] + modes
+    if "f64" in modes:
+        modes.remove("f64")
+    modes = ["f64"] + modes            # the plain float64 path is the reference
+    net_info = None
+    if any(x.endswith("+L") for x in modes):
+        net, net_info = train_scaling_net(sm, synth, dev, a.seed + 1)
+        for p in plans.values():
+            sm.sm_plan_set_mlp(p, net)
     res = {}
     ref_P = ref_E = None
     for mode in modes:
-        o = sm.default_opts(MODES[mode], graph_iters=a.graph)
-        if a.scaling == "power":
-            o.scaling, o.power_steps = sm.SM_SCALE_POWER, 8
-        plan = plans[32 if mode in ("f64", "f32") else 64]
+        o = mode_opts(sm, mode, a)
+        plan = plans[32 if MODES[mode] in ("f64", "f32") else 64]
         info = plan.info()
         n, npad = info["n"], info["npad"]
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
@@ -243,7 +289,9 @@ def main():
         fl = metrics.flops_by_class(st, n, npad, o)
         useful = sum(v[0] for v in fl.values())
         P = work.P.cpu().numpy()
-        r = {"ms_per_step": dt / a.steps * 1e3, "pad_to": 32 if mode in ("f64", "f32") else 64, "mu": mu, "bisection_passes": k, "E": E, "Ne": Ne,
+        r = {"ms_per_step": dt / a.steps * 1e3, "pad_to": 32 if MODES[mode] in ("f64", "f32") else 64, "mu": mu,
+             "bisection_passes": k, "E": E, "Ne": Ne, "scaling": int(o.scaling), "accel": int(o.accel),
+             "learned_accepted": float(np.mean(st["scale_src"] == 2)) if o.scaling == sm.SM_SCALE_LEARNED else None,
              "iters": [int(st["iters"].min()), int(st["iters"].max())],
              "iters_mean": float(st["iters"].mean()),
              "submatrices_per_s": m.n_atoms * a.steps / dt,
@@ -264,10 +312,13 @@ def main():
             per_launch = fu * metrics.MFMA_PRODUCTS[key[0]] * passes / nl
             variant = int(sm.sm_plan_tuning(plan)[key[0]])
             sym = metrics.gemm_kernel_symbol(key[0], key[1], variant, r["pad_to"])
+            bytes_launch = metrics.bytes_by_class(st, n, o).get(key, 0.0) * passes / nl
             r["kernel"] = {"name": sym, "precision": DT_NAME[key[0]],
                            "product": "square" if key[1] == 0 else "update",
                            "launches": int(launches[cls]), "avg_ms": avg_ms,
                            "algorithmic_flops_per_launch": per_launch,
+                           "algorithmic_bytes_per_launch": bytes_launch,
+                           "achieved_gbs": bytes_launch / (avg_ms * 1e-3) / 1e9,
                            "useful_flops_per_launch": fu * passes / nl,
                            "issued_flops_per_launch": fi * metrics.MFMA_PRODUCTS[key[0]] * passes / nl,
                            "achieved_tflops": per_launch / (avg_ms * 1e-3) / 1e12,
@@ -285,7 +336,8 @@ def main():
         print(f"# {mode}: {r['ms_per_step']:.2f} ms/step, {r['submatrices_per_s']:.0f} subm/s, "
               f"{r['useful_tflops']:.2f} TF/s useful, iters {r['iters']}, dE {r['rel_dE_vs_f64']:.2e}, "
               f"dP {r['max_dP_vs_f64']:.2e}, variant {best} (tune ms {' / '.join(f'{x:.2f}' for x in tune_ms)})"
-              + (f", {r['kernel']['name']} {r['kernel']['achieved_tflops']:.2f} TF/s" if prof else ""),
+              + (f", {r['kernel']['name']} {r['kernel']['achieved_tflops']:.2f} TF/s "
+                 f"{r['kernel']['achieved_gbs']:.0f} GB/s" if prof else ""),
               file=sys.stderr, flush=True)
         del work
 
@@ -301,13 +353,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if head in ("bf16x3", "f16", "bf16") else ""),
+        "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if MODES[head] in ("bf16x3", "f16", "bf16") else ""),
         "data": "synthetic",
         "config": {"workload": "lattice1000: 10x10x10 lattice, 3% vacancies, jitter 0.05, 6 orbitals "
                                "(N=5802), cutoff 2.2, 967 submatrices n=192..276, mu by bisection",
                    "n_sub": m.n_atoms, "N": m.n_orb, "mode": head, "seed": a.seed},
         "useful_tflops": h["useful_tflops"],
         "speedup_vs_fp64_plain": res["f64"]["ms_per_step"] / h["ms_per_step"],
+        "scaling_network": net_info,
         "modes": res,
     }
     if "kernel" in h:
@@ -315,10 +368,23 @@ def main():
         from paper_2205_14741_amd import profsum
         traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", "ns_gemm_traffic_lattice1000.txt"),
                                        kk["name"])
-        out["roofline"] = {"bound": "mfma", "achieved": kk["achieved_tflops"], "peak": kk["peak_tflops"],
-                           "unit": "TFLOP/s", "frac": kk["achieved_tflops"] / kk["peak_tflops"],
-                           "traffic": traffic, "kernel": kk["name"], "avg_launch_ms": kk["avg_ms"],
-                           "flops_per_launch": kk["algorithmic_flops_per_launch"]}
+        # the bound is the resource whose time at peak is larger for this
+        # kernel's algorithmic flops and bytes (its arithmetic intensity
+        # against the chip's flop / byte ridge)
+        t_mfma = kk["algorithmic_flops_per_launch"] / (kk["peak_tflops"] * 1e12)
+        t_hbm = kk["algorithmic_bytes_per_launch"] / (metrics.HBM_PEAK_GBS * 1e9)
+        if t_hbm > t_mfma:
+            rl = {"bound": "hbm", "achieved": kk["achieved_gbs"], "peak": metrics.HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": kk["achieved_gbs"] / metrics.HBM_PEAK_GBS}
+        else:
+            rl = {"bound": "mfma", "achieved": kk["achieved_tflops"], "peak": kk["peak_tflops"], "unit": "TFLOP/s",
+                  "frac": kk["achieved_tflops"] / kk["peak_tflops"]}
+        rl.update({"traffic": traffic, "kernel": kk["name"], "avg_launch_ms": kk["avg_ms"],
+                   "flops_per_launch": kk["algorithmic_flops_per_launch"],
+                   "bytes_per_launch": kk["algorithmic_bytes_per_launch"],
+                   "mfma_frac": kk["achieved_tflops"] / kk["peak_tflops"],
+                   "hbm_frac": kk["achieved_gbs"] / metrics.HBM_PEAK_GBS})
+        out["roofline"] = rl
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(m, res["f64"]["mu"], a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -92,8 +92,8 @@ typedef struct {
   int32_t variant;       /* Newton-Schulz GEMM kernel variant: -1 = the plan's tuned choice
                             (see sm_autotune; 0 before tuning); 0 = tiles dealt to workgroups
                             in list order, 1 = each XCD walks a contiguous range of the tile
-                            list (a submatrix stays in one L2), 2 = as 1 with operands
-                            prefetched two stages ahead, 3 = as 1 with 128 x 128 output
+                            list (a submatrix stays in one L2), 2 = as 1 with LDS stages
+                            of half the k depth (more workgroups per CU), 3 = as 1 with 128 x 128 output
                             tiles (float32-accumulating precisions, plans padded to 64 or
                             128; otherwise runs as 1), 4 = 128 x 128 tiles walked in list
                             order (all XCDs on the same submatrices: their operands stay in
@@ -103,12 +103,23 @@ typedef struct {
                             scheduler, updates) into one HIP graph, cached per plan / chunk /
                             workspace, and replay it until no submatrix is left (the host
                             polls once per replay).  Ignored while kernel timing is on. */
-  int32_t reserved;
+  int32_t accel;         /* 0: plain Newton-Schulz.  1: scaled Newton-Schulz in the main
+                            phase (Chen and Chow, 2014): X <- 1/2 a X (3I - a^2 X^2) with a
+                            chosen from a running lower bound l on the smallest |eigenvalue|
+                            of X (so that l and the top of the spectrum map to the same
+                            value), l_0 from the scaling network when its scale is accepted,
+                            else from lbound; l is carried through every step and raised to
+                            sqrt(1 - ||X^2 - I||_F) once that residual is below 1.  The
+                            scale a never exceeds sqrt(3) / 1.01 of the spectrum's top, so no
+                            eigenvalue can change sign; a wrong l costs iterations only.
+                            Refinement steps are plain. */
+  double lbound;         /* l_0 as a fraction of the Gershgorin bound: the smallest
+                            |eigenvalue| of T is taken to be about lbound * c_G (0: none) */
 } sm_sign_opts;
 
 /* Per-submatrix result record, written on the device by build_submatrices
  * (scale, scale_src, gersh, rho_est, feat) and submatrix_sign (the rest).
- * 120 bytes, indexed by submatrix (atom) id. */
+ * 136 bytes, indexed by submatrix (atom) id. */
 typedef struct {
   int32_t iters;       /* Newton-Schulz updates applied in total */
   int32_t iters_low;   /* ... of which in the phase-1 precision */
@@ -119,6 +130,12 @@ typedef struct {
   double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v|| (-1 if off) */
   double gersh;        /* Gershgorin bound c_G = max_p sum_q |T_pq| */
   double rho_est;      /* power-iteration estimate of rho(T) (<= rho), -1 if not run */
+  double lb0;          /* l_0 used by scaled Newton-Schulz, relative to X_0 (0: none) */
+  double lb_est;       /* plain runs (accel 0): lower bound on the smallest |eigenvalue|
+                          of X_0 that the iteration itself yields, the largest over steps
+                          k with 0.01 <= r_k = ||X_k^2 - I||_F < 1 of g^-k(sqrt(1 - r_k)),
+                          g(x) = x (3 - x^2) / 2 inverted on [0, 1] (rigorous up to the
+                          rounding of r_k); -1 if none */
   float feat[16];      /* features of the scaling network (see sm_mlp_create) */
 } sm_sub_stats;
 
@@ -148,8 +165,18 @@ int sm_plan_create(const sm_bsr_pattern* pattern, int32_t pad_to,
                    int64_t max_chunk_elems, sm_plan** out);
 void sm_plan_destroy(sm_plan* plan);
 
+/* Workspace storage code of a schedule (the storage_prec argument below):
+ * SM_F64 or SM_F32 for the iterate's type; for the SM_BF16 / SM_F16 /
+ * SM_BF16X3 main phases that phase's code: float32 buffers followed by a
+ * region of the same size with the 16-bit operand copies the products read
+ * (one plane, or hi and lo planes for SM_BF16X3).  The main-phase products
+ * store only those copies; the float32 refinement and the read-out use the
+ * float32 buffers.  Returns -1 for a null pointer. */
+int sm_ws_storage(const sm_sign_opts* opts);
+
 /* Sizes for caller-owned buffers.
- *   storage_prec SM_F64 or SM_F32 (the iterate's storage type).
+ *   storage_prec storage code (sm_ws_storage of the schedule); a workspace
+ *               must be sized for the storage of every schedule run on it.
  *   n_sub       number of submatrices (= n_atoms), n_chunks number of chunks,
  *   ws_bytes    device workspace bytes needed by build/sign/assemble,
  *   p_nnz_vals  length of P's (and H's) value array.  Any pointer may be NULL. */
@@ -220,8 +247,12 @@ int sm_gershgorin_bracket(sm_plan* plan, const double* H_vals, double* lo, doubl
  *   regions9 = [matrices, state, partials, lists, features, scratch, vecs, flag, total]
  * and, per processing index g, the element offset of submatrix order[g]'s three
  * n_pad x n_pad column-major buffers (X_even, X_odd, Y) inside the matrix region
- * of its chunk.  After build_submatrices X_even holds X_0 = T_i / c_i; after
- * submatrix_sign the converged X is the buffer of parity stats[i].iters.
+ * of its chunk (float32 / float64 elements; for the 16-bit storage codes the
+ * copies of buffer b start at float offset max_mats + off, max_mats being the
+ * largest per-chunk sum of 3 n_pad^2).  After build_submatrices X_even holds
+ * X_0 = T_i / c_i (16-bit storage codes: the copies do; the float32 buffer
+ * keeps T_i); after submatrix_sign the final X is the float32 buffer of
+ * parity stats[i].iters.
  * Either output may be NULL. */
 int sm_plan_ws_layout(const sm_plan* plan, int32_t storage_prec, int64_t* regions9,
                       int64_t* mat_off_g);
@@ -239,8 +270,10 @@ int sm_selftest_mfma(int32_t prec, double* out_host);
  * cases.  Here a float32 multilayer perceptron 16 -> 64 -> 64 -> 2 with tanh
  * hidden layers maps the 16 features of a submatrix (sm_sub_stats.feat:
  * log n, log c_G, diagonal and Gershgorin-radius statistics relative to c_G)
- * to y0 ~ log(rho(T)/c_G) and y1 (a second spectral target of the caller's
- * choice).  Inputs are normalised by a stored mean / std (32 floats).
+ * to y0 ~ log(rho(T)/c_G) and y1 ~ log(l/c_G), l the smallest |eigenvalue|
+ * of T (train on sm_sub_stats.lb_est * scale / gersh of plain runs); y1 sets
+ * l_0 of scaled Newton-Schulz (opts.accel) where the learned scale is
+ * accepted.  Inputs are normalised by a stored mean / std (32 floats).
  * Parameters are packed as W1 (64x16 row-major), b1, W2 (64x64), b2, W3 (2x64),
  * b3: 5378 floats.  Loss = mean over samples of sum over outputs of
  * (y - t)^2; Adam with beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected.

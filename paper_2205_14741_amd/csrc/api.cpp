@@ -27,6 +27,8 @@ int check_opts(const sm_sign_opts* o) {
   if (o->variant < -1 || o->variant >= kGemmVariants) return set_error(SM_ERR_ARG, "opts.variant = %d out of [-1, %d)", o->variant, kGemmVariants);
   if (o->graph_iters < 0 || o->graph_iters > 64) return set_error(SM_ERR_ARG, "opts.graph_iters = %d out of [0, 64]", o->graph_iters);
   if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
+  if (o->accel != 0 && o->accel != 1) return set_error(SM_ERR_ARG, "opts.accel = %d is not 0 or 1", o->accel);
+  if (!(o->lbound >= 0.0 && o->lbound <= 1.0)) return set_error(SM_ERR_ARG, "opts.lbound out of [0, 1]");
   if (!(o->tol >= 0) || !(o->switch_tol >= 0) || !(o->stall_ratio >= 0) || !(o->stall_below >= 0) ||
       !(o->scale_margin >= 0))
     return set_error(SM_ERR_ARG, "negative or NaN tolerance in opts");
@@ -176,7 +178,8 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
     predp = pred;
   }
   SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
-                      cg, predp, stats, storage >= SM_BF16 ? storage : 0, shadow, s));
+                      cg, predp, stats, storage >= SM_BF16 ? storage : 0, shadow, o->lbound,
+                      w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, s));
   SM_HIP(hipMemcpyAsync(&p->h_pinned[8], w.flag, 4, hipMemcpyDeviceToHost, s));
   SM_HIP(hipStreamSynchronize(s));
   p->last_storage = storage;
@@ -221,7 +224,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   auto phase = [&](int Lm, int Lr, int which) -> int {
     const int first_ref = (which == 1 && shadow_kind) ? o->refine_steps - 1 : -1;
     SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, Lm, Lr, rec_main, has_ref ? rec_ref : nullptr,
-                         tsh_main, tsh_ref, first_ref, nsub, s));
+                         tsh_main, tsh_ref, which, first_ref, nsub, s));
     int r;
     if ((r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, 0, list_count(Lm), rec_main,
                          w.partials, max_tiles, s)))
@@ -239,7 +242,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     s = st;
     r = phase(2, 3, 0);                                                   // A = X^2, Y = 3I - A
     if (!r) {
-      hipError_t e = launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref, st);
+      hipError_t e = launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref,
+                                     nullptr, nullptr, st);
       if (e != hipSuccess) r = hip_error(e, "launch_schedule");
     }
     if (!r) r = phase(0, 1, 1);                                           // X' = 1/2 X Y
@@ -247,13 +251,16 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     return r;
   };
 
-  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, tsh_main, tsh_ref, s));
+  // bounds on the spectrum of X_0 written by build_submatrices (scaled Newton-Schulz)
+  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, tsh_main, tsh_ref,
+                         w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, s));
   const int lim = o->max_iter + o->refine_steps + 2;
   const int G = p->profiling ? 0 : o->graph_iters;
   if (G == 0) {
     for (int it = 0; it <= lim; ++it) {
       if ((rc = phase(2, 3, 0))) return rc;          // squares: A = X^2, Y = 3I - A
-      SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref, s));
+      SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref,
+                             nullptr, nullptr, s));
       SM_HIP(hipMemcpyAsync(&p->h_pinned[it & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
       SM_HIP(hipEventRecord(p->ev[it & 1], s));
       if ((rc = phase(0, 1, 1))) return rc;          // updates: X' = 1/2 X Y

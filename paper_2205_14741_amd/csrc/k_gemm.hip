@@ -79,21 +79,22 @@ template <int MODE, bool PRE = Pre<MODE>::value> struct Operand;
 template <int NL>
 __device__ __forceinline__ void load_col_shadow(float (&r)[NL], const uint16_t* p, int64_t nn, int kind,
                                                 bool ok) {
-  static_assert(NL % 8 == 0, "vector width");
+  static_assert(NL % 4 == 0, "vector width");
+  typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int v = 0; v < NL / 8; ++v) {
-    u32x4 h = u32x4{0, 0, 0, 0}, l = u32x4{0, 0, 0, 0};
+  for (int v = 0; v < NL / 4; ++v) {
+    u2 h = u2{0, 0}, l = u2{0, 0};
     if (ok) {
-      h = *reinterpret_cast<const u32x4*>(p + 8 * v);
-      if (kind == SM_BF16X3) l = *reinterpret_cast<const u32x4*>(p + nn + 8 * v);
+      h = *reinterpret_cast<const u2*>(p + 4 * v);
+      if (kind == SM_BF16X3) l = *reinterpret_cast<const u2*>(p + nn + 4 * v);
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < 4; ++e) {
       const uint16_t hb = (uint16_t)(h[e >> 1] >> (16 * (e & 1)));
       const uint16_t lb = (uint16_t)(l[e >> 1] >> (16 * (e & 1)));
       float x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, hb) : bf16_bits_to_f32(hb);
       if (kind == SM_BF16X3) x += bf16_bits_to_f32(lb);
-      r[8 * v + e] = x;
+      r[4 * v + e] = x;
     }
   }
 }
@@ -166,14 +167,15 @@ __device__ __forceinline__ void stage_store(const RT (&r)[RN], LT* dst, LT* dst_
 
 // Epilogue of a float32-accumulating product for one lane's four results
 // (rows rb .. rb + 3 of column cc): entries on or below the diagonal are
-// written to (r, c) and mirrored to (c, r); for the square, Y = 3I - A is
-// stored and (A - I)^2 is added to the residual partial sum.  Products of the
+// written to (r, c) and mirrored to (c, r); for the square, Y = 3I - alpha^2 A
+// is stored and (A - I)^2 is added to the residual partial sum; the update
+// stores 1/2 alpha X Y (alpha = 1: plain Newton-Schulz).  Products of the
 // low-precision main phases store only the 16-bit copies their consumers read
 // (the float32 value is rebuilt where a refinement step or the final
 // read-out needs it); float32 products store float32.
 template <int MODE, int WHICH>
 __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t shadow_off, int64_t nn,
-                                           int npad, int rb, int cc, double& part) {
+                                           int npad, int rb, int cc, double alpha, double& part) {
   constexpr bool PRE = Pre<MODE>::value;
   float o[4];
   uint16_t h[4], l[4];
@@ -185,9 +187,9 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
       const double dg = (rr == cc) ? 1.0 : 0.0;
       const double e = a - dg;
       if (rr >= cc) part += (rr == cc) ? e * e : 2.0 * e * e;
-      o[v] = (float)(3.0 * dg - a);
+      o[v] = (float)(3.0 * dg - (alpha * alpha) * a);
     } else {
-      o[v] = (float)(0.5 * a);
+      o[v] = (float)((0.5 * alpha) * a);
     }
     if constexpr (PRE) {
       h[v] = shadow_hi(o[v], MODE);
@@ -243,8 +245,8 @@ __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
 // C[r][c] = sum_k L[k][r] R[k][c] with L = X and R = X or Y stored column-major;
 // by symmetry L[k][r] = X[r][k], so C = X R.  Both operand panels are read as
 // columns (contiguous k), i.e. LDS rows hold one output row's k-slab.
-// DEPTH: how many stages ahead the operand panels are loaded into registers
-// (1: the next stage, 2: the one after; more latency cover, more registers).
+// KDIV: the LDS stage holds K / KDIV of the k range (KDIV = 2 halves the LDS
+// footprint, so more workgroups fit on a compute unit, at twice the barriers).
 // XCD: workgroups are dealt to the 8 XCDs round-robin (workgroup b on XCD
 // b % 8), each with its own L2.  With XCD set, the workgroups of XCD x walk
 // the x-th contiguous eighth of the tile list, so all tiles of a submatrix
@@ -252,7 +254,7 @@ __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
 // all eight.
 constexpr int kXcds = 8;
 
-template <int MODE, int WHICH, int DEPTH, bool XCD>
+template <int MODE, int WHICH, int KDIV, bool XCD>
 __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::S* __restrict__ mats,
                                                          int64_t shadow_off, int shadow_kind,
                                                          const int32_t* __restrict__ count,
@@ -261,9 +263,10 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
   using Tr = Traits<MODE>;
   using S = typename Tr::S;
   using LT = typename Tr::L;
-  constexpr int K = Tr::K;
+  constexpr int K = Tr::K / KDIV;
   constexpr int LD = K + Tr::KP;
   constexpr int NL = K / 4;              // elements per thread per operand per stage
+  constexpr int KK = K / 4;              // k values per lane and stage (float64 / float32)
   constexpr bool SPLIT = (MODE == SM_BF16X3);
   constexpr bool PRE = Pre<MODE>::value;
   constexpr int NPL = SPLIT ? 2 : 1;     // operand planes (hi, lo)
@@ -295,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     if (t + t_step < t_end) nxt = recs[t + t_step];   // prefetch the next tile's record
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
+    const double alpha = (double)rec.alpha;
     S* base = mats + rec.mat_off;
     const int it = rec.it;
     const S* Xp;
@@ -330,31 +334,24 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = typename Tr::Acc{0, 0, 0, 0};
 
-    // operand stages are loaded DEPTH stages ahead of their use (register sets
-    // s % DEPTH), so a global load has DEPTH stages of MFMA work to arrive
+    // the next stage's operands are loaded into registers while the MFMAs
+    // work on the current LDS stage
     const int nst = npad / K;
     auto k_loop = [&](auto compute_tag) {
     constexpr bool COMPUTE = decltype(compute_tag)::value;
-    RT rga[DEPTH][RN], rgb[DEPTH][RN];
-#pragma unroll
-    for (int q = 0; q < DEPTH; ++q)
-      if (q < nst) {
-        opa.template load<K, NL>(rga[q], q, va);
-        opb.template load<K, NL>(rgb[q], q, vb);
-      }
+    RT ra[RN], rb[RN];
+    opa.template load<K, NL>(ra, 0, va);
+    opb.template load<K, NL>(rb, 0, vb);
     for (int s = 0; s < nst; ++s) {
       const int buf = s & 1;
-      const int rs = DEPTH == 1 ? 0 : (s % DEPTH);
-      RT (&ra)[RN] = rga[rs];
-      RT (&rb)[RN] = rgb[rs];
       // ---- registers -> LDS ----
       stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
       stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
       __syncthreads();
-      // ---- prefetch stage s + DEPTH into the register set just emptied ----
-      if (s + DEPTH < nst) {
-        opa.template load<K, NL>(ra, s + DEPTH, va);
-        opb.template load<K, NL>(rb, s + DEPTH, vb);
+      // ---- prefetch the next stage into the registers just emptied ----
+      if (s + 1 < nst) {
+        opa.template load<K, NL>(ra, s + 1, va);
+        opb.template load<K, NL>(rb, s + 1, vb);
       }
       // ---- MFMA on the LDS stage ----
       const int kq = lane >> 4;    // k group of this lane
@@ -363,33 +360,33 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
         // wave block past n_pad (or above the diagonal): nothing to accumulate
       } else if constexpr (MODE == SM_F64) {
         // 16x16x4: lane supplies A[rl][kq], B[kq][rl]; the k index inside the
-        // stage is permuted to 4 kq + kk so each lane reads 4 contiguous values.
-        double a[2][4], b[2][4];
+        // stage is permuted to KK kq + kk so each lane reads KK contiguous values.
+        double a[2][KK], b[2][KK];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            a[x][kk] = lds[buf][0][(wm * 32 + x * 16 + rl) * LD + 4 * kq + kk];
-            b[x][kk] = lds[buf][1][(wn * 32 + x * 16 + rl) * LD + 4 * kq + kk];
+          for (int kk = 0; kk < KK; ++kk) {
+            a[x][kk] = lds[buf][0][(wm * 32 + x * 16 + rl) * LD + KK * kq + kk];
+            b[x][kk] = lds[buf][1][(wn * 32 + x * 16 + rl) * LD + KK * kq + kk];
           }
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
+        for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y)
               acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][kk], b[y][kk], acc[x][y], 0, 0, 0);
       } else if constexpr (MODE == SM_F32) {
-        float a[2][8], b[2][8];
+        float a[2][KK], b[2][KK];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int kk = 0; kk < 8; ++kk) {
-            a[x][kk] = lds[buf][0][(wm * 32 + x * 16 + rl) * LD + 8 * kq + kk];
-            b[x][kk] = lds[buf][1][(wn * 32 + x * 16 + rl) * LD + 8 * kq + kk];
+          for (int kk = 0; kk < KK; ++kk) {
+            a[x][kk] = lds[buf][0][(wm * 32 + x * 16 + rl) * LD + KK * kq + kk];
+            b[x][kk] = lds[buf][1][(wn * 32 + x * 16 + rl) * LD + KK * kq + kk];
           }
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk)
+        for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -474,15 +471,15 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
               const double dg = (rr == cc) ? 1.0 : 0.0;
               const double e = a - dg;
               part += (rr == cc) ? e * e : 2.0 * e * e;
-              outv = 3.0 * dg - a;
+              outv = 3.0 * dg - (alpha * alpha) * a;
             } else {
-              outv = 0.5 * a;
+              outv = (0.5 * alpha) * a;
             }
             Out[(int64_t)cc * npad + rr] = outv;
             if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
           }
         } else {
-          store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb + 4 * kq, cc, part);
+          store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb + 4 * kq, cc, alpha, part);
         }
       }
     if (WHICH == 0) {
@@ -506,7 +503,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
                                                      int list_main, int list_ref,
                                                      TileRec* __restrict__ recs_main,
                                                      TileRec* __restrict__ recs_ref, int tshift_main,
-                                                     int tshift_ref, int first_ref) {
+                                                     int tshift_ref, int which, int first_ref) {
   const int stride = 2 + 2 * max_subs + 1;
   const int32_t* Lb = lists + (blockIdx.y == 0 ? list_main : list_ref) * stride;
   TileRec* out = blockIdx.y == 0 ? recs_main : recs_ref;
@@ -522,6 +519,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int nt = T * (T + 1) / 2;
   const int64_t mo = p.mat_off_g[g];
   const int it = st[l].iters;
+  const float alpha = (float)(which == 0 ? st[l].alpha_sq : st[l].alpha_upd);
   const int16_t flags = (blockIdx.y == 1 && first_ref >= 0 && st[l].refine_left == first_ref) ? kTileFromShadow : 0;
   const int po = p.tile_off_g[g];
   const int t64 = tiles_of(npad);
@@ -531,7 +529,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
     const int b64i = bi * f, b64j = bj * f;
     TileRec r;
     r.mat_off = mo;
-    r.l = l;
+    r.alpha = alpha;
     r.bibj = (bi << 16) | bj;
     r.npad = npad;
     r.it = it;
@@ -544,11 +542,12 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
 
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int tshift_main, int tshift_ref, int first_ref, int grid_subs,
-                         hipStream_t s) {
+                         TileRec* recs_ref, int tshift_main, int tshift_ref, int which, int first_ref,
+                         int grid_subs, hipStream_t s) {
   if (grid_subs <= 0) return hipSuccess;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, recs_ref ? 2 : 1), dim3(256), 0, s, p, g0, st, lists,
-                     max_subs, list_main, list_ref, recs_main, recs_ref, tshift_main, tshift_ref, first_ref);
+                     max_subs, list_main, list_ref, recs_main, recs_ref, tshift_main, tshift_ref, which,
+                     first_ref);
   return hipGetLastError();
 }
 
@@ -608,6 +607,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
     if (t + t_step < t_end) nxt = recs[t + t_step];
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
+    const double alpha = (double)rec.alpha;
     S* base = mats + rec.mat_off;
     const int it = rec.it;
     const S* Xp;
@@ -725,7 +725,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
 #pragma unroll
       for (int y = 0; y < 4; ++y)
         store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 64 + x * 16 + 4 * kq,
-                                c0 + wn * 64 + y * 16 + rl, part);
+                                c0 + wn * 64 + y * 16 + rl, alpha, part);
     if (WHICH == 0) {
       part = wave_sum(part);
       if (lane == 0) red[wid] = part;
@@ -747,23 +747,24 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
   }
 }
 
-// kernel variants: 0 = {depth 1, linear}, 1 = {depth 1, XCD-aware}, 2 = {depth 2, XCD-aware}
+// 64-tile kernel variants: 0 = {full stage, linear walk}, 1 = {full stage,
+// XCD-aware}, 2 = {half stage, XCD-aware}
 template <int MODE, int WHICH, int V>
 struct Var {
-  static constexpr int DEPTH = V == 2 ? 2 : 1;
+  static constexpr int KDIV = V == 2 ? 2 : 1;
   static constexpr bool XCD = V >= 1;
 };
 
 template <int MODE, int WHICH, int V>
 static void* kernel_ptr() {
-  return reinterpret_cast<void*>(&ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::DEPTH, Var<MODE, WHICH, V>::XCD>);
+  return reinterpret_cast<void*>(&ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::KDIV, Var<MODE, WHICH, V>::XCD>);
 }
 
 template <int MODE, int WHICH, int V>
 static hipError_t launch_one(void* mats, int64_t so, int sk, const int32_t* count, const TileRec* recs,
                              double* partials, int grid, hipStream_t s) {
   using S = typename Traits<MODE>::S;
-  hipLaunchKernelGGL((ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::DEPTH, Var<MODE, WHICH, V>::XCD>),
+  hipLaunchKernelGGL((ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::KDIV, Var<MODE, WHICH, V>::XCD>),
                      dim3(grid), dim3(kBlock), 0, s, (S*)mats, so, sk, count, recs, partials);
   return hipGetLastError();
 }
@@ -858,9 +859,27 @@ int ns_gemm_blocks_per_cu(int mode, int which, int variant) {
 // device scheduler
 // ---------------------------------------------------------------------------
 struct SchedOpts {
-  int refine_steps, max_iter;
+  int refine_steps, max_iter, accel;
   double tol, switch_tol, stall_below, stall_ratio;
 };
+
+// The Newton-Schulz map with scale a on one eigenvalue x >= 0.
+__device__ __forceinline__ double ns_map(double a, double x) { return 0.5 * a * x * (3.0 - a * a * x * x); }
+
+// Scale for a spectrum inside [lb, top] (absolute values): the a for which
+// lb and top have the same image, so that the image is [ns_map(a, lb), 1]
+// (for top = 1: a^2 = 3 / (1 + lb + lb^2)), capped at sqrt(3) / (1.01 top) so
+// every eigenvalue stays on the increasing branch with a margin for rounding.
+// Rounded to float, the precision in which the kernels receive it.
+__device__ __forceinline__ double ns_alpha(double lb, double top) {
+  const double l = fmin(lb / top, 1.0);
+  const double a = fmin(sqrt(3.0 / (1.0 + l + l * l)), 1.7320508075688772 / 1.01) / top;
+  return (double)(float)a;
+}
+
+// x with g(x) = y, g(x) = x (3 - x^2) / 2, on [0, 1]: x = 2 sin(asin(y) / 3)
+// (g(2 sin t) = sin 3t).
+__device__ __forceinline__ double ns_map_inv(double y) { return 2.0 * sin(asin(fmin(y, 1.0)) / 3.0); }
 
 enum { DEC_UPD = 1, DEC_SQ = 2, DEC_REF = 4 };
 
@@ -912,7 +931,9 @@ __global__ __launch_bounds__(256) void residual_kernel(DevPlan p, int g0, int ns
 // refinement precision.
 __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int nsub, SubState* st,
                                                         int32_t* lists, int max_subs, SchedOpts o,
-                                                        int first, int tshift_main, int tshift_ref) {
+                                                        int first, int tshift_main, int tshift_ref,
+                                                        const double* __restrict__ lb0,
+                                                        const double* __restrict__ top0) {
   __shared__ int sh[16];
   const int stride = 2 + 2 * max_subs + 1;
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
@@ -935,12 +956,31 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         s.status = 0;
         s.res = 1e300;
         s.res_prev = 1e300;
+        s.lb = lb0 ? fmax(lb0[l], 0.0) : 0.0;
+        s.top = top0 ? fmax(top0[l], 1.0) : 1.0;
+        s.alpha_sq = (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : 1.0;
+        s.alpha_upd = 1.0;
+        s.lb_est = -1.0;
         dec = DEC_SQ;
       } else if (s.active) {
         const double r = s.res_new;
         s.res_prev = s.res;
         s.res = r;
         const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
+        // r < 1 bounds every eigenvalue x of the current X: |x^2 - 1| <= r
+        double lb = s.lb, top = s.top;
+        if (r < 1.0) {
+          lb = fmax(lb, sqrt(1.0 - r));
+          top = fmin(top, sqrt(1.0 + r));
+          // plain run: carry the bound back to X_0.  Only residuals >= 0.01:
+          // near convergence the inverse map is steep at 1, and the rounding
+          // of a tiny residual would be amplified into the bound.
+          if (!o.accel && r >= 0.01) {
+            double x = sqrt(1.0 - r);
+            for (int j = 0; j < s.iters; ++j) x = ns_map_inv(x);
+            s.lb_est = fmax(s.lb_est, x);
+          }
+        }
         if (!(r < 1e300)) {
           s.status = -1;
           s.active = 0;
@@ -976,6 +1016,16 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
             s.status = 2;
             s.active = 0;
           }
+        }
+        if (dec & DEC_UPD) {
+          // the update of X uses its square's scale; bounds for the new X
+          const double a = s.alpha_sq;
+          s.alpha_upd = a;
+          const double lo = fmin(ns_map(a, lb), ns_map(a, top));
+          s.top = (a * top >= 1.0 && a * lb <= 1.0) ? 1.0 : fmax(ns_map(a, lb), ns_map(a, top));
+          s.lb = fmax(lo, 0.0);
+          // main-phase squares of an accelerated run are scaled, the rest plain
+          s.alpha_sq = (o.accel && !(dec & DEC_REF) && s.phase == 0 && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : 1.0;
         }
       }
       st[l] = s;
@@ -1015,12 +1065,12 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
-                           hipStream_t s) {
-  SchedOpts o{so.refine_steps, so.max_iter, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
+                           const double* lb0, const double* top0, hipStream_t s) {
+  SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
   if (!first && nsub > 0)
     hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
   hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, lists, max_subs, o, first,
-                     tshift_main, tshift_ref);
+                     tshift_main, tshift_ref, lb0, top0);
   return hipGetLastError();
 }
 

@@ -43,56 +43,65 @@ hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, c
 }
 
 // One workgroup per submatrix: copy the per-submatrix iteration record into
-// `stats` and, with probes > 0, estimate max_v ||X (X v) - v|| / ||v|| in float64
-// for fixed +-1 vectors v (a residual of sign(T)^2 = I, Eq. 13).
-template <typename T>
-__global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T* __restrict__ mats,
-                                                     const SubState* __restrict__ st, int probes,
+// `stats` and, with P > 0 probes, estimate max_v ||X (X v) - v|| / ||v|| in
+// float64 for fixed +-1 vectors v (a residual of sign(T)^2 = I, Eq. 13).
+// Thread r owns row r: (X v)_r = sum_c X[r][c] v_c reads X column-major
+// with consecutive threads on consecutive rows (coalesced), every probe in
+// the same pass, and no cross-lane reductions.  Two passes over X in all.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void finish_kernel(DevPlan p, int g0, const T* __restrict__ mats,
+                                                     const SubState* __restrict__ st,
                                                      double* __restrict__ vecs,
                                                      sm_sub_stats* __restrict__ stats) {
-  __shared__ double red[16];
+  __shared__ double red[4];
   const int l = blockIdx.x;
   const int g = g0 + l;
   const int i = p.order_g[g];
   const int npad = p.npad_g[g];
   const int n = p.height[i];
   const T* X = final_x(p, g, mats, st, l);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
   double worst = -1.0;
-  if (probes > 0) {
-    double* v = vecs + p.vec_off_g[g];
-    double* w = v + npad;
-    double* z = w + npad;
-    worst = 0.0;
-    for (int pr = 0; pr < probes; ++pr) {
-      for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] = probe_entry(pr, d);
-      __syncthreads();
-      for (int c = wid; c < n; c += nw) {
-        const T* col = X + (int64_t)c * npad;
-        double s = 0.0;
-        for (int d = lane; d < n; d += kWave) s += (double)col[d] * v[d];
-        s = wave_sum(s);
-        if (lane == 0) w[c] = s;
+  if constexpr (P > 0) {
+    double* v = vecs + p.vec_off_g[g];      // [P][npad]
+    double* w = v + (int64_t)P * npad;       // [P][npad] = X v
+    for (int d = threadIdx.x; d < n; d += blockDim.x)
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[q * npad + d] = probe_entry(q, d);
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      double acc[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) acc[q] = 0.0;
+      for (int c = 0; c < n; ++c) {
+        const double x = (double)X[(int64_t)c * npad + r];
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] += x * v[q * npad + c];
       }
-      __syncthreads();
-      for (int c = wid; c < n; c += nw) {
-        const T* col = X + (int64_t)c * npad;
-        double s = 0.0;
-        for (int d = lane; d < n; d += kWave) s += (double)col[d] * w[d];
-        s = wave_sum(s);
-        if (lane == 0) z[c] = s;
-      }
-      __syncthreads();
-      double e = 0.0;
-      for (int d = threadIdx.x; d < n; d += blockDim.x) {
-        const double t = z[d] - v[d];
-        e += t * t;
-      }
-      e = block_reduce<0>(e, red);
-      worst = fmax(worst, sqrt(e / (double)n));
+#pragma unroll
+      for (int q = 0; q < P; ++q) w[q * npad + r] = acc[q];
     }
+    __syncthreads();
+    double e[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) e[q] = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      double acc[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) acc[q] = 0.0;
+      for (int c = 0; c < n; ++c) {
+        const double x = (double)X[(int64_t)c * npad + r];
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] += x * w[q * npad + c];
+      }
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const double t = acc[q] - v[q * npad + r];
+        e[q] += t * t;
+      }
+    }
+    worst = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) worst = fmax(worst, sqrt(block_reduce<0>(e[q], red) / (double)n));
   }
   if (threadIdx.x == 0) {
     const SubState s = st[l];
@@ -101,21 +110,34 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
     r.iters_low = s.iters_low;
     r.status = s.status;
     r.res = s.res;
-    if (probes > 0) r.res_probe = worst;
+    r.lb_est = s.lb_est;
+    if (P > 0) r.res_probe = worst;
   }
+}
+
+template <typename T>
+static hipError_t launch_finish_t(const DevPlan& p, int g0, int nsub, const T* mats, const SubState* st,
+                                  int probes, double* vecs, sm_sub_stats* stats, hipStream_t s) {
+#define SM_FINISH(PR)                                                                                 \
+  case PR:                                                                                            \
+    hipLaunchKernelGGL((finish_kernel<T, PR>), dim3(nsub), dim3(256), 0, s, p, g0, mats, st, vecs, stats); \
+    break;
+  switch (probes) {
+    SM_FINISH(0) SM_FINISH(1) SM_FINISH(2) SM_FINISH(3) SM_FINISH(4) SM_FINISH(5) SM_FINISH(6)
+    SM_FINISH(7) SM_FINISH(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef SM_FINISH
+  return hipGetLastError();
 }
 
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                          const SubState* st, int probes, double* vecs, sm_sub_stats* stats,
                          hipStream_t s) {
+  static_assert(kMaxProbes == 8, "finish kernels are instantiated for 0..8 probes");
   if (nsub <= 0) return hipSuccess;
-  if (storage_f64)
-    hipLaunchKernelGGL(finish_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0,
-                       (const double*)mats, st, probes, vecs, stats);
-  else
-    hipLaunchKernelGGL(finish_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0,
-                       (const float*)mats, st, probes, vecs, stats);
-  return hipGetLastError();
+  if (storage_f64) return launch_finish_t(p, g0, nsub, (const double*)mats, st, probes, vecs, stats, s);
+  return launch_finish_t(p, g0, nsub, (const float*)mats, st, probes, vecs, stats, s);
 }
 
 // Block column i of P = 1/2 (E - X[:, loc_i : loc_i + b_i]) over the n_i rows of

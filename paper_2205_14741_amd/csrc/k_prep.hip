@@ -215,7 +215,9 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     const double* __restrict__ cg_in,
                                                     const float* __restrict__ pred,
                                                     sm_sub_stats* __restrict__ stats, int shadow_kind,
-                                                    int64_t shadow_off) {
+                                                    int64_t shadow_off, double lbound,
+                                                    double* __restrict__ lb0_out,
+                                                    double* __restrict__ top0_out) {
   __shared__ double red[16];
   const int l = blockIdx.x;
   const int g = g0 + l;
@@ -243,12 +245,11 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] *= inv;
     __syncthreads();
     for (int it = 0; it < power_steps; ++it) {
-      for (int c = wid; c < n; c += nw) {
-        const T* col = X + (int64_t)c * npad;
+      // w = T v, thread r owning row r (coalesced column-major reads)
+      for (int r = threadIdx.x; r < n; r += blockDim.x) {
         double s = 0.0;
-        for (int d = lane; d < n; d += kWave) s += (double)col[d] * v[d];
-        s = wave_sum(s);
-        if (lane == 0) w[c] = s;
+        for (int c = 0; c < n; ++c) s += (double)X[(int64_t)c * npad + r] * v[c];
+        w[r] = s;
       }
       __syncthreads();
       double nw2 = 0.0;
@@ -262,6 +263,8 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
   }
   double c = cG;
   int src = 0;
+  // smallest |eigenvalue| of T as a fraction of c_G (scaled Newton-Schulz)
+  double lrel = lbound;
   if (scaling == SM_SCALE_POWER && est > 0.0) {
     c = fmin(cG, (1.0 + margin) * est);
     src = 1;
@@ -271,26 +274,32 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     if (pred && isfinite(y0) && ch >= est && ch <= cG) {
       c = ch;
       src = 2;
+      const double y1 = (double)pred[2 * l + 1];
+      if (isfinite(y1)) lrel = exp(fmin(y1, 0.0));
     } else {
       src = 3;
     }
   }
   const double sc = 1.0 / c;
-  for (int cc = wid; cc < n; cc += nw) {
-    T* col = X + (int64_t)cc * npad;
-    for (int d = lane; d < n; d += kWave) col[d] = (T)((double)col[d] * sc);
-  }
-  if constexpr (std::is_same<T, float>::value) {
-    // operand copy of the whole padded X_0 for the low-precision products
-    if (shadow_kind) {
-      __syncthreads();
-      const int64_t nn = (int64_t)npad * npad;
-      uint16_t* hi = reinterpret_cast<uint16_t*>(X + shadow_off);
-      for (int64_t k = threadIdx.x; k < nn; k += blockDim.x) {
-        const float x = X[k];
+  bool copies = false;
+  if constexpr (std::is_same<T, float>::value) copies = shadow_kind != 0;
+  if (!copies) {
+    for (int cc = wid; cc < n; cc += nw) {
+      T* col = X + (int64_t)cc * npad;
+      for (int d = lane; d < n; d += kWave) col[d] = (T)((double)col[d] * sc);
+    }
+  } else if constexpr (std::is_same<T, float>::value) {
+    // products of the low-precision phases read only the 16-bit copies of
+    // X_0 (identity padding included); the float32 buffer keeps T
+    uint16_t* hi = reinterpret_cast<uint16_t*>(X + shadow_off);
+    const int64_t nn = (int64_t)npad * npad;
+    for (int cc = wid; cc < npad; cc += nw) {
+      const int64_t o = (int64_t)cc * npad;
+      for (int d = lane; d < npad; d += kWave) {
+        const float x = (cc < n && d < n) ? (float)((double)X[o + d] * sc) : X[o + d];
         const uint16_t h = shadow_hi(x, shadow_kind);
-        hi[k] = h;
-        if (shadow_kind == SM_BF16X3) hi[nn + k] = shadow_lo(x, h);
+        hi[o + d] = h;
+        if (shadow_kind == SM_BF16X3) hi[nn + o + d] = shadow_lo(x, h);
       }
     }
   }
@@ -299,6 +308,11 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     r.scale = c;
     r.scale_src = src;
     r.rho_est = est;
+    // X_0 = T / c: |eigenvalues| in [lrel c_G / c, c_G / c] (the top is rigorous)
+    const double lb = fmin(fmax(lrel, 0.0) * cG / c, 1.0);
+    r.lb0 = lb;
+    lb0_out[l] = lb;
+    top0_out[l] = cG / c;
   }
 }
 
@@ -317,14 +331,16 @@ hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, 
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
-                        hipStream_t s) {
+                        double lbound, double* lb0_out, double* top0_out, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   if (storage_f64)
     hipLaunchKernelGGL(scale_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats, scaling,
-                       power_steps, margin, vecs, cg_in, pred, stats, 0, (int64_t)0);
+                       power_steps, margin, vecs, cg_in, pred, stats, 0, (int64_t)0, lbound, lb0_out,
+                       top0_out);
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
-                       power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off);
+                       power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off, lbound,
+                       lb0_out, top0_out);
   return hipGetLastError();
 }
 

@@ -44,6 +44,9 @@ int ws_storage(const sm_sign_opts* o) {
 
 bool valid_storage(int storage) { return storage >= SM_F64 && storage <= SM_BF16X3; }
 
+static_assert(sizeof(sm_sign_opts) == 88, "sm_sign_opts layout");
+static_assert(sizeof(sm_sub_stats) == 136, "sm_sub_stats layout");
+
 static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 }  // namespace sm
@@ -249,6 +252,8 @@ void sm_plan_destroy(sm_plan* p) {
   }
   delete p;
 }
+
+int sm_ws_storage(const sm_sign_opts* o) { return o ? ws_storage(o) : -1; }
 
 int sm_plan_sizes(const sm_plan* p, int32_t storage_prec, int64_t* n_sub, int64_t* n_chunks,
                   int64_t* ws_bytes, int64_t* p_nnz_vals) {

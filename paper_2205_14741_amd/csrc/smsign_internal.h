@@ -42,14 +42,21 @@ struct SubState {
   double res;          // last residual
   double res_prev;     // residual before that
   double res_new;      // residual of the square just computed (residual_kernel)
-  double pad_;
+  // scaled Newton-Schulz: the spectrum of the current X is taken to lie in
+  // [lb, top] in absolute value; alpha_sq scales the square about to run,
+  // alpha_upd the update about to run (the update of X uses its square's alpha)
+  double lb;
+  double top;
+  double alpha_sq;
+  double alpha_upd;
+  double lb_est;       // plain runs: lower bound on the smallest |eigenvalue| of X_0
 };
 
 // One output tile of a Newton-Schulz GEMM launch, written by expand_kernel so
 // that a GEMM workgroup finds everything about its tile in one 32-byte load.
 struct TileRec {
   int64_t mat_off;   // element offset of the submatrix's buffers in the chunk
-  int32_t l;         // local submatrix index
+  float alpha;       // Newton-Schulz scale: square Y = 3I - alpha^2 X^2, update 1/2 alpha X Y
   int32_t bibj;      // tile row << 16 | tile column (row >= column)
   int32_t npad;
   int32_t it;        // iteration counter (parity selects the X buffer)
@@ -84,21 +91,27 @@ hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, 
                           float* features, double* cg_out, sm_sub_stats* stats, hipStream_t s);
 // shadow_kind: 0, or SM_BF16 / SM_F16 / SM_BF16X3 to also write X_0's operand
 // copy at float offset shadow_off from its float32 buffer
+// lbound: opts.lbound; lb0_out / top0_out [nsub]: bounds on the smallest /
+// largest |eigenvalue| of X_0 for scaled Newton-Schulz (learned second output
+// when the learned scale is accepted, else lbound; top c_G / c).
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
-                        hipStream_t s);
+                        double lbound, double* lb0_out, double* top0_out, hipStream_t s);
+// first != 0 initialises the iteration state; lb0 / top0 [nsub] (may be null):
+// bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz).
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
-                           hipStream_t s);
-// first_ref >= 0: refinement-list tiles of submatrices with refine_left ==
-// first_ref (their first refinement update) get kTileFromShadow.
+                           const double* lb0, const double* top0, hipStream_t s);
+// which: 0 squares, 1 updates (selects the submatrix's alpha).  first_ref >= 0:
+// refinement-list tiles of submatrices with refine_left == first_ref (their
+// first refinement update) get kTileFromShadow.
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
                          int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int tshift_main, int tshift_ref, int first_ref,
+                         TileRec* recs_ref, int tshift_main, int tshift_ref, int which, int first_ref,
                          int grid_subs, hipStream_t s);
-// 0: linear, 1: XCD-aware, 2: XCD-aware + prefetch depth 2, 3: XCD-aware 128 x 128 tiles,
+// 0: linear, 1: XCD-aware, 2: XCD-aware with half-depth LDS stages, 3: XCD-aware 128 x 128 tiles,
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices)
 constexpr int kGemmVariants = 5;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles

@@ -6,8 +6,7 @@ is symmetric, so the kernels compute the tiles on and below the diagonal only:
 
     useful flops of one product  = n^2 (n + 1)       (n(n+1)/2 entries x 2n)
     issued MFMA flops            = (32 x 32 wave blocks computed) * 2 * 32 * 32 * np
-                                   (64 x 64 tiles on / below the diagonal; a wave block
-                                   that lies past n_pad, a multiple of 32, is skipped)
+                                   (the blocks on or below the diagonal inside n_pad)
 
 With a refinement phase of r steps (status 2) the counts are
     main precision:   squares = iters_low + 1, updates = iters_low
@@ -55,17 +54,12 @@ def flops_by_class(stats: np.ndarray, n: np.ndarray, npad: np.ndarray, opts):
 
 
 def wave_blocks(npad: np.ndarray) -> np.ndarray:
-    """32 x 32 wave blocks computed per product: all blocks of the 64 x 64
-    tiles with bi >= bj, minus those past n_pad."""
-    npad = np.asarray(npad, dtype=np.int64)
-    nb = npad // 32                                  # valid 32-blocks per dimension
-    T = (npad + 63) // 64
-    full = T * (T + 1) // 2 * 4                      # every tile, 4 wave blocks
-    # blocks past n_pad appear only when nb is odd (last tile half full)
-    odd = (nb % 2 == 1)
-    # last tile row (bi = T-1) and column (bj = T-1) lose their outer half
-    lost = np.where(odd, 2 * (T - 1) + 3, 0)         # T-1 off-diagonal tiles x 2 blocks + 3 in the corner tile
-    return (full - lost).astype(np.float64)
+    """32 x 32 wave blocks computed per product by the 64-tile kernels: the
+    blocks on or below the diagonal inside n_pad (tiles with bi >= bj; a
+    diagonal tile skips its block above the diagonal, an edge tile the blocks
+    past n_pad), i.e. nb (nb + 1) / 2 with nb = n_pad / 32."""
+    nb = np.asarray(npad, dtype=np.int64) // 32
+    return (nb * (nb + 1) // 2).astype(np.float64)
 
 
 def useful_flops(stats, n, npad, opts) -> float:
@@ -86,5 +80,23 @@ def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
         v = 1
     if v >= 3:
         return f"sm::ns_gemm128_kernel<{mode}, {which}, {'true' if v == 3 else 'false'}>"
-    depth = 2 if v == 2 else 1
-    return f"sm::ns_gemm_kernel<{mode}, {which}, {depth}, {'true' if v >= 1 else 'false'}>"
+    kdiv = 2 if v == 2 else 1   # variant 2: half-depth LDS stages
+    return f"sm::ns_gemm_kernel<{mode}, {which}, {kdiv}, {'true' if v >= 1 else 'false'}>"
+
+
+# Bytes per stored element of a product's operands and result: float64 and
+# float32 iterates, 16-bit copies for bf16 / f16, hi + lo copies for split bf16.
+STORE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4}
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def bytes_by_class(stats: np.ndarray, n: np.ndarray, opts) -> dict:
+    """{(precision, kind): algorithmic memory bytes of one pass}: a square
+    reads X and writes Y, an update reads X and Y and writes X', each an
+    n x n matrix in the storage of that precision's products."""
+    n2 = n.astype(np.float64) ** 2
+    res = {}
+    for (prec, kind), cnt in product_counts(stats, opts).items():
+        per = (2.0 if kind == 0 else 3.0) * STORE_BYTES[prec] * n2
+        res[(prec, kind)] = float((np.asarray(cnt, dtype=np.float64) * per).sum())
+    return res

@@ -26,7 +26,7 @@ EXPORTED = (
     "sm_density_matrix", "sm_find_mu", "sm_gershgorin_bracket", "sm_selftest_mfma",
     "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
-    "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning",
+    "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
 )
 
 
@@ -46,7 +46,8 @@ class SignOpts(C.Structure):
                 ("max_iter", C.c_int32), ("tol", C.c_double), ("switch_tol", C.c_double),
                 ("stall_below", C.c_double), ("stall_ratio", C.c_double), ("scaling", C.c_int32),
                 ("power_steps", C.c_int32), ("scale_margin", C.c_double), ("probes", C.c_int32),
-                ("variant", C.c_int32), ("graph_iters", C.c_int32), ("reserved", C.c_int32)]
+                ("variant", C.c_int32), ("graph_iters", C.c_int32), ("accel", C.c_int32),
+                ("lbound", C.c_double)]
 
     def copy(self) -> "SignOpts":
         o = SignOpts()
@@ -58,17 +59,17 @@ class SubStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("iters_low", C.c_int32), ("status", C.c_int32),
                 ("scale_src", C.c_int32), ("scale", C.c_double), ("res", C.c_double),
                 ("res_probe", C.c_double), ("gersh", C.c_double), ("rho_est", C.c_double),
-                ("feat", C.c_float * 16)]
+                ("lb0", C.c_double), ("lb_est", C.c_double), ("feat", C.c_float * 16)]
 
 
 STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"),
                         ("scale_src", "<i4"), ("scale", "<f8"), ("res", "<f8"),
                         ("res_probe", "<f8"), ("gersh", "<f8"), ("rho_est", "<f8"),
-                        ("feat", "<f4", (16,))])
-STATS_FEAT_OFFSET = 56   # bytes from the start of a record to feat[0]
-assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 120
+                        ("lb0", "<f8"), ("lb_est", "<f8"), ("feat", "<f4", (16,))])
+STATS_FEAT_OFFSET = 72   # bytes from the start of a record to feat[0]
+assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 136
 assert STATS_DTYPE.fields["feat"][1] == STATS_FEAT_OFFSET
-assert C.sizeof(SignOpts) == 80
+assert C.sizeof(SignOpts) == 88
 
 _lib = None
 
@@ -110,6 +111,7 @@ def lib() -> C.CDLL:
         "sm_plan_set_mlp": (i32, [vp, vp]),
         "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, i32, vp, vp, vp]),
         "sm_plan_tuning": (i32, [vp, vp, vp]),
+        "sm_ws_storage": (i32, [C.POINTER(SignOpts)]),
         "sm_last_error": (C.c_char_p, []),
         "sm_version": (C.c_char_p, []),
     }
@@ -155,11 +157,7 @@ def storage_prec(opts: SignOpts) -> int:
     """Workspace storage code of a schedule: SM_F64 / SM_F32 for the iterate's
     type, or the main precision (SM_BF16 / SM_F16 / SM_BF16X3) for float32
     iterates plus the 16-bit operand copies their products read."""
-    if opts.phase1 == SM_F64 or (opts.refine_steps > 0 and opts.refine == SM_F64):
-        return SM_F64
-    if opts.phase1 in (SM_BF16, SM_F16, SM_BF16X3):
-        return int(opts.phase1)
-    return SM_F32
+    return int(lib().sm_ws_storage(C.byref(opts)))
 
 
 def _check_ws(plan, ws, opts: SignOpts):

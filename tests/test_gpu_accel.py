@@ -1,0 +1,116 @@
+"""Scaled Newton-Schulz (opts.accel) on the GPU.
+
+* the lower bound on the smallest |eigenvalue| of X_0 that a plain run
+  derives from its residuals (stats.lb_est) is a true lower bound: checked
+  against the oracle's eigenvalues of every submatrix;
+* with that bound as l_0 the scaled iteration needs fewer updates and gives
+  the same P (float64: to 1e-10 of the plain run; split bf16: within the
+  precision target of the oracle);
+* a badly wrong l_0 (too large or too small) only costs iterations;
+* learned: the scaling network's second output trained on lb_est of earlier
+  trajectory steps supplies l_0 on later steps.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import submatrix as om
+from paper_2205_14741_amd import smsign as sm
+from gpu_helpers import gap_mu, rel, run_fixed_mu
+
+pytestmark = pytest.mark.gpu
+
+
+def _system():
+    m = synth.water_system(24, 1.4, 5)
+    return m, gap_mu(m)
+
+
+def test_lb_est_is_a_lower_bound(dev):
+    m, mu = _system()
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, "f64", pad_to=32)
+    view = om.BlockView(m)
+    have = 0
+    for i in range(m.n_atoms):
+        if st["lb_est"][i] <= 0:
+            continue
+        have += 1
+        lam = np.linalg.eigvalsh(om.submatrix(view, i, mu))
+        x_min = np.min(np.abs(lam)) / st["scale"][i]
+        assert st["lb_est"][i] <= x_min * (1 + 1e-6), (i, st["lb_est"][i], x_min)
+        assert st["lb_est"][i] > 0.3 * x_min        # and not a trivial one
+    assert have == m.n_atoms
+
+
+@pytest.mark.parametrize("prec,pad,dp_max", [("f64", 32, None), ("bf16x3", 64, 1e-4)])
+def test_scaled_ns_fewer_iterations_same_p(prec, pad, dp_max, dev):
+    m, mu = _system()
+    P0, E0, N0, st0, plan = run_fixed_mu(m, mu, prec, pad_to=pad)
+    # a plain float64 run supplies the bounds (relative to c_G)
+    _, _, _, stf, _ = run_fixed_mu(m, mu, "f64", pad_to=32)
+    lrel = float(np.min(stf["lb_est"] * stf["scale"] / stf["gersh"]))
+    P1, E1, N1, st1, _ = run_fixed_mu(m, mu, prec, plan=plan, accel=1, lbound=lrel)
+    print(f"{prec}: iterations plain {st0['iters'].mean():.2f} scaled {st1['iters'].mean():.2f} "
+          f"(l_0 {lrel:.4f}), max|P1-P0| {np.max(np.abs(P1 - P0)):.2e}")
+    assert np.all(st1["status"] >= 1)
+    assert st1["iters"].mean() < st0["iters"].mean() - 2.0
+    assert np.all(st1["lb0"] > 0)
+    if prec == "f64":
+        assert np.max(np.abs(P1 - P0)) < 1e-10 and rel(E1, E0) < 1e-12
+    else:
+        Po = om.density_matrix(m, mu)
+        assert np.max(np.abs(P1 - Po)) < dp_max
+        Eo, _ = om.energy_trace(m, Po)
+        assert rel(E1, Eo) < 1e-5
+
+
+@pytest.mark.parametrize("factor", [1e-3, 20.0])
+def test_scaled_ns_wrong_bound_is_safe(factor, dev):
+    """l_0 far too small (the scale then stays near its cap) or far too large
+    (eigenvalues below l_0 grow no slower than in the plain iteration): every
+    submatrix still converges to the same P."""
+    m, mu = _system()
+    P0, E0, N0, st0, plan = run_fixed_mu(m, mu, "f64", pad_to=32)
+    _, _, _, stf, _ = run_fixed_mu(m, mu, "f64", plan=plan)
+    lrel = float(np.median(stf["lb_est"] * stf["scale"] / stf["gersh"]))
+    P1, E1, N1, st1, _ = run_fixed_mu(m, mu, "f64", plan=plan, accel=1, lbound=min(lrel * factor, 1.0))
+    print(f"l_0 x {factor}: iterations {st1['iters'].mean():.2f} (plain {st0['iters'].mean():.2f})")
+    assert np.all(st1["status"] == 1)
+    assert np.max(np.abs(P1 - P0)) < 1e-10
+    assert st1["iters"].max() <= st0["iters"].max() + 3
+
+
+def test_learned_lower_bound_on_trajectory(dev):
+    """Both outputs of the scaling network trained on plain runs of steps 0-2
+    (power-iteration bounds and lb_est); on steps 5-6 the learned scale plus
+    scaled Newton-Schulz from the learned l_0 needs fewer updates than the
+    learned scale alone, with P unchanged to 1e-9."""
+    import torch
+    mu = -2.85
+    feats, ys = [], []
+    for t in (0, 1, 2):
+        m = synth.config5_step(t, n_mol=32, cutoff=1.5)
+        o = sm.default_opts("f64", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
+        _, _, _, st, _ = run_fixed_mu(m, mu, "f64", opts=o, pad_to=32)
+        ok = st["lb_est"] > 0
+        feats.append(st["feat"][ok])
+        ys.append(np.stack([np.log(st["rho_est"] / st["gersh"]),
+                            np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok])
+    X = torch.from_numpy(np.concatenate(feats).astype(np.float32)).cuda()
+    Y = torch.from_numpy(np.concatenate(ys).astype(np.float32)).cuda()
+    net = sm.Mlp(seed=3)
+    hist = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
+    assert hist[-1] < 0.1 * hist[0]
+    for t in (5, 6):
+        m = synth.config5_step(t, n_mol=32, cutoff=1.5)
+        plan = sm.Plan(m, 32)
+        sm.sm_plan_set_mlp(plan, net)
+        kw = dict(scaling=sm.SM_SCALE_LEARNED, power_steps=4, scale_margin=0.05)
+        Pl, El, _, stl, _ = run_fixed_mu(m, mu, "f64", plan=plan, **kw)
+        Pa, Ea, _, sta, _ = run_fixed_mu(m, mu, "f64", plan=plan, accel=1, **kw)
+        Pg, Eg, _, stg, _ = run_fixed_mu(m, mu, "f64", plan=plan)
+        print(f"step {t}: iterations Gershgorin {stg['iters'].mean():.2f}, learned scale "
+              f"{stl['iters'].mean():.2f}, + learned l_0 {sta['iters'].mean():.2f}")
+        assert np.mean(sta["scale_src"] == 2) > 0.7
+        assert sta["iters"].mean() < stl["iters"].mean() - 1.0
+        assert np.max(np.abs(Pa - Pg)) < 1e-9 and rel(Ea, Eg) < 1e-12

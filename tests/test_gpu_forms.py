@@ -92,7 +92,8 @@ def test_trajectory_learned_scaling(dev):
         o = sm.default_opts("f64", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
         _, _, _, st, _ = run_fixed_mu(m, MU5, "f64", opts=o, pad_to=32)
         feats.append(st["feat"])
-        ys.append(np.stack([np.log(st["rho_est"] / st["gersh"]), np.log(st["iters"] + 1.0)], 1))
+        ys.append(np.stack([np.log(st["rho_est"] / st["gersh"]),
+                            np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1))
     X = torch.from_numpy(np.concatenate(feats).astype(np.float32)).cuda()
     Y = torch.from_numpy(np.concatenate(ys).astype(np.float32)).cuda()
     net = sm.Mlp(seed=2)

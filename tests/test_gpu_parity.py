@@ -323,7 +323,7 @@ _X0_CACHE = {}
 @pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("prec,dp_max", [("f32", 1e-5), ("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)])
 def test_gemm_variants_parity(variant, prec, dp_max, dev):
-    """Every GEMM kernel variant (tile walk, prefetch depth, 128-wide tiles with
+    """Every GEMM kernel variant (tile walk, LDS stage depth, 128-wide tiles with
     half-filled edge tiles) against the oracle."""
     m = synth.water_system(24, 1.4, 5)
     mu = gap_mu(m)

@@ -1,0 +1,59 @@
+"""Host-side accounting used by the benchmark: wave blocks per product
+against a brute-force count, product counts per precision phase, byte
+counts, and the kernel names the launcher's variant fallback selects."""
+import numpy as np
+
+from paper_2205_14741_amd import metrics
+from paper_2205_14741_amd import smsign as sm
+
+
+def _brute_blocks(npad):
+    T = (npad + 63) // 64
+    c = 0
+    for bi in range(T):
+        for bj in range(bi + 1):
+            for wm in range(2):
+                for wn in range(2):
+                    if bi * 64 + wm * 32 < npad and bj * 64 + wn * 32 < npad and not (bi == bj and wm < wn):
+                        c += 1
+    return c
+
+
+def test_wave_blocks_brute_force():
+    npads = np.arange(32, 1025, 32)
+    assert np.array_equal(metrics.wave_blocks(npads), [_brute_blocks(int(x)) for x in npads])
+
+
+def _stats(iters, low, status):
+    st = np.zeros(len(iters), dtype=sm.STATS_DTYPE)
+    st["iters"], st["iters_low"], st["status"] = iters, low, status
+    return st
+
+
+def test_product_counts_refined_and_plain():
+    o = sm.default_opts("bf16x3")          # 2 float32 refinement steps
+    st = _stats([12, 10], [10, 10], [2, 1])
+    c = metrics.product_counts(st, o)
+    # refined: 11 squares + 10 updates in bf16x3, 1 square + 2 updates in f32
+    # plain (status 1): 11 squares + 10 updates in bf16x3
+    assert list(c[(sm.SM_BF16X3, 0)]) == [11, 11] and list(c[(sm.SM_BF16X3, 1)]) == [10, 10]
+    assert list(c[(sm.SM_F32, 0)]) == [1, 0] and list(c[(sm.SM_F32, 1)]) == [2, 0]
+
+
+def test_bytes_by_class():
+    o = sm.default_opts("f64")
+    st = _stats([3], [3], [1])
+    b = metrics.bytes_by_class(st, np.array([10]), o)
+    assert b[(sm.SM_F64, 0)] == 4 * 2 * 8 * 100   # 4 squares: read X, write Y
+    assert b[(sm.SM_F64, 1)] == 3 * 3 * 8 * 100   # 3 updates: read X, Y, write X'
+
+
+def test_kernel_symbols_follow_launcher_fallback():
+    assert metrics.gemm_kernel_symbol(4, 0, 1, 64) == "sm::ns_gemm_kernel<4, 0, 1, true>"
+    assert metrics.gemm_kernel_symbol(4, 1, 2, 64) == "sm::ns_gemm_kernel<4, 1, 2, true>"
+    assert metrics.gemm_kernel_symbol(4, 1, 3, 64) == "sm::ns_gemm128_kernel<4, 1, true>"
+    assert metrics.gemm_kernel_symbol(1, 0, 4, 64) == "sm::ns_gemm128_kernel<1, 0, false>"
+    # no 128-wide tiles in float64 or on a plan padded to 32
+    assert metrics.gemm_kernel_symbol(0, 0, 3, 64) == "sm::ns_gemm_kernel<0, 0, 1, true>"
+    assert metrics.gemm_kernel_symbol(1, 0, 3, 32) == "sm::ns_gemm_kernel<1, 0, 1, true>"
+    assert metrics.gemm_kernel_symbol(0, 1, 0, 32) == "sm::ns_gemm_kernel<0, 1, 1, false>"
