@@ -323,11 +323,13 @@ int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
 int sm_plan_tuning(sm_plan* plan, int32_t* get, const int32_t* set);
 
 /* Kernel timing for measurement.  While enabled, every Newton-Schulz GEMM
- * launch made by submatrix_sign is bracketed by a pair of HIP events recorded
- * on the caller's stream.  sm_profile_read synchronises on the recorded
+ * launch made by submatrix_sign carries a pair of HIP events that the dispatch
+ * itself records (start and end of that kernel on the caller's stream; no
+ * extra stream packets).  Graph capture is off meanwhile (opts.graph_iters is
+ * ignored).  sm_profile_read synchronises on the recorded
  * events, adds up their elapsed times per kernel class, and clears them:
  * class = 2 * precision + kind (precision = sm_prec, kind 0 = square
- * A = X^2 / Y = 3I - A, kind 1 = update X' = 1/2 X Y), 10 classes.
+ * A = X^2 / Y = 3I - a^2 A, kind 1 = update X' = 1/2 a X Y), 10 classes.
  *   launches[10], ms[10]   host outputs (either may be NULL). */
 int sm_profile_enable(sm_plan* plan, int32_t on);
 int sm_profile_read(sm_plan* plan, int64_t* launches, double* ms);

@@ -90,21 +90,19 @@ int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_
   // persistent grid: all resident workgroups, a multiple of the 8 XCDs
   int grid = std::min(max_tiles, p->num_cu * ns_gemm_blocks_per_cu(mode, which, v));
   grid = std::max(8, grid / 8 * 8);
-  size_t k = 0;
-  if (p->profiling) {
-    k = p->prof_cls.size();
-    while (p->prof_ev.size() < 2 * (k + 1)) {
-      hipEvent_t e;
-      SM_HIP(hipEventCreate(&e));
-      p->prof_ev.push_back(e);
-    }
-    SM_HIP(hipEventRecord(p->prof_ev[2 * k], s));
+  if (!p->profiling) {
+    SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, shadow_kind, cnt, recs, partials, grid, s));
+    return SM_OK;
   }
-  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, shadow_kind, cnt, recs, partials, grid, s));
-  if (p->profiling) {
-    SM_HIP(hipEventRecord(p->prof_ev[2 * k + 1], s));
-    p->prof_cls.push_back(2 * mode + which);
+  const size_t k = p->prof_cls.size();
+  while (p->prof_ev.size() < 2 * (k + 1)) {
+    hipEvent_t e;
+    SM_HIP(hipEventCreate(&e));
+    p->prof_ev.push_back(e);
   }
+  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, shadow_kind, cnt, recs, partials, grid, s,
+                        p->prof_ev[2 * k], p->prof_ev[2 * k + 1]));
+  p->prof_cls.push_back(2 * mode + which);
   return SM_OK;
 }
 
@@ -157,7 +155,7 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   int g0, nsub;
   if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
   if ((rc = ensure_device(p))) return rc;
-  const size_t lds = (size_t)(2 * p->max_m + p->max_npad) * sizeof(int);
+  const size_t lds = (size_t)(2 * p->max_m + 4 * p->max_npad) * sizeof(int);   // gather: 4 row maps
   if (lds > 64 * 1024)
     return set_error(SM_ERR_ARG, "build_submatrices: index set too large for the gather (needs %zu B of LDS)", lds);
   const int storage = ws_storage(o);

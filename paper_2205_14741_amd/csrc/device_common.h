@@ -50,6 +50,57 @@ __device__ __forceinline__ double block_reduce(double v, double* red) {
   return r;
 }
 
+// Block matrix-vector products y_q = A v_q (q < Q) in float64 for a column-major
+// n x n matrix A with leading dimension lda: lanes take 64 consecutive rows
+// (coalesced column reads), the block's waves split the columns (wave w: c = w,
+// w + nw, ...), four columns in flight per thread; the wave partial sums are
+// combined through LDS in wave order, so the result is deterministic.
+// v_q = v[q * vs + c].  For every row r < n, out(q, r, y_q[r]) is called by a
+// thread of wave 0.  red: LDS scratch of (blockDim / 64) * 64 * Q doubles.
+template <int Q, typename T, typename Out>
+__device__ __forceinline__ void block_matvec(const T* __restrict__ A, int64_t lda, int n,
+                                             const double* __restrict__ v, int vs, double* red,
+                                             Out out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int r0 = 0; r0 < n; r0 += kWave) {
+    const int r = r0 + lane;
+    double acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+    if (r < n) {
+      int c = w;
+      for (; c + 3 * nw < n; c += 4 * nw) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = (double)A[(int64_t)(c + u * nw) * lda + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < Q; ++q) acc[q] += x[u] * v[q * vs + c + u * nw];
+      }
+      for (; c < n; c += nw) {
+        const double x = (double)A[(int64_t)c * lda + r];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc[q] += x * v[q * vs + c];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) red[(w * Q + q) * kWave + lane] = acc[q];
+    __syncthreads();
+    if (w == 0 && r < n) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        double s = 0.0;
+        for (int k = 0; k < nw; ++k) s += red[(k * Q + q) * kWave + lane];
+        out(q, r, s);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // float -> bfloat16 bits, round to nearest even: a plain conversion, which
 // gfx950 executes as v_cvt_pk_bf16_f32.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {

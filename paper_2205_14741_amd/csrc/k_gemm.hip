@@ -7,6 +7,7 @@
 // its transpose), which halves the MFMA work and keeps every iterate exactly
 // symmetric.  A device scheduler (one workgroup) retires converged
 // submatrices and builds the tile lists of the next launches.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -760,57 +761,70 @@ static void* kernel_ptr() {
   return reinterpret_cast<void*>(&ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::KDIV, Var<MODE, WHICH, V>::XCD>);
 }
 
+// Grid, stream and optional timing events of one GEMM launch.  With events,
+// the launch carries them (start / stop timestamps taken by the dispatch
+// itself), so timing adds no separate packets to the stream.
+struct Launch {
+  int grid;
+  hipStream_t s;
+  hipEvent_t e0, e1;
+  template <typename K, typename... A>
+  hipError_t go(K kernel, A... args) const {
+    if (e0)
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, args...);
+    else
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, args...);
+    return hipGetLastError();
+  }
+};
+
 template <int MODE, int WHICH, int V>
 static hipError_t launch_one(void* mats, int64_t so, int sk, const int32_t* count, const TileRec* recs,
-                             double* partials, int grid, hipStream_t s) {
+                             double* partials, const Launch& L) {
   using S = typename Traits<MODE>::S;
-  hipLaunchKernelGGL((ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::KDIV, Var<MODE, WHICH, V>::XCD>),
-                     dim3(grid), dim3(kBlock), 0, s, (S*)mats, so, sk, count, recs, partials);
-  return hipGetLastError();
+  return L.go(ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::KDIV, Var<MODE, WHICH, V>::XCD>, (S*)mats, so,
+              sk, count, recs, partials);
 }
 
 template <int MODE, int WHICH>
 static hipError_t launch_which(int variant, void* mats, int64_t so, int sk, const int32_t* count,
-                               const TileRec* recs, double* partials, int grid, hipStream_t s) {
+                               const TileRec* recs, double* partials, const Launch& L) {
   switch (variant) {
-    case 1: return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, grid, s);
-    case 2: return launch_one<MODE, WHICH, 2>(mats, so, sk, count, recs, partials, grid, s);
+    case 1: return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, L);
+    case 2: return launch_one<MODE, WHICH, 2>(mats, so, sk, count, recs, partials, L);
     case 3:
     case 4:
       if constexpr (MODE != SM_F64) {
         if (variant == 3)
-          hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH, true>), dim3(grid), dim3(kBlock), 0, s,
-                             (float*)mats, so, sk, count, recs, partials);
-        else
-          hipLaunchKernelGGL((ns_gemm128_kernel<MODE, WHICH, false>), dim3(grid), dim3(kBlock), 0, s,
-                             (float*)mats, so, sk, count, recs, partials);
-        return hipGetLastError();
+          return L.go(ns_gemm128_kernel<MODE, WHICH, true>, (float*)mats, so, sk, count, recs, partials);
+        return L.go(ns_gemm128_kernel<MODE, WHICH, false>, (float*)mats, so, sk, count, recs, partials);
       } else {
-        return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, grid, s);
+        return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, L);
       }
-    default: return launch_one<MODE, WHICH, 0>(mats, so, sk, count, recs, partials, grid, s);
+    default: return launch_one<MODE, WHICH, 0>(mats, so, sk, count, recs, partials, L);
   }
 }
 
 template <int MODE>
 static hipError_t launch_mode(int which, int variant, void* mats, int64_t so, int sk, const int32_t* count,
-                              const TileRec* recs, double* partials, int grid, hipStream_t s) {
-  return which == 0 ? launch_which<MODE, 0>(variant, mats, so, sk, count, recs, partials, grid, s)
-                    : launch_which<MODE, 1>(variant, mats, so, sk, count, recs, partials, grid, s);
+                              const TileRec* recs, double* partials, const Launch& L) {
+  return which == 0 ? launch_which<MODE, 0>(variant, mats, so, sk, count, recs, partials, L)
+                    : launch_which<MODE, 1>(variant, mats, so, sk, count, recs, partials, L);
 }
 
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t so, int sk,
                           const int32_t* count, const TileRec* recs, double* partials, int grid,
-                          hipStream_t s) {
+                          hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   // the bf16 / f16 / split-bf16 products, and float32 ones that may read
   // copies, need the copy region
   if ((mode >= SM_BF16 || sk != 0) && so <= 0) return hipErrorInvalidValue;
+  const Launch L{grid, s, ev_start, ev_stop};
   switch (mode) {
-    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, 0, 0, count, recs, partials, grid, s);
-    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, so, sk, count, recs, partials, grid, s);
-    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, so, 0, count, recs, partials, grid, s);
-    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, so, 0, count, recs, partials, grid, s);
-    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, so, 0, count, recs, partials, grid, s);
+    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, 0, 0, count, recs, partials, L);
+    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, so, sk, count, recs, partials, L);
+    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, so, 0, count, recs, partials, L);
+    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, so, 0, count, recs, partials, L);
+    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, so, 0, count, recs, partials, L);
   }
   return hipErrorInvalidValue;
 }

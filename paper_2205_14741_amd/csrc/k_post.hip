@@ -44,16 +44,16 @@ hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, c
 
 // One workgroup per submatrix: copy the per-submatrix iteration record into
 // `stats` and, with P > 0 probes, estimate max_v ||X (X v) - v|| / ||v|| in
-// float64 for fixed +-1 vectors v (a residual of sign(T)^2 = I, Eq. 13).
-// Thread r owns row r: (X v)_r = sum_c X[r][c] v_c reads X column-major
-// with consecutive threads on consecutive rows (coalesced), every probe in
-// the same pass, and no cross-lane reductions.  Two passes over X in all.
+// float64 for fixed +-1 vectors v (a residual of sign(T)^2 = I, Eq. 13):
+// two block matrix-vector passes over X, every probe in the same pass.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void finish_kernel(DevPlan p, int g0, const T* __restrict__ mats,
+__global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T* __restrict__ mats,
                                                      const SubState* __restrict__ st,
                                                      double* __restrict__ vecs,
                                                      sm_sub_stats* __restrict__ stats) {
-  __shared__ double red[4];
+  constexpr int Q = P > 0 ? P : 1;
+  __shared__ double red[8 * kWave * Q];
+  __shared__ double red2[8];
   const int l = blockIdx.x;
   const int g = g0 + l;
   const int i = p.order_g[g];
@@ -68,40 +68,17 @@ __global__ __launch_bounds__(256) void finish_kernel(DevPlan p, int g0, const T*
 #pragma unroll
       for (int q = 0; q < P; ++q) v[q * npad + d] = probe_entry(q, d);
     __syncthreads();
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-      double acc[P];
-#pragma unroll
-      for (int q = 0; q < P; ++q) acc[q] = 0.0;
-      for (int c = 0; c < n; ++c) {
-        const double x = (double)X[(int64_t)c * npad + r];
-#pragma unroll
-        for (int q = 0; q < P; ++q) acc[q] += x * v[q * npad + c];
-      }
-#pragma unroll
-      for (int q = 0; q < P; ++q) w[q * npad + r] = acc[q];
-    }
-    __syncthreads();
+    block_matvec<P>(X, npad, n, v, npad, red, [&](int q, int r, double y) { w[q * npad + r] = y; });
     double e[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) e[q] = 0.0;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-      double acc[P];
-#pragma unroll
-      for (int q = 0; q < P; ++q) acc[q] = 0.0;
-      for (int c = 0; c < n; ++c) {
-        const double x = (double)X[(int64_t)c * npad + r];
-#pragma unroll
-        for (int q = 0; q < P; ++q) acc[q] += x * w[q * npad + c];
-      }
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const double t = acc[q] - v[q * npad + r];
-        e[q] += t * t;
-      }
-    }
+    block_matvec<P>(X, npad, n, w, npad, red, [&](int q, int r, double y) {
+      const double t = y - v[q * npad + r];
+      e[q] += t * t;
+    });
     worst = 0.0;
 #pragma unroll
-    for (int q = 0; q < P; ++q) worst = fmax(worst, sqrt(block_reduce<0>(e[q], red) / (double)n));
+    for (int q = 0; q < P; ++q) worst = fmax(worst, sqrt(block_reduce<0>(e[q], red2) / (double)n));
   }
   if (threadIdx.x == 0) {
     const SubState s = st[l];
@@ -120,7 +97,7 @@ static hipError_t launch_finish_t(const DevPlan& p, int g0, int nsub, const T* m
                                   int probes, double* vecs, sm_sub_stats* stats, hipStream_t s) {
 #define SM_FINISH(PR)                                                                                 \
   case PR:                                                                                            \
-    hipLaunchKernelGGL((finish_kernel<T, PR>), dim3(nsub), dim3(256), 0, s, p, g0, mats, st, vecs, stats); \
+    hipLaunchKernelGGL((finish_kernel<T, PR>), dim3(nsub), dim3(512), 0, s, p, g0, mats, st, vecs, stats); \
     break;
   switch (probes) {
     SM_FINISH(0) SM_FINISH(1) SM_FINISH(2) SM_FINISH(3) SM_FINISH(4) SM_FINISH(5) SM_FINISH(6)

@@ -11,15 +11,23 @@
 
 namespace sm {
 
-// One workgroup per submatrix.  For every atom j of the index set I_i (one block
-// column of T_i at a time) the workgroup
+// One workgroup per submatrix; its waves take the atoms j of the index set I_i
+// in turn (wave w: atoms w, w + nw, ...), each wave independently:
 //   (a) intersects the stored pattern of H's block column j with I_i by binary
-//       search in LDS and records, for every destination row of T_i, which
-//       panel row of column j supplies it (-1: block not stored -> zero);
+//       search in LDS and records, in its own LDS row map, which panel row of
+//       column j supplies every destination row of T_i (-1: block not stored);
 //   (b) writes the b_j columns of T_i top to bottom (coalesced stores; reads
 //       are runs of one contiguous panel column), subtracting mu on the
-//       diagonal, and zero / identity in the padding.
-// LDS: atoms of I_i, their row offsets, and the row map (2 m + n_pad ints).
+//       diagonal, and zeros in the padding rows.
+// Only wave-level ordering is needed between (a) and (b), so the waves never
+// wait for each other.  Then the identity padding columns.
+// LDS: atoms of I_i and their row offsets (2 m ints), one row map of n_pad
+// ints per wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
                                                      double mu, T* __restrict__ mats, int* nonfinite) {
@@ -30,9 +38,12 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
   const int n = p.height[i];
   const int64_t k0 = p.col_ptr[i];
   const int m = (int)(p.col_ptr[i + 1] - k0);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
   int* s_atom = smem;
   int* s_off = smem + m;
-  int* s_src = smem + 2 * m;
+  int* s_src = smem + 2 * m + wid * npad;
   T* X = mats + p.mat_off_g[g];
   for (int t = threadIdx.x; t < m; t += blockDim.x) {
     s_atom[t] = p.row_idx[k0 + t];
@@ -40,16 +51,16 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
   }
   __syncthreads();
   bool bad = false;
-  for (int jj = 0; jj < m; ++jj) {
+  for (int jj = wid; jj < m; jj += nw) {
     const int j = s_atom[jj];
     const int locj = s_off[jj];
     const int bj = p.bs[j];
     const int hj = p.height[j];
     const int64_t kj0 = p.col_ptr[j];
     const int mj = (int)(p.col_ptr[j + 1] - kj0);
-    for (int d = threadIdx.x; d < n; d += blockDim.x) s_src[d] = -1;
-    __syncthreads();
-    for (int t = threadIdx.x; t < mj; t += blockDim.x) {
+    for (int d = lane; d < n; d += kWave) s_src[d] = -1;
+    wave_sync();
+    for (int t = lane; t < mj; t += kWave) {
       const int k = p.row_idx[kj0 + t];
       int lo = 0, hi = m;
       while (lo < hi) {
@@ -63,29 +74,28 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
         for (int q = 0; q < bk; ++q) s_src[dst + q] = src + q;
       }
     }
-    __syncthreads();
+    wave_sync();
     const double* panel = H + p.panel_off[j];
-    const int total = bj * npad;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int q = e / npad;
-      const int d = e - q * npad;
-      double v = 0.0;
-      if (d < n) {
-        const int s = s_src[d];
-        if (s >= 0) v = panel[(int64_t)q * hj + s];
-        if (d == locj + q) v -= mu;
+    for (int q = 0; q < bj; ++q) {
+      const double* pc = panel + (int64_t)q * hj;
+      T* xc = X + (int64_t)(locj + q) * npad;
+      for (int d = lane; d < npad; d += kWave) {
+        double v = 0.0;
+        if (d < n) {
+          const int s = s_src[d];
+          if (s >= 0) v = pc[s];
+          if (d == locj + q) v -= mu;
+        }
+        bad |= !isfinite(v);
+        xc[d] = (T)v;
       }
-      bad |= !isfinite(v);
-      X[(int64_t)(locj + q) * npad + d] = (T)v;
     }
-    __syncthreads();
+    wave_sync();   // the row map is rebuilt for the wave's next atom
   }
   // identity padding: X stays exactly I on the pad under the iteration
-  const int64_t padcols = (int64_t)(npad - n) * npad;
-  for (int64_t e = threadIdx.x; e < padcols; e += blockDim.x) {
-    const int c = n + (int)(e / npad);
-    const int d = (int)(e - (int64_t)(c - n) * npad);
-    X[(int64_t)c * npad + d] = (T)(d == c ? 1.0 : 0.0);
+  for (int c = n + wid; c < npad; c += nw) {
+    T* xc = X + (int64_t)c * npad;
+    for (int d = lane; d < npad; d += kWave) xc[d] = (T)(d == c ? 1.0 : 0.0);
   }
   if (bad) *nonfinite = 1 + i;
 }
@@ -94,7 +104,7 @@ hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_
                          const double* H, double mu, void* mats, int storage_f64,
                          int* nonfinite, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * max_m + max_npad) * sizeof(int);
+  const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);   // 4 waves
   if (storage_f64)
     hipLaunchKernelGGL(gather_kernel<double>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
                        (double*)mats, nonfinite);
@@ -104,9 +114,9 @@ hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_
   return hipGetLastError();
 }
 
-// One workgroup (8 waves) per submatrix, after the gather: column abs sums
-// (= row sums, T is symmetric) give the Gershgorin bound c_G >= rho(T) and,
-// with the diagonal, the 16 features of the scaling network.
+// One workgroup (8 waves) per submatrix, after the gather: row abs sums
+// (T is symmetric) give the Gershgorin bound c_G >= rho(T) and, with the
+// diagonal, the 16 features of the scaling network.
 template <typename T>
 __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, const T* __restrict__ mats,
                                                       float* __restrict__ features,
@@ -125,52 +135,67 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, const T
   const int wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
 
+  __shared__ double part[2][8 * kWave];
   double cmax = 0.0, sdiag = 0.0, sdiag2 = 0.0, mind = 1e300, maxd = -1e300, sR = 0.0, maxR = 0.0;
   double minabs = 1e300, mingap = 1e300, nneg = 0.0, ssq = 0.0, sown = 0.0, minown = 1e300, sabs = 0.0;
-  for (int c = wid; c < n; c += nw) {
-    const T* col = X + (int64_t)c * npad;
+  // abs sum and sum of squares of row r (= column r, T is symmetric): lanes
+  // take 64 consecutive rows (coalesced column reads), waves split the
+  // columns, partial sums combined in wave order
+  for (int r0 = 0; r0 < n; r0 += kWave) {
+    const int r = r0 + lane;
     double s = 0.0, q = 0.0;
-    for (int d = lane; d < n; d += kWave) {
-      const double v = (double)col[d];
-      s += fabs(v);
-      q += v * v;
+    if (r < n)
+      for (int c = wid; c < n; c += nw) {
+        const double v = (double)X[(int64_t)c * npad + r];
+        s += fabs(v);
+        q += v * v;
+      }
+    part[0][wid * kWave + lane] = s;
+    part[1][wid * kWave + lane] = q;
+    __syncthreads();
+    if (wid == 0 && r < n) {
+      s = 0.0;
+      q = 0.0;
+      for (int k = 0; k < nw; ++k) {
+        s += part[0][k * kWave + lane];
+        q += part[1][k * kWave + lane];
+      }
+      const double dg = (double)X[(int64_t)r * npad + r];
+      const double R = s - fabs(dg);
+      cmax = fmax(cmax, s);
+      sdiag += dg;
+      sdiag2 += dg * dg;
+      mind = fmin(mind, dg);
+      maxd = fmax(maxd, dg);
+      sR += R;
+      maxR = fmax(maxR, R);
+      minabs = fmin(minabs, fabs(dg));
+      mingap = fmin(mingap, fabs(dg) - R);
+      nneg += dg < 0.0 ? 1.0 : 0.0;
+      ssq += q;
+      sabs += fabs(dg);
+      if (r >= loc && r < loc + b) {
+        sown += dg;
+        minown = fmin(minown, fabs(dg));
+      }
     }
-    s = wave_sum(s);
-    q = wave_sum(q);
-    const double dg = (double)col[c];
-    const double R = s - fabs(dg);
-    cmax = fmax(cmax, s);
-    sdiag += dg;
-    sdiag2 += dg * dg;
-    mind = fmin(mind, dg);
-    maxd = fmax(maxd, dg);
-    sR += R;
-    maxR = fmax(maxR, R);
-    minabs = fmin(minabs, fabs(dg));
-    mingap = fmin(mingap, fabs(dg) - R);
-    nneg += dg < 0.0 ? 1.0 : 0.0;
-    ssq += q;
-    sabs += fabs(dg);
-    if (c >= loc && c < loc + b) {
-      sown += dg;
-      minown = fmin(minown, fabs(dg));
-    }
+    __syncthreads();
   }
-  // every lane of a wave holds the same values; reduce across waves
-  cmax = block_reduce<1>(lane == 0 ? cmax : 0.0, red);
-  sdiag = block_reduce<0>(lane == 0 ? sdiag : 0.0, red);
-  sdiag2 = block_reduce<0>(lane == 0 ? sdiag2 : 0.0, red);
-  mind = block_reduce<2>(lane == 0 ? mind : 1e300, red);
-  maxd = block_reduce<1>(lane == 0 ? maxd : -1e300, red);
-  sR = block_reduce<0>(lane == 0 ? sR : 0.0, red);
-  maxR = block_reduce<1>(lane == 0 ? maxR : 0.0, red);
-  minabs = block_reduce<2>(lane == 0 ? minabs : 1e300, red);
-  mingap = block_reduce<2>(lane == 0 ? mingap : 1e300, red);
-  nneg = block_reduce<0>(lane == 0 ? nneg : 0.0, red);
-  ssq = block_reduce<0>(lane == 0 ? ssq : 0.0, red);
-  sown = block_reduce<0>(lane == 0 ? sown : 0.0, red);
-  minown = block_reduce<2>(lane == 0 ? minown : 1e300, red);
-  sabs = block_reduce<0>(lane == 0 ? sabs : 0.0, red);
+  // the row statistics sit in the lanes of wave 0 (neutral values elsewhere)
+  cmax = block_reduce<1>(cmax, red);
+  sdiag = block_reduce<0>(sdiag, red);
+  sdiag2 = block_reduce<0>(sdiag2, red);
+  mind = block_reduce<2>(mind, red);
+  maxd = block_reduce<1>(maxd, red);
+  sR = block_reduce<0>(sR, red);
+  maxR = block_reduce<1>(maxR, red);
+  minabs = block_reduce<2>(minabs, red);
+  mingap = block_reduce<2>(mingap, red);
+  nneg = block_reduce<0>(nneg, red);
+  ssq = block_reduce<0>(ssq, red);
+  sown = block_reduce<0>(sown, red);
+  minown = block_reduce<2>(minown, red);
+  sabs = block_reduce<0>(sabs, red);
   if (threadIdx.x == 0) {
     const double cG = cmax > 0.0 ? cmax : 1.0;
     const double nn = (double)n;
@@ -219,6 +244,7 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     double* __restrict__ lb0_out,
                                                     double* __restrict__ top0_out) {
   __shared__ double red[16];
+  __shared__ double mv[8 * kWave];
   const int l = blockIdx.x;
   const int g = g0 + l;
   const int i = p.order_g[g];
@@ -245,13 +271,7 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] *= inv;
     __syncthreads();
     for (int it = 0; it < power_steps; ++it) {
-      // w = T v, thread r owning row r (coalesced column-major reads)
-      for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += (double)X[(int64_t)c * npad + r] * v[c];
-        w[r] = s;
-      }
-      __syncthreads();
+      block_matvec<1>(X, npad, n, v, 0, mv, [&](int, int r, double y) { w[r] = y; });   // w = T v
       double nw2 = 0.0;
       for (int d = threadIdx.x; d < n; d += blockDim.x) nw2 += w[d] * w[d];
       nw2 = block_reduce<0>(nw2, red);

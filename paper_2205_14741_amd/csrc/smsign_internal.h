@@ -121,9 +121,11 @@ __host__ __device__ inline int tile_shift(int variant, int mode) { return (varia
 // products read them and also write them for their outputs); 0 otherwise
 // shadow_kind: the main precision whose copies a float32 refinement product
 // reads for kTileFromShadow tiles (0: none)
+// ev_start / ev_stop (may be null): events the launch itself records.
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t shadow_off,
                           int shadow_kind, const int32_t* count, const TileRec* recs,
-                          double* partials, int grid, hipStream_t s);
+                          double* partials, int grid, hipStream_t s, hipEvent_t ev_start = nullptr,
+                          hipEvent_t ev_stop = nullptr);
 // Float32 values of the final X from its 16-bit copies, for submatrices whose
 // iteration ended in a low-precision main phase (status != 2).
 hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,
