@@ -100,6 +100,33 @@ def train_scaling_net(sm, synth, dev, seed):
                  "loss_last": float(hist[-1])}
 
 
+def train_scaling_net_water(sm, synth, dev, seed, mu):
+    """The scaling network for the water-like systems, trained on a smaller
+    system of the same family (343 molecules: the same density and cutoff, so
+    submatrices of the same size) at the same mu: power-iteration estimates
+    (rho_est) and the lower bounds of plain split-bf16 runs (lb_est)."""
+    import torch
+    m = synth.water_system(343, 3.0, seed)
+    plan = sm.Plan(m, 64)
+    H = torch.from_numpy(m.vals).to(dev)
+    o = sm.default_opts("bf16x3", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
+    work = sm.Workspace(plan, sm.storage_prec(o), dev)
+    sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
+    st = work.stats_host()
+    ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
+    X = torch.from_numpy(np.ascontiguousarray(st["feat"][ok]).astype(np.float32)).to(dev)
+    Y = torch.from_numpy(np.stack([np.log(st["rho_est"] / st["gersh"]),
+                                   np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok]
+                         .astype(np.float32)).to(dev)
+    net = sm.Mlp(seed=seed)
+    hist = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
+    print(f"# scaling network: {int(ok.sum())} samples (343-molecule system, seed {seed}), "
+          f"loss {hist[0]:.3g} -> {hist[-1]:.3g}", file=sys.stderr, flush=True)
+    del work
+    return net, {"train_system": "water343, cutoff 3.0", "train_seed": seed, "samples": int(ok.sum()),
+                 "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
+
+
 def cpu_baseline(m, mu, target_s):
     """The oracle as it stands, on a bounded sample of the same workload:
     the submatrix P columns of the first k atoms, k sized to ~target_s."""
@@ -157,10 +184,13 @@ def precision_form(a):
         sel[m.panel_off[i]:m.panel_off[i + 1]] = True
     E_or = float(np.sum(Po[sel] * m.vals[sel]))
     res = {}
-    for mode in [x for x in a.modes.split(",") if x and x != "f64"]:
-        o = sm.default_opts(MODES[mode], graph_iters=a.graph)
-        if a.scaling == "power":
-            o.scaling, o.power_steps = sm.SM_SCALE_POWER, 8
+    modes3 = [x for x in a.modes.split(",") if x and x != "f64"]
+    net_info = None
+    if any(x.endswith("+L") for x in modes3):
+        net, net_info = train_scaling_net_water(sm, synth, dev, a.seed + 1, mu)
+        sm.sm_plan_set_mlp(plan, net)
+    for mode in modes3:
+        o = mode_opts(sm, mode, a)
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
         print(f"# {mode}: autotuning on chunk 0 ...", file=sys.stderr, flush=True)
         best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4))
@@ -186,6 +216,7 @@ def precision_form(a):
              "gemm_variant": int(best), "autotune_sign_ms": [float(x) for x in tune_ms],
              "iters": [int(st["iters"].min()), int(st["iters"].max())], "iters_mean": float(st["iters"].mean()),
              "max_dP_sampled": dP, "rel_dE_sampled": dEs, "E": E, "Ne": Ne,
+             "learned_accepted": float(np.mean(st["scale_src"] == 2)) if o.scaling == sm.SM_SCALE_LEARNED else None,
              "status_ok": bool(np.all(st["status"] >= 1)),
              "kernel": {"name": metrics.gemm_kernel_symbol(key[0], key[1], int(sm.sm_plan_tuning(plan)[key[0]]), 64),
                         "launches": int(launches[cls]), "avg_ms": float(ms[cls] / max(launches[cls], 1)),
@@ -210,7 +241,8 @@ def precision_form(a):
                                   "cutoff 3.0, 3000 submatrices n=%d..%d, fixed mu" % (n.min(), n.max()),
                       "mode": head, "seed": a.seed, "chunks": plan.n_chunks},
            "useful_tflops": res[head]["useful_tflops"], "modes": res,
-           "oracle_sample": {"atoms": atoms, "seconds": t_or, "gap_around_mu": [gap_lo, gap_hi], "mu": mu}}
+           "oracle_sample": {"atoms": atoms, "seconds": t_or, "gap_around_mu": [gap_lo, gap_hi], "mu": mu},
+           "scaling_network": net_info}
     print(json.dumps(out), flush=True)
 
 

@@ -233,6 +233,32 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
     }
 }
 
+// Operand sources of a tile (rows of X for the tile's rows, rows of R = X or
+// Y for its columns; by symmetry these are the columns the product needs).
+// TE: tile edge.  Rows past n_pad load as zeros.
+template <int MODE> struct TileSrc {
+  Operand<MODE> a, b;
+  bool va, vb;
+};
+
+template <int MODE, int WHICH, int TE>
+__device__ __forceinline__ TileSrc<MODE> tile_src(const TileRec& rec, typename Traits<MODE>::S* mats,
+                                                  int64_t shadow_off, int shadow_kind, int lrow, int lpart) {
+  using S = typename Traits<MODE>::S;
+  const int npad = rec.npad;
+  const int64_t nn = (int64_t)npad * npad;
+  const S* base = mats + rec.mat_off;
+  const S* Xp = base + (int64_t)((WHICH == 0 ? rec.it : rec.it + 1) & 1) * nn;
+  const S* Rp = WHICH == 0 ? Xp : base + 2 * nn;
+  const int r0 = (rec.bibj >> 16) * TE, c0 = (rec.bibj & 0xFFFF) * TE;
+  const bool va = (r0 + lrow) < npad;
+  const bool vb = (c0 + lrow) < npad;
+  const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
+  return TileSrc<MODE>{Operand<MODE>(Xp, shadow_off, (int64_t)(va ? r0 + lrow : 0) * npad + lpart, nn, fk),
+                       Operand<MODE>(Rp, shadow_off, (int64_t)(vb ? c0 + lrow : 0) * npad + lpart, nn, fk),
+                       va, vb};
+}
+
 __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
   int r = (int)((sqrtf(8.0f * (float)lt + 1.0f) - 1.0f) * 0.5f);
   while (r * (r + 1) / 2 > lt) --r;
@@ -292,42 +318,34 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     t_begin = (int)((int64_t)total * x / kXcds) + (int)blockIdx.x / kXcds;
     t_end = (int)((int64_t)total * (x + 1) / kXcds);
   }
+  // Operand registers carry over from tile to tile: during the last stage of
+  // a tile the first stage of the workgroup's next tile is loaded, so a tile
+  // starts without waiting for memory.
+  RT ra[RN], rb[RN];
   TileRec nxt;
-  if (t_begin < t_end) nxt = recs[t_begin];
+  if (t_begin < t_end) {
+    nxt = recs[t_begin];
+    const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+    s0.a.template load<K, NL>(ra, 0, s0.va);
+    s0.b.template load<K, NL>(rb, 0, s0.vb);
+  }
   for (int t = t_begin; t < t_end; t += t_step) {
     const TileRec rec = nxt;
-    if (t + t_step < t_end) nxt = recs[t + t_step];   // prefetch the next tile's record
+    const bool has_next = t + t_step < t_end;
+    if (has_next) nxt = recs[t + t_step];   // the next tile's record, used at the last stage
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
     S* base = mats + rec.mat_off;
-    const int it = rec.it;
-    const S* Xp;
-    const S* Rp;
-    S* Out;
-    if (WHICH == 0) {
-      Xp = base + (int64_t)(it & 1) * nn;
-      Rp = Xp;
-      Out = base + 2 * nn;
-    } else {
-      Xp = base + (int64_t)((it + 1) & 1) * nn;
-      Rp = base + 2 * nn;
-      Out = base + (int64_t)(it & 1) * nn;
-    }
+    S* Out = base + (WHICH == 0 ? 2 * nn : (int64_t)(rec.it & 1) * nn);
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
     const int r0 = bi * 64, c0 = bj * 64;
     // the last tile row / column may reach past n_pad (a multiple of 32): its
-    // operand rows load as zeros and the wave blocks there are skipped
-    const bool va = (r0 + lrow) < npad;
-    const bool vb = (c0 + lrow) < npad;
-    // wave blocks past n_pad, and the block of a diagonal tile that lies
-    // wholly above the diagonal, compute nothing
+    // operand rows load as zeros and the wave blocks there are skipped;
+    // the block of a diagonal tile that lies wholly above the diagonal
+    // computes nothing either
     const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && !(bi == bj && wm < wn);
-    const int64_t oa = (int64_t)(va ? r0 + lrow : 0) * npad + lpart;
-    const int64_t ob = (int64_t)(vb ? c0 + lrow : 0) * npad + lpart;
-    const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
-    const Operand<MODE> opa(Xp, shadow_off, oa, nn, fk);
-    const Operand<MODE> opb(Rp, shadow_off, ob, nn, fk);
+    const TileSrc<MODE> src = tile_src<MODE, WHICH, 64>(rec, mats, shadow_off, shadow_kind, lrow, lpart);
 
     typename Tr::Acc acc[2][2];
 #pragma unroll
@@ -340,19 +358,20 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     const int nst = npad / K;
     auto k_loop = [&](auto compute_tag) {
     constexpr bool COMPUTE = decltype(compute_tag)::value;
-    RT ra[RN], rb[RN];
-    opa.template load<K, NL>(ra, 0, va);
-    opb.template load<K, NL>(rb, 0, vb);
     for (int s = 0; s < nst; ++s) {
       const int buf = s & 1;
       // ---- registers -> LDS ----
       stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
       stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
       __syncthreads();
-      // ---- prefetch the next stage into the registers just emptied ----
+      // ---- prefetch the next stage (or the next tile's first) ----
       if (s + 1 < nst) {
-        opa.template load<K, NL>(ra, s + 1, va);
-        opb.template load<K, NL>(rb, s + 1, vb);
+        src.a.template load<K, NL>(ra, s + 1, src.va);
+        src.b.template load<K, NL>(rb, s + 1, src.vb);
+      } else if (has_next) {
+        const TileSrc<MODE> sn = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+        sn.a.template load<K, NL>(ra, 0, sn.va);
+        sn.b.template load<K, NL>(rb, 0, sn.vb);
       }
       // ---- MFMA on the LDS stage ----
       const int kq = lane >> 4;    // k group of this lane
@@ -601,36 +620,27 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
     t_begin = (int)((int64_t)total * x8 / kXcds) + (int)blockIdx.x / kXcds;
     t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
   }
+  RT ra[RN], rb[RN];   // carried from tile to tile (next tile's first stage)
   TileRec nxt;
-  if (t_begin < t_end) nxt = recs[t_begin];
+  if (t_begin < t_end) {
+    nxt = recs[t_begin];
+    const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+    s0.a.template load<K, NL>(ra, 0, s0.va);
+    s0.b.template load<K, NL>(rb, 0, s0.vb);
+  }
   for (int t = t_begin; t < t_end; t += t_step) {
     const TileRec rec = nxt;
-    if (t + t_step < t_end) nxt = recs[t + t_step];
+    const bool has_next = t + t_step < t_end;
+    if (has_next) nxt = recs[t + t_step];
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
     S* base = mats + rec.mat_off;
-    const int it = rec.it;
-    const S* Xp;
-    const S* Rp;
-    S* Out;
-    if (WHICH == 0) {
-      Xp = base + (int64_t)(it & 1) * nn;
-      Rp = Xp;
-      Out = base + 2 * nn;
-    } else {
-      Xp = base + (int64_t)((it + 1) & 1) * nn;
-      Rp = base + 2 * nn;
-      Out = base + (int64_t)(it & 1) * nn;
-    }
+    S* Out = base + (WHICH == 0 ? 2 * nn : (int64_t)(rec.it & 1) * nn);
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
     const int r0 = bi * 128, c0 = bj * 128;
-    const bool va = (r0 + lrow) < npad;
-    const bool vb = (c0 + lrow) < npad;
     const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && !(bi == bj && wm < wn);
-    const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
-    const Operand<MODE> opa(Xp, shadow_off, (int64_t)(va ? r0 + lrow : 0) * npad + lpart, nn, fk);
-    const Operand<MODE> opb(Rp, shadow_off, (int64_t)(vb ? c0 + lrow : 0) * npad + lpart, nn, fk);
+    const TileSrc<MODE> src = tile_src<MODE, WHICH, 128>(rec, mats, shadow_off, shadow_kind, lrow, lpart);
     const int nst = npad / K;
     const int kq = lane >> 4;
     const int rl = lane & 15;
@@ -643,17 +653,18 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
 
     auto k_loop = [&](auto compute_tag) {
       constexpr bool COMPUTE = decltype(compute_tag)::value;
-      RT ra[RN], rb[RN];
-      opa.template load<K, NL>(ra, 0, va);
-      opb.template load<K, NL>(rb, 0, vb);
       for (int s = 0; s < nst; ++s) {
         const int buf = s & 1;
         stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
         stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
         __syncthreads();
         if (s + 1 < nst) {
-          opa.template load<K, NL>(ra, s + 1, va);
-          opb.template load<K, NL>(rb, s + 1, vb);
+          src.a.template load<K, NL>(ra, s + 1, src.va);
+          src.b.template load<K, NL>(rb, s + 1, src.vb);
+        } else if (has_next) {
+          const TileSrc<MODE> sn = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+          sn.a.template load<K, NL>(ra, 0, sn.va);
+          sn.b.template load<K, NL>(rb, 0, sn.vb);
         }
         if constexpr (!COMPUTE) {
         } else if constexpr (MODE == SM_F32) {
