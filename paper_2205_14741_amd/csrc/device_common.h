@@ -33,6 +33,13 @@ __device__ __forceinline__ int wave_sum_i(int v) {
   return v;
 }
 
+// Orders the LDS accesses of one wavefront (lanes exchanging data through
+// LDS without a workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Block-wide reduction through LDS; every thread gets the result.  The wave
 // partials are combined in wave order.  `red` holds >= blockDim.x/64 doubles.
 template <int OP>  // 0 sum, 1 max, 2 min
@@ -123,6 +130,17 @@ __device__ __forceinline__ uint16_t shadow_hi(float x, int kind) {
 }
 __device__ __forceinline__ uint16_t shadow_lo(float x, uint16_t hi) {
   return f32_to_bf16_bits(x - bf16_bits_to_f32(hi));
+}
+
+// Index (16-bit units) of element (row, col) of a column-major n_pad x n_pad
+// matrix in its copy: one plane, col * n_pad + row; split bf16 keeps hi and
+// lo of 32 consecutive rows side by side, col * 2 n_pad + (row / 32) * 64 +
+// row % 32 (lo at + 32), so the hi and lo of a run of rows share one
+// 128-byte line.  n_pad is a multiple of 32.
+template <bool SPLIT>
+__device__ __forceinline__ int64_t copy_idx(int64_t col, int row, int npad) {
+  if (SPLIT) return col * 2 * npad + (int64_t)(row >> 5) * 64 + (row & 31);
+  return col * npad + row;
 }
 
 // Deterministic probe-vector entry in {-1, +1} for (probe, row).

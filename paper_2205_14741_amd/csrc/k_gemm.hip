@@ -76,18 +76,19 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <int MODE, bool PRE = Pre<MODE>::value> struct Operand;
 
 // NL float32 values of an operand row rebuilt from 16-bit copies of the
-// precision `kind`: the bf16 / f16 value, or hi + lo for split bf16.
+// precision `kind`: the bf16 / f16 value, or hi + lo for split bf16.  p
+// points at the first of the NL values (for split bf16 at its hi entry; the
+// NL values lie inside one 32-row block, lo 32 entries further on).
 template <int NL>
-__device__ __forceinline__ void load_col_shadow(float (&r)[NL], const uint16_t* p, int64_t nn, int kind,
-                                                bool ok) {
-  static_assert(NL % 4 == 0, "vector width");
+__device__ __forceinline__ void load_col_shadow(float (&r)[NL], const uint16_t* p, int kind, bool ok) {
+  static_assert(NL % 4 == 0 && NL <= 32, "vector width");
   typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 #pragma unroll
   for (int v = 0; v < NL / 4; ++v) {
     u2 h = u2{0, 0}, l = u2{0, 0};
     if (ok) {
       h = *reinterpret_cast<const u2*>(p + 4 * v);
-      if (kind == SM_BF16X3) l = *reinterpret_cast<const u2*>(p + nn + 4 * v);
+      if (kind == SM_BF16X3) l = *reinterpret_cast<const u2*>(p + 32 + 4 * v);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -100,23 +101,27 @@ __device__ __forceinline__ void load_col_shadow(float (&r)[NL], const uint16_t* 
   }
 }
 
+// Operand panel row `row` of a buffer, the thread's k slice starting at
+// `part` within each stage.
 template <int MODE> struct Operand<MODE, false> {
   using S = typename Traits<MODE>::S;
   const S* p;
   const uint16_t* q;   // 16-bit copies (float32 products of a first refinement update)
-  int64_t nn;
+  int part;
   int kind;            // main precision of the copies; 0: read the buffer itself
-  __device__ Operand(const S* buf, int64_t shadow_off, int64_t off, int64_t nn_, int kind_)
-      : p(buf + off),
-        q(kind_ ? reinterpret_cast<const uint16_t*>(reinterpret_cast<const float*>(buf) + shadow_off) + off
+  __device__ Operand(const S* buf, int64_t shadow_off, int row, int part_, int npad, int kind_)
+      : p(buf + (int64_t)row * npad + part_),
+        q(kind_ ? reinterpret_cast<const uint16_t*>(reinterpret_cast<const float*>(buf) + shadow_off) +
+                      (int64_t)row * (kind_ == SM_BF16X3 ? 2 * npad : npad)
                 : nullptr),
-        nn(nn_),
+        part(part_),
         kind(kind_) {}
   template <int K, int NL>
   __device__ __forceinline__ void load(S (&r)[NL], int stage, bool ok) const {
     if constexpr (MODE == SM_F32) {
       if (kind) {
-        load_col_shadow<NL>(r, q + (int64_t)stage * K, nn, kind, ok);
+        const int k0 = stage * K + part;
+        load_col_shadow<NL>(r, q + (kind == SM_BF16X3 ? (k0 >> 5) * 64 + (k0 & 31) : k0), kind, ok);
         return;
       }
     }
@@ -125,22 +130,25 @@ template <int MODE> struct Operand<MODE, false> {
 };
 
 template <int MODE> struct Operand<MODE, true> {
+  static constexpr bool SPLIT = MODE == SM_BF16X3;
   const uint16_t* p;
-  int64_t nn;
-  __device__ Operand(const float* buf, int64_t shadow_off, int64_t off, int64_t nn_, int)
-      : p(reinterpret_cast<const uint16_t*>(buf + shadow_off) + off), nn(nn_) {}
-  // NL 16-bit values per plane (NL / 2 words), planes one after the other in r
+  int part;
+  __device__ Operand(const float* buf, int64_t shadow_off, int row, int part_, int npad, int)
+      : p(reinterpret_cast<const uint16_t*>(buf + shadow_off) + (int64_t)row * (SPLIT ? 2 * npad : npad)),
+        part(part_) {}
+  // NL 16-bit values per plane (NL / 2 words), hi then lo in r
   template <int K, int NL, int RN>
   __device__ __forceinline__ void load(uint32_t (&r)[RN], int stage, bool ok) const {
     constexpr int NW = NL / 2;
-    static_assert(RN % NW == 0 && NW % 4 == 0, "operand register layout");
+    static_assert(RN % NW == 0 && NW % 4 == 0 && NL <= 32, "operand register layout");
+    const int k0 = stage * K + part;
+    const uint16_t* src = p + (SPLIT ? (k0 >> 5) * 64 + (k0 & 31) : k0);
 #pragma unroll
     for (int q = 0; q < RN / NW; ++q) {
-      const uint16_t* src = p + q * nn + (int64_t)stage * K;
 #pragma unroll
       for (int v = 0; v < NW / 4; ++v) {
         u32x4 t = u32x4{0, 0, 0, 0};
-        if (ok) t = *reinterpret_cast<const u32x4*>(src + 8 * v);
+        if (ok) t = *reinterpret_cast<const u32x4*>(src + 32 * q + 8 * v);
 #pragma unroll
         for (int e = 0; e < 4; ++e) r[q * NW + 4 * v + e] = t[e];
       }
@@ -197,14 +205,16 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
       l[v] = MODE == SM_BF16X3 ? shadow_lo(o[v], h[v]) : 0;
     }
   }
+  constexpr bool SPLIT = MODE == SM_BF16X3;
   uint16_t* sh = PRE ? reinterpret_cast<uint16_t*>(Out + shadow_off) : nullptr;
   const int64_t dcol = (int64_t)cc * npad + rb;     // (rb .. rb + 3, cc): contiguous
+  const int64_t dcp = copy_idx<SPLIT>(cc, rb, npad);
   if (rb >= cc) {
     if constexpr (PRE) {
       typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-      *reinterpret_cast<u2*>(sh + dcol) = u2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
-      if (MODE == SM_BF16X3)
-        *reinterpret_cast<u2*>(sh + nn + dcol) = u2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
+      *reinterpret_cast<u2*>(sh + dcp) = u2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
+      if (SPLIT)
+        *reinterpret_cast<u2*>(sh + dcp + 32) = u2{l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16)};
     } else {
       *reinterpret_cast<f4*>(Out + dcol) = f4{o[0], o[1], o[2], o[3]};
     }
@@ -213,8 +223,8 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
     for (int v = 0; v < 4; ++v)
       if (rb + v >= cc) {
         if constexpr (PRE) {
-          sh[dcol + v] = h[v];
-          if (MODE == SM_BF16X3) sh[nn + dcol + v] = l[v];
+          sh[dcp + v] = h[v];
+          if (SPLIT) sh[dcp + 32 + v] = l[v];
         } else {
           Out[dcol + v] = o[v];
         }
@@ -223,14 +233,45 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
 #pragma unroll
   for (int v = 0; v < 4; ++v)
     if (rb + v > cc) {
-      const int64_t m = (int64_t)(rb + v) * npad + cc;
       if constexpr (PRE) {
+        const int64_t m = copy_idx<SPLIT>(rb + v, cc, npad);
         sh[m] = h[v];
-        if (MODE == SM_BF16X3) sh[nn + m] = l[v];
+        if (SPLIT) sh[m + 32] = l[v];
       } else {
-        Out[m] = o[v];
+        Out[(int64_t)(rb + v) * npad + cc] = o[v];
       }
     }
+}
+
+// 16 consecutive rows (row0 .. row0 + 15, row0 % 16 == 0) of column col of
+// a product's result: float32 values, or their 16-bit copies for the
+// low-precision main phases.
+template <int MODE>
+__device__ __forceinline__ void store_run16(const float (&w)[16], float* Out, int64_t shadow_off, int col,
+                                            int row0, int npad) {
+  if constexpr (!Pre<MODE>::value) {
+    f4* d = reinterpret_cast<f4*>(Out + (int64_t)col * npad + row0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = f4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+  } else {
+    constexpr bool SPLIT = MODE == SM_BF16X3;
+    uint16_t* sh = reinterpret_cast<uint16_t*>(Out + shadow_off) + copy_idx<SPLIT>(col, row0, npad);
+    uint32_t hw[8], lw[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint16_t h0 = shadow_hi(w[2 * q], MODE), h1 = shadow_hi(w[2 * q + 1], MODE);
+      hw[q] = h0 | ((uint32_t)h1 << 16);
+      if (SPLIT) lw[q] = shadow_lo(w[2 * q], h0) | ((uint32_t)shadow_lo(w[2 * q + 1], h1) << 16);
+    }
+    u32x4* dh = reinterpret_cast<u32x4*>(sh);
+    dh[0] = u32x4{hw[0], hw[1], hw[2], hw[3]};
+    dh[1] = u32x4{hw[4], hw[5], hw[6], hw[7]};
+    if (SPLIT) {
+      u32x4* dl = reinterpret_cast<u32x4*>(sh + 32);
+      dl[0] = u32x4{lw[0], lw[1], lw[2], lw[3]};
+      dl[1] = u32x4{lw[4], lw[5], lw[6], lw[7]};
+    }
+  }
 }
 
 // Operand sources of a tile (rows of X for the tile's rows, rows of R = X or
@@ -254,9 +295,8 @@ __device__ __forceinline__ TileSrc<MODE> tile_src(const TileRec& rec, typename T
   const bool va = (r0 + lrow) < npad;
   const bool vb = (c0 + lrow) < npad;
   const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
-  return TileSrc<MODE>{Operand<MODE>(Xp, shadow_off, (int64_t)(va ? r0 + lrow : 0) * npad + lpart, nn, fk),
-                       Operand<MODE>(Rp, shadow_off, (int64_t)(vb ? c0 + lrow : 0) * npad + lpart, nn, fk),
-                       va, vb};
+  return TileSrc<MODE>{Operand<MODE>(Xp, shadow_off, va ? r0 + lrow : 0, lpart, npad, fk),
+                       Operand<MODE>(Rp, shadow_off, vb ? c0 + lrow : 0, lpart, npad, fk), va, vb};
 }
 
 __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
@@ -474,13 +514,13 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     // be multiplied by -2 in every iteration instead of being left alone. ----
     double part = 0.0;
     const int kq = lane >> 4;
+    if constexpr (MODE == SM_F64) {
 #pragma unroll
-    for (int x = 0; x < (wvalid ? 2 : 0); ++x)
+      for (int x = 0; x < (wvalid ? 2 : 0); ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
-        const int rb = r0 + wm * 32 + x * 16;
-        const int cc = c0 + wn * 32 + y * 16 + (lane & 15);
-        if constexpr (MODE == SM_F64) {
+        for (int y = 0; y < 2; ++y) {
+          const int rb = r0 + wm * 32 + x * 16;
+          const int cc = c0 + wn * 32 + y * 16 + (lane & 15);
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int rr = rb + kq + 4 * v;
@@ -498,10 +538,70 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
             Out[(int64_t)cc * npad + rr] = outv;
             if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
           }
-        } else {
-          store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb + 4 * kq, cc, alpha, part);
+        }
+    } else if constexpr (!Pre<MODE>::value) {
+#pragma unroll
+      for (int x = 0; x < (wvalid ? 2 : 0); ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 32 + x * 16 + 4 * kq,
+                                  c0 + wn * 32 + y * 16 + (lane & 15), alpha, part);
+    } else {
+      // 16-bit copies: each wave stages its 32 x 32 result block in LDS,
+      // then writes it, and its mirror image, as runs of 16 rows per lane
+      // (contiguous 16-byte stores instead of scattered 2-byte ones).  The stage buffer the last stage
+      // did not use is free; with half-depth stages one buffer is too small
+      // and the whole array is used after a barrier.
+      constexpr size_t kStage = sizeof(lds[0]);
+      constexpr size_t kNeed = 4 * 32 * 33 * sizeof(float);
+      float* stg;
+      if constexpr (kStage >= kNeed) {
+        stg = reinterpret_cast<float*>(&lds[nst & 1][0][0]);
+      } else {
+        static_assert(2 * kStage >= kNeed, "epilogue staging");
+        __syncthreads();
+        stg = reinterpret_cast<float*>(&lds[0][0][0]);
+      }
+      float* my = stg + wid * (32 * 33);
+      if (wvalid) {
+        const int R0 = r0 + wm * 32, C0 = c0 + wn * 32;
+        const float a2 = (float)(alpha * alpha), ha = (float)(0.5 * alpha);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int lr = x * 16 + 4 * kq + v, lc = y * 16 + (lane & 15);
+              const float a = acc[x][y][v];
+              float o;
+              if (WHICH == 0) {
+                const float dg = (R0 + lr == C0 + lc) ? 1.0f : 0.0f;
+                const float e = a - dg;   // exact: a ~ 1 on the diagonal
+                if (R0 + lr >= C0 + lc) part += (double)(e * e) * (R0 + lr == C0 + lc ? 1.0 : 2.0);
+                o = __builtin_fmaf(-a2, a, 3.0f * dg);
+              } else {
+                o = ha * a;
+              }
+              my[lc * 33 + lr] = o;
+            }
+        wave_sync();
+        const int li = lane >> 1, h = (lane & 1) * 16;
+        const bool diag = R0 == C0;
+        float w[16];
+        // the block, column C0 + li, rows R0 + h ..; on a diagonal block the
+        // entries above the diagonal take the value of their mirror
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          w[j] = (diag && h + j < li) ? my[(h + j) * 33 + li] : my[li * 33 + h + j];
+        store_run16<MODE>(w, Out, shadow_off, C0 + li, R0 + h, npad);
+        if (!diag) {   // the mirror: column R0 + li, rows C0 + h ..
+#pragma unroll
+          for (int j = 0; j < 16; ++j) w[j] = my[(h + j) * 33 + li];
+          store_run16<MODE>(w, Out, shadow_off, R0 + li, C0 + h, npad);
         }
       }
+    }
     if (WHICH == 0) {
       part = wave_sum(part);
       if (lane == 0) red[wid] = part;

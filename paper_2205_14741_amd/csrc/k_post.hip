@@ -25,14 +25,23 @@ __global__ __launch_bounds__(256) void materialize_kernel(DevPlan p, int g0, flo
   const int l = blockIdx.x;
   if (st[l].status == 2) return;
   const int g = g0 + l;
-  const int64_t nn = (int64_t)p.npad_g[g] * p.npad_g[g];
+  const int npad = p.npad_g[g];
+  const int64_t nn = (int64_t)npad * npad;
   float* X = mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * nn;
   const uint16_t* h = reinterpret_cast<const uint16_t*>(X + shadow_off);
-  for (int64_t k = threadIdx.x; k < nn; k += blockDim.x) {
-    float x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, h[k]) : bf16_bits_to_f32(h[k]);
-    if (kind == SM_BF16X3) x += bf16_bits_to_f32(h[nn + k]);
-    X[k] = x;
-  }
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int c = threadIdx.x / kWave; c < npad; c += blockDim.x / kWave)
+    for (int d = lane; d < npad; d += kWave) {
+      float x;
+      if (kind == SM_BF16X3) {
+        const int64_t k = copy_idx<true>(c, d, npad);
+        x = bf16_bits_to_f32(h[k]) + bf16_bits_to_f32(h[k + 32]);
+      } else {
+        const uint16_t b = h[copy_idx<false>(c, d, npad)];
+        x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, b) : bf16_bits_to_f32(b);
+      }
+      X[(int64_t)c * npad + d] = x;
+    }
 }
 
 hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,

@@ -23,11 +23,6 @@ namespace sm {
 // wait for each other.  Then the identity padding columns.
 // LDS: atoms of I_i and their row offsets (2 m ints), one row map of n_pad
 // ints per wave.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
                                                      double mu, T* __restrict__ mats, int* nonfinite) {
@@ -311,15 +306,19 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
   } else if constexpr (std::is_same<T, float>::value) {
     // products of the low-precision phases read only the 16-bit copies of
     // X_0 (identity padding included); the float32 buffer keeps T
-    uint16_t* hi = reinterpret_cast<uint16_t*>(X + shadow_off);
-    const int64_t nn = (int64_t)npad * npad;
+    uint16_t* cp = reinterpret_cast<uint16_t*>(X + shadow_off);
     for (int cc = wid; cc < npad; cc += nw) {
       const int64_t o = (int64_t)cc * npad;
       for (int d = lane; d < npad; d += kWave) {
         const float x = (cc < n && d < n) ? (float)((double)X[o + d] * sc) : X[o + d];
         const uint16_t h = shadow_hi(x, shadow_kind);
-        hi[o + d] = h;
-        if (shadow_kind == SM_BF16X3) hi[nn + o + d] = shadow_lo(x, h);
+        if (shadow_kind == SM_BF16X3) {
+          const int64_t k = copy_idx<true>(cc, d, npad);
+          cp[k] = h;
+          cp[k + 32] = shadow_lo(x, h);
+        } else {
+          cp[copy_idx<false>(cc, d, npad)] = h;
+        }
       }
     }
   }

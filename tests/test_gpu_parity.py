@@ -179,8 +179,9 @@ def test_find_mu_config1(dev):
 def _read_bufs(plan, work, storage, g):
     """X_even, X_odd, Y of processing index g as float64 (column-major, shown
     transposed).  Low-precision main phases keep only the 16-bit copies their
-    products read (hi + lo for split bf16), in a region after the float32
-    buffers; those are decoded here."""
+    products read, in a region after the float32 buffers: one plane, or for
+    split bf16 hi and lo of every 32-row block of a column side by side; those
+    are decoded here."""
     reg, off = plan.ws_layout(storage)
     info = plan.info()
     npad = info["npad"][info["order"][g]]
@@ -197,13 +198,13 @@ def _read_bufs(plan, work, storage, g):
         bufs = []
         for b in range(3):
             o = 2 * (off[g] + b * nn)
-            hi = u16[o: o + nn]
             if storage == sm.SM_F16:
-                bufs.append(hi.view(np.float16).astype(np.float64))
+                bufs.append(u16[o: o + nn].view(np.float16).astype(np.float64))
             elif storage == sm.SM_BF16:
-                bufs.append(bf(hi))
-            else:
-                bufs.append(bf(hi) + bf(u16[o + nn: o + 2 * nn]))
+                bufs.append(bf(u16[o: o + nn]))
+            else:   # per column: blocks of 32 rows, 32 hi values then 32 lo values
+                blk = u16[o: o + 2 * nn].reshape(npad, npad // 32, 2, 32)
+                bufs.append((bf(blk[:, :, 0, :]) + bf(blk[:, :, 1, :])).reshape(-1))
     return [x.reshape(npad, npad).T.astype(np.float64) for x in bufs]
 
 
