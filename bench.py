@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--modes", default="f64,f32,bf16x3,f32+L,bf16x3+L")
-    ap.add_argument("--guard-steps", type=int, default=4,
+    ap.add_argument("--guard-steps", type=int, default=2,
                     help="power-iteration steps of the learned-scale guard (+L modes)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,

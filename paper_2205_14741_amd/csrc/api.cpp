@@ -164,10 +164,10 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   WsPtrs w = ws_ptrs(p, ws, storage);
   hipStream_t s = as_stream(stream);
   SM_HIP(launch_fill_i32(w.flag, 0, 1, s));
-  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, w.flag, s));
   double* cg = w.scratch;                                 // [max_subs]
   float* pred = reinterpret_cast<float*>(w.scratch + p->max_subs);  // [2 max_subs]
-  SM_HIP(launch_analyze(p->dev, g0, nsub, w.mats, f64, w.features, cg, stats, s));
+  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, w.flag, w.features, cg,
+                       stats, s));
   const float* predp = nullptr;
   if (o->scaling == SM_SCALE_LEARNED) {
     if (!p->mlp) return set_error(SM_ERR_STATE, "build_submatrices: learned scaling needs a network (sm_plan_set_mlp)");
@@ -241,7 +241,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     r = phase(2, 3, 0);                                                   // A = X^2, Y = 3I - A
     if (!r) {
       hipError_t e = launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref,
-                                     nullptr, nullptr, st);
+                                     nullptr, nullptr, nullptr, st);
       if (e != hipSuccess) r = hip_error(e, "launch_schedule");
     }
     if (!r) r = phase(0, 1, 1);                                           // X' = 1/2 X Y
@@ -251,15 +251,15 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
 
   // bounds on the spectrum of X_0 written by build_submatrices (scaled Newton-Schulz)
   SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, tsh_main, tsh_ref,
-                         w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, s));
+                         w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, nullptr, s));
   const int lim = o->max_iter + o->refine_steps + 2;
   const int G = p->profiling ? 0 : o->graph_iters;
   if (G == 0) {
     for (int it = 0; it <= lim; ++it) {
       if ((rc = phase(2, 3, 0))) return rc;          // squares: A = X^2, Y = 3I - A
+      // the scheduler writes the live count into the host word of this parity
       SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref,
-                             nullptr, nullptr, s));
-      SM_HIP(hipMemcpyAsync(&p->h_pinned[it & 1], L0 + 4 * stride, 4, hipMemcpyDeviceToHost, s));
+                             nullptr, nullptr, p->d_pinned + (it & 1), s));
       SM_HIP(hipEventRecord(p->ev[it & 1], s));
       if ((rc = phase(0, 1, 1))) return rc;          // updates: X' = 1/2 X Y
       if (it >= 1) {

@@ -703,7 +703,10 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
   constexpr int NOP = 2 * NPL;
   using RT = typename std::conditional<PRE, uint32_t, S>::type;
   constexpr int RN = PRE ? NPL * NL / 2 : NL;
-  __shared__ __attribute__((aligned(16))) LT lds[2][NOP][128 * LD];
+  // double-buffered LDS stages (a single buffer with two barriers per stage,
+  // which lets two split-bf16 workgroups share a CU, measured slower)
+  constexpr int NBUF = 2;
+  __shared__ __attribute__((aligned(16))) LT lds[NBUF][NOP][128 * LD];
   __shared__ double red[4];
 
   const int tid = threadIdx.x;
@@ -754,7 +757,8 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
     auto k_loop = [&](auto compute_tag) {
       constexpr bool COMPUTE = decltype(compute_tag)::value;
       for (int s = 0; s < nst; ++s) {
-        const int buf = s & 1;
+        const int buf = NBUF == 1 ? 0 : (s & 1);
+        if (NBUF == 1 && s > 0) __syncthreads();   // the previous stage has been read
         stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
         stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
         __syncthreads();
@@ -1058,7 +1062,8 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
                                                         int32_t* lists, int max_subs, SchedOpts o,
                                                         int first, int tshift_main, int tshift_ref,
                                                         const double* __restrict__ lb0,
-                                                        const double* __restrict__ top0) {
+                                                        const double* __restrict__ top0,
+                                                        int32_t* live_host) {
   __shared__ int sh[16];
   const int stride = 2 + 2 * max_subs + 1;
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
@@ -1183,19 +1188,21 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       Lb[2 + max_subs + run_subs[L]] = run_tiles[L];
     }
     // number of submatrices still in flight, for the host's stopping poll
-    lists[4 * stride] = run_subs[0] + run_subs[1] + run_subs[2] + run_subs[3];
+    const int live = run_subs[0] + run_subs[1] + run_subs[2] + run_subs[3];
+    lists[4 * stride] = live;
+    if (live_host) *live_host = live;
   }
 }
 
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
-                           const double* lb0, const double* top0, hipStream_t s) {
+                           const double* lb0, const double* top0, int32_t* live_host, hipStream_t s) {
   SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
   if (!first && nsub > 0)
     hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
   hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, lists, max_subs, o, first,
-                     tshift_main, tshift_ref, lb0, top0);
+                     tshift_main, tshift_ref, lb0, top0, live_host);
   return hipGetLastError();
 }
 

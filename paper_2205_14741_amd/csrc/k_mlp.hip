@@ -16,39 +16,49 @@ constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH
               oB3 = oW3 + kOut * kH, kParams = oB3 + kOut;
 static_assert(kParams == kMlpParams, "parameter count");
 
-// ---- inference: one thread per sample, parameters staged in LDS ----
+// ---- inference: one wavefront per sample (lane j = hidden unit j),
+// parameters staged in LDS, kInferPerWave samples per wavefront in turn ----
+constexpr int kInferPerWave = 4;
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
 __global__ __launch_bounds__(256) void mlp_infer_kernel(const float* __restrict__ theta,
                                                         const float* __restrict__ norm,
                                                         const float* __restrict__ X, int64_t ldx,
                                                         int64_t n, float* __restrict__ Y) {
   __shared__ float w[kParams + 2 * kIn];
+  __shared__ float hs[4][kH];
   for (int k = threadIdx.x; k < kParams; k += blockDim.x) w[k] = theta[k];
   for (int k = threadIdx.x; k < 2 * kIn; k += blockDim.x) w[kParams + k] = norm[k];
   __syncthreads();
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  float x[kIn];
-#pragma unroll
-  for (int i = 0; i < kIn; ++i) x[i] = (X[s * ldx + i] - w[kParams + i]) / w[kParams + kIn + i];
-  float h1[kH];
-#pragma unroll 4
-  for (int j = 0; j < kH; ++j) {
+  const int j = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int64_t first = ((int64_t)blockIdx.x * 4 + wv) * kInferPerWave;
+  for (int q = 0; q < kInferPerWave; ++q) {
+    const int64_t sidx = first + q;
+    if (sidx >= n) break;   // uniform across the wavefront
     float z = w[oB1 + j];
 #pragma unroll
-    for (int i = 0; i < kIn; ++i) z += w[oW1 + j * kIn + i] * x[i];
-    h1[j] = tanhf(z);
-  }
-  float y0 = w[oB3], y1 = w[oB3 + 1];
-  for (int j = 0; j < kH; ++j) {
-    float z = w[oB2 + j];
-#pragma unroll
-    for (int k = 0; k < kH; ++k) z += w[oW2 + j * kH + k] * h1[k];
+    for (int i = 0; i < kIn; ++i)
+      z += w[oW1 + j * kIn + i] * ((X[sidx * ldx + i] - w[kParams + i]) / w[kParams + kIn + i]);
+    hs[wv][j] = tanhf(z);
+    wave_sync();
+    z = w[oB2 + j];
+#pragma unroll 8
+    for (int k = 0; k < kH; ++k) z += w[oW2 + j * kH + k] * hs[wv][k];
     const float h2 = tanhf(z);
-    y0 += w[oW3 + j] * h2;
-    y1 += w[oW3 + kH + j] * h2;
+    const float y0 = wave_sum_f(w[oW3 + j] * h2) + w[oB3];
+    const float y1 = wave_sum_f(w[oW3 + kH + j] * h2) + w[oB3 + 1];
+    if (j == 0) {
+      Y[sidx * 2] = y0;
+      Y[sidx * 2 + 1] = y1;
+    }
+    wave_sync();   // hs is rewritten for the next sample
   }
-  Y[s * 2] = y0;
-  Y[s * 2 + 1] = y1;
 }
 
 // ---- loss and gradient partials: 32 samples per block, activations in LDS ----
@@ -189,8 +199,9 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ theta, co
 hipError_t launch_mlp_infer(const float* theta, const float* norm, const float* X, int64_t ldx, int64_t n,
                             float* Y, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, norm, X,
-                     ldx, n, Y);
+  const int64_t per_block = 4 * kInferPerWave;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0, s, theta,
+                     norm, X, ldx, n, Y);
   return hipGetLastError();
 }
 

@@ -11,6 +11,33 @@
 
 namespace sm {
 
+// Statistics of T_i gathered column by column: column abs sums (= row sums,
+// T is symmetric) give the Gershgorin bound c_G >= rho(T); with the diagonal
+// they give the 16 features of the scaling network.
+struct ColStats {
+  double cmax = 0.0, sdiag = 0.0, sdiag2 = 0.0, mind = 1e300, maxd = -1e300, sR = 0.0, maxR = 0.0;
+  double minabs = 1e300, mingap = 1e300, nneg = 0.0, ssq = 0.0, sown = 0.0, minown = 1e300, sabs = 0.0;
+  __device__ void add(double s, double q, double dg, bool own) {
+    const double R = s - fabs(dg);
+    cmax = fmax(cmax, s);
+    sdiag += dg;
+    sdiag2 += dg * dg;
+    mind = fmin(mind, dg);
+    maxd = fmax(maxd, dg);
+    sR += R;
+    maxR = fmax(maxR, R);
+    minabs = fmin(minabs, fabs(dg));
+    mingap = fmin(mingap, fabs(dg) - R);
+    nneg += dg < 0.0 ? 1.0 : 0.0;
+    ssq += q;
+    sabs += fabs(dg);
+    if (own) {
+      sown += dg;
+      minown = fmin(minown, fabs(dg));
+    }
+  }
+};
+
 // One workgroup per submatrix; its waves take the atoms j of the index set I_i
 // in turn (wave w: atoms w, w + nw, ...), each wave independently:
 //   (a) intersects the stored pattern of H's block column j with I_i by binary
@@ -18,19 +45,26 @@ namespace sm {
 //       column j supplies every destination row of T_i (-1: block not stored);
 //   (b) writes the b_j columns of T_i top to bottom (coalesced stores; reads
 //       are runs of one contiguous panel column), subtracting mu on the
-//       diagonal, and zeros in the padding rows.
+//       diagonal, and zeros in the padding rows, and accumulates each
+//       column's abs sum, sum of squares and diagonal entry (float64).
 // Only wave-level ordering is needed between (a) and (b), so the waves never
-// wait for each other.  Then the identity padding columns.
+// wait for each other.  Then the identity padding columns, and the features
+// of the submatrix from the statistics of all waves.
 // LDS: atoms of I_i and their row offsets (2 m ints), one row map of n_pad
 // ints per wave.
 template <typename T>
 __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
-                                                     double mu, T* __restrict__ mats, int* nonfinite) {
+                                                     double mu, T* __restrict__ mats, int* nonfinite,
+                                                     float* __restrict__ features, double* __restrict__ cg_out,
+                                                     sm_sub_stats* __restrict__ stats) {
   extern __shared__ int smem[];
+  __shared__ double red[8];
   const int g = g0 + blockIdx.x;
   const int i = p.order_g[g];
   const int npad = p.npad_g[g];
   const int n = p.height[i];
+  const int loc = p.loc[i];
+  const int bsz = p.bs[i];
   const int64_t k0 = p.col_ptr[i];
   const int m = (int)(p.col_ptr[i + 1] - k0);
   const int lane = threadIdx.x & (kWave - 1);
@@ -46,6 +80,7 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
   }
   __syncthreads();
   bool bad = false;
+  ColStats cs;   // this wave's columns (identical in every lane)
   for (int jj = wid; jj < m; jj += nw) {
     const int j = s_atom[jj];
     const int locj = s_off[jj];
@@ -72,18 +107,26 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
     wave_sync();
     const double* panel = H + p.panel_off[j];
     for (int q = 0; q < bj; ++q) {
+      const int c = locj + q;
       const double* pc = panel + (int64_t)q * hj;
-      T* xc = X + (int64_t)(locj + q) * npad;
+      T* xc = X + (int64_t)c * npad;
+      double sa = 0.0, sq = 0.0, dl = 0.0;
       for (int d = lane; d < npad; d += kWave) {
         double v = 0.0;
         if (d < n) {
           const int s = s_src[d];
           if (s >= 0) v = pc[s];
-          if (d == locj + q) v -= mu;
+          if (d == c) {
+            v -= mu;
+            dl = v;
+          }
         }
         bad |= !isfinite(v);
+        sa += fabs(v);
+        sq += v * v;
         xc[d] = (T)v;
       }
+      cs.add(wave_sum(sa), wave_sum(sq), wave_sum(dl), c >= loc && c < loc + bsz);
     }
     wave_sync();   // the row map is rebuilt for the wave's next atom
   }
@@ -93,104 +136,21 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
     for (int d = lane; d < npad; d += kWave) xc[d] = (T)(d == c ? 1.0 : 0.0);
   }
   if (bad) *nonfinite = 1 + i;
-}
-
-hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
-                         const double* H, double mu, void* mats, int storage_f64,
-                         int* nonfinite, hipStream_t s) {
-  if (nsub <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);   // 4 waves
-  if (storage_f64)
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
-                       (double*)mats, nonfinite);
-  else
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
-                       (float*)mats, nonfinite);
-  return hipGetLastError();
-}
-
-// One workgroup (8 waves) per submatrix, after the gather: row abs sums
-// (T is symmetric) give the Gershgorin bound c_G >= rho(T) and, with the
-// diagonal, the 16 features of the scaling network.
-template <typename T>
-__global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, const T* __restrict__ mats,
-                                                      float* __restrict__ features,
-                                                      double* __restrict__ cg_out,
-                                                      sm_sub_stats* __restrict__ stats) {
-  __shared__ double red[16];
-  const int l = blockIdx.x;
-  const int g = g0 + l;
-  const int i = p.order_g[g];
-  const int npad = p.npad_g[g];
-  const int n = p.height[i];
-  const int loc = p.loc[i];
-  const int b = p.bs[i];
-  const T* X = mats + p.mat_off_g[g];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-
-  __shared__ double part[2][8 * kWave];
-  double cmax = 0.0, sdiag = 0.0, sdiag2 = 0.0, mind = 1e300, maxd = -1e300, sR = 0.0, maxR = 0.0;
-  double minabs = 1e300, mingap = 1e300, nneg = 0.0, ssq = 0.0, sown = 0.0, minown = 1e300, sabs = 0.0;
-  // abs sum and sum of squares of row r (= column r, T is symmetric): lanes
-  // take 64 consecutive rows (coalesced column reads), waves split the
-  // columns, partial sums combined in wave order
-  for (int r0 = 0; r0 < n; r0 += kWave) {
-    const int r = r0 + lane;
-    double s = 0.0, q = 0.0;
-    if (r < n)
-      for (int c = wid; c < n; c += nw) {
-        const double v = (double)X[(int64_t)c * npad + r];
-        s += fabs(v);
-        q += v * v;
-      }
-    part[0][wid * kWave + lane] = s;
-    part[1][wid * kWave + lane] = q;
-    __syncthreads();
-    if (wid == 0 && r < n) {
-      s = 0.0;
-      q = 0.0;
-      for (int k = 0; k < nw; ++k) {
-        s += part[0][k * kWave + lane];
-        q += part[1][k * kWave + lane];
-      }
-      const double dg = (double)X[(int64_t)r * npad + r];
-      const double R = s - fabs(dg);
-      cmax = fmax(cmax, s);
-      sdiag += dg;
-      sdiag2 += dg * dg;
-      mind = fmin(mind, dg);
-      maxd = fmax(maxd, dg);
-      sR += R;
-      maxR = fmax(maxR, R);
-      minabs = fmin(minabs, fabs(dg));
-      mingap = fmin(mingap, fabs(dg) - R);
-      nneg += dg < 0.0 ? 1.0 : 0.0;
-      ssq += q;
-      sabs += fabs(dg);
-      if (r >= loc && r < loc + b) {
-        sown += dg;
-        minown = fmin(minown, fabs(dg));
-      }
-    }
-    __syncthreads();
-  }
-  // the row statistics sit in the lanes of wave 0 (neutral values elsewhere)
-  cmax = block_reduce<1>(cmax, red);
-  sdiag = block_reduce<0>(sdiag, red);
-  sdiag2 = block_reduce<0>(sdiag2, red);
-  mind = block_reduce<2>(mind, red);
-  maxd = block_reduce<1>(maxd, red);
-  sR = block_reduce<0>(sR, red);
-  maxR = block_reduce<1>(maxR, red);
-  minabs = block_reduce<2>(minabs, red);
-  mingap = block_reduce<2>(mingap, red);
-  nneg = block_reduce<0>(nneg, red);
-  ssq = block_reduce<0>(ssq, red);
-  sown = block_reduce<0>(sown, red);
-  minown = block_reduce<2>(minown, red);
-  sabs = block_reduce<0>(sabs, red);
+  // combine the waves (every lane of a wave holds its values)
+  const double cmax = block_reduce<1>(cs.cmax, red);
+  const double sdiag = block_reduce<0>(lane == 0 ? cs.sdiag : 0.0, red);
+  const double sdiag2 = block_reduce<0>(lane == 0 ? cs.sdiag2 : 0.0, red);
+  const double mind = block_reduce<2>(cs.mind, red);
+  const double maxd = block_reduce<1>(cs.maxd, red);
+  const double sR = block_reduce<0>(lane == 0 ? cs.sR : 0.0, red);
+  const double maxR = block_reduce<1>(cs.maxR, red);
+  const double minabs = block_reduce<2>(cs.minabs, red);
+  const double mingap = block_reduce<2>(cs.mingap, red);
+  const double nneg = block_reduce<0>(lane == 0 ? cs.nneg : 0.0, red);
+  const double ssq = block_reduce<0>(lane == 0 ? cs.ssq : 0.0, red);
+  const double sown = block_reduce<0>(lane == 0 ? cs.sown : 0.0, red);
+  const double minown = block_reduce<2>(cs.minown, red);
+  const double sabs = block_reduce<0>(lane == 0 ? cs.sabs : 0.0, red);
   if (threadIdx.x == 0) {
     const double cG = cmax > 0.0 ? cmax : 1.0;
     const double nn = (double)n;
@@ -208,18 +168,33 @@ __global__ __launch_bounds__(512) void analyze_kernel(DevPlan p, int g0, const T
     f[9] = (float)(mingap / cG);
     f[10] = (float)(nneg / nn);
     f[11] = (float)(sqrt(ssq) / (cG * sqrt(nn)));
-    f[12] = (float)(b / nn);
-    f[13] = (float)(sown / b / cG);
+    f[12] = (float)(bsz / nn);
+    f[13] = (float)(sown / bsz / cG);
     f[14] = (float)(minown / cG);
     f[15] = (float)(sabs / nn / cG);
     sm_sub_stats& r = stats[i];
     for (int k = 0; k < kNumFeatures; ++k) {
-      features[(int64_t)l * kNumFeatures + k] = f[k];
+      features[(int64_t)blockIdx.x * kNumFeatures + k] = f[k];
       r.feat[k] = f[k];
     }
     r.gersh = cG;
-    cg_out[l] = cG;
+    cg_out[blockIdx.x] = cG;
   }
+}
+
+hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
+                         const double* H, double mu, void* mats, int storage_f64,
+                         int* nonfinite, float* features, double* cg_out, sm_sub_stats* stats,
+                         hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);   // 4 waves
+  if (storage_f64)
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
+                       (double*)mats, nonfinite, features, cg_out, stats);
+  else
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
+                       (float*)mats, nonfinite, features, cg_out, stats);
+  return hipGetLastError();
 }
 
 // One workgroup per submatrix: optional power iteration on T (column dots with
@@ -333,18 +308,6 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     lb0_out[l] = lb;
     top0_out[l] = cG / c;
   }
-}
-
-hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
-                          float* features, double* cg_out, sm_sub_stats* stats, hipStream_t s) {
-  if (nsub <= 0) return hipSuccess;
-  if (storage_f64)
-    hipLaunchKernelGGL(analyze_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (const double*)mats,
-                       features, cg_out, stats);
-  else
-    hipLaunchKernelGGL(analyze_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (const float*)mats,
-                       features, cg_out, stats);
-  return hipGetLastError();
 }
 
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,

@@ -336,8 +336,10 @@ int ensure_device(sm_plan* p) {
   if ((rc = dev_alloc(p, 2 * kTraceBlocks + 8, &p->d_trace_parts)) != SM_OK) return rc;
   if ((rc = dev_alloc(p, (size_t)p->n_atoms, &p->d_ne_sub)) != SM_OK) return rc;
   if ((rc = dev_alloc(p, (size_t)2 * p->n_atoms, &p->d_gersh)) != SM_OK) return rc;
-  SM_HIP(hipHostMalloc((void**)&p->h_pinned, 64, hipHostMallocDefault));
+  // coherent and mapped: the scheduler writes the live count straight into it
+  SM_HIP(hipHostMalloc((void**)&p->h_pinned, 64, hipHostMallocMapped | hipHostMallocCoherent));
   std::memset(p->h_pinned, 0, 64);
+  SM_HIP(hipHostGetDevicePointer((void**)&p->d_pinned, p->h_pinned, 0));
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     p->num_cu = ncu;

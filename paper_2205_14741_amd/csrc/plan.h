@@ -47,7 +47,8 @@ struct sm_plan {
   double* d_trace_parts = nullptr;  // [2 * kTraceBlocks + 2]
   double* d_ne_sub = nullptr;       // [n_atoms]
   double* d_gersh = nullptr;        // [2 * n_atoms]
-  int32_t* h_pinned = nullptr;      // pinned host counters [8]
+  int32_t* h_pinned = nullptr;      // pinned, device-mapped host words [16]
+  int32_t* d_pinned = nullptr;      // the device's address of h_pinned
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_storage = -1;            // workspace storage of the last build (ws_storage; -1: none)
   int32_t tuned[5] = {0, 0, 0, 0, 0};  // GEMM variant per precision (sm_autotune)

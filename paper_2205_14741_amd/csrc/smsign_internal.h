@@ -84,11 +84,12 @@ struct WsLayout {
 };
 
 // Launchers (k_*.hip).  All return hipError_t from hipGetLastError.
+// T_i of every submatrix of the chunk, plus its Gershgorin bound (cg_out,
+// stats.gersh) and the features of the scaling network (features, stats.feat).
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
                          const double* H, double mu, void* mats, int storage_f64,
-                         int* nonfinite, hipStream_t s);
-hipError_t launch_analyze(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
-                          float* features, double* cg_out, sm_sub_stats* stats, hipStream_t s);
+                         int* nonfinite, float* features, double* cg_out, sm_sub_stats* stats,
+                         hipStream_t s);
 // shadow_kind: 0, or SM_BF16 / SM_F16 / SM_BF16X3 to also write X_0's operand
 // copy at float offset shadow_off from its float32 buffer
 // lbound: opts.lbound; lb0_out / top0_out [nsub]: bounds on the smallest /
@@ -99,11 +100,13 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
                         double lbound, double* lb0_out, double* top0_out, hipStream_t s);
 // first != 0 initialises the iteration state; lb0 / top0 [nsub] (may be null):
-// bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz).
+// bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz);
+// live_host (may be null): device-mapped host word that receives the number of
+// submatrices still iterating.
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
-                           const double* lb0, const double* top0, hipStream_t s);
+                           const double* lb0, const double* top0, int32_t* live_host, hipStream_t s);
 // which: 0 squares, 1 updates (selects the submatrix's alpha).  first_ref >= 0:
 // refinement-list tiles of submatrices with refine_left == first_ref (their
 // first refinement update) get kTileFromShadow.
