@@ -321,7 +321,14 @@ def main():
         fl = metrics.flops_by_class(st, n, npad, o)
         useful = sum(v[0] for v in fl.values())
         P = work.P.cpu().numpy()
-        r = {"ms_per_step": dt / a.steps * 1e3, "pad_to": 32 if MODES[mode] in ("f64", "f32") else 64, "mu": mu,
+        # float64 commutator check of the final X at the accepted mu (untimed)
+        res_comm = float("nan")
+        if plan.n_chunks == 1:   # the workspace holds the last chunk's X
+            oc = o.copy()
+            oc.comm_probes = 2
+            sm.sm_comm_probe(plan, 0, H, mu, oc, work.ws, work.stats)
+            res_comm = float(work.stats_host()["res_comm"].max())
+        r = {"ms_per_step": dt / a.steps * 1e3, "res_comm_max": res_comm, "pad_to": 32 if MODES[mode] in ("f64", "f32") else 64, "mu": mu,
              "bisection_passes": k, "E": E, "Ne": Ne, "scaling": int(o.scaling), "accel": int(o.accel),
              "learned_accepted": float(np.mean(st["scale_src"] == 2)) if o.scaling == sm.SM_SCALE_LEARNED else None,
              "iters": [int(st["iters"].min()), int(st["iters"].max())],
@@ -367,7 +374,7 @@ def main():
         res[mode] = r
         print(f"# {mode}: {r['ms_per_step']:.2f} ms/step, {r['submatrices_per_s']:.0f} subm/s, "
               f"{r['useful_tflops']:.2f} TF/s useful, iters {r['iters']}, dE {r['rel_dE_vs_f64']:.2e}, "
-              f"dP {r['max_dP_vs_f64']:.2e}, variant {best} (tune ms {' / '.join(f'{x:.2f}' for x in tune_ms)})"
+              f"dP {r['max_dP_vs_f64']:.2e}, comm {res_comm:.1e}, variant {best} (tune ms {' / '.join(f'{x:.2f}' for x in tune_ms)})"
               + (f", {r['kernel']['name']} {r['kernel']['achieved_tflops']:.2f} TF/s "
                  f"{r['kernel']['achieved_gbs']:.0f} GB/s" if prof else ""),
               file=sys.stderr, flush=True)

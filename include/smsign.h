@@ -115,11 +115,15 @@ typedef struct {
                             Refinement steps are plain. */
   double lbound;         /* l_0 as a fraction of the Gershgorin bound: the smallest
                             |eigenvalue| of T is taken to be about lbound * c_G (0: none) */
+  int32_t comm_probes;   /* 0..4: float64 commutator probes ||(X T - T X) v|| / (c ||v||) per
+                            submatrix (sm_comm_probe), run by sm_density_matrix after every
+                            chunk's sign and by sm_find_mu in every pass; 0 = off */
+  int32_t reserved;
 } sm_sign_opts;
 
 /* Per-submatrix result record, written on the device by build_submatrices
  * (scale, scale_src, gersh, rho_est, feat) and submatrix_sign (the rest).
- * 136 bytes, indexed by submatrix (atom) id. */
+ * 144 bytes, indexed by submatrix (atom) id. */
 typedef struct {
   int32_t iters;       /* Newton-Schulz updates applied in total */
   int32_t iters_low;   /* ... of which in the phase-1 precision */
@@ -136,6 +140,10 @@ typedef struct {
                           k with 0.01 <= r_k = ||X_k^2 - I||_F < 1 of g^-k(sqrt(1 - r_k)),
                           g(x) = x (3 - x^2) / 2 inverted on [0, 1] (rigorous up to the
                           rounding of r_k); -1 if none */
+  double res_comm;     /* float64 commutator probe: max_v ||(X T - T X) v|| / (c ||v||) for
+                          fixed +-1 vectors v (X the final iterate, T = H[idx, idx] - mu I,
+                          c the scale); it is the residual that sees an error in the
+                          occupied subspace, which X^2 = I cannot.  -1 if not run */
   float feat[16];      /* features of the scaling network (see sm_mlp_create) */
 } sm_sub_stats;
 
@@ -214,6 +222,17 @@ int submatrix_sign(sm_plan* plan, int32_t chunk, void* ws, const sm_sign_opts* o
  *   P_vals device float64 [p_nnz_vals], same layout as H. */
 int assemble_P(const sm_plan* plan, int32_t chunk, const void* ws, double* P_vals,
                void* stream);
+
+/* Float64 commutator check of every submatrix of `chunk` after submatrix_sign:
+ * stats[i].res_comm = max over opts->comm_probes (1..4) fixed +-1 vectors v of
+ * ||X (T v) - T (X v)|| / (c_i ||v||), X the final iterate in the workspace,
+ * T v formed straight from H's panels (H_vals and mu as given to
+ * build_submatrices for this chunk).  sign(T) commutes with T (Eq. 13), so
+ * this measures how far the converged X is from sign(T) in the direction the
+ * iteration cannot repair (a rotation of the occupied subspace).
+ * Asynchronous on `stream`. */
+int sm_comm_probe(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
+                  const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, void* stream);
 
 /* E = tr(P H) = sum over stored entries of P .* H (H symmetric) and
  * Ne = tr P, reduced in float64 in a fixed order (bitwise reproducible).

@@ -28,6 +28,7 @@ int check_opts(const sm_sign_opts* o) {
   if (o->graph_iters < 0 || o->graph_iters > 64) return set_error(SM_ERR_ARG, "opts.graph_iters = %d out of [0, 64]", o->graph_iters);
   if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
   if (o->accel != 0 && o->accel != 1) return set_error(SM_ERR_ARG, "opts.accel = %d is not 0 or 1", o->accel);
+  if (o->comm_probes < 0 || o->comm_probes > 4) return set_error(SM_ERR_ARG, "opts.comm_probes = %d out of [0, 4]", o->comm_probes);
   if (!(o->lbound >= 0.0 && o->lbound <= 1.0)) return set_error(SM_ERR_ARG, "opts.lbound out of [0, 1]");
   if (!(o->tol >= 0) || !(o->switch_tol >= 0) || !(o->stall_ratio >= 0) || !(o->stall_below >= 0) ||
       !(o->scale_margin >= 0))
@@ -312,6 +313,24 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   return SM_OK;
 }
 
+int sm_comm_probe(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_sign_opts* o, void* ws,
+                  sm_sub_stats* stats, void* stream) {
+  if (!p || !H || !ws || !stats) return set_error(SM_ERR_ARG, "sm_comm_probe: null argument");
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if (o->comm_probes < 1) return set_error(SM_ERR_ARG, "sm_comm_probe: opts.comm_probes must be 1..4");
+  int g0, nsub;
+  if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
+  if ((rc = ensure_device(p))) return rc;
+  const int storage = ws_storage(o);
+  if (p->last_storage != storage)
+    return set_error(SM_ERR_STATE, "sm_comm_probe: the workspace was not built for this precision schedule");
+  WsPtrs w = ws_ptrs(p, ws, storage);
+  SM_HIP(launch_comm_probe(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, storage == SM_F64, w.st,
+                           o->comm_probes, w.vecs, stats, as_stream(stream)));
+  return SM_OK;
+}
+
 int assemble_P(const sm_plan* p, int32_t chunk, const void* ws, double* P, void* stream) {
   if (!p || !ws || !P) return set_error(SM_ERR_ARG, "assemble_P: null argument");
   int g0, nsub, rc;
@@ -350,6 +369,7 @@ int sm_density_matrix(sm_plan* p, const double* H, double mu, const sm_sign_opts
   for (int c = 0; c < nch; ++c) {
     if ((rc = build_submatrices(p, c, H, mu, o, ws, stats, stream))) return rc;
     if ((rc = submatrix_sign(p, c, ws, o, stats, stream))) return rc;
+    if (o->comm_probes > 0 && (rc = sm_comm_probe(p, c, H, mu, o, ws, stats, stream))) return rc;
     if ((rc = assemble_P(p, c, ws, P, stream))) return rc;
   }
   return energy_trace(p, H, P, E, Ne, stream);
@@ -394,6 +414,7 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
     for (int c = 0; c < nch; ++c) {
       if ((rc = build_submatrices(p, c, H, mid, o, ws, stats, stream))) return rc;
       if ((rc = submatrix_sign(p, c, ws, o, stats, stream))) return rc;
+      if (o->comm_probes > 0 && (rc = sm_comm_probe(p, c, H, mid, o, ws, stats, stream))) return rc;
       int g0, nsub;
       chunk_range(p, c, g0, nsub);
       WsPtrs w = ws_ptrs(p, ws, ws_storage(o));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
+#include "row_map.h"
 #include "smsign_internal.h"
 
 namespace sm {
@@ -97,7 +98,8 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
     r.status = s.status;
     r.res = s.res;
     r.lb_est = s.lb_est;
-    if (P > 0) r.res_probe = worst;
+    r.res_probe = worst;   // -1 without probes
+    r.res_comm = -1.0;     // set by the commutator probe when it runs
   }
 }
 
@@ -124,6 +126,126 @@ hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, i
   if (nsub <= 0) return hipSuccess;
   if (storage_f64) return launch_finish_t(p, g0, nsub, (const double*)mats, st, probes, vecs, stats, s);
   return launch_finish_t(p, g0, nsub, (const float*)mats, st, probes, vecs, stats, s);
+}
+
+// y_q = T w_q (q < Q) for T = H[idx_i, idx_i] - mu I read straight from H's
+// panels: the block's waves take the atoms j of I_i in turn, build the row
+// map of block column j (row_map.h) and, for each of its columns c, form the
+// dot product of column c of T with w_q (lanes over rows, float64); T is
+// symmetric, so that is entry c of T w_q.  out(q, c, y) is called by lane 0 of
+// the wave that owns column c.  LDS: smem holds the atoms of I_i, their row
+// offsets and one row map per wave (as the gather).
+template <int Q, typename Out>
+__device__ __forceinline__ void t_matvec(const DevPlan& p, const double* __restrict__ H, double mu,
+                                         const int* s_atom, const int* s_off, int m, int n, int* s_src,
+                                         const double* __restrict__ w, int ws, Out out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  for (int jj = wid; jj < m; jj += nw) {
+    const int j = s_atom[jj];
+    const int locj = s_off[jj];
+    build_row_map(p, j, s_atom, s_off, m, n, s_src);
+    const double* panel = H + p.panel_off[j];
+    const int hj = p.height[j];
+    for (int qc = 0; qc < p.bs[j]; ++qc) {
+      const int c = locj + qc;
+      const double* pc = panel + (int64_t)qc * hj;
+      double dot[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) dot[q] = 0.0;
+      for (int d = lane; d < n; d += kWave) {
+        const int sr = s_src[d];
+        double t = sr >= 0 ? pc[sr] : 0.0;
+        if (d == c) t -= mu;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) dot[q] += t * w[q * ws + d];
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const double y = wave_sum(dot[q]);
+        if (lane == 0) out(q, c, y);
+      }
+    }
+    wave_sync();   // the row map is rebuilt for the wave's next atom
+  }
+}
+
+// One workgroup per submatrix: the commutator probe ||X (T v) - T (X v)|| /
+// (c ||v||) for P fixed +-1 vectors (float64), X the final iterate.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void comm_probe_kernel(DevPlan p, int g0, const double* __restrict__ H,
+                                                         double mu, const T* __restrict__ mats,
+                                                         const SubState* __restrict__ st,
+                                                         double* __restrict__ vecs,
+                                                         sm_sub_stats* __restrict__ stats) {
+  extern __shared__ int smem[];
+  __shared__ double red[4 * kWave * P];
+  __shared__ double red2[8];
+  const int l = blockIdx.x;
+  const int g = g0 + l;
+  const int i = p.order_g[g];
+  const int npad = p.npad_g[g];
+  const int n = p.height[i];
+  const int64_t k0 = p.col_ptr[i];
+  const int m = (int)(p.col_ptr[i + 1] - k0);
+  int* s_atom = smem;
+  int* s_off = smem + m;
+  int* s_src = smem + 2 * m + (threadIdx.x / kWave) * npad;
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    s_atom[t] = p.row_idx[k0 + t];
+    s_off[t] = p.blk_rowoff[k0 + t];
+  }
+  const T* X = final_x(p, g, mats, st, l);
+  double* v = vecs + p.vec_off_g[g];   // [P][npad] probes
+  double* a = v + P * npad;            // X v
+  double* b = a + P * npad;            // T v
+  double* c = b + P * npad;            // X (T v)
+  for (int d = threadIdx.x; d < n; d += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[q * npad + d] = probe_entry(100 + q, d);
+  __syncthreads();
+  block_matvec<P>(X, npad, n, v, npad, red, [&](int q, int r, double y) { a[q * npad + r] = y; });
+  t_matvec<P>(p, H, mu, s_atom, s_off, m, n, s_src, v, npad, [&](int q, int r, double y) { b[q * npad + r] = y; });
+  __syncthreads();
+  block_matvec<P>(X, npad, n, b, npad, red, [&](int q, int r, double y) { c[q * npad + r] = y; });
+  double e[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) e[q] = 0.0;
+  t_matvec<P>(p, H, mu, s_atom, s_off, m, n, s_src, a, npad, [&](int q, int r, double y) {
+    const double t = c[q * npad + r] - y;
+    e[q] += t * t;
+  });
+  __syncthreads();
+  double worst = 0.0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) worst = fmax(worst, sqrt(block_reduce<0>(e[q], red2) / (double)n));
+  if (threadIdx.x == 0) stats[i].res_comm = worst / stats[i].scale;
+}
+
+template <typename T>
+static hipError_t launch_comm_t(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,
+                                double mu, const T* mats, const SubState* st, int probes, double* vecs,
+                                sm_sub_stats* stats, hipStream_t s) {
+  const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);
+  switch (probes) {
+    case 1: hipLaunchKernelGGL((comm_probe_kernel<T, 1>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, mats, st, vecs, stats); break;
+    case 2: hipLaunchKernelGGL((comm_probe_kernel<T, 2>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, mats, st, vecs, stats); break;
+    case 3: hipLaunchKernelGGL((comm_probe_kernel<T, 3>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, mats, st, vecs, stats); break;
+    case 4: hipLaunchKernelGGL((comm_probe_kernel<T, 4>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, mats, st, vecs, stats); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_comm_probe(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,
+                             double mu, const void* mats, int storage_f64, const SubState* st, int probes,
+                             double* vecs, sm_sub_stats* stats, hipStream_t s) {
+  static_assert(4 * 4 <= 2 * kMaxProbes, "probe vectors fit the per-submatrix vector space");
+  if (nsub <= 0) return hipSuccess;
+  if (storage_f64)
+    return launch_comm_t(p, g0, nsub, max_m, max_npad, H, mu, (const double*)mats, st, probes, vecs, stats, s);
+  return launch_comm_t(p, g0, nsub, max_m, max_npad, H, mu, (const float*)mats, st, probes, vecs, stats, s);
 }
 
 // Block column i of P = 1/2 (E - X[:, loc_i : loc_i + b_i]) over the n_i rows of

@@ -7,6 +7,7 @@
 #include <type_traits>
 
 #include "device_common.h"
+#include "row_map.h"
 #include "smsign_internal.h"
 
 namespace sm {
@@ -86,25 +87,7 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
     const int locj = s_off[jj];
     const int bj = p.bs[j];
     const int hj = p.height[j];
-    const int64_t kj0 = p.col_ptr[j];
-    const int mj = (int)(p.col_ptr[j + 1] - kj0);
-    for (int d = lane; d < n; d += kWave) s_src[d] = -1;
-    wave_sync();
-    for (int t = lane; t < mj; t += kWave) {
-      const int k = p.row_idx[kj0 + t];
-      int lo = 0, hi = m;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (s_atom[mid] < k) lo = mid + 1; else hi = mid;
-      }
-      if (lo < m && s_atom[lo] == k) {
-        const int dst = s_off[lo];
-        const int src = p.blk_rowoff[kj0 + t];
-        const int bk = p.bs[k];
-        for (int q = 0; q < bk; ++q) s_src[dst + q] = src + q;
-      }
-    }
-    wave_sync();
+    build_row_map(p, j, s_atom, s_off, m, n, s_src);
     const double* panel = H + p.panel_off[j];
     for (int q = 0; q < bj; ++q) {
       const int c = locj + q;

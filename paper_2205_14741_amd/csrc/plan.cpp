@@ -44,8 +44,8 @@ int ws_storage(const sm_sign_opts* o) {
 
 bool valid_storage(int storage) { return storage >= SM_F64 && storage <= SM_BF16X3; }
 
-static_assert(sizeof(sm_sign_opts) == 88, "sm_sign_opts layout");
-static_assert(sizeof(sm_sub_stats) == 136, "sm_sub_stats layout");
+static_assert(sizeof(sm_sign_opts) == 96, "sm_sign_opts layout");
+static_assert(sizeof(sm_sub_stats) == 144, "sm_sub_stats layout");
 
 static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 

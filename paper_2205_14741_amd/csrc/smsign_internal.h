@@ -129,6 +129,10 @@ hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t 
                           int shadow_kind, const int32_t* count, const TileRec* recs,
                           double* partials, int grid, hipStream_t s, hipEvent_t ev_start = nullptr,
                           hipEvent_t ev_stop = nullptr);
+// Commutator probes (1..4) of the final X against T read from H's panels.
+hipError_t launch_comm_probe(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,
+                             double mu, const void* mats, int storage_f64, const SubState* st, int probes,
+                             double* vecs, sm_sub_stats* stats, hipStream_t s);
 // Float32 values of the final X from its 16-bit copies, for submatrices whose
 // iteration ended in a low-precision main phase (status != 2).
 hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,

@@ -27,6 +27,7 @@ EXPORTED = (
     "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
     "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
+    "sm_comm_probe",
 )
 
 
@@ -47,7 +48,7 @@ class SignOpts(C.Structure):
                 ("stall_below", C.c_double), ("stall_ratio", C.c_double), ("scaling", C.c_int32),
                 ("power_steps", C.c_int32), ("scale_margin", C.c_double), ("probes", C.c_int32),
                 ("variant", C.c_int32), ("graph_iters", C.c_int32), ("accel", C.c_int32),
-                ("lbound", C.c_double)]
+                ("lbound", C.c_double), ("comm_probes", C.c_int32), ("reserved", C.c_int32)]
 
     def copy(self) -> "SignOpts":
         o = SignOpts()
@@ -59,17 +60,18 @@ class SubStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("iters_low", C.c_int32), ("status", C.c_int32),
                 ("scale_src", C.c_int32), ("scale", C.c_double), ("res", C.c_double),
                 ("res_probe", C.c_double), ("gersh", C.c_double), ("rho_est", C.c_double),
-                ("lb0", C.c_double), ("lb_est", C.c_double), ("feat", C.c_float * 16)]
+                ("lb0", C.c_double), ("lb_est", C.c_double), ("res_comm", C.c_double),
+                ("feat", C.c_float * 16)]
 
 
 STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"),
                         ("scale_src", "<i4"), ("scale", "<f8"), ("res", "<f8"),
                         ("res_probe", "<f8"), ("gersh", "<f8"), ("rho_est", "<f8"),
-                        ("lb0", "<f8"), ("lb_est", "<f8"), ("feat", "<f4", (16,))])
-STATS_FEAT_OFFSET = 72   # bytes from the start of a record to feat[0]
-assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 136
+                        ("lb0", "<f8"), ("lb_est", "<f8"), ("res_comm", "<f8"), ("feat", "<f4", (16,))])
+STATS_FEAT_OFFSET = 80   # bytes from the start of a record to feat[0]
+assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 144
 assert STATS_DTYPE.fields["feat"][1] == STATS_FEAT_OFFSET
-assert C.sizeof(SignOpts) == 88
+assert C.sizeof(SignOpts) == 96
 
 _lib = None
 
@@ -112,6 +114,7 @@ def lib() -> C.CDLL:
         "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, i32, vp, vp, vp]),
         "sm_plan_tuning": (i32, [vp, vp, vp]),
         "sm_ws_storage": (i32, [C.POINTER(SignOpts)]),
+        "sm_comm_probe": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, vp]),
         "sm_last_error": (C.c_char_p, []),
         "sm_version": (C.c_char_p, []),
     }
@@ -231,6 +234,12 @@ def submatrix_sign(plan: Plan, chunk: int, ws, opts: SignOpts, stats, stream=Non
     _check_ws(plan, ws, opts)
     _check(lib().submatrix_sign(plan.handle, int(chunk), _ptr(ws), C.byref(opts), _ptr(stats),
                                 _stream(stream)))
+
+
+def sm_comm_probe(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, stream=None):
+    _check_ws(plan, ws, opts)
+    _check(lib().sm_comm_probe(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts), _ptr(ws),
+                               _ptr(stats), _stream(stream)))
 
 
 def assemble_P(plan: Plan, chunk: int, ws, P, stream=None):

@@ -8,7 +8,9 @@
   precision target of the oracle);
 * a badly wrong l_0 (too large or too small) only costs iterations;
 * learned: the scaling network's second output trained on lb_est of earlier
-  trajectory steps supplies l_0 on later steps.
+  trajectory steps supplies l_0 on later steps;
+* the float64 commutator probe ||X T v - T X v|| / (c ||v||) against a CPU
+  recomputation from the final X and the oracle's T.
 """
 import numpy as np
 import pytest
@@ -114,3 +116,58 @@ def test_learned_lower_bound_on_trajectory(dev):
         assert np.mean(sta["scale_src"] == 2) > 0.7
         assert sta["iters"].mean() < stl["iters"].mean() - 1.0
         assert np.max(np.abs(Pa - Pg)) < 1e-9 and rel(Ea, Eg) < 1e-12
+
+
+def _probe_vec(q, n):
+    """The fixed +-1 probe vector q of the float64 checks (a counter hash of
+    (q, row); the same definition as the device's)."""
+    r = np.arange(n, dtype=np.uint64)
+    M = np.uint64(0xFFFFFFFF)
+    h = (r * np.uint64(0x9E3779B1) + np.uint64(q) * np.uint64(0x85EBCA77) + np.uint64(0x165667B1)) & M
+    h ^= h >> np.uint64(15)
+    h = (h * np.uint64(0x2C1B3C6D)) & M
+    h ^= h >> np.uint64(12)
+    h = (h * np.uint64(0x297A2D39)) & M
+    h ^= h >> np.uint64(15)
+    return np.where(h & np.uint64(1), 1.0, -1.0)
+
+
+def test_commutator_probe(dev):
+    """res_comm = max_v ||X T v - T X v|| / (c ||v||): recomputed on the CPU
+    from the final float32 X in the workspace and the oracle's T; ordered by
+    precision (float64 << split bf16 << bf16) like the subspace error."""
+    import torch
+    m, mu = _system()
+    plan = sm.Plan(m, 64)
+    H = torch.from_numpy(m.vals).cuda()
+    o = sm.default_opts("f32", comm_probes=2)
+    work = sm.Workspace(plan, sm.storage_prec(o), H.device)
+    sm.build_submatrices(plan, 0, H, mu, o, work.ws, work.stats)
+    sm.submatrix_sign(plan, 0, work.ws, o, work.stats)
+    sm.sm_comm_probe(plan, 0, H, mu, o, work.ws, work.stats)
+    torch.cuda.synchronize()
+    st = work.stats_host()
+    reg, off = plan.ws_layout(sm.SM_F32)
+    mats = work.ws.cpu().numpy()[reg[0]:reg[1]].view(np.float32)
+    info = plan.info()
+    view = om.BlockView(m)
+    for g in (0, 17, 40):
+        i = info["order"][g]
+        npad, n = info["npad"][i], info["n"][i]
+        nn = npad * npad
+        b = int(st["iters"][i]) & 1
+        X = mats[off[g] + b * nn: off[g] + (b + 1) * nn].reshape(npad, npad).T[:n, :n].astype(np.float64)
+        T = om.submatrix(view, i, mu)
+        worst = 0.0
+        for q in range(2):
+            v = _probe_vec(100 + q, n)
+            worst = max(worst, np.linalg.norm(X @ (T @ v) - T @ (X @ v)) / np.sqrt(n))
+        ref = worst / st["scale"][i]
+        assert abs(st["res_comm"][i] - ref) <= 1e-6 * ref + 1e-12, (i, st["res_comm"][i], ref)
+    vals = {}
+    for prec in ("f64", "bf16x3", "bf16"):
+        P, E, Ne, st2, _ = run_fixed_mu(m, mu, prec, pad_to=64, comm_probes=2)
+        vals[prec] = float(st2["res_comm"].max())
+    print("max res_comm:", vals, "f32:", float(st["res_comm"].max()))
+    assert vals["f64"] < 1e-12 < vals["bf16x3"] < 1e-4 < vals["bf16"]
+    assert np.all(st["res_comm"] > 0)
