@@ -322,7 +322,7 @@ def main():
         useful = sum(v[0] for v in fl.values())
         P = work.P.cpu().numpy()
         # float64 commutator check of the final X at the accepted mu (untimed)
-        res_comm = float("nan")
+        res_comm = None
         if plan.n_chunks == 1:   # the workspace holds the last chunk's X
             oc = o.copy()
             oc.comm_probes = 2
@@ -374,7 +374,7 @@ def main():
         res[mode] = r
         print(f"# {mode}: {r['ms_per_step']:.2f} ms/step, {r['submatrices_per_s']:.0f} subm/s, "
               f"{r['useful_tflops']:.2f} TF/s useful, iters {r['iters']}, dE {r['rel_dE_vs_f64']:.2e}, "
-              f"dP {r['max_dP_vs_f64']:.2e}, comm {res_comm:.1e}, variant {best} (tune ms {' / '.join(f'{x:.2f}' for x in tune_ms)})"
+              f"dP {r['max_dP_vs_f64']:.2e}, comm {res_comm if res_comm is None else f'{res_comm:.1e}'}, variant {best} (tune ms {' / '.join(f'{x:.2f}' for x in tune_ms)})"
               + (f", {r['kernel']['name']} {r['kernel']['achieved_tflops']:.2f} TF/s "
                  f"{r['kernel']['achieved_gbs']:.0f} GB/s" if prof else ""),
               file=sys.stderr, flush=True)
