@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--modes", default="f64,f32,bf16x3,f32+L,bf16x3+L")
+    ap.add_argument("--pad", type=int, default=32, choices=[32, 64],
+                    help="padding of the submatrices for the 16-bit schedules (float64 / float32: 32)")
     ap.add_argument("--guard-steps", type=int, default=2,
                     help="power-iteration steps of the learned-scale guard (+L modes)")
     ap.add_argument("--seed", type=int, default=0)
@@ -270,7 +272,7 @@ def main():
         print(f"# copy kernel: {src.numel() * 4} bytes", file=sys.stderr, flush=True)
         del src, dst
     m = synth.config2(a.seed)
-    # float64 / float32 schedules pad submatrices to 32, the bf16-family ones to 64
+    # submatrices padded to 32 (--pad 64: the 16-bit schedules on a plan padded to 64)
     budget = int(a.chunk_mb * 2 ** 20 / 4)
     plans = {32: sm.Plan(m, 32, budget), 64: sm.Plan(m, 64, budget)}
     H = torch.from_numpy(m.vals).to(dev)
@@ -289,7 +291,7 @@ def main():
     ref_P = ref_E = None
     for mode in modes:
         o = mode_opts(sm, mode, a)
-        plan = plans[32 if MODES[mode] in ("f64", "f32") else 64]
+        plan = plans[32 if MODES[mode] in ("f64", "f32") else a.pad]
         info = plan.info()
         n, npad = info["n"], info["npad"]
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
@@ -328,7 +330,8 @@ def main():
             oc.comm_probes = 2
             sm.sm_comm_probe(plan, 0, H, mu, oc, work.ws, work.stats)
             res_comm = float(work.stats_host()["res_comm"].max())
-        r = {"ms_per_step": dt / a.steps * 1e3, "res_comm_max": res_comm, "pad_to": 32 if MODES[mode] in ("f64", "f32") else 64, "mu": mu,
+        r = {"ms_per_step": dt / a.steps * 1e3, "res_comm_max": res_comm,
+             "pad_to": 32 if MODES[mode] in ("f64", "f32") else a.pad, "mu": mu,
              "bisection_passes": k, "E": E, "Ne": Ne, "scaling": int(o.scaling), "accel": int(o.accel),
              "learned_accepted": float(np.mean(st["scale_src"] == 2)) if o.scaling == sm.SM_SCALE_LEARNED else None,
              "iters": [int(st["iters"].min()), int(st["iters"].max())],

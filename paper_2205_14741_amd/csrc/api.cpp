@@ -81,6 +81,9 @@ int chunk_tiles(const sm_plan* p, int g0, int nsub) {
 int effective_variant(const sm_plan* p, int mode, int variant) {
   int v = variant >= 0 ? variant : p->tuned[mode];
   if (v >= 3 && (mode == SM_F64 || p->pad_to < 64)) v = 1;
+  // bf16 / f16 / split-bf16 on a plan padded to 32: only the half-depth
+  // stages (k depth 32) divide n_pad
+  if (mode >= SM_BF16 && p->pad_to < 64) v = 2;
   return v;
 }
 
@@ -198,8 +201,6 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   const int storage = ws_storage(o);
   const int f64 = storage == SM_F64;
   const int64_t shadow = storage >= SM_BF16 ? p->shadow_off() : 0;
-  if (o->phase1 >= SM_BF16 && p->pad_to < 64)
-    return set_error(SM_ERR_ARG, "submatrix_sign: bf16 / f16 / split-bf16 phases need a plan padded to 64 or 128");
   if (p->last_storage != storage)
     return set_error(SM_ERR_STATE, "submatrix_sign: the workspace was not built for this precision schedule");
   WsPtrs w = ws_ptrs(p, ws, storage);

@@ -78,6 +78,8 @@ def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
     v = variant
     if v >= 3 and (mode == 0 or pad_to < 64):
         v = 1
+    if mode >= 2 and pad_to < 64:   # 16-bit products on a plan padded to 32
+        v = 2
     if v >= 3:
         return f"sm::ns_gemm128_kernel<{mode}, {which}, {'true' if v == 3 else 'false'}>"
     kdiv = 2 if v == 2 else 1   # variant 2: half-depth LDS stages

@@ -113,10 +113,22 @@ def test_water_multi_tile_f64(pad_to, dev):
     assert dP < 1e-9 and dE < 1e-11 and dNe < 1e-9, (dP, dE, dNe)
 
 
-def test_low_precision_needs_pad_64(dev):
-    m = synth.config1()
-    with pytest.raises(sm.SmError, match="padded to 64"):
-        run_fixed_mu(m, 0.0, "bf16x3", pad_to=32)
+@pytest.mark.parametrize("prec,dp_max", [("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)])
+def test_low_precision_on_pad_32(prec, dp_max, dev):
+    """16-bit products on a plan padded to 32: half of the last tile row /
+    column lies past n_pad, and the half-depth-stage kernel runs whatever
+    variant is requested (the same P for every request)."""
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    P0 = None
+    for variant in (-1, 0, 3):
+        P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=32, variant=variant)
+        assert np.any(plan.info()["npad"] % 64 == 32)
+        dP, dE, dNe = _compare(m, P, E, Ne, mu)
+        assert dP < dp_max and np.all(st["status"] >= 1), (variant, dP)
+        if P0 is None:
+            P0 = P
+        np.testing.assert_array_equal(P, P0)
 
 
 def test_chunked_equals_single_chunk(dev):
