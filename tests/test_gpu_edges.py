@@ -1,0 +1,92 @@
+"""Degenerate and boundary inputs on the GPU path, against the oracle:
+
+* one atom: a single submatrix, n = b = 5, padded with 27 identity rows;
+* no couplings: every submatrix is the atom's own block;
+* every index set the whole system: P is the exact projector;
+* submatrix dimensions exactly at a tile boundary (n = 64, no padding) and
+  one past it (n = 65), for both paddings;
+* NaN in H is reported before any iteration runs.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import submatrix as om
+from paper_2205_14741_amd import smsign as sm
+from gpu_helpers import h_dev, rel, run_fixed_mu
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [("f64", 1e-10), ("f32", 1e-5), ("bf16x3", 1e-4)]   # f64: the iteration stops at ||X^2 - I||_F < 1e-10
+
+
+def _check(m, mu, prec, tol, pad_to=32):
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=pad_to)
+    Po = om.density_matrix(m, mu)
+    Eo, Neo = om.energy_trace(m, Po)
+    dP = float(np.max(np.abs(P - Po)))
+    assert dP < tol, (prec, dP)
+    assert rel(E, Eo) < tol and abs(Ne - Neo) < tol * m.n_orb
+    assert np.all(st["status"] >= 1)
+    return P, plan
+
+
+@pytest.mark.parametrize("prec,tol", PRECS)
+def test_single_atom(prec, tol, dev):
+    onsite = np.array([-2.0, -0.5, 0.7, 1.5, 3.0])
+    m = synth.from_pairs([5], [], [], onsite, n_occ=2)
+    P, plan = _check(m, 0.1, prec, tol)
+    info = plan.info()
+    assert info["n"][0] == 5 and info["npad"][0] == 32
+    np.testing.assert_allclose(P.reshape(5, 5), np.diag([1.0, 1.0, 0.0, 0.0, 0.0]), atol=tol)
+
+
+@pytest.mark.parametrize("prec,tol", PRECS)
+def test_no_couplings(prec, tol, dev):
+    m = synth.lattice_system(3, 4, 0.5, seed=2)          # cutoff below the spacing
+    P, plan = _check(m, 0.0, prec, tol)
+    assert np.all(plan.info()["n"] == 4)
+
+
+@pytest.mark.parametrize("prec,tol", PRECS)
+def test_fully_coupled_is_exact_projector(prec, tol, dev):
+    m = synth.fully_coupled_lattice(seed=4, n_orb=4)     # N = 32: every index set is everything
+    lam, V = np.linalg.eigh(synth.to_dense(m))
+    mu = 0.5 * (lam[m.n_occ - 1] + lam[m.n_occ])
+    P, plan = _check(m, mu, prec, tol)
+    assert np.all(plan.info()["n"] == m.n_orb) and np.all(plan.info()["npad"] == 32)
+    Pex = V[:, :m.n_occ] @ V[:, :m.n_occ].T
+    Pd = synth.to_dense(synth.BlockSparse(**{**m.__dict__, "vals": P}))
+    assert np.max(np.abs(Pd - Pex)) < tol
+
+
+def _two_atoms(b0, b1, seed):
+    rng = np.random.default_rng(seed)
+    blk = 0.3 * rng.standard_normal((b0, b1))
+    onsite = np.concatenate([np.where(np.arange(b) < b // 2, -3.0, 3.0) + 0.3 * rng.standard_normal(b)
+                             for b in (b0, b1)])
+    return synth.from_pairs([b0, b1], [(0, 1)], [blk], onsite, n_occ=b0 // 2 + b1 // 2)
+
+
+@pytest.mark.parametrize("b1,pad_to", [(32, 32), (32, 64), (33, 32), (33, 64)])
+@pytest.mark.parametrize("prec,tol", PRECS)
+def test_tile_boundaries(b1, pad_to, prec, tol, dev):
+    m = _two_atoms(32, b1, seed=b1 + pad_to)
+    P, plan = _check(m, 0.0, prec, tol, pad_to=pad_to)
+    info = plan.info()
+    n = 32 + b1
+    assert np.all(info["n"] == n)
+    assert np.all(info["npad"] == -(-n // pad_to) * pad_to)
+
+
+def test_nonfinite_h_is_reported(dev):
+    import torch
+    m = synth.config1()
+    vals = m.vals.copy()
+    vals[17] = np.nan
+    plan = sm.Plan(m, 32)
+    H = torch.from_numpy(vals).cuda()
+    o = sm.default_opts("f64")
+    work = sm.Workspace(plan, sm.storage_prec(o), H.device)
+    with pytest.raises(sm.SmError, match="NaN"):
+        sm.build_submatrices(plan, 0, H, 0.0, o, work.ws, work.stats)
