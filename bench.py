@@ -29,11 +29,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MODES = {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3", "f16": "f16", "bf16": "bf16"}
+MODES = {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3", "f16": "f16", "bf16": "bf16",
+         "bf16x3n": "bf16x3"}   # "n": no float32 refinement (stagnation stop in split bf16)
 # "<mode>+L": the learned form -- scale and the lower spectral bound l_0 from
 # the scaling network (guarded), scaled Newton-Schulz in the main phase
 for _k in list(MODES):
-    MODES[_k + "+L"] = _k
+    MODES[_k + "+L"] = MODES[_k]
 DT_NAME = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "bf16x3"}
 
 
@@ -69,6 +70,8 @@ def parse():
 def mode_opts(sm, mode, a):
     """Schedule of a benchmark mode."""
     o = sm.default_opts(MODES[mode], graph_iters=a.graph)
+    if mode.split("+")[0].endswith("n"):
+        o.refine_steps = 0
     if mode.endswith("+L"):
         o.scaling, o.power_steps, o.scale_margin, o.accel = sm.SM_SCALE_LEARNED, a.guard_steps, 0.05, 1
     elif a.scaling == "power":
@@ -238,7 +241,8 @@ def precision_form(a):
            "value": res[head]["submatrices_per_s"], "unit": "submatrices/s", "n_gpus": 1, "steps": 1,
            "warmup": 0, "ms_per_step": res[head]["s_per_eval"] * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "data": "synthetic",
-           "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if head != "f32" else ""),
+           "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if mode_opts(sm, head, a).refine_steps > 0
+                                                                    and MODES[head] != "f32" else ""),
            "config": {"workload": "water1000: 1000 water-like molecules (O 13, H 5 orbitals, N=23000), "
                                   "cutoff 3.0, 3000 submatrices n=%d..%d, fixed mu" % (n.min(), n.max()),
                       "mode": head, "seed": a.seed, "chunks": plan.n_chunks},
@@ -395,7 +399,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if MODES[head] in ("bf16x3", "f16", "bf16") else ""),
+        "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if mode_opts(sm, head, a).refine_steps > 0
+                                                                  and MODES[head] != "f32" else ""),
         "data": "synthetic",
         "config": {"workload": "lattice1000: 10x10x10 lattice, 3% vacancies, jitter 0.05, 6 orbitals "
                                "(N=5802), cutoff 2.2, 967 submatrices n=192..276, mu by bisection",
