@@ -198,7 +198,7 @@ def precision_form(a):
         o = mode_opts(sm, mode, a)
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
         print(f"# {mode}: autotuning on chunk 0 ...", file=sys.stderr, flush=True)
-        best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4))
+        best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5))
         print(f"# {mode}: variant {best}; timing one evaluation ...", file=sys.stderr, flush=True)
         sm.sm_profile_read(plan)
         sm.sm_profile_enable(plan, True)

@@ -97,7 +97,9 @@ typedef struct {
                             tiles (float32-accumulating precisions, plans padded to 64 or
                             128; otherwise runs as 1), 4 = 128 x 128 tiles walked in list
                             order (all XCDs on the same submatrices: their operands stay in
-                            the shared last-level cache) */
+                            the shared last-level cache), 5 = as 3 with the operands loaded
+                            three stages ahead (large submatrices).  bf16 / f16 / split-bf16
+                            products on a plan padded to 32 always run as 2 */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,
                             scheduler, updates) into one HIP graph, cached per plan / chunk /
@@ -330,7 +332,7 @@ int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
  * precisions of `opts` (used when opts->variant == -1).  variant_mask: bit v
  * set = try variant v (0 = all).
  *   best_out   host int32 (may be NULL): the chosen variant
- *   times_ms   host double[5] (may be NULL): sign time of each variant (-1: not
+ *   times_ms   host double[6] (may be NULL): sign time of each variant (-1: not
  *              applicable to this plan / precision)
  * Synchronous.  Leaves the workspace holding the last variant's result. */
 int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,

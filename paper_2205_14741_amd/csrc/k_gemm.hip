@@ -685,7 +685,11 @@ template <> struct Traits128<SM_BF16> { using S = float; using L = uint16_t; sta
 template <> struct Traits128<SM_F16> { using S = float; using L = _Float16; static constexpr int K = 32, KP = 8; };
 template <> struct Traits128<SM_BF16X3> { using S = float; using L = uint16_t; static constexpr int K = 32, KP = 8; };
 
-template <int MODE, int WHICH, bool XCD>
+// DEPTH > 1: operand stages are loaded DEPTH stages ahead into a ring of
+// register sets (for large submatrices, whose operand panels come from the
+// last-level cache or HBM with a latency of many stages); the ring restarts
+// at every tile.
+template <int MODE, int WHICH, bool XCD, int DEPTH = 1>
 __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ mats, int64_t shadow_off,
                                                             int shadow_kind,
                                                             const int32_t* __restrict__ count,
@@ -723,13 +727,17 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
     t_begin = (int)((int64_t)total * x8 / kXcds) + (int)blockIdx.x / kXcds;
     t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
   }
-  RT ra[RN], rb[RN];   // carried from tile to tile (next tile's first stage)
+  // DEPTH 1: operand registers carried from tile to tile (the next tile's
+  // first stage is loaded during the last stage of the current one)
+  RT rga[DEPTH][RN], rgb[DEPTH][RN];
   TileRec nxt;
   if (t_begin < t_end) {
     nxt = recs[t_begin];
-    const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
-    s0.a.template load<K, NL>(ra, 0, s0.va);
-    s0.b.template load<K, NL>(rb, 0, s0.vb);
+    if constexpr (DEPTH == 1) {
+      const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+      s0.a.template load<K, NL>(rga[0], 0, s0.va);
+      s0.b.template load<K, NL>(rgb[0], 0, s0.vb);
+    }
   }
   for (int t = t_begin; t < t_end; t += t_step) {
     const TileRec rec = nxt;
@@ -754,18 +762,32 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
 
+    if constexpr (DEPTH > 1) {   // ring prologue: stages 0 .. DEPTH - 1
+#pragma unroll
+      for (int u = 0; u < DEPTH; ++u)
+        if (u < nst) {
+          src.a.template load<K, NL>(rga[u], u, src.va);
+          src.b.template load<K, NL>(rgb[u], u, src.vb);
+        }
+    }
+
     auto k_loop = [&](auto compute_tag) {
       constexpr bool COMPUTE = decltype(compute_tag)::value;
-      for (int s = 0; s < nst; ++s) {
-        const int buf = NBUF == 1 ? 0 : (s & 1);
-        if (NBUF == 1 && s > 0) __syncthreads();   // the previous stage has been read
+      for (int s0 = 0; s0 < nst; s0 += DEPTH)
+#pragma unroll
+      for (int u = 0; u < DEPTH; ++u) {
+        const int s = s0 + u;
+        if (DEPTH > 1 && s >= nst) break;   // uniform
+        const int buf = s & 1;
+        RT (&ra)[RN] = rga[u];
+        RT (&rb)[RN] = rgb[u];
         stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
         stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
         __syncthreads();
-        if (s + 1 < nst) {
-          src.a.template load<K, NL>(ra, s + 1, src.va);
-          src.b.template load<K, NL>(rb, s + 1, src.vb);
-        } else if (has_next) {
+        if (s + DEPTH < nst) {
+          src.a.template load<K, NL>(ra, s + DEPTH, src.va);
+          src.b.template load<K, NL>(rb, s + DEPTH, src.vb);
+        } else if (DEPTH == 1 && has_next) {
           const TileSrc<MODE> sn = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
           sn.a.template load<K, NL>(ra, 0, sn.va);
           sn.b.template load<K, NL>(rb, 0, sn.vb);
@@ -909,9 +931,12 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, int sk, cons
     case 2: return launch_one<MODE, WHICH, 2>(mats, so, sk, count, recs, partials, L);
     case 3:
     case 4:
+    case 5:
       if constexpr (MODE != SM_F64) {
         if (variant == 3)
           return L.go(ns_gemm128_kernel<MODE, WHICH, true>, (float*)mats, so, sk, count, recs, partials);
+        if (variant == 5)
+          return L.go(ns_gemm128_kernel<MODE, WHICH, true, 3>, (float*)mats, so, sk, count, recs, partials);
         return L.go(ns_gemm128_kernel<MODE, WHICH, false>, (float*)mats, so, sk, count, recs, partials);
       } else {
         return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, L);
@@ -954,6 +979,9 @@ static void* ptr_which(int variant) {
       else return kernel_ptr<MODE, WHICH, 1>();
     case 4:
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, false>);
+      else return kernel_ptr<MODE, WHICH, 1>();
+    case 5:
+      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, 3>);
       else return kernel_ptr<MODE, WHICH, 1>();
     default: return kernel_ptr<MODE, WHICH, 0>();
   }

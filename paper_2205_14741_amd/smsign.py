@@ -362,7 +362,7 @@ def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):
     _check(lib().sm_plan_set_mlp(plan.handle, None if mlp is None else mlp.handle))
 
 
-N_VARIANTS = 5
+N_VARIANTS = 6
 
 
 def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, repeats: int = 2,
