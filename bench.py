@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--modes", default="f64,f32,bf16x3,f32+L,bf16x3+L")
     ap.add_argument("--pad", type=int, default=32, choices=[32, 64],
                     help="padding of the submatrices for the 16-bit schedules (float64 / float32: 32)")
+    ap.add_argument("--refine-steps", type=int, default=-1,
+                    help="float32 refinement steps of the 16-bit schedules (-1: the library default)")
+    ap.add_argument("--switch-tol", type=float, default=-1.0,
+                    help="residual at which the 16-bit schedules switch to refinement (-1: default)")
     ap.add_argument("--guard-steps", type=int, default=2,
                     help="power-iteration steps of the learned-scale guard (+L modes)")
     ap.add_argument("--seed", type=int, default=0)
@@ -70,6 +74,11 @@ def parse():
 def mode_opts(sm, mode, a):
     """Schedule of a benchmark mode."""
     o = sm.default_opts(MODES[mode], graph_iters=a.graph)
+    if MODES[mode] in ("bf16", "f16", "bf16x3"):
+        if a.refine_steps >= 0:
+            o.refine_steps = a.refine_steps
+        if a.switch_tol > 0:
+            o.switch_tol = a.switch_tol
     if mode.split("+")[0].endswith("n"):
         o.refine_steps = 0
     if mode.endswith("+L"):

@@ -58,52 +58,79 @@ __device__ __forceinline__ double block_reduce(double v, double* red) {
 }
 
 // Block matrix-vector products y_q = A v_q (q < Q) in float64 for a column-major
-// n x n matrix A with leading dimension lda: lanes take 64 consecutive rows
-// (coalesced column reads), the block's waves split the columns (wave w: c = w,
-// w + nw, ...), four columns in flight per thread; the wave partial sums are
-// combined through LDS in wave order, so the result is deterministic.
-// v_q = v[q * vs + c].  For every row r < n, out(q, r, y_q[r]) is called by a
-// thread of wave 0.  red: LDS scratch of (blockDim / 64) * 64 * Q doubles.
+// n x n matrix A with leading dimension lda (a multiple of 32): each lane takes
+// V consecutive rows of a column with one vector load (V = 4 float32 / 2
+// float64 values for up to two vectors, fewer for more, so that the partial
+// sums stay within 32 KiB of LDS for 8 waves), the block's waves split the
+// columns (wave w: c = w, w + nw, ...) with eight columns in flight per lane;
+// the wave partial sums are combined through LDS in wave order, so the result
+// is deterministic.  v_q = v[q * vs + c].  For every row r < n, out(q, r,
+// y_q[r]) is called by one thread of the block.  red: LDS scratch of
+// matvec_red<Q, T>(waves) doubles.  Rows of a pass past n (up to the next
+// multiple of V, always inside lda) are read and dropped.
+template <int Q, typename T> struct MatvecShape {
+  static constexpr int VT = 16 / (int)sizeof(T);
+  static constexpr int VQ = Q <= 2 ? 4 : (Q <= 4 ? 2 : 1);
+  static constexpr int V = VT < VQ ? VT : VQ;
+  static constexpr int RW = kWave * V;   // rows per pass
+};
+template <int Q, typename T> constexpr int matvec_red(int waves) { return waves * Q * MatvecShape<Q, T>::RW; }
+
 template <int Q, typename T, typename Out>
 __device__ __forceinline__ void block_matvec(const T* __restrict__ A, int64_t lda, int n,
                                              const double* __restrict__ v, int vs, double* red,
                                              Out out) {
+  using Sh = MatvecShape<Q, T>;
+  constexpr int V = Sh::V, RW = Sh::RW, U = 8;
+  typedef T vec __attribute__((ext_vector_type(V)));
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-  for (int r0 = 0; r0 < n; r0 += kWave) {
-    const int r = r0 + lane;
-    double acc[Q];
+  for (int r0 = 0; r0 < n; r0 += RW) {
+    const int rb = r0 + lane * V;
+    double acc[Q][V];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-    if (r < n) {
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[q][e] = 0.0;
+    if (rb < n) {
       int c = w;
-      for (; c + 3 * nw < n; c += 4 * nw) {
-        double x[4];
+      for (; c + (U - 1) * nw < n; c += U * nw) {
+        vec x[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = (double)A[(int64_t)(c + u * nw) * lda + r];
+        for (int u = 0; u < U; ++u) x[u] = *reinterpret_cast<const vec*>(A + (int64_t)(c + u * nw) * lda + rb);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int q = 0; q < Q; ++q) acc[q] += x[u] * v[q * vs + c + u * nw];
+          for (int q = 0; q < Q; ++q) {
+            const double vq = v[q * vs + c + u * nw];
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[q][e] += (double)x[u][e] * vq;
+          }
       }
       for (; c < n; c += nw) {
-        const double x = (double)A[(int64_t)c * lda + r];
+        const vec x = *reinterpret_cast<const vec*>(A + (int64_t)c * lda + rb);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] += x * v[q * vs + c];
+        for (int q = 0; q < Q; ++q) {
+          const double vq = v[q * vs + c];
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[q][e] += (double)x[e] * vq;
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) red[(w * Q + q) * kWave + lane] = acc[q];
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int e = 0; e < V; ++e) red[(w * Q + q) * RW + lane * V + e] = acc[q][e];
     __syncthreads();
-    if (w == 0 && r < n) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        double s = 0.0;
-        for (int k = 0; k < nw; ++k) s += red[(k * Q + q) * kWave + lane];
-        out(q, r, s);
-      }
-    }
+    for (int q = 0; q < Q; ++q)
+      for (int rr = threadIdx.x; rr < RW; rr += blockDim.x)
+        if (r0 + rr < n) {
+          double s = 0.0;
+          for (int k = 0; k < nw; ++k) s += red[(k * Q + q) * RW + rr];
+          out(q, r0 + rr, s);
+        }
     __syncthreads();
   }
 }

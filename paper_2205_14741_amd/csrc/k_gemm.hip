@@ -321,8 +321,20 @@ __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
 // all eight.
 constexpr int kXcds = 8;
 
+// Workgroups of the 64-tile kernel that its LDS stages leave room for on a
+// compute unit (160 KiB), at most 4.  Each workgroup puts one wave on every
+// SIMD, so this is also the number of waves per SIMD the register budget is
+// held to (4: at most 128 registers per lane).
+template <int MODE, int KDIV> struct GemmOcc {
+  using Tr = Traits<MODE>;
+  static constexpr int NOP = MODE == SM_BF16X3 ? 4 : 2;
+  static constexpr int kLds = 2 * NOP * 64 * (Tr::K / KDIV + Tr::KP) * (int)sizeof(typename Tr::L);
+  static constexpr int by_lds = 160 * 1024 / kLds;
+  static constexpr int value = by_lds < 4 ? by_lds : 4;
+};
+
 template <int MODE, int WHICH, int KDIV, bool XCD>
-__global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::S* __restrict__ mats,
+__global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_kernel(typename Traits<MODE>::S* __restrict__ mats,
                                                          int64_t shadow_off, int shadow_kind,
                                                          const int32_t* __restrict__ count,
                                                          const TileRec* __restrict__ recs,
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
   using RT = typename std::conditional<PRE, uint32_t, S>::type;
   constexpr int RN = PRE ? NPL * NL / 2 : NL;   // registers per operand per stage
   __shared__ __attribute__((aligned(16))) LT lds[2][NOP][64 * LD];
-  __shared__ double red[4];
+  static_assert(sizeof(lds) == (size_t)GemmOcc<MODE, KDIV>::kLds, "LDS footprint");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -514,6 +526,15 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
     // be multiplied by -2 in every iteration instead of being left alone. ----
     double part = 0.0;
     const int kq = lane >> 4;
+    // the four wave sums of the residual meet in the stage buffer the last
+    // stage did not use (past the result staging of the 16-bit epilogue)
+    constexpr size_t kStageB = sizeof(lds[0]);
+    constexpr size_t kStaged = Pre<MODE>::value ? 4 * 32 * 33 * sizeof(float) : 0;
+    constexpr bool kIdleFits = kStageB >= kStaged + 4 * sizeof(double);
+    static_assert(2 * kStageB >= kStaged + 4 * sizeof(double), "residual slots");
+    double* red = reinterpret_cast<double*>(
+        kIdleFits ? reinterpret_cast<char*>(&lds[nst & 1][0][0]) + kStaged
+                  : reinterpret_cast<char*>(&lds[0][0][0]) + kStaged);
     if constexpr (MODE == SM_F64) {
 #pragma unroll
       for (int x = 0; x < (wvalid ? 2 : 0); ++x)
@@ -552,13 +573,10 @@ __global__ __launch_bounds__(kBlock) void ns_gemm_kernel(typename Traits<MODE>::
       // (contiguous 16-byte stores instead of scattered 2-byte ones).  The stage buffer the last stage
       // did not use is free; with half-depth stages one buffer is too small
       // and the whole array is used after a barrier.
-      constexpr size_t kStage = sizeof(lds[0]);
-      constexpr size_t kNeed = 4 * 32 * 33 * sizeof(float);
       float* stg;
-      if constexpr (kStage >= kNeed) {
+      if constexpr (kIdleFits) {
         stg = reinterpret_cast<float*>(&lds[nst & 1][0][0]);
       } else {
-        static_assert(2 * kStage >= kNeed, "epilogue staging");
         __syncthreads();
         stg = reinterpret_cast<float*>(&lds[0][0][0]);
       }
@@ -689,8 +707,19 @@ template <> struct Traits128<SM_BF16X3> { using S = float; using L = uint16_t; s
 // register sets (for large submatrices, whose operand panels come from the
 // last-level cache or HBM with a latency of many stages); the ring restarts
 // at every tile.
+// Register budget of the 128-tile kernel: two waves per SIMD (at most 256
+// registers per lane) where the LDS stages let two workgroups share a compute
+// unit; the deep ring (DEPTH > 1) takes more registers and runs one.
+template <int MODE, int DEPTH> struct Gemm128Occ {
+  using Tr = Traits128<MODE>;
+  static constexpr int NOP = MODE == SM_BF16X3 ? 4 : 2;
+  static constexpr int kLds = 2 * NOP * 128 * (Tr::K + Tr::KP) * (int)sizeof(typename Tr::L);
+  static constexpr int by_lds = 160 * 1024 / kLds;
+  static constexpr int value = DEPTH > 1 ? 1 : (by_lds < 2 ? by_lds : 2);
+};
+
 template <int MODE, int WHICH, bool XCD, int DEPTH = 1>
-__global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ mats, int64_t shadow_off,
+__global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_gemm128_kernel(float* __restrict__ mats, int64_t shadow_off,
                                                             int shadow_kind,
                                                             const int32_t* __restrict__ count,
                                                             const TileRec* __restrict__ recs,
@@ -711,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
   // which lets two split-bf16 workgroups share a CU, measured slower)
   constexpr int NBUF = 2;
   __shared__ __attribute__((aligned(16))) LT lds[NBUF][NOP][128 * LD];
-  __shared__ double red[4];
+  static_assert(sizeof(lds) == (size_t)Gemm128Occ<MODE, DEPTH>::kLds, "LDS footprint");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -856,8 +885,11 @@ __global__ __launch_bounds__(kBlock) void ns_gemm128_kernel(float* __restrict__ 
     };
     if (wvalid) k_loop(std::true_type{}); else k_loop(std::false_type{});
 
-    // epilogue: lower triangle mirrored (exactly symmetric result)
+    // epilogue: lower triangle mirrored (exactly symmetric result); the
+    // wave sums of the residual meet in the stage buffer the last stage did
+    // not use
     double part = 0.0;
+    double* red = reinterpret_cast<double*>(&lds[nst & 1][0][0]);
 #pragma unroll
     for (int x = 0; x < (wvalid ? 4 : 0); ++x)
 #pragma unroll

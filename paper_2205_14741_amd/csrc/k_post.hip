@@ -62,7 +62,7 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
                                                      double* __restrict__ vecs,
                                                      sm_sub_stats* __restrict__ stats) {
   constexpr int Q = P > 0 ? P : 1;
-  __shared__ double red[8 * kWave * Q];
+  __shared__ double red[matvec_red<Q, T>(8)];
   __shared__ double red2[8];
   const int l = blockIdx.x;
   const int g = g0 + l;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void comm_probe_kernel(DevPlan p, int g0, cons
                                                          double* __restrict__ vecs,
                                                          sm_sub_stats* __restrict__ stats) {
   extern __shared__ int smem[];
-  __shared__ double red[4 * kWave * P];
+  __shared__ double red[matvec_red<P, T>(4)];
   __shared__ double red2[8];
   const int l = blockIdx.x;
   const int g = g0 + l;

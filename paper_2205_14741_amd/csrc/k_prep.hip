@@ -197,7 +197,7 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     double* __restrict__ lb0_out,
                                                     double* __restrict__ top0_out) {
   __shared__ double red[16];
-  __shared__ double mv[8 * kWave];
+  __shared__ double mv[matvec_red<1, T>(8)];
   const int l = blockIdx.x;
   const int g = g0 + l;
   const int i = p.order_g[g];
