@@ -205,7 +205,9 @@ int sm_plan_info(const sm_plan* plan, int32_t* n_out, int32_t* npad_out, int32_t
  *   H_vals  device float64 [p_nnz_vals], panel layout.
  *   ws      device workspace of ws_bytes (caller-owned, reused across chunks).
  *   stats   device sm_sub_stats[n_atoms] indexed by submatrix id.
- * SM_ERR_NONFINITE (synchronous check of a device flag) if T_i holds NaN/Inf. */
+ * Asynchronous on `stream`: a NaN/Inf in some T_i is flagged by the device in
+ * host-mapped memory and reported (SM_ERR_NONFINITE) by the submatrix_sign
+ * call that follows. */
 int build_submatrices(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
                       const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, void* stream);
 
@@ -213,8 +215,11 @@ int build_submatrices(sm_plan* plan, int32_t chunk, const double* H_vals, double
  * Newton-Schulz iteration X <- 1/2 X (3I - X^2) under the precision schedule of
  * opts, all submatrices batched into the same launches; a device scheduler
  * retires converged submatrices.  Writes the per-submatrix records in `stats`.
- * Non-convergence is reported in stats[i].status, not as an error.  Blocks the
- * host only to poll the number of active submatrices. */
+ * Non-convergence is reported in stats[i].status, not as an error;
+ * SM_ERR_NONFINITE if the preceding build_submatrices found NaN/Inf in a T_i
+ * (checked at the first poll, the queued work is left to finish).  Blocks the
+ * host only to poll, once per iteration, the scheduler's count of submatrices
+ * that continue (it returns as soon as that count is zero). */
 int submatrix_sign(sm_plan* plan, int32_t chunk, void* ws, const sm_sign_opts* opts,
                    sm_sub_stats* stats, void* stream);
 

@@ -75,6 +75,15 @@ int chunk_tiles(const sm_plan* p, int g0, int nsub) {
   return (int)std::min<int64_t>(t, 1 << 30);
 }
 
+int chunk_max_tiles_sub(const sm_plan* p, int g0, int nsub) {
+  int m = 0;
+  for (int g = g0; g < g0 + nsub; ++g) {
+    const int T = tiles_of(p->npad_g[g]);
+    m = std::max(m, T * (T + 1) / 2);
+  }
+  return m;
+}
+
 // Launch one Newton-Schulz GEMM, bracketed by timing events when profiling.
 // Variant that actually runs: the 128-wide tiles need n_pad % 64 == 0 and a
 // float32-accumulating precision, otherwise the XCD-aware 64-wide kernel.
@@ -167,10 +176,14 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   const int64_t shadow = storage >= SM_BF16 ? p->shadow_off() : 0;
   WsPtrs w = ws_ptrs(p, ws, storage);
   hipStream_t s = as_stream(stream);
-  SM_HIP(launch_fill_i32(w.flag, 0, 1, s));
+  // the gather flags NaN / Inf in T straight into mapped host memory (reset
+  // here in stream order); submatrix_sign reads it once its first poll has
+  // waited past the gather
+  int32_t* flag = p->d_pinned + 8;
+  SM_HIP(launch_fill_i32(flag, 0, 1, s));
   double* cg = w.scratch;                                 // [max_subs]
   float* pred = reinterpret_cast<float*>(w.scratch + p->max_subs);  // [2 max_subs]
-  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, w.flag, w.features, cg,
+  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, flag, w.features, cg,
                        stats, s));
   const float* predp = nullptr;
   if (o->scaling == SM_SCALE_LEARNED) {
@@ -182,11 +195,7 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
                       cg, predp, stats, storage >= SM_BF16 ? storage : 0, shadow, o->lbound,
                       w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, s));
-  SM_HIP(hipMemcpyAsync(&p->h_pinned[8], w.flag, 4, hipMemcpyDeviceToHost, s));
-  SM_HIP(hipStreamSynchronize(s));
   p->last_storage = storage;
-  if (p->h_pinned[8] != 0)
-    return set_error(SM_ERR_NONFINITE, "build_submatrices: NaN/Inf in submatrix of atom %d", p->h_pinned[8] - 1);
   return SM_OK;
 }
 
@@ -209,65 +218,88 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   int32_t* L0 = w.lists;
   auto list_count = [&](int L) { return L0 + L * stride; };
   const int max_tiles = chunk_tiles(p, g0, nsub);
+  const int max_tiles_sub = chunk_max_tiles_sub(p, g0, nsub);
   const int mode_main = o->phase1;
   const int mode_ref = o->refine;
   const bool has_ref = o->refine_steps > 0;
-  TileRec* rec_main = w.tiles;
-  TileRec* rec_ref = w.tiles + p->max_tiles;
   const int ms = (int)p->max_subs;
   const int tsh_main = tile_shift(effective_variant(p, mode_main, o->variant), mode_main);
   const int tsh_ref = tile_shift(effective_variant(p, mode_ref, o->variant), mode_ref);
-  // expand lists (Lm, Lr) into tile records, then run the GEMMs of kind `which`
+  // tile records by list: 0 / 1 updates, 2 / 3 squares (main / refinement)
+  auto recs_of = [&](int L) { return w.tiles + (int64_t)L * p->max_tiles; };
   // the main phase's products keep only 16-bit copies of their results, so
   // a submatrix's first refinement update reads those (tile flag)
   const int shadow_kind = storage >= SM_BF16 ? storage : 0;
-  auto phase = [&](int Lm, int Lr, int which) -> int {
-    const int first_ref = (which == 1 && shadow_kind) ? o->refine_steps - 1 : -1;
-    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, Lm, Lr, rec_main, has_ref ? rec_ref : nullptr,
-                         tsh_main, tsh_ref, which, first_ref, nsub, s));
+  const int first_ref = shadow_kind ? o->refine_steps - 1 : -1;
+  // the scheduler's lists -> tile records of this iteration's updates and
+  // the next iteration's squares (one launch)
+  auto expand = [&]() -> int {
+    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, w.tiles, p->max_tiles, tsh_main, tsh_ref, first_ref,
+                         has_ref, nsub, s));
+    return SM_OK;
+  };
+  // the GEMMs of kind `which` over lists Lm (main precision) and Lr
+  // (refinement); a list the host knows to be empty is not launched
+  auto gemms = [&](int Lm, int Lr, int which, bool run_main, bool run_ref) -> int {
     int r;
-    if ((r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, 0, list_count(Lm), rec_main,
-                         w.partials, max_tiles, s)))
+    if (run_main && (r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, 0, list_count(Lm),
+                                     recs_of(Lm), w.partials, max_tiles, s)))
       return r;
-    if (has_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, shadow_kind,
-                                    list_count(Lr), rec_ref, w.partials, max_tiles, s)))
+    if (has_ref && run_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, shadow_kind,
+                                               list_count(Lr), recs_of(Lr), w.partials, max_tiles, s)))
       return r;
     return SM_OK;
   };
-
-  // one iteration of the loop: squares, residuals + scheduler, updates
-  auto iteration = [&](hipStream_t st) -> int {
-    int r;
+  auto schedule = [&](int first, int32_t* live_host) -> int {
+    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, first, tsh_main, tsh_ref,
+                           first ? w.scratch + 2 * p->max_subs : nullptr,
+                           first ? w.scratch + 3 * p->max_subs : nullptr, live_host, max_tiles_sub, s));
+    return SM_OK;
+  };
+  // one iteration: squares (A = X^2, Y = 3I - A), residuals + scheduler,
+  // tile records, updates (X' = 1/2 X Y).  live_host / ev: the scheduler's
+  // counts and an event recorded after it; sq_main / sq_ref: whether the
+  // square lists may be non-empty.
+  auto iteration = [&](hipStream_t st, int32_t* live_host, hipEvent_t ev, bool sq_main, bool sq_ref) -> int {
     hipStream_t keep = s;
     s = st;
-    r = phase(2, 3, 0);                                                   // A = X^2, Y = 3I - A
-    if (!r) {
-      hipError_t e = launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref,
-                                     nullptr, nullptr, nullptr, st);
-      if (e != hipSuccess) r = hip_error(e, "launch_schedule");
+    int r = gemms(2, 3, 0, sq_main, sq_ref);
+    if (!r) r = schedule(0, live_host);
+    if (!r && ev) {
+      hipError_t e = hipEventRecord(ev, st);
+      if (e != hipSuccess) r = hip_error(e, "hipEventRecord");
     }
-    if (!r) r = phase(0, 1, 1);                                           // X' = 1/2 X Y
+    if (!r) r = expand();
+    if (!r) r = gemms(0, 1, 1, true, true);
     s = keep;
     return r;
   };
+  // a NaN / Inf in T (flagged by the gather) ends the call at the first poll
+  auto nonfinite = [&]() -> int {
+    const int32_t f = p->h_pinned[8];
+    if (f != 0) return set_error(SM_ERR_NONFINITE, "submatrix_sign: NaN/Inf in submatrix of atom %d", f - 1);
+    return SM_OK;
+  };
 
-  // bounds on the spectrum of X_0 written by build_submatrices (scaled Newton-Schulz)
-  SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 1, tsh_main, tsh_ref,
-                         w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, nullptr, s));
+  // bounds on the spectrum of X_0 written by build_submatrices (scaled
+  // Newton-Schulz), then the first squares' records
+  if ((rc = schedule(1, nullptr)) || (rc = expand())) return rc;
   const int lim = o->max_iter + o->refine_steps + 2;
   const int G = p->profiling ? 0 : o->graph_iters;
   if (G == 0) {
+    // the host waits for each iteration's scheduler while that iteration's
+    // updates run, stops as soon as no submatrix squares again, and launches
+    // only the square GEMMs whose lists the scheduler filled
+    bool sq_main = true, sq_ref = true;
     for (int it = 0; it <= lim; ++it) {
-      if ((rc = phase(2, 3, 0))) return rc;          // squares: A = X^2, Y = 3I - A
-      // the scheduler writes the live count into the host word of this parity
-      SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, 0, tsh_main, tsh_ref,
-                             nullptr, nullptr, p->d_pinned + (it & 1), s));
-      SM_HIP(hipEventRecord(p->ev[it & 1], s));
-      if ((rc = phase(0, 1, 1))) return rc;          // updates: X' = 1/2 X Y
-      if (it >= 1) {
-        SM_HIP(hipEventSynchronize(p->ev[(it - 1) & 1]));
-        if (p->h_pinned[(it - 1) & 1] == 0) break;
-      }
+      const int slot = kHostCounts + 4 * (it & 1);
+      if ((rc = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref))) return rc;
+      SM_HIP(hipEventSynchronize(p->ev[it & 1]));
+      if (it == 0 && (rc = nonfinite())) return rc;
+      const int32_t* hc = p->h_pinned + slot;
+      if (hc[0] == 0) break;
+      sq_main = hc[1] > 0;
+      sq_ref = hc[2] > 0;
     }
   } else {
     // find or capture the graph of G iterations for this chunk / workspace / schedule
@@ -282,7 +314,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
         for (int wh = 0; wh < 2; ++wh) (void)ns_gemm_blocks_per_cu(m, wh, effective_variant(p, m, o->variant));
       SM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
       int r = SM_OK;
-      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream);
+      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream, nullptr, nullptr, true, true);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
       if (r) {
@@ -304,8 +336,13 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       SM_HIP(hipEventRecord(p->ev[r & 1], s));
       if (r >= 1) {
         SM_HIP(hipEventSynchronize(p->ev[(r - 1) & 1]));
+        if (r == 1 && (rc = nonfinite())) return rc;
         if (p->h_pinned[(r - 1) & 1] == 0) break;
       }
+    }
+    if (replays == 1) {
+      SM_HIP(hipEventSynchronize(p->ev[0]));
+      if ((rc = nonfinite())) return rc;
     }
   }
   if (shadow_kind)   // final X of submatrices that ended in the main phase

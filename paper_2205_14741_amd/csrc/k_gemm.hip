@@ -633,19 +633,24 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   }
 }
 
-// Tile records of the submatrices in lists `list_main` / `list_ref`: one
-// workgroup per (listed submatrix, list).  Tiles have edge 1 << tshift (64 or
-// 128); residual partial slots are always those of the 64-tiles.
+// Tile records of every list the scheduler just built, in one launch: one
+// workgroup per (listed submatrix, list).  blockIdx.y picks the list: 0
+// updates (main precision), 1 squares of the next iteration (main), 2 / 3 the
+// same in the refinement precision.  List L's records go to recs + L *
+// max_tiles.  Tiles have edge 1 << tshift (64 or 128); residual partial slots
+// are always those of the 64-tiles.
 __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const SubState* __restrict__ st,
                                                      const int32_t* __restrict__ lists, int max_subs,
-                                                     int list_main, int list_ref,
-                                                     TileRec* __restrict__ recs_main,
-                                                     TileRec* __restrict__ recs_ref, int tshift_main,
-                                                     int tshift_ref, int which, int first_ref) {
+                                                     TileRec* __restrict__ recs, int64_t max_tiles,
+                                                     int tshift_main, int tshift_ref, int first_ref) {
   const int stride = 2 + 2 * max_subs + 1;
-  const int32_t* Lb = lists + (blockIdx.y == 0 ? list_main : list_ref) * stride;
-  TileRec* out = blockIdx.y == 0 ? recs_main : recs_ref;
-  const int tshift = blockIdx.y == 0 ? tshift_main : tshift_ref;
+  const int y = blockIdx.y;
+  const int L = (y & 1) ? 2 + (y >> 1) : (y >> 1);   // 0, 2, 1, 3
+  const bool ref = (L & 1) != 0;
+  const int which = L < 2 ? 1 : 0;
+  const int32_t* Lb = lists + L * stride;
+  TileRec* out = recs + L * max_tiles;
+  const int tshift = ref ? tshift_ref : tshift_main;
   const int a = blockIdx.x;
   if (a >= Lb[1]) return;
   const int l = Lb[2 + a];
@@ -658,7 +663,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int64_t mo = p.mat_off_g[g];
   const int it = st[l].iters;
   const float alpha = (float)(which == 0 ? st[l].alpha_sq : st[l].alpha_upd);
-  const int16_t flags = (blockIdx.y == 1 && first_ref >= 0 && st[l].refine_left == first_ref) ? kTileFromShadow : 0;
+  const int16_t flags = (L == 1 && first_ref >= 0 && st[l].refine_left == first_ref) ? kTileFromShadow : 0;
   const int po = p.tile_off_g[g];
   const int t64 = tiles_of(npad);
   for (int lt = threadIdx.x; lt < nt; lt += blockDim.x) {
@@ -678,14 +683,12 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   }
 }
 
-hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
-                         int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int tshift_main, int tshift_ref, int which, int first_ref,
-                         int grid_subs, hipStream_t s) {
+hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists, int max_subs,
+                         TileRec* recs, int64_t max_tiles, int tshift_main, int tshift_ref, int first_ref,
+                         bool with_ref, int grid_subs, hipStream_t s) {
   if (grid_subs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, recs_ref ? 2 : 1), dim3(256), 0, s, p, g0, st, lists,
-                     max_subs, list_main, list_ref, recs_main, recs_ref, tshift_main, tshift_ref, which,
-                     first_ref);
+  hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, with_ref ? 4 : 2), dim3(256), 0, s, p, g0, st, lists,
+                     max_subs, recs, max_tiles, tshift_main, tshift_ref, first_ref);
   return hipGetLastError();
 }
 
@@ -1073,27 +1076,40 @@ __device__ __forceinline__ double ns_map_inv(double y) { return 2.0 * sin(asin(f
 enum { DEC_UPD = 1, DEC_SQ = 2, DEC_REF = 4 };
 
 // exclusive scan over the block; returns the block total in `total`
-__device__ int block_excl_scan(int v, int* sh, int& total) {
+// Exclusive prefix sums of K per-thread counts over the block, all K in one
+// pass (wave scans by shuffles, one exchange of wave totals through LDS).
+// sh: K * 16 ints of LDS.
+template <int K>
+__device__ void block_excl_scan(const int (&v)[K], int (&ex)[K], int (&total)[K], int* sh) {
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  int x = v;
+  int x[K];
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
+  for (int k = 0; k < K; ++k) x[k] = v[k];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int y = __shfl_up(x[k], o, 64);
+      if (lane >= o) x[k] += y;
+    }
+  __syncthreads();   // the previous call's readers are done with sh
+  if (lane == 63)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * 16 + wid] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    int off = 0, t = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int c = sh[k * 16 + w];
+      if (w < wid) off += c;
+      t += c;
+    }
+    ex[k] = off + x[k] - v[k];
+    total[k] = t;
   }
-  __syncthreads();
-  if (lane == 63) sh[wid] = x;
-  __syncthreads();
-  int off = 0;
-  total = 0;
-  for (int w = 0; w < nw; ++w) {
-    if (w < wid) off += sh[w];
-    total += sh[w];
-  }
-  __syncthreads();
-  return off + x - v;
 }
 
 // A wavefront per submatrix: the residual ||X^2 - I||_F of the square just
@@ -1117,14 +1133,17 @@ __global__ __launch_bounds__(256) void residual_kernel(DevPlan p, int g0, int ns
 // rules to the new residual, advance the counters, and compact the
 // submatrices into four tile lists by ordered block scans: update in the
 // main / refinement precision, square (next iteration) in the main /
-// refinement precision.
+// refinement precision.  fuse_res: the residual of each square is summed
+// here, by the submatrix's thread over its tile partials in tile order
+// (chunks with few tiles per submatrix); otherwise residual_kernel ran first.
 __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int nsub, SubState* st,
+                                                        const double* __restrict__ partials, int fuse_res,
                                                         int32_t* lists, int max_subs, SchedOpts o,
                                                         int first, int tshift_main, int tshift_ref,
                                                         const double* __restrict__ lb0,
                                                         const double* __restrict__ top0,
                                                         int32_t* live_host) {
-  __shared__ int sh[16];
+  __shared__ int sh[8 * 16];
   const int stride = 2 + 2 * max_subs + 1;
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
   for (int base = 0; base < nsub; base += blockDim.x) {
@@ -1133,6 +1152,14 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
     if (l < nsub) {
       SubState s = st[l];
       const int np = p.npad_g[g0 + l];
+      if (!first && fuse_res && s.active) {
+        const int T64 = tiles_of(np);
+        const int nt = T64 * (T64 + 1) / 2;
+        const double* pp = partials + p.tile_off_g[g0 + l];
+        double r = 0.0;
+        for (int k = 0; k < nt; ++k) r += pp[k];
+        s.res_new = sqrt(fmax(r, 0.0));
+      }
       const int Tm = (np + (1 << tshift_main) - 1) >> tshift_main;
       const int Tr = (np + (1 << tshift_ref) - 1) >> tshift_ref;
       ntm = Tm * (Tm + 1) / 2;
@@ -1220,23 +1247,27 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       }
       st[l] = s;
     }
+    bool in[4];
+    int cnt[8], ex[8], tot[8];
 #pragma unroll
     for (int L = 0; L < 4; ++L) {
-      const bool in = (L == 0) ? ((dec & DEC_UPD) && !(dec & DEC_REF))
-                    : (L == 1) ? ((dec & DEC_UPD) && (dec & DEC_REF))
-                    : (L == 2) ? ((dec & DEC_SQ) && !(dec & DEC_REF))
-                               : ((dec & DEC_SQ) && (dec & DEC_REF));
-      const int nt = (L & 1) ? ntr : ntm;
-      int tot_s, tot_t;
-      const int ps = block_excl_scan(in ? 1 : 0, sh, tot_s);
-      const int pt = block_excl_scan(in ? nt : 0, sh, tot_t);
+      in[L] = (L == 0) ? ((dec & DEC_UPD) && !(dec & DEC_REF))
+            : (L == 1) ? ((dec & DEC_UPD) && (dec & DEC_REF))
+            : (L == 2) ? ((dec & DEC_SQ) && !(dec & DEC_REF))
+                       : ((dec & DEC_SQ) && (dec & DEC_REF));
+      cnt[2 * L] = in[L] ? 1 : 0;
+      cnt[2 * L + 1] = in[L] ? ((L & 1) ? ntr : ntm) : 0;
+    }
+    block_excl_scan<8>(cnt, ex, tot, sh);
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
       int32_t* Lb = lists + L * stride;
-      if (in) {
-        Lb[2 + run_subs[L] + ps] = l;
-        Lb[2 + max_subs + run_subs[L] + ps] = run_tiles[L] + pt;
+      if (in[L]) {
+        Lb[2 + run_subs[L] + ex[2 * L]] = l;
+        Lb[2 + max_subs + run_subs[L] + ex[2 * L]] = run_tiles[L] + ex[2 * L + 1];
       }
-      run_subs[L] += tot_s;
-      run_tiles[L] += tot_t;
+      run_subs[L] += tot[2 * L];
+      run_tiles[L] += tot[2 * L + 1];
     }
   }
   if (threadIdx.x == 0) {
@@ -1247,22 +1278,31 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       Lb[1] = run_subs[L];
       Lb[2 + max_subs + run_subs[L]] = run_tiles[L];
     }
-    // number of submatrices still in flight, for the host's stopping poll
-    const int live = run_subs[0] + run_subs[1] + run_subs[2] + run_subs[3];
+    // submatrices that square again (work after this iteration's updates),
+    // for the host's stopping poll
+    const int live = run_subs[2] + run_subs[3];
     lists[4 * stride] = live;
-    if (live_host) *live_host = live;
+    if (live_host) {   // [live, square tiles main, square tiles refinement]
+      live_host[0] = live;
+      live_host[1] = run_tiles[2];
+      live_host[2] = run_tiles[3];
+    }
   }
 }
 
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
-                           const double* lb0, const double* top0, int32_t* live_host, hipStream_t s) {
+                           const double* lb0, const double* top0, int32_t* live_host, int max_tiles_sub,
+                           hipStream_t s) {
   SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
-  if (!first && nsub > 0)
+  // up to 64 partials per submatrix the scheduler's threads add them up
+  // themselves; more are reduced by a wavefront each first
+  const int fuse = max_tiles_sub <= 64;
+  if (!first && !fuse && nsub > 0)
     hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
-  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, lists, max_subs, o, first,
-                     tshift_main, tshift_ref, lb0, top0, live_host);
+  hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, partials, fuse, lists,
+                     max_subs, o, first, tshift_main, tshift_ref, lb0, top0, live_host);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ struct ColStats {
 // LDS: atoms of I_i and their row offsets (2 m ints), one row map of n_pad
 // ints per wave.
 template <typename T>
-__global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
+__global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
                                                      double mu, T* __restrict__ mats, int* nonfinite,
                                                      float* __restrict__ features, double* __restrict__ cg_out,
                                                      sm_sub_stats* __restrict__ stats) {
@@ -89,27 +89,37 @@ __global__ __launch_bounds__(256) void gather_kernel(DevPlan p, int g0, const do
     const int hj = p.height[j];
     build_row_map(p, j, s_atom, s_off, m, n, s_src);
     const double* panel = H + p.panel_off[j];
-    for (int q = 0; q < bj; ++q) {
-      const int c = locj + q;
-      const double* pc = panel + (int64_t)q * hj;
-      T* xc = X + (int64_t)c * npad;
-      double sa = 0.0, sq = 0.0, dl = 0.0;
+    // four columns of the atom at a time: one row-map read and four
+    // independent panel loads per row
+    for (int q0 = 0; q0 < bj; q0 += 4) {
+      double sa[4] = {0.0, 0.0, 0.0, 0.0}, sq[4] = {0.0, 0.0, 0.0, 0.0}, dl[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
       for (int d = lane; d < npad; d += kWave) {
-        double v = 0.0;
-        if (d < n) {
-          const int s = s_src[d];
-          if (s >= 0) v = pc[s];
-          if (d == c) {
-            v -= mu;
-            dl = v;
+        const int s = d < n ? s_src[d] : -1;
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (q0 + u < bj && s >= 0) ? panel[(int64_t)(q0 + u) * hj + s] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int c = locj + q0 + u;
+          if (q0 + u < bj) {
+            double x = v[u];
+            if (d == c) {   // c < n, so only rows of T_i
+              x -= mu;
+              dl[u] = x;
+            }
+            bad |= !isfinite(x);
+            sa[u] += fabs(x);
+            sq[u] += x * x;
+            X[(int64_t)c * npad + d] = (T)x;
           }
         }
-        bad |= !isfinite(v);
-        sa += fabs(v);
-        sq += v * v;
-        xc[d] = (T)v;
       }
-      cs.add(wave_sum(sa), wave_sum(sq), wave_sum(dl), c >= loc && c < loc + bsz);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = locj + q0 + u;
+        if (q0 + u < bj) cs.add(wave_sum(sa[u]), wave_sum(sq[u]), wave_sum(dl[u]), c >= loc && c < loc + bsz);
+      }
     }
     wave_sync();   // the row map is rebuilt for the wave's next atom
   }

@@ -69,7 +69,7 @@ sm::WsLayout sm_plan::layout(int storage) const {
   // 4 lists: count_tiles, count_subs, list[max_subs], prefix[max_subs+1]
   off = align256(off + 4 * (2 + max_subs + max_subs + 1) * 4 + 64);
   L.tiles = off;
-  off = align256(off + 2 * max_tiles * (int64_t)sizeof(TileRec));
+  off = align256(off + 4 * max_tiles * (int64_t)sizeof(TileRec));
   L.features = off;
   off = align256(off + max_subs * kNumFeatures * 4);
   L.scratch = off;
@@ -337,8 +337,8 @@ int ensure_device(sm_plan* p) {
   if ((rc = dev_alloc(p, (size_t)p->n_atoms, &p->d_ne_sub)) != SM_OK) return rc;
   if ((rc = dev_alloc(p, (size_t)2 * p->n_atoms, &p->d_gersh)) != SM_OK) return rc;
   // coherent and mapped: the scheduler writes the live count straight into it
-  SM_HIP(hipHostMalloc((void**)&p->h_pinned, 64, hipHostMallocMapped | hipHostMallocCoherent));
-  std::memset(p->h_pinned, 0, 64);
+  SM_HIP(hipHostMalloc((void**)&p->h_pinned, kHostWords * 4, hipHostMallocMapped | hipHostMallocCoherent));
+  std::memset(p->h_pinned, 0, kHostWords * 4);
   SM_HIP(hipHostGetDevicePointer((void**)&p->d_pinned, p->h_pinned, 0));
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)

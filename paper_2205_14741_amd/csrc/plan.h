@@ -7,6 +7,9 @@
 #include "mlp.h"
 #include "smsign_internal.h"
 
+constexpr int kHostWords = 64;
+constexpr int kHostCounts = 16;
+
 struct sm_plan {
   // pattern (copied from the caller)
   int32_t n_atoms = 0;
@@ -47,7 +50,10 @@ struct sm_plan {
   double* d_trace_parts = nullptr;  // [2 * kTraceBlocks + 2]
   double* d_ne_sub = nullptr;       // [n_atoms]
   double* d_gersh = nullptr;        // [2 * n_atoms]
-  int32_t* h_pinned = nullptr;      // pinned, device-mapped host words [16]
+  int32_t* h_pinned = nullptr;      // pinned, device-mapped host words [kHostWords]:
+                                    // [0, 2) graph-path live counts, [8] nonfinite flag,
+                                    // [10, 14) E and Ne, [kHostCounts, +8) scheduler
+                                    // counts (live, square tiles main / refinement) by parity
   int32_t* d_pinned = nullptr;      // the device's address of h_pinned
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_storage = -1;            // workspace storage of the last build (ws_storage; -1: none)

@@ -75,11 +75,12 @@ struct WsLayout {
   int64_t state;       // SubState[max_subs]
   int64_t partials;    // double[max_tiles]
   int64_t lists;       // int32: counts[4], list[2][max_subs], prefix[2][max_subs+1]
-  int64_t tiles;       // TileRec[2][max_tiles]: tile records of the main / refinement GEMMs
+  int64_t tiles;       // TileRec[4][max_tiles]: tile records of the four lists (updates main /
+                       // refinement, squares main / refinement), indexed by list
   int64_t features;    // float[max_subs * kNumFeatures]
   int64_t scratch;     // double[max_subs * 4] (power iteration, probes)
   int64_t vecs;        // double[sum over chunk of npad * kMaxProbes*2] probe / power vectors
-  int64_t flag;        // int32 nonfinite flag + padding
+  int64_t flag;        // 256 reserved bytes
   int64_t total;
 };
 
@@ -101,19 +102,23 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
                         double lbound, double* lb0_out, double* top0_out, hipStream_t s);
 // first != 0 initialises the iteration state; lb0 / top0 [nsub] (may be null):
 // bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz);
-// live_host (may be null): device-mapped host word that receives the number of
-// submatrices still iterating.
+// live_host (may be null): device-mapped host words that receive the number
+// of submatrices that square again after this iteration's updates (0: the
+// iteration is over for the chunk) and the tile counts of the next squares
+// in the main and the refinement precision.  max_tiles_sub: most 64-tiles (lower
+// triangle) of a submatrix in the chunk.
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
-                           const double* lb0, const double* top0, int32_t* live_host, hipStream_t s);
-// which: 0 squares, 1 updates (selects the submatrix's alpha).  first_ref >= 0:
-// refinement-list tiles of submatrices with refine_left == first_ref (their
-// first refinement update) get kTileFromShadow.
-hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists,
-                         int max_subs, int list_main, int list_ref, TileRec* recs_main,
-                         TileRec* recs_ref, int tshift_main, int tshift_ref, int which, int first_ref,
-                         int grid_subs, hipStream_t s);
+                           const double* lb0, const double* top0, int32_t* live_host, int max_tiles_sub,
+                           hipStream_t s);
+// Tile records of all four lists (recs: TileRec[4][max_tiles], by list; the
+// refinement lists only with with_ref).  first_ref >= 0: refinement-update
+// tiles of submatrices with refine_left == first_ref (their first refinement
+// update) get kTileFromShadow.
+hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists, int max_subs,
+                         TileRec* recs, int64_t max_tiles, int tshift_main, int tshift_ref, int first_ref,
+                         bool with_ref, int grid_subs, hipStream_t s);
 // 0: linear, 1: XCD-aware, 2: XCD-aware with half-depth LDS stages, 3: XCD-aware 128 x 128 tiles,
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices),
 // 5: as 3 with operands loaded three stages ahead

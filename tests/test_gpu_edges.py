@@ -5,7 +5,7 @@
 * every index set the whole system: P is the exact projector;
 * submatrix dimensions exactly at a tile boundary (n = 64, no padding) and
   one past it (n = 65), for both paddings;
-* NaN in H is reported before any iteration runs.
+* NaN in H is reported by the sign call that follows the build.
 """
 import numpy as np
 import pytest
@@ -88,5 +88,12 @@ def test_nonfinite_h_is_reported(dev):
     H = torch.from_numpy(vals).cuda()
     o = sm.default_opts("f64")
     work = sm.Workspace(plan, sm.storage_prec(o), H.device)
+    sm.build_submatrices(plan, 0, H, 0.0, o, work.ws, work.stats)
     with pytest.raises(sm.SmError, match="NaN"):
-        sm.build_submatrices(plan, 0, H, 0.0, o, work.ws, work.stats)
+        sm.submatrix_sign(plan, 0, work.ws, o, work.stats)
+    # the flag is cleared by the next build: a clean H runs through
+    H.copy_(torch.from_numpy(m.vals))
+    sm.build_submatrices(plan, 0, H, 0.0, o, work.ws, work.stats)
+    sm.submatrix_sign(plan, 0, work.ws, o, work.stats)
+    torch.cuda.synchronize()
+    assert np.all(work.stats_host()["status"] >= 1)
