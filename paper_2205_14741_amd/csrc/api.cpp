@@ -183,8 +183,9 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   SM_HIP(launch_fill_i32(flag, 0, 1, s));
   double* cg = w.scratch;                                 // [max_subs]
   float* pred = reinterpret_cast<float*>(w.scratch + p->max_subs);  // [2 max_subs]
-  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, flag, w.features, cg,
-                       stats, s));
+  const int shadow_kind = storage >= SM_BF16 ? storage : 0;
+  SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, shadow_kind, shadow, flag,
+                       w.features, cg, stats, s));
   const float* predp = nullptr;
   if (o->scaling == SM_SCALE_LEARNED) {
     if (!p->mlp) return set_error(SM_ERR_STATE, "build_submatrices: learned scaling needs a network (sm_plan_set_mlp)");
@@ -193,8 +194,8 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
     predp = pred;
   }
   SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
-                      cg, predp, stats, storage >= SM_BF16 ? storage : 0, shadow, o->lbound,
-                      w.scratch + 2 * p->max_subs, w.scratch + 3 * p->max_subs, s));
+                      cg, predp, stats, shadow_kind, shadow, o->lbound, w.scratch + 2 * p->max_subs,
+                      w.scratch + 3 * p->max_subs, w.scratch + 4 * p->max_subs, s));
   p->last_storage = storage;
   return SM_OK;
 }
@@ -253,7 +254,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   auto schedule = [&](int first, int32_t* live_host) -> int {
     SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, first, tsh_main, tsh_ref,
                            first ? w.scratch + 2 * p->max_subs : nullptr,
-                           first ? w.scratch + 3 * p->max_subs : nullptr, live_host, max_tiles_sub, s));
+                           first ? w.scratch + 3 * p->max_subs : nullptr,
+                           first ? w.scratch + 4 * p->max_subs : nullptr, live_host, max_tiles_sub, s));
     return SM_OK;
   };
   // one iteration: squares (A = X^2, Y = 3I - A), residuals + scheduler,
@@ -345,7 +347,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       if ((rc = nonfinite())) return rc;
     }
   }
-  if (shadow_kind)   // final X of submatrices that ended in the main phase
+  if (!f64)   // float32 final X where only its copies, or T (X = X_0), are in the buffer
     SM_HIP(launch_materialize(p->dev, g0, nsub, (float*)w.mats, w.st, shadow_kind, shadow, s));
   SM_HIP(launch_finish(p->dev, g0, nsub, w.mats, f64, w.st, o->probes, w.vecs, stats, s));
   return SM_OK;

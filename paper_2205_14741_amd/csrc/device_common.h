@@ -76,13 +76,12 @@ template <int Q, typename T> struct MatvecShape {
 };
 template <int Q, typename T> constexpr int matvec_red(int waves) { return waves * Q * MatvecShape<Q, T>::RW; }
 
-template <int Q, typename T, typename Out>
-__device__ __forceinline__ void block_matvec(const T* __restrict__ A, int64_t lda, int n,
-                                             const double* __restrict__ v, int vs, double* red,
-                                             Out out) {
-  using Sh = MatvecShape<Q, T>;
-  constexpr int V = Sh::V, RW = Sh::RW, U = 8;
-  typedef T vec __attribute__((ext_vector_type(V)));
+// Core of block_matvec over a loader: ld(c, rb, x) fills x[0 .. V) with the
+// float64 values of rows rb .. rb + V - 1 of column c.
+template <int Q, int V, typename Ld, typename Out>
+__device__ __forceinline__ void block_matvec_ld(Ld ld, int n, const double* __restrict__ v, int vs,
+                                                double* red, Out out) {
+  constexpr int RW = kWave * V, U = 8;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
@@ -96,25 +95,26 @@ __device__ __forceinline__ void block_matvec(const T* __restrict__ A, int64_t ld
     if (rb < n) {
       int c = w;
       for (; c + (U - 1) * nw < n; c += U * nw) {
-        vec x[U];
+        double x[U][V];
 #pragma unroll
-        for (int u = 0; u < U; ++u) x[u] = *reinterpret_cast<const vec*>(A + (int64_t)(c + u * nw) * lda + rb);
+        for (int u = 0; u < U; ++u) ld(c + u * nw, rb, x[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             const double vq = v[q * vs + c + u * nw];
 #pragma unroll
-            for (int e = 0; e < V; ++e) acc[q][e] += (double)x[u][e] * vq;
+            for (int e = 0; e < V; ++e) acc[q][e] += x[u][e] * vq;
           }
       }
       for (; c < n; c += nw) {
-        const vec x = *reinterpret_cast<const vec*>(A + (int64_t)c * lda + rb);
+        double x[V];
+        ld(c, rb, x);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const double vq = v[q * vs + c];
 #pragma unroll
-          for (int e = 0; e < V; ++e) acc[q][e] += (double)x[e] * vq;
+          for (int e = 0; e < V; ++e) acc[q][e] += x[e] * vq;
         }
       }
     }
@@ -133,6 +133,21 @@ __device__ __forceinline__ void block_matvec(const T* __restrict__ A, int64_t ld
         }
     __syncthreads();
   }
+}
+
+template <int Q, typename T, typename Out>
+__device__ __forceinline__ void block_matvec(const T* __restrict__ A, int64_t lda, int n,
+                                             const double* __restrict__ v, int vs, double* red,
+                                             Out out) {
+  constexpr int V = MatvecShape<Q, T>::V;
+  typedef T vec __attribute__((ext_vector_type(V)));
+  block_matvec_ld<Q, V>(
+      [&](int c, int rb, double (&x)[V]) {
+        const vec t = *reinterpret_cast<const vec*>(A + (int64_t)c * lda + rb);
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[e] = (double)t[e];
+      },
+      n, v, vs, red, out);
 }
 
 // float -> bfloat16 bits, round to nearest even: a plain conversion, which
@@ -168,6 +183,37 @@ template <bool SPLIT>
 __device__ __forceinline__ int64_t copy_idx(int64_t col, int row, int npad) {
   if (SPLIT) return col * 2 * npad + (int64_t)(row >> 5) * 64 + (row & 31);
   return col * npad + row;
+}
+
+// Value of a 16-bit copy entry of the precision `kind` (bf16 / f16).
+__device__ __forceinline__ float copy_value(uint16_t b, int kind) {
+  return kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, b) : bf16_bits_to_f32(b);
+}
+
+// block_matvec over the 16-bit operand copies of a buffer (an entry is its
+// bf16 / f16 copy, or hi + lo for split bf16; copy_idx layout).  Q <= 2.
+template <int Q, typename Out>
+__device__ __forceinline__ void block_matvec_copies(const uint16_t* __restrict__ cp, int npad, int n, int kind,
+                                                    const double* __restrict__ v, int vs, double* red,
+                                                    Out out) {
+  constexpr int V = MatvecShape<Q, float>::V;
+  static_assert(V == 4, "four rows per lane: one 8-byte load per plane");
+  typedef uint16_t h4 __attribute__((ext_vector_type(4)));
+  block_matvec_ld<Q, V>(
+      [&](int c, int rb, double (&x)[V]) {
+        if (kind == SM_BF16X3) {
+          const int64_t k = copy_idx<true>(c, rb, npad);
+          const h4 hi = *reinterpret_cast<const h4*>(cp + k);
+          const h4 lo = *reinterpret_cast<const h4*>(cp + k + 32);
+#pragma unroll
+          for (int e = 0; e < V; ++e) x[e] = (double)bf16_bits_to_f32(hi[e]) + (double)bf16_bits_to_f32(lo[e]);
+        } else {
+          const h4 hi = *reinterpret_cast<const h4*>(cp + copy_idx<false>(c, rb, npad));
+#pragma unroll
+          for (int e = 0; e < V; ++e) x[e] = (double)copy_value(hi[e], kind);
+        }
+      },
+      n, v, vs, red, out);
 }
 
 // Deterministic probe-vector entry in {-1, +1} for (probe, row).

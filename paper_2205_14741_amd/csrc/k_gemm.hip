@@ -184,7 +184,8 @@ __device__ __forceinline__ void stage_store(const RT (&r)[RN], LT* dst, LT* dst_
 // read-out needs it); float32 products store float32.
 template <int MODE, int WHICH>
 __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t shadow_off, int64_t nn,
-                                           int npad, int rb, int cc, double alpha, double& part) {
+                                           int npad, int rb, int cc, double alpha, double rscale,
+                                           double& part) {
   constexpr bool PRE = Pre<MODE>::value;
   float o[4];
   uint16_t h[4], l[4];
@@ -194,7 +195,7 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
     const double a = (double)a4[v];
     if (WHICH == 0) {
       const double dg = (rr == cc) ? 1.0 : 0.0;
-      const double e = a - dg;
+      const double e = a * rscale - dg;
       if (rr >= cc) part += (rr == cc) ? e * e : 2.0 * e * e;
       o[v] = (float)(3.0 * dg - (alpha * alpha) * a);
     } else {
@@ -388,6 +389,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
+    const double rscale = (double)rec.rscale;
     S* base = mats + rec.mat_off;
     S* Out = base + (WHICH == 0 ? 2 * nn : (int64_t)(rec.it & 1) * nn);
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
             double outv;
             if (WHICH == 0) {
               const double dg = (rr == cc) ? 1.0 : 0.0;
-              const double e = a - dg;
+              const double e = a * rscale - dg;
               part += (rr == cc) ? e * e : 2.0 * e * e;
               outv = 3.0 * dg - (alpha * alpha) * a;
             } else {
@@ -566,7 +568,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
 #pragma unroll
         for (int y = 0; y < 2; ++y)
           store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 32 + x * 16 + 4 * kq,
-                                  c0 + wn * 32 + y * 16 + (lane & 15), alpha, part);
+                                  c0 + wn * 32 + y * 16 + (lane & 15), alpha, rscale, part);
     } else {
       // 16-bit copies: each wave stages its 32 x 32 result block in LDS,
       // then writes it, and its mirror image, as runs of 16 rows per lane
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
       float* my = stg + wid * (32 * 33);
       if (wvalid) {
         const int R0 = r0 + wm * 32, C0 = c0 + wn * 32;
-        const float a2 = (float)(alpha * alpha), ha = (float)(0.5 * alpha);
+        const float a2 = (float)(alpha * alpha), ha = (float)(0.5 * alpha), rsf = (float)rscale;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -595,7 +597,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
               float o;
               if (WHICH == 0) {
                 const float dg = (R0 + lr == C0 + lc) ? 1.0f : 0.0f;
-                const float e = a - dg;   // exact: a ~ 1 on the diagonal
+                const float e = a * rsf - dg;   // exact for rsf = 1: a ~ 1 on the diagonal
                 if (R0 + lr >= C0 + lc) part += (double)(e * e) * (R0 + lr == C0 + lc ? 1.0 : 2.0);
                 o = __builtin_fmaf(-a2, a, 3.0f * dg);
               } else {
@@ -662,7 +664,12 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int nt = T * (T + 1) / 2;
   const int64_t mo = p.mat_off_g[g];
   const int it = st[l].iters;
-  const float alpha = (float)(which == 0 ? st[l].alpha_sq : st[l].alpha_upd);
+  // products that read X_0 (the square at it = 0, the update producing X_1)
+  // apply its factor x0s to the buffer's contents
+  const bool reads_x0 = which == 0 ? it == 0 : it == 1;
+  const double x0s = reads_x0 ? st[l].x0s : 1.0;
+  const float alpha = (float)((which == 0 ? st[l].alpha_sq : st[l].alpha_upd) * x0s);
+  const float rscale = (float)(which == 0 ? x0s * x0s : 1.0);
   const int16_t flags = (L == 1 && first_ref >= 0 && st[l].refine_left == first_ref) ? kTileFromShadow : 0;
   const int po = p.tile_off_g[g];
   const int t64 = tiles_of(npad);
@@ -673,6 +680,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
     TileRec r;
     r.mat_off = mo;
     r.alpha = alpha;
+    r.rscale = rscale;
     r.bibj = (bi << 16) | bj;
     r.npad = npad;
     r.it = it;
@@ -778,6 +786,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
+    const double rscale = (double)rec.rscale;
     S* base = mats + rec.mat_off;
     S* Out = base + (WHICH == 0 ? 2 * nn : (int64_t)(rec.it & 1) * nn);
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
@@ -898,7 +907,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
 #pragma unroll
       for (int y = 0; y < 4; ++y)
         store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 64 + x * 16 + 4 * kq,
-                                c0 + wn * 64 + y * 16 + rl, alpha, part);
+                                c0 + wn * 64 + y * 16 + rl, alpha, rscale, part);
     if (WHICH == 0) {
       part = wave_sum(part);
       if (lane == 0) red[wid] = part;
@@ -1142,6 +1151,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
                                                         int first, int tshift_main, int tshift_ref,
                                                         const double* __restrict__ lb0,
                                                         const double* __restrict__ top0,
+                                                        const double* __restrict__ x0s,
                                                         int32_t* live_host) {
   __shared__ int sh[8 * 16];
   const int stride = 2 + 2 * max_subs + 1;
@@ -1178,6 +1188,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         s.alpha_sq = (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : 1.0;
         s.alpha_upd = 1.0;
         s.lb_est = -1.0;
+        s.x0s = x0s ? x0s[l] : 1.0;
         dec = DEC_SQ;
       } else if (s.active) {
         const double r = s.res_new;
@@ -1293,8 +1304,8 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
-                           const double* lb0, const double* top0, int32_t* live_host, int max_tiles_sub,
-                           hipStream_t s) {
+                           const double* lb0, const double* top0, const double* x0s, int32_t* live_host,
+                           int max_tiles_sub, hipStream_t s) {
   SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
   // up to 64 partials per submatrix the scheduler's threads add them up
   // themselves; more are reduced by a wavefront each first
@@ -1302,7 +1313,7 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
   if (!first && !fuse && nsub > 0)
     hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
   hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, partials, fuse, lists,
-                     max_subs, o, first, tshift_main, tshift_ref, lb0, top0, live_host);
+                     max_subs, o, first, tshift_main, tshift_ref, lb0, top0, x0s, live_host);
   return hipGetLastError();
 }
 

@@ -16,32 +16,38 @@ __device__ __forceinline__ const T* final_x(const DevPlan& p, int g, const T* ma
   return mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * np * np;
 }
 
-// One workgroup per submatrix whose iteration ended in a low-precision main
-// phase (no refinement step ran, status != 2): its final X exists only as the
-// 16-bit operand copies; write the float32 values that the read-out kernels
-// below use (hi + lo for split bf16).
+// One workgroup per submatrix whose final X is not yet in float32 form in its
+// buffer: the iteration ended in a low-precision main phase (no refinement
+// step ran, status != 2), so X exists only as the 16-bit operand copies (hi +
+// lo for split bf16), and / or no update ran at all, so the buffer holds T
+// and X = x0s T.  Writes the float32 values the read-out kernels below use.
 __global__ __launch_bounds__(256) void materialize_kernel(DevPlan p, int g0, float* __restrict__ mats,
                                                           const SubState* __restrict__ st, int kind,
                                                           int64_t shadow_off) {
   const int l = blockIdx.x;
-  if (st[l].status == 2) return;
+  const SubState s = st[l];
+  const bool from_copies = kind != 0 && s.status != 2;
+  const bool x0 = s.iters == 0;
+  if (!from_copies && !x0) return;
+  const float sc = x0 ? (float)s.x0s : 1.0f;
   const int g = g0 + l;
   const int npad = p.npad_g[g];
   const int64_t nn = (int64_t)npad * npad;
-  float* X = mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * nn;
+  float* X = mats + p.mat_off_g[g] + (int64_t)(s.iters & 1) * nn;
   const uint16_t* h = reinterpret_cast<const uint16_t*>(X + shadow_off);
   const int lane = threadIdx.x & (kWave - 1);
   for (int c = threadIdx.x / kWave; c < npad; c += blockDim.x / kWave)
     for (int d = lane; d < npad; d += kWave) {
       float x;
-      if (kind == SM_BF16X3) {
+      if (!from_copies) {
+        x = X[(int64_t)c * npad + d];
+      } else if (kind == SM_BF16X3) {
         const int64_t k = copy_idx<true>(c, d, npad);
         x = bf16_bits_to_f32(h[k]) + bf16_bits_to_f32(h[k + 32]);
       } else {
-        const uint16_t b = h[copy_idx<false>(c, d, npad)];
-        x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, b) : bf16_bits_to_f32(b);
+        x = copy_value(h[copy_idx<false>(c, d, npad)], kind);
       }
-      X[(int64_t)c * npad + d] = x;
+      X[(int64_t)c * npad + d] = x * sc;
     }
 }
 

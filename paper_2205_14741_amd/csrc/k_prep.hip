@@ -1,7 +1,11 @@
 // Step 1 of the submatrix method (Fig. 2 of the paper): build every dense
 // principal submatrix T_i = H[idx_i, idx_i] - mu I (Eq. 14 with S = I) straight
-// from the block-column panels of H, then pick the spectral scale c_i and form
-// X_0 = T_i / c_i, the starting point of the sign iteration.
+// from the block-column panels of H, then pick the spectral scale c_i of
+// X_0 = T_i / c_i, the starting point of the sign iteration.  The float64
+// schedule stores X_0; the others keep T_i (float32, or straight in the
+// 16-bit operand copies of the low-precision products) and the first square
+// and update of the iteration multiply by 1 / c_i, which saves a pass over
+// every submatrix.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -53,9 +57,10 @@ struct ColStats {
 // of the submatrix from the statistics of all waves.
 // LDS: atoms of I_i and their row offsets (2 m ints), one row map of n_pad
 // ints per wave.
-template <typename T>
+template <typename T, int KIND>
 __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
-                                                     double mu, T* __restrict__ mats, int* nonfinite,
+                                                     double mu, T* __restrict__ mats,
+                                                     int64_t shadow_off, int* nonfinite,
                                                      float* __restrict__ features, double* __restrict__ cg_out,
                                                      sm_sub_stats* __restrict__ stats) {
   extern __shared__ int smem[];
@@ -75,6 +80,34 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   int* s_off = smem + m;
   int* s_src = smem + 2 * m + wid * npad;
   T* X = mats + p.mat_off_g[g];
+  // low-precision schedules: T goes straight into the 16-bit operand copies
+  // that the products read (the float32 buffer is not written).  Every lane
+  // of the wave calls put for the same column and row lane + 64 j, so lanes
+  // 2k and 2k + 1 hold rows d and d + 1 (both below n_pad, a multiple of 32)
+  // and trade halves: the even lane stores both hi values, the odd lane both
+  // lo values, each as one 4-byte store.
+  uint16_t* cp = reinterpret_cast<uint16_t*>(X + shadow_off);
+  auto put = [&](int c, int d, double x) {
+    if constexpr (KIND != 0) {
+      const float xf = (float)x;
+      const uint32_t h = shadow_hi(xf, KIND);
+      const bool odd = (lane & 1) != 0;
+      if constexpr (KIND == SM_BF16X3) {
+        const uint32_t lo = shadow_lo(xf, (uint16_t)h);
+        const uint32_t other = (uint32_t)__shfl_xor((int)(odd ? h : lo), 1, kWave);
+        const int64_t k = copy_idx<true>(c, d & ~1, npad);
+        if (odd)
+          *reinterpret_cast<uint32_t*>(cp + k + 32) = other | (lo << 16);
+        else
+          *reinterpret_cast<uint32_t*>(cp + k) = h | (other << 16);
+      } else {
+        const uint32_t other = (uint32_t)__shfl_xor((int)h, 1, kWave);
+        if (!odd) *reinterpret_cast<uint32_t*>(cp + copy_idx<false>(c, d, npad)) = h | (other << 16);
+      }
+    } else {
+      X[(int64_t)c * npad + d] = (T)x;
+    }
+  };
   for (int t = threadIdx.x; t < m; t += blockDim.x) {
     s_atom[t] = p.row_idx[k0 + t];
     s_off[t] = p.blk_rowoff[k0 + t];
@@ -111,7 +144,7 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
             bad |= !isfinite(x);
             sa[u] += fabs(x);
             sq[u] += x * x;
-            X[(int64_t)c * npad + d] = (T)x;
+            put(c, d, x);
           }
         }
       }
@@ -124,10 +157,8 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
     wave_sync();   // the row map is rebuilt for the wave's next atom
   }
   // identity padding: X stays exactly I on the pad under the iteration
-  for (int c = n + wid; c < npad; c += nw) {
-    T* xc = X + (int64_t)c * npad;
-    for (int d = lane; d < npad; d += kWave) xc[d] = (T)(d == c ? 1.0 : 0.0);
-  }
+  for (int c = n + wid; c < npad; c += nw)
+    for (int d = lane; d < npad; d += kWave) put(c, d, d == c ? 1.0 : 0.0);
   if (bad) *nonfinite = 1 + i;
   // combine the waves (every lane of a wave holds its values)
   const double cmax = block_reduce<1>(cs.cmax, red);
@@ -176,23 +207,27 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
 }
 
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
-                         const double* H, double mu, void* mats, int storage_f64,
-                         int* nonfinite, float* features, double* cg_out, sm_sub_stats* stats,
-                         hipStream_t s) {
+                         const double* H, double mu, void* mats, int storage_f64, int shadow_kind,
+                         int64_t shadow_off, int* nonfinite, float* features, double* cg_out,
+                         sm_sub_stats* stats, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);   // 4 waves
-  if (storage_f64)
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
-                       (double*)mats, nonfinite, features, cg_out, stats);
-  else
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(nsub), dim3(256), lds, s, p, g0, H, mu,
-                       (float*)mats, nonfinite, features, cg_out, stats);
+#define SM_GATHER(TT, K)                                                                             \
+  hipLaunchKernelGGL((gather_kernel<TT, K>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, (TT*)mats, \
+                     shadow_off, nonfinite, features, cg_out, stats)
+  if (storage_f64) SM_GATHER(double, 0);
+  else if (shadow_kind == SM_BF16X3) SM_GATHER(float, SM_BF16X3);
+  else if (shadow_kind == SM_BF16) SM_GATHER(float, SM_BF16);
+  else if (shadow_kind == SM_F16) SM_GATHER(float, SM_F16);
+  else SM_GATHER(float, 0);
+#undef SM_GATHER
   return hipGetLastError();
 }
 
 // One workgroup per submatrix: optional power iteration on T (column dots with
-// a vector kept in the workspace; est = ||T v_k|| <= rho(T)), the choice of c,
-// and X_0 = T / c on the n x n block (the identity pad is left as is).
+// a vector kept in the workspace; est = ||T v_k|| <= rho(T)), the choice of c;
+// float64: X_0 = T / c on the n x n block (the identity pad is left as is),
+// otherwise x0s_out = 1 / c for the first products.
 //   Gershgorin: c = c_G.   Power: c = min(c_G, (1 + margin) est).
 //   Learned: c_hat = c_G exp(y0) (1 + margin) from the network, accepted only if
 //   est <= c_hat <= c_G (the guard), else c = c_G.
@@ -205,7 +240,8 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     sm_sub_stats* __restrict__ stats, int shadow_kind,
                                                     int64_t shadow_off, double lbound,
                                                     double* __restrict__ lb0_out,
-                                                    double* __restrict__ top0_out) {
+                                                    double* __restrict__ top0_out,
+                                                    double* __restrict__ x0s_out) {
   __shared__ double red[16];
   __shared__ double mv[matvec_red<1, T>(8)];
   const int l = blockIdx.x;
@@ -218,6 +254,10 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
   const int wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
   const double cG = cg_in[l];
+  // low-precision schedules hold T only in its 16-bit operand copies
+  bool copies = false;
+  if constexpr (std::is_same<T, float>::value) copies = shadow_kind != 0;
+  const uint16_t* cp = reinterpret_cast<const uint16_t*>(X + shadow_off);
 
   double est = -1.0;
   if (scaling != SM_SCALE_GERSHGORIN && power_steps > 0) {
@@ -234,7 +274,10 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] *= inv;
     __syncthreads();
     for (int it = 0; it < power_steps; ++it) {
-      block_matvec<1>(X, npad, n, v, 0, mv, [&](int, int r, double y) { w[r] = y; });   // w = T v
+      if (copies)   // w = T v
+        block_matvec_copies<1>(cp, npad, n, shadow_kind, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
+      else
+        block_matvec<1>(X, npad, n, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
       double nw2 = 0.0;
       for (int d = threadIdx.x; d < n; d += blockDim.x) nw2 += w[d] * w[d];
       nw2 = block_reduce<0>(nw2, red);
@@ -264,28 +307,29 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     }
   }
   const double sc = 1.0 / c;
-  bool copies = false;
-  if constexpr (std::is_same<T, float>::value) copies = shadow_kind != 0;
-  if (!copies) {
+  // float64: X_0 = T / c in place.  float32 and the 16-bit schedules keep T
+  // in their buffers and the first square and update apply 1 / c (x0s); the
+  // identity pad's diagonal becomes c there, so that the pad of X_0 stays I
+  // (to the rounding of c and 1 / c) and does not iterate.
+  if constexpr (std::is_same<T, double>::value) {
     for (int cc = wid; cc < n; cc += nw) {
       T* col = X + (int64_t)cc * npad;
-      for (int d = lane; d < n; d += kWave) col[d] = (T)((double)col[d] * sc);
+      for (int d = lane; d < n; d += kWave) col[d] = col[d] * sc;
     }
-  } else if constexpr (std::is_same<T, float>::value) {
-    // products of the low-precision phases read only the 16-bit copies of
-    // X_0 (identity padding included); the float32 buffer keeps T
-    uint16_t* cp = reinterpret_cast<uint16_t*>(X + shadow_off);
-    for (int cc = wid; cc < npad; cc += nw) {
-      const int64_t o = (int64_t)cc * npad;
-      for (int d = lane; d < npad; d += kWave) {
-        const float x = (cc < n && d < n) ? (float)((double)X[o + d] * sc) : X[o + d];
-        const uint16_t h = shadow_hi(x, shadow_kind);
+  } else {
+    const float cf = (float)c;
+    for (int d = n + threadIdx.x; d < npad; d += blockDim.x) {
+      if (!copies) {
+        X[(int64_t)d * npad + d] = cf;
+      } else {
+        uint16_t* cw = reinterpret_cast<uint16_t*>(X + shadow_off);
+        const uint16_t h = shadow_hi(cf, shadow_kind);
         if (shadow_kind == SM_BF16X3) {
-          const int64_t k = copy_idx<true>(cc, d, npad);
-          cp[k] = h;
-          cp[k + 32] = shadow_lo(x, h);
+          const int64_t k = copy_idx<true>(d, d, npad);
+          cw[k] = h;
+          cw[k + 32] = shadow_lo(cf, h);
         } else {
-          cp[copy_idx<false>(cc, d, npad)] = h;
+          cw[copy_idx<false>(d, d, npad)] = h;
         }
       }
     }
@@ -300,22 +344,23 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     r.lb0 = lb;
     lb0_out[l] = lb;
     top0_out[l] = cG / c;
+    x0s_out[l] = std::is_same<T, double>::value ? 1.0 : sc;
   }
 }
 
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
-                        double lbound, double* lb0_out, double* top0_out, hipStream_t s) {
+                        double lbound, double* lb0_out, double* top0_out, double* x0s_out, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   if (storage_f64)
     hipLaunchKernelGGL(scale_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, 0, (int64_t)0, lbound, lb0_out,
-                       top0_out);
+                       top0_out, x0s_out);
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off, lbound,
-                       lb0_out, top0_out);
+                       lb0_out, top0_out, x0s_out);
   return hipGetLastError();
 }
 

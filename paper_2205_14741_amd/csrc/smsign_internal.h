@@ -50,13 +50,16 @@ struct SubState {
   double alpha_sq;
   double alpha_upd;
   double lb_est;       // plain runs: lower bound on the smallest |eigenvalue| of X_0
+  double x0s;          // X_0 = x0s * (buffer 0 as built): 1 / c except for float64 (1)
 };
 
 // One output tile of a Newton-Schulz GEMM launch, written by expand_kernel so
-// that a GEMM workgroup finds everything about its tile in one 32-byte load.
+// that a GEMM workgroup finds everything about its tile in one 40-byte record.
 struct TileRec {
   int64_t mat_off;   // element offset of the submatrix's buffers in the chunk
-  float alpha;       // Newton-Schulz scale: square Y = 3I - alpha^2 X^2, update 1/2 alpha X Y
+  float alpha;       // Newton-Schulz scale: square Y = 3I - alpha^2 A, update 1/2 alpha X Y, with A
+                     // and X the products / operands as stored (1 / c folded in for X_0)
+  float rscale;      // squares: the residual is ||rscale A - I|| (1 / c^2 for X_0, else 1)
   int32_t bibj;      // tile row << 16 | tile column (row >= column)
   int32_t npad;
   int32_t it;        // iteration counter (parity selects the X buffer)
@@ -87,21 +90,25 @@ struct WsLayout {
 // Launchers (k_*.hip).  All return hipError_t from hipGetLastError.
 // T_i of every submatrix of the chunk, plus its Gershgorin bound (cg_out,
 // stats.gersh) and the features of the scaling network (features, stats.feat).
+// shadow_kind: 0, or SM_BF16 / SM_F16 / SM_BF16X3 to write T_i only as the
+// operand copies at float offset shadow_off from its float32 buffer.
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
-                         const double* H, double mu, void* mats, int storage_f64,
-                         int* nonfinite, float* features, double* cg_out, sm_sub_stats* stats,
-                         hipStream_t s);
-// shadow_kind: 0, or SM_BF16 / SM_F16 / SM_BF16X3 to also write X_0's operand
-// copy at float offset shadow_off from its float32 buffer
-// lbound: opts.lbound; lb0_out / top0_out [nsub]: bounds on the smallest /
-// largest |eigenvalue| of X_0 for scaled Newton-Schulz (learned second output
-// when the learned scale is accepted, else lbound; top c_G / c).
+                         const double* H, double mu, void* mats, int storage_f64, int shadow_kind,
+                         int64_t shadow_off, int* nonfinite, float* features, double* cg_out,
+                         sm_sub_stats* stats, hipStream_t s);
+// shadow_kind / shadow_off: where T_i is (as for the gather).  lbound:
+// opts.lbound; lb0_out / top0_out [nsub]: bounds on the smallest / largest
+// |eigenvalue| of X_0 for scaled Newton-Schulz (learned second output when the
+// learned scale is accepted, else lbound; top c_G / c); x0s_out [nsub]: the
+// factor the first products apply to buffer 0 (1 / c; 1 for float64, whose
+// X_0 = T / c is stored).
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
-                        double lbound, double* lb0_out, double* top0_out, hipStream_t s);
+                        double lbound, double* lb0_out, double* top0_out, double* x0s_out, hipStream_t s);
 // first != 0 initialises the iteration state; lb0 / top0 [nsub] (may be null):
 // bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz);
+// x0s [nsub] (may be null: 1): SubState.x0s;
 // live_host (may be null): device-mapped host words that receive the number
 // of submatrices that square again after this iteration's updates (0: the
 // iteration is over for the chunk) and the tile counts of the next squares
@@ -110,8 +117,8 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
-                           const double* lb0, const double* top0, int32_t* live_host, int max_tiles_sub,
-                           hipStream_t s);
+                           const double* lb0, const double* top0, const double* x0s, int32_t* live_host,
+                           int max_tiles_sub, hipStream_t s);
 // Tile records of all four lists (recs: TileRec[4][max_tiles], by list; the
 // refinement lists only with with_ref).  first_ref >= 0: refinement-update
 // tiles of submatrices with refine_left == first_ref (their first refinement
@@ -139,8 +146,10 @@ hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t 
 hipError_t launch_comm_probe(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,
                              double mu, const void* mats, int storage_f64, const SubState* st, int probes,
                              double* vecs, sm_sub_stats* stats, hipStream_t s);
-// Float32 values of the final X from its 16-bit copies, for submatrices whose
-// iteration ended in a low-precision main phase (status != 2).
+// Float32 values of the final X: from its 16-bit copies for submatrices whose
+// iteration ended in a low-precision main phase (status != 2), times x0s when
+// the final X is X_0 (no update ran); float32 schedules (shadow_kind 0): only
+// the latter, in place.
 hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,
                               int shadow_kind, int64_t shadow_off, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);

@@ -79,6 +79,22 @@ def test_tile_boundaries(b1, pad_to, prec, tol, dev):
     assert np.all(info["npad"] == -(-n // pad_to) * pad_to)
 
 
+@pytest.mark.parametrize("prec,refine", [("f64", 0), ("f32", 0), ("bf16x3", 0), ("bf16x3", 2)])
+def test_converged_at_start(prec, refine, dev):
+    """T_i = diag(+-2) (no couplings): c = 2 and X_0 = T / c is already a sign
+    matrix, exactly in every precision, so the iteration stops after the first
+    square with no update (the final X is X_0 itself: stored as T for the
+    float32 and 16-bit schedules and rescaled on read-out), or, with
+    refinement steps, after exactly those."""
+    onsite = np.array([2.5, -1.5, -1.5, 2.5, -1.5, 2.5, 2.5, -1.5, -1.5, -1.5, 2.5, 2.5])
+    m = synth.from_pairs([4, 4, 4], [], [], onsite, n_occ=6)
+    P, E, Ne, st, plan = run_fixed_mu(m, 0.5, prec, pad_to=32, refine_steps=refine)
+    Po = om.density_matrix(m, 0.5)
+    assert np.max(np.abs(P - Po)) < 1e-14
+    assert np.all(st["scale"] == 2.0)
+    assert np.all(st["iters"] == refine) and np.all(st["status"] == (2 if refine else 1))
+
+
 def test_nonfinite_h_is_reported(dev):
     import torch
     m = synth.config1()

@@ -220,6 +220,13 @@ def _read_bufs(plan, work, storage, g):
     return [x.reshape(npad, npad).T.astype(np.float64) for x in bufs]
 
 
+def _x0_factor(storage, st, i):
+    """X_0 = factor * buffer 0 after the build: the float64 schedule stores
+    X_0 = T / c, the others keep T (and c on the pad's diagonal) and their
+    first products apply 1 / c."""
+    return 1.0 if storage == sm.SM_F64 else 1.0 / st["scale"][i]
+
+
 # unit roundoff of one product in each schedule (operand rounding; accumulation
 # is float32 except for f64)
 _U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16x3": 2.0 ** -17, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
@@ -245,8 +252,10 @@ def test_single_iteration_accuracy(prec, dev):
     assert np.all(st["iters"] == 1)
     u_acc = 2.0 ** -53 if prec == "f64" else 2.0 ** -24
     worst = []
+    info = plan.info()
     for g in (0, 7, 33):
         X0, X1, Y1 = _read_bufs(plan, work, storage, g)
+        X0 = X0 * _x0_factor(storage, st, info["order"][g])
         k = X0.shape[0]
         I = np.eye(k)
         Y0 = 3 * I - X0 @ X0
@@ -315,7 +324,8 @@ def test_trajectory_against_float64(prec, dev):
                 w1 = sm.Workspace(plan, storage, H.device)
                 sm.build_submatrices(plan, 0, H, mu, o1, w1.ws, w1.stats)
                 torch.cuda.synchronize()
-                _X0_CACHE[prec][g] = _read_bufs(plan, w1, storage, g)[0]
+                _X0_CACHE[prec][g] = (_read_bufs(plan, w1, storage, g)[0]
+                                      * _x0_factor(storage, w1.stats_host(), info["order"][g]))
             X = _X0_CACHE[prec][g]
             k = X.shape[0]
             I = np.eye(k)
