@@ -261,8 +261,12 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   // one iteration: squares (A = X^2, Y = 3I - A), residuals + scheduler,
   // tile records, updates (X' = 1/2 X Y).  live_host / ev: the scheduler's
   // counts and an event recorded after it; sq_main / sq_ref: whether the
-  // square lists may be non-empty.
-  auto iteration = [&](hipStream_t st, int32_t* live_host, hipEvent_t ev, bool sq_main, bool sq_ref) -> int {
+  // square lists may be non-empty; upd_ref: launch the refinement updates now
+  // (otherwise the host launches them after reading the scheduler's count,
+  // still before the next squares).  A main-precision update needs a
+  // main-precision square in the same iteration.
+  auto iteration = [&](hipStream_t st, int32_t* live_host, hipEvent_t ev, bool sq_main, bool sq_ref,
+                       bool upd_ref) -> int {
     hipStream_t keep = s;
     s = st;
     int r = gemms(2, 3, 0, sq_main, sq_ref);
@@ -272,7 +276,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       if (e != hipSuccess) r = hip_error(e, "hipEventRecord");
     }
     if (!r) r = expand();
-    if (!r) r = gemms(0, 1, 1, true, true);
+    if (!r) r = gemms(0, 1, 1, sq_main, upd_ref);
     s = keep;
     return r;
   };
@@ -291,14 +295,19 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   if (G == 0) {
     // the host waits for each iteration's scheduler while that iteration's
     // updates run, stops as soon as no submatrix squares again, and launches
-    // only the square GEMMs whose lists the scheduler filled
+    // only the GEMMs whose lists can be non-empty: squares as counted by the
+    // previous scheduler; refinement updates right away only while
+    // submatrices refine (a submatrix entering refinement gets its first
+    // refinement update launched once the count shows it)
     bool sq_main = true, sq_ref = true;
     for (int it = 0; it <= lim; ++it) {
       const int slot = kHostCounts + 4 * (it & 1);
-      if ((rc = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref))) return rc;
+      const bool upd_ref = sq_ref;
+      if ((rc = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref, upd_ref))) return rc;
       SM_HIP(hipEventSynchronize(p->ev[it & 1]));
       if (it == 0 && (rc = nonfinite())) return rc;
       const int32_t* hc = p->h_pinned + slot;
+      if (!upd_ref && hc[3] > 0 && (rc = gemms(0, 1, 1, false, true))) return rc;
       if (hc[0] == 0) break;
       sq_main = hc[1] > 0;
       sq_ref = hc[2] > 0;
@@ -316,7 +325,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
         for (int wh = 0; wh < 2; ++wh) (void)ns_gemm_blocks_per_cu(m, wh, effective_variant(p, m, o->variant));
       SM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
       int r = SM_OK;
-      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream, nullptr, nullptr, true, true);
+      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream, nullptr, nullptr, true, true, true);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
       if (r) {

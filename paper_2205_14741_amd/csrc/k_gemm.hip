@@ -1167,6 +1167,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         const int nt = T64 * (T64 + 1) / 2;
         const double* pp = partials + p.tile_off_g[g0 + l];
         double r = 0.0;
+#pragma unroll 8
         for (int k = 0; k < nt; ++k) r += pp[k];
         s.res_new = sqrt(fmax(r, 0.0));
       }
@@ -1293,10 +1294,11 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
     // for the host's stopping poll
     const int live = run_subs[2] + run_subs[3];
     lists[4 * stride] = live;
-    if (live_host) {   // [live, square tiles main, square tiles refinement]
+    if (live_host) {   // [live, square tiles main / refinement, refinement update tiles]
       live_host[0] = live;
       live_host[1] = run_tiles[2];
       live_host[2] = run_tiles[3];
+      live_host[3] = run_tiles[1];
     }
   }
 }

@@ -53,7 +53,8 @@ struct sm_plan {
   int32_t* h_pinned = nullptr;      // pinned, device-mapped host words [kHostWords]:
                                     // [0, 2) graph-path live counts, [8] nonfinite flag,
                                     // [10, 14) E and Ne, [kHostCounts, +8) scheduler
-                                    // counts (live, square tiles main / refinement) by parity
+                                    // counts (live, square tiles main / refinement,
+                                    // refinement update tiles) by parity
   int32_t* d_pinned = nullptr;      // the device's address of h_pinned
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_storage = -1;            // workspace storage of the last build (ws_storage; -1: none)

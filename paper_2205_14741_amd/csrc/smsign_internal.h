@@ -111,8 +111,9 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
 // x0s [nsub] (may be null: 1): SubState.x0s;
 // live_host (may be null): device-mapped host words that receive the number
 // of submatrices that square again after this iteration's updates (0: the
-// iteration is over for the chunk) and the tile counts of the next squares
-// in the main and the refinement precision.  max_tiles_sub: most 64-tiles (lower
+// iteration is over for the chunk), the tile counts of the next squares in
+// the main and the refinement precision, and that of this iteration's
+// refinement updates.  max_tiles_sub: most 64-tiles (lower
 // triangle) of a submatrix in the chunk.
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
