@@ -313,8 +313,8 @@ def main():
         best, tune_ms = sm.sm_autotune(plan, 0, H, 0.5 * (lo + hi), o, work.ws, work.stats, repeats=2)
 
         def step():
-            mu, k, _ = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P)
-            E, Ne = sm.energy_trace(plan, H, work.P)
+            # mu by bisection, P at mu, and tr(P H) / tr P of it (one call)
+            mu, k, _, E, Ne = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P, energy=True)
             return mu, k, E, Ne
 
         for _ in range(a.warmup):

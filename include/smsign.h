@@ -259,11 +259,13 @@ int sm_density_matrix(sm_plan* plan, const double* H_vals, double mu,
  * midpoint with |Ne - n_target| < accept, else after max_steps midpoints.
  * On return P_vals (if not NULL) holds P at the returned mu.
  *   mu_hist / ne_hist  host arrays of max_steps entries (may be NULL).
+ *   E_host / Ne_host   (may be NULL; need P_vals) energy_trace of the returned
+ *                      P, reduced in the same pass as the electron count.
  * Synchronises `stream`. */
 int sm_find_mu(sm_plan* plan, const double* H_vals, double n_target, double accept,
                int32_t max_steps, const sm_sign_opts* opts, void* ws, double* P_vals,
                sm_sub_stats* stats, double* mu_out, int32_t* steps_out,
-               double* mu_hist, double* ne_hist, void* stream);
+               double* mu_hist, double* ne_hist, double* E_host, double* Ne_host, void* stream);
 
 /* Global Gershgorin bracket [lo, hi] of H (synchronous). */
 int sm_gershgorin_bracket(sm_plan* plan, const double* H_vals, double* lo, double* hi,

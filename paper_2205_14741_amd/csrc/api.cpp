@@ -399,12 +399,11 @@ int energy_trace(const sm_plan* pc, const double* H, const double* P, double* E,
   int rc;
   if ((rc = ensure_device(p))) return rc;
   hipStream_t s = as_stream(stream);
-  double* out = p->d_trace_parts + 2 * kTraceBlocks;
+  // the final reduction writes E and Ne straight into mapped host memory
   SM_HIP(launch_trace(H, P, p->nvals, p->d_diag_idx, (int64_t)p->diag_idx.size(), p->d_trace_parts,
-                      kTraceBlocks, out, s));
-  double* h = reinterpret_cast<double*>(&p->h_pinned[10]);
-  SM_HIP(hipMemcpyAsync(h, out, 16, hipMemcpyDeviceToHost, s));
+                      kTraceBlocks, reinterpret_cast<double*>(p->d_pinned + kHostTrace), s));
   SM_HIP(hipStreamSynchronize(s));
+  const double* h = reinterpret_cast<const double*>(p->h_pinned + kHostTrace);
   if (E) *E = h[0];
   if (Ne) *Ne = h[1];
   return SM_OK;
@@ -429,23 +428,19 @@ int sm_gershgorin_bracket(sm_plan* p, const double* H, double* lo, double* hi, v
   int rc;
   if ((rc = ensure_device(p))) return rc;
   hipStream_t s = as_stream(stream);
-  SM_HIP(launch_gersh_rows(p->dev, p->n_atoms, H, p->d_gersh, s));
-  std::vector<double> h(2 * (size_t)p->n_atoms);
-  SM_HIP(hipMemcpyAsync(h.data(), p->d_gersh, h.size() * 8, hipMemcpyDeviceToHost, s));
+  SM_HIP(launch_gersh_rows(p->dev, p->n_atoms, H, p->d_gersh,
+                           reinterpret_cast<double*>(p->d_pinned + kHostBracket), s));
   SM_HIP(hipStreamSynchronize(s));
-  double a = h[0], b = h[1];
-  for (int c = 1; c < p->n_atoms; ++c) {
-    a = std::min(a, h[2 * c]);
-    b = std::max(b, h[2 * c + 1]);
-  }
-  *lo = a;
-  *hi = b;
+  const double* h = reinterpret_cast<const double*>(p->h_pinned + kHostBracket);
+  *lo = h[0];
+  *hi = h[1];
   return SM_OK;
 }
 
 int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int32_t max_steps,
                const sm_sign_opts* o, void* ws, double* P, sm_sub_stats* stats, double* mu_out,
-               int32_t* steps_out, double* mu_hist, double* ne_hist, void* stream) {
+               int32_t* steps_out, double* mu_hist, double* ne_hist, double* E_out, double* Ne_out,
+               void* stream) {
   if (!p || !H || !ws || !stats || !mu_out) return set_error(SM_ERR_ARG, "sm_find_mu: null argument");
   if (max_steps < 1 || max_steps > 200) return set_error(SM_ERR_ARG, "sm_find_mu: max_steps out of [1, 200]");
   if (!(accept > 0)) return set_error(SM_ERR_ARG, "sm_find_mu: accept must be > 0");
@@ -455,7 +450,6 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
   if ((rc = sm_gershgorin_bracket(p, H, &lo, &hi, stream))) return rc;
   hipStream_t s = as_stream(stream);
   const int nch = (int)p->chunk_ptr.size() - 1;
-  std::vector<double> ne_sub((size_t)p->n_atoms);
   double mid = 0.5 * (lo + hi);
   int step = 1;
   for (; step <= max_steps; ++step) {
@@ -470,16 +464,21 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
       SM_HIP(launch_ne_from_x(p->dev, g0, nsub, w.mats, storage_is_f64(o), w.st, p->d_ne_sub, s));
       if (P && (rc = assemble_P(p, c, ws, P, stream))) return rc;
     }
-    SM_HIP(hipMemcpyAsync(ne_sub.data(), p->d_ne_sub, ne_sub.size() * 8, hipMemcpyDeviceToHost, s));
+    // tr(P H), tr P of this pass's P when asked for (so the accepted pass
+    // needs no further round trip), and the compensated sum of the electron
+    // counts over the atoms, all into mapped host memory
+    const bool trace = P && (E_out || Ne_out);
+    if (trace)
+      SM_HIP(launch_trace(H, P, p->nvals, p->d_diag_idx, (int64_t)p->diag_idx.size(), p->d_trace_parts,
+                          kTraceBlocks, reinterpret_cast<double*>(p->d_pinned + kHostTrace), s));
+    SM_HIP(launch_ne_sum(p->d_ne_sub, p->n_atoms, reinterpret_cast<double*>(p->d_pinned + kHostNe), s));
     SM_HIP(hipStreamSynchronize(s));
-    // compensated sum in atom order
-    double sum = 0.0, comp = 0.0;
-    for (double x : ne_sub) {
-      const double t = sum + x;
-      comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
-      sum = t;
+    if (trace) {
+      const double* h = reinterpret_cast<const double*>(p->h_pinned + kHostTrace);
+      if (E_out) *E_out = h[0];
+      if (Ne_out) *Ne_out = h[1];
     }
-    const double ne = sum + comp;
+    const double ne = *reinterpret_cast<const double*>(p->h_pinned + kHostNe);
     if (mu_hist) mu_hist[step - 1] = mid;
     if (ne_hist) ne_hist[step - 1] = ne;
     if (std::fabs(ne - n_target) < accept) break;

@@ -398,9 +398,61 @@ __global__ __launch_bounds__(256) void gersh_kernel(DevPlan p, const double* __r
   }
 }
 
+// Smallest lower and largest upper Gershgorin end over the atoms (order-free).
+__global__ __launch_bounds__(256) void gersh_final_kernel(const double* __restrict__ lohi, int n_atoms,
+                                                          double* __restrict__ out2) {
+  __shared__ double red[8];
+  double lo = 1e300, hi = -1e300;
+  for (int c = threadIdx.x; c < n_atoms; c += blockDim.x) {
+    lo = fmin(lo, lohi[2 * c]);
+    hi = fmax(hi, lohi[2 * c + 1]);
+  }
+  lo = block_reduce<2>(lo, red);
+  hi = block_reduce<1>(hi, red);
+  if (threadIdx.x == 0) {
+    out2[0] = lo;
+    out2[1] = hi;
+  }
+}
+
 hipError_t launch_gersh_rows(const DevPlan& p, int n_atoms, const double* H, double* lohi_parts,
-                             hipStream_t s) {
+                             double* out2, hipStream_t s) {
   hipLaunchKernelGGL(gersh_kernel, dim3(n_atoms), dim3(256), 0, s, p, H, lohi_parts);
+  hipLaunchKernelGGL(gersh_final_kernel, dim3(1), dim3(256), 0, s, lohi_parts, n_atoms, out2);
+  return hipGetLastError();
+}
+
+// Electron count sum_i ne_i in a fixed order with compensation (Neumaier):
+// each thread sums a contiguous run of atoms, thread 0 combines the runs in
+// order.  out[0] = the sum (written by one thread: out may be host-mapped).
+__device__ __forceinline__ void neumaier_add(double& sum, double& comp, double x) {
+  const double t = sum + x;
+  comp += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
+  sum = t;
+}
+
+__global__ __launch_bounds__(256) void ne_sum_kernel(const double* __restrict__ ne_sub, int n_atoms,
+                                                     double* __restrict__ out) {
+  __shared__ double ps[256], pc[256];
+  const int per = (n_atoms + blockDim.x - 1) / blockDim.x;
+  const int a0 = threadIdx.x * per, a1 = min(n_atoms, a0 + per);
+  double sum = 0.0, comp = 0.0;
+  for (int a = a0; a < a1; ++a) neumaier_add(sum, comp, ne_sub[a]);
+  ps[threadIdx.x] = sum;
+  pc[threadIdx.x] = comp;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, Cc = 0.0;
+    for (int k = 0; k < (int)blockDim.x; ++k) {
+      neumaier_add(S, Cc, ps[k]);
+      Cc += pc[k];
+    }
+    out[0] = S + Cc;
+  }
+}
+
+hipError_t launch_ne_sum(const double* ne_sub, int n_atoms, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(ne_sum_kernel, dim3(1), dim3(256), 0, s, ne_sub, n_atoms, out);
   return hipGetLastError();
 }
 

@@ -9,6 +9,9 @@
 
 constexpr int kHostWords = 64;
 constexpr int kHostCounts = 16;
+constexpr int kHostBracket = 32;   // two doubles
+constexpr int kHostNe = 36;        // one double
+constexpr int kHostTrace = 10;     // E, Ne
 
 struct sm_plan {
   // pattern (copied from the caller)
@@ -52,9 +55,11 @@ struct sm_plan {
   double* d_gersh = nullptr;        // [2 * n_atoms]
   int32_t* h_pinned = nullptr;      // pinned, device-mapped host words [kHostWords]:
                                     // [0, 2) graph-path live counts, [8] nonfinite flag,
-                                    // [10, 14) E and Ne, [kHostCounts, +8) scheduler
-                                    // counts (live, square tiles main / refinement,
-                                    // refinement update tiles) by parity
+                                    // [kHostTrace, +4) E and Ne, [kHostCounts, +8)
+                                    // scheduler counts (live, square tiles main /
+                                    // refinement, refinement update tiles) by parity,
+                                    // [kHostBracket, +4) Gershgorin hull, [kHostNe, +2)
+                                    // electron count
   int32_t* d_pinned = nullptr;      // the device's address of h_pinned
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_storage = -1;            // workspace storage of the last build (ws_storage; -1: none)

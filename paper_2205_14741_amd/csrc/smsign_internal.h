@@ -165,8 +165,13 @@ hipError_t launch_trace(const double* H, const double* P, int64_t nvals, const i
 hipError_t launch_ne_from_x(const DevPlan& p, int g0, int nsub, const void* mats,
                             int storage_f64, const SubState* st, double* ne_parts,
                             hipStream_t s);
+// Gershgorin interval of every atom's rows (lohi_parts [2 n_atoms]) and
+// their hull out2 = [lo, hi] (one thread writes: out2 may be host-mapped).
 hipError_t launch_gersh_rows(const DevPlan& p, int n_atoms, const double* H, double* lohi_parts,
-                             hipStream_t s);
+                             double* out2, hipStream_t s);
+// out[0] = compensated sum of ne_sub[0 .. n_atoms) in a fixed order (one
+// thread writes: out may be host-mapped).
+hipError_t launch_ne_sum(const double* ne_sub, int n_atoms, double* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* dst, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_selftest_mfma(int prec, double* out_dev, hipStream_t s);
 

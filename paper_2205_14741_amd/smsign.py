@@ -98,7 +98,8 @@ def lib() -> C.CDLL:
         "assemble_P": (i32, [vp, i32, vp, vp, vp]),
         "energy_trace": (i32, [vp, vp, vp, vp, vp, vp]),
         "sm_density_matrix": (i32, [vp, vp, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp]),
-        "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                             vp]),
         "sm_gershgorin_bracket": (i32, [vp, vp, vp, vp, vp]),
         "sm_selftest_mfma": (i32, [i32, vp]),
         "sm_profile_enable": (i32, [vp, i32]),
@@ -261,17 +262,27 @@ def sm_density_matrix(plan: Plan, H, mu: float, opts: SignOpts, ws, P, stats, st
 
 
 def sm_find_mu(plan: Plan, H, n_target: float, opts: SignOpts, ws, stats, P=None, accept=0.5,
-               max_steps=60, stream=None):
+               max_steps=60, stream=None, energy=False):
+    """(mu, bisection steps, [(mu_k, Ne_k)]), and with energy=True (needs P)
+    also E = tr(P H) and Ne = tr P of the returned P."""
     _check_ws(plan, ws, opts)
+    if energy and P is None:
+        raise SmError(SM_ERR_ARG, "sm_find_mu: energy=True needs P")
     mu = C.c_double()
     steps = C.c_int32()
+    E, Ne = C.c_double(), C.c_double()
     mh = np.zeros(max_steps)
     nh = np.zeros(max_steps)
     _check(lib().sm_find_mu(plan.handle, _ptr(H), float(n_target), float(accept), int(max_steps),
                             C.byref(opts), _ptr(ws), _ptr(P), _ptr(stats), C.byref(mu),
-                            C.byref(steps), mh.ctypes.data, nh.ctypes.data, _stream(stream)))
+                            C.byref(steps), mh.ctypes.data, nh.ctypes.data,
+                            C.byref(E) if energy else None, C.byref(Ne) if energy else None,
+                            _stream(stream)))
     k = steps.value
-    return mu.value, k, list(zip(mh[:k].tolist(), nh[:k].tolist()))
+    hist = list(zip(mh[:k].tolist(), nh[:k].tolist()))
+    if energy:
+        return mu.value, k, hist, E.value, Ne.value
+    return mu.value, k, hist
 
 
 def sm_gershgorin_bracket(plan: Plan, H, stream=None):

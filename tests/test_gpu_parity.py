@@ -178,11 +178,13 @@ def test_find_mu_config1(dev):
     lo, hi = sm.sm_gershgorin_bracket(plan, H)
     lo_o, hi_o = om.global_gershgorin_bracket(m)
     assert rel(lo, lo_o) < 1e-14 and rel(hi, hi_o) < 1e-14
-    mu, steps, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P)
+    mu, steps, hist, E_mu, Ne_mu = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P,
+                                                energy=True)
     assert steps == steps_o
     for (a, na), (b, nb) in zip(hist, hist_o):
         assert abs(a - b) < 1e-12 and abs(na - nb) < 1e-8
     E, Ne = sm.energy_trace(plan, H, work.P)
+    assert (E, Ne) == (E_mu, Ne_mu)   # same reduction of the same P
     Po = om.density_matrix(m, mu)
     Eo, Neo = om.energy_trace(m, Po)
     assert rel(E, Eo) < 1e-11
