@@ -96,15 +96,14 @@ int effective_variant(const sm_plan* p, int mode, int variant) {
   return v;
 }
 
-int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_t shadow, int shadow_kind,
-                const int32_t* cnt,
+int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_t shadow, const int32_t* cnt,
                 const TileRec* recs, double* partials, int max_tiles, hipStream_t s) {
   const int v = effective_variant(p, mode, variant);
   // persistent grid: all resident workgroups, a multiple of the 8 XCDs
   int grid = std::min(max_tiles, p->num_cu * ns_gemm_blocks_per_cu(mode, which, v));
   grid = std::max(8, grid / 8 * 8);
   if (!p->profiling) {
-    SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, shadow_kind, cnt, recs, partials, grid, s));
+    SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, cnt, recs, partials, grid, s));
     return SM_OK;
   }
   const size_t k = p->prof_cls.size();
@@ -113,7 +112,7 @@ int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_
     SM_HIP(hipEventCreate(&e));
     p->prof_ev.push_back(e);
   }
-  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, shadow_kind, cnt, recs, partials, grid, s,
+  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, cnt, recs, partials, grid, s,
                         p->prof_ev[2 * k], p->prof_ev[2 * k + 1]));
   p->prof_cls.push_back(2 * mode + which);
   return SM_OK;
@@ -228,26 +227,25 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   const int tsh_ref = tile_shift(effective_variant(p, mode_ref, o->variant), mode_ref);
   // tile records by list: 0 / 1 updates, 2 / 3 squares (main / refinement)
   auto recs_of = [&](int L) { return w.tiles + (int64_t)L * p->max_tiles; };
-  // the main phase's products keep only 16-bit copies of their results, so
-  // a submatrix's first refinement update reads those (tile flag)
+  // the main phase's products keep only 16-bit copies of their results; a
+  // submatrix's first refinement update is run on those by the main kernel
   const int shadow_kind = storage >= SM_BF16 ? storage : 0;
-  const int first_ref = shadow_kind ? o->refine_steps - 1 : -1;
   // the scheduler's lists -> tile records of this iteration's updates and
   // the next iteration's squares (one launch)
   auto expand = [&]() -> int {
-    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, w.tiles, p->max_tiles, tsh_main, tsh_ref, first_ref,
-                         has_ref, nsub, s));
+    SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, w.tiles, p->max_tiles, tsh_main, tsh_ref, has_ref,
+                         nsub, s));
     return SM_OK;
   };
   // the GEMMs of kind `which` over lists Lm (main precision) and Lr
   // (refinement); a list the host knows to be empty is not launched
   auto gemms = [&](int Lm, int Lr, int which, bool run_main, bool run_ref) -> int {
     int r;
-    if (run_main && (r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, 0, list_count(Lm),
+    if (run_main && (r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, list_count(Lm),
                                      recs_of(Lm), w.partials, max_tiles, s)))
       return r;
-    if (has_ref && run_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, shadow_kind,
-                                               list_count(Lr), recs_of(Lr), w.partials, max_tiles, s)))
+    if (has_ref && run_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, list_count(Lr),
+                                               recs_of(Lr), w.partials, max_tiles, s)))
       return r;
     return SM_OK;
   };

@@ -75,56 +75,15 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int MODE, bool PRE = Pre<MODE>::value> struct Operand;
 
-// NL float32 values of an operand row rebuilt from 16-bit copies of the
-// precision `kind`: the bf16 / f16 value, or hi + lo for split bf16.  p
-// points at the first of the NL values (for split bf16 at its hi entry; the
-// NL values lie inside one 32-row block, lo 32 entries further on).
-template <int NL>
-__device__ __forceinline__ void load_col_shadow(float (&r)[NL], const uint16_t* p, int kind, bool ok) {
-  static_assert(NL % 4 == 0 && NL <= 32, "vector width");
-  typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-#pragma unroll
-  for (int v = 0; v < NL / 4; ++v) {
-    u2 h = u2{0, 0}, l = u2{0, 0};
-    if (ok) {
-      h = *reinterpret_cast<const u2*>(p + 4 * v);
-      if (kind == SM_BF16X3) l = *reinterpret_cast<const u2*>(p + 32 + 4 * v);
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const uint16_t hb = (uint16_t)(h[e >> 1] >> (16 * (e & 1)));
-      const uint16_t lb = (uint16_t)(l[e >> 1] >> (16 * (e & 1)));
-      float x = kind == SM_F16 ? (float)__builtin_bit_cast(_Float16, hb) : bf16_bits_to_f32(hb);
-      if (kind == SM_BF16X3) x += bf16_bits_to_f32(lb);
-      r[4 * v + e] = x;
-    }
-  }
-}
-
 // Operand panel row `row` of a buffer, the thread's k slice starting at
 // `part` within each stage.
 template <int MODE> struct Operand<MODE, false> {
   using S = typename Traits<MODE>::S;
   const S* p;
-  const uint16_t* q;   // 16-bit copies (float32 products of a first refinement update)
-  int part;
-  int kind;            // main precision of the copies; 0: read the buffer itself
-  __device__ Operand(const S* buf, int64_t shadow_off, int row, int part_, int npad, int kind_)
-      : p(buf + (int64_t)row * npad + part_),
-        q(kind_ ? reinterpret_cast<const uint16_t*>(reinterpret_cast<const float*>(buf) + shadow_off) +
-                      (int64_t)row * (kind_ == SM_BF16X3 ? 2 * npad : npad)
-                : nullptr),
-        part(part_),
-        kind(kind_) {}
+  __device__ Operand(const S* buf, int64_t, int row, int part, int npad)
+      : p(buf + (int64_t)row * npad + part) {}
   template <int K, int NL>
   __device__ __forceinline__ void load(S (&r)[NL], int stage, bool ok) const {
-    if constexpr (MODE == SM_F32) {
-      if (kind) {
-        const int k0 = stage * K + part;
-        load_col_shadow<NL>(r, q + (kind == SM_BF16X3 ? (k0 >> 5) * 64 + (k0 & 31) : k0), kind, ok);
-        return;
-      }
-    }
     load_col<S, NL>(r, p + (int64_t)stage * K, ok);
   }
 };
@@ -133,7 +92,7 @@ template <int MODE> struct Operand<MODE, true> {
   static constexpr bool SPLIT = MODE == SM_BF16X3;
   const uint16_t* p;
   int part;
-  __device__ Operand(const float* buf, int64_t shadow_off, int row, int part_, int npad, int)
+  __device__ Operand(const float* buf, int64_t shadow_off, int row, int part_, int npad)
       : p(reinterpret_cast<const uint16_t*>(buf + shadow_off) + (int64_t)row * (SPLIT ? 2 * npad : npad)),
         part(part_) {}
   // NL 16-bit values per plane (NL / 2 words), hi then lo in r
@@ -285,7 +244,7 @@ template <int MODE> struct TileSrc {
 
 template <int MODE, int WHICH, int TE>
 __device__ __forceinline__ TileSrc<MODE> tile_src(const TileRec& rec, typename Traits<MODE>::S* mats,
-                                                  int64_t shadow_off, int shadow_kind, int lrow, int lpart) {
+                                                  int64_t shadow_off, int lrow, int lpart) {
   using S = typename Traits<MODE>::S;
   const int npad = rec.npad;
   const int64_t nn = (int64_t)npad * npad;
@@ -295,9 +254,8 @@ __device__ __forceinline__ TileSrc<MODE> tile_src(const TileRec& rec, typename T
   const int r0 = (rec.bibj >> 16) * TE, c0 = (rec.bibj & 0xFFFF) * TE;
   const bool va = (r0 + lrow) < npad;
   const bool vb = (c0 + lrow) < npad;
-  const int fk = (MODE == SM_F32 && (rec.flags & kTileFromShadow)) ? shadow_kind : 0;
-  return TileSrc<MODE>{Operand<MODE>(Xp, shadow_off, va ? r0 + lrow : 0, lpart, npad, fk),
-                       Operand<MODE>(Rp, shadow_off, vb ? c0 + lrow : 0, lpart, npad, fk), va, vb};
+  return TileSrc<MODE>{Operand<MODE>(Xp, shadow_off, va ? r0 + lrow : 0, lpart, npad),
+                       Operand<MODE>(Rp, shadow_off, vb ? c0 + lrow : 0, lpart, npad), va, vb};
 }
 
 __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
@@ -336,7 +294,7 @@ template <int MODE, int KDIV> struct GemmOcc {
 
 template <int MODE, int WHICH, int KDIV, bool XCD>
 __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_kernel(typename Traits<MODE>::S* __restrict__ mats,
-                                                         int64_t shadow_off, int shadow_kind,
+                                                         int64_t shadow_off,
                                                          const int32_t* __restrict__ count,
                                                          const TileRec* __restrict__ recs,
                                                          double* __restrict__ partials) {
@@ -378,7 +336,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   TileRec nxt;
   if (t_begin < t_end) {
     nxt = recs[t_begin];
-    const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+    const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, lrow, lpart);
     s0.a.template load<K, NL>(ra, 0, s0.va);
     s0.b.template load<K, NL>(rb, 0, s0.vb);
   }
@@ -399,7 +357,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
     // the block of a diagonal tile that lies wholly above the diagonal
     // computes nothing either
     const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && !(bi == bj && wm < wn);
-    const TileSrc<MODE> src = tile_src<MODE, WHICH, 64>(rec, mats, shadow_off, shadow_kind, lrow, lpart);
+    const TileSrc<MODE> src = tile_src<MODE, WHICH, 64>(rec, mats, shadow_off, lrow, lpart);
 
     typename Tr::Acc acc[2][2];
 #pragma unroll
@@ -423,7 +381,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
         src.a.template load<K, NL>(ra, s + 1, src.va);
         src.b.template load<K, NL>(rb, s + 1, src.vb);
       } else if (has_next) {
-        const TileSrc<MODE> sn = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+        const TileSrc<MODE> sn = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, lrow, lpart);
         sn.a.template load<K, NL>(ra, 0, sn.va);
         sn.b.template load<K, NL>(rb, 0, sn.vb);
       }
@@ -614,11 +572,16 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
 #pragma unroll
         for (int j = 0; j < 16; ++j)
           w[j] = (diag && h + j < li) ? my[(h + j) * 33 + li] : my[li * 33 + h + j];
-        store_run16<MODE>(w, Out, shadow_off, C0 + li, R0 + h, npad);
+        const bool f32out = WHICH == 1 && (rec.flags & kTileStoreF32);
+        auto put16 = [&](int col, int row0) {
+          if (f32out) store_run16<SM_F32>(w, Out, shadow_off, col, row0, npad);
+          else store_run16<MODE>(w, Out, shadow_off, col, row0, npad);
+        };
+        put16(C0 + li, R0 + h);
         if (!diag) {   // the mirror: column R0 + li, rows C0 + h ..
 #pragma unroll
           for (int j = 0; j < 16; ++j) w[j] = my[(h + j) * 33 + li];
-          store_run16<MODE>(w, Out, shadow_off, R0 + li, C0 + h, npad);
+          put16(R0 + li, C0 + h);
         }
       }
     }
@@ -644,7 +607,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
 __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const SubState* __restrict__ st,
                                                      const int32_t* __restrict__ lists, int max_subs,
                                                      TileRec* __restrict__ recs, int64_t max_tiles,
-                                                     int tshift_main, int tshift_ref, int first_ref) {
+                                                     int tshift_main, int tshift_ref) {
   const int stride = 2 + 2 * max_subs + 1;
   const int y = blockIdx.y;
   const int L = (y & 1) ? 2 + (y >> 1) : (y >> 1);   // 0, 2, 1, 3
@@ -670,7 +633,9 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const double x0s = reads_x0 ? st[l].x0s : 1.0;
   const float alpha = (float)((which == 0 ? st[l].alpha_sq : st[l].alpha_upd) * x0s);
   const float rscale = (float)(which == 0 ? x0s * x0s : 1.0);
-  const int16_t flags = (L == 1 && first_ref >= 0 && st[l].refine_left == first_ref) ? kTileFromShadow : 0;
+  // list 0 also holds first refinement updates (phase 1): their result is
+  // stored in float32 for the refinement steps that follow
+  const int16_t flags = (L == 0 && st[l].phase == 1) ? kTileStoreF32 : 0;
   const int po = p.tile_off_g[g];
   const int t64 = tiles_of(npad);
   for (int lt = threadIdx.x; lt < nt; lt += blockDim.x) {
@@ -692,11 +657,11 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
 }
 
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists, int max_subs,
-                         TileRec* recs, int64_t max_tiles, int tshift_main, int tshift_ref, int first_ref,
-                         bool with_ref, int grid_subs, hipStream_t s) {
+                         TileRec* recs, int64_t max_tiles, int tshift_main, int tshift_ref, bool with_ref,
+                         int grid_subs, hipStream_t s) {
   if (grid_subs <= 0) return hipSuccess;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_subs, with_ref ? 4 : 2), dim3(256), 0, s, p, g0, st, lists,
-                     max_subs, recs, max_tiles, tshift_main, tshift_ref, first_ref);
+                     max_subs, recs, max_tiles, tshift_main, tshift_ref);
   return hipGetLastError();
 }
 
@@ -731,7 +696,6 @@ template <int MODE, int DEPTH> struct Gemm128Occ {
 
 template <int MODE, int WHICH, bool XCD, int DEPTH = 1>
 __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_gemm128_kernel(float* __restrict__ mats, int64_t shadow_off,
-                                                            int shadow_kind,
                                                             const int32_t* __restrict__ count,
                                                             const TileRec* __restrict__ recs,
                                                             double* __restrict__ partials) {
@@ -774,7 +738,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
   if (t_begin < t_end) {
     nxt = recs[t_begin];
     if constexpr (DEPTH == 1) {
-      const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+      const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, lrow, lpart);
       s0.a.template load<K, NL>(rga[0], 0, s0.va);
       s0.b.template load<K, NL>(rgb[0], 0, s0.vb);
     }
@@ -792,7 +756,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
     const int r0 = bi * 128, c0 = bj * 128;
     const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && !(bi == bj && wm < wn);
-    const TileSrc<MODE> src = tile_src<MODE, WHICH, 128>(rec, mats, shadow_off, shadow_kind, lrow, lpart);
+    const TileSrc<MODE> src = tile_src<MODE, WHICH, 128>(rec, mats, shadow_off, lrow, lpart);
     const int nst = npad / K;
     const int kq = lane >> 4;
     const int rl = lane & 15;
@@ -829,7 +793,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
           src.a.template load<K, NL>(ra, s + DEPTH, src.va);
           src.b.template load<K, NL>(rb, s + DEPTH, src.vb);
         } else if (DEPTH == 1 && has_next) {
-          const TileSrc<MODE> sn = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, shadow_kind, lrow, lpart);
+          const TileSrc<MODE> sn = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, lrow, lpart);
           sn.a.template load<K, NL>(ra, 0, sn.va);
           sn.b.template load<K, NL>(rb, 0, sn.vb);
         }
@@ -902,12 +866,15 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
     // not use
     double part = 0.0;
     double* red = reinterpret_cast<double*>(&lds[nst & 1][0][0]);
+    const bool f32out = Pre<MODE>::value && WHICH == 1 && (rec.flags & kTileStoreF32);
 #pragma unroll
     for (int x = 0; x < (wvalid ? 4 : 0); ++x)
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
-        store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 64 + x * 16 + 4 * kq,
-                                c0 + wn * 64 + y * 16 + rl, alpha, rscale, part);
+      for (int y = 0; y < 4; ++y) {
+        const int rb = r0 + wm * 64 + x * 16 + 4 * kq, cc = c0 + wn * 64 + y * 16 + rl;
+        if (f32out) store_quad<SM_F32, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part);
+        else store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part);
+      }
     if (WHICH == 0) {
       part = wave_sum(part);
       if (lane == 0) red[wid] = part;
@@ -960,55 +927,54 @@ struct Launch {
 };
 
 template <int MODE, int WHICH, int V>
-static hipError_t launch_one(void* mats, int64_t so, int sk, const int32_t* count, const TileRec* recs,
+static hipError_t launch_one(void* mats, int64_t so, const int32_t* count, const TileRec* recs,
                              double* partials, const Launch& L) {
   using S = typename Traits<MODE>::S;
   return L.go(ns_gemm_kernel<MODE, WHICH, Var<MODE, WHICH, V>::KDIV, Var<MODE, WHICH, V>::XCD>, (S*)mats, so,
-              sk, count, recs, partials);
+              count, recs, partials);
 }
 
 template <int MODE, int WHICH>
-static hipError_t launch_which(int variant, void* mats, int64_t so, int sk, const int32_t* count,
+static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_t* count,
                                const TileRec* recs, double* partials, const Launch& L) {
   switch (variant) {
-    case 1: return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, L);
-    case 2: return launch_one<MODE, WHICH, 2>(mats, so, sk, count, recs, partials, L);
+    case 1: return launch_one<MODE, WHICH, 1>(mats, so, count, recs, partials, L);
+    case 2: return launch_one<MODE, WHICH, 2>(mats, so, count, recs, partials, L);
     case 3:
     case 4:
     case 5:
       if constexpr (MODE != SM_F64) {
         if (variant == 3)
-          return L.go(ns_gemm128_kernel<MODE, WHICH, true>, (float*)mats, so, sk, count, recs, partials);
+          return L.go(ns_gemm128_kernel<MODE, WHICH, true>, (float*)mats, so, count, recs, partials);
         if (variant == 5)
-          return L.go(ns_gemm128_kernel<MODE, WHICH, true, 3>, (float*)mats, so, sk, count, recs, partials);
-        return L.go(ns_gemm128_kernel<MODE, WHICH, false>, (float*)mats, so, sk, count, recs, partials);
+          return L.go(ns_gemm128_kernel<MODE, WHICH, true, 3>, (float*)mats, so, count, recs, partials);
+        return L.go(ns_gemm128_kernel<MODE, WHICH, false>, (float*)mats, so, count, recs, partials);
       } else {
-        return launch_one<MODE, WHICH, 1>(mats, so, sk, count, recs, partials, L);
+        return launch_one<MODE, WHICH, 1>(mats, so, count, recs, partials, L);
       }
-    default: return launch_one<MODE, WHICH, 0>(mats, so, sk, count, recs, partials, L);
+    default: return launch_one<MODE, WHICH, 0>(mats, so, count, recs, partials, L);
   }
 }
 
 template <int MODE>
-static hipError_t launch_mode(int which, int variant, void* mats, int64_t so, int sk, const int32_t* count,
+static hipError_t launch_mode(int which, int variant, void* mats, int64_t so, const int32_t* count,
                               const TileRec* recs, double* partials, const Launch& L) {
-  return which == 0 ? launch_which<MODE, 0>(variant, mats, so, sk, count, recs, partials, L)
-                    : launch_which<MODE, 1>(variant, mats, so, sk, count, recs, partials, L);
+  return which == 0 ? launch_which<MODE, 0>(variant, mats, so, count, recs, partials, L)
+                    : launch_which<MODE, 1>(variant, mats, so, count, recs, partials, L);
 }
 
-hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t so, int sk,
+hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t so,
                           const int32_t* count, const TileRec* recs, double* partials, int grid,
                           hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  // the bf16 / f16 / split-bf16 products, and float32 ones that may read
-  // copies, need the copy region
-  if ((mode >= SM_BF16 || sk != 0) && so <= 0) return hipErrorInvalidValue;
+  // the bf16 / f16 / split-bf16 products need the copy region
+  if (mode >= SM_BF16 && so <= 0) return hipErrorInvalidValue;
   const Launch L{grid, s, ev_start, ev_stop};
   switch (mode) {
-    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, 0, 0, count, recs, partials, L);
-    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, so, sk, count, recs, partials, L);
-    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, so, 0, count, recs, partials, L);
-    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, so, 0, count, recs, partials, L);
-    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, so, 0, count, recs, partials, L);
+    case SM_F64: return launch_mode<SM_F64>(which, variant, mats, 0, count, recs, partials, L);
+    case SM_F32: return launch_mode<SM_F32>(which, variant, mats, so, count, recs, partials, L);
+    case SM_BF16: return launch_mode<SM_BF16>(which, variant, mats, so, count, recs, partials, L);
+    case SM_F16: return launch_mode<SM_F16>(which, variant, mats, so, count, recs, partials, L);
+    case SM_BF16X3: return launch_mode<SM_BF16X3>(which, variant, mats, so, count, recs, partials, L);
   }
   return hipErrorInvalidValue;
 }
@@ -1062,6 +1028,7 @@ int ns_gemm_blocks_per_cu(int mode, int which, int variant) {
 struct SchedOpts {
   int refine_steps, max_iter, accel;
   double tol, switch_tol, stall_below, stall_ratio;
+  int copies_main;   // the main phase keeps only 16-bit operand copies
 };
 
 // The Newton-Schulz map with scale a on one eigenvalue x >= 0.
@@ -1158,7 +1125,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
   for (int base = 0; base < nsub; base += blockDim.x) {
     const int l = base + threadIdx.x;
-    int dec = 0, ntm = 0, ntr = 0;
+    int dec = 0, ntm = 0, ntr = 0, refine_left = -1;
     if (l < nsub) {
       SubState s = st[l];
       const int np = p.npad_g[g0 + l];
@@ -1258,13 +1225,19 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         }
       }
       st[l] = s;
+      refine_left = s.refine_left;
     }
+    // a submatrix's first refinement update multiplies the main phase's
+    // operand copies, so the main-precision kernel runs it (list 0) and
+    // stores its result in float32 (tile flag)
+    const bool first_ref_upd = o.copies_main && (dec & DEC_UPD) && (dec & DEC_REF) &&
+                               refine_left == o.refine_steps - 1;
     bool in[4];
     int cnt[8], ex[8], tot[8];
 #pragma unroll
     for (int L = 0; L < 4; ++L) {
-      in[L] = (L == 0) ? ((dec & DEC_UPD) && !(dec & DEC_REF))
-            : (L == 1) ? ((dec & DEC_UPD) && (dec & DEC_REF))
+      in[L] = (L == 0) ? ((dec & DEC_UPD) && (!(dec & DEC_REF) || first_ref_upd))
+            : (L == 1) ? ((dec & DEC_UPD) && (dec & DEC_REF) && !first_ref_upd)
             : (L == 2) ? ((dec & DEC_SQ) && !(dec & DEC_REF))
                        : ((dec & DEC_SQ) && (dec & DEC_REF));
       cnt[2 * L] = in[L] ? 1 : 0;
@@ -1308,7 +1281,8 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
                            const double* lb0, const double* top0, const double* x0s, int32_t* live_host,
                            int max_tiles_sub, hipStream_t s) {
-  SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio};
+  SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio,
+              so.phase1 >= SM_BF16 ? 1 : 0};
   // up to 64 partials per submatrix the scheduler's threads add them up
   // themselves; more are reduced by a wavefront each first
   const int fuse = max_tiles_sub <= 64;

@@ -65,12 +65,14 @@ struct TileRec {
   int32_t it;        // iteration counter (parity selects the X buffer)
   int32_t part_idx;  // residual-partial slot of the 64-tile at the tile's top-left corner
   int16_t tiles64;   // 64-tiles per dimension of the submatrix (partial slots: lower triangle)
-  int16_t flags;     // kTileFromShadow: operands are the 16-bit copies of the main phase
+  int16_t flags;     // kTileStoreF32
 };
 
-// First refinement update of a submatrix: its X and Y were produced by the
-// low-precision main phase, which stores only their 16-bit operand copies.
-constexpr int16_t kTileFromShadow = 1;
+// First refinement update of a submatrix, run by the main-precision update
+// kernel on the main phase's operand copies (a split-bf16 product of them is
+// the float32 product to float32 rounding): its result is stored in float32,
+// for the refinement steps that follow, instead of as copies.
+constexpr int16_t kTileStoreF32 = 2;
 
 // Workspace layout (bytes) for one chunk, given the storage element size.
 struct WsLayout {
@@ -121,12 +123,11 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* lb0, const double* top0, const double* x0s, int32_t* live_host,
                            int max_tiles_sub, hipStream_t s);
 // Tile records of all four lists (recs: TileRec[4][max_tiles], by list; the
-// refinement lists only with with_ref).  first_ref >= 0: refinement-update
-// tiles of submatrices with refine_left == first_ref (their first refinement
-// update) get kTileFromShadow.
+// refinement lists only with with_ref).  Main-list tiles of a submatrix in
+// refinement (its first refinement update) get kTileStoreF32.
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists, int max_subs,
-                         TileRec* recs, int64_t max_tiles, int tshift_main, int tshift_ref, int first_ref,
-                         bool with_ref, int grid_subs, hipStream_t s);
+                         TileRec* recs, int64_t max_tiles, int tshift_main, int tshift_ref, bool with_ref,
+                         int grid_subs, hipStream_t s);
 // 0: linear, 1: XCD-aware, 2: XCD-aware with half-depth LDS stages, 3: XCD-aware 128 x 128 tiles,
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices),
 // 5: as 3 with operands loaded three stages ahead
@@ -135,14 +136,12 @@ constexpr int kGemmVariants = 6;
 // exist for the float32-accumulating precisions and need n_pad % 64 == 0
 __host__ __device__ inline int tile_shift(int variant, int mode) { return (variant >= 3 && mode != SM_F64) ? 7 : 6; }
 // shadow_off: float offset of the operand copies (bf16 / f16 / split-bf16
-// products read them and also write them for their outputs); 0 otherwise
-// shadow_kind: the main precision whose copies a float32 refinement product
-// reads for kTileFromShadow tiles (0: none)
+// products read them and write them for their outputs, except for
+// kTileStoreF32 tiles); 0 otherwise.
 // ev_start / ev_stop (may be null): events the launch itself records.
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t shadow_off,
-                          int shadow_kind, const int32_t* count, const TileRec* recs,
-                          double* partials, int grid, hipStream_t s, hipEvent_t ev_start = nullptr,
-                          hipEvent_t ev_stop = nullptr);
+                          const int32_t* count, const TileRec* recs, double* partials, int grid,
+                          hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Commutator probes (1..4) of the final X against T read from H's panels.
 hipError_t launch_comm_probe(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,
                              double mu, const void* mats, int storage_f64, const SubState* st, int probes,
