@@ -9,9 +9,11 @@ is symmetric, so the kernels compute the tiles on and below the diagonal only:
                                    (the blocks on or below the diagonal inside n_pad)
 
 With a refinement phase of r steps (status 2) the counts are
-    main precision:   squares = iters_low + 1, updates = iters_low
-    refinement:       squares = r - 1,         updates = r
-and without one (status 0 / 1): squares = iters + 1, updates = iters.
+    main precision:   squares = iters_low + 1, updates = iters_low (+ 1)
+    refinement:       squares = r - 1,         updates = r (- 1)
+and without one (status 0 / 1): squares = iters + 1, updates = iters.  The
+(+ 1 / - 1): after a 16-bit main phase the first refinement update multiplies
+the main phase's operand copies and runs on the main-precision kernel.
 """
 from __future__ import annotations
 
@@ -27,13 +29,15 @@ def product_counts(stats: np.ndarray, opts) -> dict:
     r = int(opts.refine_steps)
     refined = (stats["status"] == 2)
     out = {}
+    first_on_main = np.where(refined & (int(opts.phase1) >= 2), 1, 0)
     main_sq = np.where(refined, low + 1, iters + 1)
-    main_up = np.where(refined, low, iters)
+    main_up = np.where(refined, low, iters) + first_on_main
     out[(int(opts.phase1), 0)] = main_sq
     out[(int(opts.phase1), 1)] = main_up
     if r > 0:
-        ref_up = np.where(refined, iters - low, 0)
-        ref_sq = np.where(refined, np.maximum(ref_up - 1, 0), 0)
+        ref_all = np.where(refined, iters - low, 0)
+        ref_up = ref_all - first_on_main
+        ref_sq = np.where(refined, np.maximum(ref_all - 1, 0), 0)
         key_sq = (int(opts.refine), 0)
         key_up = (int(opts.refine), 1)
         out[key_sq] = out.get(key_sq, 0) + ref_sq

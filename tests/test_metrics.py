@@ -34,10 +34,15 @@ def test_product_counts_refined_and_plain():
     o = sm.default_opts("bf16x3")          # 2 float32 refinement steps
     st = _stats([12, 10], [10, 10], [2, 1])
     c = metrics.product_counts(st, o)
-    # refined: 11 squares + 10 updates in bf16x3, 1 square + 2 updates in f32
-    # plain (status 1): 11 squares + 10 updates in bf16x3
-    assert list(c[(sm.SM_BF16X3, 0)]) == [11, 11] and list(c[(sm.SM_BF16X3, 1)]) == [10, 10]
-    assert list(c[(sm.SM_F32, 0)]) == [1, 0] and list(c[(sm.SM_F32, 1)]) == [2, 0]
+    # refined: 11 squares + 10 updates in bf16x3, 1 square + 2 updates in
+    # f32, the first of which runs on the bf16x3 kernel (it multiplies the
+    # main phase's copies); plain (status 1): 11 squares + 10 updates in bf16x3
+    assert list(c[(sm.SM_BF16X3, 0)]) == [11, 11] and list(c[(sm.SM_BF16X3, 1)]) == [11, 10]
+    assert list(c[(sm.SM_F32, 0)]) == [1, 0] and list(c[(sm.SM_F32, 1)]) == [1, 0]
+    # float64 refined in float64: every product stays in float64
+    o64 = sm.default_opts("f64", refine_steps=2, switch_tol=0.1)
+    c64 = metrics.product_counts(st, o64)
+    assert list(c64[(sm.SM_F64, 1)]) == [12, 10] and list(c64[(sm.SM_F64, 0)]) == [12, 11]
 
 
 def test_bytes_by_class():
