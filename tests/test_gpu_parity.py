@@ -167,6 +167,29 @@ def test_precision_schedules_water(prec, dp_max, de_max, dev):
     assert dP < dp_max and dE < de_max, (dP, dE)
 
 
+@pytest.mark.parametrize("prec,dp_max", [("f64", 5e-7), ("f32", 1e-5), ("bf16x3", 1e-4)])
+def test_refinement_in_phase_precision(prec, dp_max, dev):
+    """Two refinement steps after the switch in every schedule: float64 and
+    float32 refine in their own precision (their first refinement update is
+    a refinement-list product the host launches once the scheduler's count
+    shows it), split bf16 in float32 (its first refinement update runs on the
+    split kernel over the main phase's copies).  Gershgorin scaling, so the
+    submatrices switch at different iterations and main-phase and refinement
+    products share iterations.  Every submatrix ends after exactly the
+    refinement steps; two steps from ||X^2 - I|| < 0.1 leave a residual of
+    order 1e-4 (quadratic convergence, r -> 3/4 r^2), which bounds the error
+    even in float64."""
+    m = synth.water_system(24, 1.4, 5)
+    mu = gap_mu(m)
+    P, E, Ne, st, _ = run_fixed_mu(m, mu, prec, pad_to=64, refine_steps=2, switch_tol=0.1)
+    dP, dE, dNe = _compare(m, P, E, Ne, mu)
+    print(f"{prec} + 2 refinement steps: max|dP| {dP:.2e} rel dE {dE:.2e} switch at "
+          f"{st['iters_low'].min()}-{st['iters_low'].max()}")
+    assert dP < dp_max
+    assert np.all(st["status"] == 2) and np.all(st["iters"] - st["iters_low"] == 2)
+    assert st["iters_low"].max() > st["iters_low"].min()   # the switches are spread out
+
+
 def test_find_mu_config1(dev):
     import torch
     m = synth.config1()
