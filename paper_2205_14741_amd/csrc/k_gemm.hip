@@ -284,10 +284,20 @@ constexpr int kXcds = 8;
 // compute unit (160 KiB), at most 4.  Each workgroup puts one wave on every
 // SIMD, so this is also the number of waves per SIMD the register budget is
 // held to (4: at most 128 registers per lane).
+// Stage rows are padded by KP elements against LDS bank conflicts (an
+// unpadded, XOR-swizzled layout measured the same).  The array also has to
+// hold the 16-bit epilogue's result staging (4 waves x 32 x kStageStride
+// floats) and the four residual slots.
+constexpr int kStageStride = 36;   // floats per staged column: 16-byte aligned runs of 4 rows
 template <int MODE, int KDIV> struct GemmOcc {
   using Tr = Traits<MODE>;
+  static constexpr bool PRE = Pre<MODE>::value;
   static constexpr int NOP = MODE == SM_BF16X3 ? 4 : 2;
-  static constexpr int kLds = 2 * NOP * 64 * (Tr::K / KDIV + Tr::KP) * (int)sizeof(typename Tr::L);
+  static constexpr int LD = Tr::K / KDIV + Tr::KP;
+  static constexpr int kStageBytes = NOP * 64 * LD * (int)sizeof(typename Tr::L);   // one buffer
+  static constexpr int kStaged = PRE ? 4 * 32 * kStageStride * 4 : 0;
+  static constexpr int kNeed = kStaged + 4 * 8;
+  static constexpr int kLds = 2 * kStageBytes > kNeed ? 2 * kStageBytes : kNeed;
   static constexpr int by_lds = 160 * 1024 / kLds;
   static constexpr int value = by_lds < 4 ? by_lds : 4;
 };
@@ -301,8 +311,9 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   using Tr = Traits<MODE>;
   using S = typename Tr::S;
   using LT = typename Tr::L;
+  using Occ = GemmOcc<MODE, KDIV>;
   constexpr int K = Tr::K / KDIV;
-  constexpr int LD = K + Tr::KP;
+  constexpr int LD = Occ::LD;
   constexpr int NL = K / 4;              // elements per thread per operand per stage
   constexpr int KK = K / 4;              // k values per lane and stage (float64 / float32)
   constexpr bool SPLIT = (MODE == SM_BF16X3);
@@ -311,8 +322,10 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   constexpr int NOP = 2 * NPL;           // A, B (+ A_lo, B_lo)
   using RT = typename std::conditional<PRE, uint32_t, S>::type;
   constexpr int RN = PRE ? NPL * NL / 2 : NL;   // registers per operand per stage
-  __shared__ __attribute__((aligned(16))) LT lds[2][NOP][64 * LD];
-  static_assert(sizeof(lds) == (size_t)GemmOcc<MODE, KDIV>::kLds, "LDS footprint");
+  __shared__ __attribute__((aligned(16))) char lds_bytes[Occ::kLds];
+  LT (*lds)[NOP][64 * LD] = reinterpret_cast<LT (*)[NOP][64 * LD]>(lds_bytes);
+  // element offset of 16-byte chunk c of stage row r (16-bit stages)
+  auto chunk_at = [](int r, int c) { return r * LD + 8 * c; };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -373,8 +386,22 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
     for (int s = 0; s < nst; ++s) {
       const int buf = s & 1;
       // ---- registers -> LDS ----
-      stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
-      stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
+      if constexpr (PRE) {   // 16-byte chunks, hi (and lo) planes
+        constexpr int NW = NL / 2;
+#pragma unroll
+        for (int q = 0; q < NPL; ++q)
+#pragma unroll
+          for (int c = 0; c < NL / 8; ++c) {
+            const int at = chunk_at(lrow, lpart / 8 + c);
+            *reinterpret_cast<u32x4*>(&lds[buf][q == 0 ? 0 : NOP - 2][at]) =
+                u32x4{ra[q * NW + 4 * c], ra[q * NW + 4 * c + 1], ra[q * NW + 4 * c + 2], ra[q * NW + 4 * c + 3]};
+            *reinterpret_cast<u32x4*>(&lds[buf][q == 0 ? 1 : NOP - 1][at]) =
+                u32x4{rb[q * NW + 4 * c], rb[q * NW + 4 * c + 1], rb[q * NW + 4 * c + 2], rb[q * NW + 4 * c + 3]};
+          }
+      } else {
+        stage_store<MODE, NL>(ra, &lds[buf][0][lrow * LD + lpart], &lds[buf][NOP - 2][lrow * LD + lpart]);
+        stage_store<MODE, NL>(rb, &lds[buf][1][lrow * LD + lpart], &lds[buf][NOP - 1][lrow * LD + lpart]);
+      }
       __syncthreads();
       // ---- prefetch the next stage (or the next tile's first) ----
       if (s + 1 < nst) {
@@ -433,8 +460,8 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
             f16x8 a[2], b[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-              a[x] = *reinterpret_cast<const f16x8*>(&lds[buf][0][(wm * 32 + x * 16 + rl) * LD + ko]);
-              b[x] = *reinterpret_cast<const f16x8*>(&lds[buf][1][(wn * 32 + x * 16 + rl) * LD + ko]);
+              a[x] = *reinterpret_cast<const f16x8*>(&lds[buf][0][chunk_at(wm * 32 + x * 16 + rl, ko / 8)]);
+              b[x] = *reinterpret_cast<const f16x8*>(&lds[buf][1][chunk_at(wn * 32 + x * 16 + rl, ko / 8)]);
             }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -445,15 +472,15 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
             bf16x8 a[2], b[2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-              a[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][0][(wm * 32 + x * 16 + rl) * LD + ko]));
-              b[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][1][(wn * 32 + x * 16 + rl) * LD + ko]));
+              a[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][0][chunk_at(wm * 32 + x * 16 + rl, ko / 8)]));
+              b[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][1][chunk_at(wn * 32 + x * 16 + rl, ko / 8)]));
             }
             if constexpr (SPLIT) {
               bf16x8 al[2], bl[2];
 #pragma unroll
               for (int x = 0; x < 2; ++x) {
-                al[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][2][(wm * 32 + x * 16 + rl) * LD + ko]));
-                bl[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][3][(wn * 32 + x * 16 + rl) * LD + ko]));
+                al[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][2][chunk_at(wm * 32 + x * 16 + rl, ko / 8)]));
+                bl[x] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&lds[buf][3][chunk_at(wn * 32 + x * 16 + rl, ko / 8)]));
               }
 #pragma unroll
               for (int x = 0; x < 2; ++x)
@@ -488,10 +515,11 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
     const int kq = lane >> 4;
     // the four wave sums of the residual meet in the stage buffer the last
     // stage did not use (past the result staging of the 16-bit epilogue)
-    constexpr size_t kStageB = sizeof(lds[0]);
-    constexpr size_t kStaged = Pre<MODE>::value ? 4 * 32 * 33 * sizeof(float) : 0;
+    constexpr size_t kStageB = Occ::kStageBytes;
+    constexpr int SS = kStageStride;
+    constexpr size_t kStaged = Occ::kStaged;
     constexpr bool kIdleFits = kStageB >= kStaged + 4 * sizeof(double);
-    static_assert(2 * kStageB >= kStaged + 4 * sizeof(double), "residual slots");
+    static_assert((size_t)Occ::kLds >= kStaged + 4 * sizeof(double), "residual slots");
     double* red = reinterpret_cast<double*>(
         kIdleFits ? reinterpret_cast<char*>(&lds[nst & 1][0][0]) + kStaged
                   : reinterpret_cast<char*>(&lds[0][0][0]) + kStaged);
@@ -540,38 +568,50 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
         __syncthreads();
         stg = reinterpret_cast<float*>(&lds[0][0][0]);
       }
-      float* my = stg + wid * (32 * 33);
+      float* my = stg + wid * (32 * SS);
       if (wvalid) {
         const int R0 = r0 + wm * 32, C0 = c0 + wn * 32;
         const float a2 = (float)(alpha * alpha), ha = (float)(0.5 * alpha), rsf = (float)rscale;
+        // staging: my[lc * SS + lr]; a lane's four rows of a column are one
+        // 16-byte store
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 2; ++y)
+          for (int y = 0; y < 2; ++y) {
+            const int lc = y * 16 + (lane & 15);
+            float o[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int lr = x * 16 + 4 * kq + v, lc = y * 16 + (lane & 15);
+              const int lr = x * 16 + 4 * kq + v;
               const float a = acc[x][y][v];
-              float o;
               if (WHICH == 0) {
                 const float dg = (R0 + lr == C0 + lc) ? 1.0f : 0.0f;
                 const float e = a * rsf - dg;   // exact for rsf = 1: a ~ 1 on the diagonal
                 if (R0 + lr >= C0 + lc) part += (double)(e * e) * (R0 + lr == C0 + lc ? 1.0 : 2.0);
-                o = __builtin_fmaf(-a2, a, 3.0f * dg);
+                o[v] = __builtin_fmaf(-a2, a, 3.0f * dg);
               } else {
-                o = ha * a;
+                o[v] = ha * a;
               }
-              my[lc * 33 + lr] = o;
             }
+            *reinterpret_cast<f4*>(&my[lc * SS + x * 16 + 4 * kq]) = f4{o[0], o[1], o[2], o[3]};
+          }
         wave_sync();
         const int li = lane >> 1, h = (lane & 1) * 16;
         const bool diag = R0 == C0;
         float w[16];
-        // the block, column C0 + li, rows R0 + h ..; on a diagonal block the
-        // entries above the diagonal take the value of their mirror
+        // the block, column C0 + li, rows R0 + h .. (four 16-byte loads); on
+        // a diagonal block the entries above the diagonal take the value of
+        // their mirror
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          w[j] = (diag && h + j < li) ? my[(h + j) * 33 + li] : my[li * 33 + h + j];
+        for (int q = 0; q < 4; ++q) {
+          const f4 t = *reinterpret_cast<const f4*>(&my[li * SS + h + 4 * q]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) w[4 * q + e] = t[e];
+        }
+        if (diag)
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (h + j < li) w[j] = my[(h + j) * SS + li];
         const bool f32out = WHICH == 1 && (rec.flags & kTileStoreF32);
         auto put16 = [&](int col, int row0) {
           if (f32out) store_run16<SM_F32>(w, Out, shadow_off, col, row0, npad);
@@ -580,7 +620,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
         put16(C0 + li, R0 + h);
         if (!diag) {   // the mirror: column R0 + li, rows C0 + h ..
 #pragma unroll
-          for (int j = 0; j < 16; ++j) w[j] = my[(h + j) * 33 + li];
+          for (int j = 0; j < 16; ++j) w[j] = my[(h + j) * SS + li];
           put16(R0 + li, C0 + h);
         }
       }

@@ -131,11 +131,14 @@ def test_low_precision_on_pad_32(prec, dp_max, dev):
         np.testing.assert_array_equal(P, P0)
 
 
-def test_chunked_equals_single_chunk(dev):
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_chunked_equals_single_chunk(prec, dev):
+    """Chunks only bound the workspace: every submatrix's products, residuals
+    and read-out are the same, so P, E and Ne are bitwise equal."""
     m = synth.water_system(24, 1.4, 5)
     mu = gap_mu(m)
-    P1, E1, N1, _, _ = run_fixed_mu(m, mu, "f64")
-    P2, E2, N2, _, plan = run_fixed_mu(m, mu, "f64", max_chunk_elems=3 * 256 * 256 * 5)
+    P1, E1, N1, _, _ = run_fixed_mu(m, mu, prec)
+    P2, E2, N2, _, plan = run_fixed_mu(m, mu, prec, max_chunk_elems=3 * 256 * 256 * 5)
     assert plan.n_chunks > 3
     np.testing.assert_array_equal(P1, P2)
     assert E1 == E2 and N1 == N2
