@@ -167,9 +167,13 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   int g0, nsub;
   if ((rc = chunk_range(p, chunk, g0, nsub))) return rc;
   if ((rc = ensure_device(p))) return rc;
-  const size_t lds = (size_t)(2 * p->max_m + 4 * p->max_npad) * sizeof(int);   // gather: 4 row maps
+  const size_t lds = gather_lds_bytes(p->max_m, p->max_npad, false);   // gather: 4 row maps
   if (lds > 64 * 1024)
     return set_error(SM_ERR_ARG, "build_submatrices: index set too large for the gather (needs %zu B of LDS)", lds);
+  // the gather also forms the first power-iteration product when the
+  // schedule runs power steps and its partial sums fit the LDS
+  const bool power_in_gather = o->scaling != SM_SCALE_GERSHGORIN && o->power_steps > 0 &&
+                               gather_lds_bytes(p->max_m, p->max_npad, true) <= 64 * 1024;
   const int storage = ws_storage(o);
   const int f64 = storage == SM_F64;
   const int64_t shadow = storage >= SM_BF16 ? p->shadow_off() : 0;
@@ -184,7 +188,7 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   float* pred = reinterpret_cast<float*>(w.scratch + p->max_subs);  // [2 max_subs]
   const int shadow_kind = storage >= SM_BF16 ? storage : 0;
   SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, shadow_kind, shadow, flag,
-                       w.features, cg, stats, s));
+                       w.features, cg, stats, power_in_gather ? w.vecs : nullptr, s));
   const float* predp = nullptr;
   if (o->scaling == SM_SCALE_LEARNED) {
     if (!p->mlp) return set_error(SM_ERR_STATE, "build_submatrices: learned scaling needs a network (sm_plan_set_mlp)");
@@ -194,7 +198,7 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   }
   SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
                       cg, predp, stats, shadow_kind, shadow, o->lbound, w.scratch + 2 * p->max_subs,
-                      w.scratch + 3 * p->max_subs, w.scratch + 4 * p->max_subs, s));
+                      w.scratch + 3 * p->max_subs, w.scratch + 4 * p->max_subs, power_in_gather, s));
   p->last_storage = storage;
   return SM_OK;
 }
@@ -231,7 +235,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   // submatrix's first refinement update is run on those by the main kernel
   const int shadow_kind = storage >= SM_BF16 ? storage : 0;
   // the scheduler's lists -> tile records of this iteration's updates and
-  // the next iteration's squares (one launch)
+  // the next iteration's squares (one launch; written by the scheduler's
+  // single workgroup itself they cost 49 instead of 4 us on the lattice)
   auto expand = [&]() -> int {
     SM_HIP(launch_expand(p->dev, g0, w.st, w.lists, ms, w.tiles, p->max_tiles, tsh_main, tsh_ref, has_ref,
                          nsub, s));

@@ -638,6 +638,57 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   }
 }
 
+// The tile records of one listed submatrix in list L (0 / 1: updates, main /
+// refinement precision; 2 / 3: squares of the next iteration): the tile
+// walk of every GEMM reads its tile's buffers, scale and flags from these.
+struct SubTiles {
+  int64_t mo;
+  float alpha, rscale;
+  int npad, it, f, nt, po, t64;
+  int16_t flags;
+};
+
+__device__ __forceinline__ SubTiles sub_tiles(const DevPlan& p, int g, int L, int tshift, int iters, int phase,
+                                              double alpha_sq, double alpha_upd, double x0s_in) {
+  const int which = L < 2 ? 1 : 0;
+  SubTiles t;
+  t.npad = p.npad_g[g];
+  const int T = (t.npad + (1 << tshift) - 1) >> tshift;
+  t.f = 1 << (tshift - 6);
+  t.nt = T * (T + 1) / 2;
+  t.mo = p.mat_off_g[g];
+  t.it = iters;
+  // products that read X_0 (the square at it = 0, the update producing X_1)
+  // apply its factor x0s to the buffer's contents
+  const bool reads_x0 = which == 0 ? iters == 0 : iters == 1;
+  const double x0s = reads_x0 ? x0s_in : 1.0;
+  t.alpha = (float)((which == 0 ? alpha_sq : alpha_upd) * x0s);
+  t.rscale = (float)(which == 0 ? x0s * x0s : 1.0);
+  // list 0 also holds first refinement updates (phase 1): their result is
+  // stored in float32 for the refinement steps that follow
+  t.flags = (L == 0 && phase == 1) ? kTileStoreF32 : 0;
+  t.po = p.tile_off_g[g];
+  t.t64 = tiles_of(t.npad);
+  return t;
+}
+
+__device__ __forceinline__ TileRec tile_rec(const SubTiles& t, int lt) {
+  int bi, bj;
+  tile_coords(lt, bi, bj);
+  const int b64i = bi * t.f, b64j = bj * t.f;
+  TileRec r;
+  r.mat_off = t.mo;
+  r.alpha = t.alpha;
+  r.rscale = t.rscale;
+  r.bibj = (bi << 16) | bj;
+  r.npad = t.npad;
+  r.it = t.it;
+  r.part_idx = t.po + b64i * (b64i + 1) / 2 + b64j;
+  r.tiles64 = (int16_t)t.t64;
+  r.flags = t.flags;
+  return r;
+}
+
 // Tile records of every list the scheduler just built, in one launch: one
 // workgroup per (listed submatrix, list).  blockIdx.y picks the list: 0
 // updates (main precision), 1 squares of the next iteration (main), 2 / 3 the
@@ -651,49 +702,16 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int stride = 2 + 2 * max_subs + 1;
   const int y = blockIdx.y;
   const int L = (y & 1) ? 2 + (y >> 1) : (y >> 1);   // 0, 2, 1, 3
-  const bool ref = (L & 1) != 0;
-  const int which = L < 2 ? 1 : 0;
   const int32_t* Lb = lists + L * stride;
   TileRec* out = recs + L * max_tiles;
-  const int tshift = ref ? tshift_ref : tshift_main;
   const int a = blockIdx.x;
   if (a >= Lb[1]) return;
   const int l = Lb[2 + a];
   const int first = Lb[2 + max_subs + a];
-  const int g = g0 + l;
-  const int npad = p.npad_g[g];
-  const int T = (npad + (1 << tshift) - 1) >> tshift;
-  const int f = 1 << (tshift - 6);
-  const int nt = T * (T + 1) / 2;
-  const int64_t mo = p.mat_off_g[g];
-  const int it = st[l].iters;
-  // products that read X_0 (the square at it = 0, the update producing X_1)
-  // apply its factor x0s to the buffer's contents
-  const bool reads_x0 = which == 0 ? it == 0 : it == 1;
-  const double x0s = reads_x0 ? st[l].x0s : 1.0;
-  const float alpha = (float)((which == 0 ? st[l].alpha_sq : st[l].alpha_upd) * x0s);
-  const float rscale = (float)(which == 0 ? x0s * x0s : 1.0);
-  // list 0 also holds first refinement updates (phase 1): their result is
-  // stored in float32 for the refinement steps that follow
-  const int16_t flags = (L == 0 && st[l].phase == 1) ? kTileStoreF32 : 0;
-  const int po = p.tile_off_g[g];
-  const int t64 = tiles_of(npad);
-  for (int lt = threadIdx.x; lt < nt; lt += blockDim.x) {
-    int bi, bj;
-    tile_coords(lt, bi, bj);
-    const int b64i = bi * f, b64j = bj * f;
-    TileRec r;
-    r.mat_off = mo;
-    r.alpha = alpha;
-    r.rscale = rscale;
-    r.bibj = (bi << 16) | bj;
-    r.npad = npad;
-    r.it = it;
-    r.part_idx = po + b64i * (b64i + 1) / 2 + b64j;
-    r.tiles64 = (int16_t)t64;
-    r.flags = flags;
-    out[first + lt] = r;
-  }
+  const SubState& s = st[l];
+  const SubTiles t = sub_tiles(p, g0 + l, L, (L & 1) ? tshift_ref : tshift_main, s.iters, s.phase, s.alpha_sq,
+                               s.alpha_upd, s.x0s);
+  for (int lt = threadIdx.x; lt < t.nt; lt += blockDim.x) out[first + lt] = tile_rec(t, lt);
 }
 
 hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int32_t* lists, int max_subs,

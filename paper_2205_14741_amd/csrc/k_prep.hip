@@ -57,13 +57,19 @@ struct ColStats {
 // of the submatrix from the statistics of all waves.
 // LDS: atoms of I_i and their row offsets (2 m ints), one row map of n_pad
 // ints per wave.
-template <typename T, int KIND>
+// POW: also the first power-iteration product w = T v0 (v0 the fixed +-1
+// probe vector 11, Euclidean norm sqrt(n)) for the scale kernel, from the
+// entries as they are gathered: each wave adds its columns' contributions to
+// its own LDS row of partial sums, combined in wave order at the end.  This
+// saves the scale kernel one read pass over T.
+template <typename T, int KIND, bool POW>
 __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const double* __restrict__ H,
                                                      double mu, T* __restrict__ mats,
                                                      int64_t shadow_off, int* nonfinite,
                                                      float* __restrict__ features, double* __restrict__ cg_out,
-                                                     sm_sub_stats* __restrict__ stats) {
-  extern __shared__ int smem[];
+                                                     sm_sub_stats* __restrict__ stats,
+                                                     double* __restrict__ vecs) {
+  extern __shared__ __attribute__((aligned(16))) int smem[];
   __shared__ double red[8];
   const int g = g0 + blockIdx.x;
   const int i = p.order_g[g];
@@ -79,6 +85,8 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   int* s_atom = smem;
   int* s_off = smem + m;
   int* s_src = smem + 2 * m + wid * npad;
+  // POW: partial sums of T v0, one row of n_pad doubles per wave
+  double* s_tv = reinterpret_cast<double*>(smem + ((2 * m + nw * npad + 1) & ~1)) + wid * npad;
   T* X = mats + p.mat_off_g[g];
   // low-precision schedules: T goes straight into the 16-bit operand copies
   // that the products read (the float32 buffer is not written).  Every lane
@@ -112,6 +120,8 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
     s_atom[t] = p.row_idx[k0 + t];
     s_off[t] = p.blk_rowoff[k0 + t];
   }
+  if constexpr (POW)
+    for (int d = lane; d < npad; d += kWave) s_tv[d] = 0.0;
   __syncthreads();
   bool bad = false;
   ColStats cs;   // this wave's columns (identical in every lane)
@@ -126,12 +136,18 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
     // independent panel loads per row
     for (int q0 = 0; q0 < bj; q0 += 4) {
       double sa[4] = {0.0, 0.0, 0.0, 0.0}, sq[4] = {0.0, 0.0, 0.0, 0.0}, dl[4] = {0.0, 0.0, 0.0, 0.0};
+      double pv[4] = {0.0, 0.0, 0.0, 0.0};   // probe entries of the four columns
+      if constexpr (POW)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q0 + u < bj) pv[u] = probe_entry(11, locj + q0 + u);
 #pragma unroll 2
       for (int d = lane; d < npad; d += kWave) {
         const int s = d < n ? s_src[d] : -1;
         double v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) v[u] = (q0 + u < bj && s >= 0) ? panel[(int64_t)(q0 + u) * hj + s] : 0.0;
+        double tv = 0.0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int c = locj + q0 + u;
@@ -144,9 +160,11 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
             bad |= !isfinite(x);
             sa[u] += fabs(x);
             sq[u] += x * x;
+            tv += x * pv[u];
             put(c, d, x);
           }
         }
+        if constexpr (POW) s_tv[d] += tv;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -160,6 +178,16 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   for (int c = n + wid; c < npad; c += nw)
     for (int d = lane; d < npad; d += kWave) put(c, d, d == c ? 1.0 : 0.0);
   if (bad) *nonfinite = 1 + i;
+  if constexpr (POW) {   // w = T v0 = the waves' partial sums in wave order
+    __syncthreads();
+    const double* tv0 = s_tv - wid * npad;
+    double* w = vecs + p.vec_off_g[g] + npad;
+    for (int d = threadIdx.x; d < n; d += blockDim.x) {
+      double y = 0.0;
+      for (int k = 0; k < nw; ++k) y += tv0[k * npad + d];
+      w[d] = y;
+    }
+  }
   // combine the waves (every lane of a wave holds its values)
   const double cmax = block_reduce<1>(cs.cmax, red);
   const double sdiag = block_reduce<0>(lane == 0 ? cs.sdiag : 0.0, red);
@@ -206,20 +234,32 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   }
 }
 
+size_t gather_lds_bytes(int max_m, int max_npad, bool power) {
+  // 4 waves: atoms + offsets, a row map per wave, (power) a row of partial
+  // sums of T v0 per wave
+  size_t b = (size_t)((2 * max_m + 4 * max_npad + 1) & ~1) * sizeof(int);
+  if (power) b += (size_t)4 * max_npad * sizeof(double);
+  return b;
+}
+
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
                          const double* H, double mu, void* mats, int storage_f64, int shadow_kind,
                          int64_t shadow_off, int* nonfinite, float* features, double* cg_out,
-                         sm_sub_stats* stats, hipStream_t s) {
+                         sm_sub_stats* stats, double* power_vecs, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);   // 4 waves
-#define SM_GATHER(TT, K)                                                                             \
-  hipLaunchKernelGGL((gather_kernel<TT, K>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, (TT*)mats, \
-                     shadow_off, nonfinite, features, cg_out, stats)
-  if (storage_f64) SM_GATHER(double, 0);
-  else if (shadow_kind == SM_BF16X3) SM_GATHER(float, SM_BF16X3);
-  else if (shadow_kind == SM_BF16) SM_GATHER(float, SM_BF16);
-  else if (shadow_kind == SM_F16) SM_GATHER(float, SM_F16);
-  else SM_GATHER(float, 0);
+  const bool pw = power_vecs != nullptr;
+  const size_t lds = gather_lds_bytes(max_m, max_npad, pw);
+#define SM_GATHER(TT, K, PW)                                                                             \
+  hipLaunchKernelGGL((gather_kernel<TT, K, PW>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, (TT*)mats, \
+                     shadow_off, nonfinite, features, cg_out, stats, power_vecs)
+#define SM_GATHER2(TT, K) \
+  if (pw) SM_GATHER(TT, K, true); else SM_GATHER(TT, K, false)
+  if (storage_f64) { SM_GATHER2(double, 0); }
+  else if (shadow_kind == SM_BF16X3) { SM_GATHER2(float, SM_BF16X3); }
+  else if (shadow_kind == SM_BF16) { SM_GATHER2(float, SM_BF16); }
+  else if (shadow_kind == SM_F16) { SM_GATHER2(float, SM_F16); }
+  else { SM_GATHER2(float, 0); }
+#undef SM_GATHER2
 #undef SM_GATHER
   return hipGetLastError();
 }
@@ -241,7 +281,7 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     int64_t shadow_off, double lbound,
                                                     double* __restrict__ lb0_out,
                                                     double* __restrict__ top0_out,
-                                                    double* __restrict__ x0s_out) {
+                                                    double* __restrict__ x0s_out, int pre_w) {
   __shared__ double red[16];
   __shared__ double mv[matvec_red<1, T>(8)];
   const int l = blockIdx.x;
@@ -263,17 +303,32 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
   if (scaling != SM_SCALE_GERSHGORIN && power_steps > 0) {
     double* v = vecs + p.vec_off_g[g];
     double* w = v + npad;
-    double nv = 0.0;
-    for (int d = threadIdx.x; d < n; d += blockDim.x) {
-      const double x = probe_entry(11, d);
-      v[d] = x;
-      nv += x * x;
+    int it0 = 0;
+    double inv;
+    if (pre_w) {
+      // the gather formed w = T v0 for the unit-free probe v0 (+-1 entries,
+      // norm sqrt(n)): the first step's estimate and the next direction
+      double nw2 = 0.0;
+      for (int d = threadIdx.x; d < n; d += blockDim.x) nw2 += w[d] * w[d];
+      nw2 = block_reduce<0>(nw2, red);
+      est = sqrt(nw2 / (double)n);
+      inv = nw2 > 0.0 ? 1.0 / sqrt(nw2) : 0.0;
+      for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] = w[d] * inv;
+      __syncthreads();
+      it0 = 1;
+    } else {
+      double nv = 0.0;
+      for (int d = threadIdx.x; d < n; d += blockDim.x) {
+        const double x = probe_entry(11, d);
+        v[d] = x;
+        nv += x * x;
+      }
+      nv = block_reduce<0>(nv, red);
+      inv = 1.0 / sqrt(nv);
+      for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] *= inv;
+      __syncthreads();
     }
-    nv = block_reduce<0>(nv, red);
-    double inv = 1.0 / sqrt(nv);
-    for (int d = threadIdx.x; d < n; d += blockDim.x) v[d] *= inv;
-    __syncthreads();
-    for (int it = 0; it < power_steps; ++it) {
+    for (int it = it0; it < power_steps; ++it) {
       if (copies)   // w = T v
         block_matvec_copies<1>(cp, npad, n, shadow_kind, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
       else
@@ -351,16 +406,17 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
-                        double lbound, double* lb0_out, double* top0_out, double* x0s_out, hipStream_t s) {
+                        double lbound, double* lb0_out, double* top0_out, double* x0s_out, bool pre_w,
+                        hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   if (storage_f64)
     hipLaunchKernelGGL(scale_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, 0, (int64_t)0, lbound, lb0_out,
-                       top0_out, x0s_out);
+                       top0_out, x0s_out, pre_w ? 1 : 0);
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off, lbound,
-                       lb0_out, top0_out, x0s_out);
+                       lb0_out, top0_out, x0s_out, pre_w ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -94,10 +94,15 @@ struct WsLayout {
 // stats.gersh) and the features of the scaling network (features, stats.feat).
 // shadow_kind: 0, or SM_BF16 / SM_F16 / SM_BF16X3 to write T_i only as the
 // operand copies at float offset shadow_off from its float32 buffer.
+// power_vecs (may be null): also w = T v0, the first power-iteration product
+// of the scale kernel, into each submatrix's vectors (the scale kernel is then
+// launched with pre_w).
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
                          const double* H, double mu, void* mats, int storage_f64, int shadow_kind,
                          int64_t shadow_off, int* nonfinite, float* features, double* cg_out,
-                         sm_sub_stats* stats, hipStream_t s);
+                         sm_sub_stats* stats, double* power_vecs, hipStream_t s);
+// Dynamic LDS bytes of the gather (with the power-product rows or without).
+size_t gather_lds_bytes(int max_m, int max_npad, bool power);
 // shadow_kind / shadow_off: where T_i is (as for the gather).  lbound:
 // opts.lbound; lb0_out / top0_out [nsub]: bounds on the smallest / largest
 // |eigenvalue| of X_0 for scaled Newton-Schulz (learned second output when the
@@ -107,7 +112,8 @@ hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_
 hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int storage_f64, int scaling,
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
-                        double lbound, double* lb0_out, double* top0_out, double* x0s_out, hipStream_t s);
+                        double lbound, double* lb0_out, double* top0_out, double* x0s_out, bool pre_w,
+                        hipStream_t s);
 // first != 0 initialises the iteration state; lb0 / top0 [nsub] (may be null):
 // bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz);
 // x0s [nsub] (may be null: 1): SubState.x0s;
@@ -115,8 +121,8 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
 // of submatrices that square again after this iteration's updates (0: the
 // iteration is over for the chunk), the tile counts of the next squares in
 // the main and the refinement precision, and that of this iteration's
-// refinement updates.  max_tiles_sub: most 64-tiles (lower
-// triangle) of a submatrix in the chunk.
+// refinement updates.  max_tiles_sub: most 64-tiles (lower triangle) of a
+// submatrix in the chunk.
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
