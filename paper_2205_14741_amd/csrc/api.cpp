@@ -361,7 +361,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   }
   if (!f64)   // float32 final X where only its copies, or T (X = X_0), are in the buffer
     SM_HIP(launch_materialize(p->dev, g0, nsub, (float*)w.mats, w.st, shadow_kind, shadow, s));
-  SM_HIP(launch_finish(p->dev, g0, nsub, w.mats, f64, w.st, o->probes, w.vecs, stats, s));
+  SM_HIP(launch_finish(p->dev, g0, nsub, w.mats, f64, w.st, o->probes, w.vecs, stats, p->max_npad, s));
   return SM_OK;
 }
 

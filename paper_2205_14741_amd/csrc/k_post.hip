@@ -66,10 +66,11 @@ template <typename T, int P>
 __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T* __restrict__ mats,
                                                      const SubState* __restrict__ st,
                                                      double* __restrict__ vecs,
-                                                     sm_sub_stats* __restrict__ stats) {
+                                                     sm_sub_stats* __restrict__ stats, int vec_lds) {
   constexpr int Q = P > 0 ? P : 1;
   __shared__ double red[matvec_red<Q, T>(8)];
   __shared__ double red2[8];
+  extern __shared__ double fvec[];   // vec_lds: the probe vectors and X v in LDS
   const int l = blockIdx.x;
   const int g = g0 + l;
   const int i = p.order_g[g];
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
   const T* X = final_x(p, g, mats, st, l);
   double worst = -1.0;
   if constexpr (P > 0) {
-    double* v = vecs + p.vec_off_g[g];      // [P][npad]
-    double* w = v + (int64_t)P * npad;       // [P][npad] = X v
+    double* v = vec_lds ? fvec : vecs + p.vec_off_g[g];   // [P][npad]
+    double* w = v + (int64_t)P * npad;                     // [P][npad] = X v
     for (int d = threadIdx.x; d < n; d += blockDim.x)
 #pragma unroll
       for (int q = 0; q < P; ++q) v[q * npad + d] = probe_entry(q, d);
@@ -111,10 +112,15 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
 
 template <typename T>
 static hipError_t launch_finish_t(const DevPlan& p, int g0, int nsub, const T* mats, const SubState* st,
-                                  int probes, double* vecs, sm_sub_stats* stats, hipStream_t s) {
+                                  int probes, double* vecs, sm_sub_stats* stats, int max_npad, hipStream_t s) {
+  // probe vectors and X v in LDS while they take at most 16 KiB (lattice
+  // submatrices), else in the workspace
+  const size_t vb = (size_t)2 * probes * max_npad * sizeof(double);
+  const size_t lds = vb <= 16 * 1024 ? vb : 0;
 #define SM_FINISH(PR)                                                                                 \
   case PR:                                                                                            \
-    hipLaunchKernelGGL((finish_kernel<T, PR>), dim3(nsub), dim3(512), 0, s, p, g0, mats, st, vecs, stats); \
+    hipLaunchKernelGGL((finish_kernel<T, PR>), dim3(nsub), dim3(512), lds, s, p, g0, mats, st, vecs, stats, \
+                       lds ? 1 : 0);                                                                  \
     break;
   switch (probes) {
     SM_FINISH(0) SM_FINISH(1) SM_FINISH(2) SM_FINISH(3) SM_FINISH(4) SM_FINISH(5) SM_FINISH(6)
@@ -126,12 +132,13 @@ static hipError_t launch_finish_t(const DevPlan& p, int g0, int nsub, const T* m
 }
 
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
-                         const SubState* st, int probes, double* vecs, sm_sub_stats* stats,
+                         const SubState* st, int probes, double* vecs, sm_sub_stats* stats, int max_npad,
                          hipStream_t s) {
   static_assert(kMaxProbes == 8, "finish kernels are instantiated for 0..8 probes");
   if (nsub <= 0) return hipSuccess;
-  if (storage_f64) return launch_finish_t(p, g0, nsub, (const double*)mats, st, probes, vecs, stats, s);
-  return launch_finish_t(p, g0, nsub, (const float*)mats, st, probes, vecs, stats, s);
+  if (storage_f64)
+    return launch_finish_t(p, g0, nsub, (const double*)mats, st, probes, vecs, stats, max_npad, s);
+  return launch_finish_t(p, g0, nsub, (const float*)mats, st, probes, vecs, stats, max_npad, s);
 }
 
 // y_q = T w_q (q < Q) for T = H[idx_i, idx_i] - mu I read straight from H's

@@ -160,7 +160,7 @@ hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, c
                               int shadow_kind, int64_t shadow_off, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
-                         const SubState* st, int probes, double* vecs, sm_sub_stats* stats,
+                         const SubState* st, int probes, double* vecs, sm_sub_stats* stats, int max_npad,
                          hipStream_t s);
 hipError_t launch_scatter(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                           const SubState* st, double* P, hipStream_t s);
