@@ -98,7 +98,7 @@ typedef struct {
                             128; otherwise runs as 1), 4 = 128 x 128 tiles walked in list
                             order (all XCDs on the same submatrices: their operands stay in
                             the shared last-level cache), 5 = as 3 with the operands loaded
-                            three stages ahead (large submatrices).  bf16 / f16 / split-bf16
+                            six stages ahead (large submatrices).  bf16 / f16 / split-bf16
                             products on a plan padded to 32 always run as 2 */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,

@@ -744,6 +744,11 @@ template <> struct Traits128<SM_BF16X3> { using S = float; using L = uint16_t; s
 // Register budget of the 128-tile kernel: two waves per SIMD (at most 256
 // registers per lane) where the LDS stages let two workgroups share a compute
 // unit; the deep ring (DEPTH > 1) takes more registers and runs one.
+// Stages in flight of variant 5 (a register ring at one wave per SIMD; on
+// the water submatrices 3 / 4 / 6 / 8 stages took 1173 / 1015 / 1002 / 1005 ms
+// per sign pass of a chunk).
+constexpr int kDeepRing = 6;
+
 template <int MODE, int DEPTH> struct Gemm128Occ {
   using Tr = Traits128<MODE>;
   static constexpr int NOP = MODE == SM_BF16X3 ? 4 : 2;
@@ -1005,7 +1010,7 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_
         if (variant == 3)
           return L.go(ns_gemm128_kernel<MODE, WHICH, true>, (float*)mats, so, count, recs, partials);
         if (variant == 5)
-          return L.go(ns_gemm128_kernel<MODE, WHICH, true, 3>, (float*)mats, so, count, recs, partials);
+          return L.go(ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>, (float*)mats, so, count, recs, partials);
         return L.go(ns_gemm128_kernel<MODE, WHICH, false>, (float*)mats, so, count, recs, partials);
       } else {
         return launch_one<MODE, WHICH, 1>(mats, so, count, recs, partials, L);
@@ -1049,7 +1054,7 @@ static void* ptr_which(int variant) {
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, false>);
       else return kernel_ptr<MODE, WHICH, 1>();
     case 5:
-      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, 3>);
+      if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>);
       else return kernel_ptr<MODE, WHICH, 1>();
     default: return kernel_ptr<MODE, WHICH, 0>();
   }

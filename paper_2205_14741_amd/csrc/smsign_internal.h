@@ -136,7 +136,7 @@ hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int
                          int grid_subs, hipStream_t s);
 // 0: linear, 1: XCD-aware, 2: XCD-aware with half-depth LDS stages, 3: XCD-aware 128 x 128 tiles,
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices),
-// 5: as 3 with operands loaded three stages ahead
+// 5: as 3 with operands loaded six stages ahead
 constexpr int kGemmVariants = 6;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
 // exist for the float32-accumulating precisions and need n_pad % 64 == 0

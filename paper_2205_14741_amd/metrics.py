@@ -85,7 +85,7 @@ def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
     if mode >= 2 and pad_to < 64:   # 16-bit products on a plan padded to 32
         v = 2
     if v >= 3:   # 128-wide tiles: <precision, kind, XCD-aware walk, prefetch depth>
-        return f"sm::ns_gemm128_kernel<{mode}, {which}, {'false' if v == 4 else 'true'}, {3 if v == 5 else 1}>"
+        return f"sm::ns_gemm128_kernel<{mode}, {which}, {'false' if v == 4 else 'true'}, {6 if v == 5 else 1}>"
     kdiv = 2 if v == 2 else 1   # variant 2: half-depth LDS stages
     return f"sm::ns_gemm_kernel<{mode}, {which}, {kdiv}, {'true' if v >= 1 else 'false'}>"
 

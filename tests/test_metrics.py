@@ -58,7 +58,7 @@ def test_kernel_symbols_follow_launcher_fallback():
     assert metrics.gemm_kernel_symbol(4, 1, 2, 64) == "sm::ns_gemm_kernel<4, 1, 2, true>"
     assert metrics.gemm_kernel_symbol(4, 1, 3, 64) == "sm::ns_gemm128_kernel<4, 1, true, 1>"
     assert metrics.gemm_kernel_symbol(1, 0, 4, 64) == "sm::ns_gemm128_kernel<1, 0, false, 1>"
-    assert metrics.gemm_kernel_symbol(4, 0, 5, 64) == "sm::ns_gemm128_kernel<4, 0, true, 3>"
+    assert metrics.gemm_kernel_symbol(4, 0, 5, 64) == "sm::ns_gemm128_kernel<4, 0, true, 6>"
     # 16-bit products on a plan padded to 32 run the half-depth-stage kernel
     assert metrics.gemm_kernel_symbol(4, 0, 3, 32) == "sm::ns_gemm_kernel<4, 0, 2, true>"
     # no 128-wide tiles in float64 or on a plan padded to 32
