@@ -38,6 +38,13 @@ for _k in list(MODES):
 DT_NAME = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "bf16x3"}
 
 
+def slab_of(sm, metrics, plan, info, m, o, pad_to):
+    """(loc, b, tile shift) of the refinement kernel, for the flop and byte
+    counts of last updates that computed only the atom's columns."""
+    v = int(o.variant) if int(o.variant) >= 0 else int(sm.sm_plan_tuning(plan)[int(o.refine)])
+    return info["loc"], m.block_size, metrics.tile_shift(int(o.refine), v, pad_to)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,7 +226,7 @@ def precision_form(a):
         sm.sm_profile_enable(plan, False)
         launches, ms = sm.sm_profile_read(plan)
         st = work.stats_host()
-        fl = metrics.flops_by_class(st, n, npad, o)
+        fl = metrics.flops_by_class(st, n, npad, o, slab_of(sm, metrics, plan, info, m, o, 64))
         useful = sum(v[0] for v in fl.values())
         P = work.P.cpu().numpy()
         dP = float(np.max(np.abs(P[mask] - Po[mask])))
@@ -333,7 +340,9 @@ def main():
             sm.sm_profile_enable(plan, False)
             launches, ms = sm.sm_profile_read(plan)
         st = work.stats_host()
-        fl = metrics.flops_by_class(st, n, npad, o)
+        pad_to = 32 if MODES[mode] in ("f64", "f32") else a.pad
+        slab = slab_of(sm, metrics, plan, info, m, o, pad_to)
+        fl = metrics.flops_by_class(st, n, npad, o, slab)
         useful = sum(v[0] for v in fl.values())
         P = work.P.cpu().numpy()
         # float64 commutator check of the final X at the accepted mu (untimed)
@@ -367,7 +376,7 @@ def main():
             per_launch = fu * metrics.MFMA_PRODUCTS[key[0]] * passes / nl
             variant = int(sm.sm_plan_tuning(plan)[key[0]])
             sym = metrics.gemm_kernel_symbol(key[0], key[1], variant, r["pad_to"])
-            bytes_launch = metrics.bytes_by_class(st, n, o).get(key, 0.0) * passes / nl
+            bytes_launch = metrics.bytes_by_class(st, n, o, slab, npad).get(key, 0.0) * passes / nl
             r["kernel"] = {"name": sym, "precision": DT_NAME[key[0]],
                            "product": "square" if key[1] == 0 else "update",
                            "launches": int(launches[cls]), "avg_ms": avg_ms,

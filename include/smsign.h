@@ -133,7 +133,10 @@ typedef struct {
   int32_t scale_src;   /* 0 Gershgorin, 1 power, 2 learned accepted, 3 learned rejected */
   double scale;        /* c used for X_0 = T / c */
   double res;          /* last ||X^2 - I||_F from the GEMM epilogue (float64 sum) */
-  double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v|| (-1 if off) */
+  double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v|| (-1 if off), X the
+                          last full iterate: a submatrix's final refinement update
+                          computes only the atom's own columns of X (the columns P
+                          takes), so for status 2 it is the X that update started from */
   double gersh;        /* Gershgorin bound c_G = max_p sum_q |T_pq| */
   double rho_est;      /* power-iteration estimate of rho(T) (<= rho), -1 if not run */
   double lb0;          /* l_0 used by scaled Newton-Schulz, relative to X_0 (0: none) */
@@ -143,7 +146,8 @@ typedef struct {
                           g(x) = x (3 - x^2) / 2 inverted on [0, 1] (rigorous up to the
                           rounding of r_k); -1 if none */
   double res_comm;     /* float64 commutator probe: max_v ||(X T - T X) v|| / (c ||v||) for
-                          fixed +-1 vectors v (X the final iterate, T = H[idx, idx] - mu I,
+                          fixed +-1 vectors v (X the last full iterate, as for res_probe,
+                          T = H[idx, idx] - mu I,
                           c the scale); it is the residual that sees an error in the
                           occupied subspace, which X^2 = I cannot.  -1 if not run */
   float feat[16];      /* features of the scaling network (see sm_mlp_create) */
@@ -232,7 +236,7 @@ int assemble_P(const sm_plan* plan, int32_t chunk, const void* ws, double* P_val
 
 /* Float64 commutator check of every submatrix of `chunk` after submatrix_sign:
  * stats[i].res_comm = max over opts->comm_probes (1..4) fixed +-1 vectors v of
- * ||X (T v) - T (X v)|| / (c_i ||v||), X the final iterate in the workspace,
+ * ||X (T v) - T (X v)|| / (c_i ||v||), X the last full iterate in the workspace,
  * T v formed straight from H's panels (H_vals and mu as given to
  * build_submatrices for this chunk).  sign(T) commutes with T (Eq. 13), so
  * this measures how far the converged X is from sign(T) in the direction the

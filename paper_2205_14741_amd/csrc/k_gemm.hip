@@ -144,7 +144,7 @@ __device__ __forceinline__ void stage_store(const RT (&r)[RN], LT* dst, LT* dst_
 template <int MODE, int WHICH>
 __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t shadow_off, int64_t nn,
                                            int npad, int rb, int cc, double alpha, double rscale,
-                                           double& part) {
+                                           double& part, bool tri = true) {
   constexpr bool PRE = Pre<MODE>::value;
   float o[4];
   uint16_t h[4], l[4];
@@ -169,7 +169,9 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
   uint16_t* sh = PRE ? reinterpret_cast<uint16_t*>(Out + shadow_off) : nullptr;
   const int64_t dcol = (int64_t)cc * npad + rb;     // (rb .. rb + 3, cc): contiguous
   const int64_t dcp = copy_idx<SPLIT>(cc, rb, npad);
-  if (rb >= cc) {
+  // tri: keep the lower triangle and write its mirror image; otherwise (a
+  // slab tile of a last refinement update) write all four as they are
+  if (!tri || rb >= cc) {
     if constexpr (PRE) {
       typedef uint32_t u2 __attribute__((ext_vector_type(2)));
       *reinterpret_cast<u2*>(sh + dcp) = u2{h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16)};
@@ -192,7 +194,7 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    if (rb + v > cc) {
+    if (tri && rb + v > cc) {
       if constexpr (PRE) {
         const int64_t m = copy_idx<SPLIT>(rb + v, cc, npad);
         sh[m] = h[v];
@@ -369,7 +371,8 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
     // operand rows load as zeros and the wave blocks there are skipped;
     // the block of a diagonal tile that lies wholly above the diagonal
     // computes nothing either
-    const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && !(bi == bj && wm < wn);
+    const bool slab = (rec.flags & kTileSlab) != 0;   // all blocks, no mirror
+    const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && (slab || !(bi == bj && wm < wn));
     const TileSrc<MODE> src = tile_src<MODE, WHICH, 64>(rec, mats, shadow_off, lrow, lpart);
 
     typename Tr::Acc acc[2][2];
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int rr = rb + kq + 4 * v;
-            if (rr < cc) continue;   // upper triangle: written by the mirror of (cc, rr)
+            if (!slab && rr < cc) continue;   // upper triangle: written by the mirror of (cc, rr)
             const double a = acc[x][y][v];
             double outv;
             if (WHICH == 0) {
@@ -545,7 +548,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
               outv = (0.5 * alpha) * a;
             }
             Out[(int64_t)cc * npad + rr] = outv;
-            if (rr != cc) Out[(int64_t)rr * npad + cc] = outv;
+            if (!slab && rr != cc) Out[(int64_t)rr * npad + cc] = outv;
           }
         }
     } else if constexpr (!Pre<MODE>::value) {
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
 #pragma unroll
         for (int y = 0; y < 2; ++y)
           store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, r0 + wm * 32 + x * 16 + 4 * kq,
-                                  c0 + wn * 32 + y * 16 + (lane & 15), alpha, rscale, part);
+                                  c0 + wn * 32 + y * 16 + (lane & 15), alpha, rscale, part, !slab);
     } else {
       // 16-bit copies: each wave stages its 32 x 32 result block in LDS,
       // then writes it, and its mirror image, as runs of 16 rows per lane
@@ -645,17 +648,25 @@ struct SubTiles {
   int64_t mo;
   float alpha, rscale;
   int npad, it, f, nt, po, t64;
+  int T, c0;      // slab: tile rows, first tile column
   int16_t flags;
 };
 
 __device__ __forceinline__ SubTiles sub_tiles(const DevPlan& p, int g, int L, int tshift, int iters, int phase,
-                                              double alpha_sq, double alpha_upd, double x0s_in) {
+                                              double alpha_sq, double alpha_upd, double x0s_in, bool slab) {
   const int which = L < 2 ? 1 : 0;
   SubTiles t;
   t.npad = p.npad_g[g];
   const int T = (t.npad + (1 << tshift) - 1) >> tshift;
   t.f = 1 << (tshift - 6);
   t.nt = T * (T + 1) / 2;
+  t.T = T;
+  t.c0 = 0;
+  if (slab) {
+    const int i = p.order_g[g];
+    t.nt = slab_tiles(t.npad, p.loc[i], p.bs[i], tshift);
+    t.c0 = p.loc[i] >> tshift;
+  }
   t.mo = p.mat_off_g[g];
   t.it = iters;
   // products that read X_0 (the square at it = 0, the update producing X_1)
@@ -667,6 +678,7 @@ __device__ __forceinline__ SubTiles sub_tiles(const DevPlan& p, int g, int L, in
   // list 0 also holds first refinement updates (phase 1): their result is
   // stored in float32 for the refinement steps that follow
   t.flags = (L == 0 && phase == 1) ? kTileStoreF32 : 0;
+  if (slab) t.flags |= kTileSlab;
   t.po = p.tile_off_g[g];
   t.t64 = tiles_of(t.npad);
   return t;
@@ -674,7 +686,12 @@ __device__ __forceinline__ SubTiles sub_tiles(const DevPlan& p, int g, int L, in
 
 __device__ __forceinline__ TileRec tile_rec(const SubTiles& t, int lt) {
   int bi, bj;
-  tile_coords(lt, bi, bj);
+  if (t.flags & kTileSlab) {   // tile column by tile column, all tile rows
+    bi = lt % t.T;
+    bj = t.c0 + lt / t.T;
+  } else {
+    tile_coords(lt, bi, bj);
+  }
   const int b64i = bi * t.f, b64j = bj * t.f;
   TileRec r;
   r.mat_off = t.mo;
@@ -710,7 +727,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int first = Lb[2 + max_subs + a];
   const SubState& s = st[l];
   const SubTiles t = sub_tiles(p, g0 + l, L, (L & 1) ? tshift_ref : tshift_main, s.iters, s.phase, s.alpha_sq,
-                               s.alpha_upd, s.x0s);
+                               s.alpha_upd, s.x0s, L == 1 && s.last_slab);
   for (int lt = threadIdx.x; lt < t.nt; lt += blockDim.x) out[first + lt] = tile_rec(t, lt);
 }
 
@@ -818,7 +835,8 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
     S* Out = base + (WHICH == 0 ? 2 * nn : (int64_t)(rec.it & 1) * nn);
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
     const int r0 = bi * 128, c0 = bj * 128;
-    const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && !(bi == bj && wm < wn);
+    const bool slab = (rec.flags & kTileSlab) != 0;   // all blocks, no mirror
+    const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && (slab || !(bi == bj && wm < wn));
     const TileSrc<MODE> src = tile_src<MODE, WHICH, 128>(rec, mats, shadow_off, lrow, lpart);
     const int nst = npad / K;
     const int kq = lane >> 4;
@@ -936,7 +954,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
       for (int y = 0; y < 4; ++y) {
         const int rb = r0 + wm * 64 + x * 16 + 4 * kq, cc = c0 + wn * 64 + y * 16 + rl;
         if (f32out) store_quad<SM_F32, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part);
-        else store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part);
+        else store_quad<MODE, WHICH>(acc[x][y], Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part, !slab);
       }
     if (WHICH == 0) {
       part = wave_sum(part);
@@ -1219,6 +1237,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         s.alpha_sq = (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : 1.0;
         s.alpha_upd = 1.0;
         s.lb_est = -1.0;
+        s.last_slab = 0;
         s.x0s = x0s ? x0s[l] : 1.0;
         dec = DEC_SQ;
       } else if (s.active) {
@@ -1274,6 +1293,18 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
           } else {
             s.status = 2;
             s.active = 0;
+            // the last update needs only the atom's own columns of X (the
+            // columns P takes), unless it is the first refinement update,
+            // which the main-precision kernel runs in full; taken only where
+            // the slab has fewer tiles than the triangle (which also keeps
+            // every submatrix within its share of the tile lists)
+            const bool first = o.copies_main && o.refine_steps == 1;
+            const int i = p.order_g[g0 + l];
+            const int nslab = slab_tiles(np, p.loc[i], p.bs[i], tshift_ref);
+            if (!first && nslab < ntr) {
+              s.last_slab = 1;
+              ntr = nslab;
+            }
           }
         }
         if (dec & DEC_UPD) {

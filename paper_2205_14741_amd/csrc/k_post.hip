@@ -16,6 +16,14 @@ __device__ __forceinline__ const T* final_x(const DevPlan& p, int g, const T* ma
   return mats + p.mat_off_g[g] + (int64_t)(st[l].iters & 1) * np * np;
 }
 
+// The last full iterate: the final X, or, where the last refinement update
+// computed only the atom's own columns, the X it was computed from.
+template <typename T>
+__device__ __forceinline__ const T* full_x(const DevPlan& p, int g, const T* mats, const SubState* st, int l) {
+  const int64_t np = p.npad_g[g];
+  return mats + p.mat_off_g[g] + (int64_t)((st[l].iters - st[l].last_slab) & 1) * np * np;
+}
+
 // One workgroup per submatrix whose final X is not yet in float32 form in its
 // buffer: the iteration ended in a low-precision main phase (no refinement
 // step ran, status != 2), so X exists only as the 16-bit operand copies (hi +
@@ -76,7 +84,7 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
   const int i = p.order_g[g];
   const int npad = p.npad_g[g];
   const int n = p.height[i];
-  const T* X = final_x(p, g, mats, st, l);
+  const T* X = full_x(p, g, mats, st, l);
   double worst = -1.0;
   if constexpr (P > 0) {
     double* v = vec_lds ? fvec : vecs + p.vec_off_g[g];   // [P][npad]
@@ -185,7 +193,7 @@ __device__ __forceinline__ void t_matvec(const DevPlan& p, const double* __restr
 }
 
 // One workgroup per submatrix: the commutator probe ||X (T v) - T (X v)|| /
-// (c ||v||) for P fixed +-1 vectors (float64), X the final iterate.
+// (c ||v||) for P fixed +-1 vectors (float64), X the last full iterate.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void comm_probe_kernel(DevPlan p, int g0, const double* __restrict__ H,
                                                          double mu, const T* __restrict__ mats,
@@ -209,7 +217,7 @@ __global__ __launch_bounds__(256) void comm_probe_kernel(DevPlan p, int g0, cons
     s_atom[t] = p.row_idx[k0 + t];
     s_off[t] = p.blk_rowoff[k0 + t];
   }
-  const T* X = final_x(p, g, mats, st, l);
+  const T* X = full_x(p, g, mats, st, l);
   double* v = vecs + p.vec_off_g[g];   // [P][npad] probes
   double* a = v + P * npad;            // X v
   double* b = a + P * npad;            // T v

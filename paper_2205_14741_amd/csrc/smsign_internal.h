@@ -39,6 +39,9 @@ struct SubState {
   int32_t iters_low;   // updates in the main phase
   int32_t refine_left; // refinement updates still to apply
   int32_t status;
+  int32_t last_slab;   // 1: the last update (a refinement update) computed only the tile
+                       // column(s) holding the atom's own columns; the last full X is the
+                       // other buffer
   double res;          // last residual
   double res_prev;     // residual before that
   double res_new;      // residual of the square just computed (residual_kernel)
@@ -73,6 +76,17 @@ struct TileRec {
 // the float32 product to float32 rounding): its result is stored in float32,
 // for the refinement steps that follow, instead of as copies.
 constexpr int16_t kTileStoreF32 = 2;
+// Last refinement update of a submatrix: only the tiles of the tile column(s)
+// that hold the atom's own b_i columns (the columns P needs), all four wave
+// blocks of each, stored as they are (no mirror image).
+constexpr int16_t kTileSlab = 4;
+
+// Tiles of that last update: all tile rows of the tile columns that
+// columns loc .. loc + b - 1 fall into (tiles of edge 1 << tshift).
+__host__ __device__ inline int slab_tiles(int npad, int loc, int b, int tshift) {
+  const int T = (npad + (1 << tshift) - 1) >> tshift;
+  return T * (((loc + b - 1) >> tshift) - (loc >> tshift) + 1);
+}
 
 // Workspace layout (bytes) for one chunk, given the storage element size.
 struct WsLayout {

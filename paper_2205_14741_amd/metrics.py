@@ -14,6 +14,15 @@ With a refinement phase of r steps (status 2) the counts are
 and without one (status 0 / 1): squares = iters + 1, updates = iters.  The
 (+ 1 / - 1): after a 16-bit main phase the first refinement update multiplies
 the main phase's operand copies and runs on the main-precision kernel.
+
+The last refinement update of a status-2 submatrix computes only the tile
+columns that hold the atom's own b columns (the ones P takes), all tile rows
+and no mirror, where that slab has fewer tiles than the triangle and the
+update is not the one that runs on the main-precision kernel:
+
+    useful flops of a slab update = 2 n^2 b            (n b entries x 2n)
+    issued MFMA flops             = (n_pad / 32) * (32-wide columns of the slab
+                                    tiles inside n_pad) * 2 * 32 * 32 * np
 """
 from __future__ import annotations
 
@@ -45,16 +54,71 @@ def product_counts(stats: np.ndarray, opts) -> dict:
     return out
 
 
-def flops_by_class(stats: np.ndarray, n: np.ndarray, npad: np.ndarray, opts):
-    """{(precision, kind): (useful flops, issued MFMA flops)} of one pass."""
-    n = n.astype(np.float64)
-    useful_one = n * n * (n + 1.0)
+def effective_variant(mode: int, variant: int, pad_to: int) -> int:
+    """The GEMM kernel variant the launcher runs for a precision: no 128-wide
+    tiles in float64 or on a plan padded to 32, and 16-bit products on a plan
+    padded to 32 take the half-depth-stage kernel."""
+    v = variant
+    if v >= 3 and (mode == 0 or pad_to < 64):
+        v = 1
+    if mode >= 2 and pad_to < 64:
+        v = 2
+    return v
+
+
+def tile_shift(mode: int, variant: int, pad_to: int) -> int:
+    """log2 of the output tile width of that kernel (64 or 128)."""
+    return 7 if effective_variant(mode, variant, pad_to) >= 3 and mode != 0 else 6
+
+
+def slab_tiles(npad, loc, b, tshift):
+    """Tiles of a last-update slab: every tile row times the tile columns
+    that hold columns loc .. loc + b - 1."""
+    npad, loc, b = (np.asarray(x, dtype=np.int64) for x in (npad, loc, b))
+    T = (npad + (1 << tshift) - 1) >> tshift
+    return T * (((loc + b - 1) >> tshift) - (loc >> tshift) + 1)
+
+
+def slab_mask(stats: np.ndarray, npad, loc, b, opts, tshift_ref: int) -> np.ndarray:
+    """Submatrices whose last refinement update ran as a column slab (the
+    scheduler's rule: status 2, not the update that runs on the main-precision
+    kernel, fewer slab tiles than triangle tiles)."""
+    npad = np.asarray(npad, dtype=np.int64)
+    first_on_main = int(opts.phase1) >= 2 and int(opts.refine_steps) == 1
+    T = (npad + (1 << tshift_ref) - 1) >> tshift_ref
+    fewer = slab_tiles(npad, loc, b, tshift_ref) < T * (T + 1) // 2
+    return (stats["status"] == 2) & fewer & (not first_on_main) & (int(opts.refine_steps) > 0)
+
+
+def slab_columns32(npad, loc, b, tshift):
+    """32-wide block columns inside n_pad covered by the slab tiles."""
+    npad, loc, b = (np.asarray(x, dtype=np.int64) for x in (npad, loc, b))
+    c0 = (loc >> tshift) << tshift
+    c1 = np.minimum((((loc + b - 1) >> tshift) + 1) << tshift, npad)
+    return (c1 - c0) // 32
+
+
+def flops_by_class(stats: np.ndarray, n: np.ndarray, npad: np.ndarray, opts, slab=None):
+    """{(precision, kind): (useful flops, issued MFMA flops)} of one pass.
+    slab: (loc, b, tshift_ref) of the plan, to count last updates that ran as
+    column slabs at their own cost (None: every update counted in full)."""
+    nf = n.astype(np.float64)
+    useful_one = nf * nf * (nf + 1.0)
     issued_one = wave_blocks(npad) * 2.0 * 32 * 32 * npad.astype(np.float64)
     res = {}
     for key, cnt in product_counts(stats, opts).items():
         cnt = np.asarray(cnt, dtype=np.float64)
-        res[key] = (float((cnt * useful_one).sum()), float((cnt * issued_one).sum()))
-    return res
+        res[key] = [float((cnt * useful_one).sum()), float((cnt * issued_one).sum())]
+    if slab is not None and int(opts.refine_steps) > 0:
+        loc, b, tsh = slab
+        msk = slab_mask(stats, npad, loc, b, opts, tsh)
+        key = (int(opts.refine), 1)
+        useful_slab = 2.0 * nf * nf * np.asarray(b, dtype=np.float64)
+        issued_slab = ((npad // 32).astype(np.float64) * slab_columns32(npad, loc, b, tsh)
+                       * 2.0 * 32 * 32 * npad.astype(np.float64))
+        res[key][0] += float(((useful_slab - useful_one) * msk).sum())
+        res[key][1] += float(((issued_slab - issued_one) * msk).sum())
+    return {k: tuple(v) for k, v in res.items()}
 
 
 def wave_blocks(npad: np.ndarray) -> np.ndarray:
@@ -66,8 +130,8 @@ def wave_blocks(npad: np.ndarray) -> np.ndarray:
     return (nb * (nb + 1) // 2).astype(np.float64)
 
 
-def useful_flops(stats, n, npad, opts) -> float:
-    return sum(v[0] for v in flops_by_class(stats, n, npad, opts).values())
+def useful_flops(stats, n, npad, opts, slab=None) -> float:
+    return sum(v[0] for v in flops_by_class(stats, n, npad, opts, slab).values())
 
 
 # Matrix-core products one product of the schedule costs: the split-bfloat16
@@ -79,11 +143,7 @@ def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
     """Demangled name prefix (as profilers print it) of the GEMM kernel that
     runs for (precision, square/update, kernel variant) on a plan with the
     given padding; mirrors the variant fallback of the launcher."""
-    v = variant
-    if v >= 3 and (mode == 0 or pad_to < 64):
-        v = 1
-    if mode >= 2 and pad_to < 64:   # 16-bit products on a plan padded to 32
-        v = 2
+    v = effective_variant(mode, variant, pad_to)
     if v >= 3:   # 128-wide tiles: <precision, kind, XCD-aware walk, prefetch depth>
         return f"sm::ns_gemm128_kernel<{mode}, {which}, {'false' if v == 4 else 'true'}, {6 if v == 5 else 1}>"
     kdiv = 2 if v == 2 else 1   # variant 2: half-depth LDS stages
@@ -96,13 +156,23 @@ STORE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 4}
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 
-def bytes_by_class(stats: np.ndarray, n: np.ndarray, opts) -> dict:
+def bytes_by_class(stats: np.ndarray, n: np.ndarray, opts, slab=None, npad=None) -> dict:
     """{(precision, kind): algorithmic memory bytes of one pass}: a square
     reads X and writes Y, an update reads X and Y and writes X', each an
-    n x n matrix in the storage of that precision's products."""
-    n2 = n.astype(np.float64) ** 2
+    n x n matrix in the storage of that precision's products; a slab update
+    (slab = (loc, b, tshift_ref), with npad) reads one whole operand and b
+    rows of the other and writes b rows."""
+    nf = n.astype(np.float64)
+    n2 = nf ** 2
     res = {}
     for (prec, kind), cnt in product_counts(stats, opts).items():
         per = (2.0 if kind == 0 else 3.0) * STORE_BYTES[prec] * n2
         res[(prec, kind)] = float((np.asarray(cnt, dtype=np.float64) * per).sum())
+    if slab is not None and int(opts.refine_steps) > 0:
+        loc, b, tsh = slab
+        msk = slab_mask(stats, npad, loc, b, opts, tsh)
+        prec = int(opts.refine)
+        bf = np.asarray(b, dtype=np.float64)
+        diff = STORE_BYTES[prec] * ((n2 + 2.0 * nf * bf) - 3.0 * n2)
+        res[(prec, 1)] += float((diff * msk).sum())
     return res

@@ -382,3 +382,38 @@ def test_gemm_variants_parity(variant, prec, dp_max, dev):
     dP, dE, dNe = _compare(m, P, E, Ne, mu)
     assert dP < dp_max, (variant, prec, dP)
     assert np.all(st["status"] >= 1)
+
+
+@pytest.mark.parametrize("prec,variant,kw,dp_max", [
+    ("bf16x3", 1, {}, 1e-4),                                     # float32 slab, 64-wide tiles
+    ("bf16x3", 5, {}, 1e-4),                                     # float32 slab, 128-wide tiles
+    ("bf16x3", 5, {"refine_steps": 3}, 1e-4),
+    ("f64", 1, {"refine_steps": 4, "switch_tol": 0.1}, 1e-9),   # float64 slab
+])
+def test_last_update_column_slab(prec, variant, kw, dp_max, dev):
+    """The last refinement update computes only the tile columns holding the
+    atom's own columns (the part of X that P takes): P still matches the
+    oracle, and the slab was taken for most submatrices."""
+    from paper_2205_14741_amd import metrics
+    m = synth.water_system(40, 1.4, 11)
+    mu = gap_mu(m)
+    o = sm.default_opts(prec, variant=variant, probes=2, **kw)
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=64, opts=o)
+    info = plan.info()
+    tsh = metrics.tile_shift(int(o.refine), variant, 64)
+    slab = metrics.slab_mask(st, info["npad"], info["loc"], m.block_size, o, tsh)
+    assert slab.mean() > 0.5, slab.mean()
+    dP, dE, dNe = _compare(m, P, E, Ne, mu)
+    assert dP < dp_max, (prec, variant, dP)
+    assert np.all(st["status"] == 2)
+    # the probes read the last full iterate, one plain Newton-Schulz step
+    # before the final X: for the float64 schedule, refine_steps - 1 steps
+    # past the switch at residual 0.1, where a plain step maps an eigenvalue
+    # error e = x^2 - 1 to -(3/4) e^2 - (1/4) e^3
+    bound = 1e-3
+    if prec == "f64":
+        e = 0.1
+        for _ in range(o.refine_steps - 1):
+            e = 0.75 * e * e + 0.25 * e ** 3
+        bound = e + 1e-12
+    assert 0.0 <= st["res_probe"].max() < bound, (st["res_probe"].max(), bound)

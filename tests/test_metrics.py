@@ -65,3 +65,52 @@ def test_kernel_symbols_follow_launcher_fallback():
     assert metrics.gemm_kernel_symbol(0, 0, 3, 64) == "sm::ns_gemm_kernel<0, 0, 1, true>"
     assert metrics.gemm_kernel_symbol(1, 0, 3, 32) == "sm::ns_gemm_kernel<1, 0, 1, true>"
     assert metrics.gemm_kernel_symbol(0, 1, 0, 32) == "sm::ns_gemm_kernel<0, 1, 1, false>"
+
+
+def _brute_slab(npad, loc, b, tsh):
+    w = 1 << tsh
+    T = (npad + w - 1) // w
+    cols = {c // w for c in range(loc, loc + b)}
+    return sum(1 for bi in range(T) for bj in range(T) if bj in cols)
+
+
+def test_slab_tiles_brute_force():
+    for npad in (64, 128, 192, 320, 576):
+        for tsh in (6, 7):
+            for loc in range(0, npad - 6, 13):
+                for b in (1, 2, 6):
+                    assert int(metrics.slab_tiles(npad, loc, b, tsh)) == _brute_slab(npad, loc, b, tsh)
+
+
+def test_slab_accounting():
+    # one refined submatrix, n = 200 padded to 256, the atom's 6 columns at
+    # 61 .. 66 (two 64-wide tile columns: 8 slab tiles < 10 triangle tiles)
+    n, npad, loc, b = np.array([200]), np.array([256]), np.array([61]), np.array([6])
+    st = _stats([12], [10], [2])
+    o = sm.default_opts("bf16x3")                   # 2 refinement steps
+    assert metrics.slab_mask(st, npad, loc, b, o, 6).all()
+    fl = metrics.flops_by_class(st, n, npad, o, (loc, b, 6))
+    full = metrics.flops_by_class(st, n, npad, o)
+    # the one float32 update (the second refinement update) is the slab
+    assert fl[(sm.SM_F32, 1)][0] == 2.0 * 200 * 200 * 6
+    # issued: 8 row blocks x 4 column blocks (two 64-wide tile columns)
+    assert fl[(sm.SM_F32, 1)][1] == 8 * 4 * 2 * 32 * 32 * 256
+    assert fl[(sm.SM_BF16X3, 1)] == full[(sm.SM_BF16X3, 1)]
+    by = metrics.bytes_by_class(st, n, o, (loc, b, 6), npad)
+    assert by[(sm.SM_F32, 1)] == 4 * (200 * 200 + 2 * 200 * 6)
+    # a single refinement step runs on the main kernel in full: no slab
+    o1 = sm.default_opts("bf16x3", refine_steps=1)
+    assert not metrics.slab_mask(st, npad, loc, b, o1, 6).any()
+    # 128-wide tiles: 2 tile rows x 1 tile column = 2 tiles < 3 triangle tiles
+    assert metrics.slab_mask(st, npad, loc, b, o, 7).all()
+    fl7 = metrics.flops_by_class(st, n, npad, o, (loc, b, 7))
+    assert fl7[(sm.SM_F32, 1)][1] == 8 * 4 * 2 * 32 * 32 * 256
+    # not converged (status 1): no refinement ran, nothing changes
+    st1 = _stats([12], [12], [1])
+    assert metrics.flops_by_class(st1, n, npad, o, (loc, b, 6)) == metrics.flops_by_class(st1, n, npad, o)
+    # a slab with no fewer tiles than the triangle is not taken (npad 64)
+    assert not metrics.slab_mask(st, np.array([64]), np.array([10]), b, o, 6).any()
+    # float64 refined in float64: the last of the float64 updates is the slab
+    o64 = sm.default_opts("f64", refine_steps=2, switch_tol=0.1)
+    f64 = metrics.flops_by_class(st, n, npad, o64, (loc, b, 6))
+    assert f64[(sm.SM_F64, 1)][0] == 11 * 200 * 200 * 201 + 2.0 * 200 * 200 * 6
