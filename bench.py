@@ -45,7 +45,7 @@ def slab_of(sm, metrics, plan, info, m, o, pad_to):
     return info["loc"], m.block_size, metrics.tile_shift(int(o.refine), v, pad_to)
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--copy-calibrate", type=float, default=0.0, metavar="MIB",
                     help="first run a plain copy kernel (negation of a float32 buffer of MIB MiB), "
                          "the reference for scaling memory-traffic counters")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def mode_opts(sm, mode, a):

@@ -1,0 +1,96 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark
+times (its own defaults, schedule, scaling network and autotuned kernel):
+
+* the 1000-atom lattice (967 submatrices, n 192-276, padded to 32), split
+  bf16 + 2 float32 refinement steps with learned scaling and mu by bisection,
+  against the oracle on every submatrix: relative energy error <= 1e-5 and
+  max |dP| <= 1e-4 (the target accuracy of the low-precision schedules), and
+  the plain float64 path within 1e-9;
+* the 1000-molecule water-like system (3000 submatrices, n ~ 2300-2900,
+  several workspace chunks), the same schedule, on sampled submatrices: their
+  P columns and their share of tr(PH).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import submatrix as om
+from paper_2205_14741_amd import smsign as sm
+from gpu_helpers import rel, h_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _bench():
+    import bench
+    return bench, bench.parse([])
+
+
+def test_lattice1000_bench_configuration(dev):
+    bench, a = _bench()
+    m = synth.config2(a.seed)
+    assert m.n_atoms == 967
+    H = h_dev(m)
+    net, _ = bench.train_scaling_net(sm, synth, dev, a.seed + 1)
+    budget = int(a.chunk_mb * 2 ** 20 / 4)
+    res = {}
+    for mode in ("f64", "bf16x3+L"):
+        o = bench.mode_opts(sm, mode, a)
+        plan = sm.Plan(m, 32 if bench.MODES[mode] in ("f64", "f32") else a.pad, budget)
+        sm.sm_plan_set_mlp(plan, net)
+        work = sm.Workspace(plan, sm.storage_prec(o), dev)
+        lo, hi = sm.sm_gershgorin_bracket(plan, H)
+        sm.sm_autotune(plan, 0, H, 0.5 * (lo + hi), o, work.ws, work.stats, repeats=1)
+        mu, k, _, E, Ne = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P, energy=True)
+        torch.cuda.synchronize()
+        res[mode] = (mu, E, Ne, work.P.cpu().numpy(), work.stats_host())
+        del work
+    for mode, (mu, E, Ne, P, st) in res.items():
+        Po = om.density_matrix(m, mu)
+        Eo, Neo = om.energy_trace(m, Po)
+        mask = ~np.isnan(Po)
+        assert mask.all()
+        dP = float(np.max(np.abs(P - Po)))
+        print(f"{mode}: mu {mu:.6f}, rel dE {rel(E, Eo):.2e}, max|dP| {dP:.2e}, |dNe| {abs(Ne - Neo):.2e}, "
+              f"iters {st['iters'].min()}-{st['iters'].max()}")
+        assert np.all(st["status"] >= 1)
+        if mode == "f64":
+            assert dP < 1e-9 and rel(E, Eo) < 1e-11 and abs(Ne - Neo) < 1e-8
+        else:
+            assert dP <= 1e-4 and rel(E, Eo) <= 1e-5 and abs(Ne - Neo) < 1e-3
+            assert np.mean(st["scale_src"] == 2) > 0.9     # learned scale accepted
+    print(f"mu f64 {res['f64'][0]:.6f}, bf16x3+L {res['bf16x3+L'][0]:.6f}")
+
+
+def test_water1000_bench_configuration_sampled(dev):
+    bench, a = _bench()
+    m = synth.config3(a.seed)
+    H = h_dev(m)
+    plan = sm.Plan(m, 64, int(a.chunk_gb * 2 ** 30 / 4))
+    assert m.n_atoms == 3000 and plan.n_chunks > 1
+    mu = -2.95          # the benchmark's mu, inside this family's gap
+    net, _ = bench.train_scaling_net_water(sm, synth, dev, a.seed + 1, mu)
+    sm.sm_plan_set_mlp(plan, net)
+    o = bench.mode_opts(sm, "bf16x3+L", a)
+    work = sm.Workspace(plan, sm.storage_prec(o), dev)
+    sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5))
+    E, Ne = sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
+    torch.cuda.synchronize()
+    P = work.P.cpu().numpy()
+    st = work.stats_host()
+    del work
+    torch.cuda.empty_cache()
+    atoms = [0, 1, 2, 1500, 2999]          # an oxygen and hydrogens, middle, last
+    Po = om.density_matrix(m, mu, atoms=atoms)
+    mask = ~np.isnan(Po)
+    sel = np.zeros_like(mask)
+    for i in atoms:
+        sel[m.panel_off[i]:m.panel_off[i + 1]] = True
+    assert np.array_equal(mask, sel)
+    dP = float(np.max(np.abs(P[mask] - Po[mask])))
+    dE = rel(float(np.sum(P[sel] * m.vals[sel])), float(np.sum(Po[sel] * m.vals[sel])))
+    print(f"water1000: max|dP| {dP:.2e}, rel dE (sampled) {dE:.2e}, iters {st['iters'].min()}-{st['iters'].max()}, "
+          f"learned accepted {np.mean(st['scale_src'] == 2):.3f}")
+    assert dP <= 1e-4 and dE <= 1e-5
+    assert np.all(st["status"] >= 1)
