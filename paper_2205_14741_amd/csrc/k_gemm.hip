@@ -282,6 +282,13 @@ __device__ __forceinline__ void tile_coords(int lt, int& bi, int& bj) {
 // all eight.
 constexpr int kXcds = 8;
 
+// Updates walk their share of the tile list backwards (t -> mirror - t over
+// [t_lo, t_end)): a square launch walks the submatrices forward, so the
+// update after it starts on the ones the square wrote last, the likeliest to
+// still sit in the memory-side cache, and the next square, forward again,
+// starts on the ones the update wrote last.  mirror < 0: forward.
+__device__ __forceinline__ int rec_index(int t, int mirror) { return mirror < 0 ? t : mirror - t; }
+
 // Workgroups of the 64-tile kernel that its LDS stages leave room for on a
 // compute unit (160 KiB), at most 4.  Each workgroup puts one wave on every
 // SIMD, so this is also the number of waves per SIMD the register budget is
@@ -337,20 +344,22 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   const int lpart = (tid & 3) * NL;      // k offset inside the stage
   const int total = count[0];
 
-  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x;
+  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x, t_lo = 0;
   if (XCD) {
     const int x = blockIdx.x % kXcds;
     t_step = ((int)gridDim.x - x + kXcds - 1) / kXcds;   // workgroups on XCD x
-    t_begin = (int)((int64_t)total * x / kXcds) + (int)blockIdx.x / kXcds;
+    t_lo = (int)((int64_t)total * x / kXcds);
+    t_begin = t_lo + (int)blockIdx.x / kXcds;
     t_end = (int)((int64_t)total * (x + 1) / kXcds);
   }
+  const int t_mirror = WHICH == 1 ? t_lo + t_end - 1 : -1;
   // Operand registers carry over from tile to tile: during the last stage of
   // a tile the first stage of the workgroup's next tile is loaded, so a tile
   // starts without waiting for memory.
   RT ra[RN], rb[RN];
   TileRec nxt;
   if (t_begin < t_end) {
-    nxt = recs[t_begin];
+    nxt = recs[rec_index(t_begin, t_mirror)];
     const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 64>(nxt, mats, shadow_off, lrow, lpart);
     s0.a.template load<K, NL>(ra, 0, s0.va);
     s0.b.template load<K, NL>(rb, 0, s0.vb);
@@ -358,7 +367,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
   for (int t = t_begin; t < t_end; t += t_step) {
     const TileRec rec = nxt;
     const bool has_next = t + t_step < t_end;
-    if (has_next) nxt = recs[t + t_step];   // the next tile's record, used at the last stage
+    if (has_next) nxt = recs[rec_index(t + t_step, t_mirror)];   // the next tile's record, used at the last stage
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
@@ -804,19 +813,21 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
   const int lrow = tid >> 1;             // 0..127
   const int lpart = (tid & 1) * NL;
   const int total = count[0];
-  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x;
+  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x, t_lo = 0;
   if (XCD) {
     const int x8 = blockIdx.x % kXcds;
     t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
-    t_begin = (int)((int64_t)total * x8 / kXcds) + (int)blockIdx.x / kXcds;
+    t_lo = (int)((int64_t)total * x8 / kXcds);
+    t_begin = t_lo + (int)blockIdx.x / kXcds;
     t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
   }
+  const int t_mirror = WHICH == 1 ? t_lo + t_end - 1 : -1;
   // DEPTH 1: operand registers carried from tile to tile (the next tile's
   // first stage is loaded during the last stage of the current one)
   RT rga[DEPTH][RN], rgb[DEPTH][RN];
   TileRec nxt;
   if (t_begin < t_end) {
-    nxt = recs[t_begin];
+    nxt = recs[rec_index(t_begin, t_mirror)];
     if constexpr (DEPTH == 1) {
       const TileSrc<MODE> s0 = tile_src<MODE, WHICH, 128>(nxt, mats, shadow_off, lrow, lpart);
       s0.a.template load<K, NL>(rga[0], 0, s0.va);
@@ -826,7 +837,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
   for (int t = t_begin; t < t_end; t += t_step) {
     const TileRec rec = nxt;
     const bool has_next = t + t_step < t_end;
-    if (has_next) nxt = recs[t + t_step];
+    if (has_next) nxt = recs[rec_index(t + t_step, t_mirror)];
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
