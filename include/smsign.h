@@ -132,7 +132,10 @@ typedef struct {
   int32_t status;      /* 1 converged, 0 hit max_iter, 2 refinement done, -1 diverged */
   int32_t scale_src;   /* 0 Gershgorin, 1 power, 2 learned accepted, 3 learned rejected */
   double scale;        /* c used for X_0 = T / c */
-  double res;          /* last ||X^2 - I||_F from the GEMM epilogue (float64 sum) */
+  double res;          /* ||X^2 - I||_F of the last full square, from the GEMM epilogue
+                          (float64 sum); with two or more refinement steps the last
+                          square computes only the atom's tile columns of Y (all the
+                          last update reads) and its partial sum only flags divergence */
   double res_probe;    /* float64 probe: max_v ||X (X v) - v|| / ||v|| (-1 if off), X the
                           last full iterate: a submatrix's final refinement update
                           computes only the atom's own columns of X (the columns P

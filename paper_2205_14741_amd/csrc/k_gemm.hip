@@ -155,7 +155,8 @@ __device__ __forceinline__ void store_quad(const f4& a4, float* Out, int64_t sha
     if (WHICH == 0) {
       const double dg = (rr == cc) ? 1.0 : 0.0;
       const double e = a * rscale - dg;
-      if (rr >= cc) part += (rr == cc) ? e * e : 2.0 * e * e;
+      if (!tri) part += e * e;   // slab: every entry once
+      else if (rr >= cc) part += (rr == cc) ? e * e : 2.0 * e * e;
       o[v] = (float)(3.0 * dg - (alpha * alpha) * a);
     } else {
       o[v] = (float)((0.5 * alpha) * a);
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
             if (WHICH == 0) {
               const double dg = (rr == cc) ? 1.0 : 0.0;
               const double e = a * rscale - dg;
-              part += (rr == cc) ? e * e : 2.0 * e * e;
+              part += (slab || rr == cc) ? e * e : 2.0 * e * e;
               outv = 3.0 * dg - (alpha * alpha) * a;
             } else {
               outv = (0.5 * alpha) * a;
@@ -709,7 +710,8 @@ __device__ __forceinline__ TileRec tile_rec(const SubTiles& t, int lt) {
   r.bibj = (bi << 16) | bj;
   r.npad = t.npad;
   r.it = t.it;
-  r.part_idx = t.po + b64i * (b64i + 1) / 2 + b64j;
+  // a slab square's tiles (fewer than the triangle's) take slots 0, 1, ...
+  r.part_idx = (t.flags & kTileSlab) ? t.po + lt : t.po + b64i * (b64i + 1) / 2 + b64j;
   r.tiles64 = (int16_t)t.t64;
   r.flags = t.flags;
   return r;
@@ -736,7 +738,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevPlan p, int g0, const Su
   const int first = Lb[2 + max_subs + a];
   const SubState& s = st[l];
   const SubTiles t = sub_tiles(p, g0 + l, L, (L & 1) ? tshift_ref : tshift_main, s.iters, s.phase, s.alpha_sq,
-                               s.alpha_upd, s.x0s, L == 1 && s.last_slab);
+                               s.alpha_upd, s.x0s, (L == 1 && s.last_slab) || (L == 3 && s.sq_slab));
   for (int lt = threadIdx.x; lt < t.nt; lt += blockDim.x) out[first + lt] = tile_rec(t, lt);
 }
 
@@ -973,13 +975,14 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
       __syncthreads();
       if (tid == 0) {
         partials[rec.part_idx] = ((red[0] + red[1]) + red[2]) + red[3];
-        // other 64-tile slots covered by this tile (lower triangle, inside n_pad)
+        // other 64-tile slots covered by this tile (lower triangle, inside
+        // n_pad); a slab tile has a slot of its own
         const int b0i = 2 * bi, b0j = 2 * bj;
         const int s0 = b0i * (b0i + 1) / 2 + b0j;
 #pragma unroll
         for (int q = 1; q < 4; ++q) {
           const int ti = b0i + (q >> 1), tj = b0j + (q & 1);
-          if (ti < rec.tiles64 && tj < rec.tiles64 && ti >= tj)
+          if (!slab && ti < rec.tiles64 && tj < rec.tiles64 && ti >= tj)
             partials[rec.part_idx + (ti * (ti + 1) / 2 + tj - s0)] = 0.0;
         }
       }
@@ -1183,13 +1186,15 @@ __device__ void block_excl_scan(const int (&v)[K], int (&ex)[K], int (&total)[K]
 // A wavefront per submatrix: the residual ||X^2 - I||_F of the square just
 // computed, from its per-tile partial sums added in tile order.
 __global__ __launch_bounds__(256) void residual_kernel(DevPlan p, int g0, int nsub, SubState* st,
-                                                       const double* __restrict__ partials) {
+                                                       const double* __restrict__ partials, int tshift_ref) {
   const int lane = threadIdx.x & 63;
   const int l = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (l >= nsub || !st[l].active) return;
   const int g = g0 + l;
   const int T = tiles_of(p.npad_g[g]);
-  const int nt = T * (T + 1) / 2;
+  const int i = p.order_g[g];
+  // a slab square wrote one slot per slab tile
+  const int nt = st[l].sq_slab ? slab_tiles(p.npad_g[g], p.loc[i], p.bs[i], tshift_ref) : T * (T + 1) / 2;
   const double* pp = partials + p.tile_off_g[g];
   double r = 0.0;
   for (int k = lane; k < nt; k += 64) r += pp[k];
@@ -1217,13 +1222,16 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
   for (int base = 0; base < nsub; base += blockDim.x) {
     const int l = base + threadIdx.x;
-    int dec = 0, ntm = 0, ntr = 0, refine_left = -1;
+    int dec = 0, ntm = 0, ntr = 0, ntr_sq = 0, refine_left = -1;
     if (l < nsub) {
       SubState s = st[l];
       const int np = p.npad_g[g0 + l];
+      const int i = p.order_g[g0 + l];
+      // tiles of a column slab of the refinement kernel (last square / update)
+      const int nslab = slab_tiles(np, p.loc[i], p.bs[i], tshift_ref);
       if (!first && fuse_res && s.active) {
         const int T64 = tiles_of(np);
-        const int nt = T64 * (T64 + 1) / 2;
+        const int nt = s.sq_slab ? nslab : T64 * (T64 + 1) / 2;
         const double* pp = partials + p.tile_off_g[g0 + l];
         double r = 0.0;
 #pragma unroll 8
@@ -1234,6 +1242,12 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       const int Tr = (np + (1 << tshift_ref) - 1) >> tshift_ref;
       ntm = Tm * (Tm + 1) / 2;
       ntr = Tr * (Tr + 1) / 2;
+      ntr_sq = ntr;
+      // the last update and the square before it compute only the slab,
+      // where it has fewer tiles than the triangle; not for the first
+      // refinement update (it runs in full on the main-precision kernel) nor
+      // for the square that decides the switch (a main-phase square)
+      const bool slab_ok = nslab < ntr && !(o.copies_main && o.refine_steps == 1);
       if (first) {
         s.active = 1;
         s.phase = 0;
@@ -1249,50 +1263,62 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         s.alpha_upd = 1.0;
         s.lb_est = -1.0;
         s.last_slab = 0;
+        s.sq_slab = 0;
         s.x0s = x0s ? x0s[l] : 1.0;
         dec = DEC_SQ;
       } else if (s.active) {
         const double r = s.res_new;
-        s.res_prev = s.res;
-        s.res = r;
-        const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
-        // r < 1 bounds every eigenvalue x of the current X: |x^2 - 1| <= r
         double lb = s.lb, top = s.top;
-        if (r < 1.0) {
-          lb = fmax(lb, sqrt(1.0 - r));
-          top = fmin(top, sqrt(1.0 + r));
-          // plain run: carry the bound back to X_0.  Only residuals >= 0.01:
-          // near convergence the inverse map is steep at 1, and the rounding
-          // of a tiny residual would be amplified into the bound.
-          if (!o.accel && r >= 0.01) {
-            double x = sqrt(1.0 - r);
-            for (int j = 0; j < s.iters; ++j) x = ns_map_inv(x);
-            s.lb_est = fmax(s.lb_est, x);
+        if (s.sq_slab) {
+          // a slab square (refinement, the last update next): its columns'
+          // residual only flags a diverged iteration; res keeps the last
+          // full one
+          s.sq_slab = 0;
+          if (!(r < 1e300)) {
+            s.status = -1;
+            s.active = 0;
           }
-        }
-        if (!(r < 1e300)) {
-          s.status = -1;
-          s.active = 0;
-        } else if (s.phase == 0) {
-          if (o.refine_steps == 0) {
-            if (r < o.tol || stalled) {
-              s.status = 1;
-              s.active = 0;
-            } else if (s.iters >= o.max_iter) {
-              s.status = 0;
-              s.active = 0;
+        } else {
+          s.res_prev = s.res;
+          s.res = r;
+          const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
+          // r < 1 bounds every eigenvalue x of the current X: |x^2 - 1| <= r
+          if (r < 1.0) {
+            lb = fmax(lb, sqrt(1.0 - r));
+            top = fmin(top, sqrt(1.0 + r));
+            // plain run: carry the bound back to X_0.  Only residuals >= 0.01:
+            // near convergence the inverse map is steep at 1, and the rounding
+            // of a tiny residual would be amplified into the bound.
+            if (!o.accel && r >= 0.01) {
+              double x = sqrt(1.0 - r);
+              for (int j = 0; j < s.iters; ++j) x = ns_map_inv(x);
+              s.lb_est = fmax(s.lb_est, x);
+            }
+          }
+          if (!(r < 1e300)) {
+            s.status = -1;
+            s.active = 0;
+          } else if (s.phase == 0) {
+            if (o.refine_steps == 0) {
+              if (r < o.tol || stalled) {
+                s.status = 1;
+                s.active = 0;
+              } else if (s.iters >= o.max_iter) {
+                s.status = 0;
+                s.active = 0;
+              } else {
+                dec = DEC_UPD | DEC_SQ;
+                s.iters++;
+                s.iters_low++;
+              }
+            } else if (r < o.switch_tol || stalled || s.iters >= o.max_iter) {
+              s.phase = 1;
+              s.refine_left = o.refine_steps;
             } else {
               dec = DEC_UPD | DEC_SQ;
               s.iters++;
               s.iters_low++;
             }
-          } else if (r < o.switch_tol || stalled || s.iters >= o.max_iter) {
-            s.phase = 1;
-            s.refine_left = o.refine_steps;
-          } else {
-            dec = DEC_UPD | DEC_SQ;
-            s.iters++;
-            s.iters_low++;
           }
         }
         if (s.active && s.phase == 1 && dec == 0) {
@@ -1301,18 +1327,20 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
           s.refine_left--;
           if (s.refine_left > 0) {
             dec |= DEC_SQ;
+            // the square before the last update: the last update reads only
+            // the slab columns of its Y
+            if (s.refine_left == 1 && slab_ok) {
+              s.sq_slab = 1;
+              ntr_sq = nslab;
+            }
           } else {
             s.status = 2;
             s.active = 0;
             // the last update needs only the atom's own columns of X (the
-            // columns P takes), unless it is the first refinement update,
-            // which the main-precision kernel runs in full; taken only where
-            // the slab has fewer tiles than the triangle (which also keeps
-            // every submatrix within its share of the tile lists)
-            const bool first = o.copies_main && o.refine_steps == 1;
-            const int i = p.order_g[g0 + l];
-            const int nslab = slab_tiles(np, p.loc[i], p.bs[i], tshift_ref);
-            if (!first && nslab < ntr) {
+            // columns P takes); taken only where the slab has fewer tiles
+            // than the triangle (which also keeps every submatrix within its
+            // share of the tile lists)
+            if (slab_ok) {
               s.last_slab = 1;
               ntr = nslab;
             }
@@ -1346,7 +1374,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
             : (L == 2) ? ((dec & DEC_SQ) && !(dec & DEC_REF))
                        : ((dec & DEC_SQ) && (dec & DEC_REF));
       cnt[2 * L] = in[L] ? 1 : 0;
-      cnt[2 * L + 1] = in[L] ? ((L & 1) ? ntr : ntm) : 0;
+      cnt[2 * L + 1] = in[L] ? (L == 1 ? ntr : L == 3 ? ntr_sq : ntm) : 0;
     }
     block_excl_scan<8>(cnt, ex, tot, sh);
 #pragma unroll
@@ -1392,7 +1420,8 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
   // themselves; more are reduced by a wavefront each first
   const int fuse = max_tiles_sub <= 64;
   if (!first && !fuse && nsub > 0)
-    hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials);
+    hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials,
+                       tshift_ref);
   hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, partials, fuse, lists,
                      max_subs, o, first, tshift_main, tshift_ref, lb0, top0, x0s, live_host);
   return hipGetLastError();

@@ -42,6 +42,9 @@ struct SubState {
   int32_t last_slab;   // 1: the last update (a refinement update) computed only the tile
                        // column(s) holding the atom's own columns; the last full X is the
                        // other buffer
+  int32_t sq_slab;     // 1: the square just scheduled (the one before that last update)
+                       // computes only the same tile columns of Y, all the last update
+                       // reads; its residual partials are those columns' sums
   double res;          // last residual
   double res_prev;     // residual before that
   double res_new;      // residual of the square just computed (residual_kernel)
@@ -68,7 +71,7 @@ struct TileRec {
   int32_t it;        // iteration counter (parity selects the X buffer)
   int32_t part_idx;  // residual-partial slot of the 64-tile at the tile's top-left corner
   int16_t tiles64;   // 64-tiles per dimension of the submatrix (partial slots: lower triangle)
-  int16_t flags;     // kTileStoreF32
+  int16_t flags;     // kTileStoreF32, kTileSlab
 };
 
 // First refinement update of a submatrix, run by the main-precision update

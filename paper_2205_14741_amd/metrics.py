@@ -23,6 +23,10 @@ update is not the one that runs on the main-precision kernel:
     useful flops of a slab update = 2 n^2 b            (n b entries x 2n)
     issued MFMA flops             = (n_pad / 32) * (32-wide columns of the slab
                                     tiles inside n_pad) * 2 * 32 * 32 * np
+
+With two or more refinement steps the square before that update (a
+refinement square) computes the same slab of Y, which is all the update
+reads: counted the same way, with bytes s (n^2 + n b).
 """
 from __future__ import annotations
 
@@ -118,6 +122,10 @@ def flops_by_class(stats: np.ndarray, n: np.ndarray, npad: np.ndarray, opts, sla
                        * 2.0 * 32 * 32 * npad.astype(np.float64))
         res[key][0] += float(((useful_slab - useful_one) * msk).sum())
         res[key][1] += float(((issued_slab - issued_one) * msk).sum())
+        if int(opts.refine_steps) >= 2:   # the slab square before it
+            key = (int(opts.refine), 0)
+            res[key][0] += float(((useful_slab - useful_one) * msk).sum())
+            res[key][1] += float(((issued_slab - issued_one) * msk).sum())
     return {k: tuple(v) for k, v in res.items()}
 
 
@@ -175,4 +183,7 @@ def bytes_by_class(stats: np.ndarray, n: np.ndarray, opts, slab=None, npad=None)
         bf = np.asarray(b, dtype=np.float64)
         diff = STORE_BYTES[prec] * ((n2 + 2.0 * nf * bf) - 3.0 * n2)
         res[(prec, 1)] += float((diff * msk).sum())
+        if int(opts.refine_steps) >= 2:   # slab square: read X, write b columns
+            diff = STORE_BYTES[prec] * ((n2 + nf * bf) - 2.0 * n2)
+            res[(prec, 0)] += float((diff * msk).sum())
     return res

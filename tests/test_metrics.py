@@ -96,8 +96,13 @@ def test_slab_accounting():
     # issued: 8 row blocks x 4 column blocks (two 64-wide tile columns)
     assert fl[(sm.SM_F32, 1)][1] == 8 * 4 * 2 * 32 * 32 * 256
     assert fl[(sm.SM_BF16X3, 1)] == full[(sm.SM_BF16X3, 1)]
+    # the one float32 square (before the last update) is a slab too
+    assert fl[(sm.SM_F32, 0)][0] == 2.0 * 200 * 200 * 6
+    assert fl[(sm.SM_F32, 0)][1] == 8 * 4 * 2 * 32 * 32 * 256
+    assert fl[(sm.SM_BF16X3, 0)] == full[(sm.SM_BF16X3, 0)]
     by = metrics.bytes_by_class(st, n, o, (loc, b, 6), npad)
     assert by[(sm.SM_F32, 1)] == 4 * (200 * 200 + 2 * 200 * 6)
+    assert by[(sm.SM_F32, 0)] == 4 * (200 * 200 + 200 * 6)
     # a single refinement step runs on the main kernel in full: no slab
     o1 = sm.default_opts("bf16x3", refine_steps=1)
     assert not metrics.slab_mask(st, npad, loc, b, o1, 6).any()
@@ -110,7 +115,16 @@ def test_slab_accounting():
     assert metrics.flops_by_class(st1, n, npad, o, (loc, b, 6)) == metrics.flops_by_class(st1, n, npad, o)
     # a slab with no fewer tiles than the triangle is not taken (npad 64)
     assert not metrics.slab_mask(st, np.array([64]), np.array([10]), b, o, 6).any()
-    # float64 refined in float64: the last of the float64 updates is the slab
+    # float64 refined in float64: the last of the float64 updates and the
+    # square before it are slabs (12 updates, 12 squares in all)
     o64 = sm.default_opts("f64", refine_steps=2, switch_tol=0.1)
     f64 = metrics.flops_by_class(st, n, npad, o64, (loc, b, 6))
     assert f64[(sm.SM_F64, 1)][0] == 11 * 200 * 200 * 201 + 2.0 * 200 * 200 * 6
+    assert f64[(sm.SM_F64, 0)][0] == 11 * 200 * 200 * 201 + 2.0 * 200 * 200 * 6
+    # one refinement step (float32 main phase): the square before the last
+    # update decided the switch and stays full
+    of1 = sm.default_opts("f32", refine_steps=1, switch_tol=0.1)
+    f1 = metrics.flops_by_class(st, n, npad, of1, (loc, b, 6))
+    f1full = metrics.flops_by_class(st, n, npad, of1)
+    assert f1[(sm.SM_F32, 0)] == f1full[(sm.SM_F32, 0)]
+    assert f1[(sm.SM_F32, 1)][0] == f1full[(sm.SM_F32, 1)][0] - 200 * 200 * 201 + 2.0 * 200 * 200 * 6
