@@ -301,8 +301,9 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     // only the GEMMs whose lists can be non-empty: squares as counted by the
     // previous scheduler; refinement updates right away only while
     // submatrices refine (a submatrix entering refinement gets its first
-    // refinement update launched once the count shows it)
-    bool sq_main = true, sq_ref = true;
+    // refinement update launched once the count shows it); no submatrix
+    // refines before its first square
+    bool sq_main = true, sq_ref = false;
     for (int it = 0; it <= lim; ++it) {
       const int slot = kHostCounts + 4 * (it & 1);
       const bool upd_ref = sq_ref;
