@@ -1226,12 +1226,15 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
     if (l < nsub) {
       SubState s = st[l];
       const int np = p.npad_g[g0 + l];
-      const int i = p.order_g[g0 + l];
-      // tiles of a column slab of the refinement kernel (last square / update)
-      const int nslab = slab_tiles(np, p.loc[i], p.bs[i], tshift_ref);
+      // tiles of a column slab of the refinement kernel (last square /
+      // update), read from the plan only where it is needed
+      auto slab_count = [&]() {
+        const int i = p.order_g[g0 + l];
+        return slab_tiles(np, p.loc[i], p.bs[i], tshift_ref);
+      };
       if (!first && fuse_res && s.active) {
         const int T64 = tiles_of(np);
-        const int nt = s.sq_slab ? nslab : T64 * (T64 + 1) / 2;
+        const int nt = s.sq_slab ? slab_count() : T64 * (T64 + 1) / 2;
         const double* pp = partials + p.tile_off_g[g0 + l];
         double r = 0.0;
 #pragma unroll 8
@@ -1247,7 +1250,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       // where it has fewer tiles than the triangle; not for the first
       // refinement update (it runs in full on the main-precision kernel) nor
       // for the square that decides the switch (a main-phase square)
-      const bool slab_ok = nslab < ntr && !(o.copies_main && o.refine_steps == 1);
+      const bool slab_allowed = !(o.copies_main && o.refine_steps == 1);
       if (first) {
         s.active = 1;
         s.phase = 0;
@@ -1325,6 +1328,8 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
           dec = DEC_UPD | DEC_REF;
           s.iters++;
           s.refine_left--;
+          const int nslab = (slab_allowed && s.refine_left <= 1) ? slab_count() : ntr;
+          const bool slab_ok = nslab < ntr;
           if (s.refine_left > 0) {
             dec |= DEC_SQ;
             // the square before the last update: the last update reads only
