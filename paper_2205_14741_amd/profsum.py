@@ -88,6 +88,25 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, cmd_f: st
     return "\n".join(out) + "\n"
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_MFMA_MOPS_F16",
+                 "SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_MOPS_F64")
+
+
+def mfma_summary(csv_path: str, cmd: str) -> str:
+    """Matrix-core flops per dispatch of every kernel that issues any, from
+    the SQ_INSTS_VALU_MFMA_MOPS_* counters (units of 512 flops)."""
+    means = {c: counter_means(csv_path, c) for c in MFMA_COUNTERS}
+    names = sorted({k for m in means.values() for k, (_, v) in m.items() if v > 0})
+    out = ["# rocprofv3 --pmc " + " ".join(c for c in MFMA_COUNTERS if means[c]),
+           "# command: " + cmd,
+           "# mfma <kernel> | dispatches | flops per dispatch: bf16 | f16 | f32 | f64"]
+    for k in names:
+        n = max(m.get(k, (0, 0.0))[0] for m in means.values())
+        vals = [means[c].get(k, (0, 0.0))[1] * 512.0 for c in MFMA_COUNTERS]
+        out.append(f"mfma {k} | {n} | " + " | ".join(f"{v:.4g}" for v in vals))
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str, symbol: str):
     """Scaled HBM bytes per dispatch of `symbol` from a traffic summary, or
     None when the summary is missing, lacks the kernel, or was taken on GEMM
