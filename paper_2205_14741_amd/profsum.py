@@ -5,6 +5,8 @@
     python -m paper_2205_14741_amd.profsum traffic --fetch FETCH_counter_collection.csv \
         --write WRITE_counter_collection.csv --copy-bytes B --cmd-fetch "..." \
         --cmd-write "..." --out SUMMARY.txt
+    python -m paper_2205_14741_amd.profsum mfma --csv MOPS_counter_collection.csv \
+        --cmd "<the profiled command>" --out SUMMARY.txt
 
 `stats` lists the kernels of a kernel-trace run by total time (calls, average,
 total, share).  `traffic` averages the FETCH_SIZE and WRITE_SIZE counters (KiB
@@ -13,6 +15,8 @@ what the same counter reads for a plain copy kernel of known size (the
 elementwise negation of a float32 buffer of B bytes, run by the profiled
 command first): factor = B / counter bytes.  The traffic lines carry a hash
 of the GEMM sources, so a reader can tell whether the kernel has changed since.
+`mfma` gives the matrix-core flops per dispatch of every kernel from the
+SQ_INSTS_VALU_MFMA_MOPS_* counters (512 flops per unit), by precision.
 """
 from __future__ import annotations
 
@@ -138,9 +142,15 @@ def main():
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out", required=True)
+    mf = sub.add_parser("mfma")
+    mf.add_argument("--csv", required=True)
+    mf.add_argument("--cmd", dest="command", required=True)
+    mf.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         text = stats_summary(a.csv, a.command)
+    elif a.cmd == "mfma":
+        text = mfma_summary(a.csv, a.command)
     else:
         text = traffic_summary(a.fetch, a.write, a.copy_bytes, a.cmd_fetch, a.cmd_write)
     with open(a.out, "w") as fh:
