@@ -285,9 +285,14 @@ int sm_gershgorin_bracket(sm_plan* plan, const double* H_vals, double* lo, doubl
  * of its chunk (float32 / float64 elements; for the 16-bit storage codes the
  * copies of buffer b start at float offset max_mats + off, max_mats being the
  * largest per-chunk sum of 3 n_pad^2).  After build_submatrices X_even holds
- * X_0 = T_i / c_i (16-bit storage codes: the copies do; the float32 buffer
- * keeps T_i); after submatrix_sign the final X is the float32 buffer of
- * parity stats[i].iters.
+ * X_0 = T_i / c_i for the float64 code; the other codes keep T_i there (the
+ * 16-bit codes only in the copies) with c_i on the identity pad's diagonal,
+ * the first square and update applying 1 / c_i.  After submatrix_sign the
+ * final X is the float32 (float64) buffer of parity stats[i].iters; where
+ * the last refinement update computed only the tile columns holding the
+ * atom's own columns (a refined submatrix whose slab has fewer tiles than
+ * the triangle), only those columns of it are set, and the other X buffer
+ * holds the last full iterate.
  * Either output may be NULL. */
 int sm_plan_ws_layout(const sm_plan* plan, int32_t storage_prec, int64_t* regions9,
                       int64_t* mat_off_g);
