@@ -272,8 +272,8 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the submatrix path shards by atom "
-              "domains; the multi-GPU exchange is not built). Use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU only (the submatrix path would shard by atom domains; "
+              "the multi-GPU halo exchange is not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if a.config == "cfg3":
         return precision_form(a)

@@ -5,7 +5,7 @@
 * every index set the whole system: P is the exact projector;
 * submatrix dimensions exactly at a tile boundary (n = 64, no padding) and
   one past it (n = 65), for both paddings;
-* NaN in H is reported by the sign call that follows the build.
+* NaN in H is reported by the sign call that follows build_submatrices.
 """
 import numpy as np
 import pytest

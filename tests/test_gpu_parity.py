@@ -249,7 +249,7 @@ def _read_bufs(plan, work, storage, g):
 
 
 def _x0_factor(storage, st, i):
-    """X_0 = factor * buffer 0 after the build: the float64 schedule stores
+    """X_0 = factor * buffer 0 after build_submatrices: the float64 schedule stores
     X_0 = T / c, the others keep T (and c on the pad's diagonal) and their
     first products apply 1 / c."""
     return 1.0 if storage == sm.SM_F64 else 1.0 / st["scale"][i]
