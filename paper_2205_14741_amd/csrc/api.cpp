@@ -1,5 +1,5 @@
 // C-ABI entry points: argument checks, chunk loop, the host side of the
-// Newton-Schulz driver, chemical-potential bisection.
+// Newton-Schulz iteration, chemical-potential bisection.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
