@@ -16,13 +16,26 @@
 
 namespace sm {
 
+// Value of v held by lane `src` (wave-uniform src), for every lane.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Lanes 2k and 2k + 1 exchange v (a DPP quad permutation [1, 0, 3, 2], no LDS
+// round trip); both lanes of the pair must be active.
+__device__ __forceinline__ uint32_t lane_pair_swap(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+}
+
 // Statistics of T_i gathered column by column: column abs sums (= row sums,
 // T is symmetric) give the Gershgorin bound c_G >= rho(T); with the diagonal
 // they give the 16 features of the scaling network.
 struct ColStats {
   double cmax = 0.0, sdiag = 0.0, sdiag2 = 0.0, mind = 1e300, maxd = -1e300, sR = 0.0, maxR = 0.0;
-  double minabs = 1e300, mingap = 1e300, nneg = 0.0, ssq = 0.0, sown = 0.0, minown = 1e300, sabs = 0.0;
-  __device__ void add(double s, double q, double dg, bool own) {
+  double minabs = 1e300, mingap = 1e300, nneg = 0.0, sown = 0.0, minown = 1e300, sabs = 0.0;
+  __device__ void add(double s, double dg, bool own) {
     const double R = s - fabs(dg);
     cmax = fmax(cmax, s);
     sdiag += dg;
@@ -34,7 +47,6 @@ struct ColStats {
     minabs = fmin(minabs, fabs(dg));
     mingap = fmin(mingap, fabs(dg) - R);
     nneg += dg < 0.0 ? 1.0 : 0.0;
-    ssq += q;
     sabs += fabs(dg);
     if (own) {
       sown += dg;
@@ -102,14 +114,14 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
       const bool odd = (lane & 1) != 0;
       if constexpr (KIND == SM_BF16X3) {
         const uint32_t lo = shadow_lo(xf, (uint16_t)h);
-        const uint32_t other = (uint32_t)__shfl_xor((int)(odd ? h : lo), 1, kWave);
+        const uint32_t other = lane_pair_swap(odd ? h : lo);
         const int64_t k = copy_idx<true>(c, d & ~1, npad);
         if (odd)
           *reinterpret_cast<uint32_t*>(cp + k + 32) = other | (lo << 16);
         else
           *reinterpret_cast<uint32_t*>(cp + k) = h | (other << 16);
       } else {
-        const uint32_t other = (uint32_t)__shfl_xor((int)h, 1, kWave);
+        const uint32_t other = lane_pair_swap(h);
         if (!odd) *reinterpret_cast<uint32_t*>(cp + copy_idx<false>(c, d, npad)) = h | (other << 16);
       }
     } else {
@@ -125,6 +137,7 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   __syncthreads();
   bool bad = false;
   ColStats cs;   // this wave's columns (identical in every lane)
+  double ssq_lane = 0.0;   // sum of squares of this lane's entries, reduced once at the end
   for (int jj = wid; jj < m; jj += nw) {
     const int j = s_atom[jj];
     const int locj = s_off[jj];
@@ -135,7 +148,7 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
     // four columns of the atom at a time: one row-map read and four
     // independent panel loads per row
     for (int q0 = 0; q0 < bj; q0 += 4) {
-      double sa[4] = {0.0, 0.0, 0.0, 0.0}, sq[4] = {0.0, 0.0, 0.0, 0.0}, dl[4] = {0.0, 0.0, 0.0, 0.0};
+      double sa[4] = {0.0, 0.0, 0.0, 0.0}, dl[4] = {0.0, 0.0, 0.0, 0.0};
       double pv[4] = {0.0, 0.0, 0.0, 0.0};   // probe entries of the four columns
       if constexpr (POW)
 #pragma unroll
@@ -157,19 +170,23 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
               x -= mu;
               dl[u] = x;
             }
-            bad |= !isfinite(x);
             sa[u] += fabs(x);
-            sq[u] += x * x;
+            ssq_lane += x * x;
             tv += x * pv[u];
             put(c, d, x);
           }
         }
         if constexpr (POW) s_tv[d] += tv;
       }
+      // per column: the abs sum over the wave (a NaN or Inf entry makes it
+      // non-finite), and the diagonal entry from the one lane that holds it
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int c = locj + q0 + u;
-        if (q0 + u < bj) cs.add(wave_sum(sa[u]), wave_sum(sq[u]), wave_sum(dl[u]), c >= loc && c < loc + bsz);
+        if (q0 + u < bj) {
+          bad |= !isfinite(sa[u]);
+          cs.add(wave_sum(sa[u]), lane_value(dl[u], c & (kWave - 1)), c >= loc && c < loc + bsz);
+        }
       }
     }
     wave_sync();   // the row map is rebuilt for the wave's next atom
@@ -199,7 +216,7 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   const double minabs = block_reduce<2>(cs.minabs, red);
   const double mingap = block_reduce<2>(cs.mingap, red);
   const double nneg = block_reduce<0>(lane == 0 ? cs.nneg : 0.0, red);
-  const double ssq = block_reduce<0>(lane == 0 ? cs.ssq : 0.0, red);
+  const double ssq = block_reduce<0>(ssq_lane, red);
   const double sown = block_reduce<0>(lane == 0 ? cs.sown : 0.0, red);
   const double minown = block_reduce<2>(cs.minown, red);
   const double sabs = block_reduce<0>(lane == 0 ? cs.sabs : 0.0, red);
