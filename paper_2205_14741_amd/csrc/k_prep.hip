@@ -115,11 +115,11 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
       if constexpr (KIND == SM_BF16X3) {
         const uint32_t lo = shadow_lo(xf, (uint16_t)h);
         const uint32_t other = lane_pair_swap(odd ? h : lo);
-        const int64_t k = copy_idx<true>(c, d & ~1, npad);
-        if (odd)
-          *reinterpret_cast<uint32_t*>(cp + k + 32) = other | (lo << 16);
-        else
-          *reinterpret_cast<uint32_t*>(cp + k) = h | (other << 16);
+        // one store per lane, no divergent branch: the even lane's word goes
+        // to the hi plane, the odd lane's to the lo plane 32 entries on
+        const int64_t k = copy_idx<true>(c, d & ~1, npad) + (odd ? 32 : 0);
+        const uint32_t word = odd ? (other | (lo << 16)) : (h | (other << 16));
+        *reinterpret_cast<uint32_t*>(cp + k) = word;
       } else {
         const uint32_t other = lane_pair_swap(h);
         if (!odd) *reinterpret_cast<uint32_t*>(cp + copy_idx<false>(c, d, npad)) = h | (other << 16);
@@ -165,11 +165,10 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
         for (int u = 0; u < 4; ++u) {
           const int c = locj + q0 + u;
           if (q0 + u < bj) {
-            double x = v[u];
-            if (d == c) {   // c < n, so only rows of T_i
-              x -= mu;
-              dl[u] = x;
-            }
+            // the diagonal (c < n, so only rows of T_i), without a branch
+            const bool on_diag = d == c;
+            const double x = on_diag ? v[u] - mu : v[u];
+            dl[u] = on_diag ? x : dl[u];
             sa[u] += fabs(x);
             ssq_lane += x * x;
             tv += x * pv[u];
