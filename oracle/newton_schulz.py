@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-The paper says the sign function (Eq. 13) is computed with "various iterative
-methods" without naming one; the iteration used on the hot path is the
+The paper computes the sign function (Eq. 13) iteratively but does not name
+the iteration; the one used on the hot path is the
 Newton-Schulz map X <- 1/2 X (3I - X^2), which converges to sign(X_0) for every
 symmetric X_0 whose eigenvalues are non-zero with |lambda| < sqrt(3).  This
 module states the iteration and its stopping rule exactly as the GPU path runs
