@@ -18,7 +18,7 @@ static_assert(kParams == kMlpParams, "parameter count");
 
 // ---- inference: one wavefront per sample (lane j = hidden unit j),
 // parameters staged in LDS, kInferPerWave samples per wavefront in turn ----
-constexpr int kInferPerWave = 4;
+constexpr int kInferPerWave = 1;
 
 __device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll
