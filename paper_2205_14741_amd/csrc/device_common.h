@@ -192,7 +192,9 @@ __device__ __forceinline__ float copy_value(uint16_t b, int kind) {
 
 // block_matvec over the 16-bit operand copies of a buffer (an entry is its
 // bf16 / f16 copy, or hi + lo for split bf16; copy_idx layout).  Q <= 2.
-template <int Q, typename Out>
+// SPLIT: the copies are split-bf16 (hi and lo planes); a compile-time choice,
+// so that the loads of all columns in flight are issued before any is used.
+template <int Q, bool SPLIT, typename Out>
 __device__ __forceinline__ void block_matvec_copies(const uint16_t* __restrict__ cp, int npad, int n, int kind,
                                                     const double* __restrict__ v, int vs, double* red,
                                                     Out out) {
@@ -201,7 +203,7 @@ __device__ __forceinline__ void block_matvec_copies(const uint16_t* __restrict__
   typedef uint16_t h4 __attribute__((ext_vector_type(4)));
   block_matvec_ld<Q, V>(
       [&](int c, int rb, double (&x)[V]) {
-        if (kind == SM_BF16X3) {
+        if constexpr (SPLIT) {
           const int64_t k = copy_idx<true>(c, rb, npad);
           const h4 hi = *reinterpret_cast<const h4*>(cp + k);
           const h4 lo = *reinterpret_cast<const h4*>(cp + k + 32);

@@ -345,10 +345,14 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
       __syncthreads();
     }
     for (int it = it0; it < power_steps; ++it) {
-      if (copies)   // w = T v
-        block_matvec_copies<1>(cp, npad, n, shadow_kind, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
-      else
+      if (copies) {   // w = T v
+        if (shadow_kind == SM_BF16X3)
+          block_matvec_copies<1, true>(cp, npad, n, shadow_kind, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
+        else
+          block_matvec_copies<1, false>(cp, npad, n, shadow_kind, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
+      } else {
         block_matvec<1>(X, npad, n, v, 0, mv, [&](int, int r, double y) { w[r] = y; });
+      }
       double nw2 = 0.0;
       for (int d = threadIdx.x; d < n; d += blockDim.x) nw2 += w[d] * w[d];
       nw2 = block_reduce<0>(nw2, red);
