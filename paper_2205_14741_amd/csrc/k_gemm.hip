@@ -382,7 +382,8 @@ __global__ __launch_bounds__(kBlock, (GemmOcc<MODE, KDIV>::value)) void ns_gemm_
     // the block of a diagonal tile that lies wholly above the diagonal
     // computes nothing either
     const bool slab = (rec.flags & kTileSlab) != 0;   // all blocks, no mirror
-    const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) && (slab || !(bi == bj && wm < wn));
+    const bool wvalid = (r0 + wm * 32 < npad) && (c0 + wn * 32 < npad) &&
+                        (slab ? (rec.flags & (kTileSlabWave << wn)) != 0 : !(bi == bj && wm < wn));
     const TileSrc<MODE> src = tile_src<MODE, WHICH, 64>(rec, mats, shadow_off, lrow, lpart);
 
     typename Tr::Acc acc[2][2];
@@ -659,6 +660,7 @@ struct SubTiles {
   float alpha, rscale;
   int npad, it, f, nt, po, t64;
   int T, c0;      // slab: tile rows, first tile column
+  int loc, b;     // slab: the atom's columns loc .. loc + b - 1
   int16_t flags;
 };
 
@@ -672,10 +674,14 @@ __device__ __forceinline__ SubTiles sub_tiles(const DevPlan& p, int g, int L, in
   t.nt = T * (T + 1) / 2;
   t.T = T;
   t.c0 = 0;
+  t.loc = 0;
+  t.b = 0;
   if (slab) {
     const int i = p.order_g[g];
-    t.nt = slab_tiles(t.npad, p.loc[i], p.bs[i], tshift);
-    t.c0 = p.loc[i] >> tshift;
+    t.loc = p.loc[i];
+    t.b = p.bs[i];
+    t.nt = slab_tiles(t.npad, t.loc, t.b, tshift);
+    t.c0 = t.loc >> tshift;
   }
   t.mo = p.mat_off_g[g];
   t.it = iters;
@@ -714,6 +720,15 @@ __device__ __forceinline__ TileRec tile_rec(const SubTiles& t, int lt) {
   r.part_idx = (t.flags & kTileSlab) ? t.po + lt : t.po + b64i * (b64i + 1) / 2 + b64j;
   r.tiles64 = (int16_t)t.t64;
   r.flags = t.flags;
+  if (t.flags & kTileSlab) {   // wave-block columns that hold atom columns
+    const int wcol = 32 * t.f;     // wave-block width: half the tile
+    const int cfirst = bj * 2 * wcol;
+#pragma unroll
+    for (int wn = 0; wn < 2; ++wn) {
+      const int lo = cfirst + wn * wcol, hi = lo + wcol;
+      if (lo < t.loc + t.b && hi > t.loc) r.flags |= (int16_t)(kTileSlabWave << wn);
+    }
+  }
   return r;
 }
 
@@ -849,7 +864,8 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
     const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
     const int r0 = bi * 128, c0 = bj * 128;
     const bool slab = (rec.flags & kTileSlab) != 0;   // all blocks, no mirror
-    const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) && (slab || !(bi == bj && wm < wn));
+    const bool wvalid = (r0 + wm * 64 < npad) && (c0 + wn * 64 < npad) &&
+                        (slab ? (rec.flags & (kTileSlabWave << wn)) != 0 : !(bi == bj && wm < wn));
     const TileSrc<MODE> src = tile_src<MODE, WHICH, 128>(rec, mats, shadow_off, lrow, lpart);
     const int nst = npad / K;
     const int kq = lane >> 4;

@@ -71,7 +71,7 @@ struct TileRec {
   int32_t it;        // iteration counter (parity selects the X buffer)
   int32_t part_idx;  // residual-partial slot of the 64-tile at the tile's top-left corner
   int16_t tiles64;   // 64-tiles per dimension of the submatrix (partial slots: lower triangle)
-  int16_t flags;     // kTileStoreF32, kTileSlab
+  int16_t flags;     // kTileStoreF32, kTileSlab, kTileSlabWave bits
 };
 
 // First refinement update of a submatrix, run by the main-precision update
@@ -79,10 +79,15 @@ struct TileRec {
 // the float32 product to float32 rounding): its result is stored in float32,
 // for the refinement steps that follow, instead of as copies.
 constexpr int16_t kTileStoreF32 = 2;
-// Last refinement update of a submatrix: only the tiles of the tile column(s)
-// that hold the atom's own b_i columns (the columns P needs), all four wave
-// blocks of each, stored as they are (no mirror image).
+// Last refinement update of a submatrix (and, with two or more refinement
+// steps, the square before it): only the tiles of the tile column(s) that
+// hold the atom's own b_i columns (the columns P needs), all tile rows, the
+// wave blocks of kTileSlabWave only, stored as they are (no mirror image).
 constexpr int16_t kTileSlab = 4;
+// Slab tiles: the two wave-block columns of the tile (32 wide in 64-wide
+// tiles, 64 wide in 128-wide ones) that hold any of the atom's columns; the
+// other wave blocks are skipped.  Bit kTileSlabWave << wn.
+constexpr int16_t kTileSlabWave = 8;
 
 // Tiles of that last update: all tile rows of the tile columns that
 // columns loc .. loc + b - 1 fall into (tiles of edge 1 << tshift).

@@ -21,8 +21,9 @@ and no mirror, where that slab has fewer tiles than the triangle and the
 update is not the one that runs on the main-precision kernel:
 
     useful flops of a slab update = 2 n^2 b            (n b entries x 2n)
-    issued MFMA flops             = (n_pad / 32) * (32-wide columns of the slab
-                                    tiles inside n_pad) * 2 * 32 * 32 * np
+    issued MFMA flops             = (n_pad / 32) * (32-wide columns of the wave
+                                    blocks that hold atom columns) * 2 * 32 * 32 * np
+                                    (wave blocks are half a tile wide: 32 or 64)
 
 With two or more refinement steps the square before that update (a
 refinement square) computes the same slab of Y, which is all the update
@@ -95,10 +96,12 @@ def slab_mask(stats: np.ndarray, npad, loc, b, opts, tshift_ref: int) -> np.ndar
 
 
 def slab_columns32(npad, loc, b, tshift):
-    """32-wide block columns inside n_pad covered by the slab tiles."""
+    """32-wide columns of the wave blocks a slab computes: the wave blocks
+    (half a tile wide) that hold any of columns loc .. loc + b - 1."""
     npad, loc, b = (np.asarray(x, dtype=np.int64) for x in (npad, loc, b))
-    c0 = (loc >> tshift) << tshift
-    c1 = np.minimum((((loc + b - 1) >> tshift) + 1) << tshift, npad)
+    ws = tshift - 1                     # log2 of the wave-block width
+    c0 = (loc >> ws) << ws
+    c1 = np.minimum((((loc + b - 1) >> ws) + 1) << ws, npad)
     return (c1 - c0) // 32
 
 

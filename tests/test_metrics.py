@@ -93,12 +93,13 @@ def test_slab_accounting():
     full = metrics.flops_by_class(st, n, npad, o)
     # the one float32 update (the second refinement update) is the slab
     assert fl[(sm.SM_F32, 1)][0] == 2.0 * 200 * 200 * 6
-    # issued: 8 row blocks x 4 column blocks (two 64-wide tile columns)
-    assert fl[(sm.SM_F32, 1)][1] == 8 * 4 * 2 * 32 * 32 * 256
+    # issued: 8 row blocks x 2 column blocks (the 32-wide wave blocks 32..63
+    # and 64..95 that hold columns 61 .. 66)
+    assert fl[(sm.SM_F32, 1)][1] == 8 * 2 * 2 * 32 * 32 * 256
     assert fl[(sm.SM_BF16X3, 1)] == full[(sm.SM_BF16X3, 1)]
     # the one float32 square (before the last update) is a slab too
     assert fl[(sm.SM_F32, 0)][0] == 2.0 * 200 * 200 * 6
-    assert fl[(sm.SM_F32, 0)][1] == 8 * 4 * 2 * 32 * 32 * 256
+    assert fl[(sm.SM_F32, 0)][1] == 8 * 2 * 2 * 32 * 32 * 256
     assert fl[(sm.SM_BF16X3, 0)] == full[(sm.SM_BF16X3, 0)]
     by = metrics.bytes_by_class(st, n, o, (loc, b, 6), npad)
     assert by[(sm.SM_F32, 1)] == 4 * (200 * 200 + 2 * 200 * 6)
@@ -109,6 +110,7 @@ def test_slab_accounting():
     # 128-wide tiles: 2 tile rows x 1 tile column = 2 tiles < 3 triangle tiles
     assert metrics.slab_mask(st, npad, loc, b, o, 7).all()
     fl7 = metrics.flops_by_class(st, n, npad, o, (loc, b, 7))
+    # 64-wide wave blocks 0..63 and 64..127: 4 columns of 32
     assert fl7[(sm.SM_F32, 1)][1] == 8 * 4 * 2 * 32 * 32 * 256
     # not converged (status 1): no refinement ran, nothing changes
     st1 = _stats([12], [12], [1])
