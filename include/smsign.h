@@ -114,23 +114,48 @@ typedef struct {
                             sqrt(1 - ||X^2 - I||_F) once that residual is below 1.  The
                             scale a never exceeds sqrt(3) / 1.01 of the spectrum's top, so no
                             eigenvalue can change sign; a wrong l costs iterations only.
-                            Refinement steps are plain. */
+                            Refinement steps are plain.  With accel 0 every step is plain
+                            except the first where the scale c is below c_G / (sqrt(3) / 1.01)
+                            (a learned or power scale): that step is scaled by
+                            a = sqrt(3) / (1.01 c_G / c), because c_G / c is the only rigorous
+                            bound on the top of the spectrum of X_0. */
   double lbound;         /* l_0 as a fraction of the Gershgorin bound: the smallest
                             |eigenvalue| of T is taken to be about lbound * c_G (0: none) */
   int32_t comm_probes;   /* 0..4: float64 commutator probes ||(X T - T X) v|| / (c ||v||) per
                             submatrix (sm_comm_probe), run by sm_density_matrix after every
                             chunk's sign and by sm_find_mu in every pass; 0 = off */
-  int32_t reserved;
+  int32_t retry;         /* 1: every submatrix that ends with status 0 (not converged) or -1
+                            (diverged) is built and iterated once more, in the same call, with
+                            the fallback schedule: Gershgorin scale, plain Newton-Schulz, the
+                            same precisions, twice max_iter (at most 1000); its record gets
+                            retried = 1 and the outcome of that second run.  0: no retry. */
+  double force_scale;    /* testing only; 0 = off.  > 0: c = force_scale * c_G for every
+                            submatrix, and the bound on the top of the spectrum of X_0 is
+                            withheld (taken as 1), as if a wrong scale had been trusted: with
+                            force_scale well below rho / c_G the iteration diverges, which
+                            exercises the divergence test and the retry. */
 } sm_sign_opts;
 
 /* Per-submatrix result record, written on the device by build_submatrices
  * (scale, scale_src, gersh, rho_est, feat) and submatrix_sign (the rest).
- * 144 bytes, indexed by submatrix (atom) id. */
+ * 152 bytes, indexed by submatrix (atom) id. */
 typedef struct {
   int32_t iters;       /* Newton-Schulz updates applied in total */
   int32_t iters_low;   /* ... of which in the phase-1 precision */
-  int32_t status;      /* 1 converged, 0 hit max_iter, 2 refinement done, -1 diverged */
-  int32_t scale_src;   /* 0 Gershgorin, 1 power, 2 learned accepted, 3 learned rejected */
+  int32_t status;      /* 1 converged (||X^2 - I||_F < tol, or stagnation below stall_below);
+                          2 refinement steps done after the main phase reached switch_tol (or
+                          stagnated);
+                          0 not converged: max_iter reached -- with refinement, the main phase
+                          ended at max_iter, or the square before the last update (its
+                          columns' part where only the atom's columns were computed) was
+                          not below max(switch_tol, stall_below);
+                          -1 diverged: a non-finite residual, a residual above 2 sqrt(n_pad)
+                          after the first update (no iterate of a valid run can have one:
+                          every eigenvalue stays in [-sqrt 3, sqrt 3]), or, at or above
+                          stall_below, a residual that grew by more than 5 % over an
+                          unscaled step (plain Newton-Schulz never increases it) */
+  int32_t scale_src;   /* 0 Gershgorin, 1 power, 2 learned accepted, 3 learned rejected,
+                          4 forced (sm_sign_opts.force_scale, testing) */
   double scale;        /* c used for X_0 = T / c */
   double res;          /* ||X^2 - I||_F of the last full square, from the GEMM epilogue
                           (float64 sum); with two or more refinement steps the last
@@ -154,6 +179,8 @@ typedef struct {
                           c the scale); it is the residual that sees an error in the
                           occupied subspace, which X^2 = I cannot.  -1 if not run */
   float feat[16];      /* features of the scaling network (see sm_mlp_create) */
+  int32_t retried;     /* 1: the record is that of the fallback run (sm_sign_opts.retry) */
+  int32_t reserved;
 } sm_sub_stats;
 
 typedef struct sm_plan sm_plan;
@@ -162,7 +189,7 @@ typedef struct sm_mlp sm_mlp;
 /* Fills `o` with the defaults for a precision schedule: phase1 = prec; for
  * SM_F64 tol 1e-10 and no refinement; for SM_F32 no refinement with a
  * stagnation stop; for SM_BF16 / SM_F16 / SM_BF16X3 switch at 0.1 (or on
- * stagnation) and 2 (3 for SM_BF16) SM_F32 refinement steps. */
+ * stagnation) and 2 (3 for SM_BF16) SM_F32 refinement steps; retry on. */
 int sm_default_opts(int32_t prec, sm_sign_opts* o);
 
 /* Symbolic plan (host only; no device work until the first device call).
@@ -222,7 +249,12 @@ int build_submatrices(sm_plan* plan, int32_t chunk, const double* H_vals, double
  * Newton-Schulz iteration X <- 1/2 X (3I - X^2) under the precision schedule of
  * opts, all submatrices batched into the same launches; a device scheduler
  * retires converged submatrices.  Writes the per-submatrix records in `stats`.
- * Non-convergence is reported in stats[i].status, not as an error;
+ * Non-convergence is reported in stats[i].status, not as an error; with
+ * opts->retry the failed submatrices are built again from the H_vals and mu
+ * of the preceding build_submatrices call of this chunk (H_vals must still be
+ * valid; SM_ERR_STATE if the last build was of another chunk) and iterated
+ * once more with the fallback schedule before the call returns (one more
+ * host synchronisation to count them);
  * SM_ERR_NONFINITE if the preceding build_submatrices found NaN/Inf in a T_i
  * (checked at the first poll, the queued work is left to finish).  Blocks the
  * host only to poll, once per iteration, the scheduler's count of submatrices

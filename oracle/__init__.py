@@ -13,6 +13,5 @@ Modules
                 full-matrix projector (the exact reference).
   newton_schulz -- the plain dense Newton-Schulz sign iteration in float64
                 (iteration counts and the convergence rule), and the scalar map.
-  features   -- per-submatrix spectral features and bounds.
   mlp        -- float64 forward / backward / Adam of the scaling network.
 """

@@ -10,11 +10,12 @@ Paper passages followed (arXiv 2205.14741):
   evaluated here (``numpy.linalg.eigh``), with sign(0) := 0.
 * Eq. 14 -- purification P = 1/2 (I - sign(S^-1 H - mu I)) S^-1; every
   workload has an orthogonal basis (S = I), so P = 1/2 (I - sign(H - mu I)).
-* Fig. 2 (caption) -- the submatrix method: (1) for every column build the
-  dense principal submatrix T_i of all rows/columns coupled to it, (2) apply
-  the matrix function to the dense T_i, (3) insert the relevant result columns
-  into the sparse result.  Columns are taken per atom block: all columns of one
-  atom share one index set.
+* Fig. 2 -- the submatrix method.  Each column of the sparse matrix gets a
+  small dense matrix: the principal submatrix T_i over every index that the
+  column couples to.  The matrix function is evaluated on that dense T_i, and
+  only the columns of the result that belong to column i are copied back into
+  the sparse output.  Here the unit is an atom block, not a single column:
+  the columns of one atom share one index set.
 * Section 2 (linear-scaling methods) -- the chemical potential mu separates
   occupied from unoccupied states; the paper gives no rule for finding it, so
   bisection on the electron count tr P is used (see ``find_mu``).
@@ -33,7 +34,7 @@ __all__ = [
     "BlockView", "index_set", "submatrix_indices", "submatrix", "sign_eigh",
     "gershgorin_bound", "density_matrix", "density_matrix_columns",
     "energy_trace", "SpectralCache", "find_mu", "global_gershgorin_bracket",
-    "full_P", "dense_H",
+    "full_P",
 ]
 
 
@@ -249,18 +250,6 @@ def find_mu(m, n_target: float, max_steps: int = 60, accept: float = 0.5,
 # ----------------------------------------------------------------------------
 # exact reference (whole matrix)
 # ----------------------------------------------------------------------------
-
-def dense_H(m) -> np.ndarray:
-    view = m if isinstance(m, BlockView) else BlockView(m)
-    N = int(view.orb_off[-1])
-    H = np.zeros((N, N))
-    for c in range(view.n_atoms):
-        oc, bc = view.orb_off[c], int(view.bs[c])
-        for r in view.rows_of(c):
-            orr, br = view.orb_off[r], int(view.bs[r])
-            H[orr:orr + br, oc:oc + bc] = view.block(r, c)
-    return H
-
 
 def full_P(H: np.ndarray, n_occ: int) -> np.ndarray:
     """Exact projector onto the n_occ lowest eigenvectors of the whole H

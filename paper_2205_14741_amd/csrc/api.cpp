@@ -29,6 +29,9 @@ int check_opts(const sm_sign_opts* o) {
   if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
   if (o->accel != 0 && o->accel != 1) return set_error(SM_ERR_ARG, "opts.accel = %d is not 0 or 1", o->accel);
   if (o->comm_probes < 0 || o->comm_probes > 4) return set_error(SM_ERR_ARG, "opts.comm_probes = %d out of [0, 4]", o->comm_probes);
+  if (o->retry != 0 && o->retry != 1) return set_error(SM_ERR_ARG, "opts.retry = %d is not 0 or 1", o->retry);
+  if (!(o->force_scale >= 0.0) || !std::isfinite(o->force_scale))
+    return set_error(SM_ERR_ARG, "opts.force_scale must be finite and >= 0");
   if (!(o->lbound >= 0.0 && o->lbound <= 1.0)) return set_error(SM_ERR_ARG, "opts.lbound out of [0, 1]");
   if (!(o->tol >= 0) || !(o->switch_tol >= 0) || !(o->stall_ratio >= 0) || !(o->stall_below >= 0) ||
       !(o->scale_margin >= 0))
@@ -188,7 +191,7 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   float* pred = reinterpret_cast<float*>(w.scratch + p->max_subs);  // [2 max_subs]
   const int shadow_kind = storage >= SM_BF16 ? storage : 0;
   SM_HIP(launch_gather(p->dev, g0, nsub, p->max_m, p->max_npad, H, mu, w.mats, f64, shadow_kind, shadow, flag,
-                       w.features, cg, stats, power_in_gather ? w.vecs : nullptr, s));
+                       w.features, cg, stats, power_in_gather ? w.vecs : nullptr, nullptr, s));
   const float* predp = nullptr;
   if (o->scaling == SM_SCALE_LEARNED) {
     if (!p->mlp) return set_error(SM_ERR_STATE, "build_submatrices: learned scaling needs a network (sm_plan_set_mlp)");
@@ -198,8 +201,12 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   }
   SM_HIP(launch_scale(p->dev, g0, nsub, w.mats, f64, o->scaling, o->power_steps, o->scale_margin, w.vecs,
                       cg, predp, stats, shadow_kind, shadow, o->lbound, w.scratch + 2 * p->max_subs,
-                      w.scratch + 3 * p->max_subs, w.scratch + 4 * p->max_subs, power_in_gather, s));
+                      w.scratch + 3 * p->max_subs, w.scratch + 4 * p->max_subs, power_in_gather,
+                      o->force_scale, nullptr, s));
   p->last_storage = storage;
+  p->last_chunk = chunk;
+  p->last_H = H;
+  p->last_mu = mu;
   return SM_OK;
 }
 
@@ -254,8 +261,10 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       return r;
     return SM_OK;
   };
+  // the schedule the scheduler applies: opts, or the fallback of the retry
+  const sm_sign_opts* cur = o;
   auto schedule = [&](int first, int32_t* live_host) -> int {
-    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *o, first, tsh_main, tsh_ref,
+    SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *cur, first, tsh_main, tsh_ref,
                            first ? w.scratch + 2 * p->max_subs : nullptr,
                            first ? w.scratch + 3 * p->max_subs : nullptr,
                            first ? w.scratch + 4 * p->max_subs : nullptr, live_host, max_tiles_sub, s));
@@ -290,32 +299,38 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     return SM_OK;
   };
 
+  // the host waits for each iteration's scheduler while that iteration's
+  // updates run, stops as soon as no submatrix squares again, and launches
+  // only the GEMMs whose lists can be non-empty: squares as counted by the
+  // previous scheduler; refinement updates right away only while
+  // submatrices refine (a submatrix entering refinement gets its first
+  // refinement update launched once the count shows it); no submatrix
+  // refines before its first square
+  auto eager_loop = [&](int lim) -> int {
+    bool sq_main = true, sq_ref = false;
+    int r;
+    for (int it = 0; it <= lim; ++it) {
+      const int slot = kHostCounts + 4 * (it & 1);
+      const bool upd_ref = sq_ref;
+      if ((r = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref, upd_ref))) return r;
+      SM_HIP(hipEventSynchronize(p->ev[it & 1]));
+      if (it == 0 && (r = nonfinite())) return r;
+      const int32_t* hc = p->h_pinned + slot;
+      if (!upd_ref && hc[3] > 0 && (r = gemms(0, 1, 1, false, true))) return r;
+      if (hc[0] == 0) break;
+      sq_main = hc[1] > 0;
+      sq_ref = hc[2] > 0;
+    }
+    return SM_OK;
+  };
+
   // bounds on the spectrum of X_0 written by build_submatrices (scaled
   // Newton-Schulz), then the first squares' records
   if ((rc = schedule(1, nullptr)) || (rc = expand())) return rc;
   const int lim = o->max_iter + o->refine_steps + 2;
   const int G = p->profiling ? 0 : o->graph_iters;
   if (G == 0) {
-    // the host waits for each iteration's scheduler while that iteration's
-    // updates run, stops as soon as no submatrix squares again, and launches
-    // only the GEMMs whose lists can be non-empty: squares as counted by the
-    // previous scheduler; refinement updates right away only while
-    // submatrices refine (a submatrix entering refinement gets its first
-    // refinement update launched once the count shows it); no submatrix
-    // refines before its first square
-    bool sq_main = true, sq_ref = false;
-    for (int it = 0; it <= lim; ++it) {
-      const int slot = kHostCounts + 4 * (it & 1);
-      const bool upd_ref = sq_ref;
-      if ((rc = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref, upd_ref))) return rc;
-      SM_HIP(hipEventSynchronize(p->ev[it & 1]));
-      if (it == 0 && (rc = nonfinite())) return rc;
-      const int32_t* hc = p->h_pinned + slot;
-      if (!upd_ref && hc[3] > 0 && (rc = gemms(0, 1, 1, false, true))) return rc;
-      if (hc[0] == 0) break;
-      sq_main = hc[1] > 0;
-      sq_ref = hc[2] > 0;
-    }
+    if ((rc = eager_loop(lim))) return rc;
   } else {
     // find or capture the graph of G iterations for this chunk / workspace / schedule
     hipGraphExec_t exec = nullptr;
@@ -358,6 +373,40 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     if (replays == 1) {
       SM_HIP(hipEventSynchronize(p->ev[0]));
       if ((rc = nonfinite())) return rc;
+    }
+  }
+  // fallback retry: submatrices that did not converge or diverged are built
+  // again from H and run once more with Gershgorin scaling and plain
+  // Newton-Schulz (a scale or bound that misled the first run is not used
+  // again) and twice the iteration cap; the others keep their result
+  if (o->retry) {
+    if (p->last_chunk != chunk || !p->last_H)
+      return set_error(SM_ERR_STATE, "submatrix_sign: retry needs the build_submatrices call of this chunk");
+    int32_t* fail = reinterpret_cast<int32_t*>(w.scratch + 5 * p->max_subs);
+    SM_HIP(launch_collect_failed(nsub, w.st, fail, p->d_pinned + kHostRetry, s));
+    SM_HIP(hipStreamSynchronize(s));
+    const int nfail = p->h_pinned[kHostRetry];
+    if (nfail > 0) {
+      sm_sign_opts fb = *o;
+      fb.scaling = SM_SCALE_GERSHGORIN;
+      fb.accel = 0;
+      fb.lbound = 0.0;
+      fb.force_scale = 0.0;
+      fb.retry = 0;
+      fb.graph_iters = 0;
+      fb.max_iter = std::min(std::max(2 * o->max_iter, 1), 1000);
+      const int shadow_kind_b = storage >= SM_BF16 ? storage : 0;
+      SM_HIP(launch_fill_i32(p->d_pinned + 8, 0, 1, s));
+      SM_HIP(launch_gather(p->dev, g0, nfail, p->max_m, p->max_npad, p->last_H, p->last_mu, w.mats, f64,
+                           shadow_kind_b, shadow, p->d_pinned + 8, w.features, w.scratch, stats, nullptr, fail, s));
+      SM_HIP(launch_scale(p->dev, g0, nfail, w.mats, f64, SM_SCALE_GERSHGORIN, 0, 0.0, w.vecs, w.scratch, nullptr,
+                          stats, shadow_kind_b, shadow, 0.0, w.scratch + 2 * p->max_subs,
+                          w.scratch + 3 * p->max_subs, w.scratch + 4 * p->max_subs, false, 0.0, fail, s));
+      cur = &fb;
+      if ((rc = schedule(2, nullptr)) || (rc = expand())) return rc;
+      rc = eager_loop(fb.max_iter + fb.refine_steps + 2);
+      cur = o;
+      if (rc) return rc;
     }
   }
   if (!f64)   // float32 final X where only its copies, or T (X = X_0), are in the buffer

@@ -1215,7 +1215,7 @@ __global__ __launch_bounds__(256) void residual_kernel(DevPlan p, int g0, int ns
   double r = 0.0;
   for (int k = lane; k < nt; k += 64) r += pp[k];
   r = wave_sum(r);
-  if (lane == 0) st[l].res_new = sqrt(fmax(r, 0.0));
+  if (lane == 0) st[l].res_new = (isnan(r) ? r : sqrt(fmax(r, 0.0)));
 }
 
 // One workgroup, a thread per submatrix: apply the stopping / phase-switch
@@ -1255,7 +1255,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         double r = 0.0;
 #pragma unroll 8
         for (int k = 0; k < nt; ++k) r += pp[k];
-        s.res_new = sqrt(fmax(r, 0.0));
+        s.res_new = (isnan(r) ? r : sqrt(fmax(r, 0.0)));
       }
       const int Tm = (np + (1 << tshift_main) - 1) >> tshift_main;
       const int Tr = (np + (1 << tshift_ref) - 1) >> tshift_ref;
@@ -1267,7 +1267,9 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       // refinement update (it runs in full on the main-precision kernel) nor
       // for the square that decides the switch (a main-phase square)
       const bool slab_allowed = !(o.copies_main && o.refine_steps == 1);
-      if (first) {
+      if (first == 2 && s.status > 0) {
+        // fallback retry: this submatrix finished well in the first run
+      } else if (first) {
         s.active = 1;
         s.phase = 0;
         s.iters = 0;
@@ -1278,20 +1280,30 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         s.res_prev = 1e300;
         s.lb = lb0 ? fmax(lb0[l], 0.0) : 0.0;
         s.top = top0 ? fmax(top0[l], 1.0) : 1.0;
-        s.alpha_sq = (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : 1.0;
+        // the first step maps the top of the spectrum to at most sqrt 3 / 1.01
+        // whatever the schedule: with a scale c below rho(T) / sqrt 3 (a learned
+        // scale the guard could not refute) an unscaled step would send the
+        // eigenvalues above sqrt 3 to the wrong sign
+        const double cap = 1.7320508075688772 / (1.01 * s.top);
+        s.alpha_sq = (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : (cap < 1.0 ? (double)(float)cap : 1.0);
         s.alpha_upd = 1.0;
+        s.a0 = 1.0;
         s.lb_est = -1.0;
         s.last_slab = 0;
         s.sq_slab = 0;
         s.x0s = x0s ? x0s[l] : 1.0;
+        s.res_last = 1e300;
+        s.cap_hit = 0;
+        s.retried = first == 2 ? 1 : 0;
         dec = DEC_SQ;
       } else if (s.active) {
         const double r = s.res_new;
         double lb = s.lb, top = s.top;
+        s.res_last = r;
         if (s.sq_slab) {
           // a slab square (refinement, the last update next): its columns'
-          // residual only flags a diverged iteration; res keeps the last
-          // full one
+          // residual only flags a diverged iteration and decides the final
+          // status; res keeps the last full one
           s.sq_slab = 0;
           if (!(r < 1e300)) {
             s.status = -1;
@@ -1301,6 +1313,14 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
           s.res_prev = s.res;
           s.res = r;
           const bool stalled = r < o.stall_below && r > o.stall_ratio * s.res_prev;
+          // divergence: after the first update every eigenvalue of a valid
+          // iterate lies in [-sqrt 3, sqrt 3], so |x^2 - 1| <= 2 and the
+          // residual is at most 2 sqrt(n_pad); and an unscaled step never
+          // increases it (|g(x)^2 - 1| <= |x^2 - 1| on that interval), so a
+          // growth well beyond rounding above stall_below means an eigenvalue
+          // has left the interval (a scale below rho / sqrt 3 was trusted)
+          const bool diverged = s.iters >= 1 && (r > 2.02 * sqrt((double)np) ||
+                                                 (s.alpha_upd == 1.0 && r >= o.stall_below && r > 1.05 * s.res_prev));
           // r < 1 bounds every eigenvalue x of the current X: |x^2 - 1| <= r
           if (r < 1.0) {
             lb = fmax(lb, sqrt(1.0 - r));
@@ -1311,10 +1331,11 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
             if (!o.accel && r >= 0.01) {
               double x = sqrt(1.0 - r);
               for (int j = 0; j < s.iters; ++j) x = ns_map_inv(x);
-              s.lb_est = fmax(s.lb_est, x);
+              // the first update was g(a0 X_0), the later ones plain
+              s.lb_est = fmax(s.lb_est, s.iters >= 1 ? x / s.a0 : x);
             }
           }
-          if (!(r < 1e300)) {
+          if (!(r < 1e300) || diverged) {
             s.status = -1;
             s.active = 0;
           } else if (s.phase == 0) {
@@ -1333,6 +1354,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
             } else if (r < o.switch_tol || stalled || s.iters >= o.max_iter) {
               s.phase = 1;
               s.refine_left = o.refine_steps;
+              s.cap_hit = !(r < o.switch_tol) && !stalled;   // ran out of main-phase iterations
             } else {
               dec = DEC_UPD | DEC_SQ;
               s.iters++;
@@ -1355,7 +1377,12 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
               ntr_sq = nslab;
             }
           } else {
-            s.status = 2;
+            // refinement done; not converged where the main phase ran out of
+            // iterations, or where the square before this last update (r; for
+            // a slab square its columns' part, a lower bound) is not below
+            // the larger of switch_tol and stall_below, i.e. outside the
+            // range in which the main phase hands over to refinement
+            s.status = (s.cap_hit || !(r < fmax(o.switch_tol, o.stall_below))) ? 0 : 2;
             s.active = 0;
             // the last update needs only the atom's own columns of X (the
             // columns P takes); taken only where the slab has fewer tiles
@@ -1371,6 +1398,7 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
           // the update of X uses its square's scale; bounds for the new X
           const double a = s.alpha_sq;
           s.alpha_upd = a;
+          if (s.iters == 1) s.a0 = a;
           const double lo = fmin(ns_map(a, lb), ns_map(a, top));
           s.top = (a * top >= 1.0 && a * lb <= 1.0) ? 1.0 : fmax(ns_map(a, lb), ns_map(a, top));
           s.lb = fmax(lo, 0.0);
@@ -1428,6 +1456,28 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
       live_host[3] = run_tiles[1];
     }
   }
+}
+
+// One workgroup: the local indices of the submatrices of the chunk whose
+// iteration failed (status 0 or -1), in ascending order, and their number
+// (one thread writes the count: it may be host-mapped memory).
+__global__ __launch_bounds__(1024) void collect_failed_kernel(int nsub, const SubState* __restrict__ st,
+                                                              int32_t* __restrict__ list, int32_t* count) {
+  __shared__ int sh[16];
+  int run = 0;
+  for (int base = 0; base < nsub; base += blockDim.x) {
+    const int l = base + threadIdx.x;
+    int v[1] = {(l < nsub && st[l].status <= 0) ? 1 : 0}, ex[1], tot[1];
+    block_excl_scan<1>(v, ex, tot, sh);
+    if (v[0]) list[run + ex[0]] = l;
+    run += tot[0];
+  }
+  if (threadIdx.x == 0) *count = run;
+}
+
+hipError_t launch_collect_failed(int nsub, const SubState* st, int32_t* list, int32_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(collect_failed_kernel, dim3(1), dim3(1024), 0, s, nsub, st, list, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,

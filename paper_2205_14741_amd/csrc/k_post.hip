@@ -111,6 +111,7 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
     r.iters = s.iters;
     r.iters_low = s.iters_low;
     r.status = s.status;
+    r.retried = s.retried;
     r.res = s.res;
     r.lb_est = s.lb_est;
     r.res_probe = worst;   // -1 without probes
@@ -158,7 +159,7 @@ hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, i
 // offsets and one row map per wave (as the gather).
 template <int Q, typename Out>
 __device__ __forceinline__ void t_matvec(const DevPlan& p, const double* __restrict__ H, double mu,
-                                         const int* s_atom, const int* s_off, int m, int n, int* s_src,
+                                         const int* s_atom, const int* s_off, int m, int n, RowSrc* s_src,
                                          const double* __restrict__ w, int ws, Out out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(256) void comm_probe_kernel(DevPlan p, int g0, cons
   const int m = (int)(p.col_ptr[i + 1] - k0);
   int* s_atom = smem;
   int* s_off = smem + m;
-  int* s_src = smem + 2 * m + (threadIdx.x / kWave) * npad;
+  RowSrc* s_src = reinterpret_cast<RowSrc*>(smem + 2 * m) + (threadIdx.x / kWave) * npad;
   for (int t = threadIdx.x; t < m; t += blockDim.x) {
     s_atom[t] = p.row_idx[k0 + t];
     s_off[t] = p.blk_rowoff[k0 + t];
@@ -248,7 +249,7 @@ template <typename T>
 static hipError_t launch_comm_t(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,
                                 double mu, const T* mats, const SubState* st, int probes, double* vecs,
                                 sm_sub_stats* stats, hipStream_t s) {
-  const size_t lds = (size_t)(2 * max_m + 4 * max_npad) * sizeof(int);
+  const size_t lds = row_maps_bytes(max_m, 4, max_npad);
   switch (probes) {
     case 1: hipLaunchKernelGGL((comm_probe_kernel<T, 1>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, mats, st, vecs, stats); break;
     case 2: hipLaunchKernelGGL((comm_probe_kernel<T, 2>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, mats, st, vecs, stats); break;

@@ -80,10 +80,13 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
                                                      int64_t shadow_off, int* nonfinite,
                                                      float* __restrict__ features, double* __restrict__ cg_out,
                                                      sm_sub_stats* __restrict__ stats,
-                                                     double* __restrict__ vecs) {
+                                                     double* __restrict__ vecs,
+                                                     const int32_t* __restrict__ subs) {
   extern __shared__ __attribute__((aligned(16))) int smem[];
   __shared__ double red[8];
-  const int g = g0 + blockIdx.x;
+  // workgroup -> local index of its submatrix in the chunk (all, or a list)
+  const int l = subs ? subs[blockIdx.x] : (int)blockIdx.x;
+  const int g = g0 + l;
   const int i = p.order_g[g];
   const int npad = p.npad_g[g];
   const int n = p.height[i];
@@ -96,9 +99,9 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
   const int nw = blockDim.x / kWave;
   int* s_atom = smem;
   int* s_off = smem + m;
-  int* s_src = smem + 2 * m + wid * npad;
+  RowSrc* s_src = reinterpret_cast<RowSrc*>(smem + 2 * m) + wid * npad;
   // POW: partial sums of T v0, one row of n_pad doubles per wave
-  double* s_tv = reinterpret_cast<double*>(smem + ((2 * m + nw * npad + 1) & ~1)) + wid * npad;
+  double* s_tv = reinterpret_cast<double*>(reinterpret_cast<char*>(smem) + row_maps_bytes(m, nw, npad)) + wid * npad;
   T* X = mats + p.mat_off_g[g];
   // low-precision schedules: T goes straight into the 16-bit operand copies
   // that the products read (the float32 buffer is not written).  Every lane
@@ -242,18 +245,18 @@ __global__ __launch_bounds__(256, 4) void gather_kernel(DevPlan p, int g0, const
     f[15] = (float)(sabs / nn / cG);
     sm_sub_stats& r = stats[i];
     for (int k = 0; k < kNumFeatures; ++k) {
-      features[(int64_t)blockIdx.x * kNumFeatures + k] = f[k];
+      features[(int64_t)l * kNumFeatures + k] = f[k];
       r.feat[k] = f[k];
     }
     r.gersh = cG;
-    cg_out[blockIdx.x] = cG;
+    cg_out[l] = cG;
   }
 }
 
 size_t gather_lds_bytes(int max_m, int max_npad, bool power) {
   // 4 waves: atoms + offsets, a row map per wave, (power) a row of partial
   // sums of T v0 per wave
-  size_t b = (size_t)((2 * max_m + 4 * max_npad + 1) & ~1) * sizeof(int);
+  size_t b = row_maps_bytes(max_m, 4, max_npad);
   if (power) b += (size_t)4 * max_npad * sizeof(double);
   return b;
 }
@@ -261,13 +264,13 @@ size_t gather_lds_bytes(int max_m, int max_npad, bool power) {
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
                          const double* H, double mu, void* mats, int storage_f64, int shadow_kind,
                          int64_t shadow_off, int* nonfinite, float* features, double* cg_out,
-                         sm_sub_stats* stats, double* power_vecs, hipStream_t s) {
+                         sm_sub_stats* stats, double* power_vecs, const int32_t* subs, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   const bool pw = power_vecs != nullptr;
   const size_t lds = gather_lds_bytes(max_m, max_npad, pw);
 #define SM_GATHER(TT, K, PW)                                                                             \
   hipLaunchKernelGGL((gather_kernel<TT, K, PW>), dim3(nsub), dim3(256), lds, s, p, g0, H, mu, (TT*)mats, \
-                     shadow_off, nonfinite, features, cg_out, stats, power_vecs)
+                     shadow_off, nonfinite, features, cg_out, stats, power_vecs, subs)
 #define SM_GATHER2(TT, K) \
   if (pw) SM_GATHER(TT, K, true); else SM_GATHER(TT, K, false)
   if (storage_f64) { SM_GATHER2(double, 0); }
@@ -297,10 +300,12 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
                                                     int64_t shadow_off, double lbound,
                                                     double* __restrict__ lb0_out,
                                                     double* __restrict__ top0_out,
-                                                    double* __restrict__ x0s_out, int pre_w) {
+                                                    double* __restrict__ x0s_out, int pre_w,
+                                                    double force_scale,
+                                                    const int32_t* __restrict__ subs) {
   __shared__ double red[16];
   __shared__ double mv[matvec_red<1, T>(8)];
-  const int l = blockIdx.x;
+  const int l = subs ? subs[blockIdx.x] : (int)blockIdx.x;
   const int g = g0 + l;
   const int i = p.order_g[g];
   const int npad = p.npad_g[g];
@@ -381,6 +386,11 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
       src = 3;
     }
   }
+  // testing: a scale forced below the spectral radius, with its bound withheld
+  if (force_scale > 0.0) {
+    c = force_scale * cG;
+    src = 4;
+  }
   const double sc = 1.0 / c;
   // float64: X_0 = T / c in place.  float32 and the 16-bit schedules keep T
   // in their buffers and the first square and update apply 1 / c (x0s); the
@@ -418,7 +428,7 @@ __global__ __launch_bounds__(512) void scale_kernel(DevPlan p, int g0, T* __rest
     const double lb = fmin(fmax(lrel, 0.0) * cG / c, 1.0);
     r.lb0 = lb;
     lb0_out[l] = lb;
-    top0_out[l] = cG / c;
+    top0_out[l] = force_scale > 0.0 ? 1.0 : cG / c;
     x0s_out[l] = std::is_same<T, double>::value ? 1.0 : sc;
   }
 }
@@ -427,16 +437,16 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
                         double lbound, double* lb0_out, double* top0_out, double* x0s_out, bool pre_w,
-                        hipStream_t s) {
+                        double force_scale, const int32_t* subs, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
   if (storage_f64)
     hipLaunchKernelGGL(scale_kernel<double>, dim3(nsub), dim3(512), 0, s, p, g0, (double*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, 0, (int64_t)0, lbound, lb0_out,
-                       top0_out, x0s_out, pre_w ? 1 : 0);
+                       top0_out, x0s_out, pre_w ? 1 : 0, force_scale, subs);
   else
     hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off, lbound,
-                       lb0_out, top0_out, x0s_out, pre_w ? 1 : 0);
+                       lb0_out, top0_out, x0s_out, pre_w ? 1 : 0, force_scale, subs);
   return hipGetLastError();
 }
 

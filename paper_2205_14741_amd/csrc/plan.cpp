@@ -44,8 +44,8 @@ int ws_storage(const sm_sign_opts* o) {
 
 bool valid_storage(int storage) { return storage >= SM_F64 && storage <= SM_BF16X3; }
 
-static_assert(sizeof(sm_sign_opts) == 96, "sm_sign_opts layout");
-static_assert(sizeof(sm_sub_stats) == 144, "sm_sub_stats layout");
+static_assert(sizeof(sm_sign_opts) == 104, "sm_sign_opts layout");
+static_assert(sizeof(sm_sub_stats) == 152, "sm_sub_stats layout");
 
 static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
@@ -105,6 +105,7 @@ int sm_default_opts(int32_t prec, sm_sign_opts* o) {
   o->probes = 2;
   o->variant = -1;
   o->graph_iters = 0;
+  o->retry = 1;
   if (prec == SM_F64) {
     o->refine_steps = 0;
     o->refine = SM_F64;
@@ -169,6 +170,10 @@ int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_
       h += p->bs[r];
     }
     if (loc < 0) { delete p; return set_error(SM_ERR_ARG, "sm_plan_create: diagonal block of column %d missing", c); }
+    if (h > 32767) {
+      delete p;
+      return set_error(SM_ERR_ARG, "sm_plan_create: block column %d has %d rows; at most 32767 are supported", c, h);
+    }
     p->height[c] = h;
     p->loc[c] = loc;
     p->npad[c] = (int32_t)((h + pad_to - 1) / pad_to * pad_to);

@@ -11,6 +11,7 @@ constexpr int kHostWords = 64;
 constexpr int kHostCounts = 16;
 constexpr int kHostBracket = 32;   // two doubles
 constexpr int kHostNe = 36;        // one double
+constexpr int kHostRetry = 40;     // submatrices of a chunk queued for the fallback retry
 constexpr int kHostTrace = 10;     // E, Ne
 
 struct sm_plan {
@@ -63,6 +64,10 @@ struct sm_plan {
   int32_t* d_pinned = nullptr;      // the device's address of h_pinned
   hipEvent_t ev[2] = {nullptr, nullptr};
   int last_storage = -1;            // workspace storage of the last build (ws_storage; -1: none)
+  // the last build_submatrices call (the fallback retry builds again from it)
+  int last_chunk = -1;
+  const double* last_H = nullptr;
+  double last_mu = 0.0;
   int32_t tuned[5] = {0, 0, 0, 0, 0};  // GEMM variant per precision (sm_autotune)
   // captured iteration graphs (sm_sign_opts.graph_iters)
   struct GraphEntry {

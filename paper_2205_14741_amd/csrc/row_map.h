@@ -7,13 +7,24 @@
 
 namespace sm {
 
+// Row-map entries are panel rows of H (< 32768: sm_plan_create refuses taller
+// panels), held as 16 bits so that four maps of the largest submatrices fit
+// the LDS of a workgroup.
+typedef int16_t RowSrc;
+
+// LDS bytes of the atoms and row offsets of an index set of m atoms followed
+// by `maps` row maps of n_pad entries, rounded up to 8 bytes.
+__host__ __device__ inline size_t row_maps_bytes(int m, int maps, int npad) {
+  return ((size_t)2 * m * sizeof(int) + (size_t)maps * npad * sizeof(RowSrc) + 7) & ~(size_t)7;
+}
+
 // For atom j of the index set (one block column of T_i): s_src[d] = the row
 // of H's panel j that supplies row d of T_i, or -1 where the block (atom of
 // row d, j) is not stored.  s_atom / s_off: the atoms of I_i (ascending) and
 // their row offsets in T_i (m of them).  One wavefront builds the map; the
 // caller orders it against the map's readers (wave_sync).
 __device__ __forceinline__ void build_row_map(const DevPlan& p, int j, const int* s_atom, const int* s_off,
-                                              int m, int n, int* s_src) {
+                                              int m, int n, RowSrc* s_src) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t kj0 = p.col_ptr[j];
   const int mj = (int)(p.col_ptr[j + 1] - kj0);
@@ -30,7 +41,7 @@ __device__ __forceinline__ void build_row_map(const DevPlan& p, int j, const int
       const int dst = s_off[lo];
       const int src = p.blk_rowoff[kj0 + t];
       const int bk = p.bs[k];
-      for (int q = 0; q < bk; ++q) s_src[dst + q] = src + q;
+      for (int q = 0; q < bk; ++q) s_src[dst + q] = (RowSrc)(src + q);
     }
   }
   wave_sync();

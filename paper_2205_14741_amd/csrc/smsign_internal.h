@@ -57,6 +57,11 @@ struct SubState {
   double alpha_upd;
   double lb_est;       // plain runs: lower bound on the smallest |eigenvalue| of X_0
   double x0s;          // X_0 = x0s * (buffer 0 as built): 1 / c except for float64 (1)
+  double a0;           // scale of the first update (below 1 only where the top of the
+                       // spectrum of X_0 could exceed sqrt 3 / 1.01; plain runs too)
+  double res_last;     // residual of the last square (a slab square: its columns' part)
+  int32_t cap_hit;     // 1: the main phase ended because max_iter was reached
+  int32_t retried;     // 1: this run is the fallback retry (sm_sign_opts.retry)
 };
 
 // One output tile of a Newton-Schulz GEMM launch, written by expand_kernel so
@@ -119,10 +124,11 @@ struct WsLayout {
 // power_vecs (may be null): also w = T v0, the first power-iteration product
 // of the scale kernel, into each submatrix's vectors (the scale kernel is then
 // launched with pre_w).
+// subs (may be null): build only these local indices (nsub of them).
 hipError_t launch_gather(const DevPlan& p, int g0, int nsub, int max_m, int max_npad,
                          const double* H, double mu, void* mats, int storage_f64, int shadow_kind,
                          int64_t shadow_off, int* nonfinite, float* features, double* cg_out,
-                         sm_sub_stats* stats, double* power_vecs, hipStream_t s);
+                         sm_sub_stats* stats, double* power_vecs, const int32_t* subs, hipStream_t s);
 // Dynamic LDS bytes of the gather (with the power-product rows or without).
 size_t gather_lds_bytes(int max_m, int max_npad, bool power);
 // shadow_kind / shadow_off: where T_i is (as for the gather).  lbound:
@@ -135,8 +141,13 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
                         int power_steps, double margin, double* vecs, const double* cg_in,
                         const float* pred, sm_sub_stats* stats, int shadow_kind, int64_t shadow_off,
                         double lbound, double* lb0_out, double* top0_out, double* x0s_out, bool pre_w,
-                        hipStream_t s);
-// first != 0 initialises the iteration state; lb0 / top0 [nsub] (may be null):
+                        double force_scale, const int32_t* subs, hipStream_t s);
+// The local indices of the chunk's submatrices with status 0 or -1 (list) and
+// their number (count, one word, may be host-mapped).
+hipError_t launch_collect_failed(int nsub, const SubState* st, int32_t* list, int32_t* count, hipStream_t s);
+// first == 1 initialises the iteration state of every submatrix; first == 2
+// (the fallback retry) only that of the submatrices whose status is 0 or -1,
+// leaving the others finished; lb0 / top0 [nsub] (may be null):
 // bounds on the smallest / largest |eigenvalue| of X_0 (scaled Newton-Schulz);
 // x0s [nsub] (may be null: 1): SubState.x0s;
 // live_host (may be null): device-mapped host words that receive the number

@@ -48,7 +48,8 @@ class SignOpts(C.Structure):
                 ("stall_below", C.c_double), ("stall_ratio", C.c_double), ("scaling", C.c_int32),
                 ("power_steps", C.c_int32), ("scale_margin", C.c_double), ("probes", C.c_int32),
                 ("variant", C.c_int32), ("graph_iters", C.c_int32), ("accel", C.c_int32),
-                ("lbound", C.c_double), ("comm_probes", C.c_int32), ("reserved", C.c_int32)]
+                ("lbound", C.c_double), ("comm_probes", C.c_int32), ("retry", C.c_int32),
+                ("force_scale", C.c_double)]
 
     def copy(self) -> "SignOpts":
         o = SignOpts()
@@ -61,17 +62,18 @@ class SubStats(C.Structure):
                 ("scale_src", C.c_int32), ("scale", C.c_double), ("res", C.c_double),
                 ("res_probe", C.c_double), ("gersh", C.c_double), ("rho_est", C.c_double),
                 ("lb0", C.c_double), ("lb_est", C.c_double), ("res_comm", C.c_double),
-                ("feat", C.c_float * 16)]
+                ("feat", C.c_float * 16), ("retried", C.c_int32), ("reserved", C.c_int32)]
 
 
 STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"),
                         ("scale_src", "<i4"), ("scale", "<f8"), ("res", "<f8"),
                         ("res_probe", "<f8"), ("gersh", "<f8"), ("rho_est", "<f8"),
-                        ("lb0", "<f8"), ("lb_est", "<f8"), ("res_comm", "<f8"), ("feat", "<f4", (16,))])
+                        ("lb0", "<f8"), ("lb_est", "<f8"), ("res_comm", "<f8"), ("feat", "<f4", (16,)),
+                        ("retried", "<i4"), ("reserved", "<i4")])
 STATS_FEAT_OFFSET = 80   # bytes from the start of a record to feat[0]
-assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 144
+assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 152
 assert STATS_DTYPE.fields["feat"][1] == STATS_FEAT_OFFSET
-assert C.sizeof(SignOpts) == 96
+assert C.sizeof(SignOpts) == 104
 
 _lib = None
 

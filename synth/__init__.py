@@ -18,6 +18,7 @@ from .systems import (  # noqa: F401
     config5_step,
     union,
     to_dense,
+    with_onsite_shift,
     fully_coupled_lattice,
     from_pairs,
     keyed_normals,

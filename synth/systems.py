@@ -47,7 +47,7 @@ import numpy as np
 __all__ = [
     "BlockSparse", "lattice_system", "water_system", "config1", "config2",
     "config3", "config4", "config5_step", "union", "to_dense",
-    "fully_coupled_lattice", "from_pairs", "keyed_normals",
+    "fully_coupled_lattice", "from_pairs", "keyed_normals", "with_onsite_shift",
 ]
 
 
@@ -462,3 +462,16 @@ def from_pairs(block_size, pairs, blocks, onsite, n_occ, name="custom") -> Block
     pos = np.zeros((bs.shape[0], 3))
     return _assemble(bs, pi, pj, flat, poff, np.asarray(onsite, dtype=np.float64), pos,
                      None, n_occ, name, dict(kind="custom", atom_ranges=[(0, bs.shape[0])]))
+
+
+def with_onsite_shift(m: BlockSparse, atom: int, orbital: int, shift: float) -> BlockSparse:
+    """A copy of ``m`` with ``shift`` added to the diagonal entry of one orbital
+    (an isolated state far from the rest of the spectrum, e.g. +20 on one
+    orbital of a lattice system: it stretches the Gershgorin bracket and the
+    spectral radius of every submatrix that contains the atom)."""
+    rows = m.row_idx[m.col_ptr[atom]:m.col_ptr[atom + 1]]
+    h = int(m.block_size[rows].sum())
+    loc = int(m.block_size[rows[rows < atom]].sum())
+    vals = m.vals.copy()
+    vals[m.panel_off[atom] + orbital * h + loc + orbital] += shift
+    return m.with_vals(vals, name=f"{m.name}+shift({atom},{orbital},{shift:g})")

@@ -1,0 +1,191 @@
+"""Robustness of the sign engine against bad scales, failed iterations and
+large index sets, through the C ABI, each case against the oracle.
+
+* the first step of every schedule maps the top of the spectrum of X_0 to at
+  most sqrt 3 / 1.01: a learned scale below rho / sqrt 3 that the power guard
+  cannot refute must not flip eigenvalues (a plain step sends x in
+  (sqrt 3, sqrt 5) to the wrong sign without any residual noticing);
+* a submatrix whose main phase runs out of iterations reports status 0, also
+  when refinement steps follow;
+* a diverging iteration is flagged (status -1) and, with opts.retry, built and
+  iterated again with the fallback schedule;
+* the chemical-potential bisection reproduces the oracle's midpoints and
+  electron counts where the first midpoint misses the gap;
+* index sets larger than 4096 orbitals go through the gather.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import submatrix as om
+from paper_2205_14741_amd import smsign as sm
+from gpu_helpers import run_fixed_mu, gap_mu, rel, h_dev
+
+pytestmark = pytest.mark.gpu
+
+N_PARAMS = 5378
+
+
+def constant_net(y0, y1):
+    """A scaling network whose output is (y0, y1) for every input: the last
+    layer's weights are zero and its bias is (y0, y1)."""
+    net = sm.Mlp(seed=0)
+    theta = np.zeros(N_PARAMS, dtype=np.float32)
+    theta[-2:] = (y0, y1)
+    net.set_weights(theta, np.concatenate([np.zeros(16), np.ones(16)]).astype(np.float32))
+    return net
+
+
+def outlier_lattice():
+    """4x4x4 lattice (config 1) with one orbital of atom 0 pushed to +20: the
+    19 submatrices that contain atom 0 have a spectral radius near 20, the
+    others near 2.5."""
+    return synth.with_onsite_shift(synth.config1(), 0, 3, 20.0)
+
+
+def _rho(m, mu):
+    v = om.BlockView(m)
+    return np.array([np.max(np.abs(np.linalg.eigvalsh(om.submatrix(v, i, mu)))) for i in range(m.n_atoms)])
+
+
+@pytest.mark.parametrize("accel", [0, 1])
+def test_learned_scale_below_rho_over_sqrt3_is_capped(accel, dev):
+    """A network that predicts c = 0.45 c_G for every submatrix, with a
+    one-step power guard: on the submatrices holding the +20 state the guard
+    (estimate ~ a few units) accepts c ~ 10, so X_0 has an eigenvalue near 2,
+    inside (sqrt 3, sqrt 5).  P must still match the oracle."""
+    m = outlier_lattice()
+    mu = gap_mu(m)
+    net = constant_net(np.log(0.45 / 1.05), np.log(1e-3))
+    plan = sm.Plan(m, 64)
+    sm.sm_plan_set_mlp(plan, net)
+    o = sm.default_opts("f64", scaling=sm.SM_SCALE_LEARNED, power_steps=1, scale_margin=0.05, accel=accel,
+                        retry=0)
+    P, E, Ne, st, _ = run_fixed_mu(m, mu, opts=o, plan=plan)
+    rho = _rho(m, mu)
+    top = rho / st["scale"]
+    risky = (st["scale_src"] == 2) & (top > np.sqrt(3.0))
+    print(f"accel {accel}: {risky.sum()} accepted scales with rho / c in "
+          f"({top[risky].min() if risky.any() else 0:.2f}, {top[risky].max() if risky.any() else 0:.2f})")
+    assert risky.sum() >= 5
+    assert np.all(top[risky] < np.sqrt(5.0))   # the silent wrong-sign range, not divergence
+    Po = om.density_matrix(m, mu)
+    assert np.max(np.abs(P - Po)) < 1e-9
+    assert np.all(st["status"] == 1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16x3"])
+def test_max_iter_reports_status_zero(prec, dev):
+    """Two updates are far too few: status 0 for every submatrix, for the
+    split-bf16 schedule also after its float32 refinement steps; with the
+    retry the fallback run (four updates) fails again and says so."""
+    m = synth.water_system(16, 1.5, 3)
+    mu = gap_mu(m)
+    for retry in (0, 1):
+        o = sm.default_opts(prec, max_iter=2, retry=retry)
+        P, E, Ne, st, _ = run_fixed_mu(m, mu, opts=o)
+        assert np.all(st["status"] == 0), np.unique(st["status"])
+        assert np.all(st["retried"] == retry)
+        assert np.all(st["iters_low"] <= 2 * (1 + retry))
+
+
+@pytest.mark.parametrize("prec,dp_max", [("f64", 1e-9), ("bf16x3", 1e-4)])
+def test_forced_underscale_diverges_and_falls_back(prec, dp_max, dev):
+    """c = 0.1 c_G with the bound withheld: X_0 has eigenvalues well above
+    sqrt 5, the iteration diverges and is flagged; with the retry (the
+    default) every submatrix is built again with the Gershgorin scale and P
+    matches the oracle."""
+    m = synth.config1()
+    mu = gap_mu(m)
+    o = sm.default_opts(prec, force_scale=0.1, retry=0)
+    _, _, _, st, _ = run_fixed_mu(m, mu, opts=o)
+    assert np.all(st["status"] == -1), np.unique(st["status"])
+    assert np.all(st["scale_src"] == 4)
+    o = sm.default_opts(prec, force_scale=0.1)
+    P, E, Ne, st, _ = run_fixed_mu(m, mu, opts=o)
+    assert np.all(st["retried"] == 1)
+    assert np.all(st["status"] >= 1)
+    assert np.all(st["scale_src"] == 0)
+    Po = om.density_matrix(m, mu)
+    assert np.max(np.abs(P - Po)) < dp_max
+
+
+def test_retry_leaves_converged_submatrices_alone(dev):
+    """With nothing failing, the retry changes nothing: P and E are bitwise
+    those of a run without it."""
+    m = synth.config1()
+    mu = gap_mu(m)
+    P0, E0, _, st0, _ = run_fixed_mu(m, mu, opts=sm.default_opts("f64", retry=0))
+    P1, E1, _, st1, _ = run_fixed_mu(m, mu, opts=sm.default_opts("f64", retry=1))
+    assert np.all(st1["retried"] == 0)
+    np.testing.assert_array_equal(P0, P1)
+    assert E0 == E1
+
+
+@pytest.mark.parametrize("make", [
+    lambda: synth.with_onsite_shift(synth.config1(), 0, 3, 20.0),
+    lambda: synth.with_onsite_shift(synth.config2(), 5, 4, 40.0),
+], ids=["config1+state", "config2+state"])
+def test_find_mu_history_matches_oracle(make, dev):
+    """The bisection of the GPU path and of the oracle take the same
+    decisions: the same number of midpoints (four or more, both lo and hi
+    moved), each midpoint to 1e-12 and each electron count to 1e-8."""
+    m = make()
+    mu_o, steps_o, hist_o = om.find_mu(m, m.n_occ)
+    assert steps_o >= 4
+    plan = sm.Plan(m, 32)
+    o = sm.default_opts("f64", max_iter=60)
+    H = h_dev(m)
+    work = sm.Workspace(plan, sm.SM_F64, H.device)
+    mu, steps, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats)[:3]
+    print(" ".join(f"({a:.4f}, {na:.3f})" for a, na in hist))
+    assert steps == steps_o
+    for (a, na), (b, nb) in zip(hist, hist_o):
+        assert abs(a - b) < 1e-12 * max(1.0, abs(b)) and abs(na - nb) < 1e-8
+    assert any(nb < m.n_occ - 0.5 for _, nb in hist_o) and any(nb > m.n_occ + 0.5 for _, nb in hist_o)
+
+
+@pytest.mark.parametrize("prec,dp_max", [("f64", 1e-9), ("bf16x3", 1e-4)])
+def test_index_set_above_4096_orbitals(prec, dp_max, dev):
+    """Two atoms of 2100 orbitals each, fully coupled: both submatrices are the
+    whole matrix (n = 4200, n_pad 4224 > 4096), so both P block columns are
+    the exact projector's (fully coupled case)."""
+    rng = np.random.default_rng(7)
+    b = 2100
+    onsite = np.where(np.arange(2 * b) % 2 == 0, -6.0, 6.0) + rng.normal(0.0, 0.3, 2 * b)
+    C = rng.normal(0.0, 0.02, size=(b, b))
+    m = synth.from_pairs([b, b], [(0, 1)], [C], onsite, n_occ=b)
+    lam, V = np.linalg.eigh(synth.to_dense(m))
+    mu = 0.5 * (lam[b - 1] + lam[b])
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=64)
+    assert plan.info()["npad"].min() > 4096
+    Pd = synth.to_dense(m.with_vals(P))
+    Vo = V[:, :b]
+    Pexact = Vo @ Vo.T
+    dP = float(np.max(np.abs(Pd - Pexact)))
+    print(f"{prec}: n = {2 * b}, max|dP| {dP:.2e}, iters {st['iters']}")
+    assert dP < dp_max
+    assert rel(E, float(np.sum(lam[:b]))) < (1e-11 if prec == "f64" else 1e-5)   # the workload tolerance
+
+
+def test_retry_reruns_only_the_failed(dev):
+    """With a cap of 11 updates the submatrices that hold the +20 state (their
+    Gershgorin scale is ~8x that of the others, so their smallest eigenvalues
+    start ~8x closer to 0) run out of iterations and the others converge.
+    The retry runs exactly the failed ones again (22 updates) and leaves the
+    others' results untouched; P then matches the oracle everywhere."""
+    m = outlier_lattice()
+    mu = gap_mu(m)
+    P0, _, _, st0, _ = run_fixed_mu(m, mu, opts=sm.default_opts("f64", max_iter=11, retry=0))
+    failed = st0["status"] == 0
+    print(f"{failed.sum()} of {m.n_atoms} submatrices hit the cap")
+    assert 0 < failed.sum() < m.n_atoms
+    P1, _, _, st1, _ = run_fixed_mu(m, mu, opts=sm.default_opts("f64", max_iter=11, retry=1))
+    np.testing.assert_array_equal(st1["retried"] == 1, failed)
+    assert np.all(st1["status"] == 1)
+    Po = om.density_matrix(m, mu)
+    assert np.max(np.abs(P1 - Po)) < 1e-9
+    # block columns of the submatrices that converged the first time: bitwise equal
+    for i in np.nonzero(~failed)[0]:
+        a, b = m.panel_off[i], m.panel_off[i + 1]
+        np.testing.assert_array_equal(P1[a:b], P0[a:b])

@@ -212,6 +212,55 @@ def test_electron_count_two_routes_and_monotone():
         assert abs(Ne - cache.ne(mu)) < 1e-10
 
 
+def test_gershgorin_bracket_three_site_chain():
+    """H = [[-1, t, 0], [t, 1, t], [0, t, -1]], t = 3/4: the row intervals are
+    [-1.75, -0.25], [-0.5, 2.5], [-1.75, -0.25], so the bracket is
+    [-1.75, 2.5].  (With |h_pp| wrongly counted in the radius it would be
+    [-2.75, 3.5].)"""
+    g = json.load(open(os.path.join(GOLDEN, "three_site_chain.json")))
+    t = g["t"]
+    m = synth.from_pairs([1, 1, 1], [(0, 1), (1, 2)], [np.array([[t]]), np.array([[t]])],
+                         g["onsite"], n_occ=2)
+    assert om.global_gershgorin_bracket(m) == (-1.75, 2.5)
+
+
+def test_gershgorin_bracket_two_atoms_closed_form():
+    """Two atoms of two orbitals, onsite diagonals (2, -1) and (1/4, 3),
+    coupling block C = [[1, -2], [1/2, 0]] (rows: atom 0's orbitals):
+        H = [[ 2,   0,   1,   -2],
+             [ 0,  -1,   1/2,  0],
+             [ 1,   1/2, 1/4,  0],
+             [-2,   0,   0,    3]]
+    Row intervals h_pp -+ R_p: [-1, 5], [-1.5, -0.5], [-1.25, 1.75], [1, 5],
+    so the bracket is [-1.5, 5].  A transposed coupling block would give row 2
+    the radius 3 and the bracket [-2.75, 5]; |h_pp| in the radius would give
+    [-4, 8]."""
+    C = np.array([[1.0, -2.0], [0.5, 0.0]])
+    m = synth.from_pairs([2, 2], [(0, 1)], [C], [2.0, -1.0, 0.25, 3.0], n_occ=2)
+    assert om.global_gershgorin_bracket(m) == (-1.5, 5.0)
+
+
+def test_find_mu_history_with_outlier_state():
+    """An isolated high state (one orbital pushed to +20) stretches the
+    Gershgorin bracket upwards, so the first midpoints fall above the gap and
+    the bisection has to move hi down several times before it lands in the gap:
+    the lo / hi update is exercised, and every midpoint is the centre of the
+    bracket the previous decisions leave."""
+    m = synth.with_onsite_shift(synth.config1(), 0, 3, 20.0)
+    lam = np.linalg.eigvalsh(synth.to_dense(m))
+    mu, steps, hist = om.find_mu(m, m.n_occ)
+    assert steps >= 4
+    assert lam[m.n_occ - 1] < mu < lam[m.n_occ]
+    lo, hi = om.global_gershgorin_bracket(m)
+    for mid, ne in hist:
+        assert mid == 0.5 * (lo + hi)
+        if ne < m.n_occ:
+            lo = mid
+        else:
+            hi = mid
+    assert any(ne < m.n_occ - 0.5 for _, ne in hist) or any(ne > m.n_occ + 0.5 for _, ne in hist[:-1])
+
+
 def test_find_mu_config1_lands_in_gap():
     m = synth.config1()
     lam = np.linalg.eigvalsh(synth.to_dense(m))
@@ -257,6 +306,28 @@ def test_newton_schulz_reaches_the_eigh_sign(n):
     X, k, hist = ons.ns_sign(T, om.gershgorin_bound(T), tol=1e-10)
     assert hist[-1] < 1e-10
     np.testing.assert_allclose(X, (Q * np.sign(lam)) @ Q.T, atol=1e-11)
+
+
+@pytest.mark.parametrize("d,tol,expect", [
+    # one entry x_0 = 1/2 (d = 1, c = 2).  Hand enumeration of the scalar map
+    # g(x) = x (3 - x^2) / 2 in exact fractions:
+    #   x_0 = 1/2            r_0 = 3/4                 = 0.75
+    #   x_1 = 11/16          r_1 = 135/256             = 0.52734375
+    #   x_2 = 7117/8192      r_2 = 16457175/67108864   ~ 0.24523
+    #   x_3 ~ 0.97530        r_3                       ~ 0.0488
+    ([1.0], 0.8, 0), ([1.0], 0.6, 1), ([1.0], 0.3, 2), ([1.0], 0.1, 3),
+    # two entries +-1/2: the residual is the Frobenius norm sqrt(2) |x_k^2 - 1|
+    # (r_0 ~ 1.0607, r_1 ~ 0.7458, r_2 ~ 0.3468, r_3 ~ 0.069).  tol 0.3 tells
+    # the Frobenius norm (3) from the largest entry (which would give 2).
+    ([1.0, -1.0], 1.1, 0), ([1.0, -1.0], 0.75, 1), ([1.0, -1.0], 0.35, 2), ([1.0, -1.0], 0.3, 3),
+])
+def test_scalar_iteration_count_hand_enumerated(d, tol, expect):
+    assert ons.ns_scalar_iterations(np.array(d), 2.0, tol=tol) == expect
+
+
+def test_scalar_iteration_count_cap():
+    assert ons.ns_scalar_iterations(np.array([1.0]), 2.0, tol=0.0, max_iter=3) == 3
+    assert ons.ns_scalar_iterations(np.array([2.0, -2.0]), 2.0, tol=1e-12) == 0
 
 
 def test_newton_schulz_diagonal_iteration_count():
