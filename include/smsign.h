@@ -310,6 +310,19 @@ int sm_find_mu(sm_plan* plan, const double* H_vals, double n_target, double acce
 int sm_gershgorin_bracket(sm_plan* plan, const double* H_vals, double* lo, double* hi,
                           void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): sm_gershgorin_bracket without any
+ * allocation or synchronisation.  lohi (device, 2 doubles) receives [lo, hi];
+ * the per-atom intervals go to a fixed device scratch of the library (room for
+ * 524288 atoms, 8 MiB, one copy per GPU, held until the process ends) instead
+ * of the plan's own table.  The plan must already hold its device tables (any
+ * earlier device call with it, e.g. sm_gershgorin_bracket; SM_ERR_STATE
+ * otherwise) on the current device.  SM_ERR_ARG for a plan of more than
+ * 524288 atoms.  Asynchronous on `stream`.  All calls on one GPU share its
+ * scratch: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must be ordered by the caller. */
+int sm_gershgorin_bracket_noalloc(const sm_plan* plan, const double* H_vals, double* lohi, void* stream);
+
 /* Workspace layout, for inspection by tests: region offsets in bytes
  *   regions9 = [matrices, state, partials, lists, features, scratch, vecs, flag, total]
  * and, per processing index g, the element offset of submatrix order[g]'s three

@@ -490,6 +490,23 @@ int sm_gershgorin_bracket(sm_plan* p, const double* H, double* lo, double* hi, v
   return SM_OK;
 }
 
+int sm_gershgorin_bracket_noalloc(const sm_plan* p, const double* H, double* lohi, void* stream) {
+  if (!p || !H || !lohi) return set_error(SM_ERR_ARG, "sm_gershgorin_bracket_noalloc: null argument");
+  if (p->n_atoms > kNoAllocMaxAtoms)
+    return set_error(SM_ERR_ARG, "sm_gershgorin_bracket_noalloc: %d atoms exceed the fixed scratch of %d atoms",
+                     p->n_atoms, kNoAllocMaxAtoms);
+  if (p->device < 0)
+    return set_error(SM_ERR_STATE, "sm_gershgorin_bracket_noalloc: the plan has no device tables yet "
+                                   "(make one device call with it first, e.g. sm_gershgorin_bracket)");
+  int dev = -1;
+  SM_HIP(hipGetDevice(&dev));
+  if (dev != p->device)
+    return set_error(SM_ERR_STATE, "sm_gershgorin_bracket_noalloc: plan lives on device %d, device %d is current",
+                     p->device, dev);
+  SM_HIP(launch_gersh_rows_noalloc(p->dev, p->n_atoms, H, lohi, as_stream(stream)));
+  return SM_OK;
+}
+
 int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int32_t max_steps,
                const sm_sign_opts* o, void* ws, double* P, sm_sub_stats* stats, double* mu_out,
                int32_t* steps_out, double* mu_hist, double* ne_hist, double* E_out, double* Ne_out,

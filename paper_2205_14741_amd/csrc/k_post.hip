@@ -3,6 +3,8 @@
 // and the float64 reductions tr(PH), tr P of Eq. 14's density matrix.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_common.h"
 #include "row_map.h"
 #include "smsign_internal.h"
@@ -436,6 +438,50 @@ hipError_t launch_gersh_rows(const DevPlan& p, int n_atoms, const double* H, dou
   hipLaunchKernelGGL(gersh_kernel, dim3(n_atoms), dim3(256), 0, s, p, H, lohi_parts);
   hipLaunchKernelGGL(gersh_final_kernel, dim3(1), dim3(256), 0, s, lohi_parts, n_atoms, out2);
   return hipGetLastError();
+}
+
+// Fixed scratch of the allocation-free bracket (sm_gershgorin_bracket_noalloc):
+// the per-atom intervals of at most kNoAllocMaxAtoms atoms (8 MiB).  Every GPU
+// the library runs on holds its own copy of the array until the process ends.
+// In host code `scratch` names a host-side stand-in, not the device array:
+// the device address comes from hipGetSymbolAddress, once per device, and is
+// the only form in which host code passes the array on.
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxAtoms];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, then kept).
+static hipError_t noalloc_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    double* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_gersh_rows_noalloc(const DevPlan& p, int n_atoms, const double* H, double* out2,
+                                     hipStream_t s) {
+  if (n_atoms < 1 || n_atoms > kNoAllocMaxAtoms) return hipErrorInvalidValue;
+  double* lohi = nullptr;
+  const hipError_t e = noalloc_scratch(&lohi);
+  if (e != hipSuccess) return e;
+  // the kernels write every one of the 2 n_atoms entries before reading it:
+  // nothing of an earlier call's contents is used
+  return launch_gersh_rows(p, n_atoms, H, lohi, out2, s);
 }
 
 // Electron count sum_i ne_i in a fixed order with compensation (Neumaier):

@@ -207,6 +207,12 @@ hipError_t launch_ne_from_x(const DevPlan& p, int g0, int nsub, const void* mats
 // their hull out2 = [lo, hi] (one thread writes: out2 may be host-mapped).
 hipError_t launch_gersh_rows(const DevPlan& p, int n_atoms, const double* H, double* lohi_parts,
                              double* out2, hipStream_t s);
+// The same into out2 (device memory), with the per-atom intervals in the
+// library's fixed device scratch instead of lohi_parts: allocates nothing.
+// hipErrorInvalidValue for n_atoms outside [1, kNoAllocMaxAtoms].
+constexpr int kNoAllocMaxAtoms = 1 << 19;
+hipError_t launch_gersh_rows_noalloc(const DevPlan& p, int n_atoms, const double* H, double* out2,
+                                     hipStream_t s);
 // out[0] = compensated sum of ne_sub[0 .. n_atoms) in a fixed order (one
 // thread writes: out may be host-mapped).
 hipError_t launch_ne_sum(const double* ne_sub, int n_atoms, double* out, hipStream_t s);

@@ -27,7 +27,7 @@ EXPORTED = (
     "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
     "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
-    "sm_comm_probe",
+    "sm_comm_probe", "sm_gershgorin_bracket_noalloc",
 )
 
 
@@ -103,6 +103,7 @@ def lib() -> C.CDLL:
         "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
                              vp]),
         "sm_gershgorin_bracket": (i32, [vp, vp, vp, vp, vp]),
+        "sm_gershgorin_bracket_noalloc": (i32, [vp, vp, vp, vp]),
         "sm_selftest_mfma": (i32, [i32, vp]),
         "sm_profile_enable": (i32, [vp, i32]),
         "sm_profile_read": (i32, [vp, vp, vp]),
@@ -291,6 +292,12 @@ def sm_gershgorin_bracket(plan: Plan, H, stream=None):
     lo, hi = C.c_double(), C.c_double()
     _check(lib().sm_gershgorin_bracket(plan.handle, _ptr(H), C.byref(lo), C.byref(hi), _stream(stream)))
     return lo.value, hi.value
+
+
+def sm_gershgorin_bracket_noalloc(plan: Plan, H, lohi, stream=None):
+    """[lo, hi] into the device tensor lohi (2 float64), allocating nothing;
+    asynchronous."""
+    _check(lib().sm_gershgorin_bracket_noalloc(plan.handle, _ptr(H), _ptr(lohi), _stream(stream)))
 
 
 def sm_selftest_mfma(prec) -> np.ndarray:

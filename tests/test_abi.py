@@ -141,3 +141,14 @@ def test_default_opts():
     assert sm.storage_prec(sm.default_opts("f32")) == sm.SM_F32
     with pytest.raises(sm.SmError):
         sm.default_opts(9)
+
+
+def test_noalloc_bracket_rejects_plans_beyond_its_scratch():
+    """More atoms than the fixed scratch holds: a clear error before any
+    device work (this runs without a GPU)."""
+    n = (1 << 19) + 1
+    m = synth.from_pairs([1] * n, [], [], np.zeros(n), n_occ=0)
+    plan = sm.Plan(m, 32)
+    rc = sm.lib().sm_gershgorin_bracket_noalloc(plan.handle, 8, 8, None)
+    assert rc == -1
+    assert b"exceed the fixed scratch" in sm.lib().sm_last_error()
