@@ -226,24 +226,29 @@ def global_gershgorin_bracket(m):
 
 
 def find_mu(m, n_target: float, max_steps: int = 60, accept: float = 0.5,
-            cache: SpectralCache | None = None):
-    """Bisection for mu: start from the global Gershgorin bracket, take
-    midpoints, stop at the first midpoint with |Ne(mu) - n_target| < accept,
-    else after ``max_steps`` midpoints.  Returns (mu, steps, history)."""
+            cache: SpectralCache | None = None, mu_start: float | None = None):
+    """Bisection for mu (Eq. 14 leaves the rule open): start from the global
+    Gershgorin bracket, take midpoints, stop at the first midpoint with
+    |Ne(mu) - n_target| < accept, else after ``max_steps`` evaluations.
+
+    ``mu_start`` (a warm start, e.g. the previous geometry's mu) replaces the
+    first midpoint: Ne is evaluated there first and, if it is not accepted, it
+    becomes the lower or upper end of the bracket (kept inside the Gershgorin
+    bracket) before the midpoints continue.  Returns (mu, steps, history)."""
     cache = cache or SpectralCache(m)
     lo, hi = global_gershgorin_bracket(m)
     hist = []
     mid = 0.5 * (lo + hi)
     for step in range(1, max_steps + 1):
-        mid = 0.5 * (lo + hi)
+        mid = mu_start if (step == 1 and mu_start is not None) else 0.5 * (lo + hi)
         ne = cache.ne(mid)
         hist.append((mid, ne))
         if abs(ne - n_target) < accept:
             return mid, step, hist
         if ne < n_target:
-            lo = mid
+            lo = min(max(lo, mid), hi)
         else:
-            hi = mid
+            hi = max(min(hi, mid), lo)
     return mid, max_steps, hist
 
 

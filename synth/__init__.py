@@ -17,6 +17,7 @@ from .systems import (  # noqa: F401
     config4,
     config5_step,
     union,
+    overlap_for,
     to_dense,
     with_onsite_shift,
     fully_coupled_lattice,

@@ -475,3 +475,44 @@ def with_onsite_shift(m: BlockSparse, atom: int, orbital: int, shift: float) -> 
     vals = m.vals.copy()
     vals[m.panel_off[atom] + orbital * h + loc + orbital] += shift
     return m.with_vals(vals, name=f"{m.name}+shift({atom},{orbital},{shift:g})")
+
+
+# ----------------------------------------------------------------------------
+# overlap matrices (non-orthogonal basis)
+# ----------------------------------------------------------------------------
+
+def overlap_for(m: BlockSparse, seed: int = 0, strength: float = 0.5, decay: float = 2.0,
+                max_row_sum: float = 0.6) -> BlockSparse:
+    """A synthetic overlap matrix S on the same block pattern as ``m``:
+    identity onsite blocks, pair blocks strength * exp(-decay r) * U(-0.2, 1)
+    (r the minimum-image distance of the two atoms), symmetric.  If the
+    largest off-diagonal absolute row sum exceeds ``max_row_sum`` all pair
+    blocks are scaled down to it, so every eigenvalue of S (and of every
+    principal submatrix) lies in [1 - max_row_sum, 1 + max_row_sum]."""
+    rng = np.random.default_rng([seed, 0x5EED])
+    bs = np.asarray(m.block_size, dtype=np.int64)
+    cols = np.repeat(np.arange(m.n_atoms), np.diff(m.col_ptr))
+    rows = np.asarray(m.row_idx, dtype=np.int64)
+    keep = rows < cols
+    pi, pj = rows[keep], cols[keep]
+    order = np.lexsort((pj, pi))
+    pi, pj = pi[order], pj[order]
+    d = m.positions[pj] - m.positions[pi]
+    if m.box is not None:
+        d -= m.box * np.round(d / m.box)
+    r = np.sqrt((d ** 2).sum(1))
+    poff, sizes = _pair_offsets(bs, pi, pj)
+    vals = rng.uniform(-0.2, 1.0, size=int(poff[-1])) * np.repeat(strength * np.exp(-decay * r), sizes)
+    # largest absolute row sum over the pair blocks (rows of i from B_ij, of j from B_ij^T)
+    rs = np.zeros(int(bs.sum()))
+    off = np.zeros(m.n_atoms + 1, dtype=np.int64)
+    np.cumsum(bs, out=off[1:])
+    for k in range(pi.shape[0]):
+        B = np.abs(vals[poff[k]:poff[k + 1]]).reshape(bs[pi[k]], bs[pj[k]])
+        rs[off[pi[k]]:off[pi[k] + 1]] += B.sum(1)
+        rs[off[pj[k]]:off[pj[k] + 1]] += B.sum(0)
+    top = float(rs.max()) if rs.size else 0.0
+    if top > max_row_sum:
+        vals *= max_row_sum / top
+    return _assemble(bs, pi, pj, vals, poff, np.ones(int(bs.sum())), m.positions, m.box, m.n_occ,
+                     f"{m.name}:S", dict(m.meta, overlap_seed=seed))

@@ -261,6 +261,38 @@ def test_find_mu_history_with_outlier_state():
     assert any(ne < m.n_occ - 0.5 for _, ne in hist) or any(ne > m.n_occ + 0.5 for _, ne in hist[:-1])
 
 
+def test_find_mu_warm_start():
+    """Warm start: a guess inside the gap is accepted at once (one evaluation,
+    mu = the guess); the bracket's own midpoint as the guess reproduces the
+    cold history exactly; a guess below the gap (Ne short of the target)
+    becomes the lower end, so every later midpoint is the centre of
+    [guess, ...] and the search still ends in the gap; a guess outside the
+    Gershgorin bracket is clamped to it and changes nothing after step 1."""
+    m = synth.with_onsite_shift(synth.config1(), 0, 3, 20.0)
+    lam = np.linalg.eigvalsh(synth.to_dense(m))
+    cache = om.SpectralCache(m)
+    mu_c, steps_c, hist_c = om.find_mu(m, m.n_occ, cache=cache)
+    mu_w, steps_w, hist_w = om.find_mu(m, m.n_occ, cache=cache, mu_start=mu_c)
+    assert (mu_w, steps_w) == (mu_c, 1)
+    lo, hi = om.global_gershgorin_bracket(m)
+    assert om.find_mu(m, m.n_occ, cache=cache, mu_start=0.5 * (lo + hi)) == (mu_c, steps_c, hist_c)
+    g = lam[m.n_occ // 2]          # inside the occupied band: Ne(g) < n_occ - 0.5
+    mu_b, steps_b, hist_b = om.find_mu(m, m.n_occ, cache=cache, mu_start=g)
+    assert hist_b[0][0] == g and hist_b[0][1] < m.n_occ - 0.5
+    assert hist_b[1][0] == 0.5 * (g + hi)
+    assert lam[m.n_occ - 1] < mu_b < lam[m.n_occ]
+    a, b = g, hi
+    for mid, ne in hist_b[1:]:
+        assert mid == 0.5 * (a + b)
+        if ne < m.n_occ:
+            a = mid
+        else:
+            b = mid
+    # below the whole spectrum: Ne = 0, lo stays at the bracket's lo
+    mu_o, steps_o, hist_o = om.find_mu(m, m.n_occ, cache=cache, mu_start=lo - 100.0)
+    assert hist_o[0][1] == 0.0 and hist_o[1:] == hist_c
+
+
 def test_find_mu_config1_lands_in_gap():
     m = synth.config1()
     lam = np.linalg.eigvalsh(synth.to_dense(m))
