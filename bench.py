@@ -2,18 +2,25 @@
 """Throughput of the submatrix-method density matrix on one MI355X.
 
 One step = one pass of the whole hot path over the synthetic system: the
-chemical potential by bisection on tr P (each midpoint a full gather, scaling,
-batched Newton-Schulz sign and electron count on the GPU), P assembled at the
-accepted mu, then tr(PH) and tr P in float64.  The symbolic plan (once per
-sparsity pattern) and the input generation are outside the timed region; H is
-resident in HBM when timing starts.
+chemical potential checked by the bisection rule on tr P (warm-started at the
+previous step's mu, so a step whose mu is still accepted costs one pass: the
+gather, scaling with the learned guard, batched Newton-Schulz sign, electron
+count), P assembled at the accepted mu, then tr(PH) and tr P in float64.  The
+symbolic plan (once per sparsity pattern), the input generation, the cold mu
+search and the training of the scaling network are outside the timed region;
+H is resident in HBM when timing starts.
 
-Workload (default): 10x10x10 lattice, 3% vacancies, jitter N(0, 0.05),
-6 orbitals per atom (N = 5802, 967 submatrices of n = 192..276), cutoff 2.2,
-mu by bisection to half filling.  Each precision schedule is timed; the plain
-float64 path is the reference for the error of the others, and the headline
-value is the fastest schedule within 1e-5 relative energy and 1e-4 max |dP| of
-it.  Prints one JSON line.
+Workload (default, --config cfg3): 1000 water-like molecules at density 1
+(O 13, H 5 orbitals, N = 23000), cutoff 3.0: 3000 submatrices of n ~ 2340-2900,
+processed in chunks.  The headline schedule (split bf16 + float32 refinement,
+learned scale, scaled Newton-Schulz) is timed for --steps steps after --warmup
+untimed ones; the plain float64 GPU path is timed on the same system at the
+same mu (--ref-steps steps) as the reference for the speedup and for the
+error of P and E; the float64 oracle checks sampled submatrices.
+--config cfg4: the mixed batch of four water systems (250/500/1000/2000
+molecules, 11250 submatrices, n ~ 1300-4500).  --config cfg2: the 10x10x10
+lattice (967 submatrices of n = 192..276), every schedule timed.  Prints one
+JSON line.
 """
 from __future__ import annotations
 
@@ -50,7 +57,17 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--modes", default="f64,f32,bf16x3,f32+L,bf16x3+L")
+    ap.add_argument("--modes", default=None,
+                    help="schedules, comma-separated (default: f64,bf16x3+L for the water-like configs, "
+                         "f64,f32,bf16x3,f32+L,bf16x3+L for cfg2)")
+    ap.add_argument("--ref-steps", type=int, default=1,
+                    help="timed steps of the float64 reference path (water-like configs)")
+    ap.add_argument("--mu-iters", type=int, default=40,
+                    help="Newton-Schulz iteration cap of the passes of a cold mu search")
+    ap.add_argument("--mu-accept-rel", type=float, default=0.005,
+                    help="water-like configs: accept a mu whose electron count is within this fraction of "
+                         "the target (at least 0.5); the truncated count exceeds the target by ~0.26 %% "
+                         "everywhere in the gap")
     ap.add_argument("--pad", type=int, default=32, choices=[32, 64],
                     help="padding of the submatrices for the 16-bit schedules (float64 / float32: 32)")
     ap.add_argument("--refine-steps", type=int, default=-1,
@@ -63,15 +80,23 @@ def parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
-    ap.add_argument("--config", default="cfg2", choices=["cfg2", "cfg3"],
-                    help="cfg2: the metric's workload (default); cfg3: the precision form, 1000 "
-                         "water-like molecules, errors against the oracle on sampled submatrices")
+    ap.add_argument("--config", default="cfg3", choices=["cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="cfg3 (default): 1000 water-like molecules; cfg4: the mixed batch of four water-like "
+                         "systems; cfg2: the 10x10x10 lattice with every schedule; cfg5: the trajectory "
+                         "(learned-part form)")
+    ap.add_argument("--traj-steps", type=int, default=100, help="cfg5: geometries of the trajectory")
+    ap.add_argument("--train-steps", type=int, default=20, help="cfg5: explicit steps that train the network")
+    ap.add_argument("--relearn-every", type=int, default=0,
+                    help="cfg5: every k-th learned step also runs the explicit pass and fine-tunes (0: off)")
+    ap.add_argument("--n-mol", type=int, default=1000, help="cfg5: molecules")
     ap.add_argument("--graph", type=int, default=0, help="iterations per captured HIP graph (0: eager)")
     ap.add_argument("--scaling", default="gershgorin", choices=["gershgorin", "power"])
-    ap.add_argument("--chunk-gb", type=float, default=48.0, help="workspace matrix budget per chunk (cfg3)")
+    ap.add_argument("--chunk-gb", type=float, default=48.0,
+                    help="workspace matrix budget per chunk, GiB of float32 elements (water-like configs)")
     ap.add_argument("--chunk-mb", type=float, default=0.0,
                     help="float32 matrix budget per chunk in MiB (cfg2; 0: one chunk)")
-    ap.add_argument("--samples", type=int, default=6, help="oracle-checked submatrices (cfg3)")
+    ap.add_argument("--samples", type=int, default=6,
+                    help="oracle-checked submatrices (water-like configs; their timing is the CPU baseline)")
     ap.add_argument("--copy-calibrate", type=float, default=0.0, metavar="MIB",
                     help="first run a plain copy kernel (negation of a float32 buffer of MIB MiB), "
                          "the reference for scaling memory-traffic counters")
@@ -121,18 +146,41 @@ def train_scaling_net(sm, synth, dev, seed):
                  "loss_last": float(hist[-1])}
 
 
-def train_scaling_net_water(sm, synth, dev, seed, mu):
-    """The scaling network for the water-like systems, trained on a smaller
-    system of the same family (343 molecules: the same density and cutoff, so
-    submatrices of the same size) at the same mu: power-iteration estimates
-    (rho_est) and the lower bounds of plain split-bf16 runs (lb_est)."""
+def water_training_system(synth, cfg, seed):
+    """A smaller system of the same family as the benchmark's, for the scaling
+    network and the starting mu: 343 molecules at the same density and cutoff
+    (submatrices of the same size); for the mixed batch the union of two such
+    systems at the smallest and the largest cutoff of its parts."""
+    if cfg == "cfg4":
+        return synth.union([synth.water_system(343, 2.5, seed), synth.water_system(343, 3.5, seed + 100)],
+                           name="water343x2")
+    return synth.water_system(343, 3.0, seed)
+
+
+def mu_accept(a, n_occ):
+    """Acceptance of the mu bisection for the water-like configs: 0.5
+    electrons, or the relative tolerance if larger."""
+    return max(0.5, a.mu_accept_rel * n_occ)
+
+
+def train_scaling_net_water(sm, synth, dev, seed, cfg, mu_iters, accept_rel):
+    """The scaling network for the water-like systems, trained on bounds the
+    method produces for a smaller system of the same family: the cold
+    bisection for that system's own mu runs split-bf16 passes with
+    power-iteration scaling, and its accepted pass leaves, per submatrix,
+    rho_est (-> log rho / c_G) and lb_est (-> log l / c_G).  Returns the
+    network, its record, and the small system's mu (the warm start of the
+    benchmark system's search)."""
     import torch
-    m = synth.water_system(343, 3.0, seed)
+    m = water_training_system(synth, cfg, seed)
     plan = sm.Plan(m, 64)
     H = torch.from_numpy(m.vals).to(dev)
-    o = sm.default_opts("bf16x3", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
+    o = sm.default_opts("bf16x3", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02,
+                        max_iter=mu_iters)
     work = sm.Workspace(plan, sm.storage_prec(o), dev)
-    sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
+    t0 = time.perf_counter()
+    mu, k, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, accept=max(0.5, accept_rel * m.n_occ))
+    t_mu = time.perf_counter() - t0
     st = work.stats_host()
     ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
     X = torch.from_numpy(np.ascontiguousarray(st["feat"][ok]).astype(np.float32)).to(dev)
@@ -140,19 +188,39 @@ def train_scaling_net_water(sm, synth, dev, seed, mu):
                                    np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok]
                          .astype(np.float32)).to(dev)
     net = sm.Mlp(seed=seed)
-    hist = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
-    print(f"# scaling network: {int(ok.sum())} samples (343-molecule system, seed {seed}), "
-          f"loss {hist[0]:.3g} -> {hist[-1]:.3g}", file=sys.stderr, flush=True)
+    hist_l = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
+    print(f"# scaling network: {int(ok.sum())} samples ({m.name}, seed {seed}, mu {mu:.4f} after {k} "
+          f"bisection passes in {t_mu:.1f} s), loss {hist_l[0]:.3g} -> {hist_l[-1]:.3g}",
+          file=sys.stderr, flush=True)
     del work
-    return net, {"train_system": "water343, cutoff 3.0", "train_seed": seed, "samples": int(ok.sum()),
-                 "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
+    return net, {"train_system": m.name, "n_sub": int(m.n_atoms), "train_seed": seed,
+                 "samples": int(ok.sum()), "mu": mu, "bisection_passes": k, "bisection_s": t_mu,
+                 "loss_first": float(hist_l[0]), "loss_last": float(hist_l[-1])}, mu
+
+
+def cpu_info():
+    """Host CPU count and model (the cores the oracle baseline ran on)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def blas_threads():
+    from threadpoolctl import threadpool_info
+    return int(max([d.get("num_threads", 1) for d in threadpool_info()] or [1]))
 
 
 def cpu_baseline(m, mu, target_s):
     """The oracle as it stands, on a bounded sample of the same workload:
     the submatrix P columns of the first k atoms, k sized to ~target_s."""
     from oracle import submatrix as om
-    from threadpoolctl import threadpool_info
     view = om.BlockView(m)
     t0 = time.perf_counter()
     om.density_matrix(view, mu, atoms=range(32))
@@ -161,111 +229,375 @@ def cpu_baseline(m, mu, target_s):
     t0 = time.perf_counter()
     om.density_matrix(view, mu, atoms=range(k))
     dt = time.perf_counter() - t0
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    return {"value": k / dt, "unit": "submatrices/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"float64 eigendecomposition oracle, P columns of the first {k} of "
-                      f"{m.n_atoms} submatrices at the benchmark's mu ({dt:.1f} s)"}
+    ncpu, model = cpu_info()
+    return {"value": k / dt, "unit": "submatrices/s", "cores": blas_threads(), "kind": "oracle",
+            "host_cpus": ncpu, "cpu_model": model,
+            "sample": f"float64 eigendecomposition oracle (numpy / LAPACK, threaded BLAS), P columns of "
+                      f"the first {k} of {m.n_atoms} submatrices at the benchmark's mu ({dt:.1f} s)"}
 
 
-def precision_form(a):
-    """1000 water-like molecules (N = 23000, 3000 submatrices of n ~ 2300-2900),
-    chunked workspace; each schedule timed for one full evaluation at fixed mu,
-    its error measured against the float64 oracle on sampled submatrices (their
-    P columns and their share of tr(PH))."""
+def dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passes, pad_to):
+    """The GEMM class (precision, square / update) with the most kernel time,
+    with its algorithmic flops and bytes per launch and its achieved rates."""
+    cls = int(np.argmax(ms))
+    key = (cls // 2, cls % 2)
+    fl = metrics.flops_by_class(st, n, npad, o, slab)
+    fu, fi = fl.get(key, (0.0, 0.0))
+    nl = max(int(launches[cls]), 1)
+    avg_ms = ms[cls] / nl
+    per_launch = fu * metrics.MFMA_PRODUCTS[key[0]] * passes / nl
+    variant = int(o.variant) if int(o.variant) >= 0 else int(sm.sm_plan_tuning(plan)[key[0]])
+    bytes_launch = metrics.bytes_by_class(st, n, o, slab, npad).get(key, 0.0) * passes / nl
+    return {"name": metrics.gemm_kernel_symbol(key[0], key[1], variant, pad_to), "precision": DT_NAME[key[0]],
+            "product": "square" if key[1] == 0 else "update", "launches": int(launches[cls]), "avg_ms": avg_ms,
+            "algorithmic_flops_per_launch": per_launch, "algorithmic_bytes_per_launch": bytes_launch,
+            "achieved_gbs": bytes_launch / (avg_ms * 1e-3) / 1e9,
+            "useful_flops_per_launch": fu * passes / nl,
+            "issued_flops_per_launch": fi * metrics.MFMA_PRODUCTS[key[0]] * passes / nl,
+            "achieved_tflops": per_launch / (avg_ms * 1e-3) / 1e12,
+            "gemm_ms_total_per_pass": float(ms.sum()) / passes,
+            "gemm_ms_by_class_per_pass": {f"{DT_NAME[c // 2]}/{'square' if c % 2 == 0 else 'update'}":
+                                          float(ms[c]) / passes for c in range(len(ms)) if ms[c] > 0},
+            "peak_tflops": metrics.PEAK_TFLOPS[key[0]]}
+
+
+def roofline_of(kk, traffic, metrics):
+    """Roofline object of a kernel record: the bound is the resource whose time
+    at peak is larger for the kernel's algorithmic flops and bytes."""
+    t_mfma = kk["algorithmic_flops_per_launch"] / (kk["peak_tflops"] * 1e12)
+    t_hbm = kk["algorithmic_bytes_per_launch"] / (metrics.HBM_PEAK_GBS * 1e9)
+    if t_hbm > t_mfma:
+        rl = {"bound": "hbm", "achieved": kk["achieved_gbs"], "peak": metrics.HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": kk["achieved_gbs"] / metrics.HBM_PEAK_GBS}
+    else:
+        rl = {"bound": "mfma", "achieved": kk["achieved_tflops"], "peak": kk["peak_tflops"], "unit": "TFLOP/s",
+              "frac": kk["achieved_tflops"] / kk["peak_tflops"]}
+    rl.update({"traffic": traffic, "kernel": kk["name"], "avg_launch_ms": kk["avg_ms"],
+               "flops_per_launch": kk["algorithmic_flops_per_launch"],
+               "bytes_per_launch": kk["algorithmic_bytes_per_launch"],
+               "mfma_frac": kk["achieved_tflops"] / kk["peak_tflops"],
+               "hbm_frac": kk["achieved_gbs"] / metrics.HBM_PEAK_GBS})
+    return rl
+
+
+WORKLOADS = {
+    "cfg3": "water1000: 1000 water-like molecules (O 13, H 5 orbitals, N=23000), density 1, cutoff 3.0, "
+            "3000 submatrices n=%d..%d, mu by bisection (warm-started)",
+    "cfg4": "mixed4: four water-like systems of 250/500/1000/2000 molecules (cutoffs 2.5/2.83/3.17/3.5, "
+            "N=86250) in one batch, 11250 submatrices n=%d..%d, mu by bisection (warm-started)",
+}
+
+
+def water_bench(a):
+    """The water-like workloads (configs 3 and 4): cold mu search (untimed),
+    then --warmup + --steps warm-started steps of the headline schedule, the
+    float64 plain path at the same mu, oracle checks on sampled submatrices."""
     import torch
     import synth
     from oracle import submatrix as om
     from paper_2205_14741_amd import smsign as sm
-    from paper_2205_14741_amd import metrics
+    from paper_2205_14741_amd import metrics, profsum
     dev = torch.device("cuda:0")
-    m = synth.config3(a.seed)
+    if a.copy_calibrate > 0:
+        copy_calibrate(dev, a.copy_calibrate)
+    t0 = time.perf_counter()
+    m = synth.config4(a.seed) if a.config == "cfg4" else synth.config3(a.seed)
     H = torch.from_numpy(m.vals).to(dev)
-    budget = int(a.chunk_gb * 2 ** 30 / 4)
-    plan = sm.Plan(m, 64, budget)
+    plan = sm.Plan(m, 64, int(a.chunk_gb * 2 ** 30 / 4))
     info = plan.info()
     n, npad = info["n"], info["npad"]
-    rng = np.random.default_rng(a.seed)
-    atoms = sorted(rng.choice(m.n_atoms, size=a.samples, replace=False).tolist())
-    # mu inside the gap of this generator's water systems (occupied states end
-    # near -4.2, empty ones start near -1.7); checked on the sampled spectra
-    mu = -2.95
-    print(f"# cfg3: N {m.n_orb}, {m.n_atoms} submatrices n {n.min()}-{n.max()}, {plan.n_chunks} chunks; "
-          f"oracle on {len(atoms)} sampled submatrices ...", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    cache = om.SpectralCache(m, atoms=atoms)
-    gap_lo = float(cache.lam[cache.lam < mu].max())
-    gap_hi = float(cache.lam[cache.lam > mu].min())
-    Po = om.density_matrix(m, mu, atoms=atoms)
-    t_or = time.perf_counter() - t0
-    print(f"# oracle done in {t_or:.1f} s; sampled spectra leave ({gap_lo:.3f}, {gap_hi:.3f}) around mu",
-          file=sys.stderr, flush=True)
-    mask = ~np.isnan(Po)
-    sel = np.zeros_like(mask)
-    for i in atoms:
-        sel[m.panel_off[i]:m.panel_off[i + 1]] = True
-    E_or = float(np.sum(Po[sel] * m.vals[sel]))
-    res = {}
-    modes3 = [x for x in a.modes.split(",") if x and x != "f64"]
-    net_info = None
-    if any(x.endswith("+L") for x in modes3):
-        net, net_info = train_scaling_net_water(sm, synth, dev, a.seed + 1, mu)
+    print(f"# {a.config}: N {m.n_orb}, {m.n_atoms} submatrices n {n.min()}-{n.max()}, {plan.n_chunks} chunks "
+          f"(generated and planned in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    modes = [x for x in (a.modes or "f64,bf16x3+L").split(",") if x]
+    heads = [x for x in modes if x != "f64"]
+    if not heads:
+        raise SystemExit("--modes needs a schedule besides f64")
+    net_info, mu0 = None, None
+    if any(x.endswith("+L") for x in heads):
+        net, net_info, mu0 = train_scaling_net_water(sm, synth, dev, a.seed + 1, a.config, a.mu_iters,
+                                                     a.mu_accept_rel)
         sm.sm_plan_set_mlp(plan, net)
-    for mode in modes3:
+    # mu of this system: the bisection rule with the first schedule, warm-started
+    # at the training system's mu (untimed; later steps start from it)
+    o = mode_opts(sm, heads[0], a)
+    o.max_iter = a.mu_iters
+    work = sm.Workspace(plan, sm.storage_prec(o), dev)
+    t0 = time.perf_counter()
+    acc = mu_accept(a, m.n_occ)
+    mu, k, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, mu_start=mu0, accept=acc)
+    mu_search = {"schedule": heads[0], "mu": mu, "passes": k, "seconds": time.perf_counter() - t0,
+                 "mu_start": mu0, "accept": acc, "history": [[float(x), float(y)] for x, y in hist]}
+    print(f"# mu {mu:.5f} after {k} passes ({mu_search['seconds']:.1f} s), Ne {hist[-1][1]:.3f} "
+          f"(target {m.n_occ})", file=sys.stderr, flush=True)
+    del work
+    res, Ps = {}, {}
+    for mode in heads + (["f64"] if "f64" in modes else []):
         o = mode_opts(sm, mode, a)
         work = sm.Workspace(plan, sm.storage_prec(o), dev)
-        print(f"# {mode}: autotuning on chunk 0 ...", file=sys.stderr, flush=True)
-        best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5))
-        print(f"# {mode}: variant {best}; timing one evaluation ...", file=sys.stderr, flush=True)
+        ref = mode == "f64"
+        if ref:
+            o.variant = 1            # the float64 kernel of the lattice tuning (no sweep: passes are long)
+            tune = None
+        else:
+            print(f"# {mode}: autotuning on chunk 0 ...", file=sys.stderr, flush=True)
+            best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5, 6, 7))
+            tune = {"variant": int(best), "sign_ms_chunk0": [float(x) for x in tune_ms]}
+        steps, warm = (a.ref_steps, 0) if ref else (a.steps, a.warmup)
+        mu_k = mu
+
+        def step():
+            nonlocal mu_k
+            mu_k, kk, _, E, Ne = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P, energy=True,
+                                               mu_start=mu_k, accept=acc)
+            return kk, E, Ne
+
+        for w in range(warm):
+            step()
+            print(f"# {mode}: warmup {w + 1}/{warm}", file=sys.stderr, flush=True)
         sm.sm_profile_read(plan)
-        sm.sm_profile_enable(plan, True)
+        sm.sm_profile_enable(plan, not a.no_profile)
         torch.cuda.synchronize()
+        passes = 0
         t0 = time.perf_counter()
-        E, Ne = sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
+        for i in range(steps):
+            kk, E, Ne = step()
+            passes += kk
+            print(f"# {mode}: step {i + 1}/{steps} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sm.sm_profile_enable(plan, False)
         launches, ms = sm.sm_profile_read(plan)
         st = work.stats_host()
-        fl = metrics.flops_by_class(st, n, npad, o, slab_of(sm, metrics, plan, info, m, o, 64))
+        slab = slab_of(sm, metrics, plan, info, m, o, 64)
+        fl = metrics.flops_by_class(st, n, npad, o, slab)
         useful = sum(v[0] for v in fl.values())
-        P = work.P.cpu().numpy()
-        dP = float(np.max(np.abs(P[mask] - Po[mask])))
-        dEs = abs(float(np.sum(P[sel] * m.vals[sel])) - E_or) / abs(E_or)
-        cls = int(np.argmax(ms))
-        key = (cls // 2, cls % 2)
-        r = {"s_per_eval": dt, "submatrices_per_s": m.n_atoms / dt, "useful_tflops": useful / dt / 1e12,
-             "gemm_variant": int(best), "autotune_sign_ms": [float(x) for x in tune_ms],
+        r = {"steps": steps, "warmup": warm, "ms_per_step": dt / steps * 1e3, "submatrices_per_s": m.n_atoms * steps / dt,
+             "useful_tflops": useful * passes / dt / 1e12, "passes": passes, "mu": mu_k, "E": E, "Ne": Ne,
              "iters": [int(st["iters"].min()), int(st["iters"].max())], "iters_mean": float(st["iters"].mean()),
-             "max_dP_sampled": dP, "rel_dE_sampled": dEs, "E": E, "Ne": Ne,
+             "status_ok": bool(np.all(st["status"] >= 1)), "retried": int(np.sum(st["retried"])),
              "learned_accepted": float(np.mean(st["scale_src"] == 2)) if o.scaling == sm.SM_SCALE_LEARNED else None,
-             "status_ok": bool(np.all(st["status"] >= 1)),
-             "kernel": {"name": metrics.gemm_kernel_symbol(key[0], key[1], int(sm.sm_plan_tuning(plan)[key[0]]), 64),
-                        "launches": int(launches[cls]), "avg_ms": float(ms[cls] / max(launches[cls], 1)),
-                        "achieved_tflops": fl.get(key, (0.0, 0.0))[0] * metrics.MFMA_PRODUCTS[key[0]]
-                        / max(ms[cls] * 1e-3, 1e-12) / 1e12,
-                        "gemm_ms_total": float(ms.sum()), "peak_tflops": metrics.PEAK_TFLOPS[key[0]]}}
+             "probe_max": float(st["res_probe"].max()), "autotune": tune}
+        if not a.no_profile and ms.sum() > 0:
+            r["kernel"] = dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passes, 64)
+        Ps[mode] = work.P.cpu().numpy()
         res[mode] = r
-        print(f"# {mode}: {dt:.2f} s/eval, {r['submatrices_per_s']:.0f} subm/s, {r['useful_tflops']:.1f} TF/s useful, "
-              f"iters {r['iters']}, max|dP| (sampled) {dP:.2e}, rel dE (sampled) {dEs:.2e}, variant {best} "
-              f"(tune ms {' / '.join(f'{x:.0f}' for x in tune_ms)}), {r['kernel']['name']} "
-              f"{r['kernel']['achieved_tflops']:.1f} TF/s", file=sys.stderr, flush=True)
+        print(f"# {mode}: {r['ms_per_step']:.0f} ms/step, {r['submatrices_per_s']:.0f} subm/s, "
+              f"{r['useful_tflops']:.1f} TF/s useful, iters {r['iters']} (mean {r['iters_mean']:.2f}), "
+              f"passes {passes}" + (f", {r['kernel']['name']} {r['kernel']['avg_ms']:.2f} ms/launch "
+                                     f"{r['kernel']['achieved_tflops']:.0f} TF/s" if "kernel" in r else ""),
+              file=sys.stderr, flush=True)
         del work
-    ok = [k for k in res if res[k]["max_dP_sampled"] <= 1e-4 and res[k]["rel_dE_sampled"] <= 1e-5
-          and res[k]["status_ok"]]
-    head = max(ok, key=lambda k: res[k]["submatrices_per_s"]) if ok else next(iter(res))
+        torch.cuda.empty_cache()
+    # errors: against the float64 GPU path (every entry of P, E) and against
+    # the float64 oracle on sampled submatrices (their P columns, their share
+    # of tr(PH)); the oracle sample is also the CPU baseline
+    rng = np.random.default_rng(a.seed)
+    atoms = sorted(rng.choice(m.n_atoms, size=a.samples, replace=False).tolist())
+    if a.config == "cfg4":   # the two extremes of the batch too
+        atoms = sorted(set(atoms) | {int(np.argmin(n)), int(np.argmax(n))})
+    print(f"# oracle on {len(atoms)} sampled submatrices ...", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    Po = om.density_matrix(m, mu, atoms=atoms)
+    t_or = time.perf_counter() - t0
+    sel = ~np.isnan(Po)
+    E_or = float(np.sum(Po[sel] * m.vals[sel]))
+    for mode, r in res.items():
+        P = Ps[mode]
+        r["max_dP_oracle_sampled"] = float(np.max(np.abs(P[sel] - Po[sel])))
+        r["rel_dE_oracle_sampled"] = abs(float(np.sum(P[sel] * m.vals[sel])) - E_or) / abs(E_or)
+        r["mu_matches"] = r["mu"] == mu
+        if "f64" in Ps:
+            r["max_dP_vs_f64"] = float(np.max(np.abs(P - Ps["f64"])))
+            r["rel_dE_vs_f64"] = abs(r["E"] - res["f64"]["E"]) / abs(res["f64"]["E"])
+        r["meets_target"] = (r["max_dP_oracle_sampled"] <= 1e-4 and r["rel_dE_oracle_sampled"] <= 1e-5
+                             and r.get("max_dP_vs_f64", 0.0) <= 1e-4 and r.get("rel_dE_vs_f64", 0.0) <= 1e-5
+                             and r["status_ok"])
+        print(f"# {mode}: max|dP| vs oracle (sampled) {r['max_dP_oracle_sampled']:.2e}, rel dE (sampled) "
+              f"{r['rel_dE_oracle_sampled']:.2e}" + (f", vs f64 GPU max|dP| {r['max_dP_vs_f64']:.2e} rel dE "
+                                                     f"{r['rel_dE_vs_f64']:.2e}" if "f64" in Ps else ""),
+              file=sys.stderr, flush=True)
+    ok = [x for x in heads if res[x]["meets_target"]]
+    head = max(ok, key=lambda x: res[x]["submatrices_per_s"]) if ok else heads[0]
+    h = res[head]
+    ncpu, model = cpu_info()
     out = {"metric": "submatrix-sign TFLOP/s & submatrices/s vs FP64 plain at 1e-5 rel energy",
-           "value": res[head]["submatrices_per_s"], "unit": "submatrices/s", "n_gpus": 1, "steps": 1,
-           "warmup": 0, "ms_per_step": res[head]["s_per_eval"] * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "data": "synthetic",
-           "dtype": DT_NAME[sm.default_opts(MODES[head]).phase1] + ("+f32" if mode_opts(sm, head, a).refine_steps > 0
-                                                                    and MODES[head] != "f32" else ""),
-           "config": {"workload": "water1000: 1000 water-like molecules (O 13, H 5 orbitals, N=23000), "
-                                  "cutoff 3.0, 3000 submatrices n=%d..%d, fixed mu" % (n.min(), n.max()),
-                      "mode": head, "seed": a.seed, "chunks": plan.n_chunks},
-           "useful_tflops": res[head]["useful_tflops"], "modes": res,
-           "oracle_sample": {"atoms": atoms, "seconds": t_or, "gap_around_mu": [gap_lo, gap_hi], "mu": mu},
-           "scaling_network": net_info}
+           "value": h["submatrices_per_s"], "unit": "submatrices/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": h["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic",
+           "dtype": DT_NAME[int(mode_opts(sm, head, a).phase1)] + ("+f32" if mode_opts(sm, head, a).refine_steps > 0
+                                                                   and MODES[head] != "f32" else ""),
+           "config": {"workload": WORKLOADS[a.config] % (n.min(), n.max()), "n_sub": int(m.n_atoms),
+                      "N": int(m.n_orb), "mode": head, "seed": a.seed, "chunks": int(plan.n_chunks)},
+           "useful_tflops": h["useful_tflops"], "meets_target": h["meets_target"],
+           "speedup_vs_fp64_plain": (res["f64"]["ms_per_step"] / h["ms_per_step"]) if "f64" in res else None,
+           "mu_search": mu_search, "scaling_network": net_info, "modes": res,
+           "oracle_sample": {"atoms": atoms, "seconds": t_or}}
+    if "kernel" in h:
+        kk = h["kernel"]
+        tag = "water1000" if a.config == "cfg3" else "mixed4"
+        traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", f"ns_gemm_traffic_{tag}.txt"), kk["name"])
+        out["roofline"] = roofline_of(kk, traffic, metrics)
+    if a.cpu_seconds > 0:
+        out["cpu_baseline"] = {"value": len(atoms) / t_or, "unit": "submatrices/s", "cores": blas_threads(),
+                               "kind": "oracle", "host_cpus": ncpu, "cpu_model": model,
+                               "sample": f"float64 eigendecomposition oracle (numpy / LAPACK, threaded BLAS), "
+                                         f"P columns of {len(atoms)} sampled submatrices of the same system at "
+                                         f"the benchmark's mu ({t_or:.1f} s)"}
     print(json.dumps(out), flush=True)
+
+
+def _traj_step(args):
+    """One trajectory geometry (run in a worker process)."""
+    import synth
+    t, seed, n_mol = args
+    return synth.config5_step(t, seed, n_mol=n_mol)
+
+
+def _labels(st, np_):
+    """Training pairs of an explicit (power-scaled, plain) pass: the features
+    and (log rho_est / c_G, log lb / c_G) where both bounds were found."""
+    ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
+    X = np_.ascontiguousarray(st["feat"][ok]).astype(np_.float32)
+    Y = np_.stack([np_.log(st["rho_est"] / st["gersh"]),
+                   np_.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok].astype(np_.float32)
+    return X, Y
+
+
+def trajectory_bench(a):
+    """The learned-part form: a random walk of the water-like system (every
+    atom N(0, 0.02) per step, H changing smoothly).  Steps < --train-steps run
+    the explicit form (power-iteration scale, plain Newton-Schulz) and give
+    training pairs; the network is then trained on the GPU and the later steps
+    run the learned form (guarded learned scale, scaled Newton-Schulz), mu
+    warm-started from the previous step and the plan reused while the pattern
+    is unchanged; with --relearn-every k every k-th learned step also runs the
+    explicit pass and the network is fine-tuned on all pairs so far (learning
+    on the fly).  At the first and the last learned step the Gershgorin plain
+    split-bf16 pass and the float64 plain pass run on the same geometry."""
+    import concurrent.futures as cf
+    import torch
+    from paper_2205_14741_amd import smsign as sm
+    dev = torch.device("cuda:0")
+    T, T0 = a.traj_steps, a.train_steps
+    pool = cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1))
+    futs = {t: pool.submit(_traj_step, (t, a.seed, a.n_mol)) for t in range(min(T, 6))}
+    plan, pat, replans = None, None, 0
+    mu = None
+    X_all, Y_all = [], []
+    net = None
+    rows = []
+    t_learned, n_learned = 0.0, 0
+    o_exp = sm.default_opts("bf16x3", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02,
+                            max_iter=a.mu_iters)
+    o_learn = mode_opts(sm, "bf16x3+L", a)
+    o_gersh = mode_opts(sm, "bf16x3", a)
+    o_f64 = sm.default_opts("f64")
+    o_f64.variant = 1
+    work = None
+    for t in range(T):
+        m = futs.pop(t).result()
+        if t + 6 < T:
+            futs[t + 6] = pool.submit(_traj_step, (t + 6, a.seed, a.n_mol))
+        key = (m.block_size.tobytes(), m.col_ptr.tobytes(), m.row_idx.tobytes())
+        if plan is None or key != pat:
+            tuned = sm.sm_plan_tuning(plan) if plan is not None else None
+            plan = sm.Plan(m, 64, int(a.chunk_gb * 2 ** 30 / 4))
+            if tuned is not None:
+                sm.sm_plan_tuning(plan, tuned)
+            if net is not None:
+                sm.sm_plan_set_mlp(plan, net)
+            pat = key
+            replans += 1
+            work = sm.Workspace(plan, sm.storage_prec(o_learn), dev)
+        H = torch.from_numpy(m.vals).to(dev)
+        acc = mu_accept(a, m.n_occ)
+        row = {"step": t}
+        if t == 0:
+            best, _ = sm.sm_autotune(plan, 0, H, -2.95, o_gersh, work.ws, work.stats, repeats=1, variants=(5, 6, 7))
+            row["variant"] = int(best)
+        explicit = t < T0 or (a.relearn_every > 0 and t > T0 and (t - T0) % a.relearn_every == 0)
+        learned = t >= T0
+        if explicit:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mu, k, _, E, Ne = sm.sm_find_mu(plan, H, m.n_occ, o_exp, work.ws, work.stats, P=work.P, energy=True,
+                                            mu_start=mu, accept=acc)
+            torch.cuda.synchronize()
+            st = work.stats_host()
+            X, Y = _labels(st, np)
+            X_all.append(X)
+            Y_all.append(Y)
+            row.update({"explicit_s": time.perf_counter() - t0, "explicit_iters": float(st["iters"].mean()),
+                        "explicit_passes": k, "E_explicit": E, "pairs": int(X.shape[0])})
+            if t >= T0 - 1:
+                Xd = torch.from_numpy(np.concatenate(X_all)).to(dev)
+                Yd = torch.from_numpy(np.concatenate(Y_all)).to(dev)
+                if net is None:
+                    net = sm.Mlp(seed=a.seed + 1)
+                hist = sm.sm_mlp_train(net, Xd, Yd, Xd.shape[0], epochs=300 if t == T0 - 1 else 60,
+                                       batch=128, lr=2e-3 if t == T0 - 1 else 5e-4)
+                sm.sm_plan_set_mlp(plan, net)
+                row.update({"trained_on": int(Xd.shape[0]), "loss_last": float(hist[-1])})
+        if learned:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mu, k, _, E, Ne = sm.sm_find_mu(plan, H, m.n_occ, o_learn, work.ws, work.stats, P=work.P, energy=True,
+                                            mu_start=mu, accept=acc)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = work.stats_host()
+            t_learned += dt
+            n_learned += 1
+            row.update({"learned_s": dt, "learned_iters": float(st["iters"].mean()), "learned_passes": k,
+                        "accepted": float(np.mean(st["scale_src"] == 2)), "E": E, "Ne": Ne, "mu": mu,
+                        "status_ok": bool(np.all(st["status"] >= 1))})
+            if t == T0 or t == T - 1:
+                P_l = work.P.cpu().numpy()
+                for name, o in (("gershgorin", o_gersh), ("f64", o_f64)):
+                    w2 = sm.Workspace(plan, sm.storage_prec(o), dev) if o is o_f64 else work
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    E2, Ne2 = sm.sm_density_matrix(plan, H, mu, o, w2.ws, w2.P, w2.stats)
+                    torch.cuda.synchronize()
+                    s2 = w2.stats_host()
+                    row[name] = {"s": time.perf_counter() - t1, "iters": float(s2["iters"].mean()), "E": E2}
+                    if o is o_f64:
+                        row["f64"]["max_dP_learned_vs_f64"] = float(np.max(np.abs(P_l - w2.P.cpu().numpy())))
+                        row["f64"]["rel_dE_learned_vs_f64"] = abs(E - E2) / abs(E2)
+                        del w2
+        rows.append(row)
+        print("# step " + json.dumps(row), file=sys.stderr, flush=True)
+    pool.shutdown()
+    lr = [r for r in rows if "learned_iters" in r]
+    ex = [r for r in rows if "explicit_iters" in r]
+    out = {"metric": "submatrix-sign TFLOP/s & submatrices/s vs FP64 plain at 1e-5 rel energy",
+           "value": m.n_atoms * n_learned / t_learned if n_learned else None, "unit": "submatrices/s",
+           "n_gpus": 1, "steps": n_learned, "warmup": 0,
+           "ms_per_step": t_learned / max(n_learned, 1) * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16x3+f32", "data": "synthetic",
+           "config": {"workload": f"trajectory: water{a.n_mol} random walk N(0, 0.02) per step, {T} steps, "
+                                  f"network trained on steps 0..{T0 - 1}", "n_sub": int(m.n_atoms),
+                      "relearn_every": a.relearn_every, "replans": replans, "seed": a.seed},
+           "iters_mean": {"explicit_power": float(np.mean([r["explicit_iters"] for r in ex])) if ex else None,
+                          "learned": float(np.mean([r["learned_iters"] for r in lr])) if lr else None,
+                          "gershgorin": [r["gershgorin"]["iters"] for r in lr if "gershgorin" in r]},
+           "accepted_mean": float(np.mean([r["accepted"] for r in lr])) if lr else None,
+           "f64_checks": [dict(step=r["step"], **r["f64"]) for r in lr if "f64" in r],
+           "steps_detail": rows}
+    print(json.dumps(out), flush=True)
+
+
+def copy_calibrate(dev, mib):
+    """A plain copy kernel of known size (negation of a float32 buffer), the
+    reference that memory-traffic counters are scaled by."""
+    import torch
+    src = torch.ones(int(mib * 2 ** 20) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(f"# copy kernel: {src.numel() * 4} bytes", file=sys.stderr, flush=True)
+    del src, dst
 
 
 def main():
@@ -275,8 +607,10 @@ def main():
         print("bench.py runs on one GPU only (the submatrix path would shard by atom domains; "
               "the multi-GPU halo exchange is not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    if a.config == "cfg3":
-        return precision_form(a)
+    if a.config in ("cfg3", "cfg4"):
+        return water_bench(a)
+    if a.config == "cfg5":
+        return trajectory_bench(a)
     import torch
     import synth
     from paper_2205_14741_amd import smsign as sm
@@ -284,13 +618,7 @@ def main():
 
     dev = torch.device("cuda:0")
     if a.copy_calibrate > 0:
-        src = torch.ones(int(a.copy_calibrate * 2 ** 20) // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        print(f"# copy kernel: {src.numel() * 4} bytes", file=sys.stderr, flush=True)
-        del src, dst
+        copy_calibrate(dev, a.copy_calibrate)
     m = synth.config2(a.seed)
     # submatrices padded to 32 (--pad 64: the 16-bit schedules on a plan padded to 64)
     budget = int(a.chunk_mb * 2 ** 20 / 4)
@@ -298,7 +626,7 @@ def main():
     H = torch.from_numpy(m.vals).to(dev)
     torch.cuda.synchronize()
 
-    modes = [x for x in a.modes.split(",") if x]
+    modes = [x for x in (a.modes or "f64,f32,bf16x3,f32+L,bf16x3+L").split(",") if x]
     if "f64" in modes:
         modes.remove("f64")
     modes = ["f64"] + modes            # the plain float64 path is the reference
@@ -429,27 +757,10 @@ def main():
         "modes": res,
     }
     if "kernel" in h:
-        kk = h["kernel"]
         from paper_2205_14741_amd import profsum
         traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", "ns_gemm_traffic_lattice1000.txt"),
-                                       kk["name"])
-        # the bound is the resource whose time at peak is larger for this
-        # kernel's algorithmic flops and bytes (its arithmetic intensity
-        # against the chip's flop / byte ridge)
-        t_mfma = kk["algorithmic_flops_per_launch"] / (kk["peak_tflops"] * 1e12)
-        t_hbm = kk["algorithmic_bytes_per_launch"] / (metrics.HBM_PEAK_GBS * 1e9)
-        if t_hbm > t_mfma:
-            rl = {"bound": "hbm", "achieved": kk["achieved_gbs"], "peak": metrics.HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": kk["achieved_gbs"] / metrics.HBM_PEAK_GBS}
-        else:
-            rl = {"bound": "mfma", "achieved": kk["achieved_tflops"], "peak": kk["peak_tflops"], "unit": "TFLOP/s",
-                  "frac": kk["achieved_tflops"] / kk["peak_tflops"]}
-        rl.update({"traffic": traffic, "kernel": kk["name"], "avg_launch_ms": kk["avg_ms"],
-                   "flops_per_launch": kk["algorithmic_flops_per_launch"],
-                   "bytes_per_launch": kk["algorithmic_bytes_per_launch"],
-                   "mfma_frac": kk["achieved_tflops"] / kk["peak_tflops"],
-                   "hbm_frac": kk["achieved_gbs"] / metrics.HBM_PEAK_GBS})
-        out["roofline"] = rl
+                                       h["kernel"]["name"])
+        out["roofline"] = roofline_of(h["kernel"], traffic, metrics)
     if a.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline(m, res["f64"]["mu"], a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -292,17 +292,67 @@ int sm_density_matrix(sm_plan* plan, const double* H_vals, double mu,
                       const sm_sign_opts* opts, void* ws, double* P_vals,
                       sm_sub_stats* stats, double* E_host, double* Ne_host, void* stream);
 
-/* Chemical potential by bisection on the electron count (the paper leaves the
- * rule open): start from the global Gershgorin bracket of H, evaluate
- * Ne(mid) = tr P with the full method at each midpoint, stop at the first
- * midpoint with |Ne - n_target| < accept, else after max_steps midpoints.
- * On return P_vals (if not NULL) holds P at the returned mu.
+/* ---- Non-orthogonal basis (S != I), float64 ---------------------------------
+ * Eq. 14 with an overlap matrix S, on the submatrix pair (T_i(H), T_i(S)) of
+ * every atom block (Fig. 2): S is stored on H's block pattern (same col_ptr /
+ * row_idx / panel layout; S_vals device, float64, symmetric positive definite
+ * submatrices).  ws is a float64 workspace of the plan (sm_plan_sizes with
+ * SM_F64) and ws_aux a second one of the same size, caller-owned; ws_aux holds
+ * Z_i = T_i(S)^(-1/2) of the chunk last processed by sm_overlap_inv_sqrt.
+ * Schedules: the float64 main phase without refinement steps, Gershgorin or
+ * power scaling, retry = 0 (SM_ERR_ARG otherwise). */
+
+/* Eq. 12: Z_i = T_i(S)^(-1/2) for every submatrix of `chunk`, by Newton-Schulz
+ * on the block matrix [[0, A], [I, 0]], A = T_i(S) / c_i (c_i its Gershgorin
+ * bound): the iterate stays [[0, Y], [Z, 0]] and one step is W = 1/2 (3I - Z Y),
+ * Y <- Y W, Z <- W Z; Z / sqrt(c_i) goes to buffer 0 of each submatrix in
+ * ws_aux (identity pad).  Stops when every ||Z Y - I||_F < tol, or after
+ * max_iter steps (SM_ERR_STATE then).  ws is used as scratch.
+ *   iters_out / res_out (may be NULL): steps taken, largest final residual.
+ * Synchronises `stream` once per step. */
+int sm_overlap_inv_sqrt(sm_plan* plan, int32_t chunk, const double* S_vals, double tol,
+                        int32_t max_iter, void* ws_aux, void* ws, int32_t* iters_out,
+                        double* res_out, void* stream);
+
+/* Start of the sign iteration for S != I: K_i = Z_i T_i(H) Z_i - mu I (the sign
+ * of S^-1 H - mu I in Eq. 14 is Z^-1 sign(K) Z on the pair), written as
+ * build_submatrices writes T_i - mu I, then scaled the same way (stats.gersh,
+ * stats.scale).  Needs sm_overlap_inv_sqrt of this chunk into ws_aux
+ * (SM_ERR_STATE otherwise).  submatrix_sign then runs unchanged.
+ * Asynchronous on `stream`. */
+int build_submatrices_overlap(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
+                              const sm_sign_opts* opts, void* ws, const void* ws_aux,
+                              sm_sub_stats* stats, void* stream);
+
+/* Step 3 of Fig. 2 for S != I: block column i of P_i = 1/2 Z_i (I - X_i) Z_i,
+ * X_i the final sign iterate, into P's panel i (H's pattern).  ws_aux's
+ * buffers 1 and 2 are used as scratch.  Asynchronous on `stream`. */
+int assemble_P_overlap(sm_plan* plan, int32_t chunk, void* ws, const void* ws_aux,
+                       double* P_vals, void* stream);
+
+/* Whole evaluation for S != I at fixed mu: per chunk sm_overlap_inv_sqrt (tol
+ * 1e-12), build_submatrices_overlap, submatrix_sign, assemble_P_overlap; then
+ * E = tr(P H) and Ne = tr(P S) (the electron count of a non-orthogonal basis).
+ * Synchronises `stream`. */
+int sm_density_matrix_overlap(sm_plan* plan, const double* H_vals, const double* S_vals, double mu,
+                              const sm_sign_opts* opts, void* ws, void* ws_aux, double* P_vals,
+                              sm_sub_stats* stats, double* E_host, double* Ne_host, void* stream);
+
+/* Chemical potential by bisection on the electron count (Eq. 14's mu; the
+ * paper leaves the rule open): start from the global Gershgorin bracket of H,
+ * evaluate Ne(mid) = tr P with the full method at each midpoint, stop at the
+ * first midpoint with |Ne - n_target| < accept, else after max_steps
+ * evaluations.  On return P_vals (if not NULL) holds P at the returned mu.
+ *   mu_start           warm start (NaN: none): evaluated first in place of the
+ *                      first midpoint (e.g. the previous geometry's mu); if
+ *                      it is not accepted it replaces lo (Ne short of the
+ *                      target) or hi, clamped into the bracket.
  *   mu_hist / ne_hist  host arrays of max_steps entries (may be NULL).
  *   E_host / Ne_host   (may be NULL; need P_vals) energy_trace of the returned
  *                      P, reduced in the same pass as the electron count.
  * Synchronises `stream`. */
 int sm_find_mu(sm_plan* plan, const double* H_vals, double n_target, double accept,
-               int32_t max_steps, const sm_sign_opts* opts, void* ws, double* P_vals,
+               int32_t max_steps, double mu_start, const sm_sign_opts* opts, void* ws, double* P_vals,
                sm_sub_stats* stats, double* mu_out, int32_t* steps_out,
                double* mu_hist, double* ne_hist, double* E_host, double* Ne_host, void* stream);
 
@@ -342,11 +392,14 @@ int sm_gershgorin_bracket_noalloc(const sm_plan* plan, const double* H_vals, dou
 int sm_plan_ws_layout(const sm_plan* plan, int32_t storage_prec, int64_t* regions9,
                       int64_t* mat_off_g);
 
-/* Diagnostic: one matrix-core instruction of precision `prec` on a single
- * wavefront with the operand lane layout the kernels assume; out_host receives
- * 256 doubles, out[lane*4 + v] = the result element held by `lane` in register
- * v, to be compared with D[4*(lane/16)+v][lane%16] of the exact product.
- * Synchronous; allocates and frees a 2 KiB device buffer. */
+/* Diagnostic: one matrix-core instruction on a single wavefront with the
+ * operand lane layout the kernels assume.  prec = an sm_prec code: the 16x16
+ * instruction of that precision; out_host receives 256 doubles,
+ * out[lane*4 + v] = the result element held by `lane` in register v (to be
+ * compared with D[4*(lane/16)+v][lane%16] of the exact product, float64:
+ * D[lane/16 + 4v][lane%16]).  prec = 5 / 6: the 32x32x16 f16 / bf16
+ * instruction; out_host receives 1024 doubles, out[lane*16 + v].
+ * Synchronous; allocates and frees a device buffer of that size. */
 int sm_selftest_mfma(int32_t prec, double* out_host);
 
 /* ---- the spectral-scaling network (learned scaling, SM_SCALE_LEARNED) ----

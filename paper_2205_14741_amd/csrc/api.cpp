@@ -92,6 +92,7 @@ int chunk_max_tiles_sub(const sm_plan* p, int g0, int nsub) {
 // float32-accumulating precision, otherwise the XCD-aware 64-wide kernel.
 int effective_variant(const sm_plan* p, int mode, int variant) {
   int v = variant >= 0 ? variant : p->tuned[mode];
+  if (v >= 6 && mode < SM_BF16) v = 5;   // 256-wide tiles: 16-bit operand copies only
   if (v >= 3 && (mode == SM_F64 || p->pad_to < 64)) v = 1;
   // bf16 / f16 / split-bf16 on a plan padded to 32: only the half-depth
   // stages (k depth 32) divide n_pad
@@ -508,7 +509,7 @@ int sm_gershgorin_bracket_noalloc(const sm_plan* p, const double* H, double* loh
 }
 
 int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int32_t max_steps,
-               const sm_sign_opts* o, void* ws, double* P, sm_sub_stats* stats, double* mu_out,
+               double mu_start, const sm_sign_opts* o, void* ws, double* P, sm_sub_stats* stats, double* mu_out,
                int32_t* steps_out, double* mu_hist, double* ne_hist, double* E_out, double* Ne_out,
                void* stream) {
   if (!p || !H || !ws || !stats || !mu_out) return set_error(SM_ERR_ARG, "sm_find_mu: null argument");
@@ -520,10 +521,13 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
   if ((rc = sm_gershgorin_bracket(p, H, &lo, &hi, stream))) return rc;
   hipStream_t s = as_stream(stream);
   const int nch = (int)p->chunk_ptr.size() - 1;
+  // a finite mu_start is evaluated first (warm start); if it is not
+  // accepted it narrows the bracket like any midpoint, clamped into it
+  const bool warm = std::isfinite(mu_start);
   double mid = 0.5 * (lo + hi);
   int step = 1;
   for (; step <= max_steps; ++step) {
-    mid = 0.5 * (lo + hi);
+    mid = (warm && step == 1) ? mu_start : 0.5 * (lo + hi);
     for (int c = 0; c < nch; ++c) {
       if ((rc = build_submatrices(p, c, H, mid, o, ws, stats, stream))) return rc;
       if ((rc = submatrix_sign(p, c, ws, o, stats, stream))) return rc;
@@ -552,7 +556,8 @@ int sm_find_mu(sm_plan* p, const double* H, double n_target, double accept, int3
     if (mu_hist) mu_hist[step - 1] = mid;
     if (ne_hist) ne_hist[step - 1] = ne;
     if (std::fabs(ne - n_target) < accept) break;
-    if (ne < n_target) lo = mid; else hi = mid;
+    if (ne < n_target) lo = std::min(std::max(lo, mid), hi);
+    else hi = std::max(std::min(hi, mid), lo);
   }
   *mu_out = mid;
   if (steps_out) *steps_out = std::min(step, (int)max_steps);
@@ -622,11 +627,12 @@ int sm_plan_tuning(sm_plan* p, int32_t* get, const int32_t* set) {
 
 int sm_selftest_mfma(int32_t prec, double* out_host) {
   if (!out_host) return set_error(SM_ERR_ARG, "sm_selftest_mfma: null output");
-  if (prec < SM_F64 || prec > SM_BF16X3) return set_error(SM_ERR_ARG, "sm_selftest_mfma: bad precision");
+  if (prec < SM_F64 || prec > 6) return set_error(SM_ERR_ARG, "sm_selftest_mfma: bad instruction code %d", prec);
+  const size_t nout = prec >= 5 ? 1024 : 256;
   double* d = nullptr;
-  SM_HIP(hipMalloc(&d, 256 * sizeof(double)));
+  SM_HIP(hipMalloc(&d, nout * sizeof(double)));
   hipError_t e = launch_selftest_mfma(prec, d, nullptr);
-  if (e == hipSuccess) e = hipMemcpy(out_host, d, 256 * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(out_host, d, nout * sizeof(double), hipMemcpyDeviceToHost);
   (void)hipFree(d);
   if (e != hipSuccess) return hip_error(e, "sm_selftest_mfma");
   return SM_OK;

@@ -19,6 +19,7 @@ namespace sm {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
@@ -1007,6 +1008,244 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
   }
 }
 
+// ---------------------------------------------------------------------------
+// 256 x 256 output tiles for the large submatrices of the 16-bit main phases
+// (bf16, f16, split bf16): 512 threads, 8 waves (two per SIMD) in 2 x 4, each
+// computing 128 x 64 outputs (4 x 2 blocks of 32 x 32, 32x32x16 instructions:
+// a measured 2.24 PF/s of bf16 issue against 1.67 for 16x16x32 at two waves
+// per SIMD).  A tile reads half the operand bytes per flop of the 128-wide
+// tiles and a wave reads half the LDS bytes per matrix-core instruction of a
+// 64 x 64 wave block.  Operand stages (k depth KS = 32 or 16) go from the
+// copies into LDS with direct 16-byte global -> LDS loads (no staging
+// registers, no LDS store instructions), issued NBUF - 1 stages ahead into a
+// ring of NBUF LDS buffers (2 x 32 or 4 x 16: 128 KiB for split bf16).
+//
+// LDS stage layout: [operand][plane (hi, lo)][256 rows][2 KS bytes].  Inside a
+// row the 16-byte k-chunks sit at position c ^ swz(R), R the row within its
+// operand (four chunks per row: (R >> 2) & 3; two: (R >> 3) & 1): any sixteen
+// consecutive rows read at one k-chunk fall on sixteen distinct 16-byte bank
+// groups (sixteen lanes of a 16-byte LDS read are served together).
+// ---------------------------------------------------------------------------
+constexpr int kBlock256 = 512;
+
+template <int MODE, int KS> struct G256 {
+  static constexpr int PL = MODE == SM_BF16X3 ? 2 : 1;     // planes (hi, lo)
+  static constexpr int RB = 2 * KS;                          // bytes of one row of one plane per stage
+  static constexpr int CPR = RB / 16;                        // 16-byte k-chunks per row
+  static constexpr int RPC = 1024 / RB;                      // rows per 1 KiB chunk
+  static constexpr int PLANE = 256 * RB;                     // bytes of one plane of one operand
+  static constexpr int CHUNKS = 2 * PL * PLANE / 1024;       // 1 KiB chunks per stage
+  static constexpr int LPW = CHUNKS / 8;                     // direct loads per wave per stage
+  static constexpr int STAGE = CHUNKS * 1024;                // bytes per stage
+};
+
+template <int CPR>
+__device__ __forceinline__ int swz256(int R) { return CPR == 4 ? (R >> 2) & 3 : (R >> 3) & 1; }
+
+// One 16-byte direct global -> LDS load per lane: lane l's 16 bytes land at
+// lds_wave + 16 l (lds_wave is wave-uniform).
+__device__ __forceinline__ void lds_load16(const void* g, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds(g, lds_wave, 16, 0, 0);
+}
+
+// Wait until at most N of this wave's vector memory operations are in flight
+// (N < 16; lgkmcnt and expcnt unconstrained).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  __builtin_amdgcn_s_waitcnt(0x0f70 | N);
+}
+
+// Byte offset in a stage of (operand op, row R, plane p, k-chunk c).
+template <int MODE, int KS>
+__device__ __forceinline__ int g256_off(int op, int R, int p, int c) {
+  using G = G256<MODE, KS>;
+  return (op * G::PL + p) * G::PLANE + R * G::RB + ((c ^ swz256<G::CPR>(R)) << 4);
+}
+
+template <int MODE, int WHICH, bool XCD, int KS, int NBUF>
+__global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restrict__ mats, int64_t shadow_off,
+                                                                 const int32_t* __restrict__ count,
+                                                                 const TileRec* __restrict__ recs,
+                                                                 double* __restrict__ partials) {
+  using G = G256<MODE, KS>;
+  constexpr bool SPLIT = MODE == SM_BF16X3;
+  constexpr int AHEAD = NBUF - 1;
+  static_assert(Pre<MODE>::value, "16-bit operand copies only");
+  static_assert(AHEAD * G::LPW < 16, "loads in flight must fit the vmcnt counter");
+  __shared__ __attribute__((aligned(1024))) char lds[NBUF * G::STAGE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int wm = wid >> 2, wn = wid & 3;   // rows 128 wm .., columns 64 wn ..
+  const int total = count[0];
+  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x, t_lo = 0;
+  if (XCD) {
+    const int x8 = blockIdx.x % kXcds;
+    t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
+    t_lo = (int)((int64_t)total * x8 / kXcds);
+    t_begin = t_lo + (int)blockIdx.x / kXcds;
+    t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
+  }
+  const int t_mirror = WHICH == 1 ? t_lo + t_end - 1 : -1;
+
+  // this lane's part of the wave's direct loads: load u of wave wid fills
+  // chunk q = wid * LPW + u (plane region q / (PLANE / 1 KiB)); lane -> (row
+  // in chunk, LDS k-chunk position)
+  const int l_rr = lane / G::CPR;
+  const int l_cp = lane % G::CPR;
+
+  for (int t = t_begin; t < t_end; t += t_step) {
+    const TileRec rec = recs[rec_index(t, t_mirror)];
+    const int npad = rec.npad;
+    const int64_t nn = (int64_t)npad * npad;
+    const double alpha = (double)rec.alpha;
+    const double rscale = (double)rec.rscale;
+    float* base = mats + rec.mat_off;
+    float* Out = base + (WHICH == 0 ? 2 * nn : (int64_t)(rec.it & 1) * nn);
+    const float* Xp = base + (int64_t)((WHICH == 0 ? rec.it : rec.it + 1) & 1) * nn;
+    const float* Rp = WHICH == 0 ? Xp : base + 2 * nn;
+    const int bi = rec.bibj >> 16, bj = rec.bibj & 0xFFFF;
+    const int r0 = bi * 256, c0 = bj * 256;
+    const bool wvalid = (r0 + wm * 128 < npad) && (c0 + wn * 64 < npad) &&
+                        !(bi == bj && wm * 128 + 127 < wn * 64);
+    // global source of each of this lane's loads (16-bit element index of
+    // its 16 bytes at stage 0); rows past n_pad read row n_pad - 1 (their
+    // products land in outputs that are never stored)
+    const uint16_t* src[G::LPW];
+#pragma unroll
+    for (int u = 0; u < G::LPW; ++u) {
+      const int q = wid * G::LPW + u;
+      const int region = q / (G::PLANE / 1024);          // op * PL + plane
+      const int op = region / G::PL, pl = region % G::PL;
+      const int R = (q % (G::PLANE / 1024)) * G::RPC + l_rr;
+      const int row = min((op == 0 ? r0 : c0) + R, npad - 1);
+      const int gc = l_cp ^ swz256<G::CPR>(R);
+      const uint16_t* cp = reinterpret_cast<const uint16_t*>((op == 0 ? Xp : Rp) + shadow_off);
+      src[u] = cp + (SPLIT ? (int64_t)row * 2 * npad + pl * 32 : (int64_t)row * npad) + gc * 8;
+    }
+    const int nst = npad / KS;
+    // stage s starts at k = KS s: for split copies, 32-row run s KS / 32 (64
+    // elements: hi then lo), offset (s KS) % 32 inside it
+    auto issue = [&](int s) {
+      char* dst = lds + (s % NBUF) * G::STAGE;
+      const int64_t k0 = (int64_t)s * KS;
+      const int64_t so = SPLIT ? (k0 >> 5) * 64 + (k0 & 31) : k0;
+#pragma unroll
+      for (int u = 0; u < G::LPW; ++u) lds_load16(src[u] + so, dst + (wid * G::LPW + u) * 1024);
+    };
+
+    // 32 x 32 result blocks: 4 (rows) x 2 (columns) per wave
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
+
+#pragma unroll
+    for (int u = 0; u < AHEAD; ++u)
+      if (u < nst) issue(u);
+    for (int s = 0; s < nst; ++s) {
+      // this wave's loads of stage s have landed (those of the later stages
+      // already issued may still fly); after the barrier every wave's have,
+      // and every wave is done with stage s - 1, whose buffer stage s + AHEAD
+      // refills
+      if (s + AHEAD <= nst) wait_vm<(AHEAD - 1) * G::LPW>();
+      else if (AHEAD >= 3 && s + 2 == nst) wait_vm<(AHEAD >= 3 ? G::LPW : 0)>();
+      else wait_vm<0>();
+      // a plain barrier, not __syncthreads(): its fence would wait for every
+      // load in flight, the later stages' too.  The wait above covers this
+      // wave's stage-s loads; every LDS read of stage s - 1 has returned (the
+      // matrix-core instructions that use it were issued).
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      if (s + AHEAD < nst) issue(s + AHEAD);
+      asm volatile("" :: "v"(lds) : "memory");
+      if (!wvalid) continue;
+      const char* st = lds + (s % NBUF) * G::STAGE;
+      // 32x32x16: lane l supplies row l % 32 of its operand block and the
+      // 8 k values of k-chunk 2 ks + l / 32 (16 bytes)
+      const int r32 = lane & 31, kh = lane >> 5;
+#pragma unroll
+      for (int ks = 0; ks < KS / 16; ++ks) {
+        const int kc = 2 * ks + kh;
+        u32x4 bh[2], bl[2];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int R = wn * 64 + y * 32 + r32;
+          bh[y] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(1, R, 0, kc));
+          if (SPLIT) bl[y] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(1, R, 1, kc));
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int R = wm * 128 + x * 32 + r32;
+          const u32x4 ah = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(0, R, 0, kc));
+          u32x4 al;
+          if (SPLIT) al = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(0, R, 1, kc));
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            if constexpr (MODE == SM_F16) {
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, ah),
+                                                                 __builtin_bit_cast(f16x8, bh[y]), acc[x][y], 0, 0, 0);
+            } else {
+              const bf16x8 a = __builtin_bit_cast(bf16x8, ah), b = __builtin_bit_cast(bf16x8, bh[y]);
+              if constexpr (SPLIT) {
+                acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), b, acc[x][y], 0, 0, 0);
+                acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, bl[y]), acc[x][y], 0, 0, 0);
+              }
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[x][y], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+
+    // epilogue: register v of lane l in a 32 x 32 block holds row
+    // 8 (v / 4) + 4 (l / 32) + v % 4 and column l % 32 (sm_selftest_mfma);
+    // lower triangle mirrored, 16-bit copies (or float32 for a first
+    // refinement update); residual partial sums of the square
+    double part = 0.0;
+    const bool f32out = WHICH == 1 && (rec.flags & kTileStoreF32);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int R0 = r0 + wm * 128 + x * 32, C0 = c0 + wn * 64 + y * 32;
+        if (!wvalid || R0 >= npad || C0 >= npad) continue;
+        const int cc = C0 + (lane & 31);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int rb = R0 + 8 * g + 4 * (lane >> 5);
+          const f4 q = f4{acc[x][y][4 * g], acc[x][y][4 * g + 1], acc[x][y][4 * g + 2], acc[x][y][4 * g + 3]};
+          if (f32out) store_quad<SM_F32, WHICH>(q, Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part);
+          else store_quad<MODE, WHICH>(q, Out, shadow_off, nn, npad, rb, cc, alpha, rscale, part);
+        }
+      }
+    if (WHICH == 0) {
+      // the buffer of stage nst (no load fills it and no wave reads it)
+      double* red = reinterpret_cast<double*>(lds + (nst % NBUF) * G::STAGE);
+      part = wave_sum(part);
+      if (lane == 0) red[wid] = part;
+      __syncthreads();
+      if (tid == 0) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) sum += red[w];
+        partials[rec.part_idx] = sum;
+      }
+      // the other 64-tile slots this tile covers (lower triangle, inside n_pad)
+      if (tid > 0 && tid < 16) {
+        const int ti = 4 * bi + (tid >> 2), tj = 4 * bj + (tid & 3);
+        const int s0 = (4 * bi) * (4 * bi + 1) / 2 + 4 * bj;
+        if (ti < rec.tiles64 && tj < rec.tiles64 && ti >= tj)
+          partials[rec.part_idx + (ti * (ti + 1) / 2 + tj - s0)] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // 64-tile kernel variants: 0 = {full stage, linear walk}, 1 = {full stage,
 // XCD-aware}, 2 = {half stage, XCD-aware}
 template <int MODE, int WHICH, int V>
@@ -1029,10 +1268,14 @@ struct Launch {
   hipEvent_t e0, e1;
   template <typename K, typename... A>
   hipError_t go(K kernel, A... args) const {
+    return go_block(kBlock, kernel, args...);
+  }
+  template <typename K, typename... A>
+  hipError_t go_block(int block, K kernel, A... args) const {
     if (e0)
-      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, e0, e1, 0, args...);
+      hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, e0, e1, 0, args...);
     else
-      hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, args...);
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, args...);
     return hipGetLastError();
   }
 };
@@ -1051,13 +1294,24 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_
   switch (variant) {
     case 1: return launch_one<MODE, WHICH, 1>(mats, so, count, recs, partials, L);
     case 2: return launch_one<MODE, WHICH, 2>(mats, so, count, recs, partials, L);
+    case 6:
+      if constexpr (Pre<MODE>::value)
+        return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, true, 32, 2>, (float*)mats, so, count, recs,
+                          partials);
+      [[fallthrough]];
+    case 7:
+      if constexpr (Pre<MODE>::value)
+        if (variant == 7)
+          return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, true, 16, 4>, (float*)mats, so, count, recs,
+                            partials);
+      [[fallthrough]];
     case 3:
     case 4:
     case 5:
       if constexpr (MODE != SM_F64) {
         if (variant == 3)
           return L.go(ns_gemm128_kernel<MODE, WHICH, true>, (float*)mats, so, count, recs, partials);
-        if (variant == 5)
+        if (variant >= 5)
           return L.go(ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>, (float*)mats, so, count, recs, partials);
         return L.go(ns_gemm128_kernel<MODE, WHICH, false>, (float*)mats, so, count, recs, partials);
       } else {
@@ -1101,6 +1355,13 @@ static void* ptr_which(int variant) {
     case 4:
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, false>);
       else return kernel_ptr<MODE, WHICH, 1>();
+    case 6:
+      if constexpr (Pre<MODE>::value) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, true, 32, 2>);
+      [[fallthrough]];
+    case 7:
+      if constexpr (Pre<MODE>::value)
+        if (variant == 7) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, true, 16, 4>);
+      [[fallthrough]];
     case 5:
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>);
       else return kernel_ptr<MODE, WHICH, 1>();
@@ -1128,7 +1389,8 @@ int ns_gemm_blocks_per_cu(int mode, int which, int variant) {
     default: f = ptr_mode<SM_BF16X3>(which, variant); break;
   }
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  const int block = (variant >= 6 && mode >= SM_BF16) ? kBlock256 : kBlock;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, 0) != hipSuccess || nb < 1) nb = 1;
   c = nb;
   return nb;
 }
@@ -1526,7 +1788,7 @@ __global__ void selftest_kernel(int prec, double* out) {
     f4 acc{0, 0, 0, 0};
     acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
     for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
-  } else {
+  } else if (prec == SM_BF16 || prec == SM_BF16X3) {
     u16x8 a, b;
     for (int e = 0; e < 8; ++e) {
       a[e] = f32_to_bf16_bits(st_a(rl, 8 * kq + e));
@@ -1536,6 +1798,28 @@ __global__ void selftest_kernel(int prec, double* out) {
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                   __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
     for (int v = 0; v < 4; ++v) out[l * 4 + v] = acc[v];
+  } else {
+    // 32x32x16 (prec 5: f16, 6: bf16): lane l supplies A[l % 32][8 (l / 32) ..]
+    // and B[8 (l / 32) ..][l % 32]; out[lane * 16 + v] for the 16 registers
+    const int r32 = l & 31, kh = l >> 5;
+    f32x16 acc{};
+    if (prec == 5) {
+      f16x8 a, b;
+      for (int e = 0; e < 8; ++e) {
+        a[e] = (_Float16)st_a(r32, 8 * kh + e);
+        b[e] = (_Float16)st_b(8 * kh + e, r32);
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, acc, 0, 0, 0);
+    } else {
+      u16x8 a, b;
+      for (int e = 0; e < 8; ++e) {
+        a[e] = f32_to_bf16_bits(st_a(r32, 8 * kh + e));
+        b[e] = f32_to_bf16_bits(st_b(8 * kh + e, r32));
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                    __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    }
+    for (int v = 0; v < 16; ++v) out[l * 16 + v] = acc[v];
   }
 }
 

@@ -85,6 +85,19 @@ struct sm_plan {
   std::vector<hipEvent_t> prof_ev;  // pool, pairs (start, stop)
   std::vector<int> prof_cls;        // class of every recorded pair
 
+  // non-orthogonal basis: tile lists of the products by (chunk, kind: 0
+  // lower triangle, 1 all tiles, 2 the tile columns of the atom's own
+  // columns), per-submatrix scalars (c of T(S), its scratch), device copies
+  struct OvlJobs {
+    int chunk, kind, n;
+    sm::OvlJob* d;
+  };
+  std::vector<OvlJobs> ovl_jobs;
+  double* d_ovl = nullptr;          // [4 * max_subs]: c_i, residual sums, 1 / sqrt(c_i), spare
+  int32_t* d_ovl_xbuf = nullptr;    // [max_subs]
+  int ovl_chunk = -1;               // chunk whose Z_i the auxiliary workspace holds (-1: none)
+  const void* ovl_aux = nullptr;    // that workspace
+
   sm::WsLayout layout(int storage) const;
   // float offset of a float32 buffer's pre-converted operand copy
   int64_t shadow_off() const { return max_mats; }

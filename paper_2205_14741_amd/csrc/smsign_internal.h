@@ -169,11 +169,18 @@ hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int
                          int grid_subs, hipStream_t s);
 // 0: linear, 1: XCD-aware, 2: XCD-aware with half-depth LDS stages, 3: XCD-aware 128 x 128 tiles,
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices),
-// 5: as 3 with operands loaded six stages ahead
-constexpr int kGemmVariants = 6;
+// 5: as 3 with operands loaded six stages ahead,
+// 6: XCD-aware 256 x 256 tiles of 512 threads (bf16, f16, split bf16 only),
+// k-depth-32 stages one ahead, 7: the same with k-depth-16 stages three ahead
+constexpr int kGemmVariants = 8;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
-// exist for the float32-accumulating precisions and need n_pad % 64 == 0
-__host__ __device__ inline int tile_shift(int variant, int mode) { return (variant >= 3 && mode != SM_F64) ? 7 : 6; }
+// exist for the float32-accumulating precisions and need n_pad % 64 == 0,
+// 256-wide ones for the 16-bit precisions (the launcher maps variants 6 and
+// 7 to 5 for float32)
+__host__ __device__ inline int tile_shift(int variant, int mode) {
+  if (variant >= 6 && mode >= SM_BF16) return 8;
+  return (variant >= 3 && mode != SM_F64) ? 7 : 6;
+}
 // shadow_off: float offset of the operand copies (bf16 / f16 / split-bf16
 // products read them and write them for their outputs, except for
 // kTileStoreF32 tiles); 0 otherwise.
@@ -192,6 +199,32 @@ hipError_t launch_comm_probe(const DevPlan& p, int g0, int nsub, int max_m, int 
 hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, const SubState* st,
                               int shadow_kind, int64_t shadow_off, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);
+
+// Non-orthogonal basis (k_ovl.hip): one 64 x 64 output tile of a product
+// (local submatrix index, tile row, tile column).
+struct OvlJob {
+  int32_t l;
+  int16_t bi, bj;
+};
+hipError_t launch_ovl_fill(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int b, double dv, double dp,
+                           hipStream_t s);
+hipError_t launch_ovl_gather(const DevPlan& p, int g0, int nsub, int max_m, const double* V, double* mats, int b,
+                             hipStream_t s);
+hipError_t launch_ovl_gersh(const DevPlan& p, int g0, int nsub, double* mats, int b, double* out, int pad_one,
+                            sm_sub_stats* stats, hipStream_t s);
+hipError_t launch_ovl_scale(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int b, const double* v,
+                            int mode, hipStream_t s);
+hipError_t launch_ovl_copy(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int src, int dst,
+                           hipStream_t s);
+hipError_t launch_ovl_prod(const DevPlan& p, int g0, const OvlJob* jobs, int njobs, const double* A, int abuf,
+                           const int32_t* abuf_l, const double* B, int bbuf, double* C, int cbuf,
+                           const double* alpha_l, double alpha, double beta, int kind, double* res, hipStream_t s);
+hipError_t launch_ovl_slab_diff(const DevPlan& p, int g0, int nsub, const double* Z, int zbuf, const double* U,
+                                int ubuf, double* D, int dbuf, const double* f_l, hipStream_t s);
+hipError_t launch_ovl_scatter(const DevPlan& p, int g0, int nsub, const double* R, int rbuf, double* P, hipStream_t s);
+hipError_t launch_ovl_xbuf(const SubState* st, int nsub, int32_t* xbuf, hipStream_t s);
+hipError_t launch_ovl_zero(double* v, int n, hipStream_t s);
+hipError_t launch_ovl_max(const double* v, int n, double* out, hipStream_t s);
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                          const SubState* st, int probes, double* vecs, sm_sub_stats* stats, int max_npad,
                          hipStream_t s);

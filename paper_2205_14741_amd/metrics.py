@@ -64,6 +64,8 @@ def effective_variant(mode: int, variant: int, pad_to: int) -> int:
     tiles in float64 or on a plan padded to 32, and 16-bit products on a plan
     padded to 32 take the half-depth-stage kernel."""
     v = variant
+    if v >= 6 and mode < 2:      # 256-wide tiles: 16-bit operand copies only
+        v = 5
     if v >= 3 and (mode == 0 or pad_to < 64):
         v = 1
     if mode >= 2 and pad_to < 64:
@@ -72,8 +74,11 @@ def effective_variant(mode: int, variant: int, pad_to: int) -> int:
 
 
 def tile_shift(mode: int, variant: int, pad_to: int) -> int:
-    """log2 of the output tile width of that kernel (64 or 128)."""
-    return 7 if effective_variant(mode, variant, pad_to) >= 3 and mode != 0 else 6
+    """log2 of the output tile width of that kernel (64, 128 or 256)."""
+    v = effective_variant(mode, variant, pad_to)
+    if v >= 6:
+        return 8
+    return 7 if v >= 3 and mode != 0 else 6
 
 
 def slab_tiles(npad, loc, b, tshift):
@@ -155,6 +160,8 @@ def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
     runs for (precision, square/update, kernel variant) on a plan with the
     given padding; mirrors the variant fallback of the launcher."""
     v = effective_variant(mode, variant, pad_to)
+    if v >= 6:   # 256-wide tiles, 512 threads: <precision, kind, XCD-aware walk, stage depth, buffers>
+        return f"sm::ns_gemm256_kernel<{mode}, {which}, true, {32 if v == 6 else 16}, {2 if v == 6 else 4}>"
     if v >= 3:   # 128-wide tiles: <precision, kind, XCD-aware walk, prefetch depth>
         return f"sm::ns_gemm128_kernel<{mode}, {which}, {'false' if v == 4 else 'true'}, {6 if v == 5 else 1}>"
     kdiv = 2 if v == 2 else 1   # variant 2: half-depth LDS stages

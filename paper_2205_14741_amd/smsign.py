@@ -27,7 +27,8 @@ EXPORTED = (
     "sm_profile_enable", "sm_profile_read", "sm_last_error", "sm_version",
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
     "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
-    "sm_comm_probe", "sm_gershgorin_bracket_noalloc",
+    "sm_comm_probe", "sm_gershgorin_bracket_noalloc", "sm_overlap_inv_sqrt", "build_submatrices_overlap",
+    "assemble_P_overlap", "sm_density_matrix_overlap",
 )
 
 
@@ -100,7 +101,11 @@ def lib() -> C.CDLL:
         "assemble_P": (i32, [vp, i32, vp, vp, vp]),
         "energy_trace": (i32, [vp, vp, vp, vp, vp, vp]),
         "sm_density_matrix": (i32, [vp, vp, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp]),
-        "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
+        "sm_overlap_inv_sqrt": (i32, [vp, i32, vp, dbl, i32, vp, vp, vp, vp, vp]),
+        "build_submatrices_overlap": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, vp, vp]),
+        "assemble_P_overlap": (i32, [vp, i32, vp, vp, vp, vp]),
+        "sm_density_matrix_overlap": (i32, [vp, vp, vp, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp]),
+        "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
                              vp]),
         "sm_gershgorin_bracket": (i32, [vp, vp, vp, vp, vp]),
         "sm_gershgorin_bracket_noalloc": (i32, [vp, vp, vp, vp]),
@@ -264,10 +269,42 @@ def sm_density_matrix(plan: Plan, H, mu: float, opts: SignOpts, ws, P, stats, st
     return E.value, Ne.value
 
 
+def sm_overlap_inv_sqrt(plan: Plan, chunk: int, S, ws_aux, ws, tol=1e-12, max_iter=100, stream=None):
+    """Z_i = T_i(S)^(-1/2) of the chunk's submatrices into ws_aux buffer 0;
+    returns (steps, largest final residual)."""
+    it, r = C.c_int32(), C.c_double()
+    _check(lib().sm_overlap_inv_sqrt(plan.handle, int(chunk), _ptr(S), float(tol), int(max_iter), _ptr(ws_aux),
+                                     _ptr(ws), C.byref(it), C.byref(r), _stream(stream)))
+    return it.value, r.value
+
+
+def build_submatrices_overlap(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, ws_aux, stats,
+                              stream=None):
+    _check_ws(plan, ws, opts)
+    _check(lib().build_submatrices_overlap(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts), _ptr(ws),
+                                           _ptr(ws_aux), _ptr(stats), _stream(stream)))
+
+
+def assemble_P_overlap(plan: Plan, chunk: int, ws, ws_aux, P, stream=None):
+    _check(lib().assemble_P_overlap(plan.handle, int(chunk), _ptr(ws), _ptr(ws_aux), _ptr(P), _stream(stream)))
+
+
+def sm_density_matrix_overlap(plan: Plan, H, S, mu: float, opts: SignOpts, ws, ws_aux, P, stats, stream=None):
+    """P for S != I at fixed mu; returns (E = tr(PH), Ne = tr(PS))."""
+    _check_ws(plan, ws, opts)
+    _check_ws(plan, ws_aux, opts)
+    E, Ne = C.c_double(), C.c_double()
+    _check(lib().sm_density_matrix_overlap(plan.handle, _ptr(H), _ptr(S), float(mu), C.byref(opts), _ptr(ws),
+                                           _ptr(ws_aux), _ptr(P), _ptr(stats), C.byref(E), C.byref(Ne),
+                                           _stream(stream)))
+    return E.value, Ne.value
+
+
 def sm_find_mu(plan: Plan, H, n_target: float, opts: SignOpts, ws, stats, P=None, accept=0.5,
-               max_steps=60, stream=None, energy=False):
+               max_steps=60, stream=None, energy=False, mu_start=None):
     """(mu, bisection steps, [(mu_k, Ne_k)]), and with energy=True (needs P)
-    also E = tr(P H) and Ne = tr P of the returned P."""
+    also E = tr(P H) and Ne = tr P of the returned P.  mu_start: warm start
+    (evaluated first; None = the cold rule)."""
     _check_ws(plan, ws, opts)
     if energy and P is None:
         raise SmError(SM_ERR_ARG, "sm_find_mu: energy=True needs P")
@@ -277,7 +314,7 @@ def sm_find_mu(plan: Plan, H, n_target: float, opts: SignOpts, ws, stats, P=None
     mh = np.zeros(max_steps)
     nh = np.zeros(max_steps)
     _check(lib().sm_find_mu(plan.handle, _ptr(H), float(n_target), float(accept), int(max_steps),
-                            C.byref(opts), _ptr(ws), _ptr(P), _ptr(stats), C.byref(mu),
+                            float("nan") if mu_start is None else float(mu_start), C.byref(opts), _ptr(ws), _ptr(P), _ptr(stats), C.byref(mu),
                             C.byref(steps), mh.ctypes.data, nh.ctypes.data,
                             C.byref(E) if energy else None, C.byref(Ne) if energy else None,
                             _stream(stream)))
@@ -301,8 +338,10 @@ def sm_gershgorin_bracket_noalloc(plan: Plan, H, lohi, stream=None):
 
 
 def sm_selftest_mfma(prec) -> np.ndarray:
-    out = np.zeros(256)
+    """prec: a precision name / code (its 16x16 instruction, 256 values) or
+    5 / 6 (the 32x32x16 f16 / bf16 instruction, 1024 values)."""
     p = PREC[prec] if isinstance(prec, str) else int(prec)
+    out = np.zeros(1024 if p >= 5 else 256)
     _check(lib().sm_selftest_mfma(p, out.ctypes.data))
     return out
 

@@ -1,6 +1,6 @@
-"""The benchmark's command line, on the CPU: its defaults (the lattice
-workload, the headline schedule among the modes, a bounded run) and its
-refusal of more than one GPU before any GPU work."""
+"""The benchmark's command line, on the CPU: its defaults (the water-like
+workload, the float64 reference and the headline schedule, a bounded run)
+and its refusal of more than one GPU before any GPU work."""
 import os
 import subprocess
 import sys
@@ -12,11 +12,12 @@ def test_defaults():
     sys.path.insert(0, ROOT)
     import bench
     a = bench.parse([])
-    assert a.gpus == 1 and a.config == "cfg2"
-    modes = a.modes.split(",")
-    assert "f64" in modes and "bf16x3+L" in modes
-    assert 1 <= a.steps <= 50 and 0 <= a.warmup <= 10
+    assert a.gpus == 1 and a.config == "cfg3" and a.modes is None
+    assert 1 <= a.steps <= 50 and 0 <= a.warmup <= 10 and a.ref_steps >= 1
     assert a.pad in (32, 64)
+    a = bench.parse(["--steps", "20", "--warmup", "5", "--config", "cfg4"])
+    assert (a.steps, a.warmup, a.config) == (20, 5, "cfg4")
+    assert "cfg3" in bench.WORKLOADS and "cfg4" in bench.WORKLOADS
 
 
 def test_more_than_one_gpu_is_refused():

@@ -36,6 +36,18 @@ def test_mfma_lane_layout(prec, dev):
     np.testing.assert_array_equal(out, expect)
 
 
+@pytest.mark.parametrize("code", [5, 6])
+def test_mfma_lane_layout_32x32(code, dev):
+    """32x32x16 f16 (5) / bf16 (6): register v of lane l holds row
+    8 (v / 4) + 4 (l / 32) + v % 4, column l % 32."""
+    out = sm.sm_selftest_mfma(code)
+    A = np.array([[((r + 3 * k) % 11) - 5 for k in range(16)] for r in range(32)], float)
+    B = np.array([[((2 * k + 5 * c) % 13) - 6 for c in range(32)] for k in range(16)], float)
+    D = A @ B
+    expect = np.array([D[8 * (v // 4) + 4 * (l // 32) + v % 4, l % 32] for l in range(64) for v in range(16)])
+    np.testing.assert_array_equal(out, expect)
+
+
 def _oracle_T_scaled(view, i, mu, c):
     return om.submatrix(view, i, mu) * (1.0 / c)
 
@@ -381,16 +393,36 @@ def test_trajectory_against_float64(prec, dev):
 _X0_CACHE = {}
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("prec,dp_max", [("f32", 1e-5), ("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)])
 def test_gemm_variants_parity(variant, prec, dp_max, dev):
     """Every GEMM kernel variant (tile walk, LDS stage depth, 128-wide tiles with
-    half-filled edge tiles) against the oracle."""
+    half-filled edge tiles, 256-wide tiles with direct-to-LDS loads, which
+    float32 runs on the 128-wide kernel) against the oracle."""
     m = synth.water_system(24, 1.4, 5)
     mu = gap_mu(m)
     P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=64, variant=variant)
     dP, dE, dNe = _compare(m, P, E, Ne, mu)
     assert dP < dp_max, (variant, prec, dP)
+    assert np.all(st["status"] >= 1)
+
+
+@pytest.mark.parametrize("variant", [6, 7])
+@pytest.mark.parametrize("prec,dp_max", [("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)])
+def test_gemm256_multi_tile(prec, dp_max, variant, dev):
+    """The 256-wide tiles on submatrices of three to four tile rows (n 590 to
+    830: diagonal tiles, interior tiles, edge tiles cut by n_pad), sampled
+    P columns against the oracle, and every submatrix converged."""
+    m = synth.water_system(64, 1.95, 2)
+    mu = gap_mu(m)
+    P, E, Ne, st, plan = run_fixed_mu(m, mu, prec, pad_to=64, variant=variant)
+    npad = plan.info()["npad"]
+    assert npad.min() > 512 and npad.max() > 768
+    atoms = list(range(0, m.n_atoms, 23))
+    dP, _, _ = _compare(m, P, E, Ne, mu, atoms=atoms)
+    print(f"{prec}: n_pad {npad.min()}-{npad.max()}, max|dP| (sampled) {dP:.2e}, iters "
+          f"{st['iters'].min()}-{st['iters'].max()}")
+    assert dP < dp_max
     assert np.all(st["status"] >= 1)
 
 

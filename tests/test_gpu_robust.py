@@ -145,6 +145,33 @@ def test_find_mu_history_matches_oracle(make, dev):
     assert any(nb < m.n_occ - 0.5 for _, nb in hist_o) and any(nb > m.n_occ + 0.5 for _, nb in hist_o)
 
 
+def test_find_mu_warm_start_matches_oracle(dev):
+    """Warm start from a guess inside the occupied band (Ne short of the
+    target): the guess becomes lo and the GPU path's midpoints and electron
+    counts follow the oracle's warm-started history; a guess inside the gap
+    is accepted with one evaluation."""
+    m = synth.with_onsite_shift(synth.config2(), 5, 4, 40.0)
+    cache = om.SpectralCache(m)
+    lam = np.sort(cache.lam)
+    g = float(lam[len(lam) // 4])
+    mu_o, steps_o, hist_o = om.find_mu(m, m.n_occ, cache=cache, mu_start=g)
+    assert steps_o >= 3 and hist_o[0][1] < m.n_occ - 0.5
+    plan = sm.Plan(m, 32)
+    o = sm.default_opts("f64", max_iter=60)
+    H = h_dev(m)
+    work = sm.Workspace(plan, sm.SM_F64, H.device)
+    mu, steps, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, mu_start=g)[:3]
+    print(" ".join(f"({a:.4f}, {na:.3f})" for a, na in hist))
+    assert steps == steps_o
+    for k, ((a, na), (b, nb)) in enumerate(zip(hist, hist_o)):
+        # the guess lies inside a band: eigenvalues next to it are not resolved
+        # in 60 iterations, so that pass's count is close, not exact (the
+        # decision it drives is the same); the later midpoints converge
+        assert abs(a - b) < 1e-12 * max(1.0, abs(b)) and abs(na - nb) < (0.05 if k == 0 else 1e-8)
+    mu2, steps2, hist2 = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, mu_start=mu)[:3]
+    assert (mu2, steps2) == (mu, 1)
+
+
 @pytest.mark.parametrize("prec,dp_max", [("f64", 1e-9), ("bf16x3", 1e-4)])
 def test_index_set_above_4096_orbitals(prec, dp_max, dev):
     """Two atoms of 2100 orbitals each, fully coupled: both submatrices are the
