@@ -98,8 +98,11 @@ typedef struct {
                             128; otherwise runs as 1), 4 = 128 x 128 tiles walked in list
                             order (all XCDs on the same submatrices: their operands stay in
                             the shared last-level cache), 5 = as 3 with the operands loaded
-                            six stages ahead (large submatrices).  bf16 / f16 / split-bf16
-                            products on a plan padded to 32 always run as 2 */
+                            six stages ahead (large submatrices), 6 = 256 x 256 tiles of
+                            512 threads with direct global -> LDS operand loads one
+                            k-depth-32 stage ahead (bf16 / f16 / split bf16; float32 runs
+                            as 5), 7 = as 6 with k-depth-16 stages three ahead.  bf16 / f16 /
+                            split-bf16 products on a plan padded to 32 always run as 2 */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,
                             scheduler, updates) into one HIP graph, cached per plan / chunk /
@@ -449,12 +452,16 @@ int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
  * precisions of `opts` (used when opts->variant == -1).  variant_mask: bit v
  * set = try variant v (0 = all).
  *   best_out   host int32 (may be NULL): the chosen variant
- *   times_ms   host double[6] (may be NULL): sign time of each variant (-1: not
- *              applicable to this plan / precision)
+ *   times_ms   host double[SM_GEMM_VARIANTS] (may be NULL): sign time of each
+ *              variant (-1: not tried, or not applicable to this plan / precision)
  * Synchronous.  Leaves the workspace holding the last variant's result. */
 int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
                 const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, int32_t repeats,
                 int32_t variant_mask, int32_t* best_out, double* times_ms, void* stream);
+/* Number of GEMM kernel variants (sm_sign_opts.variant in [0, SM_GEMM_VARIANTS)). */
+#define SM_GEMM_VARIANTS 8
+int32_t sm_gemm_variants(void);
+
 /* Tuned variant per precision (int32[5], indexed by sm_prec): `get` receives
  * the table, `set` (if not NULL) replaces it -- to persist the autotuner's
  * choices across processes.  Either pointer may be NULL. */

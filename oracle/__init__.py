@@ -14,4 +14,7 @@ Modules
   newton_schulz -- the plain dense Newton-Schulz sign iteration in float64
                 (iteration counts and the convergence rule), and the scalar map.
   mlp        -- float64 forward / backward / Adam of the scaling network.
+  overlap    -- a non-orthogonal basis: inverse square roots (Eq. 12 by its
+                definition), P of Eq. 14 on every submatrix pair by the
+                generalized symmetric eigendecomposition, tr(PH), tr(PS).
 """

@@ -614,6 +614,8 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
   return SM_OK;
 }
 
+int32_t sm_gemm_variants(void) { return kGemmVariants; }
+
 int sm_plan_tuning(sm_plan* p, int32_t* get, const int32_t* set) {
   if (!p) return set_error(SM_ERR_ARG, "sm_plan_tuning: null plan");
   if (get) std::memcpy(get, p->tuned, sizeof(p->tuned));

@@ -172,7 +172,7 @@ hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int
 // 5: as 3 with operands loaded six stages ahead,
 // 6: XCD-aware 256 x 256 tiles of 512 threads (bf16, f16, split bf16 only),
 // k-depth-32 stages one ahead, 7: the same with k-depth-16 stages three ahead
-constexpr int kGemmVariants = 8;
+constexpr int kGemmVariants = SM_GEMM_VARIANTS;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
 // exist for the float32-accumulating precisions and need n_pad % 64 == 0,
 // 256-wide ones for the 16-bit precisions (the launcher maps variants 6 and

@@ -7,6 +7,8 @@
         --cmd-write "..." --out SUMMARY.txt
     python -m paper_2205_14741_amd.profsum mfma --csv MOPS_counter_collection.csv \
         --cmd "<the profiled command>" --out SUMMARY.txt
+    python -m paper_2205_14741_amd.profsum counters --csv A.csv B.csv --cmd "<cmd A>" "<cmd B>" \
+        [--kernels ns_gemm] --out SUMMARY.txt
 
 `stats` lists the kernels of a kernel-trace run by total time (calls, average,
 total, share).  `traffic` averages the FETCH_SIZE and WRITE_SIZE counters (KiB
@@ -111,6 +113,27 @@ def mfma_summary(csv_path: str, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def counters_summary(csv_paths: list, cmds: list, kernels_like: str = "") -> str:
+    """Mean value per dispatch of every counter in the given counter-collection
+    CSVs (one rocprofv3 --pmc pass each), by kernel: one line per (kernel,
+    counter).  kernels_like: keep only kernels whose name contains it."""
+    rows = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            k = short_name(r["Kernel_Name"])
+            if kernels_like and kernels_like not in k:
+                continue
+            rows[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    out = ["# rocprofv3 --pmc, one pass per command (counters summed over the chip, mean per dispatch)"]
+    out += [f"# command (pass {i + 1}): {c}" for i, c in enumerate(cmds)]
+    out.append("# counter <kernel> | dispatches | counter | mean per dispatch")
+    for k in sorted(rows):
+        for cn in sorted(rows[k]):
+            v = rows[k][cn]
+            out.append(f"counter {k} | {len(v)} | {cn} | {sum(v) / len(v):.6g}")
+    return "\n".join(out) + "\n"
+
+
 def read_traffic(path: str, symbol: str):
     """Scaled HBM bytes per dispatch of `symbol` from a traffic summary, or
     None when the summary is missing, lacks the kernel, or was taken on GEMM
@@ -142,6 +165,11 @@ def main():
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out", required=True)
+    cn = sub.add_parser("counters")
+    cn.add_argument("--csv", nargs="+", required=True)
+    cn.add_argument("--cmd", dest="commands", nargs="+", required=True)
+    cn.add_argument("--kernels", default="")
+    cn.add_argument("--out", required=True)
     mf = sub.add_parser("mfma")
     mf.add_argument("--csv", required=True)
     mf.add_argument("--cmd", dest="command", required=True)
@@ -151,6 +179,8 @@ def main():
         text = stats_summary(a.csv, a.command)
     elif a.cmd == "mfma":
         text = mfma_summary(a.csv, a.command)
+    elif a.cmd == "counters":
+        text = counters_summary(a.csv, a.commands, a.kernels)
     else:
         text = traffic_summary(a.fetch, a.write, a.copy_bytes, a.cmd_fetch, a.cmd_write)
     with open(a.out, "w") as fh:

@@ -28,7 +28,7 @@ EXPORTED = (
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
     "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
     "sm_comm_probe", "sm_gershgorin_bracket_noalloc", "sm_overlap_inv_sqrt", "build_submatrices_overlap",
-    "assemble_P_overlap", "sm_density_matrix_overlap",
+    "assemble_P_overlap", "sm_density_matrix_overlap", "sm_gemm_variants",
 )
 
 
@@ -122,6 +122,7 @@ def lib() -> C.CDLL:
         "sm_plan_set_mlp": (i32, [vp, vp]),
         "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, i32, vp, vp, vp]),
         "sm_plan_tuning": (i32, [vp, vp, vp]),
+        "sm_gemm_variants": (i32, []),
         "sm_ws_storage": (i32, [C.POINTER(SignOpts)]),
         "sm_comm_probe": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, vp]),
         "sm_last_error": (C.c_char_p, []),
@@ -421,7 +422,6 @@ def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):
     _check(lib().sm_plan_set_mlp(plan.handle, None if mlp is None else mlp.handle))
 
 
-N_VARIANTS = 6
 
 
 def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats, repeats: int = 2,
@@ -429,7 +429,7 @@ def sm_autotune(plan: Plan, chunk: int, H, mu: float, opts: SignOpts, ws, stats,
     """(best variant, sign-phase ms per variant) -- the plan keeps the choice."""
     _check_ws(plan, ws, opts)
     best = C.c_int32()
-    t = np.zeros(N_VARIANTS)
+    t = np.zeros(int(lib().sm_gemm_variants()))
     mask = 0 if variants is None else sum(1 << v for v in variants)
     _check(lib().sm_autotune(plan.handle, int(chunk), _ptr(H), float(mu), C.byref(opts), _ptr(ws),
                              _ptr(stats), int(repeats), int(mask), C.byref(best), t.ctypes.data,
