@@ -132,17 +132,12 @@ def train_scaling_net(sm, synth, dev, seed):
     o = sm.default_opts("f64", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
     work = sm.Workspace(plan, sm.storage_prec(o), dev)
     sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats)
-    st = work.stats_host()
-    ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
-    X = torch.from_numpy(np.ascontiguousarray(st["feat"][ok]).astype(np.float32)).to(dev)
-    Y = torch.from_numpy(np.stack([np.log(st["rho_est"] / st["gersh"]),
-                                   np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok]
-                         .astype(np.float32)).to(dev)
+    X, Y = sm.sm_scaling_pairs(work.stats, m.n_atoms)
     net = sm.Mlp(seed=seed)
     hist = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
-    print(f"# scaling network: {int(ok.sum())} samples from seed {seed}, loss {hist[0]:.3g} -> {hist[-1]:.3g}",
+    print(f"# scaling network: {X.shape[0]} samples from seed {seed}, loss {hist[0]:.3g} -> {hist[-1]:.3g}",
           file=sys.stderr, flush=True)
-    return net, {"train_seed": seed, "samples": int(ok.sum()), "loss_first": float(hist[0]),
+    return net, {"train_seed": seed, "samples": int(X.shape[0]), "loss_first": float(hist[0]),
                  "loss_last": float(hist[-1])}
 
 
@@ -181,20 +176,15 @@ def train_scaling_net_water(sm, synth, dev, seed, cfg, mu_iters, accept_rel):
     t0 = time.perf_counter()
     mu, k, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, accept=max(0.5, accept_rel * m.n_occ))
     t_mu = time.perf_counter() - t0
-    st = work.stats_host()
-    ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
-    X = torch.from_numpy(np.ascontiguousarray(st["feat"][ok]).astype(np.float32)).to(dev)
-    Y = torch.from_numpy(np.stack([np.log(st["rho_est"] / st["gersh"]),
-                                   np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok]
-                         .astype(np.float32)).to(dev)
+    X, Y = sm.sm_scaling_pairs(work.stats, m.n_atoms)
     net = sm.Mlp(seed=seed)
     hist_l = sm.sm_mlp_train(net, X, Y, X.shape[0], epochs=300, batch=128, lr=2e-3)
-    print(f"# scaling network: {int(ok.sum())} samples ({m.name}, seed {seed}, mu {mu:.4f} after {k} "
+    print(f"# scaling network: {X.shape[0]} samples ({m.name}, seed {seed}, mu {mu:.4f} after {k} "
           f"bisection passes in {t_mu:.1f} s), loss {hist_l[0]:.3g} -> {hist_l[-1]:.3g}",
           file=sys.stderr, flush=True)
     del work
     return net, {"train_system": m.name, "n_sub": int(m.n_atoms), "train_seed": seed,
-                 "samples": int(ok.sum()), "mu": mu, "bisection_passes": k, "bisection_s": t_mu,
+                 "samples": int(X.shape[0]), "mu": mu, "bisection_passes": k, "bisection_s": t_mu,
                  "loss_first": float(hist_l[0]), "loss_last": float(hist_l[-1])}, mu
 
 
@@ -399,6 +389,19 @@ def water_bench(a):
     t0 = time.perf_counter()
     Po = om.density_matrix(m, mu, atoms=atoms)
     t_or = time.perf_counter() - t0
+    # the CPU baseline: the oracle as it stands on a bounded sample of about
+    # --cpu-seconds of work (the checked submatrices and more of the same system)
+    n_base, t_base = len(atoms), t_or
+    if a.cpu_seconds > t_or:
+        more = int((a.cpu_seconds - t_or) / max(t_or / len(atoms), 1e-3))
+        rest = np.setdiff1d(np.arange(m.n_atoms), atoms)
+        extra = sorted(rng.choice(rest, size=min(more, rest.size), replace=False).tolist())
+        if extra:
+            print(f"# oracle baseline: {len(extra)} more submatrices ...", file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            om.density_matrix(m, mu, atoms=extra)
+            t_base += time.perf_counter() - t0
+            n_base += len(extra)
     sel = ~np.isnan(Po)
     E_or = float(np.sum(Po[sel] * m.vals[sel]))
     for mode, r in res.items():
@@ -438,11 +441,11 @@ def water_bench(a):
         traffic = profsum.read_traffic(os.path.join(ROOT, "profiles", f"ns_gemm_traffic_{tag}.txt"), kk["name"])
         out["roofline"] = roofline_of(kk, traffic, metrics)
     if a.cpu_seconds > 0:
-        out["cpu_baseline"] = {"value": len(atoms) / t_or, "unit": "submatrices/s", "cores": blas_threads(),
+        out["cpu_baseline"] = {"value": n_base / t_base, "unit": "submatrices/s", "cores": blas_threads(),
                                "kind": "oracle", "host_cpus": ncpu, "cpu_model": model,
                                "sample": f"float64 eigendecomposition oracle (numpy / LAPACK, threaded BLAS), "
-                                         f"P columns of {len(atoms)} sampled submatrices of the same system at "
-                                         f"the benchmark's mu ({t_or:.1f} s)"}
+                                         f"P columns of {n_base} randomly sampled submatrices of the same "
+                                         f"system at the benchmark's mu ({t_base:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 
@@ -451,16 +454,6 @@ def _traj_step(args):
     import synth
     t, seed, n_mol = args
     return synth.config5_step(t, seed, n_mol=n_mol)
-
-
-def _labels(st, np_):
-    """Training pairs of an explicit (power-scaled, plain) pass: the features
-    and (log rho_est / c_G, log lb / c_G) where both bounds were found."""
-    ok = (st["lb_est"] > 0) & (st["rho_est"] > 0)
-    X = np_.ascontiguousarray(st["feat"][ok]).astype(np_.float32)
-    Y = np_.stack([np_.log(st["rho_est"] / st["gersh"]),
-                   np_.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok].astype(np_.float32)
-    return X, Y
 
 
 def trajectory_bench(a):
@@ -475,12 +468,16 @@ def trajectory_bench(a):
     on the fly).  At the first and the last learned step the Gershgorin plain
     split-bf16 pass and the float64 plain pass run on the same geometry."""
     import concurrent.futures as cf
+    import multiprocessing as mp
+    T, T0 = a.traj_steps, a.train_steps
+    # the generator workers (CPU only) are all forked here, before this
+    # process touches the GPU, and stay busy generating up to 6 steps ahead
+    depth = 6
+    pool = cf.ProcessPoolExecutor(max_workers=depth, mp_context=mp.get_context("fork"))
+    futs = {t: pool.submit(_traj_step, (t, a.seed, a.n_mol)) for t in range(min(T, depth))}
     import torch
     from paper_2205_14741_amd import smsign as sm
     dev = torch.device("cuda:0")
-    T, T0 = a.traj_steps, a.train_steps
-    pool = cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1))
-    futs = {t: pool.submit(_traj_step, (t, a.seed, a.n_mol)) for t in range(min(T, 6))}
     plan, pat, replans = None, None, 0
     mu = None
     X_all, Y_all = [], []
@@ -496,8 +493,8 @@ def trajectory_bench(a):
     work = None
     for t in range(T):
         m = futs.pop(t).result()
-        if t + 6 < T:
-            futs[t + 6] = pool.submit(_traj_step, (t + 6, a.seed, a.n_mol))
+        if t + depth < T:
+            futs[t + depth] = pool.submit(_traj_step, (t + depth, a.seed, a.n_mol))
         key = (m.block_size.tobytes(), m.col_ptr.tobytes(), m.row_idx.tobytes())
         if plan is None or key != pat:
             tuned = sm.sm_plan_tuning(plan) if plan is not None else None
@@ -524,14 +521,14 @@ def trajectory_bench(a):
                                             mu_start=mu, accept=acc)
             torch.cuda.synchronize()
             st = work.stats_host()
-            X, Y = _labels(st, np)
-            X_all.append(X)
-            Y_all.append(Y)
+            X, Y = sm.sm_scaling_pairs(work.stats, m.n_atoms)
+            X_all.append(X.clone())
+            Y_all.append(Y.clone())
             row.update({"explicit_s": time.perf_counter() - t0, "explicit_iters": float(st["iters"].mean()),
                         "explicit_passes": k, "E_explicit": E, "pairs": int(X.shape[0])})
             if t >= T0 - 1:
-                Xd = torch.from_numpy(np.concatenate(X_all)).to(dev)
-                Yd = torch.from_numpy(np.concatenate(Y_all)).to(dev)
+                Xd = torch.cat(X_all).contiguous()
+                Yd = torch.cat(Y_all).contiguous()
                 if net is None:
                     net = sm.Mlp(seed=a.seed + 1)
                 hist = sm.sm_mlp_train(net, Xd, Yd, Xd.shape[0], epochs=300 if t == T0 - 1 else 60,

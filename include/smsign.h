@@ -434,6 +434,15 @@ int sm_mlp_infer(sm_mlp* mlp, const float* X, int64_t ldx, int64_t n, float* Y, 
  * for device inputs X (stride ldx) and targets T[n][2].  Synchronous. */
 int sm_mlp_loss_grad(sm_mlp* mlp, const float* X, int64_t ldx, const float* T, int64_t n,
                      double* loss, float* grad, void* stream);
+/* Training pairs of the scaling network from the per-submatrix records of an
+ * explicit pass (power-iteration scale, plain Newton-Schulz): every record
+ * with rho_est > 0, lb_est > 0 and gersh > 0 gives X[k] = its 16 features and
+ * T[k] = (log(rho_est / gersh), log(lb_est * scale / gersh)), the targets of
+ * sm_mlp_train, in record order.  stats, X (float[n][16]) and T (float[n][2])
+ * are device arrays of the caller; *n_pairs (host) = pairs written.
+ * Synchronises `stream`. */
+int sm_scaling_pairs(const sm_sub_stats* stats, int64_t n, float* X, float* T, int64_t* n_pairs,
+                     void* stream);
 /* Mini-batch Adam: `epochs` passes over the n samples in batches of `batch`
  * (order shuffled per epoch from shuffle_seed, or kept if 0), learning rate
  * lr; with fit_norm the normalisation is first set to the samples' mean/std.

@@ -225,4 +225,49 @@ hipError_t launch_adam(float* theta, const float* g, float* m, float* v, float l
   return hipGetLastError();
 }
 
+// Training pairs from the per-submatrix records of an explicit pass (power
+// scale, plain Newton-Schulz): every record with both bounds found (rho_est
+// > 0, lb_est > 0) gives x = its 16 features and t = (log(rho_est / c_G),
+// log(lb_est c / c_G)), written in record order (one workgroup: a scan over
+// tiles of 1024 records).  n_out[0] = number of pairs.
+__global__ __launch_bounds__(1024) void scaling_pairs_kernel(const sm_sub_stats* __restrict__ st, int64_t n,
+                                                             float* __restrict__ X, float* __restrict__ T,
+                                                             int64_t* __restrict__ n_out) {
+  __shared__ int wsum[16];
+  __shared__ int64_t base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  for (int64_t t0 = 0; t0 < n; t0 += blockDim.x) {
+    const int64_t i = t0 + threadIdx.x;
+    const bool ok = i < n && st[i].rho_est > 0.0 && st[i].lb_est > 0.0 && st[i].gersh > 0.0;
+    const unsigned long long bal = __ballot(ok);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wv; ++w) off += wsum[w];
+    if (ok) {
+      const int64_t k = base + off + before;
+      for (int f = 0; f < kIn; ++f) X[k * kIn + f] = st[i].feat[f];
+      T[2 * k] = (float)log(st[i].rho_est / st[i].gersh);
+      T[2 * k + 1] = (float)log(st[i].lb_est * st[i].scale / st[i].gersh);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tot += wsum[w];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_out = base;
+}
+
+hipError_t launch_scaling_pairs(const sm_sub_stats* st, int64_t n, float* X, float* T, int64_t* n_out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(scaling_pairs_kernel, dim3(1), dim3(1024), 0, s, st, n, X, T, n_out);
+  return hipGetLastError();
+}
+
 }  // namespace sm

@@ -204,4 +204,18 @@ int sm_plan_set_mlp(sm_plan* p, sm_mlp* m) {
   return SM_OK;
 }
 
+int sm_scaling_pairs(const sm_sub_stats* stats, int64_t n, float* X, float* T, int64_t* n_pairs, void* stream) {
+  if (!stats || !X || !T || !n_pairs) return set_error(SM_ERR_ARG, "sm_scaling_pairs: null argument");
+  if (n < 0) return set_error(SM_ERR_ARG, "sm_scaling_pairs: n < 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int64_t* d = nullptr;
+  SM_HIP(hipMalloc(&d, sizeof(int64_t)));
+  hipError_t e = launch_scaling_pairs(stats, n, X, T, d, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(n_pairs, d, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_error(e, "sm_scaling_pairs");
+  return SM_OK;
+}
+
 }  // extern "C"

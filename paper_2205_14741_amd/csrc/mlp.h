@@ -17,6 +17,8 @@ hipError_t launch_mlp_grad(const float* theta, const float* norm, const float* X
                            const int32_t* perm, int64_t b0, int64_t nb, float inv_n, float* part,
                            double* loss_part, float* grad, double* loss_out, hipStream_t s);
 hipError_t launch_adam(float* theta, const float* g, float* m, float* v, float lr, int step, hipStream_t s);
+hipError_t launch_scaling_pairs(const sm_sub_stats* st, int64_t n, float* X, float* T, int64_t* n_out,
+                                hipStream_t s);
 
 }  // namespace sm
 

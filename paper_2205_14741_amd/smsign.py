@@ -28,7 +28,7 @@ EXPORTED = (
     "sm_mlp_create", "sm_mlp_destroy", "sm_mlp_set_weights", "sm_mlp_get_weights", "sm_mlp_infer",
     "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
     "sm_comm_probe", "sm_gershgorin_bracket_noalloc", "sm_overlap_inv_sqrt", "build_submatrices_overlap",
-    "assemble_P_overlap", "sm_density_matrix_overlap", "sm_gemm_variants",
+    "assemble_P_overlap", "sm_density_matrix_overlap", "sm_gemm_variants", "sm_scaling_pairs",
 )
 
 
@@ -123,6 +123,7 @@ def lib() -> C.CDLL:
         "sm_autotune": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, i32, i32, vp, vp, vp]),
         "sm_plan_tuning": (i32, [vp, vp, vp]),
         "sm_gemm_variants": (i32, []),
+        "sm_scaling_pairs": (i32, [vp, i64, vp, vp, vp, vp]),
         "sm_ws_storage": (i32, [C.POINTER(SignOpts)]),
         "sm_comm_probe": (i32, [vp, i32, vp, dbl, C.POINTER(SignOpts), vp, vp, vp]),
         "sm_last_error": (C.c_char_p, []),
@@ -416,6 +417,17 @@ def sm_mlp_train(mlp: Mlp, X, T, n: int, epochs: int, batch: int, lr: float, ldx
                               float(lr), 1 if fit_norm else 0, int(shuffle_seed), hist.ctypes.data,
                               _stream(stream)))
     return hist[:epochs]
+
+
+def sm_scaling_pairs(stats, n: int, stream=None):
+    """Training pairs (X [k, 16], T [k, 2], device float32) of the scaling
+    network from the records `stats` (device) of an explicit pass."""
+    import torch
+    X = torch.empty((max(n, 1), 16), dtype=torch.float32, device=stats.device)
+    T = torch.empty((max(n, 1), 2), dtype=torch.float32, device=stats.device)
+    k = C.c_int64()
+    _check(lib().sm_scaling_pairs(_ptr(stats), int(n), _ptr(X), _ptr(T), C.byref(k), _stream(stream)))
+    return X[:k.value], T[:k.value]
 
 
 def sm_plan_set_mlp(plan: Plan, mlp: Mlp | None):

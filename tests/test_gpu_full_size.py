@@ -8,7 +8,11 @@ times (its own defaults, schedule, scaling network and autotuned kernel):
   the plain float64 path within 1e-9;
 * the 1000-molecule water-like system (3000 submatrices, n ~ 2300-2900,
   several workspace chunks), the same schedule, on sampled submatrices: their
-  P columns and their share of tr(PH).
+  P columns and their share of tr(PH);
+* the mixed batch of four water-like systems (250 / 500 / 1000 / 2000
+  molecules, 11250 submatrices, n 1335-4458) in one plan, the same schedule
+  with a network trained on the two extreme cutoffs, on sampled submatrices
+  of every part including the largest and the smallest.
 """
 import numpy as np
 import pytest
@@ -70,7 +74,7 @@ def test_water1000_bench_configuration_sampled(dev):
     plan = sm.Plan(m, 64, int(a.chunk_gb * 2 ** 30 / 4))
     assert m.n_atoms == 3000 and plan.n_chunks > 1
     mu = -2.95          # the benchmark's mu, inside this family's gap
-    net, _ = bench.train_scaling_net_water(sm, synth, dev, a.seed + 1, mu)
+    net, _, _ = bench.train_scaling_net_water(sm, synth, dev, a.seed + 1, "cfg3", a.mu_iters, a.mu_accept_rel)
     sm.sm_plan_set_mlp(plan, net)
     o = bench.mode_opts(sm, "bf16x3+L", a)
     work = sm.Workspace(plan, sm.storage_prec(o), dev)
@@ -94,3 +98,43 @@ def test_water1000_bench_configuration_sampled(dev):
           f"learned accepted {np.mean(st['scale_src'] == 2):.3f}")
     assert dP <= 1e-4 and dE <= 1e-5
     assert np.all(st["status"] >= 1)
+
+
+def test_mixed4_batch_sampled(dev):
+    bench, a = _bench()
+    m = synth.config4(a.seed)
+    assert m.n_atoms == 11250
+    H = h_dev(m)
+    plan = sm.Plan(m, 64, int(a.chunk_gb * 2 ** 30 / 4))
+    info = plan.info()
+    n = info["n"]
+    net, _, mu0 = bench.train_scaling_net_water(sm, synth, dev, a.seed + 1, "cfg4", a.mu_iters, a.mu_accept_rel)
+    sm.sm_plan_set_mlp(plan, net)
+    o = bench.mode_opts(sm, "bf16x3+L", a)
+    work = sm.Workspace(plan, sm.storage_prec(o), dev)
+    sm.sm_autotune(plan, 0, H, mu0, o, work.ws, work.stats, repeats=1, variants=(5, 6))
+    # mu of the batch: the bisection rule warm-started at the training system's
+    mu, k, hist = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P, mu_start=mu0,
+                                accept=bench.mu_accept(a, m.n_occ))
+    torch.cuda.synchronize()
+    P = work.P.cpu().numpy()
+    st = work.stats_host()
+    del work
+    torch.cuda.empty_cache()
+    ranges = m.meta["atom_ranges"]
+    rng = np.random.default_rng(5)
+    atoms = {int(np.argmin(n)), int(np.argmax(n))}
+    for lo, hi in ranges:                  # two submatrices from every part
+        atoms |= set(int(x) for x in rng.choice(np.arange(lo, hi), size=2, replace=False))
+    atoms = sorted(atoms)
+    Po = om.density_matrix(m, mu, atoms=atoms)
+    mask = ~np.isnan(Po)
+    dP = float(np.max(np.abs(P[mask] - Po[mask])))
+    dE = rel(float(np.sum(P[mask] * m.vals[mask])), float(np.sum(Po[mask] * m.vals[mask])))
+    print(f"mixed4: mu {mu:.5f} ({k} passes), n {n.min()}-{n.max()}, {plan.n_chunks} chunks, sampled {atoms} "
+          f"(n {[int(n[i]) for i in atoms]}): max|dP| {dP:.2e}, rel dE {dE:.2e}, learned accepted "
+          f"{np.mean(st['scale_src'] == 2):.3f}, iters {st['iters'].min()}-{st['iters'].max()}")
+    assert n.max() > 4400 and n.min() < 1400
+    assert dP <= 1e-4 and dE <= 1e-5
+    assert np.all(st["status"] >= 1)
+    assert np.mean(st["scale_src"] == 2) > 0.5

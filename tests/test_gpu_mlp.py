@@ -119,3 +119,26 @@ def test_learned_scaling_guard_and_fallback(dev):
     assert np.all(st_c["scale_src"] == 3)
     np.testing.assert_array_equal(st_c["scale"], st_g["scale"])
     assert np.nanmax(np.abs(work.P.cpu().numpy() - Po)) < 1e-9
+
+
+def test_scaling_pairs_from_records(dev):
+    """The training pairs the library builds from the records of an explicit
+    pass (power scale, plain Newton-Schulz) are the records with both bounds,
+    in record order: features copied, targets log(rho_est / c_G) and
+    log(lb_est c / c_G) (float32 of the float64 values)."""
+    import torch
+    m = synth.water_system(16, 1.5, 3)
+    lam = np.linalg.eigvalsh(synth.to_dense(m))
+    mu = 0.5 * (lam[m.n_occ - 1] + lam[m.n_occ])
+    o = sm.default_opts("f64", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02)
+    plan = sm.Plan(m, 64)
+    H = torch.from_numpy(m.vals).to(dev)
+    work = sm.Workspace(plan, sm.storage_prec(o), dev)
+    sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
+    st = work.stats_host()
+    X, T = sm.sm_scaling_pairs(work.stats, m.n_atoms)
+    ok = (st["rho_est"] > 0) & (st["lb_est"] > 0) & (st["gersh"] > 0)
+    assert ok.sum() > m.n_atoms // 2 and X.shape[0] == ok.sum()
+    np.testing.assert_array_equal(X.cpu().numpy(), st["feat"][ok])
+    want = np.stack([np.log(st["rho_est"] / st["gersh"]), np.log(st["lb_est"] * st["scale"] / st["gersh"])], 1)[ok]
+    np.testing.assert_allclose(T.cpu().numpy(), want, rtol=1e-6, atol=1e-6)
