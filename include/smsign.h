@@ -90,7 +90,9 @@ typedef struct {
   double scale_margin;   /* c = (1 + margin) * estimate for the power / learned scale */
   int32_t probes;        /* float64 probe vectors for the final residual check (0..8) */
   int32_t variant;       /* Newton-Schulz GEMM kernel variant: -1 = the plan's tuned choice
-                            (see sm_autotune; 0 before tuning); 0 = tiles dealt to workgroups
+                            (see sm_autotune; before tuning: 1 for float64 and for submatrices
+                            under 768 rows, 5 (float32) / 6 (16-bit) above, 2 for 16-bit
+                            products on plans padded to 32); 0 = tiles dealt to workgroups
                             in list order, 1 = each XCD walks a contiguous range of the tile
                             list (a submatrix stays in one L2), 2 = as 1 with LDS stages
                             of half the k depth (more workgroups per CU), 3 = as 1 with 128 x 128 output

@@ -236,6 +236,14 @@ int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_
     p->max_subs = std::max(p->max_subs, subs);
   }
   p->chunk_ptr.push_back(n);
+  // GEMM variants until sm_autotune measures better ones: the XCD-aware
+  // 64-wide tiles for float64 and small submatrices, the 256-wide tiles for
+  // the 16-bit precisions on large ones (their float32 refinement on the
+  // 128-wide ring kernel), the half-depth stages on plans padded to 32
+  const bool big = p->pad_to >= 64 && p->max_npad >= 768;
+  p->tuned[SM_F64] = 1;
+  p->tuned[SM_F32] = big ? 5 : 1;
+  for (int m : {SM_BF16, SM_F16, SM_BF16X3}) p->tuned[m] = p->pad_to < 64 ? 2 : big ? 6 : 1;
   *out = p;
   return SM_OK;
 }
