@@ -158,7 +158,7 @@ def mu_accept(a, n_occ):
     return max(0.5, a.mu_accept_rel * n_occ)
 
 
-def train_scaling_net_water(sm, synth, dev, seed, cfg, mu_iters, accept_rel):
+def train_scaling_net_water(sm, synth, dev, seed, cfg, mu_iters, accept_rel, chunk_gb=48.0):
     """The scaling network for the water-like systems, trained on bounds the
     method produces for a smaller system of the same family: the cold
     bisection for that system's own mu runs split-bf16 passes with
@@ -168,7 +168,7 @@ def train_scaling_net_water(sm, synth, dev, seed, cfg, mu_iters, accept_rel):
     benchmark system's search)."""
     import torch
     m = water_training_system(synth, cfg, seed)
-    plan = sm.Plan(m, 64)
+    plan = sm.Plan(m, 64, int(chunk_gb * 2 ** 30 / 4))
     H = torch.from_numpy(m.vals).to(dev)
     o = sm.default_opts("bf16x3", scaling=sm.SM_SCALE_POWER, power_steps=40, scale_margin=0.02,
                         max_iter=mu_iters)
@@ -305,7 +305,7 @@ def water_bench(a):
     net_info, mu0 = None, None
     if any(x.endswith("+L") for x in heads):
         net, net_info, mu0 = train_scaling_net_water(sm, synth, dev, a.seed + 1, a.config, a.mu_iters,
-                                                     a.mu_accept_rel)
+                                                     a.mu_accept_rel, a.chunk_gb)
         sm.sm_plan_set_mlp(plan, net)
     # mu of this system: the bisection rule with the first schedule, warm-started
     # at the training system's mu (untimed; later steps start from it)

@@ -1027,6 +1027,7 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
 // groups (sixteen lanes of a 16-byte LDS read are served together).
 // ---------------------------------------------------------------------------
 constexpr int kBlock256 = 512;
+constexpr int kWalk7 = 4;   // variant 7: blocks of 4 tiles dealt to the XCDs in turn
 
 template <int MODE, int KS> struct G256 {
   static constexpr int PL = MODE == SM_BF16X3 ? 2 : 1;     // planes (hi, lo)
@@ -1063,7 +1064,22 @@ __device__ __forceinline__ int g256_off(int op, int R, int p, int c) {
   return (op * G::PL + p) * G::PLANE + R * G::RB + ((c ^ swz256<G::CPR>(R)) << 4);
 }
 
-template <int MODE, int WHICH, bool XCD, int KS, int NBUF>
+// Tile walk WALK > 0: the tile list is cut into blocks of WALK consecutive
+// tiles dealt to the 8 XCDs in turn (block b to XCD b % 8), so all XCDs work
+// on the same few submatrices at a time (their operands stay in the shared
+// memory-side cache) while an XCD's consecutive tiles share a tile row (its
+// L2 serves the shared row panel).  Tiles of XCD x: j-th = ((j / WALK) * 8 +
+// x) * WALK + j % WALK, increasing in j; walk_count = how many are < total.
+__device__ __forceinline__ int walk_tile(int j, int g, int x) { return ((j / g) * kXcds + x) * g + j % g; }
+__device__ __forceinline__ int walk_count(int total, int g, int x) {
+  const int nb = (total + g - 1) / g;
+  const int mine = nb > x ? (nb - 1 - x) / kXcds + 1 : 0;
+  int c = mine * g;
+  if (mine > 0 && (nb - 1) % kXcds == x) c -= nb * g - total;
+  return c;
+}
+
+template <int MODE, int WHICH, int WALK, int KS, int NBUF>
 __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restrict__ mats, int64_t shadow_off,
                                                                  const int32_t* __restrict__ count,
                                                                  const TileRec* __restrict__ recs,
@@ -1080,15 +1096,26 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
   const int wid = tid >> 6;
   const int wm = wid >> 2, wn = wid & 3;   // rows 128 wm .., columns 64 wn ..
   const int total = count[0];
-  int t_begin = blockIdx.x, t_end = total, t_step = gridDim.x, t_lo = 0;
-  if (XCD) {
-    const int x8 = blockIdx.x % kXcds;
-    t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
+  // WALK 0: the workgroups of XCD x walk the x-th contiguous eighth of the
+  // list; WALK > 0: interleaved blocks of WALK tiles (above).  Updates walk
+  // their share backwards (see rec_index).
+  const int x8 = blockIdx.x % kXcds;
+  const int t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
+  int t_begin, t_end, t_lo = 0;
+  if constexpr (WALK == 0) {
     t_lo = (int)((int64_t)total * x8 / kXcds);
     t_begin = t_lo + (int)blockIdx.x / kXcds;
     t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
+  } else {
+    t_begin = (int)blockIdx.x / kXcds;
+    t_end = walk_count(total, WALK, x8);
   }
   const int t_mirror = WHICH == 1 ? t_lo + t_end - 1 : -1;
+  auto tile_at = [&](int t) {
+    const int j = rec_index(t, t_mirror);
+    if constexpr (WALK == 0) return j;
+    else return walk_tile(j, WALK, x8);
+  };
 
   // this lane's part of the wave's direct loads: load u of wave wid fills
   // chunk q = wid * LPW + u (plane region q / (PLANE / 1 KiB)); lane -> (row
@@ -1097,7 +1124,7 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
   const int l_cp = lane % G::CPR;
 
   for (int t = t_begin; t < t_end; t += t_step) {
-    const TileRec rec = recs[rec_index(t, t_mirror)];
+    const TileRec rec = recs[tile_at(t)];
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
@@ -1296,13 +1323,13 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_
     case 2: return launch_one<MODE, WHICH, 2>(mats, so, count, recs, partials, L);
     case 6:
       if constexpr (Pre<MODE>::value)
-        return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, true, 32, 2>, (float*)mats, so, count, recs,
+        return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 0, 32, 2>, (float*)mats, so, count, recs,
                           partials);
       [[fallthrough]];
     case 7:
       if constexpr (Pre<MODE>::value)
         if (variant == 7)
-          return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, true, 16, 4>, (float*)mats, so, count, recs,
+          return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, kWalk7, 32, 2>, (float*)mats, so, count, recs,
                             partials);
       [[fallthrough]];
     case 3:
@@ -1356,11 +1383,11 @@ static void* ptr_which(int variant) {
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, false>);
       else return kernel_ptr<MODE, WHICH, 1>();
     case 6:
-      if constexpr (Pre<MODE>::value) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, true, 32, 2>);
+      if constexpr (Pre<MODE>::value) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, 0, 32, 2>);
       [[fallthrough]];
     case 7:
       if constexpr (Pre<MODE>::value)
-        if (variant == 7) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, true, 16, 4>);
+        if (variant == 7) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, kWalk7, 32, 2>);
       [[fallthrough]];
     case 5:
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>);
