@@ -103,8 +103,7 @@ typedef struct {
                             six stages ahead (large submatrices), 6 = 256 x 256 tiles of
                             512 threads with direct global -> LDS operand loads one
                             k-depth-32 stage ahead (bf16 / f16 / split bf16; float32 runs
-                            as 5), 7 = as 6 with the tile list dealt to the XCDs in blocks of
-                            4 tiles in turn (all XCDs on the same submatrices).  bf16 / f16 /
+                            as 5), 7 = as 6 with k-depth-16 stages three ahead.  bf16 / f16 /
                             split-bf16 products on a plan padded to 32 always run as 2 */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,

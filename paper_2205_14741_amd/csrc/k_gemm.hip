@@ -1027,7 +1027,6 @@ __global__ __launch_bounds__(kBlock, (Gemm128Occ<MODE, DEPTH>::value)) void ns_g
 // groups (sixteen lanes of a 16-byte LDS read are served together).
 // ---------------------------------------------------------------------------
 constexpr int kBlock256 = 512;
-constexpr int kWalk7 = 4;   // variant 7: blocks of 4 tiles dealt to the XCDs in turn
 
 template <int MODE, int KS> struct G256 {
   static constexpr int PL = MODE == SM_BF16X3 ? 2 : 1;     // planes (hi, lo)
@@ -1064,22 +1063,7 @@ __device__ __forceinline__ int g256_off(int op, int R, int p, int c) {
   return (op * G::PL + p) * G::PLANE + R * G::RB + ((c ^ swz256<G::CPR>(R)) << 4);
 }
 
-// Tile walk WALK > 0: the tile list is cut into blocks of WALK consecutive
-// tiles dealt to the 8 XCDs in turn (block b to XCD b % 8), so all XCDs work
-// on the same few submatrices at a time (their operands stay in the shared
-// memory-side cache) while an XCD's consecutive tiles share a tile row (its
-// L2 serves the shared row panel).  Tiles of XCD x: j-th = ((j / WALK) * 8 +
-// x) * WALK + j % WALK, increasing in j; walk_count = how many are < total.
-__device__ __forceinline__ int walk_tile(int j, int g, int x) { return ((j / g) * kXcds + x) * g + j % g; }
-__device__ __forceinline__ int walk_count(int total, int g, int x) {
-  const int nb = (total + g - 1) / g;
-  const int mine = nb > x ? (nb - 1 - x) / kXcds + 1 : 0;
-  int c = mine * g;
-  if (mine > 0 && (nb - 1) % kXcds == x) c -= nb * g - total;
-  return c;
-}
-
-template <int MODE, int WHICH, int WALK, int KS, int NBUF>
+template <int MODE, int WHICH, int KS, int NBUF>
 __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restrict__ mats, int64_t shadow_off,
                                                                  const int32_t* __restrict__ count,
                                                                  const TileRec* __restrict__ recs,
@@ -1096,26 +1080,14 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
   const int wid = tid >> 6;
   const int wm = wid >> 2, wn = wid & 3;   // rows 128 wm .., columns 64 wn ..
   const int total = count[0];
-  // WALK 0: the workgroups of XCD x walk the x-th contiguous eighth of the
-  // list; WALK > 0: interleaved blocks of WALK tiles (above).  Updates walk
-  // their share backwards (see rec_index).
+  // the workgroups of XCD x walk the x-th contiguous eighth of the list
+  // (updates backwards, see rec_index)
   const int x8 = blockIdx.x % kXcds;
   const int t_step = ((int)gridDim.x - x8 + kXcds - 1) / kXcds;
-  int t_begin, t_end, t_lo = 0;
-  if constexpr (WALK == 0) {
-    t_lo = (int)((int64_t)total * x8 / kXcds);
-    t_begin = t_lo + (int)blockIdx.x / kXcds;
-    t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
-  } else {
-    t_begin = (int)blockIdx.x / kXcds;
-    t_end = walk_count(total, WALK, x8);
-  }
+  const int t_lo = (int)((int64_t)total * x8 / kXcds);
+  const int t_begin = t_lo + (int)blockIdx.x / kXcds;
+  const int t_end = (int)((int64_t)total * (x8 + 1) / kXcds);
   const int t_mirror = WHICH == 1 ? t_lo + t_end - 1 : -1;
-  auto tile_at = [&](int t) {
-    const int j = rec_index(t, t_mirror);
-    if constexpr (WALK == 0) return j;
-    else return walk_tile(j, WALK, x8);
-  };
 
   // this lane's part of the wave's direct loads: load u of wave wid fills
   // chunk q = wid * LPW + u (plane region q / (PLANE / 1 KiB)); lane -> (row
@@ -1124,7 +1096,7 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
   const int l_cp = lane % G::CPR;
 
   for (int t = t_begin; t < t_end; t += t_step) {
-    const TileRec rec = recs[tile_at(t)];
+    const TileRec rec = recs[rec_index(t, t_mirror)];
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
     const double alpha = (double)rec.alpha;
@@ -1137,21 +1109,19 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
     const int r0 = bi * 256, c0 = bj * 256;
     const bool wvalid = (r0 + wm * 128 < npad) && (c0 + wn * 64 < npad) &&
                         !(bi == bj && wm * 128 + 127 < wn * 64);
-    // global source of each of this lane's loads (16-bit element index of
-    // its 16 bytes at stage 0); rows past n_pad read row n_pad - 1 (their
-    // products land in outputs that are never stored)
-    const uint16_t* src[G::LPW];
-#pragma unroll
-    for (int u = 0; u < G::LPW; ++u) {
-      const int q = wid * G::LPW + u;
-      const int region = q / (G::PLANE / 1024);          // op * PL + plane
-      const int op = region / G::PL, pl = region % G::PL;
-      const int R = (q % (G::PLANE / 1024)) * G::RPC + l_rr;
-      const int row = min((op == 0 ? r0 : c0) + R, npad - 1);
-      const int gc = l_cp ^ swz256<G::CPR>(R);
-      const uint16_t* cp = reinterpret_cast<const uint16_t*>((op == 0 ? Xp : Rp) + shadow_off);
-      src[u] = cp + (SPLIT ? (int64_t)row * 2 * npad + pl * 32 : (int64_t)row * npad) + gc * 8;
-    }
+    // global source of this lane's loads: the LPW chunks of a wave lie in one
+    // (operand, plane) region, rows R_0 + u RPC (u < LPW) at one k-chunk
+    // (the swizzle of R_0 + u RPC is that of R_0); rows past n_pad read row
+    // n_pad - 1 (their products land in outputs that are never stored)
+    static_assert((G::PLANE / 1024) % G::LPW == 0, "a wave's loads stay in one plane region");
+    const int q0 = wid * G::LPW;
+    const int region = q0 / (G::PLANE / 1024);             // op * PL + plane
+    const int op = region / G::PL, pl = region % G::PL;
+    const int R0l = (q0 % (G::PLANE / 1024)) * G::RPC + l_rr;
+    const int row0 = (op == 0 ? r0 : c0) + R0l;
+    const int64_t rstride = SPLIT ? 2 * (int64_t)npad : npad;
+    const uint16_t* cbase = reinterpret_cast<const uint16_t*>((op == 0 ? Xp : Rp) + shadow_off) + pl * 32 +
+                            (l_cp ^ swz256<G::CPR>(R0l)) * 8;
     const int nst = npad / KS;
     // stage s starts at k = KS s: for split copies, 32-row run s KS / 32 (64
     // elements: hi then lo), offset (s KS) % 32 inside it
@@ -1160,7 +1130,9 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
       const int64_t k0 = (int64_t)s * KS;
       const int64_t so = SPLIT ? (k0 >> 5) * 64 + (k0 & 31) : k0;
 #pragma unroll
-      for (int u = 0; u < G::LPW; ++u) lds_load16(src[u] + so, dst + (wid * G::LPW + u) * 1024);
+      for (int u = 0; u < G::LPW; ++u)
+        lds_load16(cbase + (int64_t)min(row0 + u * G::RPC, npad - 1) * rstride + so,
+                   dst + (q0 + u) * 1024);
     };
 
     // 32 x 32 result blocks: 4 (rows) x 2 (columns) per wave
@@ -1170,6 +1142,55 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = f32x16{};
 
+    // 32x32x16 operand fragments of one k-step: lane l supplies row l % 32
+    // of each of its operand blocks and the 8 k values of k-chunk
+    // 2 ks + l / 32 (16 bytes); A of the wave's 4 block rows, B of its 2
+    // block columns, hi and (split) lo
+    const int r32 = lane & 31, kh = lane >> 5;
+    struct Frag {
+      u32x4 ah[4], al[4], bh[2], bl[2];
+    };
+    auto load_frag = [&](Frag& f, const char* st, int ks) {
+      const int kc = 2 * ks + kh;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int R = wn * 64 + y * 32 + r32;
+        f.bh[y] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(1, R, 0, kc));
+        if (SPLIT) f.bl[y] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(1, R, 1, kc));
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int R = wm * 128 + x * 32 + r32;
+        f.ah[x] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(0, R, 0, kc));
+        if (SPLIT) f.al[x] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(0, R, 1, kc));
+      }
+    };
+    auto mfma_frag = [&](const Frag& f) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          if constexpr (MODE == SM_F16) {
+            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, f.ah[x]),
+                                                               __builtin_bit_cast(f16x8, f.bh[y]), acc[x][y], 0, 0, 0);
+          } else {
+            const bf16x8 a = __builtin_bit_cast(bf16x8, f.ah[x]), b = __builtin_bit_cast(bf16x8, f.bh[y]);
+            if constexpr (SPLIT) {
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, f.al[x]), b, acc[x][y], 0, 0, 0);
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, f.bl[y]), acc[x][y], 0, 0, 0);
+            }
+            acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[x][y], 0, 0, 0);
+          }
+        }
+    };
+    // a plain barrier, not __syncthreads(): its fence would wait for every
+    // load in flight, the later stages' too
+    auto barrier = [&]() {
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" :: "v"(lds) : "memory");
+    };
+
 #pragma unroll
     for (int u = 0; u < AHEAD; ++u)
       if (u < nst) issue(u);
@@ -1177,54 +1198,20 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
       // this wave's loads of stage s have landed (those of the later stages
       // already issued may still fly); after the barrier every wave's have,
       // and every wave is done with stage s - 1, whose buffer stage s + AHEAD
-      // refills
+      // refills (every LDS read of stage s - 1 has returned: the matrix-core
+      // instructions that use it were issued)
       if (s + AHEAD <= nst) wait_vm<(AHEAD - 1) * G::LPW>();
       else if (AHEAD >= 3 && s + 2 == nst) wait_vm<(AHEAD >= 3 ? G::LPW : 0)>();
       else wait_vm<0>();
-      // a plain barrier, not __syncthreads(): its fence would wait for every
-      // load in flight, the later stages' too.  The wait above covers this
-      // wave's stage-s loads; every LDS read of stage s - 1 has returned (the
-      // matrix-core instructions that use it were issued).
-      asm volatile("" ::: "memory");
-      __builtin_amdgcn_s_barrier();
+      barrier();
       if (s + AHEAD < nst) issue(s + AHEAD);
-      asm volatile("" :: "v"(lds) : "memory");
       if (!wvalid) continue;
       const char* st = lds + (s % NBUF) * G::STAGE;
-      // 32x32x16: lane l supplies row l % 32 of its operand block and the
-      // 8 k values of k-chunk 2 ks + l / 32 (16 bytes)
-      const int r32 = lane & 31, kh = lane >> 5;
 #pragma unroll
       for (int ks = 0; ks < KS / 16; ++ks) {
-        const int kc = 2 * ks + kh;
-        u32x4 bh[2], bl[2];
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-          const int R = wn * 64 + y * 32 + r32;
-          bh[y] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(1, R, 0, kc));
-          if (SPLIT) bl[y] = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(1, R, 1, kc));
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int R = wm * 128 + x * 32 + r32;
-          const u32x4 ah = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(0, R, 0, kc));
-          u32x4 al;
-          if (SPLIT) al = *reinterpret_cast<const u32x4*>(st + g256_off<MODE, KS>(0, R, 1, kc));
-#pragma unroll
-          for (int y = 0; y < 2; ++y) {
-            if constexpr (MODE == SM_F16) {
-              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, ah),
-                                                                 __builtin_bit_cast(f16x8, bh[y]), acc[x][y], 0, 0, 0);
-            } else {
-              const bf16x8 a = __builtin_bit_cast(bf16x8, ah), b = __builtin_bit_cast(bf16x8, bh[y]);
-              if constexpr (SPLIT) {
-                acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), b, acc[x][y], 0, 0, 0);
-                acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, bl[y]), acc[x][y], 0, 0, 0);
-              }
-              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[x][y], 0, 0, 0);
-            }
-          }
-        }
+        Frag f;
+        load_frag(f, st, ks);
+        mfma_frag(f);
       }
     }
 
@@ -1323,13 +1310,13 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_
     case 2: return launch_one<MODE, WHICH, 2>(mats, so, count, recs, partials, L);
     case 6:
       if constexpr (Pre<MODE>::value)
-        return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 0, 32, 2>, (float*)mats, so, count, recs,
+        return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 32, 2>, (float*)mats, so, count, recs,
                           partials);
       [[fallthrough]];
     case 7:
       if constexpr (Pre<MODE>::value)
         if (variant == 7)
-          return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, kWalk7, 32, 2>, (float*)mats, so, count, recs,
+          return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 16, 4>, (float*)mats, so, count, recs,
                             partials);
       [[fallthrough]];
     case 3:
@@ -1383,11 +1370,11 @@ static void* ptr_which(int variant) {
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, false>);
       else return kernel_ptr<MODE, WHICH, 1>();
     case 6:
-      if constexpr (Pre<MODE>::value) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, 0, 32, 2>);
+      if constexpr (Pre<MODE>::value) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, 32, 2>);
       [[fallthrough]];
     case 7:
       if constexpr (Pre<MODE>::value)
-        if (variant == 7) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, kWalk7, 32, 2>);
+        if (variant == 7) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, 16, 4>);
       [[fallthrough]];
     case 5:
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>);

@@ -171,8 +171,7 @@ hipError_t launch_expand(const DevPlan& p, int g0, const SubState* st, const int
 // 4: 128 x 128 tiles walked linearly (all XCDs on the same submatrices),
 // 5: as 3 with operands loaded six stages ahead,
 // 6: XCD-aware 256 x 256 tiles of 512 threads (bf16, f16, split bf16 only),
-// k-depth-32 stages one ahead, 7: the same with the tiles dealt to the XCDs
-// in blocks of 4 in turn
+// k-depth-32 stages one ahead, 7: the same with k-depth-16 stages three ahead
 constexpr int kGemmVariants = SM_GEMM_VARIANTS;
 // output tile edge (log2) of a GEMM variant for a precision; 128-wide tiles
 // exist for the float32-accumulating precisions and need n_pad % 64 == 0,
