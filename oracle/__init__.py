@@ -17,4 +17,7 @@ Modules
   overlap    -- a non-orthogonal basis: inverse square roots (Eq. 12 by its
                 definition), P of Eq. 14 on every submatrix pair by the
                 generalized symmetric eigendecomposition, tr(PH), tr(PS).
+  fermi      -- the general f of Fig. 2 taken as the Fermi-Dirac occupation
+                at inverse temperature beta: f(T_i) by eigendecomposition,
+                the electron count and its mu-derivative, mu by bisection.
 """
