@@ -178,9 +178,10 @@ int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_
     p->loc[c] = loc;
     p->npad[c] = (int32_t)((h + pad_to - 1) / pad_to * pad_to);
     if ((int64_t)h * p->bs[c] != p->panel_off[c + 1] - p->panel_off[c]) {
+      const int32_t w = p->bs[c];
       delete p;
       return set_error(SM_ERR_ARG, "sm_plan_create: panel_off of column %d does not match height %d x width %d",
-                       c, h, p->bs[c]);
+                       c, h, w);
     }
     for (int32_t q = 0; q < p->bs[c]; ++q)
       p->diag_idx[dpos++] = p->panel_off[c] + (int64_t)q * h + loc + q;
