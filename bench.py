@@ -97,6 +97,9 @@ def parse(argv=None):
                     help="float32 matrix budget per chunk in MiB (cfg2; 0: one chunk)")
     ap.add_argument("--samples", type=int, default=6,
                     help="oracle-checked submatrices (water-like configs; their timing is the CPU baseline)")
+    ap.add_argument("--fermi", type=float, default=0.0, metavar="BETA",
+                    help="finite temperature instead of the sign: Fermi-Dirac f(T_i) at inverse "
+                         "temperature BETA (cfg2: the lattice; cfg3: --n-mol water-like molecules)")
     ap.add_argument("--copy-calibrate", type=float, default=0.0, metavar="MIB",
                     help="first run a plain copy kernel (negation of a float32 buffer of MIB MiB), "
                          "the reference for scaling memory-traffic counters")
@@ -226,9 +229,11 @@ def cpu_baseline(m, mu, target_s):
                       f"the first {k} of {m.n_atoms} submatrices at the benchmark's mu ({dt:.1f} s)"}
 
 
-def dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passes, pad_to):
+def dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passes, pad_to, chunk=None):
     """The GEMM class (precision, square / update) with the most kernel time,
-    with its algorithmic flops and bytes per launch and its achieved rates."""
+    with its algorithmic flops and bytes per launch and its achieved rates;
+    the kernel named is the variant of `chunk`'s size class (default: the
+    plan-wide choice)."""
     cls = int(np.argmax(ms))
     key = (cls // 2, cls % 2)
     fl = metrics.flops_by_class(st, n, npad, o, slab)
@@ -236,7 +241,12 @@ def dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passe
     nl = max(int(launches[cls]), 1)
     avg_ms = ms[cls] / nl
     per_launch = fu * metrics.MFMA_PRODUCTS[key[0]] * passes / nl
-    variant = int(o.variant) if int(o.variant) >= 0 else int(sm.sm_plan_tuning(plan)[key[0]])
+    if int(o.variant) >= 0:
+        variant = int(o.variant)
+    elif chunk is not None:
+        variant = int(plan.chunk_variants(chunk)[1][key[0]])
+    else:
+        variant = int(sm.sm_plan_tuning(plan)[key[0]])
     bytes_launch = metrics.bytes_by_class(st, n, o, slab, npad).get(key, 0.0) * passes / nl
     return {"name": metrics.gemm_kernel_symbol(key[0], key[1], variant, pad_to), "precision": DT_NAME[key[0]],
             "product": "square" if key[1] == 0 else "update", "launches": int(launches[cls]), "avg_ms": avg_ms,
@@ -329,9 +339,19 @@ def water_bench(a):
             o.variant = 1            # the float64 kernel of the lattice tuning (no sweep: passes are long)
             tune = None
         else:
-            print(f"# {mode}: autotuning on chunk 0 ...", file=sys.stderr, flush=True)
-            best, tune_ms = sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5, 6, 7))
-            tune = {"variant": int(best), "sign_ms_chunk0": [float(x) for x in tune_ms]}
+            # one autotuning per size class (the first chunk of each): a mixed
+            # batch gets a tile shape per submatrix size
+            first = {}
+            for c in range(plan.n_chunks):
+                first.setdefault(plan.chunk_variants(c)[0], c)
+            tune = {}
+            for cls, c in sorted(first.items()):
+                print(f"# {mode}: autotuning on chunk {c} (size class {cls}) ...", file=sys.stderr, flush=True)
+                best, tune_ms = sm.sm_autotune(plan, c, H, mu, o, work.ws, work.stats, repeats=1,
+                                               variants=(1, 3, 4, 5, 6, 7))
+                tune[str(cls)] = {"chunk": c, "variant": int(best), "sign_ms": [float(x) for x in tune_ms]}
+                print(f"#   variant {best}: " + " / ".join(f"{x:.0f}" for x in tune_ms if x > 0) + " ms",
+                      file=sys.stderr, flush=True)
         steps, warm = (a.ref_steps, 0) if ref else (a.steps, a.warmup)
         mu_k = mu
 
@@ -368,7 +388,9 @@ def water_bench(a):
              "learned_accepted": float(np.mean(st["scale_src"] == 2)) if o.scaling == sm.SM_SCALE_LEARNED else None,
              "probe_max": float(st["res_probe"].max()), "autotune": tune}
         if not a.no_profile and ms.sum() > 0:
-            r["kernel"] = dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passes, 64)
+            # the kernel of the largest submatrices' size class (most of the work)
+            r["kernel"] = dominant_kernel(sm, metrics, plan, st, n, npad, o, slab, launches, ms, passes, 64,
+                                          chunk=int(info["chunk"][int(np.argmax(n))]))
         Ps[mode] = work.P.cpu().numpy()
         res[mode] = r
         print(f"# {mode}: {r['ms_per_step']:.0f} ms/step, {r['submatrices_per_s']:.0f} subm/s, "
@@ -584,6 +606,108 @@ def trajectory_bench(a):
     print(json.dumps(out), flush=True)
 
 
+def fermi_bench(a):
+    """Finite temperature: one step = mu from the electron count at inverse
+    temperature beta (safeguarded Newton, warm-started at the previous step's
+    mu), P = block columns of f(T_i), tr(PH), tr P.  Float64 throughout."""
+    import torch
+    import synth
+    from paper_2205_14741_amd import smsign as sm
+    from oracle import fermi as fd
+    from oracle import submatrix as om
+
+    dev = torch.device("cuda:0")
+    if a.config == "cfg2":
+        m = synth.config2(a.seed)
+        wl = "lattice1000 (967 submatrices n=192..276)"
+    elif a.config == "cfg3":
+        m = synth.config3(a.seed, n_mol=a.n_mol)
+        wl = f"water{a.n_mol} (cutoff 3.0, {m.n_atoms} submatrices)"
+    else:
+        raise SystemExit("--fermi runs with --config cfg2 or cfg3")
+    beta = a.fermi
+    budget = int(a.chunk_gb * 2 ** 30 / 8) if a.config == "cfg3" else 0   # float64 elements
+    plan = sm.Plan(m, 64, budget)
+    info = plan.info()
+    n, npad = info["n"].astype(np.float64), info["npad"].astype(np.float64)
+    H = torch.from_numpy(m.vals).to(dev)
+    o = sm.default_opts("f64", retry=0)
+    work = sm.Workspace(plan, sm.SM_F64, dev)
+    target = float(m.n_occ)
+    t0 = time.perf_counter()
+    mu, k0, _, E, Ne = sm.sm_find_mu_fermi(plan, H, target, beta, o, work.ws, work.P, work.stats, tol=1e-6)
+    torch.cuda.synchronize()
+    print(f"# {wl}: cold mu {mu:.8f} after {k0} evaluations ({time.perf_counter() - t0:.1f} s), "
+          f"{plan.n_chunks} chunks", file=sys.stderr, flush=True)
+    # doublings of every chunk at this beta (the same for every step)
+    doublings = []
+    for c in range(plan.n_chunks):
+        sm.build_submatrices(plan, c, H, mu, o, work.ws, work.stats)
+        doublings.append(sm.sm_fermi_dirac(plan, c, work.ws, beta, work.stats))
+    torch.cuda.synchronize()
+
+    def step(mu0):
+        return sm.sm_find_mu_fermi(plan, H, target, beta, o, work.ws, work.P, work.stats, tol=1e-6,
+                                   mu_start=mu0)
+
+    for _ in range(a.warmup):
+        step(mu)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    for i in range(a.steps):
+        mu, k, _, E, Ne = step(mu)
+        evals += k
+        print(f"# fermi: step {i + 1}/{a.steps} ({time.perf_counter() - t0:.1f} s, {k} evaluations)",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # float64 products per evaluation: 14 + 10 m per submatrix, lower-triangle
+    # products (n (n + 1) / 2 entries x 2 n flops useful; 64-tiles issued)
+    chunk = info["chunk"]
+    prods = np.array([14 + 10 * doublings[int(c)] for c in chunk], dtype=np.float64)
+    useful = float(np.sum(prods * n * (n + 1) * n))
+    T = np.ceil(npad / 64)
+    issued = float(np.sum(prods * T * (T + 1) / 2 * 2 * 64 * 64 * npad))
+    P = work.P.cpu().numpy()
+    rng = np.random.default_rng(a.seed)
+    atoms = sorted(rng.choice(m.n_atoms, size=min(a.samples, m.n_atoms), replace=False).tolist())
+    Po = fd.density_matrix_fd(m, mu, beta, atoms=atoms)
+    sel = ~np.isnan(Po)
+    dP = float(np.max(np.abs(P[sel] - Po[sel])))
+    view = om.BlockView(m)
+    t1 = time.perf_counter()
+    kc = 0
+    while kc < m.n_atoms and (kc < 8 or time.perf_counter() - t1 < a.cpu_seconds):
+        fd.density_matrix_columns_fd(view, kc, mu, beta)
+        kc += 1
+    cdt = time.perf_counter() - t1
+    ncpu, model = cpu_info()
+    out = {
+        "metric": "finite-temperature submatrix P: submatrices/s (float64)",
+        "value": m.n_atoms * a.steps / dt,
+        "unit": "submatrices/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl, "beta": beta, "doublings": doublings, "N": m.n_orb, "n_sub": m.n_atoms},
+        "evaluations_per_step": evals / a.steps,
+        "useful_tflops": useful * evals / dt / 1e12,
+        "issued_tflops": issued * evals / dt / 1e12,
+        "mu": mu, "E": E, "Ne": Ne,
+        "oracle_max_dP_sampled": dP, "oracle_sampled_atoms": atoms,
+        "cpu_baseline": {"value": kc / cdt, "unit": "submatrices/s", "cores": blas_threads(), "kind": "oracle",
+                         "host_cpus": ncpu, "cpu_model": model,
+                         "sample": f"float64 eigendecomposition oracle, f(T_i) columns of the first {kc} "
+                                   f"submatrices ({cdt:.1f} s)"},
+    }
+    print(f"# fermi: {out['ms_per_step']:.1f} ms/step, {out['value']:.0f} subm/s, "
+          f"{out['evaluations_per_step']:.2f} evaluations/step, {out['useful_tflops']:.2f} TF/s useful "
+          f"({out['issued_tflops']:.2f} issued), sampled max|dP| {dP:.2e}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibrate(dev, mib):
     """A plain copy kernel of known size (negation of a float32 buffer), the
     reference that memory-traffic counters are scaled by."""
@@ -604,6 +728,8 @@ def main():
         print("bench.py runs on one GPU only (the submatrix path would shard by atom domains; "
               "the multi-GPU halo exchange is not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if a.fermi > 0:
+        return fermi_bench(a)
     if a.config in ("cfg3", "cfg4"):
         return water_bench(a)
     if a.config == "cfg5":

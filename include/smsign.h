@@ -202,8 +202,8 @@ int sm_default_opts(int32_t prec, sm_sign_opts* o);
  *                   unsorted, the diagonal block is missing, panel_off does not
  *                   match the block sizes, or a block size is < 1.
  *   pad_to          every submatrix is stored padded to a multiple of this
- *                   (64 or 128); the pad is the identity, a fixed point of the
- *                   iteration.
+ *                   (32, 64 or 128); the pad is the identity, a fixed point of
+ *                   the iteration.
  *   max_chunk_elems workspace budget in matrix elements per chunk: submatrices
  *                   are processed in chunks whose three n_pad^2 buffers fit
  *                   (a single larger submatrix forms its own chunk); <= 0 means
@@ -213,6 +213,18 @@ int sm_default_opts(int32_t prec, sm_sign_opts* o);
 int sm_plan_create(const sm_bsr_pattern* pattern, int32_t pad_to,
                    int64_t max_chunk_elems, sm_plan** out);
 void sm_plan_destroy(sm_plan* plan);
+
+/* Processing order from atom positions (Fig. 2 leaves the order of the
+ * submatrices open): size buckets of `bucket_rows` padded rows, larger first
+ * (bucket_rows <= 0: one bucket), so that every chunk holds submatrices of
+ * similar size, and inside a bucket the Morton (Z-order) curve of the atom
+ * centres, so that consecutive gathers read neighbouring H panels.  Rebuilds
+ * the chunks with the plan's budget (sm_plan_info reports the new order and
+ * chunks; results do not depend on the order).
+ *   xyz  host double[3 n_atoms]: x, y, z of every atom (any units and origin).
+ * SM_ERR_STATE once the plan has been used on a device; SM_ERR_ARG for a
+ * non-finite position. */
+int sm_plan_set_positions(sm_plan* plan, const double* xyz, int32_t bucket_rows);
 
 /* Workspace storage code of a schedule (the storage_prec argument below):
  * SM_F64 or SM_F32 for the iterate's type; for the SM_BF16 / SM_F16 /
@@ -343,6 +355,59 @@ int sm_density_matrix_overlap(sm_plan* plan, const double* H_vals, const double*
                               const sm_sign_opts* opts, void* ws, void* ws_aux, double* P_vals,
                               sm_sub_stats* stats, double* E_host, double* Ne_host, void* stream);
 
+/* ---- finite temperature: the general f of Fig. 2 as Fermi-Dirac ----------
+ * Step 2 of Fig. 2 with f(x) = 1 / (1 + exp(beta x)) instead of Eq. 14's step
+ * 1/2 (1 - sign x), on T_i = H[idx_i, idx_i] - mu I, in float64 (beta > 0:
+ * inverse temperature in the units of 1 / H).  As beta grows, f(T_i) tends
+ * to the P_i of Eq. 14 where T_i has no eigenvalue at 0.  The workspace is a
+ * float64 one (sm_plan_sizes with SM_F64) built by build_submatrices with
+ * phase1 = SM_F64, refine_steps = 0 (any scaling: only T_i matters). */
+
+/* f(T_i) for every submatrix of `chunk`, from X_0 = T_i / c in buffer 0 of ws
+ * (build_submatrices of this chunk with the float64 schedule must be the last
+ * build into ws: SM_ERR_STATE otherwise).  With m the smallest count such
+ * that beta max(stats.gersh, stats.scale) <= 2^(m+1) / 4 over the chunk,
+ * f(beta T / 2^m) = 1/2 (1 - tanh z), z = beta T / 2^(m+1), comes from the
+ * Taylor polynomial of tanh to z^15, then m doublings of the argument,
+ * f(2y) = f(y)^2 (f(y)^2 + (1 - f(y))^2)^-1, the inverse as a product of
+ * five Neumann factors; 14 + 10 m float64 products per submatrix.  The result
+ * stays in ws for assemble_P_fermi.  m > 60 is refused (SM_ERR_ARG).
+ *   stats          the records build_submatrices wrote (device, read only).
+ *   doublings_out  (may be NULL) m.
+ * Synchronises `stream` once (to read the bound that sets m). */
+int sm_fermi_dirac(sm_plan* plan, int32_t chunk, void* ws, double beta, const sm_sub_stats* stats,
+                   int32_t* doublings_out, void* stream);
+
+/* Step 3 of Fig. 2 for f(T_i): block column i of f(T_i) into P's panel i,
+ * and the atom's electron count sum_q f(T_i)_qq and its mu-derivative
+ * (without the factor beta) into the plan's per-atom arrays.  Needs
+ * sm_fermi_dirac of this chunk into this ws (SM_ERR_STATE otherwise).
+ * Asynchronous on `stream`. */
+int assemble_P_fermi(sm_plan* plan, int32_t chunk, const void* ws, double* P_vals, void* stream);
+
+/* Whole evaluation at fixed mu and beta: per chunk build_submatrices,
+ * sm_fermi_dirac, assemble_P_fermi; then E = tr(P H), Ne = tr P and
+ * dNe/dmu = beta sum_i sum_q [f(T_i)(I - f(T_i))]_qq (f' = -beta f (1 - f)),
+ * each into host memory when not NULL.  Synchronises `stream`. */
+int sm_density_matrix_fermi(sm_plan* plan, const double* H_vals, double mu, double beta,
+                            const sm_sign_opts* opts, void* ws, double* P_vals, sm_sub_stats* stats,
+                            double* E_host, double* Ne_host, double* dNe_host, void* stream);
+
+/* mu with Ne(mu) = n_target at inverse temperature beta (Ne is continuous and
+ * increasing in mu at finite temperature, so the root is unique): Newton
+ * steps with the exact derivative, kept inside a bracket that starts as the
+ * Gershgorin hull of H widened by 40 / beta on each side (bisection when a
+ * step would leave it), from mu_start when finite (clamped into the bracket),
+ * else from the bracket's midpoint.  Stops at |Ne - n_target| <= tol, when the
+ * bracket cannot shrink further, or after max_steps evaluations (in [1, 200]).
+ * On return P_vals holds P at *mu_out; mu_hist / ne_hist [max_steps] (may be
+ * NULL) the evaluated points; E_out / Ne_out (may be NULL) tr(P H) and tr P
+ * there.  Synchronises `stream` once per evaluation. */
+int sm_find_mu_fermi(sm_plan* plan, const double* H_vals, double n_target, double beta, double tol,
+                     int32_t max_steps, double mu_start, const sm_sign_opts* opts, void* ws,
+                     double* P_vals, sm_sub_stats* stats, double* mu_out, int32_t* steps_out,
+                     double* mu_hist, double* ne_hist, double* E_out, double* Ne_out, void* stream);
+
 /* Chemical potential by bisection on the electron count (Eq. 14's mu; the
  * paper leaves the rule open): start from the global Gershgorin bracket of H,
  * evaluate Ne(mid) = tr P with the full method at each midpoint, stop at the
@@ -459,9 +524,13 @@ int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
 
 /* Autotuner: for every GEMM kernel variant, one build + submatrix_sign pass
  * over `chunk` at fixed mu (the sign phase timed with HIP events, best of
- * `repeats`), then records the fastest variant as the plan's choice for the
- * precisions of `opts` (used when opts->variant == -1).  variant_mask: bit v
- * set = try variant v (0 = all).
+ * `repeats`), then records the fastest variant for the precisions of `opts`
+ * (used when opts->variant == -1) as the choice of every chunk in the same
+ * size class as `chunk` (the number of 256-row tiles of a chunk's largest
+ * padded submatrix: one tuning per class serves a batch of mixed sizes) and
+ * as the plan-wide choice that sm_plan_tuning reports.  Chunks of classes
+ * never tuned keep the size-based defaults (see sm_sign_opts.variant).
+ * variant_mask: bit v set = try variant v (0 = all).
  *   best_out   host int32 (may be NULL): the chosen variant
  *   times_ms   host double[SM_GEMM_VARIANTS] (may be NULL): sign time of each
  *              variant (-1: not tried, or not applicable to this plan / precision)
@@ -474,9 +543,14 @@ int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
 int32_t sm_gemm_variants(void);
 
 /* Tuned variant per precision (int32[5], indexed by sm_prec): `get` receives
- * the table, `set` (if not NULL) replaces it -- to persist the autotuner's
- * choices across processes.  Either pointer may be NULL. */
+ * the plan-wide table, `set` (if not NULL) replaces it and the table of every
+ * size class -- to persist the autotuner's choices across processes.  Either
+ * pointer may be NULL. */
 int sm_plan_tuning(sm_plan* plan, int32_t* get, const int32_t* set);
+/* The size class of `chunk` (256-row tiles of its largest padded submatrix)
+ * and the GEMM variant per precision (int32[5], indexed by sm_prec) its
+ * launches use when opts->variant == -1.  Either output may be NULL. */
+int sm_plan_chunk_variants(const sm_plan* plan, int32_t chunk, int32_t* class_out, int32_t* variants_out);
 
 /* Kernel timing for measurement.  While enabled, every Newton-Schulz GEMM
  * launch made by submatrix_sign carries a pair of HIP events that the dispatch

@@ -20,8 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsmsign.so")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "api.cpp", "api_ovl.cpp", "mlp.cpp", "k_prep.hip", "k_gemm.hip", "k_post.hip", "k_mlp.hip",
-           "k_ovl.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "api_ovl.cpp", "api_fermi.cpp", "mlp.cpp", "k_prep.hip", "k_gemm.hip",
+           "k_post.hip", "k_mlp.hip", "k_ovl.hip", "k_fermi.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -91,7 +91,7 @@ int chunk_max_tiles_sub(const sm_plan* p, int g0, int nsub) {
 // Variant that actually runs: the 128-wide tiles need n_pad % 64 == 0 and a
 // float32-accumulating precision, otherwise the XCD-aware 64-wide kernel.
 int effective_variant(const sm_plan* p, int mode, int variant) {
-  int v = variant >= 0 ? variant : p->tuned[mode];
+  int v = variant >= 0 ? variant : p->tuned_for(p->active_chunk)[mode];
   if (v >= 6 && mode < SM_BF16) v = 5;   // 256-wide tiles: 16-bit operand copies only
   if (v >= 3 && (mode == SM_F64 || p->pad_to < 64)) v = 1;
   // bf16 / f16 / split-bf16 on a plan padded to 32: only the half-depth
@@ -208,6 +208,7 @@ int build_submatrices(sm_plan* p, int32_t chunk, const double* H, double mu, con
   p->last_chunk = chunk;
   p->last_H = H;
   p->last_mu = mu;
+  p->fd_chunk = -1;   // the workspace no longer holds a finite-temperature result
   return SM_OK;
 }
 
@@ -224,6 +225,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   const int64_t shadow = storage >= SM_BF16 ? p->shadow_off() : 0;
   if (p->last_storage != storage)
     return set_error(SM_ERR_STATE, "submatrix_sign: the workspace was not built for this precision schedule");
+  p->fd_chunk = -1;
+  p->active_chunk = chunk;   // its size class's GEMM variants
   WsPtrs w = ws_ptrs(p, ws, storage);
   hipStream_t s = as_stream(stream);   // the lambdas below launch on `s`
   const int64_t stride = list_stride(p);
@@ -337,7 +340,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     hipGraphExec_t exec = nullptr;
     for (auto& e : p->graphs)
       if (e.chunk == chunk && e.ws == ws && std::memcmp(&e.opts, o, sizeof(*o)) == 0 &&
-          std::memcmp(e.tuned, p->tuned, sizeof(p->tuned)) == 0)
+          std::memcmp(e.tuned, p->tuned_for(chunk), sizeof(e.tuned)) == 0)
         exec = e.exec;
     if (!exec) {
       if (!p->capture_stream) SM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
@@ -357,7 +360,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
       sm_plan::GraphEntry ge{chunk, ws, *o, {0}, exec};
-      std::memcpy(ge.tuned, p->tuned, sizeof(p->tuned));
+      std::memcpy(ge.tuned, p->tuned_for(chunk), sizeof(ge.tuned));
       p->graphs.push_back(ge);
     }
     const int replays = (lim + G) / G;
@@ -571,6 +574,8 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
   if (rc) return rc;
   if (!p || !H || !ws || !stats) return set_error(SM_ERR_ARG, "sm_autotune: null argument");
   if (repeats < 1 || repeats > 20) return set_error(SM_ERR_ARG, "sm_autotune: repeats out of [1, 20]");
+  if (chunk < 0 || chunk >= (int)p->chunk_class.size())
+    return set_error(SM_ERR_ARG, "sm_autotune: chunk %d out of [0, %d)", chunk, (int)p->chunk_class.size());
   if ((rc = ensure_device(p))) return rc;
   hipStream_t s = as_stream(stream);
   hipEvent_t e0, e1;
@@ -608,13 +613,27 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   if (best < 0) return set_error(SM_ERR_ARG, "sm_autotune: no variant selected by the mask");
+  // the plan-wide choice, and that of the chunk's size class (which its
+  // chunks use from now on)
   p->tuned[o->phase1] = best;
   if (o->refine_steps > 0) p->tuned[o->refine] = best;
+  auto& ct = p->class_tuned[p->chunk_class[chunk]];
+  ct[o->phase1] = best;
+  if (o->refine_steps > 0) ct[o->refine] = best;
   if (best_out) *best_out = best;
   return SM_OK;
 }
 
 int32_t sm_gemm_variants(void) { return kGemmVariants; }
+
+int sm_plan_chunk_variants(const sm_plan* p, int32_t chunk, int32_t* class_out, int32_t* variants_out) {
+  if (!p) return set_error(SM_ERR_ARG, "sm_plan_chunk_variants: null plan");
+  if (chunk < 0 || chunk >= (int)p->chunk_class.size())
+    return set_error(SM_ERR_ARG, "sm_plan_chunk_variants: chunk %d out of [0, %d)", chunk, (int)p->chunk_class.size());
+  if (class_out) *class_out = p->chunk_class[chunk];
+  if (variants_out) std::memcpy(variants_out, p->tuned_for(chunk), 5 * sizeof(int32_t));
+  return SM_OK;
+}
 
 int sm_plan_tuning(sm_plan* p, int32_t* get, const int32_t* set) {
   if (!p) return set_error(SM_ERR_ARG, "sm_plan_tuning: null plan");
@@ -623,6 +642,7 @@ int sm_plan_tuning(sm_plan* p, int32_t* get, const int32_t* set) {
     for (int k = 0; k < 5; ++k)
       if (set[k] < 0 || set[k] >= kGemmVariants) return set_error(SM_ERR_ARG, "sm_plan_tuning: variant out of range");
     std::memcpy(p->tuned, set, sizeof(p->tuned));
+    for (int32_t c : p->chunk_class) std::memcpy(p->class_tuned[c].data(), set, sizeof(p->tuned));
   }
   return SM_OK;
 }

@@ -12,13 +12,7 @@ using namespace sm;
 
 namespace {
 
-constexpr int kHostOvl = 44;   // one double in the mapped host words: largest residual
-
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-double* mats_of(const sm_plan* p, const void* ws) {
-  return reinterpret_cast<double*>(static_cast<char*>(const_cast<void*>(ws)) + p->layout(SM_F64).mats);
-}
 
 int chunk_range(const sm_plan* p, int32_t chunk, int& g0, int& nsub) {
   const int nch = (int)p->chunk_ptr.size() - 1;
@@ -26,6 +20,14 @@ int chunk_range(const sm_plan* p, int32_t chunk, int& g0, int& nsub) {
   g0 = (int)p->chunk_ptr[chunk];
   nsub = (int)(p->chunk_ptr[chunk + 1] - p->chunk_ptr[chunk]);
   return SM_OK;
+}
+
+}  // namespace
+
+namespace sm {
+
+double* f64_mats(const sm_plan* p, const void* ws) {
+  return reinterpret_cast<double*>(static_cast<char*>(const_cast<void*>(ws)) + p->layout(SM_F64).mats);
 }
 
 int ensure_ovl(sm_plan* p) {
@@ -73,6 +75,10 @@ int ovl_jobs(sm_plan* p, int chunk, int kind, const OvlJob** jobs, int* n) {
   return SM_OK;
 }
 
+}  // namespace sm
+
+namespace {
+
 int check_schedule(const sm_sign_opts* o, const char* who) {
   if (!o) return set_error(SM_ERR_ARG, "%s: null sm_sign_opts", who);
   if (o->phase1 != SM_F64 || o->refine_steps != 0)
@@ -100,8 +106,8 @@ int sm_overlap_inv_sqrt(sm_plan* p, int32_t chunk, const double* S, double tol, 
   int nj;
   if ((rc = ovl_jobs(p, chunk, 0, &jobs, &nj))) return rc;
   hipStream_t s = as_stream(stream);
-  double* aux = mats_of(p, ws_aux);
-  double* wm = mats_of(p, ws);
+  double* aux = f64_mats(p, ws_aux);
+  double* wm = f64_mats(p, ws);
   double* c = p->d_ovl;                    // Gershgorin bound of T(S)
   double* res = p->d_ovl + p->max_subs;    // ||Z Y - I||_F^2 per submatrix
   const int mp = p->max_npad;
@@ -113,20 +119,21 @@ int sm_overlap_inv_sqrt(sm_plan* p, int32_t chunk, const double* S, double tol, 
   SM_HIP(launch_ovl_fill(p->dev, g0, nsub, mp, aux, 0, 1.0, 1.0, s));
   int y = 0, z = 0, it = 0;
   double r = INFINITY;
+  if (p->fd_ws == ws || p->fd_ws == ws_aux) p->fd_chunk = -1;   // both workspaces are overwritten
   const double* hres = reinterpret_cast<const double*>(p->h_pinned + kHostOvl);
   double* dres = reinterpret_cast<double*>(p->d_pinned + kHostOvl);
   for (;; ++it) {
     // W = 1/2 (3I - Z Y) into aux buffer 2, with ||Z Y - I||_F^2
     SM_HIP(launch_ovl_zero(res, nsub, s));
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, aux, z, nullptr, wm, y, aux, 2, nullptr, -0.5, 1.5, 0, res, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, aux, z, nullptr, wm, y, aux, 2, nullptr, -0.5, 1.5, nullptr, 0, 0.0, 0, res, s));
     SM_HIP(launch_ovl_max(res, nsub, dres, s));
     SM_HIP(hipStreamSynchronize(s));
     r = std::sqrt(*hres);
     if (!std::isfinite(r)) return set_error(SM_ERR_NONFINITE, "sm_overlap_inv_sqrt: non-finite residual at step %d", it);
     if (r < tol || it >= max_iter) break;
     // Y <- Y W (ws buffers 0 / 1), Z <- W Z (aux buffers 0 / 1)
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, y, nullptr, aux, 2, wm, 1 - y, nullptr, 1.0, 0.0, 0, nullptr, s));
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, aux, 2, nullptr, aux, z, aux, 1 - z, nullptr, 1.0, 0.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, y, nullptr, aux, 2, wm, 1 - y, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, aux, 2, nullptr, aux, z, aux, 1 - z, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 0, nullptr, s));
     y = 1 - y;
     z = 1 - z;
   }
@@ -158,8 +165,8 @@ int build_submatrices_overlap(sm_plan* p, int32_t chunk, const double* H, double
   int ns, nf;
   if ((rc = ovl_jobs(p, chunk, 0, &sym, &ns)) || (rc = ovl_jobs(p, chunk, 1, &full, &nf))) return rc;
   hipStream_t s = as_stream(stream);
-  const double* aux = mats_of(p, ws_aux);
-  double* wm = mats_of(p, ws);
+  const double* aux = f64_mats(p, ws_aux);
+  double* wm = f64_mats(p, ws);
   const int mp = p->max_npad;
   const WsLayout L = p->layout(SM_F64);
   double* scratch = reinterpret_cast<double*>(static_cast<char*>(ws) + L.scratch);
@@ -167,8 +174,8 @@ int build_submatrices_overlap(sm_plan* p, int32_t chunk, const double* H, double
   // T(H) (zero pad) -> ws buffer 1; Q = T(H) Z -> buffer 2; K - mu I = Q^T Z -> buffer 0
   SM_HIP(launch_ovl_fill(p->dev, g0, nsub, mp, wm, 1, 0.0, 0.0, s));
   SM_HIP(launch_ovl_gather(p->dev, g0, nsub, p->max_m, H, wm, 1, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, full, nf, wm, 1, nullptr, aux, 0, wm, 2, nullptr, 1.0, 0.0, 1, nullptr, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, sym, ns, wm, 2, nullptr, aux, 0, wm, 0, nullptr, 1.0, -mu, 0, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, full, nf, wm, 1, nullptr, aux, 0, wm, 2, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 1, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, sym, ns, wm, 2, nullptr, aux, 0, wm, 0, nullptr, 1.0, -mu, nullptr, 0, 0.0, 0, nullptr, s));
   // the identity pad of the sign iteration, its Gershgorin bound (stats.gersh),
   // then the scale and X_0 = T / c exactly as build_submatrices leaves them
   double* cg = scratch;
@@ -180,6 +187,7 @@ int build_submatrices_overlap(sm_plan* p, int32_t chunk, const double* H, double
   p->last_chunk = chunk;
   p->last_H = nullptr;   // no fallback rebuild from H alone
   p->last_mu = mu;
+  p->fd_chunk = -1;
   return SM_OK;
 }
 
@@ -194,16 +202,16 @@ int assemble_P_overlap(sm_plan* p, int32_t chunk, void* ws, const void* ws_aux_i
   int nj;
   if ((rc = ovl_jobs(p, chunk, 2, &slab, &nj))) return rc;
   hipStream_t s = as_stream(stream);
-  double* aux = mats_of(p, ws_aux_in);
-  double* wm = mats_of(p, ws);
+  double* aux = f64_mats(p, ws_aux_in);
+  double* wm = f64_mats(p, ws);
   const WsLayout L = p->layout(SM_F64);
   const SubState* st = reinterpret_cast<const SubState*>(static_cast<char*>(ws) + L.state);
   // U = X Z[:, cols] (aux buffer 2), D = Z[:, cols] - U (aux buffer 1),
   // R = 1/2 Z D (aux buffer 2): block column i of P_i
   SM_HIP(launch_ovl_xbuf(st, nsub, p->d_ovl_xbuf, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, wm, 0, p->d_ovl_xbuf, aux, 0, aux, 2, nullptr, 1.0, 0.0, 1, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, wm, 0, p->d_ovl_xbuf, aux, 0, aux, 2, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 1, nullptr, s));
   SM_HIP(launch_ovl_slab_diff(p->dev, g0, nsub, aux, 0, aux, 2, aux, 1, nullptr, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, aux, 0, nullptr, aux, 1, aux, 2, nullptr, 0.5, 0.0, 1, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, aux, 0, nullptr, aux, 1, aux, 2, nullptr, 0.5, 0.0, nullptr, 0, 0.0, 1, nullptr, s));
   SM_HIP(launch_ovl_scatter(p->dev, g0, nsub, aux, 2, P, s));
   return SM_OK;
 }

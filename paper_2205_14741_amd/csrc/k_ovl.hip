@@ -137,19 +137,22 @@ __global__ __launch_bounds__(256) void ovl_copy_kernel(DevPlan p, int g0, double
     D[e] = S[e];
 }
 
-// One 64 x 64 output tile of C = alpha M + beta I, M = alpha_l A^T B, per
-// workgroup (A, B column-major n_pad x n_pad, so A^T B = A B for symmetric A): 4 waves of
-// 32 x 32, float64 16x16x4 instructions (register v of lane l holds row
-// l / 16 + 4 v, column l % 16), k stages of 16 through LDS.  kind 0: tile
-// on or below the diagonal, entries on or below the diagonal written to
-// (r, c) and (c, r); kind 1: every entry as is.  abuf_l (may be null): per
-// submatrix buffer of A.  res (may be null): the sum over the valid n x n
-// block of (M - I)^2 per submatrix (atomic).
+// One 64 x 64 output tile of C = alpha M + beta I + gamma E, M = alpha_l A^T B,
+// per workgroup (A, B column-major n_pad x n_pad, so A^T B = A B for symmetric
+// A): 4 waves of 32 x 32, float64 16x16x4 instructions (register v of lane l
+// holds row l / 16 + 4 v, column l % 16), k stages of 16 through LDS.  kind 0:
+// tile on or below the diagonal, entries on or below the diagonal written to
+// (r, c) and (c, r) (so M and E must be symmetric); kind 1: every entry as
+// is.  abuf_l (may be null): per submatrix buffer of A.  Em (may be null):
+// buffer ebuf of the same submatrix, read at (r, c); it may be A or B but not
+// C.  res (may be null): the sum over the valid n x n block of (M - I)^2 per
+// submatrix (atomic).
 __global__ __launch_bounds__(256) void ovl_prod_kernel(DevPlan p, int g0, const OvlJob* __restrict__ jobs,
                                                        const double* Am, int abuf, const int32_t* __restrict__ abuf_l,
                                                        const double* Bm, int bbuf, double* Cm, int cbuf,
                                                        const double* __restrict__ alpha_l, double alpha, double beta,
-                                                       int kind, double* __restrict__ res) {
+                                                       const double* Em, int ebuf, double gamma, int kind,
+                                                       double* __restrict__ res) {
   constexpr int KS = 16, LD = KS + 2;
   __shared__ double la[64 * LD], lb[64 * LD];
   __shared__ double red[8];
@@ -162,6 +165,7 @@ __global__ __launch_bounds__(256) void ovl_prod_kernel(DevPlan p, int g0, const 
   const double* A = Am + p.mat_off_g[g] + (int64_t)(abuf_l ? abuf_l[l] : abuf) * nn;
   const double* B = Bm + p.mat_off_g[g] + (int64_t)bbuf * nn;
   double* C = Cm + p.mat_off_g[g] + (int64_t)cbuf * nn;
+  const double* E = Em ? Em + p.mat_off_g[g] + (int64_t)ebuf * nn : nullptr;
   const int r0 = job.bi * 64, c0 = job.bj * 64;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = wid >> 1, wn = wid & 1;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(256) void ovl_prod_kernel(DevPlan p, int g0, const 
         const double m = al * acc[x][y][v];
         const double dg = r == c ? 1.0 : 0.0;
         if (res && r < n && c < n) part += (kind == 0 && r != c ? 2.0 : 1.0) * (m - dg) * (m - dg);
-        const double out = alpha * m + beta * dg;
+        const double out = alpha * m + beta * dg + (E ? gamma * E[(int64_t)c * npad + r] : 0.0);
         C[(int64_t)c * npad + r] = out;
         if (kind == 0 && r != c) C[(int64_t)r * npad + c] = out;
       }
@@ -318,10 +322,11 @@ hipError_t launch_ovl_copy(const DevPlan& p, int g0, int nsub, int max_npad, dou
 
 hipError_t launch_ovl_prod(const DevPlan& p, int g0, const OvlJob* jobs, int njobs, const double* A, int abuf,
                            const int32_t* abuf_l, const double* B, int bbuf, double* C, int cbuf,
-                           const double* alpha_l, double alpha, double beta, int kind, double* res, hipStream_t s) {
+                           const double* alpha_l, double alpha, double beta, const double* E, int ebuf,
+                           double gamma, int kind, double* res, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
   hipLaunchKernelGGL(ovl_prod_kernel, dim3(njobs), dim3(256), 0, s, p, g0, jobs, A, abuf, abuf_l, B, bbuf, C, cbuf,
-                     alpha_l, alpha, beta, kind, res);
+                     alpha_l, alpha, beta, E, ebuf, gamma, kind, res);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 // processing order, chunking of the workspace, and the device copies of these
 // tables.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -120,6 +121,125 @@ int sm_default_opts(int32_t prec, sm_sign_opts* o) {
   return SM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Processing order -> the order-dependent tables: per processing index g the
+// submatrix, its padded size and offsets inside its chunk; chunks fill the
+// element budget in processing order (a larger submatrix forms its own);
+// every chunk's size class (256-row tiles of its largest submatrix) and the
+// default GEMM variants of every class until sm_autotune measures better
+// ones: the XCD-aware 64-wide tiles for float64 and small submatrices, the
+// 256-wide tiles for the 16-bit precisions on large ones (their float32
+// refinement on the 128-wide ring kernel), the half-depth stages on plans
+// padded to 32.
+void assign_order(sm_plan* p, const std::vector<int32_t>& order) {
+  const int32_t n = p->n_atoms;
+  p->order_g.assign(order.begin(), order.end());
+  p->npad_g.assign(n, 0);
+  p->mat_off_g.assign(n, 0);
+  p->tile_off_g.assign(n, 0);
+  p->vec_off_g.assign(n, 0);
+  p->chunk_of.assign(n, 0);
+  p->chunk_ptr.assign(1, 0);
+  p->chunk_class.clear();
+  p->max_mats = p->max_tiles = p->max_vecs = p->max_subs = 0;
+  int64_t mats = 0, tiles = 0, vecs = 0, subs = 0;
+  int32_t chunk_max = 0;
+  auto close_chunk = [&]() { p->chunk_class.push_back((chunk_max + kClassRows - 1) / kClassRows); };
+  for (int32_t g = 0; g < n; ++g) {
+    const int32_t i = order[g];
+    const int64_t np = p->npad[i];
+    const int64_t need = 3 * np * np;
+    const int64_t T = tiles_of((int)np);
+    const int64_t nt = T * (T + 1) / 2;
+    if (subs > 0 && p->max_chunk_elems > 0 && mats + need > p->max_chunk_elems) {
+      close_chunk();
+      p->chunk_ptr.push_back(g);
+      mats = tiles = vecs = subs = 0;
+      chunk_max = 0;
+    }
+    p->npad_g[g] = (int32_t)np;
+    p->mat_off_g[g] = mats;
+    p->tile_off_g[g] = (int32_t)tiles;
+    p->vec_off_g[g] = vecs;
+    p->chunk_of[i] = (int32_t)p->chunk_ptr.size() - 1;
+    chunk_max = std::max(chunk_max, (int32_t)np);
+    mats += need;
+    tiles += nt;
+    vecs += np * 2 * kMaxProbes;
+    subs += 1;
+    p->max_mats = std::max(p->max_mats, mats);
+    p->max_tiles = std::max(p->max_tiles, tiles);
+    p->max_vecs = std::max(p->max_vecs, vecs);
+    p->max_subs = std::max(p->max_subs, subs);
+  }
+  close_chunk();
+  p->chunk_ptr.push_back(n);
+  auto defaults = [&](int32_t largest, int32_t* t) {
+    const bool big = p->pad_to >= 64 && largest >= 768;
+    t[SM_F64] = 1;
+    t[SM_F32] = big ? 5 : 1;
+    for (int m : {SM_BF16, SM_F16, SM_BF16X3}) t[m] = p->pad_to < 64 ? 2 : big ? 6 : 1;
+  };
+  defaults(p->max_npad, p->tuned);
+  p->class_tuned.assign(kMaxClasses, {-1, -1, -1, -1, -1});
+  for (int32_t c : p->chunk_class) defaults(c * kClassRows, p->class_tuned[c].data());
+}
+
+// Morton (Z-order) key of a point inside [lo, lo + span)^3, 21 bits per axis.
+uint64_t morton3(const double* x, const double* lo, double span) {
+  uint64_t key = 0;
+  uint32_t q[3];
+  for (int d = 0; d < 3; ++d) {
+    const double t = span > 0 ? (x[d] - lo[d]) / span : 0.0;
+    const double c = std::min(std::max(t, 0.0), 1.0) * 2097151.0;
+    q[d] = (uint32_t)c;
+  }
+  for (int b = 20; b >= 0; --b)
+    for (int d = 0; d < 3; ++d) key = (key << 1) | ((q[d] >> b) & 1u);
+  return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sm_plan_set_positions(sm_plan* p, const double* xyz, int32_t bucket_rows) {
+  if (!p || !xyz) return set_error(SM_ERR_ARG, "sm_plan_set_positions: null argument");
+  if (p->device >= 0)
+    return set_error(SM_ERR_STATE, "sm_plan_set_positions: the plan has already been used on a device");
+  const int32_t n = p->n_atoms;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int32_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      const double v = xyz[3 * (int64_t)i + d];
+      if (!std::isfinite(v)) return set_error(SM_ERR_ARG, "sm_plan_set_positions: position of atom %d is not finite", i);
+      lo[d] = std::min(lo[d], v);
+      hi[d] = std::max(hi[d], v);
+    }
+  const double span = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]}) * (1.0 + 1e-12);
+  struct Key {
+    int32_t bucket;
+    uint64_t z;
+    int32_t i;
+  };
+  std::vector<Key> keys(n);
+  for (int32_t i = 0; i < n; ++i)
+    keys[i] = Key{bucket_rows > 0 ? p->npad[i] / bucket_rows : 0, morton3(xyz + 3 * (int64_t)i, lo, span), i};
+  // larger size buckets first, Morton order inside a bucket, atom id on ties
+  std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+    if (a.bucket != b.bucket) return a.bucket > b.bucket;
+    if (a.z != b.z) return a.z < b.z;
+    return a.i < b.i;
+  });
+  std::vector<int32_t> order(n);
+  for (int32_t g = 0; g < n; ++g) order[g] = keys[g].i;
+  assign_order(p, order);
+  return SM_OK;
+}
+
 int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_elems,
                    sm_plan** out) {
   if (!pat || !out) return set_error(SM_ERR_ARG, "sm_plan_create: null argument");
@@ -202,49 +322,10 @@ int sm_plan_create(const sm_bsr_pattern* pat, int32_t pad_to, int64_t max_chunk_
       }
     }
   }
-  // processing order: atoms in index order; chunks fill the element budget
-  p->order_g.resize(n);
-  p->npad_g.resize(n);
-  p->mat_off_g.resize(n);
-  p->tile_off_g.resize(n);
-  p->vec_off_g.resize(n);
-  p->chunk_of.resize(n);
-  p->chunk_ptr.push_back(0);
-  int64_t mats = 0, tiles = 0, vecs = 0, subs = 0;
-  for (int32_t g = 0; g < n; ++g) {
-    int32_t i = g;
-    int64_t np = p->npad[i];
-    int64_t need = 3 * np * np;
-    int64_t T = tiles_of((int)np);
-    int64_t nt = T * (T + 1) / 2;
-    if (subs > 0 && max_chunk_elems > 0 && mats + need > max_chunk_elems) {
-      p->chunk_ptr.push_back(g);
-      mats = tiles = vecs = subs = 0;
-    }
-    p->order_g[g] = i;
-    p->npad_g[g] = (int32_t)np;
-    p->mat_off_g[g] = mats;
-    p->tile_off_g[g] = (int32_t)tiles;
-    p->vec_off_g[g] = vecs;
-    p->chunk_of[i] = (int32_t)p->chunk_ptr.size() - 1;
-    mats += need;
-    tiles += nt;
-    vecs += np * 2 * kMaxProbes;
-    subs += 1;
-    p->max_mats = std::max(p->max_mats, mats);
-    p->max_tiles = std::max(p->max_tiles, tiles);
-    p->max_vecs = std::max(p->max_vecs, vecs);
-    p->max_subs = std::max(p->max_subs, subs);
-  }
-  p->chunk_ptr.push_back(n);
-  // GEMM variants until sm_autotune measures better ones: the XCD-aware
-  // 64-wide tiles for float64 and small submatrices, the 256-wide tiles for
-  // the 16-bit precisions on large ones (their float32 refinement on the
-  // 128-wide ring kernel), the half-depth stages on plans padded to 32
-  const bool big = p->pad_to >= 64 && p->max_npad >= 768;
-  p->tuned[SM_F64] = 1;
-  p->tuned[SM_F32] = big ? 5 : 1;
-  for (int m : {SM_BF16, SM_F16, SM_BF16X3}) p->tuned[m] = p->pad_to < 64 ? 2 : big ? 6 : 1;
+  p->max_chunk_elems = max_chunk_elems;
+  std::vector<int32_t> order(n);
+  for (int32_t g = 0; g < n; ++g) order[g] = g;
+  assign_order(p, order);
   *out = p;
   return SM_OK;
 }

@@ -1,6 +1,7 @@
 // Host-side plan object and error helpers (internal).
 #pragma once
 
+#include <array>
 #include <string>
 #include <vector>
 
@@ -13,6 +14,11 @@ constexpr int kHostBracket = 32;   // two doubles
 constexpr int kHostNe = 36;        // one double
 constexpr int kHostRetry = 40;     // submatrices of a chunk queued for the fallback retry
 constexpr int kHostTrace = 10;     // E, Ne
+constexpr int kHostOvl = 44;       // one double: largest residual of the S != I inverse square roots
+constexpr int kHostFd = 46;        // one double: largest bound of |beta x| (finite temperature)
+constexpr int kHostDne = 48;       // one double: dNe / dmu
+constexpr int kClassRows = 256;    // size class of a chunk: 256-row tiles of its largest submatrix
+constexpr int kMaxClasses = 32767 / kClassRows + 2;
 
 struct sm_plan {
   // pattern (copied from the caller)
@@ -38,6 +44,8 @@ struct sm_plan {
   std::vector<int64_t> vec_off_g;   // probe / power vector offset inside the chunk
   std::vector<int32_t> chunk_of;    // [n_atoms] chunk of every submatrix
   std::vector<int64_t> chunk_ptr;   // [n_chunks+1] ranges of g
+  std::vector<int32_t> chunk_class; // [n_chunks] size class (kClassRows tiles of its largest n_pad)
+  int64_t max_chunk_elems = 0;      // the chunk budget the plan was created with
   int64_t max_mats = 0;             // max over chunks of sum 3 npad^2
   int64_t max_subs = 0;
   int64_t max_tiles = 0;
@@ -68,7 +76,19 @@ struct sm_plan {
   int last_chunk = -1;
   const double* last_H = nullptr;
   double last_mu = 0.0;
-  int32_t tuned[5] = {0, 0, 0, 0, 0};  // GEMM variant per precision (sm_autotune)
+  int32_t tuned[5] = {0, 0, 0, 0, 0};  // plan-wide GEMM variant per precision (sm_plan_tuning)
+  // GEMM variants of every size class (sm_autotune of a chunk sets its
+  // class's; [0] < 0: the class has no chunk), and the chunk whose class
+  // the next launches use
+  std::vector<std::array<int32_t, 5>> class_tuned;
+  int active_chunk = -1;
+  const int32_t* tuned_for(int chunk) const {
+    if (chunk >= 0 && chunk < (int)chunk_class.size()) {
+      const auto& t = class_tuned[chunk_class[chunk]];
+      if (t[0] >= 0) return t.data();
+    }
+    return tuned;
+  }
   // captured iteration graphs (sm_sign_opts.graph_iters)
   struct GraphEntry {
     int chunk;
@@ -98,6 +118,15 @@ struct sm_plan {
   int ovl_chunk = -1;               // chunk whose Z_i the auxiliary workspace holds (-1: none)
   const void* ovl_aux = nullptr;    // that workspace
 
+  // finite temperature: [2 * max_subs] per-submatrix scalars (s, s^2) and
+  // [n_atoms] dNe / dmu of every atom; the chunk, workspace and buffer that
+  // hold the last f(T_i)
+  double* d_fd = nullptr;
+  double* d_fd_dne = nullptr;
+  int fd_chunk = -1;
+  const void* fd_ws = nullptr;
+  int fd_buf = -1;
+
   sm::WsLayout layout(int storage) const;
   // float offset of a float32 buffer's pre-converted operand copy
   int64_t shadow_off() const { return max_mats; }
@@ -112,6 +141,14 @@ int ensure_device(sm_plan* p);
 int storage_is_f64(const sm_sign_opts* o);
 int ws_storage(const sm_sign_opts* o);
 bool valid_storage(int storage);
+// float64 submatrix buffers of a workspace (the SM_F64 layout)
+double* f64_mats(const sm_plan* p, const void* ws);
+// device tables of the float64 tile products (api_ovl.cpp): per-submatrix
+// scalars, and the tile list of a product kind over a chunk (0 lower
+// triangle, 1 all tiles, 2 the tile columns of the atom's own columns),
+// built once and kept on the device
+int ensure_ovl(sm_plan* p);
+int ovl_jobs(sm_plan* p, int chunk, int kind, const OvlJob** jobs, int* n);
 }  // namespace sm
 
 #define SM_HIP(expr)                                         \

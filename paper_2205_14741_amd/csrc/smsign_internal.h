@@ -218,7 +218,17 @@ hipError_t launch_ovl_copy(const DevPlan& p, int g0, int nsub, int max_npad, dou
                            hipStream_t s);
 hipError_t launch_ovl_prod(const DevPlan& p, int g0, const OvlJob* jobs, int njobs, const double* A, int abuf,
                            const int32_t* abuf_l, const double* B, int bbuf, double* C, int cbuf,
-                           const double* alpha_l, double alpha, double beta, int kind, double* res, hipStream_t s);
+                           const double* alpha_l, double alpha, double beta, const double* E, int ebuf,
+                           double gamma, int kind, double* res, hipStream_t s);
+// Finite-temperature occupation (k_fermi.hip).
+hipError_t launch_fd_bound(const DevPlan& p, int g0, int nsub, const sm_sub_stats* stats, double beta, double* out,
+                           hipStream_t s);
+hipError_t launch_fd_coef(const DevPlan& p, int g0, int nsub, const sm_sub_stats* stats, double beta, double inv2m1,
+                          double* sv, double* s2, hipStream_t s);
+hipError_t launch_fd_lincomb(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int xb, double a, int yb,
+                             double b, double d, int cb, hipStream_t s);
+hipError_t launch_fd_count(const DevPlan& p, int g0, int nsub, const double* mats, int fb, double beta, double* ne,
+                           double* dne, hipStream_t s);
 hipError_t launch_ovl_slab_diff(const DevPlan& p, int g0, int nsub, const double* Z, int zbuf, const double* U,
                                 int ubuf, double* D, int dbuf, const double* f_l, hipStream_t s);
 hipError_t launch_ovl_scatter(const DevPlan& p, int g0, int nsub, const double* R, int rbuf, double* P, hipStream_t s);

@@ -11,7 +11,10 @@
         [--kernels ns_gemm] --out SUMMARY.txt
 
 `stats` lists the kernels of a kernel-trace run by total time (calls, average,
-total, share).  `traffic` averages the FETCH_SIZE and WRITE_SIZE counters (KiB
+total, share); with `--trace RUN_kernel_trace.csv --tail KERNEL=N` it also
+averages the last N dispatches of KERNEL (a benchmark's timed steps come
+last, after its set-up launches of the same kernel).  `traffic --tail` does the
+same for the counters.  `traffic` averages the FETCH_SIZE and WRITE_SIZE counters (KiB
 per dispatch) of every GEMM kernel over two counter runs, and scales each by
 what the same counter reads for a plain copy kernel of known size (the
 elementwise negation of a float32 buffer of B bytes, run by the profiled
@@ -47,7 +50,19 @@ def short_name(name: str) -> str:
     return (m.group(1) if m else name).strip()
 
 
-def stats_summary(path: str, cmd: str, top: int = 25) -> str:
+def parse_tails(specs) -> list:
+    """'KERNEL=N' items: the last N dispatches of KERNEL (a short name)."""
+    out = []
+    for spec in specs or []:
+        name, _, n = spec.rpartition("=")
+        out.append((name.strip(), int(n)))
+    return out
+
+
+def stats_summary(path: str, cmd: str, top: int = 25, trace: str | None = None, tails=()) -> str:
+    """Kernels by total time; with the per-dispatch trace, also the average
+    duration of the last N dispatches of each kernel in `tails` (the
+    profiled benchmark's timed steps come last)."""
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     out = ["# rocprofv3 --kernel-trace --stats", f"# command: {cmd}",
@@ -56,20 +71,39 @@ def stats_summary(path: str, cmd: str, top: int = 25) -> str:
         out.append(f"  {short_name(r['Name'])[:64]:64s} {int(r['Calls']):7d} "
                    f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['TotalDurationNs']) / 1e6:10.3f} "
                    f"{float(r['Percentage']):6.2f}")
+    if trace and tails:
+        out.append("# tail <kernel> | last N dispatches | their average duration (us)")
+        disp = collections.defaultdict(list)
+        for r in csv.DictReader(open(trace)):
+            disp[short_name(r["Kernel_Name"])].append(
+                (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        for name, n in tails:
+            d = sorted(disp.get(name, []))[-n:]
+            if d:
+                out.append(f"tail {name} | {len(d)} | {sum(x[1] for x in d) / len(d) / 1e3:.2f}")
     return "\n".join(out) + "\n"
 
 
-def counter_means(path: str, counter: str) -> dict:
-    """{kernel short name: (dispatches, mean counter value per dispatch)}."""
+def counter_means(path: str, counter: str, tails: dict | None = None) -> dict:
+    """{kernel short name: (dispatches, mean counter value per dispatch)};
+    for a kernel in `tails` ({name: N}) only its last N dispatches count."""
     acc = collections.defaultdict(list)
-    for r in csv.DictReader(open(path)):
+    for i, r in enumerate(csv.DictReader(open(path))):
         if r["Counter_Name"] != counter:
             continue
-        acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-    return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
+        order = int(r["Dispatch_Id"]) if r.get("Dispatch_Id") else i
+        acc[short_name(r["Kernel_Name"])].append((order, float(r["Counter_Value"])))
+    out = {}
+    for k, v in acc.items():
+        v.sort()
+        if tails and k in tails:
+            v = v[-tails[k]:]
+        out[k] = (len(v), sum(x[1] for x in v) / len(v))
+    return out
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, cmd_f: str, cmd_w: str) -> str:
+def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, cmd_f: str, cmd_w: str,
+                    tails=()) -> str:
     fe = counter_means(fetch_csv, "FETCH_SIZE")
     wr = counter_means(write_csv, "WRITE_SIZE")
     copy_f = [v for k, v in fe.items() if "neg" in k]
@@ -91,6 +125,17 @@ def traffic_summary(fetch_csv: str, write_csv: str, copy_bytes: float, cmd_f: st
         n, f = fe[k]
         _, w = wr[k]
         out.append(f"traffic {k} | {n} | {f:.1f} | {w:.1f} | {f * 1024 * ff + w * 1024 * fw:.0f}")
+    if tails:
+        # the profiled benchmark's timed steps come last: the same kernel
+        # averaged over its last N dispatches only
+        td = dict(tails)
+        fe_t, wr_t = counter_means(fetch_csv, "FETCH_SIZE", td), counter_means(write_csv, "WRITE_SIZE", td)
+        out.append("# traffic_tail <kernel> | last N dispatches | fetch_kib | write_kib | scaled_bytes_per_dispatch")
+        for k, _ in tails:
+            if k in fe_t and k in wr_t:
+                n, f = fe_t[k]
+                _, w = wr_t[k]
+                out.append(f"traffic_tail {k} | {n} | {f:.1f} | {w:.1f} | {f * 1024 * ff + w * 1024 * fw:.0f}")
     return "\n".join(out) + "\n"
 
 
@@ -113,24 +158,31 @@ def mfma_summary(csv_path: str, cmd: str) -> str:
     return "\n".join(out) + "\n"
 
 
-def counters_summary(csv_paths: list, cmds: list, kernels_like: str = "") -> str:
+def counters_summary(csv_paths: list, cmds: list, kernels_like: str = "", tails=()) -> str:
     """Mean value per dispatch of every counter in the given counter-collection
     CSVs (one rocprofv3 --pmc pass each), by kernel: one line per (kernel,
-    counter).  kernels_like: keep only kernels whose name contains it."""
+    counter).  kernels_like: keep only kernels whose name contains it.  For a
+    kernel in `tails` ((name, N) pairs) only its last N dispatches count."""
+    td = dict(tails)
     rows = collections.defaultdict(lambda: collections.defaultdict(list))
     for path in csv_paths:
-        for r in csv.DictReader(open(path)):
+        for i, r in enumerate(csv.DictReader(open(path))):
             k = short_name(r["Kernel_Name"])
             if kernels_like and kernels_like not in k:
                 continue
-            rows[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+            order = int(r["Dispatch_Id"]) if r.get("Dispatch_Id") else i
+            rows[k][r["Counter_Name"]].append((order, float(r["Counter_Value"])))
     out = ["# rocprofv3 --pmc, one pass per command (counters summed over the chip, mean per dispatch)"]
     out += [f"# command (pass {i + 1}): {c}" for i, c in enumerate(cmds)]
+    if td:
+        out.append("# last dispatches only: " + ", ".join(f"{k} (last {n})" for k, n in td.items()))
     out.append("# counter <kernel> | dispatches | counter | mean per dispatch")
     for k in sorted(rows):
         for cn in sorted(rows[k]):
-            v = rows[k][cn]
-            out.append(f"counter {k} | {len(v)} | {cn} | {sum(v) / len(v):.6g}")
+            v = sorted(rows[k][cn])
+            if k in td:
+                v = v[-td[k]:]
+            out.append(f"counter {k} | {len(v)} | {cn} | {sum(x[1] for x in v) / len(v):.6g}")
     return "\n".join(out) + "\n"
 
 
@@ -140,15 +192,17 @@ def read_traffic(path: str, symbol: str):
     sources other than the current ones."""
     if not os.path.exists(path):
         return None
-    sha, val = None, None
+    sha, val, tail = None, None, None
     for line in open(path):
         if line.startswith("gemm_source_sha "):
             sha = line.split()[1]
         elif line.startswith("traffic ") and line[8:].split(" | ")[0].strip() == symbol:
             val = float(line.rsplit("|", 1)[1])
+        elif line.startswith("traffic_tail ") and line[13:].split(" | ")[0].strip() == symbol:
+            tail = float(line.rsplit("|", 1)[1])
     if sha != gemm_source_hash():
         return None
-    return val
+    return tail if tail is not None else val
 
 
 def main():
@@ -157,6 +211,8 @@ def main():
     s = sub.add_parser("stats")
     s.add_argument("--csv", required=True)
     s.add_argument("--cmd", dest="command", required=True)
+    s.add_argument("--trace", default=None, help="the run's kernel_trace.csv (for --tail)")
+    s.add_argument("--tail", nargs="*", default=[], metavar="KERNEL=N")
     s.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
@@ -164,11 +220,13 @@ def main():
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
+    t.add_argument("--tail", nargs="*", default=[], metavar="KERNEL=N")
     t.add_argument("--out", required=True)
     cn = sub.add_parser("counters")
     cn.add_argument("--csv", nargs="+", required=True)
     cn.add_argument("--cmd", dest="commands", nargs="+", required=True)
     cn.add_argument("--kernels", default="")
+    cn.add_argument("--tail", nargs="*", default=[], metavar="KERNEL=N")
     cn.add_argument("--out", required=True)
     mf = sub.add_parser("mfma")
     mf.add_argument("--csv", required=True)
@@ -176,13 +234,13 @@ def main():
     mf.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
-        text = stats_summary(a.csv, a.command)
+        text = stats_summary(a.csv, a.command, trace=a.trace, tails=parse_tails(a.tail))
     elif a.cmd == "mfma":
         text = mfma_summary(a.csv, a.command)
     elif a.cmd == "counters":
-        text = counters_summary(a.csv, a.commands, a.kernels)
+        text = counters_summary(a.csv, a.commands, a.kernels, parse_tails(a.tail))
     else:
-        text = traffic_summary(a.fetch, a.write, a.copy_bytes, a.cmd_fetch, a.cmd_write)
+        text = traffic_summary(a.fetch, a.write, a.copy_bytes, a.cmd_fetch, a.cmd_write, parse_tails(a.tail))
     with open(a.out, "w") as fh:
         fh.write(text)
     print(text)

@@ -29,6 +29,8 @@ EXPORTED = (
     "sm_mlp_loss_grad", "sm_mlp_train", "sm_plan_set_mlp", "sm_autotune", "sm_plan_tuning", "sm_ws_storage",
     "sm_comm_probe", "sm_gershgorin_bracket_noalloc", "sm_overlap_inv_sqrt", "build_submatrices_overlap",
     "assemble_P_overlap", "sm_density_matrix_overlap", "sm_gemm_variants", "sm_scaling_pairs",
+    "sm_fermi_dirac", "assemble_P_fermi", "sm_density_matrix_fermi", "sm_find_mu_fermi",
+    "sm_plan_set_positions", "sm_plan_chunk_variants",
 )
 
 
@@ -107,6 +109,13 @@ def lib() -> C.CDLL:
         "sm_density_matrix_overlap": (i32, [vp, vp, vp, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp]),
         "sm_find_mu": (i32, [vp, vp, dbl, dbl, i32, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp, vp, vp,
                              vp]),
+        "sm_fermi_dirac": (i32, [vp, i32, vp, dbl, vp, vp, vp]),
+        "sm_plan_set_positions": (i32, [vp, vp, i32]),
+        "sm_plan_chunk_variants": (i32, [vp, i32, vp, vp]),
+        "assemble_P_fermi": (i32, [vp, i32, vp, vp, vp]),
+        "sm_density_matrix_fermi": (i32, [vp, vp, dbl, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp, vp]),
+        "sm_find_mu_fermi": (i32, [vp, vp, dbl, dbl, dbl, i32, dbl, C.POINTER(SignOpts), vp, vp, vp, vp, vp, vp,
+                                   vp, vp, vp, vp]),
         "sm_gershgorin_bracket": (i32, [vp, vp, vp, vp, vp]),
         "sm_gershgorin_bracket_noalloc": (i32, [vp, vp, vp, vp]),
         "sm_selftest_mfma": (i32, [i32, vp]),
@@ -209,6 +218,20 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_positions(self, xyz, bucket_rows: int = 512):
+        """Processing order: size buckets of bucket_rows padded rows (larger
+        first), Morton order of the atom centres inside a bucket.  Before the
+        plan's first device use."""
+        x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(self.n_atoms, 3)
+        _check(lib().sm_plan_set_positions(self.handle, x.ctypes.data, int(bucket_rows)))
+
+    def chunk_variants(self, chunk: int):
+        """(size class, GEMM variant per precision) of a chunk."""
+        cls = C.c_int32()
+        v = np.zeros(5, np.int32)
+        _check(lib().sm_plan_chunk_variants(self.handle, int(chunk), C.byref(cls), v.ctypes.data))
+        return int(cls.value), v.tolist()
 
     def sizes(self, storage: int):
         v = [C.c_int64() for _ in range(4)]
@@ -325,6 +348,46 @@ def sm_find_mu(plan: Plan, H, n_target: float, opts: SignOpts, ws, stats, P=None
     if energy:
         return mu.value, k, hist, E.value, Ne.value
     return mu.value, k, hist
+
+
+def sm_fermi_dirac(plan: Plan, chunk: int, ws, beta: float, stats, stream=None):
+    """f(T_i) = (I + exp(beta T_i))^-1 for the chunk's submatrices (after
+    build_submatrices with the float64 schedule); returns the doublings m."""
+    m = C.c_int32()
+    _check(lib().sm_fermi_dirac(plan.handle, int(chunk), _ptr(ws), float(beta), _ptr(stats), C.byref(m),
+                                _stream(stream)))
+    return m.value
+
+
+def assemble_P_fermi(plan: Plan, chunk: int, ws, P, stream=None):
+    _check(lib().assemble_P_fermi(plan.handle, int(chunk), _ptr(ws), _ptr(P), _stream(stream)))
+
+
+def sm_density_matrix_fermi(plan: Plan, H, mu: float, beta: float, opts: SignOpts, ws, P, stats, stream=None):
+    """Finite-temperature P at fixed mu; returns (E = tr(PH), Ne = tr P, dNe/dmu)."""
+    _check_ws(plan, ws, opts)
+    E, Ne, dNe = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().sm_density_matrix_fermi(plan.handle, _ptr(H), float(mu), float(beta), C.byref(opts), _ptr(ws),
+                                         _ptr(P), _ptr(stats), C.byref(E), C.byref(Ne), C.byref(dNe),
+                                         _stream(stream)))
+    return E.value, Ne.value, dNe.value
+
+
+def sm_find_mu_fermi(plan: Plan, H, n_target: float, beta: float, opts: SignOpts, ws, P, stats, tol=1e-8,
+                     max_steps=60, mu_start=None, stream=None):
+    """(mu, evaluations, [(mu_k, Ne_k)], E, Ne) at inverse temperature beta:
+    safeguarded Newton on the electron count; P holds P at mu."""
+    _check_ws(plan, ws, opts)
+    mu, steps = C.c_double(), C.c_int32()
+    E, Ne = C.c_double(), C.c_double()
+    mh = np.zeros(max_steps)
+    nh = np.zeros(max_steps)
+    _check(lib().sm_find_mu_fermi(plan.handle, _ptr(H), float(n_target), float(beta), float(tol), int(max_steps),
+                                  float("nan") if mu_start is None else float(mu_start), C.byref(opts), _ptr(ws),
+                                  _ptr(P), _ptr(stats), C.byref(mu), C.byref(steps), mh.ctypes.data,
+                                  nh.ctypes.data, C.byref(E), C.byref(Ne), _stream(stream)))
+    k = steps.value
+    return mu.value, k, list(zip(mh[:k].tolist(), nh[:k].tolist())), E.value, Ne.value
 
 
 def sm_gershgorin_bracket(plan: Plan, H, stream=None):

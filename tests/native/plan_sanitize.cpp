@@ -4,6 +4,7 @@
 // with ragged block sizes), every padding and chunk budget, every storage
 // code, and each malformed pattern the plan must refuse.  Touches no device.
 // Exit status 0 when every check holds; prints the first failure otherwise.
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -82,15 +83,22 @@ bool read_pattern(const char* path, Pattern& p) {
   return ok;
 }
 
-// every pad and budget: sizes, the per-atom tables and their invariants
+// every pad and budget, in index order and in the order of positions (size
+// buckets, Morton order): sizes, the per-atom tables and their invariants
 void exercise(const Pattern& p) {
   const int n = (int)p.bs.size();
   const sm_bsr_pattern v = p.view();
-  for (int pad : {32, 64, 128}) {
+  std::vector<double> xyz(3 * (size_t)n);
+  for (int i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) xyz[3 * i + d] = std::sin(1.7 * i + 2.3 * d) * (d + 1);
+  for (int pad : {32, 64, 128})
+  for (int bucket : {-1, 0, 64})
+  {
     for (int64_t budget : {(int64_t)0, (int64_t)3 * 64 * 64, (int64_t)1 << 22}) {
       sm_plan* plan = nullptr;
       CHECK(sm_plan_create(&v, pad, budget, &plan) == SM_OK && plan);
       if (!plan) continue;
+      if (bucket >= 0) CHECK(sm_plan_set_positions(plan, xyz.data(), bucket) == SM_OK);
       std::vector<int32_t> nn(n), npad(n), loc(n), chunk(n), order(n);
       CHECK(sm_plan_info(plan, nn.data(), npad.data(), loc.data(), chunk.data(), order.data()) == SM_OK);
       int64_t n_sub = 0, n_chunks = 0, ws = 0, nvals = 0;
@@ -111,6 +119,15 @@ void exercise(const Pattern& p) {
       }
       for (int i = 0; i < n; ++i) CHECK(seen[i] == 1);
       if (budget == 0) CHECK(n_chunks == 1);
+      // chunks are contiguous ranges of the processing order
+      for (int g = 1; g < n; ++g) CHECK(chunk[order[g]] == chunk[order[g - 1]] || chunk[order[g]] == chunk[order[g - 1]] + 1);
+      if (bucket > 0)   // larger buckets first
+        for (int g = 1; g < n; ++g) CHECK(npad[order[g]] / bucket <= npad[order[g - 1]] / bucket);
+      if (bucket >= 0) {
+        std::vector<double> bad(xyz);
+        bad[0] = NAN;
+        CHECK(sm_plan_set_positions(plan, bad.data(), bucket) == SM_ERR_ARG);
+      }
       sm_plan_destroy(plan);
     }
   }

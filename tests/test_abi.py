@@ -91,6 +91,35 @@ def test_chunking_respects_budget():
     assert ws_small < ws_full
 
 
+def test_positions_order():
+    """Morton order of the atom centres: a permutation in which consecutive
+    atoms are close (much closer than in the random sequential placement
+    order), larger size buckets first, chunks contiguous in the new order;
+    refused once the plan lives on a device (not testable here) or for a
+    non-finite position."""
+    m = synth.water_system(64, 1.5, 2)
+    p = sm.Plan(m, 64, 3 * 256 * 256 * 8)
+    p.set_positions(m.positions, bucket_rows=0)
+    info = p.info()
+    order = info["order"]
+    assert sorted(order) == list(range(m.n_atoms))
+    pos = m.positions
+
+    def mean_step(o, lag=9):   # atoms three molecules apart in the order
+        return float(np.mean(np.linalg.norm(pos[o[lag:]] - pos[o[:-lag]], axis=1)))
+
+    assert mean_step(order) < 0.75 * mean_step(np.arange(m.n_atoms))
+    ch = info["chunk"][order]
+    assert np.all(np.diff(ch) >= 0) and np.all(np.diff(ch) <= 1)
+    p.set_positions(m.positions, bucket_rows=64)
+    info = p.info()
+    assert np.all(np.diff(info["npad"][info["order"]] // 64) <= 0)
+    bad = m.positions.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(sm.SmError):
+        p.set_positions(bad)
+
+
 def test_pad_128():
     m = synth.config1()
     info = sm.Plan(m, 128).info()

@@ -18,6 +18,9 @@ def test_defaults():
     a = bench.parse(["--steps", "20", "--warmup", "5", "--config", "cfg4"])
     assert (a.steps, a.warmup, a.config) == (20, 5, "cfg4")
     assert "cfg3" in bench.WORKLOADS and "cfg4" in bench.WORKLOADS
+    assert a.fermi == 0.0     # the sign path unless a finite temperature is asked for
+    a = bench.parse(["--fermi", "20", "--config", "cfg2"])
+    assert a.fermi == 20.0 and a.config == "cfg2"
 
 
 def test_more_than_one_gpu_is_refused():

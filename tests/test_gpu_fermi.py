@@ -1,0 +1,195 @@
+"""The finite-temperature occupation (Fermi-Dirac f of Fig. 2) on the GPU
+through the C ABI, against the oracle (oracle/fermi.py): P entry by entry,
+tr(PH), tr P, dNe/dmu, the doubling count, mu from the electron count, the
+zero-temperature limit and the error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fermi as fd
+from oracle import submatrix as om
+from paper_2205_14741_amd import smsign as sm
+from gpu_helpers import gap_mu, h_dev, rel, run_fixed_mu
+
+pytestmark = pytest.mark.gpu
+
+
+def _fd_run(m, mu, beta, pad_to=64, max_chunk_elems=0, scaling=sm.SM_SCALE_GERSHGORIN):
+    import torch
+    plan = sm.Plan(m, pad_to, max_chunk_elems)
+    o = sm.default_opts("f64", retry=0, scaling=scaling)
+    H = h_dev(m)
+    w = sm.Workspace(plan, sm.SM_F64, H.device)
+    E, Ne, dNe = sm.sm_density_matrix_fermi(plan, H, mu, beta, o, w.ws, w.P, w.stats)
+    torch.cuda.synchronize()
+    return w.P.cpu().numpy(), E, Ne, dNe, w, plan
+
+
+def _water16():
+    return synth.water_system(16, 1.5, 3)
+
+
+CASES = [
+    # (system, pad, mu, beta): small, moderate and large beta x spectral radius
+    ("config1", 64, -0.1, 0.5),
+    ("config1", 64, -0.1, 6.0),
+    ("config1", 32, 0.05, 60.0),
+    ("water16", 64, -2.5, 2.0),
+    ("water16", 64, -2.5, 25.0),
+]
+
+
+@pytest.mark.parametrize("name,pad_to,mu,beta", CASES,
+                         ids=[f"{c[0]}-pad{c[1]}-beta{c[3]}" for c in CASES])
+def test_fermi_dirac_parity(name, pad_to, mu, beta, dev):
+    """Every entry of P against f(T_i) of the oracle (eigendecomposition):
+    max |dP| < 1e-10; tr(PH) and tr P to 1e-11 relative; dNe/dmu to 1e-9
+    relative, or, where the occupations are all near 0 or 1 and the
+    derivative is tiny, to the rounding of its terms (each F_qq - sum_r F_rq^2
+    is a difference of numbers near 1: beta x 1e-13 per orbital)."""
+    m = synth.config1(0) if name == "config1" else _water16()
+    P, E, Ne, dNe, w, _ = _fd_run(m, mu, beta, pad_to)
+    Po = fd.density_matrix_fd(m, mu, beta)
+    Eo, Neo = om.energy_trace(m, Po)
+    dNeo = fd.FermiCache(m).dne(mu, beta)
+    dP = float(np.max(np.abs(P - Po)))
+    print(f"{name} beta {beta}: max|dP| {dP:.2e}, E {E:.12f} ({Eo:.12f}), Ne {Ne:.10f} ({Neo:.10f}), "
+          f"dNe {dNe:.12e} ({dNeo:.12e})")
+    assert np.all(np.isfinite(P))
+    assert dP < 1e-10
+    assert rel(E, Eo) < 1e-11 and abs(Ne - Neo) < 1e-10 * max(1.0, Neo)
+    assert abs(dNe - dNeo) <= 1e-9 * abs(dNeo) + beta * m.n_orb * 1e-13
+
+
+def test_fermi_doublings_follow_the_bound(dev):
+    """m is the smallest count with beta max(c_G, c) <= 2^(m+1) / 4 over the
+    chunk (c_G, c from the records the build wrote)."""
+    import torch
+    m = synth.config1(0)
+    plan = sm.Plan(m, 64)
+    o = sm.default_opts("f64", retry=0)
+    H = h_dev(m)
+    w = sm.Workspace(plan, sm.SM_F64, H.device)
+    for beta in (0.01, 3.0, 200.0):
+        sm.build_submatrices(plan, 0, H, 0.0, o, w.ws, w.stats)
+        got = sm.sm_fermi_dirac(plan, 0, w.ws, beta, w.stats)
+        torch.cuda.synchronize()
+        st = w.stats_host()
+        bound = beta * float(np.max(np.maximum(st["gersh"], st["scale"])))
+        want = 0
+        while bound > 0.25 * 2.0 ** (want + 1):
+            want += 1
+        assert got == want, (beta, got, want)
+
+
+def test_fermi_chunked_and_power_scaled(dev):
+    """Several workspace chunks, and the power-iteration scale (X_0 = T / c
+    with another c), give the single-chunk Gershgorin-scaled result."""
+    m = _water16()
+    P1, E1, Ne1, d1, _, _ = _fd_run(m, -2.5, 8.0)
+    P2, E2, Ne2, d2, _, p2 = _fd_run(m, -2.5, 8.0, max_chunk_elems=3 * 320 * 320)
+    P3, E3, _, _, _, _ = _fd_run(m, -2.5, 8.0, scaling=sm.SM_SCALE_POWER)
+    assert p2.n_chunks > 2
+    # the chunks set their own doubling counts, so rounding differs: dNe/dmu to
+    # the rounding of its terms (beta x 1e-13 per orbital)
+    assert float(np.max(np.abs(P1 - P2))) < 1e-13 and rel(E2, E1) < 1e-13
+    assert abs(d2 - d1) <= 8.0 * m.n_orb * 1e-13
+    assert float(np.max(np.abs(P1 - P3))) < 1e-11 and rel(E3, E1) < 1e-12
+
+
+def test_fermi_zero_temperature_limit(dev):
+    """mu in the gap, beta x (distance of the nearest submatrix eigenvalue) =
+    60: P equals the float64 sign path's P of Eq. 14."""
+    m = synth.config1(0)
+    mu = gap_mu(m)
+    cache = fd.FermiCache(m)
+    beta = 60.0 / float(np.min(np.abs(cache.lam - mu)))
+    P, E, Ne, _, _, _ = _fd_run(m, mu, beta)
+    P0, E0, Ne0, _, _ = run_fixed_mu(m, mu, "f64", pad_to=64)
+    print(f"beta {beta:.1f}: max|P - P_sign| {np.max(np.abs(P - P0)):.2e}")
+    assert float(np.max(np.abs(P - P0))) < 1e-10
+    assert rel(E, E0) < 1e-11 and abs(Ne - Ne0) < 1e-9
+
+
+def test_fermi_fully_coupled_is_the_whole_function(dev):
+    """Every submatrix is the whole H - mu I: P = f(H - mu I) exactly."""
+    m = synth.fully_coupled_lattice(4)
+    beta, mu = 4.0, 0.2
+    P, E, Ne, _, _, _ = _fd_run(m, mu, beta)
+    lam, V = np.linalg.eigh(synth.to_dense(m))
+    occ = fd.fermi(lam - mu, beta)
+    Pd = (V * occ) @ V.T
+    assert float(np.max(np.abs(synth.to_dense(m.with_vals(P)) - Pd))) < 1e-11
+    assert abs(Ne - math.fsum(occ.tolist())) < 1e-10
+
+
+def test_fermi_several_tiles_sampled(dev):
+    """Larger submatrices (several 64-tiles and a ragged tail): sampled block
+    columns against the oracle."""
+    m = synth.water_system(48, 2.2, 5)
+    P, E, Ne, dNe, w, plan = _fd_run(m, -2.0, 10.0)
+    info = plan.info()
+    assert int(info["npad"].max()) >= 256 and np.any(info["n"] % 64 != 0)
+    atoms = [0, 17, 60, 101, int(m.n_atoms) - 1]
+    Po = fd.density_matrix_fd(m, -2.0, 10.0, atoms=atoms)
+    sel = ~np.isnan(Po)
+    dP = float(np.max(np.abs(P[sel] - Po[sel])))
+    print(f"n {info['n'].min()}-{info['n'].max()}, sampled max|dP| {dP:.2e}")
+    assert dP < 1e-10
+
+
+@pytest.mark.parametrize("name", ["config1", "water16"])
+def test_find_mu_fermi(name, dev):
+    """The mu that meets the electron count at finite temperature against the
+    oracle's bisection: the counts agree to the tolerance, mu to tol / (dNe/dmu)
+    and a rounding margin; Newton needs few evaluations, fewer again from a
+    warm start; P at the returned mu is the oracle's."""
+    import torch
+    m = synth.config1(0) if name == "config1" else _water16()
+    beta = 10.0
+    target = float(m.n_occ) + 0.37
+    cache = fd.FermiCache(m)
+    mu_o, _, _ = fd.find_mu_fd(m, target, beta, tol=1e-10, cache=cache)
+    plan = sm.Plan(m, 64)
+    o = sm.default_opts("f64", retry=0)
+    H = h_dev(m)
+    w = sm.Workspace(plan, sm.SM_F64, H.device)
+    mu, steps, hist, E, Ne = sm.sm_find_mu_fermi(plan, H, target, beta, o, w.ws, w.P, w.stats, tol=1e-8)
+    torch.cuda.synchronize()
+    slope = cache.dne(mu_o, beta)
+    print(f"mu {mu:.12f} (oracle {mu_o:.12f}), {steps} evaluations, Ne {Ne:.10f}, hist {hist}")
+    assert abs(Ne - target) <= 1e-8 + 1e-10
+    assert abs(mu - mu_o) <= (1e-8 + 1e-10) / slope + 1e-12
+    assert steps <= 12
+    Po = fd.density_matrix_fd(m, mu, beta)
+    assert float(np.max(np.abs(w.P.cpu().numpy() - Po))) < 1e-10
+    mu2, steps2, _, _, Ne2 = sm.sm_find_mu_fermi(plan, H, target, beta, o, w.ws, w.P, w.stats, tol=1e-8,
+                                                 mu_start=mu + 0.01)
+    assert abs(Ne2 - target) <= 1e-8 + 1e-10 and steps2 <= 4 and steps2 < steps
+
+
+def test_fermi_error_paths(dev):
+    import torch
+    m = synth.config1(0)
+    plan = sm.Plan(m, 64)
+    H = h_dev(m)
+    w = sm.Workspace(plan, sm.SM_F64, H.device)
+    o = sm.default_opts("f64", retry=0)
+    with pytest.raises(sm.SmError):   # float32 schedule
+        w32 = sm.Workspace(plan, sm.SM_F32, H.device)
+        sm.sm_density_matrix_fermi(plan, H, 0.0, 1.0, sm.default_opts("f32"), w32.ws, w32.P, w32.stats)
+    for beta in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(sm.SmError):
+            sm.sm_density_matrix_fermi(plan, H, 0.0, beta, o, w.ws, w.P, w.stats)
+    with pytest.raises(sm.SmError):   # the workspace holds no f(T_i) yet
+        sm.assemble_P_fermi(plan, 0, w.ws, w.P)
+    sm.build_submatrices(plan, 0, H, 0.0, o, w.ws, w.stats)
+    with pytest.raises(sm.SmError):   # beta c_G needs more than 60 doublings
+        sm.sm_fermi_dirac(plan, 0, w.ws, 1e30, w.stats)
+    sm.sm_fermi_dirac(plan, 0, w.ws, 1.0, w.stats)
+    sm.submatrix_sign(plan, 0, w.ws, o, w.stats)
+    with pytest.raises(sm.SmError):   # the sign iteration overwrote f(T_i)
+        sm.assemble_P_fermi(plan, 0, w.ws, w.P)
+    torch.cuda.synchronize()

@@ -50,3 +50,30 @@ def test_mfma_summary_units(tmp_path):
     lines = [l for l in text.splitlines() if l.startswith("mfma ")]
     assert len(lines) == 1                       # the copy kernel issues none
     assert lines[0] == "mfma sm::ns_gemm_kernel<4, 1, 2, true> | 2 | 1536 | 0 | 0 | 0"
+
+
+def test_tail_averages_the_last_dispatches(tmp_path):
+    """A benchmark's timed launches come last: --tail averages only the last
+    N dispatches, and a stored tail figure is the one the benchmark reads."""
+    fe = _csv(tmp_path / "f.csv", [(COPY, "FETCH_SIZE", 512), (GEMM, "FETCH_SIZE", 100), (GEMM, "FETCH_SIZE", 300),
+                                   (GEMM, "FETCH_SIZE", 500)])
+    wr = _csv(tmp_path / "w.csv", [(COPY, "WRITE_SIZE", 1024), (GEMM, "WRITE_SIZE", 50), (GEMM, "WRITE_SIZE", 50),
+                                   (GEMM, "WRITE_SIZE", 80)])
+    name = "sm::ns_gemm_kernel<4, 1, 2, true>"
+    text = profsum.traffic_summary(fe, wr, 2 ** 20, "cmd-f", "cmd-w", [(name, 2)])
+    out = tmp_path / "t.txt"
+    out.write_text(text)
+    assert profsum.read_traffic(str(out), name) == 400 * 1024 * 2 + 65 * 1024
+    trace = tmp_path / "trace.csv"
+    with open(trace, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        for t0, d in [(0, 1000), (5000, 3000), (9000, 5000)]:
+            w.writerow([GEMM, t0, t0 + d])
+    stats = tmp_path / "s.csv"
+    with open(stats, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Name", "Calls", "AverageNs", "TotalDurationNs", "Percentage"])
+        w.writerow([GEMM, 3, 3000, 9000, 100.0])
+    text = profsum.stats_summary(str(stats), "cmd", trace=str(trace), tails=profsum.parse_tails([f"{name}=2"]))
+    assert f"tail {name} | 2 | 4.00" in text
