@@ -317,6 +317,7 @@ def water_bench(a):
         net, net_info, mu0 = train_scaling_net_water(sm, synth, dev, a.seed + 1, a.config, a.mu_iters,
                                                      a.mu_accept_rel, a.chunk_gb)
         sm.sm_plan_set_mlp(plan, net)
+        torch.cuda.empty_cache()   # the training system's workspace
     # mu of this system: the bisection rule with the first schedule, warm-started
     # at the training system's mu (untimed; later steps start from it)
     o = mode_opts(sm, heads[0], a)
@@ -348,7 +349,7 @@ def water_bench(a):
             for cls, c in sorted(first.items()):
                 print(f"# {mode}: autotuning on chunk {c} (size class {cls}) ...", file=sys.stderr, flush=True)
                 best, tune_ms = sm.sm_autotune(plan, c, H, mu, o, work.ws, work.stats, repeats=1,
-                                               variants=(1, 3, 4, 5, 6, 7))
+                                               variants=(1, 3, 4, 5, 6, 7, 8))
                 tune[str(cls)] = {"chunk": c, "variant": int(best), "sign_ms": [float(x) for x in tune_ms]}
                 print(f"#   variant {best}: " + " / ".join(f"{x:.0f}" for x in tune_ms if x > 0) + " ms",
                       file=sys.stderr, flush=True)
@@ -357,6 +358,20 @@ def water_bench(a):
 
         def step():
             nonlocal mu_k
+            if ref:
+                # the float64 reference at the cold search's mu, one chunk at a
+                # time from here (a pass of the mixed batch takes minutes; every
+                # chunk reports): the kernels of one accepted sm_find_mu pass
+                for c in range(plan.n_chunks):
+                    t1 = time.perf_counter()
+                    sm.build_submatrices(plan, c, H, mu_k, o, work.ws, work.stats)
+                    sm.submatrix_sign(plan, c, work.ws, o, work.stats)
+                    sm.assemble_P(plan, c, work.ws, work.P)
+                    torch.cuda.synchronize()
+                    print(f"# {mode}: chunk {c + 1}/{plan.n_chunks} ({time.perf_counter() - t1:.1f} s)",
+                          file=sys.stderr, flush=True)
+                E, Ne = sm.energy_trace(plan, H, work.P)
+                return 1, E, Ne
             mu_k, kk, _, E, Ne = sm.sm_find_mu(plan, H, m.n_occ, o, work.ws, work.stats, P=work.P, energy=True,
                                                mu_start=mu_k, accept=acc)
             return kk, E, Ne
@@ -527,6 +542,10 @@ def trajectory_bench(a):
                 sm.sm_plan_set_mlp(plan, net)
             pat = key
             replans += 1
+            # release the previous workspace before the new one is allocated
+            # (two of them would not fit next to each other)
+            work = None
+            torch.cuda.empty_cache()
             work = sm.Workspace(plan, sm.storage_prec(o_learn), dev)
         H = torch.from_numpy(m.vals).to(dev)
         acc = mu_accept(a, m.n_occ)
@@ -584,6 +603,7 @@ def trajectory_bench(a):
                         row["f64"]["max_dP_learned_vs_f64"] = float(np.max(np.abs(P_l - w2.P.cpu().numpy())))
                         row["f64"]["rel_dE_learned_vs_f64"] = abs(E - E2) / abs(E2)
                         del w2
+                        torch.cuda.empty_cache()
         rows.append(row)
         print("# step " + json.dumps(row), file=sys.stderr, flush=True)
     pool.shutdown()

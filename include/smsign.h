@@ -103,8 +103,11 @@ typedef struct {
                             six stages ahead (large submatrices), 6 = 256 x 256 tiles of
                             512 threads with direct global -> LDS operand loads one
                             k-depth-32 stage ahead (bf16 / f16 / split bf16; float32 runs
-                            as 5), 7 = as 6 with k-depth-16 stages three ahead.  bf16 / f16 /
-                            split-bf16 products on a plan padded to 32 always run as 2 */
+                            as 5), 7 = as 6 with k-depth-16 stages three ahead, 8 = as 6
+                            with the workgroups of an XCD starting every round of tiles
+                            together (the round's operand panels stream through its L2
+                            together).  bf16 / f16 / split-bf16 products on a plan padded
+                            to 32 always run as 2 */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,
                             scheduler, updates) into one HIP graph, cached per plan / chunk /
@@ -539,7 +542,7 @@ int sm_autotune(sm_plan* plan, int32_t chunk, const double* H_vals, double mu,
                 const sm_sign_opts* opts, void* ws, sm_sub_stats* stats, int32_t repeats,
                 int32_t variant_mask, int32_t* best_out, double* times_ms, void* stream);
 /* Number of GEMM kernel variants (sm_sign_opts.variant in [0, SM_GEMM_VARIANTS)). */
-#define SM_GEMM_VARIANTS 8
+#define SM_GEMM_VARIANTS 9
 int32_t sm_gemm_variants(void);
 
 /* Tuned variant per precision (int32[5], indexed by sm_prec): `get` receives

@@ -1063,11 +1063,19 @@ __device__ __forceinline__ int g256_off(int op, int R, int p, int c) {
   return (op * G::PL + p) * G::PLANE + R * G::RB + ((c ^ swz256<G::CPR>(R)) << 4);
 }
 
-template <int MODE, int WHICH, int KS, int NBUF>
-__global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restrict__ mats, int64_t shadow_off,
-                                                                 const int32_t* __restrict__ count,
-                                                                 const TileRec* __restrict__ recs,
-                                                                 double* __restrict__ partials) {
+// Round barriers of the synchronized walk (variant 8): per XCD the number of
+// tile rounds its workgroups have finished, and the workgroups that have left
+// the kernel (the last one resets all of it for the next launch).  Only the
+// timing depends on these counters: a wait gives up after kSyncSpins polls,
+// and every access is a relaxed device-scope atomic (an acquire or release
+// would invalidate or write back the L2 whose reuse the barrier is for).
+__device__ unsigned int g256_rounds[kXcds + 1];
+constexpr int kSyncSpins = 4096;
+
+template <int MODE, int WHICH, int KS, int NBUF, bool SYNC>
+__device__ __forceinline__ void gemm256_body(float* __restrict__ mats, int64_t shadow_off,
+                                             const int32_t* __restrict__ count, const TileRec* __restrict__ recs,
+                                             double* __restrict__ partials) {
   using G = G256<MODE, KS>;
   constexpr bool SPLIT = MODE == SM_BF16X3;
   constexpr int AHEAD = NBUF - 1;
@@ -1095,7 +1103,24 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
   const int l_rr = lane / G::CPR;
   const int l_cp = lane % G::CPR;
 
-  for (int t = t_begin; t < t_end; t += t_step) {
+  int round = 0;
+  for (int t = t_begin; t < t_end; t += t_step, ++round) {
+    if constexpr (SYNC) {
+      // start round r once every workgroup of this XCD has finished round
+      // r - 1: the XCD's tiles of a round (consecutive in the list, mostly of
+      // one submatrix, sharing operand panels) then stream through k together
+      // and reuse each other's panel slices from the L2
+      if (round > 0) {
+        if (tid == 0) {
+          const unsigned target = (unsigned)round * (unsigned)t_step;
+          for (int k = 0; k < kSyncSpins; ++k) {
+            if (__hip_atomic_load(&g256_rounds[x8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            __builtin_amdgcn_s_sleep(4);
+          }
+        }
+        __syncthreads();
+      }
+    }
     const TileRec rec = recs[rec_index(t, t_mirror)];
     const int npad = rec.npad;
     const int64_t nn = (int64_t)npad * npad;
@@ -1257,7 +1282,42 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
       }
     }
     __syncthreads();
+    if constexpr (SYNC)
+      if (tid == 0) __hip_atomic_fetch_add(&g256_rounds[x8], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  if constexpr (SYNC) {
+    if (tid == 0) {
+      // the rounds this workgroup has no tile for count as finished
+      const int rounds_x = (t_end - t_lo + t_step - 1) / t_step;
+      if (rounds_x > round)
+        __hip_atomic_fetch_add(&g256_rounds[x8], (unsigned)(rounds_x - round), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned out = __hip_atomic_fetch_add(&g256_rounds[kXcds], 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT) + 1;
+      if (out == gridDim.x)
+        for (int x = 0; x <= kXcds; ++x)
+          __hip_atomic_exchange(&g256_rounds[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <int MODE, int WHICH, int KS, int NBUF>
+__global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restrict__ mats, int64_t shadow_off,
+                                                                 const int32_t* __restrict__ count,
+                                                                 const TileRec* __restrict__ recs,
+                                                                 double* __restrict__ partials) {
+  gemm256_body<MODE, WHICH, KS, NBUF, false>(mats, shadow_off, count, recs, partials);
+}
+
+// Variant 8: variant 6 with the XCD's workgroups starting every tile round
+// together (the round barriers above).
+template <int MODE, int WHICH>
+__global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_sync_kernel(float* __restrict__ mats,
+                                                                      int64_t shadow_off,
+                                                                      const int32_t* __restrict__ count,
+                                                                      const TileRec* __restrict__ recs,
+                                                                      double* __restrict__ partials) {
+  gemm256_body<MODE, WHICH, 32, 2, true>(mats, shadow_off, count, recs, partials);
 }
 
 // 64-tile kernel variants: 0 = {full stage, linear walk}, 1 = {full stage,
@@ -1314,10 +1374,15 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_
                           partials);
       [[fallthrough]];
     case 7:
-      if constexpr (Pre<MODE>::value)
+    case 8:
+      if constexpr (Pre<MODE>::value) {
         if (variant == 7)
           return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 16, 4>, (float*)mats, so, count, recs,
                             partials);
+        if (variant == 8)
+          return L.go_block(kBlock256, ns_gemm256_sync_kernel<MODE, WHICH>, (float*)mats, so, count, recs,
+                            partials);
+      }
       [[fallthrough]];
     case 3:
     case 4:
@@ -1373,8 +1438,11 @@ static void* ptr_which(int variant) {
       if constexpr (Pre<MODE>::value) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, 32, 2>);
       [[fallthrough]];
     case 7:
-      if constexpr (Pre<MODE>::value)
+    case 8:
+      if constexpr (Pre<MODE>::value) {
         if (variant == 7) return reinterpret_cast<void*>(&ns_gemm256_kernel<MODE, WHICH, 16, 4>);
+        if (variant == 8) return reinterpret_cast<void*>(&ns_gemm256_sync_kernel<MODE, WHICH>);
+      }
       [[fallthrough]];
     case 5:
       if constexpr (MODE != SM_F64) return reinterpret_cast<void*>(&ns_gemm128_kernel<MODE, WHICH, true, kDeepRing>);

@@ -147,7 +147,12 @@ void assign_order(sm_plan* p, const std::vector<int32_t>& order) {
   p->max_mats = p->max_tiles = p->max_vecs = p->max_subs = 0;
   int64_t mats = 0, tiles = 0, vecs = 0, subs = 0;
   int32_t chunk_max = 0;
-  auto close_chunk = [&]() { p->chunk_class.push_back((chunk_max + kClassRows - 1) / kClassRows); };
+  std::vector<int32_t> class_max(kMaxClasses, 0);   // largest n_pad of every class
+  auto close_chunk = [&]() {
+    const int32_t c = (chunk_max + kClassRows - 1) / kClassRows;
+    p->chunk_class.push_back(c);
+    class_max[c] = std::max(class_max[c], chunk_max);
+  };
   for (int32_t g = 0; g < n; ++g) {
     const int32_t i = order[g];
     const int64_t np = p->npad[i];
@@ -185,7 +190,7 @@ void assign_order(sm_plan* p, const std::vector<int32_t>& order) {
   };
   defaults(p->max_npad, p->tuned);
   p->class_tuned.assign(kMaxClasses, {-1, -1, -1, -1, -1});
-  for (int32_t c : p->chunk_class) defaults(c * kClassRows, p->class_tuned[c].data());
+  for (int32_t c : p->chunk_class) defaults(class_max[c], p->class_tuned[c].data());
 }
 
 // Morton (Z-order) key of a point inside [lo, lo + span)^3, 21 bits per axis.

@@ -160,6 +160,8 @@ def gemm_kernel_symbol(mode: int, which: int, variant: int, pad_to: int) -> str:
     runs for (precision, square/update, kernel variant) on a plan with the
     given padding; mirrors the variant fallback of the launcher."""
     v = effective_variant(mode, variant, pad_to)
+    if v == 8:   # 256-wide tiles, synchronized rounds
+        return f"sm::ns_gemm256_sync_kernel<{mode}, {which}>"
     if v >= 6:   # 256-wide tiles, 512 threads: <precision, kind, stage depth, buffers>
         return f"sm::ns_gemm256_kernel<{mode}, {which}, {32 if v == 6 else 16}, {2 if v == 6 else 4}>"
     if v >= 3:   # 128-wide tiles: <precision, kind, XCD-aware walk, prefetch depth>

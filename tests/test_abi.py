@@ -187,10 +187,10 @@ def test_default_gemm_variants():
     """Before tuning, a plan holds size-based GEMM variants: 64-wide XCD-aware
     tiles for float64 and small submatrices, 256-wide (16-bit) and 128-wide
     ring (float32) tiles for large ones padded to 64, half-depth stages for
-    16-bit products padded to 32; the library reports 8 variants."""
+    16-bit products padded to 32; the library reports 9 variants."""
     import synth
     from paper_2205_14741_amd import smsign as sm
-    assert sm.lib().sm_gemm_variants() == 8
+    assert sm.lib().sm_gemm_variants() == 9
     small = synth.config1()
     assert list(sm.sm_plan_tuning(sm.Plan(small, 64))) == [1, 1, 1, 1, 1]
     assert list(sm.sm_plan_tuning(sm.Plan(small, 32))) == [1, 1, 2, 2, 2]

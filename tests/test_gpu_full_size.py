@@ -78,7 +78,7 @@ def test_water1000_bench_configuration_sampled(dev):
     sm.sm_plan_set_mlp(plan, net)
     o = bench.mode_opts(sm, "bf16x3+L", a)
     work = sm.Workspace(plan, sm.storage_prec(o), dev)
-    sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5, 6, 7))
+    sm.sm_autotune(plan, 0, H, mu, o, work.ws, work.stats, repeats=1, variants=(1, 3, 4, 5, 6, 7, 8))
     E, Ne = sm.sm_density_matrix(plan, H, mu, o, work.ws, work.P, work.stats)
     torch.cuda.synchronize()
     P = work.P.cpu().numpy()

@@ -393,7 +393,7 @@ def test_trajectory_against_float64(prec, dev):
 _X0_CACHE = {}
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("prec,dp_max", [("f32", 1e-5), ("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)])
 def test_gemm_variants_parity(variant, prec, dp_max, dev):
     """Every GEMM kernel variant (tile walk, LDS stage depth, 128-wide tiles with
@@ -407,7 +407,7 @@ def test_gemm_variants_parity(variant, prec, dp_max, dev):
     assert np.all(st["status"] >= 1)
 
 
-@pytest.mark.parametrize("variant", [6, 7])
+@pytest.mark.parametrize("variant", [6, 7, 8])
 @pytest.mark.parametrize("prec,dp_max", [("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)])
 def test_gemm256_multi_tile(prec, dp_max, variant, dev):
     """The 256-wide tiles on submatrices of three to four tile rows (n 590 to
