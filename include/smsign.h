@@ -91,7 +91,7 @@ typedef struct {
   int32_t probes;        /* float64 probe vectors for the final residual check (0..8) */
   int32_t variant;       /* Newton-Schulz GEMM kernel variant: -1 = the plan's tuned choice
                             (see sm_autotune; before tuning: 1 for float64 and for submatrices
-                            under 768 rows, 5 (float32) / 6 (16-bit) above, 2 for 16-bit
+                            under 768 rows, 5 (float32) / 8 (16-bit) above, 2 for 16-bit
                             products on plans padded to 32); 0 = tiles dealt to workgroups
                             in list order, 1 = each XCD walks a contiguous range of the tile
                             list (a submatrix stays in one L2), 2 = as 1 with LDS stages

@@ -131,9 +131,9 @@ namespace {
 // every chunk's size class (256-row tiles of its largest submatrix) and the
 // default GEMM variants of every class until sm_autotune measures better
 // ones: the XCD-aware 64-wide tiles for float64 and small submatrices, the
-// 256-wide tiles for the 16-bit precisions on large ones (their float32
-// refinement on the 128-wide ring kernel), the half-depth stages on plans
-// padded to 32.
+// 256-wide tiles with synchronized rounds for the 16-bit precisions on large
+// ones (their float32 refinement on the 128-wide ring kernel), the half-depth
+// stages on plans padded to 32.
 void assign_order(sm_plan* p, const std::vector<int32_t>& order) {
   const int32_t n = p->n_atoms;
   p->order_g.assign(order.begin(), order.end());
@@ -186,7 +186,7 @@ void assign_order(sm_plan* p, const std::vector<int32_t>& order) {
     const bool big = p->pad_to >= 64 && largest >= 768;
     t[SM_F64] = 1;
     t[SM_F32] = big ? 5 : 1;
-    for (int m : {SM_BF16, SM_F16, SM_BF16X3}) t[m] = p->pad_to < 64 ? 2 : big ? 6 : 1;
+    for (int m : {SM_BF16, SM_F16, SM_BF16X3}) t[m] = p->pad_to < 64 ? 2 : big ? 8 : 1;
   };
   defaults(p->max_npad, p->tuned);
   p->class_tuned.assign(kMaxClasses, {-1, -1, -1, -1, -1});

@@ -195,4 +195,4 @@ def test_default_gemm_variants():
     assert list(sm.sm_plan_tuning(sm.Plan(small, 64))) == [1, 1, 1, 1, 1]
     assert list(sm.sm_plan_tuning(sm.Plan(small, 32))) == [1, 1, 2, 2, 2]
     big = synth.water_system(64, 1.95, 2)          # n_pad up to 896
-    assert list(sm.sm_plan_tuning(sm.Plan(big, 64))) == [1, 5, 6, 6, 6]
+    assert list(sm.sm_plan_tuning(sm.Plan(big, 64))) == [1, 5, 8, 8, 8]
