@@ -551,7 +551,8 @@ def trajectory_bench(a):
         acc = mu_accept(a, m.n_occ)
         row = {"step": t}
         if t == 0:
-            best, _ = sm.sm_autotune(plan, 0, H, -2.95, o_gersh, work.ws, work.stats, repeats=1, variants=(5, 6, 7))
+            best, _ = sm.sm_autotune(plan, 0, H, -2.95, o_gersh, work.ws, work.stats, repeats=1,
+                                     variants=(5, 6, 7, 8))
             row["variant"] = int(best)
         explicit = t < T0 or (a.relearn_every > 0 and t > T0 and (t - T0) % a.relearn_every == 0)
         learned = t >= T0
