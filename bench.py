@@ -688,8 +688,9 @@ def fermi_bench(a):
     chunk = info["chunk"]
     prods = np.array([14 + 10 * doublings[int(c)] for c in chunk], dtype=np.float64)
     useful = float(np.sum(prods * n * (n + 1) * n))
-    T = np.ceil(npad / 64)
-    issued = float(np.sum(prods * T * (T + 1) / 2 * 2 * 64 * 64 * npad))
+    edge = 128 if npad.max() >= 256 else 64   # the library's tile edge for these products
+    T = np.ceil(npad / edge)
+    issued = float(np.sum(prods * T * (T + 1) / 2 * 2 * edge * edge * npad))
     P = work.P.cpu().numpy()
     rng = np.random.default_rng(a.seed)
     atoms = sorted(rng.choice(m.n_atoms, size=min(a.samples, m.n_atoms), replace=False).tolist())
@@ -712,7 +713,8 @@ def fermi_bench(a):
         "ms_per_step": dt / a.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": wl, "beta": beta, "doublings": doublings, "N": m.n_orb, "n_sub": m.n_atoms},
+        "config": {"workload": wl, "beta": beta, "doublings": doublings, "N": m.n_orb, "n_sub": m.n_atoms,
+                   "tile_edge": edge},
         "evaluations_per_step": evals / a.steps,
         "useful_tflops": useful * evals / dt / 1e12,
         "issued_tflops": issued * evals / dt / 1e12,

@@ -124,16 +124,16 @@ int sm_fermi_dirac(sm_plan* p, int32_t chunk, void* ws, double beta, const sm_su
   // Horner steps u <- c_k I + s^2 X_0 (X_0 u) (buffer 2, X_0 u in buffer 1),
   // then F_0 = 1/2 I - 1/2 s X_0 u = f(beta T / 2^m) into buffer 1
   SM_HIP(launch_fd_lincomb(p->dev, g0, nsub, mp, wm, 0, kTanh[7], -1, 0.0, 0.0, 1, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, 0, nullptr, wm, 1, wm, 2, s2, 1.0, kTanh[6], nullptr, 0, 0.0, 0,
-                         nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, 0, nullptr, wm, 1, wm, 2, s2, 1.0, kTanh[6], nullptr,
+                         0, 0.0, 0, nullptr, s));
   for (int k = 5; k >= 0; --k) {
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, 0, nullptr, wm, 2, wm, 1, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 0,
-                           nullptr, s));
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, 0, nullptr, wm, 1, wm, 2, s2, 1.0, kTanh[k], nullptr, 0, 0.0, 0,
-                           nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, 0, nullptr, wm, 2, wm, 1, nullptr, 1.0, 0.0,
+                           nullptr, 0, 0.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, 0, nullptr, wm, 1, wm, 2, s2, 1.0, kTanh[k],
+                           nullptr, 0, 0.0, 0, nullptr, s));
   }
-  SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, 0, nullptr, wm, 2, wm, 1, sv, -0.5, 0.5, nullptr, 0, 0.0, 0,
-                         nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, 0, nullptr, wm, 2, wm, 1, sv, -0.5, 0.5, nullptr, 0,
+                         0.0, 0, nullptr, s));
   // m doublings, F in buffer f = 1 throughout, q and t the other two:
   //   Q = F F (q); R = 8/3 (F - Q) - 1/3 I (in place of F); acc = 4/3 (Q R + Q) (t);
   //   then four times: S <- S S (the free buffer), acc <- acc S + acc,
@@ -141,20 +141,20 @@ int sm_fermi_dirac(sm_plan* p, int32_t chunk, void* ws, double beta, const sm_su
   const int f = 1;
   for (int d = 0; d < m; ++d) {
     int b[3] = {f, 2, 0};   // b[0] F / R, b[1] Q, b[2] acc
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, b[0], nullptr, wm, b[0], wm, b[1], nullptr, 1.0, 0.0, nullptr, 0,
-                           0.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, b[0], nullptr, wm, b[0], wm, b[1], nullptr, 1.0,
+                           0.0, nullptr, 0, 0.0, 0, nullptr, s));
     SM_HIP(launch_fd_lincomb(p->dev, g0, nsub, mp, wm, b[0], 8.0 / 3.0, b[1], -8.0 / 3.0, -1.0 / 3.0, b[0], s));
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, b[1], nullptr, wm, b[0], wm, b[2], nullptr, 4.0 / 3.0, 0.0, wm,
-                           b[1], 4.0 / 3.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, b[1], nullptr, wm, b[0], wm, b[2], nullptr,
+                           4.0 / 3.0, 0.0, wm, b[1], 4.0 / 3.0, 0, nullptr, s));
     // buffers now: R at b[0], acc at b[2], b[1] free; S starts as R
     int S = b[0], acc = b[2], freeb = b[1];
     for (int j = 0; j < 4; ++j) {
-      SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, S, nullptr, wm, S, wm, freeb, nullptr, 1.0, 0.0, nullptr, 0,
-                             0.0, 0, nullptr, s));
+      SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, S, nullptr, wm, S, wm, freeb, nullptr, 1.0, 0.0,
+                             nullptr, 0, 0.0, 0, nullptr, s));
       const int S2 = freeb;
       freeb = S;   // the old power is dead once squared
-      SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, acc, nullptr, wm, S2, wm, freeb, nullptr, 1.0, 0.0, wm, acc,
-                             1.0, 0, nullptr, s));
+      SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, acc, nullptr, wm, S2, wm, freeb, nullptr, 1.0,
+                             0.0, wm, acc, 1.0, 0, nullptr, s));
       const int acc2 = freeb;
       freeb = acc;
       acc = acc2;

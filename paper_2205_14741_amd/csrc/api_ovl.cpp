@@ -33,6 +33,9 @@ double* f64_mats(const sm_plan* p, const void* ws) {
 int ensure_ovl(sm_plan* p) {
   int rc;
   if ((rc = ensure_device(p))) return rc;
+  // 128-wide tiles once a submatrix spans two of them (the 64-wide kernel
+  // for smaller ones: less padding work)
+  if (p->ovl_edge == 0) p->ovl_edge = p->max_npad >= 256 ? 128 : 64;
   if (!p->d_ovl) {
     void* d = nullptr;
     SM_HIP(hipMalloc(&d, std::max<int64_t>(p->max_subs, 1) * 4 * sizeof(double)));
@@ -58,10 +61,11 @@ int ovl_jobs(sm_plan* p, int chunk, int kind, const OvlJob** jobs, int* n) {
   std::vector<OvlJob> v;
   for (int l = 0; l < nsub; ++l) {
     const int g = g0 + l;
-    const int T = (p->npad_g[g] + 63) / 64;
+    const int e = p->ovl_edge;
+    const int T = (p->npad_g[g] + e - 1) / e;
     const int i = p->order_g[g];
     for (int bj = 0; bj < T; ++bj) {
-      if (kind == 2 && (bj < p->loc[i] / 64 || bj > (p->loc[i] + p->bs[i] - 1) / 64)) continue;
+      if (kind == 2 && (bj < p->loc[i] / e || bj > (p->loc[i] + p->bs[i] - 1) / e)) continue;
       for (int bi = (kind == 0 ? bj : 0); bi < T; ++bi) v.push_back(OvlJob{l, (int16_t)bi, (int16_t)bj});
     }
   }
@@ -125,15 +129,18 @@ int sm_overlap_inv_sqrt(sm_plan* p, int32_t chunk, const double* S, double tol, 
   for (;; ++it) {
     // W = 1/2 (3I - Z Y) into aux buffer 2, with ||Z Y - I||_F^2
     SM_HIP(launch_ovl_zero(res, nsub, s));
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, aux, z, nullptr, wm, y, aux, 2, nullptr, -0.5, 1.5, nullptr, 0, 0.0, 0, res, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, aux, z, nullptr, wm, y, aux, 2, nullptr, -0.5, 1.5,
+                           nullptr, 0, 0.0, 0, res, s));
     SM_HIP(launch_ovl_max(res, nsub, dres, s));
     SM_HIP(hipStreamSynchronize(s));
     r = std::sqrt(*hres);
     if (!std::isfinite(r)) return set_error(SM_ERR_NONFINITE, "sm_overlap_inv_sqrt: non-finite residual at step %d", it);
     if (r < tol || it >= max_iter) break;
     // Y <- Y W (ws buffers 0 / 1), Z <- W Z (aux buffers 0 / 1)
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, wm, y, nullptr, aux, 2, wm, 1 - y, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 0, nullptr, s));
-    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, aux, 2, nullptr, aux, z, aux, 1 - z, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, wm, y, nullptr, aux, 2, wm, 1 - y, nullptr, 1.0, 0.0,
+                           nullptr, 0, 0.0, 0, nullptr, s));
+    SM_HIP(launch_ovl_prod(p->dev, g0, jobs, nj, p->ovl_edge, aux, 2, nullptr, aux, z, aux, 1 - z, nullptr, 1.0, 0.0,
+                           nullptr, 0, 0.0, 0, nullptr, s));
     y = 1 - y;
     z = 1 - z;
   }
@@ -174,8 +181,10 @@ int build_submatrices_overlap(sm_plan* p, int32_t chunk, const double* H, double
   // T(H) (zero pad) -> ws buffer 1; Q = T(H) Z -> buffer 2; K - mu I = Q^T Z -> buffer 0
   SM_HIP(launch_ovl_fill(p->dev, g0, nsub, mp, wm, 1, 0.0, 0.0, s));
   SM_HIP(launch_ovl_gather(p->dev, g0, nsub, p->max_m, H, wm, 1, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, full, nf, wm, 1, nullptr, aux, 0, wm, 2, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 1, nullptr, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, sym, ns, wm, 2, nullptr, aux, 0, wm, 0, nullptr, 1.0, -mu, nullptr, 0, 0.0, 0, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, full, nf, p->ovl_edge, wm, 1, nullptr, aux, 0, wm, 2, nullptr, 1.0, 0.0, nullptr,
+                         0, 0.0, 1, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, sym, ns, p->ovl_edge, wm, 2, nullptr, aux, 0, wm, 0, nullptr, 1.0, -mu, nullptr,
+                         0, 0.0, 0, nullptr, s));
   // the identity pad of the sign iteration, its Gershgorin bound (stats.gersh),
   // then the scale and X_0 = T / c exactly as build_submatrices leaves them
   double* cg = scratch;
@@ -209,9 +218,11 @@ int assemble_P_overlap(sm_plan* p, int32_t chunk, void* ws, const void* ws_aux_i
   // U = X Z[:, cols] (aux buffer 2), D = Z[:, cols] - U (aux buffer 1),
   // R = 1/2 Z D (aux buffer 2): block column i of P_i
   SM_HIP(launch_ovl_xbuf(st, nsub, p->d_ovl_xbuf, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, wm, 0, p->d_ovl_xbuf, aux, 0, aux, 2, nullptr, 1.0, 0.0, nullptr, 0, 0.0, 1, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, p->ovl_edge, wm, 0, p->d_ovl_xbuf, aux, 0, aux, 2, nullptr, 1.0, 0.0,
+                         nullptr, 0, 0.0, 1, nullptr, s));
   SM_HIP(launch_ovl_slab_diff(p->dev, g0, nsub, aux, 0, aux, 2, aux, 1, nullptr, s));
-  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, aux, 0, nullptr, aux, 1, aux, 2, nullptr, 0.5, 0.0, nullptr, 0, 0.0, 1, nullptr, s));
+  SM_HIP(launch_ovl_prod(p->dev, g0, slab, nj, p->ovl_edge, aux, 0, nullptr, aux, 1, aux, 2, nullptr, 0.5, 0.0,
+                         nullptr, 0, 0.0, 1, nullptr, s));
   SM_HIP(launch_ovl_scatter(p->dev, g0, nsub, aux, 2, P, s));
   return SM_OK;
 }

@@ -18,7 +18,7 @@
 #include <algorithm>
 
 #include "device_common.h"
-#include "smsign_internal.h"
+#include "ovl_internal.h"
 
 namespace sm {
 

@@ -15,7 +15,7 @@
 #include <algorithm>
 
 #include "device_common.h"
-#include "smsign_internal.h"
+#include "ovl_internal.h"
 
 namespace sm {
 
@@ -226,6 +226,114 @@ __global__ __launch_bounds__(256) void ovl_prod_kernel(DevPlan p, int g0, const 
   }
 }
 
+// The same product on 128 x 128 output tiles (the job's bi, bj count
+// 128-tiles): 4 waves in 2 x 2, 64 x 64 outputs each (4 x 4 blocks of
+// 16 x 16), k stages of 16 double-buffered through LDS, the next stage's
+// operands loaded into registers while the current one is multiplied; one
+// barrier per stage.  Four times the work per operand byte of the 64-wide
+// tiles.
+__global__ __launch_bounds__(256, 2) void ovl_prod128_kernel(DevPlan p, int g0, const OvlJob* __restrict__ jobs,
+                                                           const double* Am, int abuf,
+                                                           const int32_t* __restrict__ abuf_l, const double* Bm,
+                                                           int bbuf, double* Cm, int cbuf,
+                                                           const double* __restrict__ alpha_l, double alpha,
+                                                           double beta, const double* Em, int ebuf, double gamma,
+                                                           int kind, double* __restrict__ res) {
+  constexpr int KS = 16, LD = KS + 1, TE = 128;
+  __shared__ double la[2][TE * LD], lb[2][TE * LD];
+  __shared__ double red[8];
+  const OvlJob job = jobs[blockIdx.x];
+  const int l = job.l;
+  const int g = g0 + l;
+  const int npad = p.npad_g[g];
+  const int n = p.height[p.order_g[g]];
+  const int64_t nn = (int64_t)npad * npad;
+  const double* A = Am + p.mat_off_g[g] + (int64_t)(abuf_l ? abuf_l[l] : abuf) * nn;
+  const double* B = Bm + p.mat_off_g[g] + (int64_t)bbuf * nn;
+  double* C = Cm + p.mat_off_g[g] + (int64_t)cbuf * nn;
+  const double* E = Em ? Em + p.mat_off_g[g] + (int64_t)ebuf * nn : nullptr;
+  const int r0 = job.bi * TE, c0 = job.bj * TE;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  // loads: thread t fills row t / 2 of both operand stages, k half (t % 2) * 8
+  const int lrow = tid >> 1, lk = (tid & 1) * 8;
+  const bool va = r0 + lrow < npad, vb = c0 + lrow < npad;
+  const double* pa = A + (int64_t)(va ? r0 + lrow : 0) * npad + lk;
+  const double* pb = B + (int64_t)(vb ? c0 + lrow : 0) * npad + lk;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 ra[4], rb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ra[e] = va ? *reinterpret_cast<const d2*>(pa + k0 + 2 * e) : d2{0.0, 0.0};
+      rb[e] = vb ? *reinterpret_cast<const d2*>(pb + k0 + 2 * e) : d2{0.0, 0.0};
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      la[buf][lrow * LD + lk + 2 * e] = ra[e].x;
+      la[buf][lrow * LD + lk + 2 * e + 1] = ra[e].y;
+      lb[buf][lrow * LD + lk + 2 * e] = rb[e].x;
+      lb[buf][lrow * LD + lk + 2 * e + 1] = rb[e].y;
+    }
+  };
+  const int rl = lane & 15, kq = lane >> 4;
+  d4o acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = d4o{0, 0, 0, 0};
+  const int nst = npad / KS;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int s = 0; s < nst; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nst) fetch((s + 1) * KS);
+#pragma unroll
+    for (int kk = 0; kk < KS / 4; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        av[x] = la[buf][(wm * 64 + x * 16 + rl) * LD + kk * 4 + kq];
+        bv[x] = lb[buf][(wn * 64 + x * 16 + rl) * LD + kk * 4 + kq];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+    // the other buffer was last read in stage s - 1, before the barrier that
+    // ended it
+    if (s + 1 < nst) stash(buf ^ 1);
+    __syncthreads();
+  }
+  const double al = alpha_l ? alpha_l[l] : 1.0;
+  double part = 0.0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + wm * 64 + x * 16 + kq + 4 * v;
+        const int c = c0 + wn * 64 + y * 16 + rl;
+        if (r >= npad || c >= npad) continue;
+        if (kind == 0 && r < c) continue;
+        const double m = al * acc[x][y][v];
+        const double dg = r == c ? 1.0 : 0.0;
+        if (res && r < n && c < n) part += (kind == 0 && r != c ? 2.0 : 1.0) * (m - dg) * (m - dg);
+        const double out = alpha * m + beta * dg + (E ? gamma * E[(int64_t)c * npad + r] : 0.0);
+        C[(int64_t)c * npad + r] = out;
+        if (kind == 0 && r != c) C[(int64_t)r * npad + c] = out;
+      }
+  if (res) {
+    part = block_reduce<0>(part, red);
+    if (tid == 0) atomicAdd(res + l, part);
+  }
+}
+
 // D[:, loc .. loc + b) = f(l) Z[:, ...] - U[:, ...] for the rows < n (f: 1 / sqrt(c)).
 __global__ __launch_bounds__(256) void ovl_slab_diff_kernel(DevPlan p, int g0, const double* Zm, int zbuf,
                                                             const double* Um, int ubuf, double* Dm, int dbuf,
@@ -320,13 +428,17 @@ hipError_t launch_ovl_copy(const DevPlan& p, int g0, int nsub, int max_npad, dou
   return hipGetLastError();
 }
 
-hipError_t launch_ovl_prod(const DevPlan& p, int g0, const OvlJob* jobs, int njobs, const double* A, int abuf,
-                           const int32_t* abuf_l, const double* B, int bbuf, double* C, int cbuf,
+hipError_t launch_ovl_prod(const DevPlan& p, int g0, const OvlJob* jobs, int njobs, int edge, const double* A,
+                           int abuf, const int32_t* abuf_l, const double* B, int bbuf, double* C, int cbuf,
                            const double* alpha_l, double alpha, double beta, const double* E, int ebuf,
                            double gamma, int kind, double* res, hipStream_t s) {
   if (njobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(ovl_prod_kernel, dim3(njobs), dim3(256), 0, s, p, g0, jobs, A, abuf, abuf_l, B, bbuf, C, cbuf,
-                     alpha_l, alpha, beta, E, ebuf, gamma, kind, res);
+  if (edge == 128)
+    hipLaunchKernelGGL(ovl_prod128_kernel, dim3(njobs), dim3(256), 0, s, p, g0, jobs, A, abuf, abuf_l, B, bbuf, C,
+                       cbuf, alpha_l, alpha, beta, E, ebuf, gamma, kind, res);
+  else
+    hipLaunchKernelGGL(ovl_prod_kernel, dim3(njobs), dim3(256), 0, s, p, g0, jobs, A, abuf, abuf_l, B, bbuf, C,
+                       cbuf, alpha_l, alpha, beta, E, ebuf, gamma, kind, res);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "mlp.h"
+#include "ovl_internal.h"
 #include "smsign_internal.h"
 
 constexpr int kHostWords = 64;
@@ -113,6 +114,7 @@ struct sm_plan {
     sm::OvlJob* d;
   };
   std::vector<OvlJobs> ovl_jobs;
+  int ovl_edge = 0;                 // tile edge of these products (64 or 128; 0: not chosen yet)
   double* d_ovl = nullptr;          // [4 * max_subs]: c_i, residual sums, 1 / sqrt(c_i), spare
   int32_t* d_ovl_xbuf = nullptr;    // [max_subs]
   int ovl_chunk = -1;               // chunk whose Z_i the auxiliary workspace holds (-1: none)

@@ -200,41 +200,6 @@ hipError_t launch_materialize(const DevPlan& p, int g0, int nsub, float* mats, c
                               int shadow_kind, int64_t shadow_off, hipStream_t s);
 int ns_gemm_blocks_per_cu(int mode, int which, int variant);
 
-// Non-orthogonal basis (k_ovl.hip): one 64 x 64 output tile of a product
-// (local submatrix index, tile row, tile column).
-struct OvlJob {
-  int32_t l;
-  int16_t bi, bj;
-};
-hipError_t launch_ovl_fill(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int b, double dv, double dp,
-                           hipStream_t s);
-hipError_t launch_ovl_gather(const DevPlan& p, int g0, int nsub, int max_m, const double* V, double* mats, int b,
-                             hipStream_t s);
-hipError_t launch_ovl_gersh(const DevPlan& p, int g0, int nsub, double* mats, int b, double* out, int pad_one,
-                            sm_sub_stats* stats, hipStream_t s);
-hipError_t launch_ovl_scale(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int b, const double* v,
-                            int mode, hipStream_t s);
-hipError_t launch_ovl_copy(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int src, int dst,
-                           hipStream_t s);
-hipError_t launch_ovl_prod(const DevPlan& p, int g0, const OvlJob* jobs, int njobs, const double* A, int abuf,
-                           const int32_t* abuf_l, const double* B, int bbuf, double* C, int cbuf,
-                           const double* alpha_l, double alpha, double beta, const double* E, int ebuf,
-                           double gamma, int kind, double* res, hipStream_t s);
-// Finite-temperature occupation (k_fermi.hip).
-hipError_t launch_fd_bound(const DevPlan& p, int g0, int nsub, const sm_sub_stats* stats, double beta, double* out,
-                           hipStream_t s);
-hipError_t launch_fd_coef(const DevPlan& p, int g0, int nsub, const sm_sub_stats* stats, double beta, double inv2m1,
-                          double* sv, double* s2, hipStream_t s);
-hipError_t launch_fd_lincomb(const DevPlan& p, int g0, int nsub, int max_npad, double* mats, int xb, double a, int yb,
-                             double b, double d, int cb, hipStream_t s);
-hipError_t launch_fd_count(const DevPlan& p, int g0, int nsub, const double* mats, int fb, double beta, double* ne,
-                           double* dne, hipStream_t s);
-hipError_t launch_ovl_slab_diff(const DevPlan& p, int g0, int nsub, const double* Z, int zbuf, const double* U,
-                                int ubuf, double* D, int dbuf, const double* f_l, hipStream_t s);
-hipError_t launch_ovl_scatter(const DevPlan& p, int g0, int nsub, const double* R, int rbuf, double* P, hipStream_t s);
-hipError_t launch_ovl_xbuf(const SubState* st, int nsub, int32_t* xbuf, hipStream_t s);
-hipError_t launch_ovl_zero(double* v, int n, hipStream_t s);
-hipError_t launch_ovl_max(const double* v, int n, double* out, hipStream_t s);
 hipError_t launch_finish(const DevPlan& p, int g0, int nsub, const void* mats, int storage_f64,
                          const SubState* st, int probes, double* vecs, sm_sub_stats* stats, int max_npad,
                          hipStream_t s);
