@@ -101,13 +101,13 @@ int effective_variant(const sm_plan* p, int mode, int variant) {
 }
 
 int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_t shadow, const int32_t* cnt,
-                const TileRec* recs, double* partials, int max_tiles, hipStream_t s) {
+                const TileRec* recs, double* partials, unsigned* sync, int max_tiles, hipStream_t s) {
   const int v = effective_variant(p, mode, variant);
   // persistent grid: all resident workgroups, a multiple of the 8 XCDs
   int grid = std::min(max_tiles, p->num_cu * ns_gemm_blocks_per_cu(mode, which, v));
   grid = std::max(8, grid / 8 * 8);
   if (!p->profiling) {
-    SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, cnt, recs, partials, grid, s));
+    SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, cnt, recs, partials, sync, grid, s));
     return SM_OK;
   }
   const size_t k = p->prof_cls.size();
@@ -116,7 +116,7 @@ int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_
     SM_HIP(hipEventCreate(&e));
     p->prof_ev.push_back(e);
   }
-  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, cnt, recs, partials, grid, s,
+  SM_HIP(launch_ns_gemm(mode, which, v, mats, shadow, cnt, recs, partials, sync, grid, s,
                         p->prof_ev[2 * k], p->prof_ev[2 * k + 1]));
   p->prof_cls.push_back(2 * mode + which);
   return SM_OK;
@@ -229,6 +229,9 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   p->active_chunk = chunk;   // its size class's GEMM variants
   WsPtrs w = ws_ptrs(p, ws, storage);
   hipStream_t s = as_stream(stream);   // the lambdas below launch on `s`
+  // the round counters of the synchronized GEMM walk start at zero (a fill
+  // kernel, outside any captured graph; each launch leaves them at zero)
+  SM_HIP(launch_fill_i32(w.flag, 0, 16, s));
   const int64_t stride = list_stride(p);
   int32_t* L0 = w.lists;
   auto list_count = [&](int L) { return L0 + L * stride; };
@@ -257,11 +260,12 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   // (refinement); a list the host knows to be empty is not launched
   auto gemms = [&](int Lm, int Lr, int which, bool run_main, bool run_ref) -> int {
     int r;
+    unsigned* sync = reinterpret_cast<unsigned*>(w.flag);
     if (run_main && (r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, list_count(Lm),
-                                     recs_of(Lm), w.partials, max_tiles, s)))
+                                     recs_of(Lm), w.partials, sync, max_tiles, s)))
       return r;
     if (has_ref && run_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, list_count(Lr),
-                                               recs_of(Lr), w.partials, max_tiles, s)))
+                                               recs_of(Lr), w.partials, sync, max_tiles, s)))
       return r;
     return SM_OK;
   };

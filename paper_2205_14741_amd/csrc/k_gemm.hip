@@ -1063,19 +1063,20 @@ __device__ __forceinline__ int g256_off(int op, int R, int p, int c) {
   return (op * G::PL + p) * G::PLANE + R * G::RB + ((c ^ swz256<G::CPR>(R)) << 4);
 }
 
-// Round barriers of the synchronized walk (variant 8): per XCD the number of
-// tile rounds its workgroups have finished, and the workgroups that have left
-// the kernel (the last one resets all of it for the next launch).  Only the
-// timing depends on these counters: a wait gives up after kSyncSpins polls,
-// and every access is a relaxed device-scope atomic (an acquire or release
-// would invalidate or write back the L2 whose reuse the barrier is for).
-__device__ unsigned int g256_rounds[kXcds + 1];
+// Round barriers of the synchronized walk (variant 8): `sync` (kXcds + 1
+// counters in the workspace, zero before the first launch) holds per XCD the
+// number of tile rounds its workgroups have finished, and the workgroups that
+// have left the kernel (the last one resets all of it for the next launch).
+// Only the timing depends on these counters: a wait gives up after
+// kSyncSpins polls, and every access is a relaxed device-scope atomic (an
+// acquire or release would invalidate or write back the L2 whose reuse the
+// barrier is for).
 constexpr int kSyncSpins = 4096;
 
 template <int MODE, int WHICH, int KS, int NBUF, bool SYNC>
 __device__ __forceinline__ void gemm256_body(float* __restrict__ mats, int64_t shadow_off,
                                              const int32_t* __restrict__ count, const TileRec* __restrict__ recs,
-                                             double* __restrict__ partials) {
+                                             double* __restrict__ partials, unsigned* __restrict__ sync) {
   using G = G256<MODE, KS>;
   constexpr bool SPLIT = MODE == SM_BF16X3;
   constexpr int AHEAD = NBUF - 1;
@@ -1114,7 +1115,7 @@ __device__ __forceinline__ void gemm256_body(float* __restrict__ mats, int64_t s
         if (tid == 0) {
           const unsigned target = (unsigned)round * (unsigned)t_step;
           for (int k = 0; k < kSyncSpins; ++k) {
-            if (__hip_atomic_load(&g256_rounds[x8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(&sync[x8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
             __builtin_amdgcn_s_sleep(4);
           }
         }
@@ -1283,20 +1284,20 @@ __device__ __forceinline__ void gemm256_body(float* __restrict__ mats, int64_t s
     }
     __syncthreads();
     if constexpr (SYNC)
-      if (tid == 0) __hip_atomic_fetch_add(&g256_rounds[x8], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) __hip_atomic_fetch_add(&sync[x8], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if constexpr (SYNC) {
     if (tid == 0) {
       // the rounds this workgroup has no tile for count as finished
       const int rounds_x = (t_end - t_lo + t_step - 1) / t_step;
       if (rounds_x > round)
-        __hip_atomic_fetch_add(&g256_rounds[x8], (unsigned)(rounds_x - round), __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(&sync[x8], (unsigned)(rounds_x - round), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned out = __hip_atomic_fetch_add(&g256_rounds[kXcds], 1u, __ATOMIC_RELAXED,
+      const unsigned out = __hip_atomic_fetch_add(&sync[kXcds], 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT) + 1;
       if (out == gridDim.x)
         for (int x = 0; x <= kXcds; ++x)
-          __hip_atomic_exchange(&g256_rounds[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_exchange(&sync[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -1306,7 +1307,7 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
                                                                  const int32_t* __restrict__ count,
                                                                  const TileRec* __restrict__ recs,
                                                                  double* __restrict__ partials) {
-  gemm256_body<MODE, WHICH, KS, NBUF, false>(mats, shadow_off, count, recs, partials);
+  gemm256_body<MODE, WHICH, KS, NBUF, false>(mats, shadow_off, count, recs, partials, nullptr);
 }
 
 // Variant 8: variant 6 with the XCD's workgroups starting every tile round
@@ -1316,8 +1317,9 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_sync_kernel(float* __
                                                                       int64_t shadow_off,
                                                                       const int32_t* __restrict__ count,
                                                                       const TileRec* __restrict__ recs,
-                                                                      double* __restrict__ partials) {
-  gemm256_body<MODE, WHICH, 32, 2, true>(mats, shadow_off, count, recs, partials);
+                                                                      double* __restrict__ partials,
+                                                                      unsigned* __restrict__ sync) {
+  gemm256_body<MODE, WHICH, 32, 2, true>(mats, shadow_off, count, recs, partials, sync);
 }
 
 // 64-tile kernel variants: 0 = {full stage, linear walk}, 1 = {full stage,
@@ -1340,6 +1342,7 @@ struct Launch {
   int grid;
   hipStream_t s;
   hipEvent_t e0, e1;
+  unsigned* sync;   // round counters of variant 8
   template <typename K, typename... A>
   hipError_t go(K kernel, A... args) const {
     return go_block(kBlock, kernel, args...);
@@ -1379,8 +1382,11 @@ static hipError_t launch_which(int variant, void* mats, int64_t so, const int32_
         if (variant == 7)
           return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 16, 4>, (float*)mats, so, count, recs,
                             partials);
-        if (variant == 8)
+        if (variant == 8 && L.sync)
           return L.go_block(kBlock256, ns_gemm256_sync_kernel<MODE, WHICH>, (float*)mats, so, count, recs,
+                            partials, L.sync);
+        if (variant == 8)   // no counters: the same tiles without the round barriers
+          return L.go_block(kBlock256, ns_gemm256_kernel<MODE, WHICH, 32, 2>, (float*)mats, so, count, recs,
                             partials);
       }
       [[fallthrough]];
@@ -1408,11 +1414,11 @@ static hipError_t launch_mode(int which, int variant, void* mats, int64_t so, co
 }
 
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t so,
-                          const int32_t* count, const TileRec* recs, double* partials, int grid,
+                          const int32_t* count, const TileRec* recs, double* partials, unsigned* sync, int grid,
                           hipStream_t s, hipEvent_t ev_start, hipEvent_t ev_stop) {
   // the bf16 / f16 / split-bf16 products need the copy region
   if (mode >= SM_BF16 && so <= 0) return hipErrorInvalidValue;
-  const Launch L{grid, s, ev_start, ev_stop};
+  const Launch L{grid, s, ev_start, ev_stop, sync};
   switch (mode) {
     case SM_F64: return launch_mode<SM_F64>(which, variant, mats, 0, count, recs, partials, L);
     case SM_F32: return launch_mode<SM_F32>(which, variant, mats, so, count, recs, partials, L);

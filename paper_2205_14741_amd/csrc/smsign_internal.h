@@ -112,7 +112,7 @@ struct WsLayout {
   int64_t features;    // float[max_subs * kNumFeatures]
   int64_t scratch;     // double[max_subs * 4] (power iteration, probes)
   int64_t vecs;        // double[sum over chunk of npad * kMaxProbes*2] probe / power vectors
-  int64_t flag;        // 256 reserved bytes
+  int64_t flag;        // 256 bytes: the round counters of the synchronized GEMM walk
   int64_t total;
 };
 
@@ -185,8 +185,9 @@ __host__ __device__ inline int tile_shift(int variant, int mode) {
 // products read them and write them for their outputs, except for
 // kTileStoreF32 tiles); 0 otherwise.
 // ev_start / ev_stop (may be null): events the launch itself records.
+// sync: the workspace's round counters (variant 8; zero before the first launch)
 hipError_t launch_ns_gemm(int mode, int which, int variant, void* mats, int64_t shadow_off,
-                          const int32_t* count, const TileRec* recs, double* partials, int grid,
+                          const int32_t* count, const TileRec* recs, double* partials, unsigned* sync, int grid,
                           hipStream_t s, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // Commutator probes (1..4) of the final X against T read from H's panels.
 hipError_t launch_comm_probe(const DevPlan& p, int g0, int nsub, int max_m, int max_npad, const double* H,

@@ -70,3 +70,45 @@ def test_autotune_sets_its_size_class_only(dev):
     sm.sm_plan_tuning(plan, table)
     for c in range(plan.n_chunks):
         assert plan.chunk_variants(c)[1] == table
+
+
+def test_synchronized_rounds_on_two_streams_at_once(dev):
+    """Two plans, each with its own workspace (and so its own round counters
+    of the synchronized 256-wide kernel), run their sign passes at the same
+    time from two host threads on two streams: both results equal the ones
+    each gives alone, bit for bit (the round barriers order only time)."""
+    import threading
+    import torch
+    m = synth.water_system(48, 2.2, 5)       # n_pad up to 1024: the 256-wide tiles
+    mu = gap_mu(m)
+    o = sm.default_opts("bf16x3", variant=8)
+    H = h_dev(m)
+    runs = []
+    for _ in range(2):
+        plan = sm.Plan(m, 64)
+        w = sm.Workspace(plan, sm.storage_prec(o), H.device)
+        runs.append((plan, w, torch.cuda.Stream()))
+    torch.cuda.synchronize()   # H's upload (current stream) before the other streams read it
+    alone = []
+    for plan, w, st in runs:
+        sm.sm_density_matrix(plan, H, mu, o, w.ws, w.P, w.stats, stream=st)
+        torch.cuda.synchronize()
+        alone.append(w.P.cpu().numpy().copy())
+    errors = []
+
+    def work(plan, w, st):
+        try:
+            for _ in range(2):
+                sm.sm_density_matrix(plan, H, mu, o, w.ws, w.P, w.stats, stream=st)
+        except Exception as e:   # reported below
+            errors.append(e)
+
+    ts = [threading.Thread(target=work, args=r) for r in runs]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for (plan, w, st), P0 in zip(runs, alone):
+        assert np.array_equal(w.P.cpu().numpy(), P0)
