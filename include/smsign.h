@@ -107,7 +107,9 @@ typedef struct {
                             with the workgroups of an XCD starting every round of tiles
                             together (the round's operand panels stream through its L2
                             together).  bf16 / f16 / split-bf16 products on a plan padded
-                            to 32 always run as 2 */
+                            to 32 always run as 2.  With -1, the float32 refinement after
+                            a 16-bit main phase of at most two refinement steps runs as 1
+                            (its products are the atom's own columns only) */
   int32_t graph_iters;   /* 0: launch every kernel of the iteration loop from the host;
                             G > 0: capture G iterations (tile expansion, squares, residuals,
                             scheduler, updates) into one HIP graph, cached per plan / chunk /
@@ -528,7 +530,8 @@ int sm_plan_set_mlp(sm_plan* plan, sm_mlp* mlp);
 /* Autotuner: for every GEMM kernel variant, one build + submatrix_sign pass
  * over `chunk` at fixed mu (the sign phase timed with HIP events, best of
  * `repeats`), then records the fastest variant for the precisions of `opts`
- * (used when opts->variant == -1) as the choice of every chunk in the same
+ * (used when opts->variant == -1; the refinement precision's entry only
+ * when the main phase is float64) as the choice of every chunk in the same
  * size class as `chunk` (the number of 256-row tiles of a chunk's largest
  * padded submatrix: one tuning per class serves a batch of mixed sizes) and
  * as the plan-wide choice that sm_plan_tuning reports.  Chunks of classes

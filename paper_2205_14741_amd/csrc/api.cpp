@@ -100,6 +100,20 @@ int effective_variant(const sm_plan* p, int mode, int variant) {
   return v;
 }
 
+// Variant of the refinement products (opts->variant == -1): after a 16-bit
+// main phase with at most two refinement steps, every refinement product is a
+// slab product (the first refinement update runs on the main kernel; the
+// square before the last update and that update take only the tile columns
+// of the atom's own columns), and for those the 64-wide XCD-aware tiles
+// waste the least (water, split bf16: 48 against 81 ms per pass on the
+// 128-wide ring kernel); otherwise the tuned variant of the refinement
+// precision.
+int refine_variant(const sm_plan* p, const sm_sign_opts* o) {
+  if (o->variant >= 0) return o->variant;
+  if (o->phase1 >= SM_BF16 && o->refine_steps <= 2) return 1;
+  return p->tuned_for(p->active_chunk)[o->refine];
+}
+
 int gemm_launch(sm_plan* p, int mode, int which, int variant, void* mats, int64_t shadow, const int32_t* cnt,
                 const TileRec* recs, double* partials, unsigned* sync, int max_tiles, hipStream_t s) {
   const int v = effective_variant(p, mode, variant);
@@ -242,7 +256,8 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   const bool has_ref = o->refine_steps > 0;
   const int ms = (int)p->max_subs;
   const int tsh_main = tile_shift(effective_variant(p, mode_main, o->variant), mode_main);
-  const int tsh_ref = tile_shift(effective_variant(p, mode_ref, o->variant), mode_ref);
+  const int var_ref = refine_variant(p, o);
+  const int tsh_ref = tile_shift(effective_variant(p, mode_ref, var_ref), mode_ref);
   // tile records by list: 0 / 1 updates, 2 / 3 squares (main / refinement)
   auto recs_of = [&](int L) { return w.tiles + (int64_t)L * p->max_tiles; };
   // the main phase's products keep only 16-bit copies of their results; a
@@ -264,7 +279,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     if (run_main && (r = gemm_launch(p, mode_main, which, o->variant, w.mats, shadow, list_count(Lm),
                                      recs_of(Lm), w.partials, sync, max_tiles, s)))
       return r;
-    if (has_ref && run_ref && (r = gemm_launch(p, mode_ref, which, o->variant, w.mats, shadow, list_count(Lr),
+    if (has_ref && run_ref && (r = gemm_launch(p, mode_ref, which, var_ref, w.mats, shadow, list_count(Lr),
                                                recs_of(Lr), w.partials, sync, max_tiles, s)))
       return r;
     return SM_OK;
@@ -349,7 +364,10 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     if (!exec) {
       if (!p->capture_stream) SM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
       for (int m = 0; m < 5; ++m)                    // occupancy queries outside the capture
-        for (int wh = 0; wh < 2; ++wh) (void)ns_gemm_blocks_per_cu(m, wh, effective_variant(p, m, o->variant));
+        for (int wh = 0; wh < 2; ++wh) {
+          (void)ns_gemm_blocks_per_cu(m, wh, effective_variant(p, m, o->variant));
+          (void)ns_gemm_blocks_per_cu(m, wh, effective_variant(p, m, var_ref));
+        }
       SM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
       int r = SM_OK;
       for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream, nullptr, nullptr, true, true, true);
@@ -619,11 +637,14 @@ int sm_autotune(sm_plan* p, int32_t chunk, const double* H, double mu, const sm_
   if (best < 0) return set_error(SM_ERR_ARG, "sm_autotune: no variant selected by the mask");
   // the plan-wide choice, and that of the chunk's size class (which its
   // chunks use from now on)
+  // (the refinement precision's entry too when it is the same kind of
+  // product: after a float64 main phase; see refine_variant)
+  const bool ref_too = o->refine_steps > 0 && o->phase1 < SM_BF16;
   p->tuned[o->phase1] = best;
-  if (o->refine_steps > 0) p->tuned[o->refine] = best;
+  if (ref_too) p->tuned[o->refine] = best;
   auto& ct = p->class_tuned[p->chunk_class[chunk]];
   ct[o->phase1] = best;
-  if (o->refine_steps > 0) ct[o->refine] = best;
+  if (ref_too) ct[o->refine] = best;
   if (best_out) *best_out = best;
   return SM_OK;
 }

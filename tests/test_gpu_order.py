@@ -58,7 +58,8 @@ def test_autotune_sets_its_size_class_only(dev):
     best, times = sm.sm_autotune(plan, 0, H, mu, o, w.ws, w.stats, repeats=1, variants=(4,))
     torch.cuda.synchronize()
     assert best == 4
-    assert plan.chunk_variants(0)[1][sm.SM_BF16X3] == 4 and plan.chunk_variants(0)[1][sm.SM_F32] == 4
+    # the float32 refinement keeps its own choice (slab products, see the header)
+    assert plan.chunk_variants(0)[1][sm.SM_BF16X3] == 4 and plan.chunk_variants(0)[1][sm.SM_F32] == v0[sm.SM_F32]
     assert plan.chunk_variants(1)[1] == v1
     assert int(sm.sm_plan_tuning(plan)[sm.SM_BF16X3]) == 4
     E, Ne = sm.sm_density_matrix(plan, H, mu, o, w.ws, w.P, w.stats)
