@@ -221,6 +221,8 @@ int sm_find_mu_fermi(sm_plan* p, const double* H, double n_target, double beta, 
   for (; step <= max_steps; ++step) {
     double ne, dne;
     if ((rc = evaluate(p, H, mu, beta, o, ws, P, stats, &ne, &dne, stream))) return rc;
+    if (!std::isfinite(ne) || !std::isfinite(dne))
+      return set_error(SM_ERR_NONFINITE, "sm_find_mu_fermi: non-finite electron count at mu = %.17g", mu);
     dne *= beta;
     if (mu_hist) mu_hist[step - 1] = mu;
     if (ne_hist) ne_hist[step - 1] = ne;
