@@ -407,7 +407,8 @@ int sm_density_matrix_fermi(sm_plan* plan, const double* H_vals, double mu, doub
  * bracket cannot shrink further, or after max_steps evaluations (in [1, 200]).
  * On return P_vals holds P at *mu_out; mu_hist / ne_hist [max_steps] (may be
  * NULL) the evaluated points; E_out / Ne_out (may be NULL) tr(P H) and tr P
- * there.  Synchronises `stream` once per evaluation. */
+ * there.  SM_ERR_NONFINITE if a count or its derivative is not finite.
+ * Synchronises `stream` once per evaluation. */
 int sm_find_mu_fermi(sm_plan* plan, const double* H_vals, double n_target, double beta, double tol,
                      int32_t max_steps, double mu_start, const sm_sign_opts* opts, void* ws,
                      double* P_vals, sm_sub_stats* stats, double* mu_out, int32_t* steps_out,
