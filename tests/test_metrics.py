@@ -65,6 +65,12 @@ def test_kernel_symbols_follow_launcher_fallback():
     assert metrics.gemm_kernel_symbol(0, 0, 3, 64) == "sm::ns_gemm_kernel<0, 0, 1, true>"
     assert metrics.gemm_kernel_symbol(1, 0, 3, 32) == "sm::ns_gemm_kernel<1, 0, 1, true>"
     assert metrics.gemm_kernel_symbol(0, 1, 0, 32) == "sm::ns_gemm_kernel<0, 1, 1, false>"
+    # 256-wide tiles (16-bit copies only; float32 falls back to the ring kernel)
+    assert metrics.gemm_kernel_symbol(4, 1, 6, 64) == "sm::ns_gemm256_kernel<4, 1, 32, 2>"
+    assert metrics.gemm_kernel_symbol(3, 0, 7, 64) == "sm::ns_gemm256_kernel<3, 0, 16, 4>"
+    assert metrics.gemm_kernel_symbol(4, 1, 8, 64) == "sm::ns_gemm256_sync_kernel<4, 1>"
+    assert metrics.gemm_kernel_symbol(1, 1, 8, 64) == "sm::ns_gemm128_kernel<1, 1, true, 6>"
+    assert metrics.gemm_kernel_symbol(4, 1, 8, 32) == "sm::ns_gemm_kernel<4, 1, 2, true>"
 
 
 def _brute_slab(npad, loc, b, tsh):
