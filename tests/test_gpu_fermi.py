@@ -192,4 +192,11 @@ def test_fermi_error_paths(dev):
     sm.submatrix_sign(plan, 0, w.ws, o, w.stats)
     with pytest.raises(sm.SmError):   # the sign iteration overwrote f(T_i)
         sm.assemble_P_fermi(plan, 0, w.ws, w.P)
+    # a submatrix of the non-orthogonal path (K = Z T(H) Z) is not f's input
+    S = h_dev(synth.overlap_for(m, 1))
+    aux = torch.empty_like(w.ws)
+    sm.sm_overlap_inv_sqrt(plan, 0, S, aux, w.ws)
+    sm.build_submatrices_overlap(plan, 0, H, 0.0, o, w.ws, aux, w.stats)
+    with pytest.raises(sm.SmError):
+        sm.sm_fermi_dirac(plan, 0, w.ws, 1.0, w.stats)
     torch.cuda.synchronize()
