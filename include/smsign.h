@@ -127,8 +127,15 @@ typedef struct {
                             Refinement steps are plain.  With accel 0 every step is plain
                             except the first where the scale c is below c_G / (sqrt(3) / 1.01)
                             (a learned or power scale): that step is scaled by
-                            a = sqrt(3) / (1.01 c_G / c), because c_G / c is the only rigorous
-                            bound on the top of the spectrum of X_0. */
+                            a = sqrt(3) / (1.01 c_G / c), because c_G / c is the only a
+                            priori bound on the top of the spectrum of X_0.  With accel 1
+                            and c_G / c > 1 the first square runs unscaled and yields a
+                            tighter rigorous bound: rho(X_0)^2 = rho(X_0^2) is at most the
+                            largest column sum of |X_0^2| (plus a bound on the product's
+                            rounding); the first update is scaled for that top
+                            (sm_sub_stats.top1), after Y = 3I - a^2 X_0^2 is formed from
+                            the stored 3I - X_0^2 by one elementwise pass.  2: as 1 with
+                            the first step scaled for c_G / c (no such bound). */
   double lbound;         /* l_0 as a fraction of the Gershgorin bound: the smallest
                             |eigenvalue| of T is taken to be about lbound * c_G (0: none) */
   int32_t comm_probes;   /* 0..4: float64 commutator probes ||(X T - T X) v|| / (c ||v||) per
@@ -190,7 +197,9 @@ typedef struct {
                           occupied subspace, which X^2 = I cannot.  -1 if not run */
   float feat[16];      /* features of the scaling network (see sm_mlp_create) */
   int32_t retried;     /* 1: the record is that of the fallback run (sm_sign_opts.retry) */
-  int32_t reserved;
+  float top1;          /* accel 1: the bound on the top of the spectrum of X_0 the first
+                          update was scaled for, from the first square's column sums
+                          (at most c_G / scale); 0 where that square ran scaled */
 } sm_sub_stats;
 
 typedef struct sm_plan sm_plan;

@@ -27,7 +27,7 @@ int check_opts(const sm_sign_opts* o) {
   if (o->variant < -1 || o->variant >= kGemmVariants) return set_error(SM_ERR_ARG, "opts.variant = %d out of [-1, %d)", o->variant, kGemmVariants);
   if (o->graph_iters < 0 || o->graph_iters > 64) return set_error(SM_ERR_ARG, "opts.graph_iters = %d out of [0, 64]", o->graph_iters);
   if (o->power_steps < 0 || o->power_steps > 200) return set_error(SM_ERR_ARG, "opts.power_steps out of [0, 200]");
-  if (o->accel != 0 && o->accel != 1) return set_error(SM_ERR_ARG, "opts.accel = %d is not 0 or 1", o->accel);
+  if (o->accel < 0 || o->accel > 2) return set_error(SM_ERR_ARG, "opts.accel = %d is not 0, 1 or 2", o->accel);
   if (o->comm_probes < 0 || o->comm_probes > 4) return set_error(SM_ERR_ARG, "opts.comm_probes = %d out of [0, 4]", o->comm_probes);
   if (o->retry != 0 && o->retry != 1) return set_error(SM_ERR_ARG, "opts.retry = %d is not 0 or 1", o->retry);
   if (!(o->force_scale >= 0.0) || !std::isfinite(o->force_scale))
@@ -286,11 +286,13 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   };
   // the schedule the scheduler applies: opts, or the fallback of the retry
   const sm_sign_opts* cur = o;
+  // the first squares' column-sum bounds (scaled runs, accel 1)
+  double* colmax = w.scratch + 6 * p->max_subs;
   auto schedule = [&](int first, int32_t* live_host) -> int {
     SM_HIP(launch_schedule(p->dev, g0, nsub, w.st, w.partials, w.lists, ms, *cur, first, tsh_main, tsh_ref,
                            first ? w.scratch + 2 * p->max_subs : nullptr,
                            first ? w.scratch + 3 * p->max_subs : nullptr,
-                           first ? w.scratch + 4 * p->max_subs : nullptr, live_host, max_tiles_sub, s));
+                           first ? w.scratch + 4 * p->max_subs : nullptr, live_host, max_tiles_sub, colmax, s));
     return SM_OK;
   };
   // one iteration: squares (A = X^2, Y = 3I - A), residuals + scheduler,
@@ -300,12 +302,24 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
   // (otherwise the host launches them after reading the scheduler's count,
   // still before the next squares).  A main-precision update needs a
   // main-precision square in the same iteration.
+  // first_it: the first iteration of a scaled run (accel 1), whose squares
+  // may have run unscaled: their column-sum bounds before the scheduler,
+  // and Y formed for the first updates after it.
   auto iteration = [&](hipStream_t st, int32_t* live_host, hipEvent_t ev, bool sq_main, bool sq_ref,
-                       bool upd_ref) -> int {
+                       bool upd_ref, bool first_it) -> int {
     hipStream_t keep = s;
     s = st;
+    const bool amode = first_it && cur->accel == 1;
     int r = gemms(2, 3, 0, sq_main, sq_ref);
+    if (!r && amode) {
+      hipError_t e = launch_first_colmax(p->dev, g0, nsub, w.mats, storage, shadow, w.st, colmax, s);
+      if (e != hipSuccess) r = hip_error(e, "first_colmax");
+    }
     if (!r) r = schedule(0, live_host);
+    if (!r && amode) {
+      hipError_t e = launch_first_fix_y(p->dev, g0, nsub, p->max_npad, w.mats, storage, shadow, w.st, s);
+      if (e != hipSuccess) r = hip_error(e, "first_fix_y");
+    }
     if (!r && ev) {
       hipError_t e = hipEventRecord(ev, st);
       if (e != hipSuccess) r = hip_error(e, "hipEventRecord");
@@ -335,7 +349,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
     for (int it = 0; it <= lim; ++it) {
       const int slot = kHostCounts + 4 * (it & 1);
       const bool upd_ref = sq_ref;
-      if ((r = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref, upd_ref))) return r;
+      if ((r = iteration(s, p->d_pinned + slot, p->ev[it & 1], sq_main, sq_ref, upd_ref, it == 0))) return r;
       SM_HIP(hipEventSynchronize(p->ev[it & 1]));
       if (it == 0 && (r = nonfinite())) return r;
       const int32_t* hc = p->h_pinned + slot;
@@ -370,7 +384,7 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
         }
       SM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
       int r = SM_OK;
-      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream, nullptr, nullptr, true, true, true);
+      for (int k = 0; k < G && !r; ++k) r = iteration(p->capture_stream, nullptr, nullptr, true, true, true, false);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
       if (r) {
@@ -385,6 +399,9 @@ int submatrix_sign(sm_plan* p, int32_t chunk, void* ws, const sm_sign_opts* o, s
       std::memcpy(ge.tuned, p->tuned_for(chunk), sizeof(ge.tuned));
       p->graphs.push_back(ge);
     }
+    // the first iteration outside the graph (its squares' bounds and the
+    // forming of Y run only there)
+    if ((rc = iteration(s, nullptr, nullptr, true, true, true, true))) return rc;
     const int replays = (lim + G) / G;
     for (int r = 0; r < replays; ++r) {
       SM_HIP(hipGraphLaunch(exec, s));

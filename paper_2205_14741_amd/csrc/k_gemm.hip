@@ -1490,6 +1490,11 @@ struct SchedOpts {
   int refine_steps, max_iter, accel;
   double tol, switch_tol, stall_below, stall_ratio;
   int copies_main;   // the main phase keeps only 16-bit operand copies
+  // entrywise error model of the first square as stored: |A~ - A| <= (eps_rep
+  // + n_pad eps_acc) |X_0| |X_0| for the operands' representation and the
+  // product's accumulation (precision of the main phase), with the storage
+  // rounding of Y' inside eps_rep
+  double eps_rep, eps_acc;
 };
 
 // The Newton-Schulz map with scale a on one eigenvalue x >= 0.
@@ -1582,7 +1587,8 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
                                                         const double* __restrict__ lb0,
                                                         const double* __restrict__ top0,
                                                         const double* __restrict__ x0s,
-                                                        int32_t* live_host) {
+                                                        int32_t* live_host,
+                                                        const double* __restrict__ colmax) {
   __shared__ int sh[8 * 16];
   const int stride = 2 + 2 * max_subs + 1;
   int run_subs[4] = {0, 0, 0, 0}, run_tiles[4] = {0, 0, 0, 0};
@@ -1635,7 +1641,14 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         // scale the guard could not refute) an unscaled step would send the
         // eigenvalues above sqrt 3 to the wrong sign
         const double cap = 1.7320508075688772 / (1.01 * s.top);
-        s.alpha_sq = (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : (cap < 1.0 ? (double)(float)cap : 1.0);
+        // a scaled run with c_G / c > 1: the first square runs unscaled (Y' =
+        // 3I - A) and the first update's scale waits for the bound on rho(X_0)
+        // that A gives (accel 2: the scale from c_G / c, before the square)
+        s.amode = (o.accel == 1 && s.top > 1.0) ? 1 : 0;
+        s.fix_y = 0;
+        s.top1 = 0.0;
+        s.alpha_sq = s.amode ? 1.0
+                   : (o.accel && s.lb > 0.0) ? ns_alpha(s.lb, s.top) : (cap < 1.0 ? (double)(float)cap : 1.0);
         s.alpha_upd = 1.0;
         s.a0 = 1.0;
         s.lb_est = -1.0;
@@ -1650,6 +1663,16 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
         const double r = s.res_new;
         double lb = s.lb, top = s.top;
         s.res_last = r;
+        s.fix_y = 0;
+        if (s.amode && s.iters == 0 && colmax) {
+          // rho(X_0)^2 = rho(A) <= the largest column sum of |A|; the stored
+          // A~ differs from A by at most (eps_rep + n_pad eps_acc) times the
+          // column sums of |X_0| |X_0|, each at most top^2 (top = c_G / c
+          // bounds the column sums of |X_0|), plus the rounding of the 3I
+          const double slack = (2.0 * o.eps_rep + (double)np * o.eps_acc) * top * top + 6.0 * o.eps_rep;
+          const double t1 = sqrt(colmax[l] + slack);
+          if (isfinite(t1)) top = fmax(fmin(top, t1), 1.0);
+        }
         if (s.sq_slab) {
           // a slab square (refinement, the last update next): its columns'
           // residual only flags a diverged iteration and decides the final
@@ -1745,6 +1768,17 @@ __global__ __launch_bounds__(1024) void schedule_kernel(DevPlan p, int g0, int n
           }
         }
         if (dec & DEC_UPD) {
+          if (s.amode && s.iters == 1) {
+            // the first update after an unscaled first square: its scale from
+            // the bounds as they stand now (the square's column sums, the
+            // residual), the same rule as for any other first step; Y = 3I -
+            // a^2 A is formed from Y' before it runs (fix_y)
+            const double cap = 1.7320508075688772 / (1.01 * top);
+            s.alpha_sq = (o.accel && s.phase == 0 && lb > 0.0) ? ns_alpha(lb, top)
+                                                                 : (cap < 1.0 ? (double)(float)cap : 1.0);
+            s.fix_y = 1;
+            s.top1 = top;
+          }
           // the update of X uses its square's scale; bounds for the new X
           const double a = s.alpha_sq;
           s.alpha_upd = a;
@@ -1834,9 +1868,15 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& so, int first, int tshift_main, int tshift_ref,
                            const double* lb0, const double* top0, const double* x0s, int32_t* live_host,
-                           int max_tiles_sub, hipStream_t s) {
+                           int max_tiles_sub, const double* colmax, hipStream_t s) {
+  // representation error of the main phase's operands and stored results
+  // (twice the unit roundoff of the value each holds: split bf16 about 17
+  // bits, f16 11, bf16 8) and float32 / float64 accumulation
+  const double eps_rep = so.phase1 == SM_F64 ? 0x1p-50 : so.phase1 == SM_F32 ? 0x1p-22
+                       : so.phase1 == SM_BF16X3 ? 0x1p-15 : so.phase1 == SM_F16 ? 0x1p-10 : 0x1p-7;
+  const double eps_acc = so.phase1 == SM_F64 ? 0x1p-52 : 0x1p-23;
   SchedOpts o{so.refine_steps, so.max_iter, so.accel, so.tol, so.switch_tol, so.stall_below, so.stall_ratio,
-              so.phase1 >= SM_BF16 ? 1 : 0};
+              so.phase1 >= SM_BF16 ? 1 : 0, eps_rep, eps_acc};
   // up to 64 partials per submatrix the scheduler's threads add them up
   // themselves; more are reduced by a wavefront each first
   const int fuse = max_tiles_sub <= 64;
@@ -1844,7 +1884,7 @@ hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
     hipLaunchKernelGGL(residual_kernel, dim3((nsub + 3) / 4), dim3(256), 0, s, p, g0, nsub, st, partials,
                        tshift_ref);
   hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, s, p, g0, nsub, st, partials, fuse, lists,
-                     max_subs, o, first, tshift_main, tshift_ref, lb0, top0, x0s, live_host);
+                     max_subs, o, first, tshift_main, tshift_ref, lb0, top0, x0s, live_host, colmax);
   return hipGetLastError();
 }
 

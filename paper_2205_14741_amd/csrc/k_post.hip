@@ -114,6 +114,7 @@ __global__ __launch_bounds__(512) void finish_kernel(DevPlan p, int g0, const T*
     r.iters_low = s.iters_low;
     r.status = s.status;
     r.retried = s.retried;
+    r.top1 = (float)s.top1;
     r.res = s.res;
     r.lb_est = s.lb_est;
     r.res_probe = worst;   // -1 without probes

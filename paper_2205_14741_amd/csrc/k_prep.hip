@@ -8,6 +8,7 @@
 // every submatrix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "device_common.h"
@@ -447,6 +448,186 @@ hipError_t launch_scale(const DevPlan& p, int g0, int nsub, void* mats, int stor
     hipLaunchKernelGGL(scale_kernel<float>, dim3(nsub), dim3(512), 0, s, p, g0, (float*)mats, scaling,
                        power_steps, margin, vecs, cg_in, pred, stats, shadow_kind, shadow_off, lbound,
                        lb0_out, top0_out, x0s_out, pre_w ? 1 : 0, force_scale, subs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// First-step bound of scaled Newton-Schulz (SubState.amode): the first square
+// ran unscaled and left Y' = 3I - A, A = X_0^2, in buffer 2 of its submatrix.
+// The largest column sum of |A| bounds rho(A) = rho(X_0)^2 (Gershgorin on the
+// square, usually several times tighter than (c_G / c)^2, since the signs of
+// the entries of X_0 cancel in its square); the scheduler takes the first
+// update's scale from it, and Y = 3I - a^2 A is then formed in place.
+// Storage kinds: 0 float64, 1 float32, 2 split-bf16 copies, 3 bf16, 4 f16.
+// ---------------------------------------------------------------------------
+typedef uint16_t y_h4 __attribute__((ext_vector_type(4)));
+typedef float y_f4 __attribute__((ext_vector_type(4)));
+
+template <int KIND>
+__device__ __forceinline__ void y_load4(const void* base, int64_t col, int rb, int npad, double (&v)[4]) {
+  if constexpr (KIND == 0) {
+    const double* y = static_cast<const double*>(base) + col * npad + rb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = y[e];
+  } else if constexpr (KIND == 1) {
+    const y_f4 t = *reinterpret_cast<const y_f4*>(static_cast<const float*>(base) + col * npad + rb);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (double)t[e];
+  } else if constexpr (KIND == 2) {
+    const uint16_t* cp = static_cast<const uint16_t*>(base);
+    const int64_t k = copy_idx<true>(col, rb, npad);
+    const y_h4 hi = *reinterpret_cast<const y_h4*>(cp + k);
+    const y_h4 lo = *reinterpret_cast<const y_h4*>(cp + k + 32);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (double)bf16_bits_to_f32(hi[e]) + (double)bf16_bits_to_f32(lo[e]);
+  } else {
+    const uint16_t* cp = static_cast<const uint16_t*>(base);
+    const y_h4 hi = *reinterpret_cast<const y_h4*>(cp + copy_idx<false>(col, rb, npad));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (double)copy_value(hi[e], KIND == 4 ? SM_F16 : SM_BF16);
+  }
+}
+
+// The same four entries written back in the storage's own form (the copies
+// as the products write them: the float32 value rounded to hi, and lo).
+template <int KIND>
+__device__ __forceinline__ void y_store4(void* base, int64_t col, int rb, int npad, const double (&v)[4]) {
+  if constexpr (KIND == 0) {
+    double* y = static_cast<double*>(base) + col * npad + rb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[e] = v[e];
+  } else if constexpr (KIND == 1) {
+    *reinterpret_cast<y_f4*>(static_cast<float*>(base) + col * npad + rb) =
+        y_f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+  } else {
+    uint16_t* cp = static_cast<uint16_t*>(base);
+    y_h4 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float f = (float)v[e];
+      hi[e] = shadow_hi(f, KIND == 4 ? SM_F16 : (KIND == 3 ? SM_BF16 : SM_BF16X3));
+      if (KIND == 2) lo[e] = shadow_lo(f, hi[e]);
+    }
+    if constexpr (KIND == 2) {
+      const int64_t k = copy_idx<true>(col, rb, npad);
+      *reinterpret_cast<y_h4*>(cp + k) = hi;
+      *reinterpret_cast<y_h4*>(cp + k + 32) = lo;
+    } else {
+      *reinterpret_cast<y_h4*>(cp + copy_idx<false>(col, rb, npad)) = hi;
+    }
+  }
+}
+
+// Buffer 2 of processing index g as stored (float64 / float32 values, or the
+// operand copies).
+template <int KIND>
+__device__ __forceinline__ void* y_base(const DevPlan& p, void* mats, int g, int64_t shadow_off) {
+  const int64_t np = p.npad_g[g];
+  const int64_t off = p.mat_off_g[g] + 2 * np * np;
+  if constexpr (KIND == 0) return static_cast<double*>(mats) + off;
+  if constexpr (KIND == 1) return static_cast<float*>(mats) + off;
+  return static_cast<float*>(mats) + off + shadow_off;
+}
+
+// One workgroup (16 waves) per submatrix, a wave per column in turn; column
+// sums in float64 in a fixed order, so colmax does not depend on timing.
+template <int KIND>
+__global__ __launch_bounds__(1024) void first_colmax_kernel(DevPlan p, int g0, const void* mats,
+                                                            int64_t shadow_off, const SubState* __restrict__ st,
+                                                            double* __restrict__ colmax) {
+  __shared__ double red[16];
+  const int l = blockIdx.x;
+  if (!(st[l].amode && st[l].iters == 0 && st[l].active)) {
+    if (threadIdx.x == 0) colmax[l] = 0.0;
+    return;
+  }
+  const int g = g0 + l;
+  const int npad = p.npad_g[g];
+  const void* y = y_base<KIND>(p, const_cast<void*>(mats), g, shadow_off);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double mx = 0.0;
+  for (int c = wid; c < npad; c += 16) {
+    double sum = 0.0;
+    for (int rb = 4 * lane; rb < npad; rb += 256) {
+      double v[4];
+      y_load4<KIND>(y, c, rb, npad, v);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sum += (rb + e == c) ? fabs(3.0 - v[e]) : fabs(v[e]);
+    }
+    sum = wave_sum(sum);
+    mx = (sum == sum) ? fmax(mx, sum) : INFINITY;   // a NaN leaves c_G / c in force
+  }
+  if (lane == 0) red[wid] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) m = fmax(m, red[w]);
+    colmax[l] = m;
+  }
+}
+
+// Y = a^2 Y' + 3 (1 - a^2) I over the padded submatrix, four rows of a
+// column per thread and step.
+template <int KIND>
+__global__ __launch_bounds__(256) void first_fix_y_kernel(DevPlan p, int g0, void* mats, int64_t shadow_off,
+                                                          const SubState* __restrict__ st) {
+  const int l = blockIdx.x;
+  if (!st[l].fix_y) return;
+  const double a = st[l].alpha_upd;
+  const double a2 = a * a, d = 3.0 * (1.0 - a2);
+  const int g = g0 + l;
+  const int npad = p.npad_g[g];
+  const int q4 = npad / 4;
+  void* y = y_base<KIND>(p, mats, g, shadow_off);
+  const int64_t quads = (int64_t)npad * q4;
+  for (int64_t q = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; q < quads;
+       q += (int64_t)gridDim.y * blockDim.x) {
+    const int64_t c = q / q4;
+    const int rb = 4 * (int)(q - c * q4);
+    double v[4];
+    y_load4<KIND>(y, c, rb, npad, v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = a2 * v[e] + ((rb + e == c) ? d : 0.0);
+    y_store4<KIND>(y, c, rb, npad, v);
+  }
+}
+
+static int y_kind(int storage) {
+  return storage == SM_F64 ? 0 : storage == SM_F32 ? 1 : storage == SM_BF16X3 ? 2 : storage == SM_BF16 ? 3 : 4;
+}
+
+hipError_t launch_first_colmax(const DevPlan& p, int g0, int nsub, const void* mats, int storage,
+                               int64_t shadow_off, const SubState* st, double* colmax, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+#define SM_COLMAX(K)                                                                                        \
+  hipLaunchKernelGGL(first_colmax_kernel<K>, dim3(nsub), dim3(1024), 0, s, p, g0, mats, shadow_off, st, colmax)
+  switch (y_kind(storage)) {
+    case 0: SM_COLMAX(0); break;
+    case 1: SM_COLMAX(1); break;
+    case 2: SM_COLMAX(2); break;
+    case 3: SM_COLMAX(3); break;
+    default: SM_COLMAX(4); break;
+  }
+#undef SM_COLMAX
+  return hipGetLastError();
+}
+
+hipError_t launch_first_fix_y(const DevPlan& p, int g0, int nsub, int max_npad, void* mats, int storage,
+                              int64_t shadow_off, SubState* st, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  const int64_t quads = (int64_t)max_npad * (max_npad / 4);
+  const int spread = (int)std::min<int64_t>(64, std::max<int64_t>(1, quads / (256 * 16)));
+#define SM_FIXY(K)                                                                                          \
+  hipLaunchKernelGGL(first_fix_y_kernel<K>, dim3(nsub, spread), dim3(256), 0, s, p, g0, mats, shadow_off, st)
+  switch (y_kind(storage)) {
+    case 0: SM_FIXY(0); break;
+    case 1: SM_FIXY(1); break;
+    case 2: SM_FIXY(2); break;
+    case 3: SM_FIXY(3); break;
+    default: SM_FIXY(4); break;
+  }
+#undef SM_FIXY
   return hipGetLastError();
 }
 

@@ -62,6 +62,14 @@ struct SubState {
   double res_last;     // residual of the last square (a slab square: its columns' part)
   int32_t cap_hit;     // 1: the main phase ended because max_iter was reached
   int32_t retried;     // 1: this run is the fallback retry (sm_sign_opts.retry)
+  // first-step bound from the first square (scaled runs where c_G / c > 1):
+  // that square stores Y' = 3I - A (A = X_0^2, scale 1), the largest column
+  // sum of |A| bounds rho(X_0)^2, and the first update's scale comes from
+  // that tighter top; fix_y: Y = 3I - a^2 A still has to be formed from Y'
+  // before that update
+  int32_t amode;
+  int32_t fix_y;
+  double top1;         // the top of the spectrum of X_0 the first update used (0: no bound)
 };
 
 // One output tile of a Newton-Schulz GEMM launch, written by expand_kernel so
@@ -110,7 +118,8 @@ struct WsLayout {
   int64_t tiles;       // TileRec[4][max_tiles]: tile records of the four lists (updates main /
                        // refinement, squares main / refinement), indexed by list
   int64_t features;    // float[max_subs * kNumFeatures]
-  int64_t scratch;     // double[max_subs * 4] (power iteration, probes)
+  int64_t scratch;     // double[max_subs * 8]: c_G, network outputs, lb0, top0, x0s, the
+                       // failed list of the retry, column-sum bounds of the first square
   int64_t vecs;        // double[sum over chunk of npad * kMaxProbes*2] probe / power vectors
   int64_t flag;        // 256 bytes: the round counters of the synchronized GEMM walk
   int64_t total;
@@ -156,11 +165,24 @@ hipError_t launch_collect_failed(int nsub, const SubState* st, int32_t* list, in
 // the main and the refinement precision, and that of this iteration's
 // refinement updates.  max_tiles_sub: most 64-tiles (lower triangle) of a
 // submatrix in the chunk.
+// colmax [nsub]: the first squares' bounds (launch_first_colmax), read at
+// the decision after them.
 hipError_t launch_schedule(const DevPlan& p, int g0, int nsub, SubState* st,
                            const double* partials, int32_t* lists, int max_subs,
                            const sm_sign_opts& o, int first, int tshift_main, int tshift_ref,
                            const double* lb0, const double* top0, const double* x0s, int32_t* live_host,
-                           int max_tiles_sub, hipStream_t s);
+                           int max_tiles_sub, const double* colmax, hipStream_t s);
+// First square of a submatrix with SubState.amode (its Y' = 3I - A in buffer
+// 2: float64, float32 or the operand copies of `storage`): colmax[l] = the
+// largest column sum of |A| over the padded matrix (A = 3I - Y'), 0 for the
+// other submatrices.  One workgroup per submatrix, column sums in float64,
+// so the value does not depend on the launch.
+hipError_t launch_first_colmax(const DevPlan& p, int g0, int nsub, const void* mats, int storage,
+                               int64_t shadow_off, const SubState* st, double* colmax, hipStream_t s);
+// Submatrices with SubState.fix_y: Y = 3I - a^2 A = 3 (1 - a^2) I + a^2 Y'
+// in place (a = SubState.alpha_upd, the first update's scale), then fix_y = 0.
+hipError_t launch_first_fix_y(const DevPlan& p, int g0, int nsub, int max_npad, void* mats, int storage,
+                              int64_t shadow_off, SubState* st, hipStream_t s);
 // Tile records of all four lists (recs: TileRec[4][max_tiles], by list; the
 // refinement lists only with with_ref).  Main-list tiles of a submatrix in
 // refinement (its first refinement update) get kTileStoreF32.

@@ -65,14 +65,14 @@ class SubStats(C.Structure):
                 ("scale_src", C.c_int32), ("scale", C.c_double), ("res", C.c_double),
                 ("res_probe", C.c_double), ("gersh", C.c_double), ("rho_est", C.c_double),
                 ("lb0", C.c_double), ("lb_est", C.c_double), ("res_comm", C.c_double),
-                ("feat", C.c_float * 16), ("retried", C.c_int32), ("reserved", C.c_int32)]
+                ("feat", C.c_float * 16), ("retried", C.c_int32), ("top1", C.c_float)]
 
 
 STATS_DTYPE = np.dtype([("iters", "<i4"), ("iters_low", "<i4"), ("status", "<i4"),
                         ("scale_src", "<i4"), ("scale", "<f8"), ("res", "<f8"),
                         ("res_probe", "<f8"), ("gersh", "<f8"), ("rho_est", "<f8"),
                         ("lb0", "<f8"), ("lb_est", "<f8"), ("res_comm", "<f8"), ("feat", "<f4", (16,)),
-                        ("retried", "<i4"), ("reserved", "<i4")])
+                        ("retried", "<i4"), ("top1", "<f4")])
 STATS_FEAT_OFFSET = 80   # bytes from the start of a record to feat[0]
 assert STATS_DTYPE.itemsize == C.sizeof(SubStats) == 152
 assert STATS_DTYPE.fields["feat"][1] == STATS_FEAT_OFFSET

@@ -171,3 +171,52 @@ def test_commutator_probe(dev):
     print("max res_comm:", vals, "f32:", float(st["res_comm"].max()))
     assert vals["f64"] < 1e-12 < vals["bf16x3"] < 1e-4 < vals["bf16"]
     assert np.all(st["res_comm"] > 0)
+
+
+FIRST_SQUARE = [("f64", 1e-9), ("f32", 1e-5), ("bf16x3", 1e-4), ("f16", 5e-3), ("bf16", 5e-2)]
+
+
+@pytest.mark.parametrize("prec,dp_max", FIRST_SQUARE, ids=[c[0] for c in FIRST_SQUARE])
+def test_first_square_bounds_the_first_step(prec, dp_max, dev):
+    """Power scale (c near rho(T), far below c_G) with accel 1: the first
+    square runs unscaled and the largest column sum of |X_0^2| bounds the top
+    of the spectrum of X_0 the first update is scaled for (stats.top1).  That
+    bound is rigorous (never below rho(T) / c from the oracle's eigenvalues of
+    every submatrix), at most c_G / c and well below it; the run needs fewer
+    updates than accel 2 (the first step scaled for c_G / c) and its P matches
+    the oracle within the schedule's bar (bf16, whose main phase ends at its
+    precision floor, needs no more updates); a graph replay gives the eager P.
+    Cutoff 2.5 (submatrices up to 552 rows): c_G / c near 5, where the
+    tighter first step saves an update."""
+    m = synth.water_system(24, 2.5, 5)
+    mu = gap_mu(m)
+    view = om.BlockView(m)
+    rho, lrel = np.empty(m.n_atoms), np.inf
+    for i in range(m.n_atoms):
+        T = om.submatrix(view, i, mu)
+        lam = np.abs(np.linalg.eigvalsh(T))
+        rho[i] = lam.max()
+        lrel = min(lrel, lam.min() / om.gershgorin_bound(T))
+    plan = sm.Plan(m, 64)
+    kw = dict(scaling=sm.SM_SCALE_POWER, power_steps=20, scale_margin=0.02, lbound=0.8 * lrel, retry=0)
+    P1, E1, _, st1, _ = run_fixed_mu(m, mu, prec, plan=plan, accel=1, **kw)
+    P2, E2, _, st2, _ = run_fixed_mu(m, mu, prec, plan=plan, accel=2, **kw)
+    top0 = st1["gersh"] / st1["scale"]
+    top1 = st1["top1"].astype(np.float64)
+    print(f"{prec}: top c_G/c {top0.mean():.2f} -> {top1.mean():.2f} (rho/c {np.mean(rho / st1['scale']):.3f}); "
+          f"updates {st2['iters'].mean():.2f} -> {st1['iters'].mean():.2f}")
+    assert np.all(top0 > 1.5) and np.all(st2["top1"] == 0)
+    assert np.all(top1 >= (rho / st1["scale"]) * (1 - 1e-6))
+    assert np.all(top1 <= top0 * (1 + 1e-6)) and top1.mean() < 0.7 * top0.mean()
+    assert np.all(st1["status"] >= 1) and np.all(st2["status"] >= 1)
+    if prec == "bf16":   # its main phase ends at the bf16 floor (stagnation), not by convergence
+        assert st1["iters"].sum() <= st2["iters"].sum()
+    else:
+        assert st1["iters"].sum() < st2["iters"].sum()
+    Po = om.density_matrix(m, mu)
+    Eo, _ = om.energy_trace(m, Po)
+    assert float(np.max(np.abs(P1 - Po))) < dp_max
+    if prec in ("f64", "bf16x3"):
+        assert rel(E1, Eo) < (1e-11 if prec == "f64" else 1e-5)
+        Pg, Eg, _, _, _ = run_fixed_mu(m, mu, prec, plan=plan, accel=1, graph_iters=3, **kw)
+        assert np.array_equal(Pg, P1) and Eg == E1
