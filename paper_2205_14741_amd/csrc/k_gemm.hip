@@ -1233,11 +1233,41 @@ __device__ __forceinline__ void gemm256_body(float* __restrict__ mats, int64_t s
       if (s + AHEAD < nst) issue(s + AHEAD);
       if (!wvalid) continue;
       const char* st = lds + (s % NBUF) * G::STAGE;
+      if constexpr (SYNC && SPLIT && KS == 32) {
+        // the stage's fragment reads in the order the matrix-core blocks
+        // use them, each block row's reads issued while the previous row's
+        // products run (left to itself the compiler reads a group, waits
+        // for it and multiplies, so every wave waits on the LDS several
+        // times per k-step)
+        Frag f0, f1;
+        load_frag(f0, st, 0);
+        load_frag(f1, st, 1);
+        mfma_frag(f0);
+        mfma_frag(f1);
+        __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);   // B of k-step 0, A of block row 0
 #pragma unroll
-      for (int ks = 0; ks < KS / 16; ++ks) {
-        Frag f;
-        load_frag(f, st, ks);
-        mfma_frag(f);
+        for (int q = 0; q < 6; ++q) {                         // rows 0-2; A of rows 1-3
+          __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {                         // row 3; B and A of row 0, k-step 1
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {                         // k-step 1 rows 0-2; A of rows 1-3
+          __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);   // k-step 1 row 3
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < KS / 16; ++ks) {
+          Frag f;
+          load_frag(f, st, ks);
+          mfma_frag(f);
+        }
       }
     }
 
@@ -1311,7 +1341,8 @@ __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_kernel(float* __restr
 }
 
 // Variant 8: variant 6 with the XCD's workgroups starting every tile round
-// together (the round barriers above).
+// together (the round barriers above), and for split bf16 the fragment reads
+// ordered into the products.
 template <int MODE, int WHICH>
 __global__ __launch_bounds__(kBlock256, 1) void ns_gemm256_sync_kernel(float* __restrict__ mats,
                                                                       int64_t shadow_off,
