@@ -113,3 +113,41 @@ def test_nonfinite_h_is_reported(dev):
     sm.submatrix_sign(plan, 0, work.ws, o, work.stats)
     torch.cuda.synchronize()
     assert np.all(work.stats_host()["status"] >= 1)
+
+
+def _near_sign_chain(seed=7):
+    """Four atoms of two orbitals at about -4 and +4, nearest neighbours
+    coupled by 0.03-sized blocks: every submatrix is within a few percent of
+    a signed identity once scaled by its spectral radius (||X_0^2 - I||_F
+    0.02-0.07), while c_G exceeds that radius by the couplings' absolute row
+    sums (c_G / rho 1.004-1.024)."""
+    rng = np.random.default_rng(seed)
+    onsite = np.tile([-4.0, 4.0], 4) + 0.001 * rng.standard_normal(8)
+    pairs = [(0, 1), (1, 2), (2, 3)]
+    blocks = [0.03 * rng.standard_normal((2, 2)) for _ in pairs]
+    return synth.from_pairs([2, 2, 2, 2], pairs, blocks, onsite, n_occ=4)
+
+
+@pytest.mark.parametrize("prec,tol", PRECS)
+def test_first_square_bound_when_the_first_square_has_converged(prec, tol, dev):
+    """Power scale within 0.1 % of rho with accel 1: the first square runs
+    unscaled (c_G / c > 1) and its residual is already below switch_tol, so
+    for split bf16 the first update is a refinement step (two updates in all,
+    none in the main phase); the bound it was scaled for lies between
+    rho(T) / c and c_G / c, and P matches the oracle."""
+    m = _near_sign_chain()
+    view = om.BlockView(m)
+    o = sm.default_opts(prec, scaling=sm.SM_SCALE_POWER, power_steps=30, scale_margin=1e-3, accel=1,
+                        lbound=0.9, retry=0)
+    P, E, Ne, st, plan = run_fixed_mu(m, 0.0, opts=o, pad_to=32)
+    rho = np.array([np.max(np.abs(np.linalg.eigvalsh(om.submatrix(view, i, 0.0)))) for i in range(m.n_atoms)])
+    top0 = st["gersh"] / st["scale"]
+    top1 = st["top1"].astype(np.float64)
+    print(f"{prec}: c_G/c {top0.round(4)}, top1 {top1.round(4)}, updates {st['iters']}")
+    assert np.all(top0 > 1.002)
+    assert np.all(top1 >= (rho / st["scale"]) * (1 - 1e-6)) and np.all(top1 <= top0 * (1 + 1e-6))
+    assert np.all(st["status"] >= 1)
+    if prec == "bf16x3":
+        assert np.all(st["iters_low"] == 0) and np.all(st["iters"] == 2)
+    Po = om.density_matrix(m, 0.0)
+    assert float(np.max(np.abs(P - Po))) < tol
