@@ -140,3 +140,33 @@ def test_overlap_rejects_unsupported_schedules(dev):
             sm.sm_density_matrix_overlap(plan, H, S, 0.0, bad, w.ws, aux, w.P, w.stats)
     with pytest.raises(sm.SmError):   # K needs this chunk's Z first
         sm.build_submatrices_overlap(plan, 0, H, 0.0, o, w.ws, aux, w.stats)
+
+
+def test_overlap_scaled_first_step_from_the_square(dev):
+    """The non-orthogonal path with a power scale and scaled Newton-Schulz
+    (accel 1): the first step of every K_i = Z_i T_i(H) Z_i takes its scale
+    from the first square's column-sum bound (stats.top1 between 1 and
+    c_G / c), and P still matches the oracle to 1e-9."""
+    import torch
+    m = synth.water_system(16, 1.5, 3)
+    s = synth.overlap_for(m, 1)
+    mu = _pencil_gap_mu(m, s)
+    plan = sm.Plan(m, 64)
+    H, S = h_dev(m), h_dev(s)
+    _, w, aux = _workspaces(plan, H.device)
+    o = sm.default_opts("f64", retry=0, scaling=sm.SM_SCALE_POWER, power_steps=20, scale_margin=0.02,
+                        accel=1, lbound=0.01)
+    E, Ne = sm.sm_density_matrix_overlap(plan, H, S, mu, o, w.ws, aux, w.P, w.stats)
+    torch.cuda.synchronize()
+    P, st = w.P.cpu().numpy(), w.stats_host()
+    top0 = st["gersh"] / st["scale"]
+    bounded = top0 > 1.0 + 1e-9
+    print(f"{int(bounded.sum())} of {m.n_atoms} with c_G/c > 1: top {top0[bounded].mean():.2f} -> "
+          f"{st['top1'][bounded].mean():.2f}; updates {st['iters'].mean():.2f}")
+    assert bounded.sum() > m.n_atoms // 2
+    assert np.all(st["top1"][bounded] >= 1.0) and np.all(st["top1"][bounded] <= top0[bounded] * (1 + 1e-6))
+    assert np.all(st["status"] == 1)
+    Po = ov.density_matrix_overlap(m, s, mu)
+    Eo, Neo = ov.traces_overlap(m, s, Po)
+    assert float(np.max(np.abs(P - Po))) < 1e-9
+    assert rel(E, Eo) < 1e-11 and abs(Ne - Neo) < 1e-9
